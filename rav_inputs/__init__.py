@@ -1,0 +1,121 @@
+"""Seeded synthetic inputs for the restricted additive Vanka (RAV) multigrid.
+
+This module only draws random numbers and packs them into flat arrays.  It
+holds none of the method's arithmetic: the manufactured-solution forcing,
+the viscosity field and every operator are evaluated separately by the CPU
+oracle (``oracle/``) and by the HIP library, each from the packed draws.
+
+Workloads (the paper's cavity/cylinder runs on adaptive grids are replaced by
+uniform-grid Taylor-Hood Q2/Q1 Stokes problems of comparable size, Sec. 4):
+
+* ``2d-32``   : 2D 32x32, 3 levels, eta = 1, all-Dirichlet, seed 1001
+* ``2d-512``  : 2D 512x512, 7 levels, seed 1002
+* ``3d-64``   : 3D 64^3, 5 levels, element patches, seed 1003
+* ``batch256``: 256 2D problems, N in {64,128,256}, coarsest 16x16,
+                1-8 circular inclusions at viscosity contrast 1e3, seeds 2000+i
+* ``2d-1024`` : 2D 1024x1024, 8 levels, inclusions at contrast 1e4, seed 1005
+"""
+from __future__ import annotations
+
+import numpy as np
+
+N_MODES = 4
+
+#: Dirichlet side bits: bit 2*d is the side x_d = 0, bit 2*d+1 the side x_d = 1.
+ALL_DIRICHLET_2D = 0b1111
+ALL_DIRICHLET_3D = 0b111111
+#: Outflow variant: natural (do-nothing) boundary on x = 1, Dirichlet elsewhere.
+OUTFLOW_2D = 0b1101
+OUTFLOW_3D = 0b111101
+
+
+def mms_params(dim: int, seed: int, eta: float = 1.0) -> np.ndarray:
+    """Draw the manufactured-solution modes and pack them into a flat array.
+
+    Layout (float64):
+      2D: [eta, a(4), m(4), n(4), c(4), r(4), s(4)]                 -> 25 values
+      3D: [eta, for comp in 0..2: a(4), m(4), n(4), l(4),
+                c(4), r(4), s(4), t(4)]                             -> 65 values
+    a, c ~ N(0, 1); integer wave numbers are drawn uniformly from {1, 2, 3}.
+    ``eta`` is the viscosity used in the forcing.
+    """
+    rng = np.random.default_rng(seed)
+    out = [float(eta)]
+    if dim == 2:
+        a = rng.standard_normal(N_MODES)
+        m = rng.integers(1, 4, N_MODES)
+        n = rng.integers(1, 4, N_MODES)
+        c = rng.standard_normal(N_MODES)
+        r = rng.integers(1, 4, N_MODES)
+        s = rng.integers(1, 4, N_MODES)
+        for arr in (a, m, n, c, r, s):
+            out.extend(float(v) for v in arr)
+    elif dim == 3:
+        for _comp in range(3):
+            a = rng.standard_normal(N_MODES)
+            m = rng.integers(1, 4, N_MODES)
+            n = rng.integers(1, 4, N_MODES)
+            l = rng.integers(1, 4, N_MODES)
+            for arr in (a, m, n, l):
+                out.extend(float(v) for v in arr)
+        c = rng.standard_normal(N_MODES)
+        r = rng.integers(1, 4, N_MODES)
+        s = rng.integers(1, 4, N_MODES)
+        t = rng.integers(1, 4, N_MODES)
+        for arr in (c, r, s, t):
+            out.extend(float(v) for v in arr)
+    else:
+        raise ValueError("dim must be 2 or 3")
+    return np.asarray(out, dtype=np.float64)
+
+
+def inclusions(seed: int, n_min: int = 1, n_max: int = 8,
+               c_lo: float = 0.1, c_hi: float = 0.9,
+               r_lo: float = 0.03, r_hi: float = 0.12) -> np.ndarray:
+    """Circular inclusions as an (n, 3) array of (cx, cy, radius)."""
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(n_min, n_max + 1))
+    cx = rng.uniform(c_lo, c_hi, k)
+    cy = rng.uniform(c_lo, c_hi, k)
+    rad = rng.uniform(r_lo, r_hi, k)
+    return np.stack([cx, cy, rad], axis=1).astype(np.float64)
+
+
+def random_vector(n: int, seed: int) -> np.ndarray:
+    """Standard-normal float64 vector (initial iterates, test right-hand sides)."""
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+def batch_sizes(n_problems: int = 256, seed: int = 2000) -> np.ndarray:
+    """Fine-grid sizes of the batched workload, uniform over {64, 128, 256}."""
+    rng = np.random.default_rng(seed)
+    return np.asarray([64, 128, 256])[rng.integers(0, 3, n_problems)]
+
+
+def levels_to(n_cells: int, coarsest: int) -> int:
+    """Number of levels of a uniform hierarchy from n_cells down to coarsest."""
+    lv = 1
+    n = n_cells
+    while n > coarsest:
+        if n % 2:
+            raise ValueError("n_cells must halve down to the coarsest grid")
+        n //= 2
+        lv += 1
+    if n != coarsest:
+        raise ValueError("coarsest grid not reached")
+    return lv
+
+
+#: The five synthetic workloads.  ``dmask`` = Dirichlet side bits.
+CONFIGS = {
+    "2d-32": dict(dim=2, n_cells=32, n_levels=3, seed=1001, dmask=ALL_DIRICHLET_2D,
+                  eta_out=1.0, eta_in=1.0, contrast=None),
+    "2d-512": dict(dim=2, n_cells=512, n_levels=7, seed=1002, dmask=ALL_DIRICHLET_2D,
+                   eta_out=1.0, eta_in=1.0, contrast=None),
+    "3d-64": dict(dim=3, n_cells=64, n_levels=5, seed=1003, dmask=ALL_DIRICHLET_3D,
+                  eta_out=1.0, eta_in=1.0, contrast=None),
+    "batch256": dict(dim=2, n_problems=256, coarsest=16, seed=2000,
+                     dmask=ALL_DIRICHLET_2D, eta_out=1.0, contrast=1e3),
+    "2d-1024": dict(dim=2, n_cells=1024, n_levels=8, seed=1005, dmask=ALL_DIRICHLET_2D,
+                    eta_out=1.0, contrast=1e4),
+}
