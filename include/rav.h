@@ -1,0 +1,200 @@
+/*
+ * rav.h - restricted additive Vanka (RAV) geometric multigrid for Taylor-Hood
+ * Q2/Q1 Stokes systems on MI355X (gfx950).
+ *
+ * Method: S. Saberi, G. Meschke, A. Vogel, "A restricted additive Vanka
+ * smoother for geometric multigrid", arXiv 2103.10127.
+ *
+ * The library solves L x = b (Sec. 3, eq. 9) for the block system
+ * L = [[A, B], [B^T, 0]] of the stationary Stokes problem (Sec. 2, eqs. 1, 6, 7)
+ * discretised on a uniform quad (2D) or hex (3D) grid of [0,1]^d, with
+ * geometric multigrid V-cycles (Sec. 2, Fig. 1) whose smoother is one of
+ *   MV  multiplicative Vanka       (Sec. 3, eq. 11; residual update eq. 15)
+ *   AV  additive Vanka             (Sec. 3, eq. 12)
+ *   RAV restricted additive Vanka  (Sec. 3, eq. 13; row-limited inverse, Sec. 4.3)
+ * each applied as the fixed-point iteration x <- x + S (b - L x) (eq. 10).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Vectors.  A level-l vector has n_total(l) = d (2N_l+1)^d + (N_l+1)^d FP64
+ *   entries ordered [u_1; ...; u_d; p] (eq. 6): velocity component c at
+ *   half-grid node a in [0,2N]^d at c*(2N+1)^d + sum_k a_k (2N+1)^k (x fastest),
+ *   pressure at vertex k in [0,N]^d after all velocity entries.  Velocity
+ *   entries on Dirichlet sides are masked: they stay 0 and have residual 0.
+ * Levels.  Level 0 is the coarsest, level n_levels-1 the finest;
+ *   N_l = n_cells / 2^(n_levels-1-l).
+ * Memory.  Arguments named *_dev are device pointers (e.g. from
+ *   torch.empty(..., device='cuda', dtype=torch.float64)); the caller owns
+ *   them and they must hold n_total(level) doubles.  Arguments named *_host
+ *   are host pointers.  Every hierarchy buffer (operators, patch inverses,
+ *   coarse inverse, level vectors) is allocated by the library in rav_create /
+ *   rav_factor_patches and released by rav_destroy.
+ * Streams.  All device work of a context is ordered on the hipStream_t given
+ *   to rav_create (NULL = default stream).  Calls that return host values
+ *   (norms, iteration counts, exported data) synchronise that stream.
+ * Errors.  Every function returns a rav_status; none throws.  Negative values
+ *   are hard errors and leave a message retrievable with rav_last_error.
+ *   Invalid arguments are rejected before any device work.  A context is not
+ *   thread-safe: calls on one context must not overlap.
+ */
+#ifndef RAV_H
+#define RAV_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RAV_OK = 0,
+  RAV_NOT_CONVERGED = 1,   /* soft: maxit reached before the tolerance   */
+  RAV_EINVAL = -1,         /* invalid argument / descriptor              */
+  RAV_ENOMEM = -2,         /* device allocation failed                   */
+  RAV_ESINGULAR = -3,      /* zero pivot in a patch or the coarse matrix */
+  RAV_EDIVERGED = -4,      /* residual NaN/Inf or > 1e3 x initial        */
+  RAV_EDEVICE = -5,        /* HIP runtime error                          */
+  RAV_EUNSUPPORTED = -6    /* valid but not implemented combination      */
+} rav_status;
+
+typedef enum { RAV_SMOOTHER_RAV = 0, RAV_SMOOTHER_AV = 1, RAV_SMOOTHER_MV = 2 } rav_smoother;
+
+/* Vertex patches: pressure vertex k plus every velocity DoF coupled to it by
+ * B^T (Sec. 3).  Element patches: the velocity and pressure DoFs of one cell. */
+typedef enum { RAV_PATCH_VERTEX = 0, RAV_PATCH_ELEMENT = 1 } rav_patch_kind;
+
+/* Storage precision of the patch inverse rows used by RAV (the outer
+ * residual, local factorisation and coarse solve are always FP64). */
+typedef enum { RAV_FP64 = 0, RAV_FP32 = 1, RAV_BF16 = 2 } rav_precision;
+
+/* Circular (2D: cx, cy, r) or spherical (3D: cx, cy, cz, r) inclusion. */
+typedef struct { double cx, cy, cz, r; } rav_inclusion;
+
+typedef struct {
+  int dim;                      /* 2 or 3                                        */
+  int n_cells;                  /* N of the finest grid, divisible by 2^(n_levels-1) */
+  int n_levels;                 /* >= 2                                          */
+  unsigned bc_dirichlet_mask;   /* bit 2k: side x_k = 0, bit 2k+1: side x_k = 1 is
+                                   Dirichlet (u = 0); other sides natural (eq. 2) */
+  double eta_out, eta_in;       /* viscosity outside / inside inclusions, > 0   */
+  int n_incl;                   /* number of inclusions (0..64)                  */
+  const rav_inclusion* incl;    /* host array, copied by rav_create              */
+  rav_patch_kind patch;         /* 2D: VERTEX; 3D: ELEMENT                       */
+  rav_smoother smoother;
+  double omega;                 /* damping, > 0 (Sec. 4: 0.66 RAV/MV, 0.1 AV)    */
+  int nu_pre, nu_post;          /* smoothing steps, >= 0                         */
+  rav_precision inv_precision;  /* RAV only; AV/MV store FP64 full inverses      */
+} rav_problem_desc;
+
+typedef struct rav_ctx rav_ctx;
+
+/* Builds the level hierarchy (Sec. 2): grids, DoF numbering, Dirichlet masks,
+ * patch buckets, the rediscretised operator of every level ("assembled on all
+ * grids", Sec. 4) in FP64, and the coarse direct solver (Sec. 2: LU to machine
+ * accuracy).  With Dirichlet velocity on every side the coarse solve uses the
+ * bordered system [[L_0, e],[e^T, 0]], e = (0, 1_p), i.e. zero-mean pressure.
+ * hip_stream: a hipStream_t or NULL.  On success *out owns all device memory. */
+rav_status rav_create(const rav_problem_desc* desc, void* hip_stream, rav_ctx** out);
+
+/* Factors every local system L_i = R_i L R_i^T (Sec. 3) on every smoothed
+ * level with partial pivoting in FP64 and stores, for RAV, the owned rows of
+ * L_i^{-1} (Sec. 4.3) in the context's precision, for AV/MV the full inverse.
+ * RAV_ESINGULAR if a pivot is zero (rav_last_error names level and patch). */
+rav_status rav_factor_patches(rav_ctx* ctx);
+
+/* DoF counts of a level: all entries (including masked) and free entries. */
+rav_status rav_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free);
+/* Number of levels and number of patches of a level. */
+rav_status rav_n_levels(const rav_ctx* ctx, int* n_levels);
+rav_status rav_n_patches(const rav_ctx* ctx, int level, long* n_patches);
+
+/* b_dev = [(f, phi); 0] on the finest level (eq. 5 right-hand side, 3^d Gauss)
+ * for the manufactured forcing f = -eta Lap u + grad p.  mms_params (host):
+ * 2D: 25 doubles [eta, a(4), m(4), n(4), c(4), r(4), s(4)],
+ * 3D: 65 doubles [eta, 3 x (a(4), m(4), n(4), l(4)), c(4), r(4), s(4), t(4)];
+ * u from the stream function / vector potential sum_k a_k prod sin^2(w pi x),
+ * p = sum_k c_k prod cos(w pi x). */
+rav_status rav_assemble_rhs(rav_ctx* ctx, const double* mms_params_host, int n_params, double* b_dev);
+
+/* r_dev = b_dev - L x_dev on free rows, 0 on masked rows (eq. 10).  If
+ * norm_host is non-NULL it receives ||r||_2 (synchronises). */
+rav_status rav_residual(rav_ctx* ctx, int level, const double* x_dev, const double* b_dev,
+                        double* r_dev, double* norm_host);
+
+/* `sweeps` smoother steps x <- x + S (b - L x) on a level >= 1 (eqs. 10-13),
+ * in place on x_dev. */
+rav_status rav_smooth(rav_ctx* ctx, int level, int sweeps, double* x_dev, const double* b_dev);
+
+/* Grid transfer between level `level` (fine) and level-1 (coarse): nested
+ * Q2/Q1 interpolation P and restriction P^T (Sec. 2).
+ * rav_restrict: bc_dev = P^T rf_dev.  rav_prolong_add: xf_dev += P xc_dev. */
+rav_status rav_restrict(rav_ctx* ctx, int level, const double* rf_dev, double* bc_dev);
+rav_status rav_prolong_add(rav_ctx* ctx, int level, const double* xc_dev, double* xf_dev);
+
+/* Direct solve on level 0 (Sec. 2): x0_dev = L_0^{-1} b0_dev (bordered form
+ * for the all-Dirichlet case). */
+rav_status rav_coarse_solve(rav_ctx* ctx, const double* b0_dev, double* x0_dev);
+
+/* One V(nu_pre, nu_post) cycle on the finest level, in place on x_dev (Fig. 1). */
+rav_status rav_vcycle(rav_ctx* ctx, double* x_dev, const double* b_dev);
+
+/* V-cycles from the given x_dev until ||b - L x||_2 <= rtol ||b - L x_0||_2
+ * (Sec. 4: reduction by 1e8) or maxit cycles.  One FP64 norm is read back per
+ * cycle.  Returns RAV_OK, RAV_NOT_CONVERGED or RAV_EDIVERGED; *iters and
+ * *rel_res (final ||r|| / ||r_0||) are set in every case. */
+rav_status rav_solve(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit,
+                     int* iters, double* rel_res);
+
+/* Change damping and smoothing steps without refactoring. */
+rav_status rav_set_params(rav_ctx* ctx, double omega, int nu_pre, int nu_post);
+
+/* Per-patch damping omega_i (the diagonal weighting of eq. 11, one scalar per
+ * patch) for `level`: omega_dev holds n_patches(level) floats and must stay
+ * valid while used; NULL restores the scalar omega. */
+rav_status rav_set_patch_omega(rav_ctx* ctx, int level, const float* omega_dev);
+
+/* Host-side patch map of patch `patch` on `level`: its free DoFs in local
+ * order (component-major, lexicographic nodes, pressure last) into dofs_host
+ * (capacity >= 128), their count into *n, and owned_host[j] = 1 if the DoF is
+ * owned by the patch (restricted prolongation of eq. 13), else 0. */
+rav_status rav_get_patch_map(const rav_ctx* ctx, int level, long patch, int* dofs_host, int* n,
+                             int* owned_host);
+
+/* Host-only versions of the two maps above, computed from the descriptor with
+ * the same index code the kernels use; they touch no device and work on a
+ * machine without a GPU.  owner_host holds n_total(level) int32. */
+rav_status rav_map_patch(const rav_problem_desc* desc, int level, long patch, int* dofs_host, int* n,
+                         int* owned_host);
+rav_status rav_map_owner(const rav_problem_desc* desc, int level, int* owner_host);
+
+/* Device-computed owner of every DoF (patch index, -1 for masked DoFs) into
+ * owner_dev (n_total(level) int32 on the device). */
+rav_status rav_get_owner(rav_ctx* ctx, int level, int* owner_dev);
+
+/* Stored inverse rows of one patch, mapped to the patch's free local order:
+ * out_host (row-major, *rows x *cols, capacity 128*128 doubles) receives the
+ * owned rows of L_i^{-1} (RAV) or the full inverse (AV/MV) as FP64. */
+rav_status rav_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* out_host, int* rows,
+                                 int* cols);
+
+/* Dense copy of the level operator (free rows/cols, masked ones zero) into
+ * out_host (row-major n_total x n_total); only for n_total(level) <= 20000. */
+rav_status rav_export_matrix(rav_ctx* ctx, int level, double* out_host);
+
+/* Times `reps` smoother sweeps of `level` with HIP events recorded on the
+ * context stream around each kernel: average ms of the residual kernel and of
+ * the patch-apply kernel(s) per sweep.  x_dev is updated as by rav_smooth. */
+rav_status rav_time_sweep(rav_ctx* ctx, int level, int reps, double* x_dev, const double* b_dev,
+                          float* ms_residual, float* ms_apply);
+
+/* Plain device copy of n doubles on hip_stream (bandwidth calibration). */
+rav_status rav_stream_copy(void* hip_stream, double* dst_dev, const double* src_dev, long n);
+
+rav_status rav_destroy(rav_ctx* ctx);
+
+/* Message of the last hard error on ctx (or of the last failed rav_create
+ * when ctx is NULL).  Valid until the next call on the same context. */
+const char* rav_last_error(const rav_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RAV_H */

@@ -1,0 +1,280 @@
+"""ctypes binding of ``include/rav.h`` (argument marshalling only).
+
+Every numerical step runs inside ``librav.so``; this module only converts
+torch tensors to device pointers, passes the current HIP stream and turns
+negative status codes into :class:`RavError`.  Importing it fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librav.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "rav.h")
+
+RAV_OK, RAV_NOT_CONVERGED = 0, 1
+STATUS_NAMES = {0: "RAV_OK", 1: "RAV_NOT_CONVERGED", -1: "RAV_EINVAL", -2: "RAV_ENOMEM",
+                -3: "RAV_ESINGULAR", -4: "RAV_EDIVERGED", -5: "RAV_EDEVICE", -6: "RAV_EUNSUPPORTED"}
+SMOOTHERS = {"rav": 0, "av": 1, "mv": 2}
+KINDS = {"vertex": 0, "element": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+
+class RavError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class RavInclusion(ctypes.Structure):
+    _fields_ = [("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double), ("r", ctypes.c_double)]
+
+
+class RavProblemDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_cells", ctypes.c_int), ("n_levels", ctypes.c_int),
+                ("bc_dirichlet_mask", ctypes.c_uint), ("eta_out", ctypes.c_double), ("eta_in", ctypes.c_double),
+                ("n_incl", ctypes.c_int), ("incl", ctypes.POINTER(RavInclusion)), ("patch", ctypes.c_int),
+                ("smoother", ctypes.c_int), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
+                ("nu_post", ctypes.c_int), ("inv_precision", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_L = ctypes.c_long
+_D = ctypes.c_double
+_S = ctypes.c_int   # rav_status
+
+SIGNATURES = {
+    "rav_create": (_S, [ctypes.POINTER(RavProblemDesc), _P, ctypes.POINTER(_P)]),
+    "rav_factor_patches": (_S, [_P]),
+    "rav_dofs": (_S, [_P, _I, ctypes.POINTER(_L), ctypes.POINTER(_L)]),
+    "rav_n_levels": (_S, [_P, ctypes.POINTER(_I)]),
+    "rav_n_patches": (_S, [_P, _I, ctypes.POINTER(_L)]),
+    "rav_assemble_rhs": (_S, [_P, ctypes.POINTER(_D), _I, _P]),
+    "rav_residual": (_S, [_P, _I, _P, _P, _P, ctypes.POINTER(_D)]),
+    "rav_smooth": (_S, [_P, _I, _I, _P, _P]),
+    "rav_restrict": (_S, [_P, _I, _P, _P]),
+    "rav_prolong_add": (_S, [_P, _I, _P, _P]),
+    "rav_coarse_solve": (_S, [_P, _P, _P]),
+    "rav_vcycle": (_S, [_P, _P, _P]),
+    "rav_solve": (_S, [_P, _P, _P, _D, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
+    "rav_set_params": (_S, [_P, _D, _I, _I]),
+    "rav_set_patch_omega": (_S, [_P, _I, _P]),
+    "rav_get_patch_map": (_S, [_P, _I, _L, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "rav_get_owner": (_S, [_P, _I, _P]),
+    "rav_map_patch": (_S, [ctypes.POINTER(RavProblemDesc), _I, _L, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                           ctypes.POINTER(_I)]),
+    "rav_map_owner": (_S, [ctypes.POINTER(RavProblemDesc), _I, ctypes.POINTER(_I)]),
+    "rav_get_patch_inverse": (_S, [_P, _I, _L, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "rav_export_matrix": (_S, [_P, _I, ctypes.POINTER(_D)]),
+    "rav_time_sweep": (_S, [_P, _I, _I, _P, _P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "rav_stream_copy": (_S, [_P, _P, _P, _L]),
+    "rav_destroy": (_S, [_P]),
+    "rav_last_error": (ctypes.c_char_p, [_P]),
+}
+
+
+def header_functions(path: str = HEADER) -> list[str]:
+    """Names of the functions declared in include/rav.h."""
+    text = open(path).read()
+    return sorted(set(re.findall(r"^\s*(?:rav_status|const char\*)\s+(rav_\w+)\s*\(", text, re.M)))
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def _ptr(t) -> int:
+    """Device pointer of a contiguous torch tensor (or a raw integer address)."""
+    if isinstance(t, int):
+        return t
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Hierarchy:
+    """A RAV multigrid hierarchy (one ``rav_ctx``)."""
+
+    def __init__(self, dim=2, n_cells=32, n_levels=3, dmask=0b1111, kind="vertex", smoother="rav",
+                 omega=0.66, nu_pre=2, nu_post=2, precision="fp64", eta_out=1.0, eta_in=1.0,
+                 inclusions=None, stream=None):
+        self.lib = lib()
+        incl = np.zeros((0, 4)) if inclusions is None else np.asarray(inclusions, dtype=np.float64)
+        if incl.size and incl.shape[1] == dim + 1:   # (cx, cy[, cz], r) -> (cx, cy, cz, r)
+            full = np.zeros((len(incl), 4))
+            full[:, :dim] = incl[:, :dim]
+            full[:, 3] = incl[:, dim]
+            incl = full
+        self._incl = (RavInclusion * max(len(incl), 1))()
+        for i, row in enumerate(incl):
+            self._incl[i] = RavInclusion(*row)
+        self.desc = RavProblemDesc(dim, n_cells, n_levels, dmask, eta_out, eta_in, len(incl),
+                                   ctypes.cast(self._incl, ctypes.POINTER(RavInclusion)), KINDS[kind],
+                                   SMOOTHERS[smoother], omega, nu_pre, nu_post, PRECISIONS[precision])
+        self.stream = _stream() if stream is None else stream
+        h = _P()
+        st = self.lib.rav_create(ctypes.byref(self.desc), self.stream, ctypes.byref(h))
+        if st < 0:
+            raise RavError(st, self.lib.rav_last_error(None).decode())
+        self.h = h
+        self.dim, self.n_levels = dim, n_levels
+
+    def _chk(self, st):
+        if st < 0:
+            raise RavError(st, self.lib.rav_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rav_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def factor(self):
+        return self._chk(self.lib.rav_factor_patches(self.h))
+
+    def dofs(self, level):
+        nt, nf = _L(), _L()
+        self._chk(self.lib.rav_dofs(self.h, level, ctypes.byref(nt), ctypes.byref(nf)))
+        return nt.value, nf.value
+
+    def n_patches(self, level):
+        n = _L()
+        self._chk(self.lib.rav_n_patches(self.h, level, ctypes.byref(n)))
+        return n.value
+
+    def assemble_rhs(self, params, b):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        return self._chk(self.lib.rav_assemble_rhs(self.h, p.ctypes.data_as(ctypes.POINTER(_D)), len(p), _ptr(b)))
+
+    def residual(self, level, x, b, r, norm=False):
+        nv = _D()
+        self._chk(self.lib.rav_residual(self.h, level, _ptr(x), _ptr(b), _ptr(r),
+                                        ctypes.byref(nv) if norm else None))
+        return nv.value if norm else None
+
+    def smooth(self, level, sweeps, x, b):
+        return self._chk(self.lib.rav_smooth(self.h, level, sweeps, _ptr(x), _ptr(b)))
+
+    def restrict(self, level, rf, bc):
+        return self._chk(self.lib.rav_restrict(self.h, level, _ptr(rf), _ptr(bc)))
+
+    def prolong_add(self, level, xc, xf):
+        return self._chk(self.lib.rav_prolong_add(self.h, level, _ptr(xc), _ptr(xf)))
+
+    def coarse_solve(self, b0, x0):
+        return self._chk(self.lib.rav_coarse_solve(self.h, _ptr(b0), _ptr(x0)))
+
+    def vcycle(self, x, b):
+        return self._chk(self.lib.rav_vcycle(self.h, _ptr(x), _ptr(b)))
+
+    def solve(self, x, b, rtol=1e-8, maxit=200):
+        it, rel = _I(), _D()
+        st = self.lib.rav_solve(self.h, _ptr(x), _ptr(b), rtol, maxit, ctypes.byref(it), ctypes.byref(rel))
+        if st < 0 and st != -4:
+            self._chk(st)
+        return st, it.value, rel.value
+
+    def set_params(self, omega, nu_pre, nu_post):
+        return self._chk(self.lib.rav_set_params(self.h, omega, nu_pre, nu_post))
+
+    def set_patch_omega(self, level, omega_dev):
+        return self._chk(self.lib.rav_set_patch_omega(self.h, level, None if omega_dev is None else _ptr(omega_dev)))
+
+    def patch_map(self, level, patch):
+        dofs = (_I * 512)()
+        own = (_I * 512)()
+        n = _I()
+        self._chk(self.lib.rav_get_patch_map(self.h, level, patch, dofs, ctypes.byref(n), own))
+        return np.array(dofs[:n.value], dtype=np.int64), np.array(own[:n.value], dtype=bool)
+
+    def owner(self, level):
+        import torch
+        nt, _ = self.dofs(level)
+        out = torch.empty(nt, dtype=torch.int32, device="cuda")
+        self._chk(self.lib.rav_get_owner(self.h, level, _ptr(out)))
+        return out
+
+    def patch_inverse(self, level, patch):
+        buf = (_D * (128 * 128))()
+        r, c = _I(), _I()
+        self._chk(self.lib.rav_get_patch_inverse(self.h, level, patch, buf, ctypes.byref(r), ctypes.byref(c)))
+        return np.ctypeslib.as_array(buf)[: r.value * c.value].reshape(r.value, c.value).copy()
+
+    def export_matrix(self, level):
+        nt, _ = self.dofs(level)
+        out = np.zeros((nt, nt))
+        self._chk(self.lib.rav_export_matrix(self.h, level, out.ctypes.data_as(ctypes.POINTER(_D))))
+        return out
+
+    def time_sweep(self, level, reps, x, b):
+        a, c = ctypes.c_float(), ctypes.c_float()
+        self._chk(self.lib.rav_time_sweep(self.h, level, reps, _ptr(x), _ptr(b), ctypes.byref(a), ctypes.byref(c)))
+        return a.value, c.value
+
+
+def make_desc(dim=2, n_cells=32, n_levels=3, dmask=0b1111, kind="vertex", smoother="rav", omega=0.66,
+              nu_pre=2, nu_post=2, precision="fp64", eta_out=1.0, eta_in=1.0):
+    """Descriptor without inclusions (for the host-only map functions)."""
+    return RavProblemDesc(dim, n_cells, n_levels, dmask, eta_out, eta_in, 0, None, KINDS[kind],
+                          SMOOTHERS[smoother], omega, nu_pre, nu_post, PRECISIONS[precision])
+
+
+def map_patch(desc, level, patch):
+    """Host-only patch map: (global DoFs in local order, owned flags)."""
+    dofs = (_I * 512)()
+    own = (_I * 512)()
+    n = _I()
+    st = lib().rav_map_patch(ctypes.byref(desc), level, patch, dofs, ctypes.byref(n), own)
+    if st < 0:
+        raise RavError(st, "rav_map_patch")
+    return np.array(dofs[:n.value], dtype=np.int64), np.array(own[:n.value], dtype=bool)
+
+
+def map_owner(desc, level, n_total):
+    """Host-only owner map (int32, -1 for masked DoFs)."""
+    out = np.zeros(n_total, dtype=np.int32)
+    st = lib().rav_map_owner(ctypes.byref(desc), level, out.ctypes.data_as(ctypes.POINTER(_I)))
+    if st < 0:
+        raise RavError(st, "rav_map_owner")
+    return out
+
+
+def stream_copy(dst, src, n=None, stream=None):
+    st = lib().rav_stream_copy(_stream() if stream is None else stream, _ptr(dst), _ptr(src),
+                               dst.numel() if n is None else n)
+    if st < 0:
+        raise RavError(st, "stream copy failed")

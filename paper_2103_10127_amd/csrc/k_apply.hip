@@ -1,0 +1,400 @@
+// Patch corrections of the three Vanka smoothers (Sec. 3).
+//
+// RAV (eq. 13, Sec. 4.3): x[owned(i)] += omega_i W_i r[I_i] where W_i holds the
+//   owned rows of L_i^{-1}.  One lane per patch: the lane gathers r at the
+//   patch's columns (the overlapping reads of neighbouring lanes hit the
+//   caches) and streams its W_i with 16-byte loads from the patch-interleaved
+//   layout, so a wavefront reads 1 KiB contiguously per load.  Owned sets
+//   partition the DoFs, so the scatter needs no atomics and no colouring.
+//   Low-precision W (FP32/BF16) is expanded to FP32 and accumulated in FP32;
+//   the correction is added to the FP64 iterate.
+// AV (eq. 12): the full L_i^{-1} r_i of every patch is written to a per-patch
+//   buffer, then every DoF gathers the corrections of the patches that
+//   contain it (deterministic, no atomics).
+// MV (eqs. 11, 15): one launch per colour; patches of one colour touch
+//   disjoint residual rows, so each wavefront recomputes its patch residual
+//   b_i - L[I_i,:] x, applies L_i^{-1} and updates x[I_i] in place, which is
+//   the sequential product of eq. (11) in colour-major order.
+#include <hip/hip_runtime.h>
+
+#include "rav_internal.h"
+
+namespace rav {
+
+struct bf16_t { unsigned short u; };
+
+template <typename WT> struct WTraits;
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef unsigned int uvec4 __attribute__((ext_vector_type(4)));
+template <> struct WTraits<double> { static constexpr int V = 2; typedef double acc_t; typedef dvec2 vec_t; };
+template <> struct WTraits<float> { static constexpr int V = 4; typedef float acc_t; typedef fvec4 vec_t; };
+template <> struct WTraits<bf16_t> { static constexpr int V = 8; typedef float acc_t; typedef uvec4 vec_t; };
+
+template <typename WT>
+__device__ __forceinline__ typename WTraits<WT>::acc_t vec_elem(const typename WTraits<WT>::vec_t& v, int i);
+template <>
+__device__ __forceinline__ double vec_elem<double>(const dvec2& v, int i) { return v[i]; }
+template <>
+__device__ __forceinline__ float vec_elem<float>(const fvec4& v, int i) { return v[i]; }
+template <>
+__device__ __forceinline__ float vec_elem<bf16_t>(const uvec4& v, int i) {
+  const unsigned w = v[i >> 1];
+  const unsigned bits = (i & 1) ? (w & 0xffff0000u) : (w << 16);
+  return __uint_as_float(bits);
+}
+
+// Global index of local column `l` of the patch anchored at k, -1 if the
+// column is outside the grid (masked columns carry r = 0 and zero weights).
+template <int DIM, int KIND>
+__device__ __forceinline__ long long patch_col(const Geo& g, const int* k, int l) {
+  if (KIND == KIND_VERTEX) {
+    constexpr int NV = ipow(5, DIM);
+    if (l < DIM * NV) {
+      const int c = l / NV;
+      int r = l % NV;
+      int a[3] = {0, 0, 0};
+      bool ok = true;
+      for (int d = 0; d < DIM; ++d) {
+        a[d] = 2 * k[d] + (r % 5) - 2;
+        r /= 5;
+        ok = ok && a[d] >= 0 && a[d] <= 2 * g.N;
+      }
+      return ok ? c * g.nV + node_lin(g, a) : -1;
+    }
+    return DIM * g.nV + vert_lin(g, k);
+  }
+  constexpr int NV = ipow(3, DIM);
+  if (l < DIM * NV) {
+    const int c = l / NV;
+    int r = l % NV;
+    int a[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) { a[d] = 2 * k[d] + (r % 3); r /= 3; }
+    return c * g.nV + node_lin(g, a);
+  }
+  int r = l - DIM * NV;
+  int v[3] = {0, 0, 0};
+  for (int d = 0; d < DIM; ++d) { v[d] = k[d] + (r & 1); r >>= 1; }
+  return DIM * g.nV + vert_lin(g, v);
+}
+
+__host__ __device__ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+
+// Columns are processed in groups of G = V / gcd(nown, V) so that every group
+// starts on a 16-byte chunk boundary: the group loop runs at run time (small
+// code, bounded registers), the chunks inside a group and the ragged tail are
+// unrolled at compile time.
+template <int DIM, int KIND, int CLS, typename WT>
+__global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__ G,
+                                                      const BlockTask* __restrict__ tasks) {
+  typedef typename WTraits<WT>::acc_t acc_t;
+  typedef typename WTraits<WT>::vec_t vec_t;
+  constexpr int V = WTraits<WT>::V;
+  constexpr int NPAD = patch_npad(DIM, KIND);
+  constexpr int NOWN = bucket_nown(DIM, KIND, CLS);
+  constexpr int GC = V / gcd_c(NOWN, V);      // columns per group
+  constexpr int CPG = GC * NOWN / V;          // 16-byte chunks per group
+  constexpr int NG = NPAD / GC;               // full groups
+  constexpr int TAIL = NPAD - NG * GC;        // leftover columns
+  constexpr int TAIL_E = TAIL * NOWN;
+  constexpr int TAIL_CH = (TAIL_E + V - 1) / V;
+  const BlockTask t = tasks[blockIdx.x];
+  if (t.grid < 0) return;
+  const GridDev& gd = G[t.grid];
+  const Bucket& bk = gd.bk[t.part];
+  const long long p = t.start + threadIdx.x;
+  if (p >= bk.count) return;
+  const Geo& g = gd.g;
+  int k[3] = {0, 0, 0};
+  bucket_anchor(g, KIND, CLS, p, k);
+  const double* __restrict__ r = gd.r;
+  const vec_t* __restrict__ W = reinterpret_cast<const vec_t*>(bk.W) + p;
+  const long long cs = bk.count_pad;   // chunk stride in vectors
+  acc_t acc[NOWN];
+#pragma unroll
+  for (int j = 0; j < NOWN; ++j) acc[j] = acc_t(0);
+#pragma unroll 1
+  for (int gi = 0; gi < NG; ++gi) {
+    vec_t w[CPG];
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) w[i] = __builtin_nontemporal_load(W + (long long)(gi * CPG + i) * cs);
+    acc_t rv[GC];
+#pragma unroll
+    for (int q = 0; q < GC; ++q) {
+      const long long col = patch_col<DIM, KIND>(g, k, gi * GC + q);
+      rv[q] = col >= 0 ? acc_t(r[col]) : acc_t(0);
+    }
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int el = i * V + v;
+        acc[el % NOWN] += vec_elem<WT>(w[i], v) * rv[el / NOWN];
+      }
+    }
+  }
+  if constexpr (TAIL > 0) {
+    vec_t w[TAIL_CH];
+#pragma unroll
+    for (int i = 0; i < TAIL_CH; ++i) w[i] = __builtin_nontemporal_load(W + (long long)(NG * CPG + i) * cs);
+    acc_t rv[TAIL];
+#pragma unroll
+    for (int q = 0; q < TAIL; ++q) {
+      const long long col = patch_col<DIM, KIND>(g, k, NG * GC + q);
+      rv[q] = col >= 0 ? acc_t(r[col]) : acc_t(0);
+    }
+#pragma unroll
+    for (int el = 0; el < TAIL_E; ++el) acc[el % NOWN] += vec_elem<WT>(w[el / V], el % V) * rv[el / NOWN];
+  }
+  const double om = gd.omega_patch ? (double)gd.omega_patch[patch_lin(g, KIND, k)] : gd.omega;
+  double* __restrict__ x = gd.x;
+#pragma unroll
+  for (int j = 0; j < NOWN; ++j) {
+    const int l = bucket_own_local(DIM, KIND, CLS, j);
+    int comp, node[3];
+    const long long gi = patch_local_dof(g, KIND, k, l, &comp, node);
+    if (gi >= 0) x[gi] += om * (double)acc[j];
+  }
+}
+
+template <int DIM, int KIND, typename WT>
+static void launch_apply_t(int cls, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
+#define RAV_APPLY_CASE(C)                                                                          \
+  case C:                                                                                         \
+    hipLaunchKernelGGL((k_rav_apply<DIM, KIND, C, WT>), dim3(ntasks), dim3(BLOCK), 0, s, G, tasks); \
+    break;
+  if constexpr (KIND == KIND_VERTEX) {
+    hipLaunchKernelGGL((k_rav_apply<DIM, KIND, 0, WT>), dim3(ntasks), dim3(BLOCK), 0, s, G, tasks);
+  } else if constexpr (DIM == 2) {
+    switch (cls) {
+      RAV_APPLY_CASE(0)
+      RAV_APPLY_CASE(1)
+      RAV_APPLY_CASE(2)
+      RAV_APPLY_CASE(3)
+      default: break;
+    }
+  } else {
+    switch (cls) {
+      RAV_APPLY_CASE(0)
+      RAV_APPLY_CASE(1)
+      RAV_APPLY_CASE(2)
+      RAV_APPLY_CASE(3)
+      RAV_APPLY_CASE(4)
+      RAV_APPLY_CASE(5)
+      RAV_APPLY_CASE(6)
+      RAV_APPLY_CASE(7)
+      default: break;
+    }
+  }
+#undef RAV_APPLY_CASE
+}
+
+template <int DIM, int KIND>
+static void launch_apply_k(int cls, int prec, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
+  if (prec == P_FP64) launch_apply_t<DIM, KIND, double>(cls, G, tasks, ntasks, s);
+  else if (prec == P_FP32) launch_apply_t<DIM, KIND, float>(cls, G, tasks, ntasks, s);
+  else launch_apply_t<DIM, KIND, bf16_t>(cls, G, tasks, ntasks, s);
+}
+
+void launch_rav_apply(int dim, int kind, int cls, int prec, const GridDev* G, const BlockTask* tasks, int ntasks,
+                      hipStream_t s) {
+  if (dim == 2 && kind == KIND_VERTEX) launch_apply_k<2, KIND_VERTEX>(cls, prec, G, tasks, ntasks, s);
+  else if (dim == 2) launch_apply_k<2, KIND_ELEMENT>(cls, prec, G, tasks, ntasks, s);
+  else launch_apply_k<3, KIND_ELEMENT>(cls, prec, G, tasks, ntasks, s);
+}
+
+// ---- AV ---------------------------------------------------------------------
+// One wavefront per patch; lane l owns local rows l and l + 64.
+template <int DIM, int KIND>
+__global__ __launch_bounds__(64) void k_av_apply(const GridDev* __restrict__ G, long long npatch) {
+  constexpr int NPAD = patch_npad(DIM, KIND);
+  const long long p = blockIdx.x;
+  if (p >= npatch) return;
+  const GridDev& gd = *G;
+  const Geo& g = gd.g;
+  int k[3] = {0, 0, 0};
+  patch_anchor(g, KIND, p, k);
+  const double* __restrict__ Wi = gd.Winv + p * (long long)NPAD * NPAD;
+  const int lane = threadIdx.x;
+  double y0 = 0.0, y1 = 0.0;
+  for (int c = 0; c < NPAD; ++c) {
+    const long long gi = patch_col<DIM, KIND>(g, k, c);
+    const double rc = gi >= 0 ? gd.r[gi] : 0.0;
+    if (lane < NPAD) y0 += Wi[c * NPAD + lane] * rc;
+    if (lane + 64 < NPAD) y1 += Wi[c * NPAD + lane + 64] * rc;
+  }
+  const double om = gd.omega_patch ? (double)gd.omega_patch[p] : gd.omega;
+  if (lane < NPAD) gd.Y[p * NPAD + lane] = om * y0;
+  if (lane + 64 < NPAD) gd.Y[p * NPAD + lane + 64] = om * y1;
+}
+
+// x[i] += sum over patches q containing DoF i of Y[q][local index of i in q].
+template <int DIM, int KIND>
+__global__ __launch_bounds__(256) void k_av_gather(const GridDev* __restrict__ G, long long n) {
+  constexpr int NPAD = patch_npad(DIM, KIND);
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const GridDev& gd = *G;
+  const Geo& g = gd.g;
+  int a[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  int comp;
+  if (i < DIM * g.nV) {
+    comp = (int)(i / g.nV);
+    node_of(g, i % g.nV, a);
+    if (node_dirichlet(g, a)) return;
+    for (int d = 0; d < DIM; ++d) {
+      if (KIND == KIND_VERTEX) {   // 2k - 2 <= a <= 2k + 2
+        lo[d] = max((a[d] - 1) >> 1, 0);
+        hi[d] = min((a[d] + 2) >> 1, g.N);
+      } else {                     // 2e <= a <= 2e + 2
+        lo[d] = max((a[d] - 1) >> 1, 0);
+        hi[d] = min(a[d] >> 1, g.N - 1);
+      }
+    }
+  } else {
+    comp = DIM;
+    vert_of(g, i - DIM * g.nV, a);
+    for (int d = 0; d < DIM; ++d) {
+      if (KIND == KIND_VERTEX) { lo[d] = a[d]; hi[d] = a[d]; }
+      else { lo[d] = max(a[d] - 1, 0); hi[d] = min(a[d], g.N - 1); }
+    }
+  }
+  double s = 0.0;
+  for (int qz = (DIM == 3 ? lo[2] : 0); qz <= (DIM == 3 ? hi[2] : 0); ++qz)
+    for (int qy = lo[1]; qy <= hi[1]; ++qy)
+      for (int qx = lo[0]; qx <= hi[0]; ++qx) {
+        int q[3] = {qx, qy, qz};
+        int l = 0, st = 1;
+        if (comp < DIM) {
+          const int base = KIND == KIND_VERTEX ? 5 : 3;
+          for (int d = 0; d < DIM; ++d) {
+            l += (KIND == KIND_VERTEX ? a[d] - 2 * q[d] + 2 : a[d] - 2 * q[d]) * st;
+            st *= base;
+          }
+          l += comp * ipow(base, DIM);
+        } else if (KIND == KIND_VERTEX) {
+          l = DIM * ipow(5, DIM);
+        } else {
+          for (int d = 0; d < DIM; ++d) { l += (a[d] - q[d]) * st; st *= 2; }
+          l += DIM * ipow(3, DIM);
+        }
+        s += gd.Y[patch_lin(g, KIND, q) * NPAD + l];
+      }
+  gd.x[i] += s;
+}
+
+// ---- MV ---------------------------------------------------------------------
+// Row `R` of L times x (runtime node type).
+template <int DIM>
+__device__ double row_times_x(const GridDev& gd, long long R) {
+  const Geo& g = gd.g;
+  double acc = 0.0;
+  if (R < DIM * g.nV) {
+    const int c = (int)(R / g.nV);
+    int a[3] = {0, 0, 0};
+    node_of(g, R % g.nV, a);
+    const int t = node_type(g, a);
+    const int s = c * (1 << DIM) + t;
+    const long long rows = gd.seg_rows[s], row = vel_seg_row(g, t, a);
+    const double* v = gd.vals + gd.seg_off[s] + row;
+    int w[3] = {0, 0, 0}, m[3] = {1, 1, 1}, lo[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) {
+      w[d] = a_halfwidth(t, d);
+      m[d] = 3 - ((t >> d) & 1);
+      lo[d] = (a[d] >> 1) - 1 + ((t >> d) & 1);
+    }
+    int slot = 0;
+    for (int oz = -w[2]; oz <= w[2]; ++oz)
+      for (int oy = -w[1]; oy <= w[1]; ++oy)
+        for (int ox = -w[0]; ox <= w[0]; ++ox, ++slot) {
+          int b[3] = {a[0] + ox, a[1] + oy, a[2] + oz};
+          if (node_inside(g, b)) acc += v[slot * rows] * gd.x[c * g.nV + node_lin(g, b)];
+        }
+    for (int jz = 0; jz < m[2]; ++jz)
+      for (int jy = 0; jy < m[1]; ++jy)
+        for (int jx = 0; jx < m[0]; ++jx, ++slot) {
+          int kk[3] = {lo[0] + jx, lo[1] + jy, lo[2] + jz};
+          bool ok = true;
+          for (int d = 0; d < DIM; ++d) ok = ok && kk[d] >= 0 && kk[d] <= g.N;
+          if (ok) acc += v[slot * rows] * gd.x[DIM * g.nV + vert_lin(g, kk)];
+        }
+    return acc;
+  }
+  const long long row = R - DIM * g.nV;
+  int k[3] = {0, 0, 0};
+  vert_of(g, row, k);
+  const int s = pressure_segment(DIM);
+  const long long rows = gd.seg_rows[s];
+  const double* v = gd.vals + gd.seg_off[s] + row;
+  const int wz = DIM == 3 ? 2 : 0;
+  int slot = 0;
+  for (int c = 0; c < DIM; ++c)
+    for (int oz = -wz; oz <= wz; ++oz)
+      for (int oy = -2; oy <= 2; ++oy)
+        for (int ox = -2; ox <= 2; ++ox, ++slot) {
+          int b[3] = {2 * k[0] + ox, 2 * k[1] + oy, DIM == 3 ? 2 * k[2] + oz : 0};
+          if (node_inside(g, b)) acc += v[slot * rows] * gd.x[c * g.nV + node_lin(g, b)];
+        }
+  return acc;
+}
+
+template <int DIM, int KIND>
+__global__ __launch_bounds__(64) void k_mv_colour(const GridDev* __restrict__ G, int colour, long long npc) {
+  constexpr int NPAD = patch_npad(DIM, KIND);
+  __shared__ double rl[NPAD];
+  __shared__ long long gl[NPAD];
+  const long long q = blockIdx.x;
+  if (q >= npc) return;
+  const GridDev& gd = *G;
+  const Geo& g = gd.g;
+  const int M = colour_modulus(KIND);
+  const int ext = KIND == KIND_VERTEX ? g.N + 1 : g.N;
+  int k[3] = {0, 0, 0};
+  long long rem = q;
+  int cc = colour;
+  for (int d = 0; d < DIM; ++d) {
+    const int cd = cc % M;
+    cc /= M;
+    const int cnt = (ext - cd + M - 1) / M;
+    k[d] = cd + M * (int)(rem % cnt);
+    rem /= cnt;
+  }
+  const long long p = patch_lin(g, KIND, k);
+  const int lane = threadIdx.x;
+  for (int l = lane; l < NPAD; l += 64) {
+    int comp, node[3];
+    const long long R = patch_local_dof(g, KIND, k, l, &comp, node);
+    gl[l] = R;
+    rl[l] = R >= 0 ? gd.b[R] - row_times_x<DIM>(gd, R) : 0.0;
+  }
+  __syncthreads();
+  const double* __restrict__ Wi = gd.Winv + p * (long long)NPAD * NPAD;
+  const double om = gd.omega_patch ? (double)gd.omega_patch[p] : gd.omega;
+  for (int l = lane; l < NPAD; l += 64) {
+    double y = 0.0;
+    for (int c = 0; c < NPAD; ++c) y += Wi[c * NPAD + l] * rl[c];
+    if (gl[l] >= 0) gd.x[gl[l]] += om * y;
+  }
+}
+
+void launch_av_apply(int dim, int kind, const GridDev* G, long long npatch, hipStream_t s) {
+  if (dim == 2 && kind == KIND_VERTEX) hipLaunchKernelGGL((k_av_apply<2, KIND_VERTEX>), dim3(npatch), dim3(64), 0, s, G, npatch);
+  else if (dim == 2) hipLaunchKernelGGL((k_av_apply<2, KIND_ELEMENT>), dim3(npatch), dim3(64), 0, s, G, npatch);
+  else hipLaunchKernelGGL((k_av_apply<3, KIND_ELEMENT>), dim3(npatch), dim3(64), 0, s, G, npatch);
+}
+
+void launch_av_gather(int dim, int kind, const GridDev* G, long long n, hipStream_t s) {
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (dim == 2 && kind == KIND_VERTEX) hipLaunchKernelGGL((k_av_gather<2, KIND_VERTEX>), dim3(nb), dim3(256), 0, s, G, n);
+  else if (dim == 2) hipLaunchKernelGGL((k_av_gather<2, KIND_ELEMENT>), dim3(nb), dim3(256), 0, s, G, n);
+  else hipLaunchKernelGGL((k_av_gather<3, KIND_ELEMENT>), dim3(nb), dim3(256), 0, s, G, n);
+}
+
+void launch_mv_colour(int dim, int kind, const GridDev* G, int colour, long long npc, hipStream_t s) {
+  if (npc <= 0) return;
+  if (dim == 2 && kind == KIND_VERTEX) hipLaunchKernelGGL((k_mv_colour<2, KIND_VERTEX>), dim3(npc), dim3(64), 0, s, G, colour, npc);
+  else if (dim == 2) hipLaunchKernelGGL((k_mv_colour<2, KIND_ELEMENT>), dim3(npc), dim3(64), 0, s, G, colour, npc);
+  else hipLaunchKernelGGL((k_mv_colour<3, KIND_ELEMENT>), dim3(npc), dim3(64), 0, s, G, colour, npc);
+}
+
+}  // namespace rav

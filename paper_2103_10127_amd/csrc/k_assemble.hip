@@ -1,0 +1,366 @@
+// Level operator and right-hand side assembly (Sec. 2, eqs. 5-7).
+//
+// Every value of the ELL operator is computed by the thread that owns its
+// row, as a gather over the (at most 2^d) cells that contain both the row
+// node and the column node, so no two threads write the same address and no
+// atomics are needed.  Cell matrices:
+//   A_e[a][b] = h^(d-2) sum_q w_q eta_q grad phi_a(q) . grad phi_b(q)
+//   B_e[c][a][k] = -h^(d-1) sum_q w_q psi_k(q) d_c phi_a(q)   (C = 0)
+// with the viscosity taken per Gauss point (inclusions: closed disc/ball).
+#include <hip/hip_runtime.h>
+
+#include "rav_internal.h"
+
+namespace rav {
+
+__constant__ RefTables c_ref;
+
+void set_ref_tables(const RefTables& t, hipStream_t s) {
+  (void)hipStreamSynchronize(s);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_ref), &t, sizeof(RefTables), 0, hipMemcpyHostToDevice);
+}
+
+// ---- viscosity at the Gauss points of every cell ---------------------------
+// etaq[cell * nq + q]; uniform[cell] = 1 when all nq values are equal.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_eta(const GridDev* G, const double* incl, int n_incl,
+                                              double eta_out, double eta_in, double* etaq,
+                                              unsigned char* uniform) {
+#pragma clang fp contract(off)
+  constexpr int NQ = ipow(3, DIM);
+  const Geo& g = G->g;
+  long long ncell = (long long)g.N * g.N * (DIM == 3 ? g.N : 1);
+  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= ncell) return;
+  int E[3] = {0, 0, 0};
+  long long t = e;
+  for (int d = 0; d < DIM; ++d) { E[d] = (int)(t % g.N); t /= g.N; }
+  const double h = G->h;
+  bool uni = true;
+  double first = 0.0;
+  for (int q = 0; q < NQ; ++q) {
+    int qq = q;
+    double x[3];
+    for (int d = 0; d < DIM; ++d) { x[d] = ((double)E[d] + c_ref.gt[qq % 3]) * h; qq /= 3; }
+    bool inside = false;
+    for (int i = 0; i < n_incl; ++i) {
+      const double* ic = incl + 4 * i;
+      double d2 = 0.0;
+      for (int d = 0; d < DIM; ++d) { double dd = x[d] - ic[d]; d2 = d2 + dd * dd; }
+      double rad = ic[3];
+      inside = inside || (d2 <= rad * rad);
+    }
+    double v = inside ? eta_in : eta_out;
+    etaq[e * NQ + q] = v;
+    if (q == 0) first = v;
+    uni = uni && (v == first);
+  }
+  uniform[e] = uni ? 1 : 0;
+}
+
+template <int DIM>
+__device__ __forceinline__ double cell_stiffness(const double* etaq, const unsigned char* uniform,
+                                                 long long cell, const int* la, const int* lb) {
+  constexpr int NQ = ipow(3, DIM);
+  int ia = 0, ib = 0, st = 1;
+  for (int d = 0; d < DIM; ++d) { ia += la[d] * st; ib += lb[d] * st; st *= 3; }
+  if (uniform[cell]) {
+    double aref = DIM == 2 ? c_ref.aref2[ia][ib] : c_ref.aref3[ia][ib];
+    return etaq[cell * NQ] * aref;
+  }
+  double s = 0.0;
+  for (int q = 0; q < NQ; ++q) {
+    int qd[3], qq = q;
+    for (int d = 0; d < DIM; ++d) { qd[d] = qq % 3; qq /= 3; }
+    double w = 1.0, gg = 0.0;
+    for (int d = 0; d < DIM; ++d) w *= c_ref.gw[qd[d]];
+    for (int c = 0; c < DIM; ++c) {
+      double p = 1.0;
+      for (int d = 0; d < DIM; ++d)
+        p *= (d == c) ? c_ref.dphi[la[d]][qd[d]] * c_ref.dphi[lb[d]][qd[d]]
+                      : c_ref.phi[la[d]][qd[d]] * c_ref.phi[lb[d]][qd[d]];
+      gg += p;
+    }
+    s += w * etaq[cell * NQ + q] * gg;
+  }
+  return s;
+}
+
+template <int DIM>
+__device__ __forceinline__ double bref(int c, const int* la, const int* lk) {
+  int ia = 0, ik = 0, sa = 1, sk = 1;
+  for (int d = 0; d < DIM; ++d) { ia += la[d] * sa; ik += lk[d] * sk; sa *= 3; sk *= 2; }
+  return DIM == 2 ? c_ref.bref2[c][ia][ik] : c_ref.bref3[c][ia][ik];
+}
+
+__device__ __forceinline__ int ceil_half(int v) { return v >= 0 ? (v + 1) >> 1 : -((-v) >> 1); }
+
+// Range of cells E_d containing both half-grid positions a and b (1D).
+__device__ __forceinline__ void common_cells(int a, int b, int N, int& lo, int& hi) {
+  lo = max(ceil_half(a - 2), ceil_half(b - 2));
+  hi = min(a >> 1, b >> 1);
+  lo = max(lo, 0);
+  hi = min(hi, N - 1);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_assemble(const GridDev* G, const BlockTask* tasks,
+                                                   const double* etaq, const unsigned char* uniform) {
+  const BlockTask t = tasks[blockIdx.x];
+  if (t.grid < 0) return;
+  const GridDev& gd = G[t.grid];
+  const Geo& g = gd.g;
+  const int s = t.part;
+  const long long rows = gd.seg_rows[s];
+  const long long row = t.start + threadIdx.x;
+  if (row >= rows) return;
+  double* out = gd.vals + gd.seg_off[s] + row;
+  const int nslot = seg_slots(DIM, s);
+  const double h = gd.h;
+  const double hA = DIM == 2 ? 1.0 : h;       // h^(d-2)
+  const double hB = DIM == 2 ? h : h * h;     // h^(d-1)
+  const int N = g.N;
+  if (s == pressure_segment(DIM)) {
+    int k[3] = {0, 0, 0};
+    vert_of(g, row, k);
+    for (int slot = 0; slot < nslot; ++slot) {
+      int c = slot / ipow(5, DIM), r = slot % ipow(5, DIM);
+      int b[3] = {0, 0, 0};
+      for (int d = 0; d < DIM; ++d) { b[d] = 2 * k[d] + (r % 5) - 2; r /= 5; }
+      double v = 0.0;
+      if (node_inside(g, b) && !node_dirichlet(g, b)) {
+        int lo[3], hi[3];
+        for (int d = 0; d < DIM; ++d) {
+          lo[d] = max(max(k[d] - 1, ceil_half(b[d] - 2)), 0);
+          hi[d] = min(min(k[d], b[d] >> 1), N - 1);
+        }
+        for (int ez = (DIM == 3 ? lo[2] : 0); ez <= (DIM == 3 ? hi[2] : 0); ++ez)
+          for (int ey = lo[1]; ey <= hi[1]; ++ey)
+            for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+              int E[3] = {ex, ey, ez};
+              int lb[3], lk[3];
+              for (int d = 0; d < DIM; ++d) { lb[d] = b[d] - 2 * E[d]; lk[d] = k[d] - E[d]; }
+              v += hB * bref<DIM>(c, lb, lk);
+            }
+      }
+      out[(long long)slot * rows] = v;
+    }
+    return;
+  }
+  const int c = s >> DIM;
+  const int ty = s & ((1 << DIM) - 1);
+  int a[3] = {0, 0, 0};
+  vel_row_node(g, ty, row, a);
+  const bool row_masked = node_dirichlet(g, a);
+  const int na = n_aslots(DIM, ty);
+  for (int slot = 0; slot < nslot; ++slot) {
+    double v = 0.0;
+    if (!row_masked) {
+      if (slot < na) {
+        int b[3] = {0, 0, 0}, r = slot;
+        for (int d = 0; d < DIM; ++d) {
+          int w = a_halfwidth(ty, d);
+          b[d] = a[d] + (r % (2 * w + 1)) - w;
+          r /= 2 * w + 1;
+        }
+        if (node_inside(g, b) && !node_dirichlet(g, b)) {
+          int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+          for (int d = 0; d < DIM; ++d) common_cells(a[d], b[d], N, lo[d], hi[d]);
+          for (int ez = (DIM == 3 ? lo[2] : 0); ez <= (DIM == 3 ? hi[2] : 0); ++ez)
+            for (int ey = lo[1]; ey <= hi[1]; ++ey)
+              for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+                int E[3] = {ex, ey, ez};
+                int la[3], lb[3];
+                for (int d = 0; d < DIM; ++d) { la[d] = a[d] - 2 * E[d]; lb[d] = b[d] - 2 * E[d]; }
+                long long cell = ex + (long long)N * (ey + (long long)N * ez);
+                v += hA * cell_stiffness<DIM>(etaq, uniform, cell, la, lb);
+              }
+        }
+      } else {
+        int k[3] = {0, 0, 0}, r = slot - na;
+        bool inside = true;
+        for (int d = 0; d < DIM; ++d) {
+          int px = (ty >> d) & 1, m = 3 - px, lo = (a[d] >> 1) - 1 + px;
+          k[d] = lo + (r % m);
+          r /= m;
+          inside = inside && k[d] >= 0 && k[d] <= N;
+        }
+        if (inside) {
+          int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+          for (int d = 0; d < DIM; ++d) {
+            lo[d] = max(max(ceil_half(a[d] - 2), k[d] - 1), 0);
+            hi[d] = min(min(a[d] >> 1, k[d]), N - 1);
+          }
+          for (int ez = (DIM == 3 ? lo[2] : 0); ez <= (DIM == 3 ? hi[2] : 0); ++ez)
+            for (int ey = lo[1]; ey <= hi[1]; ++ey)
+              for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+                int E[3] = {ex, ey, ez};
+                int la[3], lk[3];
+                for (int d = 0; d < DIM; ++d) { la[d] = a[d] - 2 * E[d]; lk[d] = k[d] - E[d]; }
+                v += hB * bref<DIM>(c, la, lk);
+              }
+        }
+      }
+    }
+    out[(long long)slot * rows] = v;
+  }
+}
+
+// ---- manufactured right-hand side (eq. 5 with f = -eta Lap u + grad p) ------
+__device__ __forceinline__ double sfun(int order, double t, double m) {
+  const double w = m * M_PI;
+  switch (order) {
+    case 0: { double s = sin(w * t); return s * s; }
+    case 1: return w * sin(2.0 * w * t);
+    case 2: return 2.0 * w * w * cos(2.0 * w * t);
+    default: return -4.0 * w * w * w * sin(2.0 * w * t);
+  }
+}
+
+template <int DIM>
+__device__ double prod_term(const double* x, const double* w, const int* ord) {
+  double p = 1.0;
+  for (int d = 0; d < DIM; ++d) p *= sfun(ord[d], x[d], w[d]);
+  return p;
+}
+template <int DIM>
+__device__ double lap_prod(const double* x, const double* w, const int* ord) {
+  double s = 0.0;
+  for (int d = 0; d < DIM; ++d) {
+    int o[3] = {ord[0], ord[1], DIM == 3 ? ord[2] : 0};
+    o[d] += 2;
+    s += prod_term<DIM>(x, w, o);
+  }
+  return s;
+}
+
+template <int DIM>
+__device__ void forcing(const double* P, const double* x, double* f) {
+  const double eta = P[0];
+  double lap[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
+  if (DIM == 2) {
+    const double *a = P + 1, *m = P + 5, *n = P + 9, *c = P + 13, *r = P + 17, *s = P + 21;
+    for (int k = 0; k < 4; ++k) {
+      double w[2] = {m[k], n[k]};
+      int o01[2] = {0, 1}, o10[2] = {1, 0};
+      lap[0] += a[k] * lap_prod<2>(x, w, o01);
+      lap[1] -= a[k] * lap_prod<2>(x, w, o10);
+      double wr = r[k] * M_PI, ws = s[k] * M_PI;
+      gp[0] += c[k] * (-wr * sin(wr * x[0])) * cos(ws * x[1]);
+      gp[1] += c[k] * cos(wr * x[0]) * (-ws * sin(ws * x[1]));
+    }
+  } else {
+    for (int i = 0; i < 3; ++i) {
+      int j = (i + 1) % 3, kk = (i + 2) % 3;
+      const double* Pk = P + 1 + 16 * kk;
+      const double* Pj = P + 1 + 16 * j;
+      for (int m = 0; m < 4; ++m) {
+        int oj[3] = {0, 0, 0}, ok[3] = {0, 0, 0};
+        oj[j] = 1; ok[kk] = 1;
+        double wk[3] = {Pk[4 + m], Pk[8 + m], Pk[12 + m]};
+        double wj[3] = {Pj[4 + m], Pj[8 + m], Pj[12 + m]};
+        lap[i] += Pk[m] * lap_prod<3>(x, wk, oj);
+        lap[i] -= Pj[m] * lap_prod<3>(x, wj, ok);
+      }
+    }
+    const double *c = P + 49, *r = P + 53, *s = P + 57, *t = P + 61;
+    for (int k = 0; k < 4; ++k) {
+      double w[3] = {r[k] * M_PI, s[k] * M_PI, t[k] * M_PI};
+      for (int cc = 0; cc < 3; ++cc) {
+        double term = c[k];
+        for (int d = 0; d < 3; ++d) term *= (d == cc) ? -w[d] * sin(w[d] * x[d]) : cos(w[d] * x[d]);
+        gp[cc] += term;
+      }
+    }
+  }
+  for (int d = 0; d < DIM; ++d) f[d] = -eta * lap[d] + gp[d];
+}
+
+// f at every Gauss point of every cell: fq[(cell * NQ + q) * DIM + c].
+template <int DIM>
+__global__ __launch_bounds__(256) void k_rhs_qp(const GridDev* G, const double* P, double* fq) {
+  constexpr int NQ = ipow(3, DIM);
+  const Geo& g = G->g;
+  long long ncell = (long long)g.N * g.N * (DIM == 3 ? g.N : 1);
+  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= ncell) return;
+  int E[3] = {0, 0, 0};
+  long long t = e;
+  for (int d = 0; d < DIM; ++d) { E[d] = (int)(t % g.N); t /= g.N; }
+  for (int q = 0; q < NQ; ++q) {
+    int qq = q;
+    double x[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) { x[d] = ((double)E[d] + c_ref.gt[qq % 3]) * G->h; qq /= 3; }
+    double f[3];
+    forcing<DIM>(P, x, f);
+    for (int c = 0; c < DIM; ++c) fq[(e * NQ + q) * DIM + c] = f[c];
+  }
+}
+
+// b[row] = sum over cells containing the node of sum_q w_q h^d f_c(x_q) phi_a(q).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_rhs_gather(const GridDev* G, const double* fq, double* b) {
+  constexpr int NQ = ipow(3, DIM);
+  const Geo& g = G->g;
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  if (i >= DIM * g.nV) { b[i] = 0.0; return; }
+  int c = (int)(i / g.nV);
+  int a[3] = {0, 0, 0};
+  node_of(g, i % g.nV, a);
+  if (node_dirichlet(g, a)) { b[i] = 0.0; return; }
+  double hd = 1.0;
+  for (int d = 0; d < DIM; ++d) hd *= G->h;
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int d = 0; d < DIM; ++d) {
+    lo[d] = max(ceil_half(a[d] - 2), 0);
+    hi[d] = min(a[d] >> 1, g.N - 1);
+  }
+  double s = 0.0;
+  for (int ez = (DIM == 3 ? lo[2] : 0); ez <= (DIM == 3 ? hi[2] : 0); ++ez)
+    for (int ey = lo[1]; ey <= hi[1]; ++ey)
+      for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+        int E[3] = {ex, ey, ez};
+        long long cell = ex + (long long)g.N * (ey + (long long)g.N * ez);
+        for (int q = 0; q < NQ; ++q) {
+          int qq = q;
+          double w = 1.0, phi = 1.0;
+          for (int d = 0; d < DIM; ++d) {
+            int qd = qq % 3;
+            qq /= 3;
+            w *= c_ref.gw[qd];
+            phi *= c_ref.phi[a[d] - 2 * E[d]][qd];
+          }
+          s += w * hd * fq[(cell * NQ + q) * DIM + c] * phi;
+        }
+      }
+  b[i] = s;
+}
+
+static inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_assemble(int dim, long long ncell, const GridDev* G, const BlockTask* tasks, int ntasks,
+                     const double* incl, int n_incl, double eta_out, double eta_in, double* etaq,
+                     unsigned char* uni, hipStream_t s) {
+  if (dim == 2) {
+    hipLaunchKernelGGL(k_eta<2>, dim3(nblk(ncell, 256)), dim3(256), 0, s, G, incl, n_incl, eta_out, eta_in, etaq, uni);
+    hipLaunchKernelGGL(k_assemble<2>, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, etaq, uni);
+  } else {
+    hipLaunchKernelGGL(k_eta<3>, dim3(nblk(ncell, 256)), dim3(256), 0, s, G, incl, n_incl, eta_out, eta_in, etaq, uni);
+    hipLaunchKernelGGL(k_assemble<3>, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, etaq, uni);
+  }
+}
+
+void launch_rhs(int dim, const GridDev* Gh, const GridDev* Gd, const double* params, double* fq, double* b,
+                hipStream_t s) {
+  long long ncell = (long long)Gh->g.N * Gh->g.N * (dim == 3 ? Gh->g.N : 1);
+  if (dim == 2) {
+    hipLaunchKernelGGL(k_rhs_qp<2>, dim3(nblk(ncell, 256)), dim3(256), 0, s, Gd, params, fq);
+    hipLaunchKernelGGL(k_rhs_gather<2>, dim3(nblk(Gh->g.n, 256)), dim3(256), 0, s, Gd, fq, b);
+  } else {
+    hipLaunchKernelGGL(k_rhs_qp<3>, dim3(nblk(ncell, 256)), dim3(256), 0, s, Gd, params, fq);
+    hipLaunchKernelGGL(k_rhs_gather<3>, dim3(nblk(Gh->g.n, 256)), dim3(256), 0, s, Gd, fq, b);
+  }
+}
+
+}  // namespace rav

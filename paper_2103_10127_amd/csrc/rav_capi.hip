@@ -1,0 +1,875 @@
+// Host driver and C-ABI of the RAV multigrid library.
+//
+// Builds the uniform level hierarchy (Sec. 2), uploads one GridDev
+// descriptor per level, and orders every step of a V-cycle (Fig. 1) on the
+// caller's stream: smoothing (Sec. 3, eqs. 10-13), residual, restriction,
+// recursion, coarse direct solve, prolongation.  The solve loop reads back one
+// FP64 norm per cycle for the stopping test (Sec. 4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rav.h"
+#include "rav_internal.h"
+
+using namespace rav;
+
+namespace {
+
+struct ApplyLaunch {
+  int bucket = 0;
+  int cls = 0;
+  BlockTask* tasks = nullptr;
+  int ntasks = 0;
+};
+
+struct LevelHost {
+  GridDev hd{};
+  GridDev* dd = nullptr;
+  long long nvals = 0;
+  BlockTask* res_tasks = nullptr;
+  int n_res_tasks = 0;
+  int n_res_tiles = 0;
+  double* partials = nullptr;
+  std::vector<ApplyLaunch> apply;
+  long long npatch = 0;
+};
+
+std::string g_create_error;
+
+}  // namespace
+
+struct rav_ctx {
+  rav_problem_desc desc{};
+  std::vector<rav_inclusion> incl;
+  hipStream_t stream = nullptr;
+  std::vector<LevelHost> lv;
+  double* d_incl = nullptr;
+  double* Minv = nullptr;
+  long long nb = 0;
+  int bordered = 0;
+  int* d_status = nullptr;
+  int* d_piv = nullptr;
+  double* d_colk = nullptr;
+  double* d_norm = nullptr;
+  double* h_norm = nullptr;   // pinned
+  int factored = 0;
+  int prec = P_FP64;
+  std::string err;
+};
+
+#define CK(expr)                                                                     \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                  \
+      return e_ == hipErrorOutOfMemory ? RAV_ENOMEM : RAV_EDEVICE;                   \
+    }                                                                                \
+  } while (0)
+
+namespace {
+
+// ---- reference-element tables from the Lagrange bases ----------------------
+void q2(double t, double* v) { v[0] = (1 - t) * (1 - 2 * t); v[1] = 4 * t * (1 - t); v[2] = t * (2 * t - 1); }
+void dq2(double t, double* v) { v[0] = 4 * t - 3; v[1] = 4 - 8 * t; v[2] = 4 * t - 1; }
+
+RefTables make_tables() {
+  RefTables T{};
+  T.gt[0] = 0.5 - 0.5 * std::sqrt(0.6); T.gt[1] = 0.5; T.gt[2] = 0.5 + 0.5 * std::sqrt(0.6);
+  T.gw[0] = 5.0 / 18.0; T.gw[1] = 8.0 / 18.0; T.gw[2] = 5.0 / 18.0;
+  for (int q = 0; q < 3; ++q) {
+    double v[3], dv[3];
+    q2(T.gt[q], v);
+    dq2(T.gt[q], dv);
+    for (int a = 0; a < 3; ++a) { T.phi[a][q] = v[a]; T.dphi[a][q] = dv[a]; }
+    T.psi[0][q] = 1 - T.gt[q];
+    T.psi[1][q] = T.gt[q];
+  }
+  // 2D and 3D reference stiffness (h = 1) and divergence tables.
+  for (int dim = 2; dim <= 3; ++dim) {
+    const int nv = dim == 2 ? 9 : 27, np = dim == 2 ? 4 : 8, nq = nv;
+    for (int a = 0; a < nv; ++a)
+      for (int b = 0; b < nv; ++b) {
+        double s = 0.0;
+        for (int q = 0; q < nq; ++q) {
+          int ia[3] = {a % 3, (a / 3) % 3, a / 9}, ib[3] = {b % 3, (b / 3) % 3, b / 9}, iq[3] = {q % 3, (q / 3) % 3, q / 9};
+          double w = 1.0, gg = 0.0;
+          for (int d = 0; d < dim; ++d) w *= T.gw[iq[d]];
+          for (int c = 0; c < dim; ++c) {
+            double p = 1.0;
+            for (int d = 0; d < dim; ++d)
+              p *= (d == c) ? T.dphi[ia[d]][iq[d]] * T.dphi[ib[d]][iq[d]] : T.phi[ia[d]][iq[d]] * T.phi[ib[d]][iq[d]];
+            gg += p;
+          }
+          s += w * gg;
+        }
+        if (dim == 2) T.aref2[a][b] = s; else T.aref3[a][b] = s;
+      }
+    for (int c = 0; c < dim; ++c)
+      for (int a = 0; a < nv; ++a)
+        for (int k = 0; k < np; ++k) {
+          double s = 0.0;
+          for (int q = 0; q < nq; ++q) {
+            int ia[3] = {a % 3, (a / 3) % 3, a / 9}, ik[3] = {k & 1, (k >> 1) & 1, k >> 2},
+                iq[3] = {q % 3, (q / 3) % 3, q / 9};
+            double w = 1.0, ps = 1.0, dphi = 1.0;
+            for (int d = 0; d < dim; ++d) {
+              w *= T.gw[iq[d]];
+              ps *= T.psi[ik[d]][iq[d]];
+              dphi *= (d == c) ? T.dphi[ia[d]][iq[d]] : T.phi[ia[d]][iq[d]];
+            }
+            s += w * ps * dphi;
+          }
+          if (dim == 2) T.bref2[c][a][k] = -s; else T.bref3[c][a][k] = -s;
+        }
+  }
+  return T;
+}
+
+// Permute logical tiles so that hardware block b (dispatched to XCD b % 8)
+// processes logical tile (b % 8) * (T / 8) + b / 8: each XCD sweeps one
+// contiguous range of the grid and its L2 sees the overlapping reads.
+std::vector<BlockTask> xcd_order(const std::vector<BlockTask>& logical) {
+  const size_t T = (logical.size() + 7) / 8 * 8;
+  std::vector<BlockTask> out(T);
+  for (size_t b = 0; b < T; ++b) {
+    const size_t l = (b % 8) * (T / 8) + b / 8;
+    if (l < logical.size()) out[b] = logical[l];
+    else { out[b].grid = -1; out[b].part = 0; out[b].start = 0; out[b].logical = 0; out[b].pad = 0; }
+  }
+  return out;
+}
+
+}  // namespace
+
+static rav_status set_err(rav_ctx* ctx, rav_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg; else g_create_error = msg;
+  return st;
+}
+
+static rav_status upload_tasks(rav_ctx* ctx, const std::vector<BlockTask>& logical, BlockTask** out, int* n) {
+  std::vector<BlockTask> t = xcd_order(logical);
+  *n = (int)t.size();
+  CK(hipMalloc((void**)out, sizeof(BlockTask) * std::max<size_t>(t.size(), 1)));
+  CK(hipMemcpy(*out, t.data(), sizeof(BlockTask) * t.size(), hipMemcpyHostToDevice));
+  return RAV_OK;
+}
+
+static rav_status upload_desc(rav_ctx* ctx, LevelHost& L) {
+  CK(hipStreamSynchronize(ctx->stream));
+  CK(hipMemcpy(L.dd, &L.hd, sizeof(GridDev), hipMemcpyHostToDevice));
+  return RAV_OK;
+}
+
+static rav_status build_level(rav_ctx* ctx, int l) {
+  const rav_problem_desc& D = ctx->desc;
+  LevelHost& L = ctx->lv[l];
+  const int N = D.n_cells >> (D.n_levels - 1 - l);
+  GridDev& h = L.hd;
+  std::memset(&h, 0, sizeof(GridDev));
+  h.g = make_geo(D.dim, N, D.bc_dirichlet_mask);
+  h.kind = D.patch;
+  h.h = 1.0 / N;
+  h.omega = D.omega;
+  const Geo& g = h.g;
+  const int nseg = n_segments(D.dim);
+  long long off = 0;
+  for (int s = 0; s < nseg; ++s) {
+    h.seg_off[s] = off;
+    h.seg_rows[s] = seg_rows(g, s);
+    off += h.seg_rows[s] * seg_slots(D.dim, s);
+  }
+  L.nvals = off;
+  CK(hipMalloc((void**)&h.x, sizeof(double) * g.n));
+  CK(hipMalloc((void**)&h.b, sizeof(double) * g.n));
+  CK(hipMalloc((void**)&h.r, sizeof(double) * g.n));
+  CK(hipMalloc((void**)&h.vals, sizeof(double) * off));
+  CK(hipMemsetAsync(h.x, 0, sizeof(double) * g.n, ctx->stream));
+  CK(hipMemsetAsync(h.b, 0, sizeof(double) * g.n, ctx->stream));
+  CK(hipMemsetAsync(h.r, 0, sizeof(double) * g.n, ctx->stream));
+  CK(hipMalloc((void**)&L.dd, sizeof(GridDev)));
+  L.npatch = n_patches(g, D.patch);
+  // residual tiles: one block of 256 rows of a single segment
+  std::vector<BlockTask> tiles;
+  for (int s = 0; s < nseg; ++s)
+    for (long long r0 = 0; r0 < h.seg_rows[s]; r0 += BLOCK) {
+      BlockTask t{};
+      t.grid = 0; t.part = s; t.start = r0; t.logical = (int)tiles.size();
+      tiles.push_back(t);
+    }
+  L.n_res_tiles = (int)tiles.size();
+  rav_status st = upload_tasks(ctx, tiles, &L.res_tasks, &L.n_res_tasks);
+  if (st != RAV_OK) return st;
+  CK(hipMalloc((void**)&L.partials, sizeof(double) * std::max(L.n_res_tiles, 1)));
+  // patch buckets (smoothed levels only)
+  if (l > 0) {
+    const int nbk = n_buckets(D.dim, D.patch);
+    for (int m = 0; m < nbk; ++m) {
+      const long long cnt = bucket_count(g, D.patch, m);
+      if (cnt <= 0) continue;
+      Bucket& B = h.bk[h.nbk];
+      B.cls = D.patch == KIND_VERTEX ? 0 : m;
+      B.nown = bucket_nown(D.dim, D.patch, B.cls);
+      B.count = cnt;
+      B.count_pad = (cnt + 63) / 64 * 64;
+      ApplyLaunch al;
+      al.bucket = h.nbk;
+      al.cls = B.cls;
+      std::vector<BlockTask> at;
+      for (long long p0 = 0; p0 < cnt; p0 += BLOCK) {
+        BlockTask t{};
+        t.grid = 0; t.part = h.nbk; t.start = p0; t.logical = (int)at.size();
+        at.push_back(t);
+      }
+      st = upload_tasks(ctx, at, &al.tasks, &al.ntasks);
+      if (st != RAV_OK) return st;
+      L.apply.push_back(al);
+      ++h.nbk;
+    }
+  }
+  // operator assembly on the device
+  st = upload_desc(ctx, L);
+  if (st != RAV_OK) return st;
+  const long long ncell = (long long)N * N * (D.dim == 3 ? N : 1);
+  double* etaq = nullptr;
+  unsigned char* uni = nullptr;
+  CK(hipMalloc((void**)&etaq, sizeof(double) * ncell * (D.dim == 2 ? 9 : 27)));
+  CK(hipMalloc((void**)&uni, ncell));
+  std::vector<BlockTask> at;
+  for (int s = 0; s < nseg; ++s)
+    for (long long r0 = 0; r0 < h.seg_rows[s]; r0 += BLOCK) {
+      BlockTask t{};
+      t.grid = 0; t.part = s; t.start = r0; t.logical = (int)at.size();
+      at.push_back(t);
+    }
+  BlockTask* atd = nullptr;
+  int natd = 0;
+  st = upload_tasks(ctx, at, &atd, &natd);
+  if (st != RAV_OK) return st;
+  launch_assemble(D.dim, ncell, L.dd, atd, natd, ctx->d_incl, D.n_incl, D.eta_out, D.eta_in, etaq, uni,
+                  ctx->stream);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(ctx->stream));
+  CK(hipFree(etaq));
+  CK(hipFree(uni));
+  CK(hipFree(atd));
+  return RAV_OK;
+}
+
+static rav_status build_coarse(rav_ctx* ctx) {
+  LevelHost& L = ctx->lv[0];
+  const Geo& g = L.hd.g;
+  bool all_dir = true;
+  for (int b = 0; b < 2 * g.dim; ++b) all_dir = all_dir && ((g.dmask >> b) & 1u);
+  ctx->bordered = all_dir ? 1 : 0;
+  ctx->nb = g.n + ctx->bordered;
+  const long long nb = ctx->nb;
+  CK(hipMalloc((void**)&ctx->Minv, sizeof(double) * nb * nb));
+  CK(hipMalloc((void**)&ctx->d_piv, sizeof(int) * nb));
+  CK(hipMalloc((void**)&ctx->d_colk, sizeof(double) * nb));
+  const int big = INT_MAX;
+  CK(hipMemcpy(ctx->d_status, &big, sizeof(int), hipMemcpyHostToDevice));
+  launch_coarse_build(L.dd, g.dim, ctx->Minv, nb, ctx->bordered, 1, ctx->stream);
+  for (long long k = 0; k < nb; ++k)
+    launch_coarse_gj_step(ctx->Minv, nb, k, ctx->d_piv, ctx->d_colk, ctx->d_status, ctx->stream);
+  launch_coarse_colswap(ctx->Minv, nb, ctx->d_piv, ctx->stream);
+  CK(hipGetLastError());
+  int st = 0;
+  CK(hipMemcpyAsync(&st, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  if (st != INT_MAX)
+    return set_err(ctx, RAV_ESINGULAR, "zero pivot in the coarse matrix at column " + std::to_string(st));
+  return RAV_OK;
+}
+
+// ---- device sequences -------------------------------------------------------
+static void residual_level(rav_ctx* ctx, int l, bool with_norm) {
+  LevelHost& L = ctx->lv[l];
+  launch_residual(ctx->desc.dim, L.dd, L.res_tasks, L.n_res_tasks, with_norm ? L.partials : nullptr, ctx->stream);
+  if (with_norm) launch_norm_finalize(L.partials, 0, L.n_res_tiles, ctx->d_norm, ctx->stream);
+}
+
+static void apply_level(rav_ctx* ctx, int l) {
+  LevelHost& L = ctx->lv[l];
+  const rav_problem_desc& D = ctx->desc;
+  if (D.smoother == RAV_SMOOTHER_RAV) {
+    for (const ApplyLaunch& al : L.apply)
+      launch_rav_apply(D.dim, D.patch, al.cls, ctx->prec, L.dd, al.tasks, al.ntasks, ctx->stream);
+  } else if (D.smoother == RAV_SMOOTHER_AV) {
+    launch_av_apply(D.dim, D.patch, L.dd, L.npatch, ctx->stream);
+    launch_av_gather(D.dim, D.patch, L.dd, L.hd.g.n, ctx->stream);
+  }
+}
+
+static void mv_sweep(rav_ctx* ctx, int l) {
+  LevelHost& L = ctx->lv[l];
+  const rav_problem_desc& D = ctx->desc;
+  const Geo& g = L.hd.g;
+  const int M = colour_modulus(D.patch);
+  const int ext = D.patch == KIND_VERTEX ? g.N + 1 : g.N;
+  int ncol = 1;
+  for (int d = 0; d < D.dim; ++d) ncol *= M;
+  for (int col = 0; col < ncol; ++col) {
+    long long cnt = 1;
+    int cc = col;
+    for (int d = 0; d < D.dim; ++d) {
+      const int cd = cc % M;
+      cc /= M;
+      cnt *= std::max(0, (ext - cd + M - 1) / M);
+    }
+    launch_mv_colour(D.dim, D.patch, L.dd, col, cnt, ctx->stream);
+  }
+}
+
+static void smooth_level(rav_ctx* ctx, int l, int sweeps) {
+  for (int s = 0; s < sweeps; ++s) {
+    if (ctx->desc.smoother == RAV_SMOOTHER_MV) {
+      mv_sweep(ctx, l);
+    } else {
+      residual_level(ctx, l, false);
+      apply_level(ctx, l);
+    }
+  }
+}
+
+static void coarse_solve_level(rav_ctx* ctx) {
+  LevelHost& L = ctx->lv[0];
+  launch_coarse_gemv(ctx->Minv, ctx->nb, L.hd.g.n, L.hd.b, L.hd.x, ctx->stream);
+}
+
+static void vcycle_level(rav_ctx* ctx, int l) {
+  if (l == 0) { coarse_solve_level(ctx); return; }
+  LevelHost& L = ctx->lv[l];
+  smooth_level(ctx, l, ctx->desc.nu_pre);
+  residual_level(ctx, l, false);
+  launch_restrict(ctx->desc.dim, L.dd, ctx->lv[l - 1].hd.g.n, ctx->stream);
+  vcycle_level(ctx, l - 1);
+  launch_prolong(ctx->desc.dim, L.dd, L.hd.g.n, ctx->stream);
+  smooth_level(ctx, l, ctx->desc.nu_post);
+}
+
+static rav_status read_norm(rav_ctx* ctx, double* out) {
+  CK(hipMemcpyAsync(ctx->h_norm, ctx->d_norm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  *out = std::sqrt(*ctx->h_norm);
+  return RAV_OK;
+}
+
+static rav_status check_level(const rav_ctx* ctx, int level, bool smoothed) {
+  if (!ctx) return RAV_EINVAL;
+  if (level < 0 || level >= (int)ctx->lv.size()) return RAV_EINVAL;
+  if (smoothed && level == 0) return RAV_EINVAL;
+  return RAV_OK;
+}
+
+static rav_status need_factors(rav_ctx* ctx) {
+  if (!ctx->factored) return set_err(ctx, RAV_EINVAL, "rav_factor_patches has not been called");
+  return RAV_OK;
+}
+
+// ============================================================================
+extern "C" {
+
+rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out) {
+  if (!d || !out) return set_err(nullptr, RAV_EINVAL, "null descriptor or output pointer");
+  *out = nullptr;
+  if (d->dim != 2 && d->dim != 3) return set_err(nullptr, RAV_EINVAL, "dim must be 2 or 3");
+  if (d->n_levels < 2) return set_err(nullptr, RAV_EINVAL, "n_levels must be >= 2");
+  if (d->n_levels > 20 || d->n_cells <= 0 || d->n_cells % (1 << (d->n_levels - 1)))
+    return set_err(nullptr, RAV_EINVAL, "n_cells must be divisible by 2^(n_levels-1)");
+  if (!(d->omega > 0.0) || d->nu_pre < 0 || d->nu_post < 0)
+    return set_err(nullptr, RAV_EINVAL, "omega must be > 0 and smoothing steps >= 0");
+  if (!(d->eta_out > 0.0) || !(d->eta_in > 0.0)) return set_err(nullptr, RAV_EINVAL, "viscosities must be > 0");
+  if (d->n_incl < 0 || d->n_incl > MAX_INCL || (d->n_incl > 0 && !d->incl))
+    return set_err(nullptr, RAV_EINVAL, "n_incl must be in [0, 64] with a valid array");
+  if (d->bc_dirichlet_mask >> (2 * d->dim)) return set_err(nullptr, RAV_EINVAL, "bc mask has bits beyond 2*dim");
+  if (d->patch != RAV_PATCH_VERTEX && d->patch != RAV_PATCH_ELEMENT) return set_err(nullptr, RAV_EINVAL, "bad patch kind");
+  if (d->smoother < RAV_SMOOTHER_RAV || d->smoother > RAV_SMOOTHER_MV) return set_err(nullptr, RAV_EINVAL, "bad smoother");
+  if (d->inv_precision < RAV_FP64 || d->inv_precision > RAV_BF16) return set_err(nullptr, RAV_EINVAL, "bad precision");
+  if (d->dim == 3 && d->patch == RAV_PATCH_VERTEX)
+    return set_err(nullptr, RAV_EUNSUPPORTED, "3D vertex patches (376 DoFs) are not supported; use element patches");
+  if (d->smoother != RAV_SMOOTHER_RAV && d->inv_precision != RAV_FP64)
+    return set_err(nullptr, RAV_EUNSUPPORTED, "low-precision inverses are provided for RAV only");
+
+  rav_ctx* ctx = new rav_ctx();
+  ctx->desc = *d;
+  if (d->n_incl > 0) ctx->incl.assign(d->incl, d->incl + d->n_incl);
+  ctx->desc.incl = ctx->incl.empty() ? nullptr : ctx->incl.data();
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->prec = d->inv_precision;
+  auto fail = [&](rav_status st) {
+    g_create_error = ctx->err;
+    rav_destroy(ctx);
+    return st;
+  };
+  {
+    hipError_t e = hipMalloc((void**)&ctx->d_status, sizeof(int));
+    if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
+    e = hipMalloc((void**)&ctx->d_norm, sizeof(double));
+    if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
+    e = hipHostMalloc((void**)&ctx->h_norm, sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
+    std::vector<double> inc(4 * std::max(d->n_incl, 1), 0.0);
+    for (int i = 0; i < d->n_incl; ++i) {
+      const rav_inclusion& c = d->incl[i];
+      inc[4 * i + 0] = c.cx; inc[4 * i + 1] = c.cy; inc[4 * i + 2] = c.cz; inc[4 * i + 3] = c.r;
+    }
+    e = hipMalloc((void**)&ctx->d_incl, sizeof(double) * inc.size());
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_incl, inc.data(), sizeof(double) * inc.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
+  }
+  set_ref_tables(make_tables(), ctx->stream);
+  ctx->lv.resize(d->n_levels);
+  for (int l = 0; l < d->n_levels; ++l) {
+    rav_status st = build_level(ctx, l);
+    if (st != RAV_OK) return fail(st);
+  }
+  for (int l = 1; l < d->n_levels; ++l) {
+    LevelHost& L = ctx->lv[l];
+    L.hd.has_coarse = 1;
+    L.hd.gc = ctx->lv[l - 1].hd.g;
+    L.hd.xc = ctx->lv[l - 1].hd.x;
+    L.hd.bc = ctx->lv[l - 1].hd.b;
+    rav_status st = upload_desc(ctx, L);
+    if (st != RAV_OK) return fail(st);
+  }
+  rav_status st = build_coarse(ctx);
+  if (st != RAV_OK) return fail(st);
+  *out = ctx;
+  return RAV_OK;
+}
+
+rav_status rav_factor_patches(rav_ctx* ctx) {
+  if (!ctx) return RAV_EINVAL;
+  const rav_problem_desc& D = ctx->desc;
+  const bool full = D.smoother != RAV_SMOOTHER_RAV;
+  const int npad = patch_npad(D.dim, D.patch);
+  const int big = INT_MAX;
+  for (size_t l = 1; l < ctx->lv.size(); ++l) {
+    LevelHost& L = ctx->lv[l];
+    GridDev& h = L.hd;
+    if (full) {
+      if (!h.Winv) {
+        CK(hipMalloc((void**)&h.Winv, sizeof(double) * L.npatch * npad * npad));
+        if (D.smoother == RAV_SMOOTHER_AV) CK(hipMalloc((void**)&h.Y, sizeof(double) * L.npatch * npad));
+      }
+    } else {
+      const int V = ctx->prec == P_FP64 ? 2 : ctx->prec == P_FP32 ? 4 : 8;
+      const size_t esz = ctx->prec == P_FP64 ? 8 : ctx->prec == P_FP32 ? 4 : 2;
+      for (int bi = 0; bi < h.nbk; ++bi) {
+        Bucket& B = h.bk[bi];
+        B.nchunk = ((long long)npad * B.nown + V - 1) / V;
+        B.wstride = B.count_pad * V;
+        if (!B.W) {
+          const size_t bytes = esz * (size_t)B.nchunk * (size_t)B.wstride;
+          CK(hipMalloc(&B.W, bytes));
+          CK(hipMemsetAsync(B.W, 0, bytes, ctx->stream));
+        }
+      }
+    }
+    rav_status st = upload_desc(ctx, L);
+    if (st != RAV_OK) return st;
+    CK(hipMemcpy(ctx->d_status, &big, sizeof(int), hipMemcpyHostToDevice));
+    if (full) {
+      launch_factor(D.dim, D.patch, 0, P_FP64, 1, L.dd, L.npatch, 0, ctx->d_status, ctx->stream);
+    } else {
+      for (int bi = 0; bi < h.nbk; ++bi)
+        launch_factor(D.dim, D.patch, h.bk[bi].cls, ctx->prec, 0, L.dd, h.bk[bi].count, bi, ctx->d_status,
+                      ctx->stream);
+    }
+    CK(hipGetLastError());
+    int stv = 0;
+    CK(hipMemcpyAsync(&stv, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    if (stv != INT_MAX)
+      return set_err(ctx, RAV_ESINGULAR,
+                     "zero pivot in patch " + std::to_string(stv) + " on level " + std::to_string(l));
+  }
+  ctx->factored = 1;
+  return RAV_OK;
+}
+
+rav_status rav_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free) {
+  if (check_level(ctx, level, false) != RAV_OK) return RAV_EINVAL;
+  const Geo& g = ctx->lv[level].hd.g;
+  if (n_total) *n_total = (long)g.n;
+  if (n_free) {
+    long long masked1 = 0;   // masked nodes per component
+    for (long long i = 0; i < g.nV; ++i) {
+      int a[3] = {0, 0, 0};
+      node_of(g, i, a);
+      if (node_dirichlet(g, a)) ++masked1;
+    }
+    *n_free = (long)(g.n - g.dim * masked1);
+  }
+  return RAV_OK;
+}
+
+rav_status rav_n_levels(const rav_ctx* ctx, int* n) {
+  if (!ctx || !n) return RAV_EINVAL;
+  *n = (int)ctx->lv.size();
+  return RAV_OK;
+}
+
+rav_status rav_n_patches(const rav_ctx* ctx, int level, long* n) {
+  if (check_level(ctx, level, false) != RAV_OK || !n) return RAV_EINVAL;
+  *n = (long)ctx->lv[level].npatch;
+  return RAV_OK;
+}
+
+rav_status rav_assemble_rhs(rav_ctx* ctx, const double* params, int n_params, double* b_dev) {
+  if (!ctx || !params || !b_dev) return RAV_EINVAL;
+  const int need = ctx->desc.dim == 2 ? 25 : 65;
+  if (n_params != need) return set_err(ctx, RAV_EINVAL, "mms parameter array must have " + std::to_string(need) + " entries");
+  LevelHost& L = ctx->lv.back();
+  const Geo& g = L.hd.g;
+  const long long ncell = (long long)g.N * g.N * (g.dim == 3 ? g.N : 1);
+  const int nq = g.dim == 2 ? 9 : 27;
+  double *dp = nullptr, *fq = nullptr;
+  CK(hipMalloc((void**)&dp, sizeof(double) * n_params));
+  CK(hipMalloc((void**)&fq, sizeof(double) * ncell * nq * g.dim));
+  CK(hipMemcpy(dp, params, sizeof(double) * n_params, hipMemcpyHostToDevice));
+  launch_rhs(g.dim, &L.hd, L.dd, dp, fq, b_dev, ctx->stream);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(ctx->stream));
+  CK(hipFree(dp));
+  CK(hipFree(fq));
+  return RAV_OK;
+}
+
+rav_status rav_residual(rav_ctx* ctx, int level, const double* x, const double* b, double* r, double* norm) {
+  if (check_level(ctx, level, false) != RAV_OK || !x || !b || !r) return RAV_EINVAL;
+  LevelHost& L = ctx->lv[level];
+  const long long n = L.hd.g.n;
+  launch_copy(L.hd.x, x, n, ctx->stream);
+  launch_copy(L.hd.b, b, n, ctx->stream);
+  residual_level(ctx, level, norm != nullptr);
+  launch_copy(r, L.hd.r, n, ctx->stream);
+  CK(hipGetLastError());
+  if (norm) return read_norm(ctx, norm);
+  return RAV_OK;
+}
+
+rav_status rav_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const double* b) {
+  if (check_level(ctx, level, true) != RAV_OK || !x || !b || sweeps < 0) return RAV_EINVAL;
+  if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
+  LevelHost& L = ctx->lv[level];
+  const long long n = L.hd.g.n;
+  launch_copy(L.hd.x, x, n, ctx->stream);
+  launch_copy(L.hd.b, b, n, ctx->stream);
+  smooth_level(ctx, level, sweeps);
+  launch_copy(x, L.hd.x, n, ctx->stream);
+  CK(hipGetLastError());
+  return RAV_OK;
+}
+
+rav_status rav_restrict(rav_ctx* ctx, int level, const double* rf, double* bc) {
+  if (check_level(ctx, level, true) != RAV_OK || !rf || !bc) return RAV_EINVAL;
+  LevelHost& L = ctx->lv[level];
+  launch_copy(L.hd.r, rf, L.hd.g.n, ctx->stream);
+  launch_restrict(ctx->desc.dim, L.dd, L.hd.gc.n, ctx->stream);
+  launch_copy(bc, ctx->lv[level - 1].hd.b, L.hd.gc.n, ctx->stream);
+  CK(hipGetLastError());
+  return RAV_OK;
+}
+
+rav_status rav_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf) {
+  if (check_level(ctx, level, true) != RAV_OK || !xc || !xf) return RAV_EINVAL;
+  LevelHost& L = ctx->lv[level];
+  launch_copy(ctx->lv[level - 1].hd.x, xc, L.hd.gc.n, ctx->stream);
+  launch_copy(L.hd.x, xf, L.hd.g.n, ctx->stream);
+  launch_prolong(ctx->desc.dim, L.dd, L.hd.g.n, ctx->stream);
+  launch_copy(xf, L.hd.x, L.hd.g.n, ctx->stream);
+  CK(hipGetLastError());
+  return RAV_OK;
+}
+
+rav_status rav_coarse_solve(rav_ctx* ctx, const double* b0, double* x0) {
+  if (!ctx || !b0 || !x0) return RAV_EINVAL;
+  launch_coarse_gemv(ctx->Minv, ctx->nb, ctx->lv[0].hd.g.n, b0, x0, ctx->stream);
+  CK(hipGetLastError());
+  return RAV_OK;
+}
+
+rav_status rav_vcycle(rav_ctx* ctx, double* x, const double* b) {
+  if (!ctx || !x || !b) return RAV_EINVAL;
+  if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
+  const int lf = (int)ctx->lv.size() - 1;
+  LevelHost& L = ctx->lv[lf];
+  const long long n = L.hd.g.n;
+  launch_copy(L.hd.x, x, n, ctx->stream);
+  launch_copy(L.hd.b, b, n, ctx->stream);
+  vcycle_level(ctx, lf);
+  launch_copy(x, L.hd.x, n, ctx->stream);
+  CK(hipGetLastError());
+  return RAV_OK;
+}
+
+rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int maxit, int* iters,
+                     double* rel_res) {
+  if (!ctx || !x || !b || !(rtol > 0.0) || maxit < 0) return RAV_EINVAL;
+  if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
+  const int lf = (int)ctx->lv.size() - 1;
+  LevelHost& L = ctx->lv[lf];
+  const long long n = L.hd.g.n;
+  launch_copy(L.hd.x, x, n, ctx->stream);
+  launch_copy(L.hd.b, b, n, ctx->stream);
+  residual_level(ctx, lf, true);
+  double r0 = 0.0;
+  rav_status st = read_norm(ctx, &r0);
+  if (st != RAV_OK) return st;
+  if (iters) *iters = 0;
+  if (rel_res) *rel_res = r0 > 0.0 ? 1.0 : 0.0;
+  if (!std::isfinite(r0)) return set_err(ctx, RAV_EDIVERGED, "initial residual is not finite");
+  rav_status result = RAV_NOT_CONVERGED;
+  if (r0 == 0.0) result = RAV_OK;
+  int k = 0;
+  double rk = r0;
+  while (result == RAV_NOT_CONVERGED && k < maxit) {
+    vcycle_level(ctx, lf);
+    residual_level(ctx, lf, true);
+    st = read_norm(ctx, &rk);
+    if (st != RAV_OK) return st;
+    ++k;
+    if (!std::isfinite(rk) || rk > 1e3 * r0) {
+      result = RAV_EDIVERGED;
+      ctx->err = "residual diverged at cycle " + std::to_string(k);
+    } else if (rk <= rtol * r0) {
+      result = RAV_OK;
+    }
+  }
+  if (iters) *iters = k;
+  if (rel_res) *rel_res = r0 > 0.0 ? rk / r0 : 0.0;
+  launch_copy(x, L.hd.x, n, ctx->stream);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(ctx->stream));
+  return result;
+}
+
+rav_status rav_set_params(rav_ctx* ctx, double omega, int nu_pre, int nu_post) {
+  if (!ctx || !(omega > 0.0) || nu_pre < 0 || nu_post < 0) return RAV_EINVAL;
+  ctx->desc.omega = omega;
+  ctx->desc.nu_pre = nu_pre;
+  ctx->desc.nu_post = nu_post;
+  for (LevelHost& L : ctx->lv) {
+    L.hd.omega = omega;
+    rav_status st = upload_desc(ctx, L);
+    if (st != RAV_OK) return st;
+  }
+  return RAV_OK;
+}
+
+rav_status rav_set_patch_omega(rav_ctx* ctx, int level, const float* omega_dev) {
+  if (check_level(ctx, level, true) != RAV_OK) return RAV_EINVAL;
+  ctx->lv[level].hd.omega_patch = omega_dev;
+  return upload_desc(ctx, ctx->lv[level]);
+}
+
+static rav_status map_patch_geo(const Geo& g, int kind, long long npatch, long patch, int* dofs, int* n,
+                                int* owned) {
+  if (patch < 0 || patch >= npatch || !dofs || !n) return RAV_EINVAL;
+  int k[3] = {0, 0, 0};
+  patch_anchor(g, kind, patch, k);
+  const int npad = patch_npad(g.dim, kind);
+  int cnt = 0;
+  for (int l = 0; l < npad; ++l) {
+    int comp, node[3];
+    const long long gi = patch_local_dof(g, kind, k, l, &comp, node);
+    if (gi < 0) continue;
+    dofs[cnt] = (int)gi;
+    if (owned) owned[cnt] = owner_of(g, kind, gi) == patch ? 1 : 0;
+    ++cnt;
+  }
+  *n = cnt;
+  return RAV_OK;
+}
+
+static rav_status desc_geo(const rav_problem_desc* d, int level, Geo* g) {
+  if (!d || (d->dim != 2 && d->dim != 3) || d->n_levels < 1 || d->n_levels > 20 || level < 0 ||
+      level >= d->n_levels || d->n_cells <= 0 || d->n_cells % (1 << (d->n_levels - 1)) ||
+      (d->patch != RAV_PATCH_VERTEX && d->patch != RAV_PATCH_ELEMENT))
+    return RAV_EINVAL;
+  *g = make_geo(d->dim, d->n_cells >> (d->n_levels - 1 - level), d->bc_dirichlet_mask);
+  return RAV_OK;
+}
+
+rav_status rav_map_patch(const rav_problem_desc* d, int level, long patch, int* dofs, int* n, int* owned) {
+  Geo g;
+  if (desc_geo(d, level, &g) != RAV_OK) return RAV_EINVAL;
+  return map_patch_geo(g, d->patch, n_patches(g, d->patch), patch, dofs, n, owned);
+}
+
+rav_status rav_map_owner(const rav_problem_desc* d, int level, int* owner) {
+  Geo g;
+  if (desc_geo(d, level, &g) != RAV_OK || !owner) return RAV_EINVAL;
+  for (long long i = 0; i < g.n; ++i) {
+    if (i < g.dim * g.nV) {
+      int a[3] = {0, 0, 0};
+      node_of(g, i % g.nV, a);
+      if (node_dirichlet(g, a)) { owner[i] = -1; continue; }
+    }
+    owner[i] = (int)owner_of(g, d->patch, i);
+  }
+  return RAV_OK;
+}
+
+rav_status rav_get_patch_map(const rav_ctx* ctx, int level, long patch, int* dofs, int* n, int* owned) {
+  if (check_level(ctx, level, false) != RAV_OK) return RAV_EINVAL;
+  const LevelHost& L = ctx->lv[level];
+  return map_patch_geo(L.hd.g, ctx->desc.patch, L.npatch, patch, dofs, n, owned);
+}
+
+rav_status rav_get_owner(rav_ctx* ctx, int level, int* owner_dev) {
+  if (check_level(ctx, level, false) != RAV_OK || !owner_dev) return RAV_EINVAL;
+  LevelHost& L = ctx->lv[level];
+  launch_owner(L.dd, ctx->desc.patch, L.hd.g.n, owner_dev, ctx->stream);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(ctx->stream));
+  return RAV_OK;
+}
+
+rav_status rav_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* out, int* rows, int* cols) {
+  if (check_level(ctx, level, true) != RAV_OK || !out || !rows || !cols) return RAV_EINVAL;
+  if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
+  LevelHost& L = ctx->lv[level];
+  if (patch < 0 || patch >= L.npatch) return RAV_EINVAL;
+  const Geo& g = L.hd.g;
+  const int kind = ctx->desc.patch;
+  const int npad = patch_npad(g.dim, kind);
+  int k[3] = {0, 0, 0};
+  patch_anchor(g, kind, patch, k);
+  std::vector<int> vcol;
+  for (int c = 0; c < npad; ++c) {
+    int comp, node[3];
+    if (patch_local_dof(g, kind, k, c, &comp, node) >= 0) vcol.push_back(c);
+  }
+  CK(hipStreamSynchronize(ctx->stream));
+  if (ctx->desc.smoother != RAV_SMOOTHER_RAV) {
+    std::vector<double> A((size_t)npad * npad);
+    CK(hipMemcpy(A.data(), L.hd.Winv + (long long)patch * npad * npad, sizeof(double) * A.size(),
+                 hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < vcol.size(); ++i)
+      for (size_t j = 0; j < vcol.size(); ++j) out[i * vcol.size() + j] = A[(size_t)vcol[j] * npad + vcol[i]];
+    *rows = *cols = (int)vcol.size();
+    return RAV_OK;
+  }
+  const int cls = kind == KIND_VERTEX ? 0 : element_class(g, k);
+  int bi = -1;
+  for (int i = 0; i < L.hd.nbk; ++i)
+    if (L.hd.bk[i].cls == cls) bi = i;
+  if (bi < 0) return set_err(ctx, RAV_EINVAL, "patch bucket not found");
+  const Bucket& B = L.hd.bk[bi];
+  const long long pos = kind == KIND_VERTEX ? patch : bucket_pos(g, cls, k);
+  const int V = ctx->prec == P_FP64 ? 2 : ctx->prec == P_FP32 ? 4 : 8;
+  const size_t esz = ctx->prec == P_FP64 ? 8 : ctx->prec == P_FP32 ? 4 : 2;
+  std::vector<double> W((size_t)B.nchunk * V);
+  std::vector<unsigned char> chunk(16);
+  for (long long m = 0; m < B.nchunk; ++m) {
+    CK(hipMemcpy(chunk.data(), (const char*)B.W + esz * (size_t)(m * B.wstride + pos * V), 16,
+                 hipMemcpyDeviceToHost));
+    for (int v = 0; v < V; ++v) {
+      double val;
+      if (esz == 8) { double t; std::memcpy(&t, chunk.data() + 8 * v, 8); val = t; }
+      else if (esz == 4) { float t; std::memcpy(&t, chunk.data() + 4 * v, 4); val = t; }
+      else { unsigned short u; std::memcpy(&u, chunk.data() + 2 * v, 2); unsigned bits = (unsigned)u << 16; float t; std::memcpy(&t, &bits, 4); val = t; }
+      W[(size_t)m * V + v] = val;
+    }
+  }
+  int nr = 0;
+  for (int j = 0; j < B.nown; ++j) {
+    const int l = bucket_own_local(g.dim, kind, cls, j);
+    int comp, node[3];
+    if (patch_local_dof(g, kind, k, l, &comp, node) < 0) continue;
+    for (size_t c = 0; c < vcol.size(); ++c) out[(size_t)nr * vcol.size() + c] = W[(size_t)vcol[c] * B.nown + j];
+    ++nr;
+  }
+  *rows = nr;
+  *cols = (int)vcol.size();
+  return RAV_OK;
+}
+
+rav_status rav_export_matrix(rav_ctx* ctx, int level, double* out) {
+  if (check_level(ctx, level, false) != RAV_OK || !out) return RAV_EINVAL;
+  LevelHost& L = ctx->lv[level];
+  const long long n = L.hd.g.n;
+  if (n > 20000) return set_err(ctx, RAV_EINVAL, "level too large for a dense export");
+  double* M = nullptr;
+  CK(hipMalloc((void**)&M, sizeof(double) * n * n));
+  launch_coarse_build(L.dd, ctx->desc.dim, M, n, 0, 0, ctx->stream);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(ctx->stream));
+  CK(hipMemcpy(out, M, sizeof(double) * n * n, hipMemcpyDeviceToHost));
+  CK(hipFree(M));
+  return RAV_OK;
+}
+
+rav_status rav_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const double* b, float* ms_res,
+                          float* ms_apply) {
+  if (check_level(ctx, level, true) != RAV_OK || !x || !b || reps <= 0) return RAV_EINVAL;
+  if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
+  if (ctx->desc.smoother == RAV_SMOOTHER_MV) return set_err(ctx, RAV_EUNSUPPORTED, "MV has no separate residual kernel");
+  LevelHost& L = ctx->lv[level];
+  const long long n = L.hd.g.n;
+  launch_copy(L.hd.x, x, n, ctx->stream);
+  launch_copy(L.hd.b, b, n, ctx->stream);
+  std::vector<hipEvent_t> ev(3 * reps);
+  for (auto& e : ev) CK(hipEventCreate(&e));
+  for (int i = 0; i < reps; ++i) {
+    CK(hipEventRecord(ev[3 * i], ctx->stream));
+    residual_level(ctx, level, false);
+    CK(hipEventRecord(ev[3 * i + 1], ctx->stream));
+    apply_level(ctx, level);
+    CK(hipEventRecord(ev[3 * i + 2], ctx->stream));
+  }
+  CK(hipEventSynchronize(ev.back()));
+  double tr = 0.0, ta = 0.0;
+  for (int i = 0; i < reps; ++i) {
+    float a = 0.f, c = 0.f;
+    CK(hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]));
+    CK(hipEventElapsedTime(&c, ev[3 * i + 1], ev[3 * i + 2]));
+    tr += a;
+    ta += c;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (ms_res) *ms_res = (float)(tr / reps);
+  if (ms_apply) *ms_apply = (float)(ta / reps);
+  launch_copy(x, L.hd.x, n, ctx->stream);
+  CK(hipStreamSynchronize(ctx->stream));
+  return RAV_OK;
+}
+
+rav_status rav_stream_copy(void* stream, double* dst, const double* src, long n) {
+  if (!dst || !src || n < 0) return RAV_EINVAL;
+  launch_copy(dst, src, n, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? RAV_OK : RAV_EDEVICE;
+}
+
+rav_status rav_destroy(rav_ctx* ctx) {
+  if (!ctx) return RAV_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (LevelHost& L : ctx->lv) {
+    GridDev& h = L.hd;
+    (void)hipFree(h.x); (void)hipFree(h.b); (void)hipFree(h.r); (void)hipFree(h.vals);
+    (void)hipFree(h.Winv); (void)hipFree(h.Y);
+    for (int i = 0; i < h.nbk; ++i) (void)hipFree(h.bk[i].W);
+    (void)hipFree(L.dd); (void)hipFree(L.res_tasks); (void)hipFree(L.partials);
+    for (ApplyLaunch& a : L.apply) (void)hipFree(a.tasks);
+  }
+  (void)hipFree(ctx->d_incl); (void)hipFree(ctx->Minv); (void)hipFree(ctx->d_status);
+  (void)hipFree(ctx->d_piv); (void)hipFree(ctx->d_colk); (void)hipFree(ctx->d_norm);
+  if (ctx->h_norm) (void)hipHostFree(ctx->h_norm);
+  delete ctx;
+  return RAV_OK;
+}
+
+const char* rav_last_error(const rav_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Internal device-side descriptors of the RAV library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "rav_index.h"
+
+namespace rav {
+
+constexpr int MAX_SEG = 25;      // 3 components x 8 parity types + pressure
+constexpr int MAX_BUCKETS = 8;
+constexpr int MAX_INCL = 64;
+constexpr int BLOCK = 256;       // threads per block of the streaming kernels
+
+enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
+
+// Owned inverse rows of one bucket of patches (same owned pattern).
+// Entry e = c * nown + j (column c of the padded patch, owned row j) of patch p
+// lives at W[(e / V) * wstride + p * V + e % V] with V = 16 bytes / element
+// size, so a wavefront streaming one chunk of 64 patches reads 1 KiB
+// contiguously.
+struct Bucket {
+  int cls;
+  int nown;
+  long long count;       // patches in the bucket
+  long long count_pad;   // rounded up to a multiple of 64
+  long long nchunk;      // ceil(npad * nown / V)
+  long long wstride;     // count_pad * V (elements)
+  void* W;
+};
+
+// One level of one problem, resident in device memory.
+struct GridDev {
+  Geo g;
+  int kind;
+  double h;
+  double* x;             // level iterate
+  double* b;             // level right-hand side
+  double* r;             // level residual
+  double* vals;          // ELL operator values
+  long long seg_off[MAX_SEG];
+  long long seg_rows[MAX_SEG];
+  // coarser level (transfer target), valid when has_coarse
+  int has_coarse;
+  Geo gc;
+  double* xc;
+  double* bc;
+  // smoother data
+  int nbk;
+  Bucket bk[MAX_BUCKETS];
+  double* Winv;          // AV/MV: full local inverses, [patch][npad][npad], column-major per patch
+  double* Y;             // AV: per-patch corrections [patch][npad]
+  const float* omega_patch;
+  double omega;
+};
+
+// One block of a streaming launch.  `part` selects the ELL segment or patch
+// bucket, `start` the first row/patch of the tile, `logical` the tile's
+// position in grid order (blocks are permuted so that each XCD walks a
+// contiguous range of tiles), grid = -1 marks padding blocks.
+struct BlockTask {
+  int grid;
+  int part;
+  long long start;
+  int logical;
+  int pad;
+};
+
+// Reference-element tables (filled on the host from the Lagrange bases).
+struct RefTables {
+  double gt[3], gw[3];            // 3-point Gauss on [0,1]
+  double phi[3][3], dphi[3][3];   // Q2 1D basis / derivative [node][qp]
+  double psi[2][3];               // Q1 1D basis [node][qp]
+  double aref2[9][9];             // sum_q w_q grad.grad, 2D reference cell (h = 1)
+  double aref3[27][27];
+  double bref2[2][9][4];          // -sum_q w_q psi_k d_c phi_a (h = 1)
+  double bref3[3][27][8];
+};
+
+// ---- kernel launchers (defined in the .hip files) --------------------------
+void set_ref_tables(const RefTables& t, hipStream_t s);
+
+void launch_assemble(int dim, long long ncell, const GridDev* G, const BlockTask* tasks, int ntasks,
+                     const double* incl, int n_incl, double eta_out, double eta_in, double* etaq,
+                     unsigned char* uni, hipStream_t s);
+void launch_rhs(int dim, const GridDev* Gh, const GridDev* Gd, const double* params, double* fq,
+                double* b, hipStream_t s);
+void launch_residual(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, double* partials,
+                     hipStream_t s);
+void launch_norm_finalize(const double* partials, int first, int count, double* out, hipStream_t s);
+void launch_rav_apply(int dim, int kind, int cls, int prec, const GridDev* G, const BlockTask* tasks,
+                      int ntasks, hipStream_t s);
+void launch_factor(int dim, int kind, int cls, int prec, int full, const GridDev* G, long long count,
+                   int bucket, int* status, hipStream_t s);
+void launch_av_apply(int dim, int kind, const GridDev* G, long long npatch, hipStream_t s);
+void launch_av_gather(int dim, int kind, const GridDev* G, long long n, hipStream_t s);
+void launch_mv_colour(int dim, int kind, const GridDev* G, int colour, long long npatch_colour,
+                      hipStream_t s);
+void launch_restrict(int dim, const GridDev* G, long long nc, hipStream_t s);
+void launch_prolong(int dim, const GridDev* G, long long nf, hipStream_t s);
+void launch_coarse_build(const GridDev* G, int dim, double* M, long long nb, int bordered, int unit_masked,
+                         hipStream_t s);
+void launch_coarse_gj_step(double* M, long long nb, long long k, int* piv, double* colk, int* status,
+                           hipStream_t s);
+void launch_coarse_colswap(double* M, long long nb, const int* piv, hipStream_t s);
+void launch_coarse_gemv(const double* Minv, long long nb, long long n0, const double* b, double* x,
+                        hipStream_t s);
+void launch_owner(const GridDev* G, int kind, long long n, int* owner, hipStream_t s);
+void launch_copy(double* dst, const double* src, long long n, hipStream_t s);
+void launch_fill(double* dst, double v, long long n, hipStream_t s);
+
+}  // namespace rav
