@@ -185,10 +185,42 @@ rav_status rav_export_matrix(rav_ctx* ctx, int level, double* out_host);
 rav_status rav_time_sweep(rav_ctx* ctx, int level, int reps, double* x_dev, const double* b_dev,
                           float* ms_residual, float* ms_apply);
 
+/* Kernel timing during ordinary calls: after rav_profile_begin, every smoother
+ * residual launch and patch-apply launch on `level` (up to max_launches of
+ * each) is bracketed by HIP events recorded on the context stream.
+ * rav_profile_end synchronises, stops recording and returns the average
+ * duration in ms of the residual launches, of the apply launches (all buckets
+ * of one sweep count as one launch) and how many apply launches were timed. */
+rav_status rav_profile_begin(rav_ctx* ctx, int level, int max_launches);
+rav_status rav_profile_end(rav_ctx* ctx, float* avg_residual_ms, float* avg_apply_ms, int* n_apply);
+
 /* Plain device copy of n doubles on hip_stream (bandwidth calibration). */
 rav_status rav_stream_copy(void* hip_stream, double* dst_dev, const double* src_dev, long n);
 
 rav_status rav_destroy(rav_ctx* ctx);
+
+/* ---- batched problems -------------------------------------------------------
+ * Many independent problems solved together with RAV V-cycles (the additive,
+ * order-free sweep of eq. 13 lets the patches of all problems share one
+ * launch per V-cycle stage).  All descriptors must share dim, patch kind,
+ * smoother (RAV), inverse precision, smoothing steps and the coarsest grid
+ * size n_cells / 2^(n_levels-1); grid sizes, level counts, viscosity fields
+ * and omega may differ.  x_dev / b_dev are host arrays of n_problems device
+ * pointers, each holding that problem's finest-level vector.  Problems stop
+ * being updated once converged; iters and rel_res (host arrays of n_problems)
+ * receive per-problem results.  The batch owns one context per problem. */
+typedef struct rav_batch rav_batch;
+rav_status rav_batch_create(const rav_problem_desc* descs, int n_problems, void* hip_stream, rav_batch** out);
+rav_status rav_batch_factor(rav_batch* batch);
+rav_status rav_batch_size(const rav_batch* batch, int* n_problems);
+rav_status rav_batch_dofs(const rav_batch* batch, int problem, long* n_total, long* n_free);
+rav_status rav_batch_assemble_rhs(rav_batch* batch, int problem, const double* mms_params_host, int n_params,
+                                  double* b_dev);
+rav_status rav_batch_vcycle(rav_batch* batch, double* const* x_dev, const double* const* b_dev);
+rav_status rav_batch_solve(rav_batch* batch, double* const* x_dev, const double* const* b_dev, double rtol,
+                           int maxit, int* iters, double* rel_res);
+rav_status rav_batch_destroy(rav_batch* batch);
+const char* rav_batch_last_error(const rav_batch* batch);
 
 /* Message of the last hard error on ctx (or of the last failed rav_create
  * when ctx is NULL).  Valid until the next call on the same context. */

@@ -74,7 +74,20 @@ SIGNATURES = {
     "rav_export_matrix": (_S, [_P, _I, ctypes.POINTER(_D)]),
     "rav_time_sweep": (_S, [_P, _I, _I, _P, _P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "rav_stream_copy": (_S, [_P, _P, _P, _L]),
+    "rav_profile_begin": (_S, [_P, _I, _I]),
+    "rav_profile_end": (_S, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(_I)]),
     "rav_destroy": (_S, [_P]),
+    "rav_batch_create": (_S, [ctypes.POINTER(RavProblemDesc), _I, _P, ctypes.POINTER(_P)]),
+    "rav_batch_factor": (_S, [_P]),
+    "rav_batch_size": (_S, [_P, ctypes.POINTER(_I)]),
+    "rav_batch_dofs": (_S, [_P, _I, ctypes.POINTER(_L), ctypes.POINTER(_L)]),
+    "rav_batch_assemble_rhs": (_S, [_P, _I, ctypes.POINTER(_D), _I, _P]),
+    "rav_batch_vcycle": (_S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "rav_batch_solve": (_S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _I, ctypes.POINTER(_I),
+                             ctypes.POINTER(_D)]),
+    "rav_batch_destroy": (_S, [_P]),
+    "rav_batch_last_error": (ctypes.c_char_p, [_P]),
     "rav_last_error": (ctypes.c_char_p, [_P]),
 }
 
@@ -240,10 +253,105 @@ class Hierarchy:
         self._chk(self.lib.rav_export_matrix(self.h, level, out.ctypes.data_as(ctypes.POINTER(_D))))
         return out
 
+    def profile_begin(self, level, max_launches=4096):
+        return self._chk(self.lib.rav_profile_begin(self.h, level, max_launches))
+
+    def profile_end(self):
+        a, c, n = ctypes.c_float(), ctypes.c_float(), _I()
+        self._chk(self.lib.rav_profile_end(self.h, ctypes.byref(a), ctypes.byref(c), ctypes.byref(n)))
+        return a.value, c.value, n.value
+
     def time_sweep(self, level, reps, x, b):
         a, c = ctypes.c_float(), ctypes.c_float()
         self._chk(self.lib.rav_time_sweep(self.h, level, reps, _ptr(x), _ptr(b), ctypes.byref(a), ctypes.byref(c)))
         return a.value, c.value
+
+
+class Batch:
+    """Many independent problems solved together (one ``rav_batch``).
+
+    ``problems`` is a list of dicts with the keyword arguments of
+    :class:`Hierarchy` (dim, n_cells, n_levels, dmask, omega, eta_out, eta_in,
+    inclusions, precision, nu_pre, nu_post)."""
+
+    def __init__(self, problems, stream=None):
+        self.lib = lib()
+        n = len(problems)
+        self.descs = (RavProblemDesc * n)()
+        self._keep = []
+        for i, p in enumerate(problems):
+            dim = p.get("dim", 2)
+            incl = p.get("inclusions")
+            incl = np.zeros((0, 4)) if incl is None else np.asarray(incl, dtype=np.float64)
+            if incl.size and incl.shape[1] == dim + 1:
+                full = np.zeros((len(incl), 4))
+                full[:, :dim] = incl[:, :dim]
+                full[:, 3] = incl[:, dim]
+                incl = full
+            arr = (RavInclusion * max(len(incl), 1))()
+            for j, row in enumerate(incl):
+                arr[j] = RavInclusion(*row)
+            self._keep.append(arr)
+            self.descs[i] = RavProblemDesc(dim, p["n_cells"], p["n_levels"], p.get("dmask", 0b1111),
+                                           p.get("eta_out", 1.0), p.get("eta_in", 1.0), len(incl),
+                                           ctypes.cast(arr, ctypes.POINTER(RavInclusion)),
+                                           KINDS[p.get("kind", "vertex")], SMOOTHERS["rav"], p.get("omega", 0.66),
+                                           p.get("nu_pre", 2), p.get("nu_post", 2),
+                                           PRECISIONS[p.get("precision", "fp64")])
+        self.n = n
+        self.stream = _stream() if stream is None else stream
+        h = _P()
+        st = self.lib.rav_batch_create(self.descs, n, self.stream, ctypes.byref(h))
+        if st < 0:
+            raise RavError(st, self.lib.rav_batch_last_error(None).decode())
+        self.h = h
+
+    def _chk(self, st):
+        if st < 0:
+            raise RavError(st, self.lib.rav_batch_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rav_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def factor(self):
+        return self._chk(self.lib.rav_batch_factor(self.h))
+
+    def dofs(self, problem):
+        nt, nf = _L(), _L()
+        self._chk(self.lib.rav_batch_dofs(self.h, problem, ctypes.byref(nt), ctypes.byref(nf)))
+        return nt.value, nf.value
+
+    def assemble_rhs(self, problem, params, b):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        return self._chk(self.lib.rav_batch_assemble_rhs(self.h, problem, p.ctypes.data_as(ctypes.POINTER(_D)),
+                                                         len(p), _ptr(b)))
+
+    @staticmethod
+    def _ptrs(ts):
+        arr = (_P * len(ts))()
+        for i, t in enumerate(ts):
+            arr[i] = _ptr(t)
+        return arr
+
+    def vcycle(self, xs, bs):
+        return self._chk(self.lib.rav_batch_vcycle(self.h, self._ptrs(xs), self._ptrs(bs)))
+
+    def solve(self, xs, bs, rtol=1e-8, maxit=200):
+        its = (_I * self.n)()
+        rel = (_D * self.n)()
+        st = self.lib.rav_batch_solve(self.h, self._ptrs(xs), self._ptrs(bs), rtol, maxit, its, rel)
+        if st < 0 and st != -4:
+            self._chk(st)
+        return st, list(its), list(rel)
 
 
 def make_desc(dim=2, n_cells=32, n_levels=3, dmask=0b1111, kind="vertex", smoother="rav", omega=0.66,

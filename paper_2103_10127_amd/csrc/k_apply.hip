@@ -83,8 +83,11 @@ __host__ __device__ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_
 // Columns are processed in groups of G = V / gcd(nown, V) so that every group
 // starts on a 16-byte chunk boundary: the group loop runs at run time (small
 // code, bounded registers), the chunks inside a group and the ragged tail are
-// unrolled at compile time.
-template <int DIM, int KIND, int CLS, typename WT>
+// unrolled at compile time.  SPLIT lanes share one patch (column groups dealt
+// round-robin, partial sums combined with shuffles): SPLIT = 1 streams the
+// large levels, SPLIT = 8 shortens the dependent load chain on small levels
+// where too few wavefronts exist to hide memory latency.
+template <int DIM, int KIND, int CLS, typename WT, int SPLIT>
 __global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__ G,
                                                       const BlockTask* __restrict__ tasks) {
   typedef typename WTraits<WT>::acc_t acc_t;
@@ -101,9 +104,11 @@ __global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__
   const BlockTask t = tasks[blockIdx.x];
   if (t.grid < 0) return;
   const GridDev& gd = G[t.grid];
+  if (grid_idle(gd)) return;
   const Bucket& bk = gd.bk[t.part];
-  const long long p = t.start + threadIdx.x;
-  if (p >= bk.count) return;
+  const int sl = SPLIT > 1 ? (int)(threadIdx.x % SPLIT) : 0;
+  const long long p = t.start + threadIdx.x / SPLIT;
+  if (p >= bk.count) return;   // whole groups of SPLIT lanes leave together
   const Geo& g = gd.g;
   int k[3] = {0, 0, 0};
   bucket_anchor(g, KIND, CLS, p, k);
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__
 #pragma unroll
   for (int j = 0; j < NOWN; ++j) acc[j] = acc_t(0);
 #pragma unroll 1
-  for (int gi = 0; gi < NG; ++gi) {
+  for (int gi = sl; gi < NG; gi += SPLIT) {
     vec_t w[CPG];
 #pragma unroll
     for (int i = 0; i < CPG; ++i) w[i] = __builtin_nontemporal_load(W + (long long)(gi * CPG + i) * cs);
@@ -134,22 +139,32 @@ __global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__
     }
   }
   if constexpr (TAIL > 0) {
-    vec_t w[TAIL_CH];
+    if (sl == SPLIT - 1) {
+      vec_t w[TAIL_CH];
 #pragma unroll
-    for (int i = 0; i < TAIL_CH; ++i) w[i] = __builtin_nontemporal_load(W + (long long)(NG * CPG + i) * cs);
-    acc_t rv[TAIL];
+      for (int i = 0; i < TAIL_CH; ++i) w[i] = __builtin_nontemporal_load(W + (long long)(NG * CPG + i) * cs);
+      acc_t rv[TAIL];
 #pragma unroll
-    for (int q = 0; q < TAIL; ++q) {
-      const long long col = patch_col<DIM, KIND>(g, k, NG * GC + q);
-      rv[q] = col >= 0 ? acc_t(r[col]) : acc_t(0);
+      for (int q = 0; q < TAIL; ++q) {
+        const long long col = patch_col<DIM, KIND>(g, k, NG * GC + q);
+        rv[q] = col >= 0 ? acc_t(r[col]) : acc_t(0);
+      }
+#pragma unroll
+      for (int el = 0; el < TAIL_E; ++el) acc[el % NOWN] += vec_elem<WT>(w[el / V], el % V) * rv[el / NOWN];
     }
+  }
+  if constexpr (SPLIT > 1) {
 #pragma unroll
-    for (int el = 0; el < TAIL_E; ++el) acc[el % NOWN] += vec_elem<WT>(w[el / V], el % V) * rv[el / NOWN];
+    for (int j = 0; j < NOWN; ++j) {
+#pragma unroll
+      for (int o = SPLIT / 2; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o, SPLIT);
+    }
   }
   const double om = gd.omega_patch ? (double)gd.omega_patch[patch_lin(g, KIND, k)] : gd.omega;
   double* __restrict__ x = gd.x;
 #pragma unroll
   for (int j = 0; j < NOWN; ++j) {
+    if (SPLIT > 1 && (j % SPLIT) != sl) continue;
     const int l = bucket_own_local(DIM, KIND, CLS, j);
     int comp, node[3];
     const long long gi = patch_local_dof(g, KIND, k, l, &comp, node);
@@ -157,14 +172,14 @@ __global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__
   }
 }
 
-template <int DIM, int KIND, typename WT>
+template <int DIM, int KIND, typename WT, int SPLIT>
 static void launch_apply_t(int cls, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
-#define RAV_APPLY_CASE(C)                                                                          \
-  case C:                                                                                         \
-    hipLaunchKernelGGL((k_rav_apply<DIM, KIND, C, WT>), dim3(ntasks), dim3(BLOCK), 0, s, G, tasks); \
+#define RAV_APPLY_CASE(C)                                                                                 \
+  case C:                                                                                                \
+    hipLaunchKernelGGL((k_rav_apply<DIM, KIND, C, WT, SPLIT>), dim3(ntasks), dim3(BLOCK), 0, s, G, tasks); \
     break;
   if constexpr (KIND == KIND_VERTEX) {
-    hipLaunchKernelGGL((k_rav_apply<DIM, KIND, 0, WT>), dim3(ntasks), dim3(BLOCK), 0, s, G, tasks);
+    hipLaunchKernelGGL((k_rav_apply<DIM, KIND, 0, WT, SPLIT>), dim3(ntasks), dim3(BLOCK), 0, s, G, tasks);
   } else if constexpr (DIM == 2) {
     switch (cls) {
       RAV_APPLY_CASE(0)
@@ -189,18 +204,25 @@ static void launch_apply_t(int cls, const GridDev* G, const BlockTask* tasks, in
 #undef RAV_APPLY_CASE
 }
 
-template <int DIM, int KIND>
+template <int DIM, int KIND, int SPLIT>
 static void launch_apply_k(int cls, int prec, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
-  if (prec == P_FP64) launch_apply_t<DIM, KIND, double>(cls, G, tasks, ntasks, s);
-  else if (prec == P_FP32) launch_apply_t<DIM, KIND, float>(cls, G, tasks, ntasks, s);
-  else launch_apply_t<DIM, KIND, bf16_t>(cls, G, tasks, ntasks, s);
+  if (prec == P_FP64) launch_apply_t<DIM, KIND, double, SPLIT>(cls, G, tasks, ntasks, s);
+  else if (prec == P_FP32) launch_apply_t<DIM, KIND, float, SPLIT>(cls, G, tasks, ntasks, s);
+  else launch_apply_t<DIM, KIND, bf16_t, SPLIT>(cls, G, tasks, ntasks, s);
 }
 
-void launch_rav_apply(int dim, int kind, int cls, int prec, const GridDev* G, const BlockTask* tasks, int ntasks,
-                      hipStream_t s) {
-  if (dim == 2 && kind == KIND_VERTEX) launch_apply_k<2, KIND_VERTEX>(cls, prec, G, tasks, ntasks, s);
-  else if (dim == 2) launch_apply_k<2, KIND_ELEMENT>(cls, prec, G, tasks, ntasks, s);
-  else launch_apply_k<3, KIND_ELEMENT>(cls, prec, G, tasks, ntasks, s);
+template <int SPLIT>
+static void launch_apply_s(int dim, int kind, int cls, int prec, const GridDev* G, const BlockTask* tasks,
+                           int ntasks, hipStream_t s) {
+  if (dim == 2 && kind == KIND_VERTEX) launch_apply_k<2, KIND_VERTEX, SPLIT>(cls, prec, G, tasks, ntasks, s);
+  else if (dim == 2) launch_apply_k<2, KIND_ELEMENT, SPLIT>(cls, prec, G, tasks, ntasks, s);
+  else launch_apply_k<3, KIND_ELEMENT, SPLIT>(cls, prec, G, tasks, ntasks, s);
+}
+
+void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const GridDev* G, const BlockTask* tasks,
+                      int ntasks, hipStream_t s) {
+  if (split > 1) launch_apply_s<APPLY_SPLIT>(dim, kind, cls, prec, G, tasks, ntasks, s);
+  else launch_apply_s<1>(dim, kind, cls, prec, G, tasks, ntasks, s);
 }
 
 // ---- AV ---------------------------------------------------------------------
@@ -239,8 +261,9 @@ __global__ __launch_bounds__(256) void k_av_gather(const GridDev* __restrict__ G
   int a[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   int comp;
   if (i < DIM * g.nV) {
-    comp = (int)(i / g.nV);
-    node_of(g, i % g.nV, a);
+    long long nl_;
+    comp = split_vel(g, i, &nl_);
+    node_of(g, nl_, a);
     if (node_dirichlet(g, a)) return;
     for (int d = 0; d < DIM; ++d) {
       if (KIND == KIND_VERTEX) {   // 2k - 2 <= a <= 2k + 2
@@ -290,9 +313,10 @@ __device__ double row_times_x(const GridDev& gd, long long R) {
   const Geo& g = gd.g;
   double acc = 0.0;
   if (R < DIM * g.nV) {
-    const int c = (int)(R / g.nV);
+    long long nl_;
+    const int c = split_vel(g, R, &nl_);
     int a[3] = {0, 0, 0};
-    node_of(g, R % g.nV, a);
+    node_of(g, nl_, a);
     const int t = node_type(g, a);
     const int s = c * (1 << DIM) + t;
     const long long rows = gd.seg_rows[s], row = vel_seg_row(g, t, a);

@@ -305,9 +305,10 @@ __global__ __launch_bounds__(256) void k_rhs_gather(const GridDev* G, const doub
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i >= g.n) return;
   if (i >= DIM * g.nV) { b[i] = 0.0; return; }
-  int c = (int)(i / g.nV);
+  long long nl_;
+  const int c = split_vel(g, i, &nl_);
   int a[3] = {0, 0, 0};
-  node_of(g, i % g.nV, a);
+  node_of(g, nl_, a);
   if (node_dirichlet(g, a)) { b[i] = 0.0; return; }
   double hd = 1.0;
   for (int d = 0; d < DIM; ++d) hd *= G->h;

@@ -29,9 +29,10 @@ __global__ __launch_bounds__(256) void k_coarse_build(const GridDev* __restrict_
   double* row = M + R * nb;
   if (bordered) row[g.n] = (R >= DIM * g.nV) ? 1.0 : 0.0;
   if (R < DIM * g.nV) {
-    const int c = (int)(R / g.nV);
+    long long nl_;
+    const int c = split_vel(g, R, &nl_);
     int a[3] = {0, 0, 0};
-    node_of(g, R % g.nV, a);
+    node_of(g, nl_, a);
     if (node_dirichlet(g, a)) { row[R] = unit_masked ? 1.0 : 0.0; return; }
     const int t = node_type(g, a);
     const int s = c * (1 << DIM) + t;
@@ -162,6 +163,30 @@ __global__ __launch_bounds__(256) void k_coarse_gemv(const double* __restrict__ 
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if (lane == 0) x[row] = s;
+}
+
+// Batched coarse solve: task = (problem, block of 4 rows), one wavefront per row.
+__global__ __launch_bounds__(256) void k_coarse_gemv_batch(const GridDev* __restrict__ G,
+                                                            const BlockTask* __restrict__ tasks) {
+  const BlockTask t = tasks[blockIdx.x];
+  if (t.grid < 0) return;
+  const GridDev& gd = G[t.grid];
+  if (grid_idle(gd)) return;
+  const long long n0 = gd.g.n;
+  const long long row = t.start + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n0) return;
+  const double* m = gd.Minv + row * gd.nbc;
+  const double* b = gd.b;
+  double s = 0.0;
+  for (long long j = lane; j < n0; j += 64) s += m[j] * b[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) gd.x[row] = s;
+}
+
+void launch_coarse_gemv_batch(const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_gemv_batch, dim3(ntasks), dim3(256), 0, s, G, tasks);
 }
 
 void launch_coarse_build(const GridDev* G, int dim, double* M, long long nb, int bordered, int unit_masked,

@@ -125,6 +125,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                                                      double* __restrict__ partials) {
   const BlockTask t = tasks[blockIdx.x];
   if (t.grid < 0) return;   // padding block of the XCD permutation (whole block)
+  if (grid_idle(G[t.grid])) return;
   double sq = 0.0;
   {
     const GridDev& gd = G[t.grid];
@@ -177,6 +178,34 @@ __global__ __launch_bounds__(256) void k_norm_finalize(const double* __restrict_
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// One block per problem: out[g] = sum of partials[first[g] .. first[g] + count[g]).
+__global__ __launch_bounds__(256) void k_norm_finalize_batch(const double* __restrict__ partials,
+                                                              const int* __restrict__ first,
+                                                              const int* __restrict__ count,
+                                                              double* __restrict__ out) {
+  __shared__ double red[256];
+  const int gidx = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count[gidx]; i += 256) s += partials[first[gidx] + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[gidx] = red[0];
+}
+
+// Batched copy: task = (problem, block of 256 entries).
+__global__ __launch_bounds__(256) void k_copy_batch(double* const* __restrict__ dst, const double* const* __restrict__ src,
+                                                     const long long* __restrict__ n,
+                                                     const BlockTask* __restrict__ tasks) {
+  const BlockTask t = tasks[blockIdx.x];
+  if (t.grid < 0) return;
+  const long long i = t.start + threadIdx.x;
+  if (i < n[t.grid]) dst[t.grid][i] = src[t.grid][i];
+}
+
 __global__ __launch_bounds__(256) void k_copy(double* __restrict__ dst, const double* __restrict__ src, long long n) {
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -196,7 +225,9 @@ __global__ __launch_bounds__(256) void k_owner(const GridDev* __restrict__ G, in
   const Geo& g = G->g;
   if (i < g.dim * g.nV) {
     int a[3] = {0, 0, 0};
-    node_of(g, i % g.nV, a);
+    long long nl_;
+    split_vel(g, i, &nl_);
+    node_of(g, nl_, a);
     if (node_dirichlet(g, a)) { owner[i] = -1; return; }
   }
   owner[i] = (int)owner_of(g, kind, i);
@@ -208,6 +239,16 @@ void launch_residual(int dim, const GridDev* G, const BlockTask* tasks, int ntas
     hipLaunchKernelGGL(k_residual<2>, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, partials);
   else
     hipLaunchKernelGGL(k_residual<3>, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, partials);
+}
+
+void launch_norm_finalize_batch(const double* partials, const int* first, const int* count, int ngrids,
+                                double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_finalize_batch, dim3(ngrids), dim3(256), 0, s, partials, first, count, out);
+}
+
+void launch_copy_batch(double* const* dst, const double* const* src, const long long* n, const BlockTask* tasks,
+                       int ntasks, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_batch, dim3(ntasks), dim3(256), 0, s, dst, src, n, tasks);
 }
 
 void launch_norm_finalize(const double* partials, int first, int count, double* out, hipStream_t s) {

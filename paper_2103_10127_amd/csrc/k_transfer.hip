@@ -41,18 +41,22 @@ __device__ __forceinline__ int q2_prolong_1d(int a, int* node, double* w) {
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void k_restrict(const GridDev* __restrict__ G, long long nc) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= nc) return;
-  const GridDev& gd = *G;
+__global__ __launch_bounds__(256) void k_restrict(const GridDev* __restrict__ G, const BlockTask* __restrict__ tasks) {
+  const BlockTask t = tasks[blockIdx.x];
+  if (t.grid < 0) return;
+  const GridDev& gd = G[t.grid];
+  if (grid_idle(gd)) return;
+  const long long i = t.start + threadIdx.x;
+  if (i >= gd.gc.n) return;
   const Geo& gf = gd.g;
   const Geo& gc = gd.gc;
   const double* __restrict__ rf = gd.r;
   double s = 0.0;
   if (i < DIM * gc.nV) {
-    const int c = (int)(i / gc.nV);
+    long long nl_;
+    const int c = split_vel(gc, i, &nl_);
     int A[3] = {0, 0, 0};
-    node_of(gc, i % gc.nV, A);
+    node_of(gc, nl_, A);
     if (!node_dirichlet(gc, A)) {
       int off[3][5];
       double w[3][5];
@@ -88,18 +92,22 @@ __global__ __launch_bounds__(256) void k_restrict(const GridDev* __restrict__ G,
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void k_prolong(const GridDev* __restrict__ G, long long nf) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= nf) return;
-  const GridDev& gd = *G;
+__global__ __launch_bounds__(256) void k_prolong(const GridDev* __restrict__ G, const BlockTask* __restrict__ tasks) {
+  const BlockTask t = tasks[blockIdx.x];
+  if (t.grid < 0) return;
+  const GridDev& gd = G[t.grid];
+  if (grid_idle(gd)) return;
+  const long long i = t.start + threadIdx.x;
+  if (i >= gd.g.n) return;
   const Geo& gf = gd.g;
   const Geo& gc = gd.gc;
   const double* __restrict__ xc = gd.xc;
   double s = 0.0;
   if (i < DIM * gf.nV) {
-    const int c = (int)(i / gf.nV);
+    long long nl_;
+    const int c = split_vel(gf, i, &nl_);
     int a[3] = {0, 0, 0};
-    node_of(gf, i % gf.nV, a);
+    node_of(gf, nl_, a);
     if (node_dirichlet(gf, a)) return;
     int nodes[3][3];
     double w[3][3];
@@ -135,16 +143,14 @@ __global__ __launch_bounds__(256) void k_prolong(const GridDev* __restrict__ G, 
   gd.x[i] += s;
 }
 
-void launch_restrict(int dim, const GridDev* G, long long nc, hipStream_t s) {
-  const unsigned nb = (unsigned)((nc + 255) / 256);
-  if (dim == 2) hipLaunchKernelGGL(k_restrict<2>, dim3(nb), dim3(256), 0, s, G, nc);
-  else hipLaunchKernelGGL(k_restrict<3>, dim3(nb), dim3(256), 0, s, G, nc);
+void launch_restrict(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
+  if (dim == 2) hipLaunchKernelGGL(k_restrict<2>, dim3(ntasks), dim3(256), 0, s, G, tasks);
+  else hipLaunchKernelGGL(k_restrict<3>, dim3(ntasks), dim3(256), 0, s, G, tasks);
 }
 
-void launch_prolong(int dim, const GridDev* G, long long nf, hipStream_t s) {
-  const unsigned nb = (unsigned)((nf + 255) / 256);
-  if (dim == 2) hipLaunchKernelGGL(k_prolong<2>, dim3(nb), dim3(256), 0, s, G, nf);
-  else hipLaunchKernelGGL(k_prolong<3>, dim3(nb), dim3(256), 0, s, G, nf);
+void launch_prolong(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
+  if (dim == 2) hipLaunchKernelGGL(k_prolong<2>, dim3(ntasks), dim3(256), 0, s, G, tasks);
+  else hipLaunchKernelGGL(k_prolong<3>, dim3(ntasks), dim3(256), 0, s, G, tasks);
 }
 
 }  // namespace rav

@@ -9,60 +9,20 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "rav.h"
-#include "rav_internal.h"
+#include "rav_ctx.h"
 
 using namespace rav;
 
 namespace {
-
-struct ApplyLaunch {
-  int bucket = 0;
-  int cls = 0;
-  BlockTask* tasks = nullptr;
-  int ntasks = 0;
-};
-
-struct LevelHost {
-  GridDev hd{};
-  GridDev* dd = nullptr;
-  long long nvals = 0;
-  BlockTask* res_tasks = nullptr;
-  int n_res_tasks = 0;
-  int n_res_tiles = 0;
-  double* partials = nullptr;
-  std::vector<ApplyLaunch> apply;
-  long long npatch = 0;
-};
-
 std::string g_create_error;
-
 }  // namespace
-
-struct rav_ctx {
-  rav_problem_desc desc{};
-  std::vector<rav_inclusion> incl;
-  hipStream_t stream = nullptr;
-  std::vector<LevelHost> lv;
-  double* d_incl = nullptr;
-  double* Minv = nullptr;
-  long long nb = 0;
-  int bordered = 0;
-  int* d_status = nullptr;
-  int* d_piv = nullptr;
-  double* d_colk = nullptr;
-  double* d_norm = nullptr;
-  double* h_norm = nullptr;   // pinned
-  int factored = 0;
-  int prec = P_FP64;
-  std::string err;
-};
 
 #define CK(expr)                                                                     \
   do {                                                                               \
@@ -132,9 +92,9 @@ RefTables make_tables() {
   return T;
 }
 
-// Permute logical tiles so that hardware block b (dispatched to XCD b % 8)
-// processes logical tile (b % 8) * (T / 8) + b / 8: each XCD sweeps one
-// contiguous range of the grid and its L2 sees the overlapping reads.
+}  // namespace
+
+namespace rav {
 std::vector<BlockTask> xcd_order(const std::vector<BlockTask>& logical) {
   const size_t T = (logical.size() + 7) / 8 * 8;
   std::vector<BlockTask> out(T);
@@ -146,14 +106,21 @@ std::vector<BlockTask> xcd_order(const std::vector<BlockTask>& logical) {
   return out;
 }
 
-}  // namespace
+void append_tiles(std::vector<BlockTask>& out, int grid, int part, long long n, int per_block) {
+  for (long long s0 = 0; s0 < n; s0 += per_block) {
+    BlockTask t{};
+    t.grid = grid; t.part = part; t.start = s0; t.logical = (int)out.size();
+    out.push_back(t);
+  }
+}
+}  // namespace rav
 
 static rav_status set_err(rav_ctx* ctx, rav_status st, const std::string& msg) {
   if (ctx) ctx->err = msg; else g_create_error = msg;
   return st;
 }
 
-static rav_status upload_tasks(rav_ctx* ctx, const std::vector<BlockTask>& logical, BlockTask** out, int* n) {
+rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<BlockTask>& logical, BlockTask** out, int* n) {
   std::vector<BlockTask> t = xcd_order(logical);
   *n = (int)t.size();
   CK(hipMalloc((void**)out, sizeof(BlockTask) * std::max<size_t>(t.size(), 1)));
@@ -204,8 +171,18 @@ static rav_status build_level(rav_ctx* ctx, int l) {
       tiles.push_back(t);
     }
   L.n_res_tiles = (int)tiles.size();
-  rav_status st = upload_tasks(ctx, tiles, &L.res_tasks, &L.n_res_tasks);
+  rav_status st = rav_upload_tasks(ctx, tiles, &L.res_tasks, &L.n_res_tasks);
   if (st != RAV_OK) return st;
+  if (l > 0) {
+    const Geo gc = make_geo(D.dim, N / 2, D.bc_dirichlet_mask);
+    std::vector<BlockTask> rt, pt;
+    append_tiles(rt, 0, 0, gc.n, BLOCK);
+    append_tiles(pt, 0, 0, g.n, BLOCK);
+    st = rav_upload_tasks(ctx, rt, &L.rtasks, &L.n_rtasks);
+    if (st != RAV_OK) return st;
+    st = rav_upload_tasks(ctx, pt, &L.ptasks, &L.n_ptasks);
+    if (st != RAV_OK) return st;
+  }
   CK(hipMalloc((void**)&L.partials, sizeof(double) * std::max(L.n_res_tiles, 1)));
   // patch buckets (smoothed levels only)
   if (l > 0) {
@@ -221,13 +198,15 @@ static rav_status build_level(rav_ctx* ctx, int l) {
       ApplyLaunch al;
       al.bucket = h.nbk;
       al.cls = B.cls;
+      al.split = cnt < ctx->split_below ? APPLY_SPLIT : 1;
+      const int per_block = BLOCK / al.split;
       std::vector<BlockTask> at;
-      for (long long p0 = 0; p0 < cnt; p0 += BLOCK) {
+      for (long long p0 = 0; p0 < cnt; p0 += per_block) {
         BlockTask t{};
         t.grid = 0; t.part = h.nbk; t.start = p0; t.logical = (int)at.size();
         at.push_back(t);
       }
-      st = upload_tasks(ctx, at, &al.tasks, &al.ntasks);
+      st = rav_upload_tasks(ctx, at, &al.tasks, &al.ntasks);
       if (st != RAV_OK) return st;
       L.apply.push_back(al);
       ++h.nbk;
@@ -250,7 +229,7 @@ static rav_status build_level(rav_ctx* ctx, int l) {
     }
   BlockTask* atd = nullptr;
   int natd = 0;
-  st = upload_tasks(ctx, at, &atd, &natd);
+  st = rav_upload_tasks(ctx, at, &atd, &natd);
   if (st != RAV_OK) return st;
   launch_assemble(D.dim, ncell, L.dd, atd, natd, ctx->d_incl, D.n_incl, D.eta_out, D.eta_in, etaq, uni,
                   ctx->stream);
@@ -285,7 +264,13 @@ static rav_status build_coarse(rav_ctx* ctx) {
   CK(hipStreamSynchronize(ctx->stream));
   if (st != INT_MAX)
     return set_err(ctx, RAV_ESINGULAR, "zero pivot in the coarse matrix at column " + std::to_string(st));
-  return RAV_OK;
+  L.hd.Minv = ctx->Minv;
+  L.hd.nbc = nb;
+  std::vector<BlockTask> ct;
+  append_tiles(ct, 0, 0, g.n, 4);
+  rav_status rs = rav_upload_tasks(ctx, ct, &ctx->coarse_tasks, &ctx->n_coarse_tasks);
+  if (rs != RAV_OK) return rs;
+  return upload_desc(ctx, L);
 }
 
 // ---- device sequences -------------------------------------------------------
@@ -295,16 +280,30 @@ static void residual_level(rav_ctx* ctx, int l, bool with_norm) {
   if (with_norm) launch_norm_finalize(L.partials, 0, L.n_res_tiles, ctx->d_norm, ctx->stream);
 }
 
+static bool prof_mark(rav_ctx* ctx, int l, std::vector<hipEvent_t>& ev, int& n, bool start) {
+  if (ctx->prof_level != l) return false;
+  if (start) {
+    if (n >= ctx->prof_max) return false;
+    (void)hipEventRecord(ev[2 * n], ctx->stream);
+  } else {
+    (void)hipEventRecord(ev[2 * n + 1], ctx->stream);
+    ++n;
+  }
+  return true;
+}
+
 static void apply_level(rav_ctx* ctx, int l) {
   LevelHost& L = ctx->lv[l];
   const rav_problem_desc& D = ctx->desc;
+  const bool timed = prof_mark(ctx, l, ctx->prof_app, ctx->prof_napp, true);
   if (D.smoother == RAV_SMOOTHER_RAV) {
     for (const ApplyLaunch& al : L.apply)
-      launch_rav_apply(D.dim, D.patch, al.cls, ctx->prec, L.dd, al.tasks, al.ntasks, ctx->stream);
+      launch_rav_apply(D.dim, D.patch, al.cls, ctx->prec, al.split, L.dd, al.tasks, al.ntasks, ctx->stream);
   } else if (D.smoother == RAV_SMOOTHER_AV) {
     launch_av_apply(D.dim, D.patch, L.dd, L.npatch, ctx->stream);
     launch_av_gather(D.dim, D.patch, L.dd, L.hd.g.n, ctx->stream);
   }
+  if (timed) prof_mark(ctx, l, ctx->prof_app, ctx->prof_napp, false);
 }
 
 static void mv_sweep(rav_ctx* ctx, int l) {
@@ -332,15 +331,16 @@ static void smooth_level(rav_ctx* ctx, int l, int sweeps) {
     if (ctx->desc.smoother == RAV_SMOOTHER_MV) {
       mv_sweep(ctx, l);
     } else {
+      const bool timed = prof_mark(ctx, l, ctx->prof_res, ctx->prof_nres, true);
       residual_level(ctx, l, false);
+      if (timed) prof_mark(ctx, l, ctx->prof_res, ctx->prof_nres, false);
       apply_level(ctx, l);
     }
   }
 }
 
 static void coarse_solve_level(rav_ctx* ctx) {
-  LevelHost& L = ctx->lv[0];
-  launch_coarse_gemv(ctx->Minv, ctx->nb, L.hd.g.n, L.hd.b, L.hd.x, ctx->stream);
+  launch_coarse_gemv_batch(ctx->lv[0].dd, ctx->coarse_tasks, ctx->n_coarse_tasks, ctx->stream);
 }
 
 static void vcycle_level(rav_ctx* ctx, int l) {
@@ -348,9 +348,9 @@ static void vcycle_level(rav_ctx* ctx, int l) {
   LevelHost& L = ctx->lv[l];
   smooth_level(ctx, l, ctx->desc.nu_pre);
   residual_level(ctx, l, false);
-  launch_restrict(ctx->desc.dim, L.dd, ctx->lv[l - 1].hd.g.n, ctx->stream);
+  launch_restrict(ctx->desc.dim, L.dd, L.rtasks, L.n_rtasks, ctx->stream);
   vcycle_level(ctx, l - 1);
-  launch_prolong(ctx->desc.dim, L.dd, L.hd.g.n, ctx->stream);
+  launch_prolong(ctx->desc.dim, L.dd, L.ptasks, L.n_ptasks, ctx->stream);
   smooth_level(ctx, l, ctx->desc.nu_post);
 }
 
@@ -403,6 +403,7 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
   ctx->desc.incl = ctx->incl.empty() ? nullptr : ctx->incl.data();
   ctx->stream = (hipStream_t)hip_stream;
   ctx->prec = d->inv_precision;
+  if (const char* e = std::getenv("RAV_SPLIT_BELOW")) ctx->split_below = std::atoll(e);
   auto fail = [&](rav_status st) {
     g_create_error = ctx->err;
     rav_destroy(ctx);
@@ -573,7 +574,7 @@ rav_status rav_restrict(rav_ctx* ctx, int level, const double* rf, double* bc) {
   if (check_level(ctx, level, true) != RAV_OK || !rf || !bc) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   launch_copy(L.hd.r, rf, L.hd.g.n, ctx->stream);
-  launch_restrict(ctx->desc.dim, L.dd, L.hd.gc.n, ctx->stream);
+  launch_restrict(ctx->desc.dim, L.dd, L.rtasks, L.n_rtasks, ctx->stream);
   launch_copy(bc, ctx->lv[level - 1].hd.b, L.hd.gc.n, ctx->stream);
   CK(hipGetLastError());
   return RAV_OK;
@@ -584,7 +585,7 @@ rav_status rav_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf
   LevelHost& L = ctx->lv[level];
   launch_copy(ctx->lv[level - 1].hd.x, xc, L.hd.gc.n, ctx->stream);
   launch_copy(L.hd.x, xf, L.hd.g.n, ctx->stream);
-  launch_prolong(ctx->desc.dim, L.dd, L.hd.g.n, ctx->stream);
+  launch_prolong(ctx->desc.dim, L.dd, L.ptasks, L.n_ptasks, ctx->stream);
   launch_copy(xf, L.hd.x, L.hd.g.n, ctx->stream);
   CK(hipGetLastError());
   return RAV_OK;
@@ -844,6 +845,41 @@ rav_status rav_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const do
   return RAV_OK;
 }
 
+rav_status rav_profile_begin(rav_ctx* ctx, int level, int max_launches) {
+  if (check_level(ctx, level, true) != RAV_OK || max_launches <= 0) return RAV_EINVAL;
+  for (auto& e : ctx->prof_res) (void)hipEventDestroy(e);
+  for (auto& e : ctx->prof_app) (void)hipEventDestroy(e);
+  ctx->prof_res.assign(2 * (size_t)max_launches, nullptr);
+  ctx->prof_app.assign(2 * (size_t)max_launches, nullptr);
+  for (auto& e : ctx->prof_res) CK(hipEventCreate(&e));
+  for (auto& e : ctx->prof_app) CK(hipEventCreate(&e));
+  ctx->prof_max = max_launches;
+  ctx->prof_nres = ctx->prof_napp = 0;
+  ctx->prof_level = level;
+  return RAV_OK;
+}
+
+rav_status rav_profile_end(rav_ctx* ctx, float* avg_res, float* avg_app, int* n_app) {
+  if (!ctx) return RAV_EINVAL;
+  ctx->prof_level = -1;
+  CK(hipStreamSynchronize(ctx->stream));
+  double tr = 0.0, ta = 0.0;
+  for (int i = 0; i < ctx->prof_nres; ++i) {
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, ctx->prof_res[2 * i], ctx->prof_res[2 * i + 1]));
+    tr += ms;
+  }
+  for (int i = 0; i < ctx->prof_napp; ++i) {
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, ctx->prof_app[2 * i], ctx->prof_app[2 * i + 1]));
+    ta += ms;
+  }
+  if (avg_res) *avg_res = ctx->prof_nres ? (float)(tr / ctx->prof_nres) : 0.f;
+  if (avg_app) *avg_app = ctx->prof_napp ? (float)(ta / ctx->prof_napp) : 0.f;
+  if (n_app) *n_app = ctx->prof_napp;
+  return RAV_OK;
+}
+
 rav_status rav_stream_copy(void* stream, double* dst, const double* src, long n) {
   if (!dst || !src || n < 0) return RAV_EINVAL;
   launch_copy(dst, src, n, (hipStream_t)stream);
@@ -859,11 +895,15 @@ rav_status rav_destroy(rav_ctx* ctx) {
     (void)hipFree(h.Winv); (void)hipFree(h.Y);
     for (int i = 0; i < h.nbk; ++i) (void)hipFree(h.bk[i].W);
     (void)hipFree(L.dd); (void)hipFree(L.res_tasks); (void)hipFree(L.partials);
+    (void)hipFree(L.rtasks); (void)hipFree(L.ptasks);
     for (ApplyLaunch& a : L.apply) (void)hipFree(a.tasks);
   }
   (void)hipFree(ctx->d_incl); (void)hipFree(ctx->Minv); (void)hipFree(ctx->d_status);
   (void)hipFree(ctx->d_piv); (void)hipFree(ctx->d_colk); (void)hipFree(ctx->d_norm);
+  (void)hipFree(ctx->coarse_tasks);
   if (ctx->h_norm) (void)hipHostFree(ctx->h_norm);
+  for (auto& e : ctx->prof_res) if (e) (void)hipEventDestroy(e);
+  for (auto& e : ctx->prof_app) if (e) (void)hipEventDestroy(e);
   delete ctx;
   return RAV_OK;
 }

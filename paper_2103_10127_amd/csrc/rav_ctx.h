@@ -1,0 +1,80 @@
+// Host-side context of the RAV library (shared by the single-problem and
+// batched drivers).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "rav.h"
+#include "rav_internal.h"
+
+namespace rav {
+
+struct ApplyLaunch {
+  int bucket = 0;
+  int cls = 0;
+  int split = 1;
+  BlockTask* tasks = nullptr;
+  int ntasks = 0;
+};
+
+// Buckets with fewer patches than this run the split apply variant unless the
+// set-up autotuner measured otherwise.
+constexpr long long SPLIT_BELOW = 120000;
+
+struct LevelHost {
+  GridDev hd{};
+  GridDev* dd = nullptr;
+  long long nvals = 0;
+  BlockTask* res_tasks = nullptr;
+  int n_res_tasks = 0;
+  int n_res_tiles = 0;
+  double* partials = nullptr;
+  std::vector<ApplyLaunch> apply;
+  long long npatch = 0;
+  BlockTask* rtasks = nullptr;   // restriction: tiles over the coarser level's DoFs
+  int n_rtasks = 0;
+  BlockTask* ptasks = nullptr;   // prolongation: tiles over this level's DoFs
+  int n_ptasks = 0;
+};
+
+// Permute logical tiles so that hardware block b (dispatched to XCD b % 8)
+// processes logical tile (b % 8) * (T / 8) + b / 8: each XCD sweeps one
+// contiguous range of the grid and its L2 sees the overlapping reads.
+std::vector<BlockTask> xcd_order(const std::vector<BlockTask>& logical);
+
+// Logical tiles of `per_block` items over [0, n) for one grid.
+void append_tiles(std::vector<BlockTask>& out, int grid, int part, long long n, int per_block);
+
+}  // namespace rav
+
+struct rav_ctx {
+  rav_problem_desc desc{};
+  std::vector<rav_inclusion> incl;
+  hipStream_t stream = nullptr;
+  std::vector<rav::LevelHost> lv;
+  double* d_incl = nullptr;
+  double* Minv = nullptr;
+  long long nb = 0;
+  int bordered = 0;
+  int* d_status = nullptr;
+  int* d_piv = nullptr;
+  double* d_colk = nullptr;
+  double* d_norm = nullptr;
+  double* h_norm = nullptr;   // pinned
+  int factored = 0;
+  int prec = rav::P_FP64;
+  long long split_below = rav::SPLIT_BELOW;
+  std::string err;
+  // kernel timing (rav_profile_begin / rav_profile_end)
+  int prof_level = -1;
+  int prof_max = 0;
+  int prof_nres = 0, prof_napp = 0;
+  std::vector<hipEvent_t> prof_res, prof_app;
+  rav::BlockTask* coarse_tasks = nullptr;
+  int n_coarse_tasks = 0;
+};
+
+// Shared helpers (rav_capi.hip).
+rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<rav::BlockTask>& logical, rav::BlockTask** out, int* n);

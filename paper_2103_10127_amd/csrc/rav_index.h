@@ -80,11 +80,23 @@ RAV_HD long long vert_lin(const Geo& g, const int* k) {
   for (int d = g.dim - 2; d >= 0; --d) i = i * g.np1 + k[d];
   return i;
 }
+// Level sizes stay below 2^31, so index decoding uses 32-bit unsigned
+// division (64-bit division is a long software sequence on the GPU).
 RAV_HD void node_of(const Geo& g, long long lin, int* a) {
-  for (int d = 0; d < g.dim; ++d) { a[d] = (int)(lin % g.nn); lin /= g.nn; }
+  unsigned u = (unsigned)lin;
+  const unsigned nn = (unsigned)g.nn;
+  for (int d = 0; d < g.dim; ++d) { a[d] = (int)(u % nn); u /= nn; }
 }
 RAV_HD void vert_of(const Geo& g, long long lin, int* k) {
-  for (int d = 0; d < g.dim; ++d) { k[d] = (int)(lin % g.np1); lin /= g.np1; }
+  unsigned u = (unsigned)lin;
+  const unsigned np1 = (unsigned)g.np1;
+  for (int d = 0; d < g.dim; ++d) { k[d] = (int)(u % np1); u /= np1; }
+}
+// Split a global velocity index into component and node (32-bit division).
+RAV_HD int split_vel(const Geo& g, long long i, long long* node_lin_out) {
+  const unsigned u = (unsigned)i, nv = (unsigned)g.nV;
+  *node_lin_out = (long long)(u % nv);
+  return (int)(u / nv);
 }
 
 // ---- ELL segments -------------------------------------------------------
@@ -125,10 +137,11 @@ RAV_HD long long vel_seg_row(const Geo& g, int t, const int* a) {
   return r;
 }
 RAV_HD void vel_row_node(const Geo& g, int t, long long row, int* a) {
+  unsigned u = (unsigned)row;
   for (int d = 0; d < g.dim; ++d) {
-    long long c = type_count(g, t, d);
-    a[d] = 2 * (int)(row % c) + ((t >> d) & 1);
-    row /= c;
+    const unsigned c = (unsigned)type_count(g, t, d);
+    a[d] = 2 * (int)(u % c) + ((t >> d) & 1);
+    u /= c;
   }
 }
 // Slot of velocity column node b in the row of node a (same component), or -1.
@@ -179,8 +192,9 @@ RAV_HD long long patch_lin(const Geo& g, int kind, const int* k) {
   return i;
 }
 RAV_HD void patch_anchor(const Geo& g, int kind, long long p, int* k) {
-  long long base = kind == KIND_VERTEX ? g.np1 : g.N;
-  for (int d = 0; d < g.dim; ++d) { k[d] = (int)(p % base); p /= base; }
+  const unsigned base = (unsigned)(kind == KIND_VERTEX ? g.np1 : g.N);
+  unsigned u = (unsigned)p;
+  for (int d = 0; d < g.dim; ++d) { k[d] = (int)(u % base); u /= base; }
 }
 
 // Local DoF `l` of the patch anchored at k: returns -1 for padding (outside
@@ -260,9 +274,10 @@ RAV_HD long long bucket_count(const Geo& g, int kind, int m) {
 }
 RAV_HD void bucket_anchor(const Geo& g, int kind, int m, long long p, int* k) {
   if (kind == KIND_VERTEX) { patch_anchor(g, kind, p, k); return; }
+  unsigned u = (unsigned)p;
   for (int d = 0; d < g.dim; ++d) {
     if ((m >> d) & 1) { k[d] = g.N - 1; }
-    else { long long ext = g.N - 1; k[d] = (int)(p % ext); p /= ext; }
+    else { const unsigned ext = (unsigned)(g.N - 1); k[d] = (int)(u % ext); u /= ext; }
   }
 }
 // Position of an element inside its bucket.
@@ -281,7 +296,9 @@ RAV_HDC int n_buckets(int dim, int kind) { return kind == KIND_VERTEX ? 1 : (1 <
 RAV_HD long long owner_of(const Geo& g, int kind, long long dof) {
   int a[3], k[3];
   if (dof < g.dim * g.nV) {
-    node_of(g, dof % g.nV, a);
+    long long nl;
+    split_vel(g, dof, &nl);
+    node_of(g, nl, a);
     for (int d = 0; d < g.dim; ++d) {
       int o = a[d] >> 1;
       k[d] = (kind == KIND_ELEMENT && o > g.N - 1) ? g.N - 1 : o;

@@ -11,6 +11,7 @@ constexpr int MAX_SEG = 25;      // 3 components x 8 parity types + pressure
 constexpr int MAX_BUCKETS = 8;
 constexpr int MAX_INCL = 64;
 constexpr int BLOCK = 256;       // threads per block of the streaming kernels
+constexpr int APPLY_SPLIT = 8;   // lanes per patch of the small-level RAV apply
 
 enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
 
@@ -52,7 +53,14 @@ struct GridDev {
   double* Y;             // AV: per-patch corrections [patch][npad]
   const float* omega_patch;
   double omega;
+  // coarsest level only: dense inverse of the (bordered) coarse matrix
+  const double* Minv;
+  long long nbc;
+  // batched solves: problem stops being updated once *active == 0 (null = always)
+  const int* active;
 };
+
+__host__ __device__ __forceinline__ bool grid_idle(const GridDev& gd) { return gd.active && *gd.active == 0; }
 
 // One block of a streaming launch.  `part` selects the ELL segment or patch
 // bucket, `start` the first row/patch of the tile, `logical` the tile's
@@ -88,7 +96,7 @@ void launch_rhs(int dim, const GridDev* Gh, const GridDev* Gd, const double* par
 void launch_residual(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, double* partials,
                      hipStream_t s);
 void launch_norm_finalize(const double* partials, int first, int count, double* out, hipStream_t s);
-void launch_rav_apply(int dim, int kind, int cls, int prec, const GridDev* G, const BlockTask* tasks,
+void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const GridDev* G, const BlockTask* tasks,
                       int ntasks, hipStream_t s);
 void launch_factor(int dim, int kind, int cls, int prec, int full, const GridDev* G, long long count,
                    int bucket, int* status, hipStream_t s);
@@ -96,8 +104,13 @@ void launch_av_apply(int dim, int kind, const GridDev* G, long long npatch, hipS
 void launch_av_gather(int dim, int kind, const GridDev* G, long long n, hipStream_t s);
 void launch_mv_colour(int dim, int kind, const GridDev* G, int colour, long long npatch_colour,
                       hipStream_t s);
-void launch_restrict(int dim, const GridDev* G, long long nc, hipStream_t s);
-void launch_prolong(int dim, const GridDev* G, long long nf, hipStream_t s);
+void launch_restrict(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s);
+void launch_prolong(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s);
+void launch_coarse_gemv_batch(const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s);
+void launch_norm_finalize_batch(const double* partials, const int* first, const int* count, int ngrids,
+                                double* out, hipStream_t s);
+void launch_copy_batch(double* const* dst, const double* const* src, const long long* n, const BlockTask* tasks,
+                       int ntasks, hipStream_t s);
 void launch_coarse_build(const GridDev* G, int dim, double* M, long long nb, int bordered, int unit_masked,
                          hipStream_t s);
 void launch_coarse_gj_step(double* M, long long nb, long long k, int* piv, double* colk, int* status,
