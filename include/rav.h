@@ -151,6 +151,13 @@ rav_status rav_set_params(rav_ctx* ctx, double omega, int nu_pre, int nu_post);
  * valid while used; NULL restores the scalar omega. */
 rav_status rav_set_patch_omega(rav_ctx* ctx, int level, const float* omega_dev);
 
+/* Fallback for per-patch weights: during rav_solve, if a cycle reduces the
+ * residual by a factor worse than rho_max (||r_k|| > rho_max ||r_{k-1}||)
+ * while per-patch weights are set, they are dropped and the solve continues
+ * with the scalar omega.  rho_max = 0 disables it.  *fell_back (may be NULL)
+ * reports whether the previous rav_solve fell back. */
+rav_status rav_set_fallback(rav_ctx* ctx, double rho_max, int* fell_back);
+
 /* Host-side patch map of patch `patch` on `level`: its free DoFs in local
  * order (component-major, lexicographic nodes, pressure last) into dofs_host
  * (capacity >= 128), their count into *n, and owned_host[j] = 1 if the DoF is
@@ -198,6 +205,35 @@ rav_status rav_profile_end(rav_ctx* ctx, float* avg_residual_ms, float* avg_appl
 rav_status rav_stream_copy(void* hip_stream, double* dst_dev, const double* src_dev, long n);
 
 rav_status rav_destroy(rav_ctx* ctx);
+
+/* ---- learned per-patch damping ---------------------------------------------
+ * A small network predicts the per-patch weight omega_i (one scalar per
+ * subdomain: the diagonal weighting of eq. 11 in its simplest form) from 16
+ * local features of each 2D vertex patch: log10(eta/eta_out)/4 sampled at the
+ * 3x3 points (k + (a,b)/2) h, a,b in {-1,0,1}; their min, max and mean;
+ * boundary flags in x and y; log2(N)/10; 1.  Network 16 -> 64 -> 64 -> 1, ReLU,
+ * omega = 0.2 + sigmoid(z), FP32 parameters (5313 floats, flat: W1 64x16, b1,
+ * W2 64x64, b2, w3, b3).  Supported for 2D vertex-patch RAV contexts. */
+typedef struct rav_mlp rav_mlp;
+rav_status rav_mlp_create(const float* theta_host, rav_mlp** out);
+/* Copies the parameters and/or the last gradient (FP64) to the host (NULL skips). */
+rav_status rav_mlp_get(const rav_mlp* mlp, float* theta_host, double* grad_host);
+rav_status rav_mlp_destroy(rav_mlp* mlp);
+/* omega_dev (n_patches(level) floats, device) = network output on `level`. */
+rav_status rav_learn_patch_omega(rav_ctx* ctx, const rav_mlp* mlp, int level, float* omega_dev);
+/* Per-patch weights from the network on every smoothed level (library-owned
+ * arrays); mlp = NULL restores the scalar omega. */
+rav_status rav_learn_set_omega(rav_ctx* ctx, const rav_mlp* mlp);
+/* Two-grid training objective of a 2-level context (FP64 rows, exact coarse
+ * solve): J = ||L x_out||^2 / ||L x0||^2 after nu RAV sweeps with the
+ * network's weights, the exact coarse correction, nu sweeps, from the error
+ * x0_dev (b = 0).  Returns J, dJ/domega_i (grad_omega_dev: n_patches doubles,
+ * may be NULL) and dJ/dtheta (grad_theta_host: 5313 doubles, may be NULL),
+ * computed by the reverse sweep of the cycle and back-propagation. */
+rav_status rav_learn_twogrid(rav_ctx* ctx, const rav_mlp* mlp, const double* x0_dev, int nu, double* loss,
+                             double* grad_omega_dev, double* grad_theta_host);
+/* rav_learn_twogrid followed by one Adam step (beta1 0.9, beta2 0.999) of size lr. */
+rav_status rav_learn_step(rav_ctx* ctx, rav_mlp* mlp, const double* x0_dev, int nu, double lr, double* loss);
 
 /* ---- batched problems -------------------------------------------------------
  * Many independent problems solved together with RAV V-cycles (the additive,

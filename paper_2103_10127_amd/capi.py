@@ -78,6 +78,14 @@ SIGNATURES = {
     "rav_profile_end": (_S, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                              ctypes.POINTER(_I)]),
     "rav_destroy": (_S, [_P]),
+    "rav_set_fallback": (_S, [_P, _D, ctypes.POINTER(_I)]),
+    "rav_mlp_create": (_S, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_P)]),
+    "rav_mlp_get": (_S, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_D)]),
+    "rav_mlp_destroy": (_S, [_P]),
+    "rav_learn_patch_omega": (_S, [_P, _P, _I, _P]),
+    "rav_learn_set_omega": (_S, [_P, _P]),
+    "rav_learn_twogrid": (_S, [_P, _P, _P, _I, ctypes.POINTER(_D), _P, ctypes.POINTER(_D)]),
+    "rav_learn_step": (_S, [_P, _P, _P, _I, _D, ctypes.POINTER(_D)]),
     "rav_batch_create": (_S, [ctypes.POINTER(RavProblemDesc), _I, _P, ctypes.POINTER(_P)]),
     "rav_batch_factor": (_S, [_P]),
     "rav_batch_size": (_S, [_P, ctypes.POINTER(_I)]),
@@ -261,10 +269,68 @@ class Hierarchy:
         self._chk(self.lib.rav_profile_end(self.h, ctypes.byref(a), ctypes.byref(c), ctypes.byref(n)))
         return a.value, c.value, n.value
 
+    def set_fallback(self, rho_max):
+        fb = _I()
+        self._chk(self.lib.rav_set_fallback(self.h, rho_max, ctypes.byref(fb)))
+        return fb.value
+
+    def learn_patch_omega(self, mlp, level, omega_dev):
+        return self._chk(self.lib.rav_learn_patch_omega(self.h, mlp.h, level, _ptr(omega_dev)))
+
+    def learn_set_omega(self, mlp):
+        return self._chk(self.lib.rav_learn_set_omega(self.h, None if mlp is None else mlp.h))
+
+    def learn_twogrid(self, mlp, x0, nu=2, grad_omega=None, want_theta=True):
+        loss = _D()
+        gt = (_D * 5313)() if want_theta else None
+        self._chk(self.lib.rav_learn_twogrid(self.h, mlp.h, _ptr(x0), nu, ctypes.byref(loss),
+                                             None if grad_omega is None else _ptr(grad_omega), gt))
+        return loss.value, (np.ctypeslib.as_array(gt).copy() if want_theta else None)
+
+    def learn_step(self, mlp, x0, nu=2, lr=1e-3):
+        loss = _D()
+        self._chk(self.lib.rav_learn_step(self.h, mlp.h, _ptr(x0), nu, lr, ctypes.byref(loss)))
+        return loss.value
+
     def time_sweep(self, level, reps, x, b):
         a, c = ctypes.c_float(), ctypes.c_float()
         self._chk(self.lib.rav_time_sweep(self.h, level, reps, _ptr(x), _ptr(b), ctypes.byref(a), ctypes.byref(c)))
         return a.value, c.value
+
+
+class MLP:
+    """Per-patch damping network (``rav_mlp``): 16 -> 64 -> 64 -> 1, FP32."""
+
+    NPARAM = 5313
+
+    def __init__(self, theta):
+        self.lib = lib()
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.size != self.NPARAM:
+            raise ValueError("the network has 5313 parameters")
+        h = _P()
+        st = self.lib.rav_mlp_create(th.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(h))
+        if st < 0:
+            raise RavError(st, "rav_mlp_create")
+        self.h = h
+
+    def theta(self):
+        out = np.zeros(self.NPARAM, dtype=np.float32)
+        st = self.lib.rav_mlp_get(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), None)
+        if st < 0:
+            raise RavError(st, "rav_mlp_get")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rav_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

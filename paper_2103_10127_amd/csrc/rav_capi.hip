@@ -128,7 +128,7 @@ rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<BlockTask>& logical,
   return RAV_OK;
 }
 
-static rav_status upload_desc(rav_ctx* ctx, LevelHost& L) {
+rav_status rav_upload_desc(rav_ctx* ctx, LevelHost& L) {
   CK(hipStreamSynchronize(ctx->stream));
   CK(hipMemcpy(L.dd, &L.hd, sizeof(GridDev), hipMemcpyHostToDevice));
   return RAV_OK;
@@ -213,7 +213,7 @@ static rav_status build_level(rav_ctx* ctx, int l) {
     }
   }
   // operator assembly on the device
-  st = upload_desc(ctx, L);
+  st = rav_upload_desc(ctx, L);
   if (st != RAV_OK) return st;
   const long long ncell = (long long)N * N * (D.dim == 3 ? N : 1);
   double* etaq = nullptr;
@@ -270,11 +270,11 @@ static rav_status build_coarse(rav_ctx* ctx) {
   append_tiles(ct, 0, 0, g.n, 4);
   rav_status rs = rav_upload_tasks(ctx, ct, &ctx->coarse_tasks, &ctx->n_coarse_tasks);
   if (rs != RAV_OK) return rs;
-  return upload_desc(ctx, L);
+  return rav_upload_desc(ctx, L);
 }
 
 // ---- device sequences -------------------------------------------------------
-static void residual_level(rav_ctx* ctx, int l, bool with_norm) {
+void rav_residual_level(rav_ctx* ctx, int l, bool with_norm) {
   LevelHost& L = ctx->lv[l];
   launch_residual(ctx->desc.dim, L.dd, L.res_tasks, L.n_res_tasks, with_norm ? L.partials : nullptr, ctx->stream);
   if (with_norm) launch_norm_finalize(L.partials, 0, L.n_res_tiles, ctx->d_norm, ctx->stream);
@@ -292,7 +292,7 @@ static bool prof_mark(rav_ctx* ctx, int l, std::vector<hipEvent_t>& ev, int& n, 
   return true;
 }
 
-static void apply_level(rav_ctx* ctx, int l) {
+void rav_apply_level(rav_ctx* ctx, int l) {
   LevelHost& L = ctx->lv[l];
   const rav_problem_desc& D = ctx->desc;
   const bool timed = prof_mark(ctx, l, ctx->prof_app, ctx->prof_napp, true);
@@ -332,9 +332,9 @@ static void smooth_level(rav_ctx* ctx, int l, int sweeps) {
       mv_sweep(ctx, l);
     } else {
       const bool timed = prof_mark(ctx, l, ctx->prof_res, ctx->prof_nres, true);
-      residual_level(ctx, l, false);
+      rav_residual_level(ctx, l, false);
       if (timed) prof_mark(ctx, l, ctx->prof_res, ctx->prof_nres, false);
-      apply_level(ctx, l);
+      rav_apply_level(ctx, l);
     }
   }
 }
@@ -347,14 +347,14 @@ static void vcycle_level(rav_ctx* ctx, int l) {
   if (l == 0) { coarse_solve_level(ctx); return; }
   LevelHost& L = ctx->lv[l];
   smooth_level(ctx, l, ctx->desc.nu_pre);
-  residual_level(ctx, l, false);
+  rav_residual_level(ctx, l, false);
   launch_restrict(ctx->desc.dim, L.dd, L.rtasks, L.n_rtasks, ctx->stream);
   vcycle_level(ctx, l - 1);
   launch_prolong(ctx->desc.dim, L.dd, L.ptasks, L.n_ptasks, ctx->stream);
   smooth_level(ctx, l, ctx->desc.nu_post);
 }
 
-static rav_status read_norm(rav_ctx* ctx, double* out) {
+rav_status rav_read_norm(rav_ctx* ctx, double* out) {
   CK(hipMemcpyAsync(ctx->h_norm, ctx->d_norm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   CK(hipStreamSynchronize(ctx->stream));
   *out = std::sqrt(*ctx->h_norm);
@@ -437,7 +437,7 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
     L.hd.gc = ctx->lv[l - 1].hd.g;
     L.hd.xc = ctx->lv[l - 1].hd.x;
     L.hd.bc = ctx->lv[l - 1].hd.b;
-    rav_status st = upload_desc(ctx, L);
+    rav_status st = rav_upload_desc(ctx, L);
     if (st != RAV_OK) return fail(st);
   }
   rav_status st = build_coarse(ctx);
@@ -474,7 +474,7 @@ rav_status rav_factor_patches(rav_ctx* ctx) {
         }
       }
     }
-    rav_status st = upload_desc(ctx, L);
+    rav_status st = rav_upload_desc(ctx, L);
     if (st != RAV_OK) return st;
     CK(hipMemcpy(ctx->d_status, &big, sizeof(int), hipMemcpyHostToDevice));
     if (full) {
@@ -550,10 +550,10 @@ rav_status rav_residual(rav_ctx* ctx, int level, const double* x, const double* 
   const long long n = L.hd.g.n;
   launch_copy(L.hd.x, x, n, ctx->stream);
   launch_copy(L.hd.b, b, n, ctx->stream);
-  residual_level(ctx, level, norm != nullptr);
+  rav_residual_level(ctx, level, norm != nullptr);
   launch_copy(r, L.hd.r, n, ctx->stream);
   CK(hipGetLastError());
-  if (norm) return read_norm(ctx, norm);
+  if (norm) return rav_read_norm(ctx, norm);
   return RAV_OK;
 }
 
@@ -621,9 +621,9 @@ rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int 
   const long long n = L.hd.g.n;
   launch_copy(L.hd.x, x, n, ctx->stream);
   launch_copy(L.hd.b, b, n, ctx->stream);
-  residual_level(ctx, lf, true);
+  rav_residual_level(ctx, lf, true);
   double r0 = 0.0;
-  rav_status st = read_norm(ctx, &r0);
+  rav_status st = rav_read_norm(ctx, &r0);
   if (st != RAV_OK) return st;
   if (iters) *iters = 0;
   if (rel_res) *rel_res = r0 > 0.0 ? 1.0 : 0.0;
@@ -632,12 +632,26 @@ rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int 
   if (r0 == 0.0) result = RAV_OK;
   int k = 0;
   double rk = r0;
+  ctx->fell_back = 0;
   while (result == RAV_NOT_CONVERGED && k < maxit) {
+    const double rprev = rk;
     vcycle_level(ctx, lf);
-    residual_level(ctx, lf, true);
-    st = read_norm(ctx, &rk);
+    rav_residual_level(ctx, lf, true);
+    st = rav_read_norm(ctx, &rk);
     if (st != RAV_OK) return st;
     ++k;
+    if (ctx->fallback_rho > 0.0 && !ctx->fell_back && rk > ctx->fallback_rho * rprev) {
+      // the per-patch weights reduce the residual less than the fixed-omega
+      // reference rate: continue with the scalar omega
+      bool any = false;
+      for (LevelHost& Lv : ctx->lv) {
+        if (!Lv.hd.omega_patch) continue;
+        Lv.hd.omega_patch = nullptr;
+        any = true;
+        if ((st = rav_upload_desc(ctx, Lv)) != RAV_OK) return st;
+      }
+      ctx->fell_back = any ? 1 : 0;
+    }
     if (!std::isfinite(rk) || rk > 1e3 * r0) {
       result = RAV_EDIVERGED;
       ctx->err = "residual diverged at cycle " + std::to_string(k);
@@ -660,16 +674,23 @@ rav_status rav_set_params(rav_ctx* ctx, double omega, int nu_pre, int nu_post) {
   ctx->desc.nu_post = nu_post;
   for (LevelHost& L : ctx->lv) {
     L.hd.omega = omega;
-    rav_status st = upload_desc(ctx, L);
+    rav_status st = rav_upload_desc(ctx, L);
     if (st != RAV_OK) return st;
   }
+  return RAV_OK;
+}
+
+rav_status rav_set_fallback(rav_ctx* ctx, double rho_max, int* fell_back) {
+  if (!ctx || rho_max < 0.0) return RAV_EINVAL;
+  ctx->fallback_rho = rho_max;
+  if (fell_back) *fell_back = ctx->fell_back;
   return RAV_OK;
 }
 
 rav_status rav_set_patch_omega(rav_ctx* ctx, int level, const float* omega_dev) {
   if (check_level(ctx, level, true) != RAV_OK) return RAV_EINVAL;
   ctx->lv[level].hd.omega_patch = omega_dev;
-  return upload_desc(ctx, ctx->lv[level]);
+  return rav_upload_desc(ctx, ctx->lv[level]);
 }
 
 static rav_status map_patch_geo(const Geo& g, int kind, long long npatch, long patch, int* dofs, int* n,
@@ -823,9 +844,9 @@ rav_status rav_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const do
   for (auto& e : ev) CK(hipEventCreate(&e));
   for (int i = 0; i < reps; ++i) {
     CK(hipEventRecord(ev[3 * i], ctx->stream));
-    residual_level(ctx, level, false);
+    rav_residual_level(ctx, level, false);
     CK(hipEventRecord(ev[3 * i + 1], ctx->stream));
-    apply_level(ctx, level);
+    rav_apply_level(ctx, level);
     CK(hipEventRecord(ev[3 * i + 2], ctx->stream));
   }
   CK(hipEventSynchronize(ev.back()));
@@ -889,6 +910,7 @@ rav_status rav_stream_copy(void* stream, double* dst, const double* src, long n)
 rav_status rav_destroy(rav_ctx* ctx) {
   if (!ctx) return RAV_OK;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->learn_free) ctx->learn_free(ctx);
   for (LevelHost& L : ctx->lv) {
     GridDev& h = L.hd;
     (void)hipFree(h.x); (void)hipFree(h.b); (void)hipFree(h.r); (void)hipFree(h.vals);

@@ -74,7 +74,17 @@ struct rav_ctx {
   std::vector<hipEvent_t> prof_res, prof_app;
   rav::BlockTask* coarse_tasks = nullptr;
   int n_coarse_tasks = 0;
+  // learned damping: state owned by rav_learn.hip, released through learn_free
+  void* learn = nullptr;
+  void (*learn_free)(rav_ctx*) = nullptr;
+  // fall back to the scalar omega when a cycle reduces the residual by less than this factor (0 = off)
+  double fallback_rho = 0.0;
+  int fell_back = 0;
 };
 
 // Shared helpers (rav_capi.hip).
+rav_status rav_upload_desc(rav_ctx* ctx, rav::LevelHost& L);
+void rav_residual_level(rav_ctx* ctx, int l, bool with_norm);
+void rav_apply_level(rav_ctx* ctx, int l);
+rav_status rav_read_norm(rav_ctx* ctx, double* out);
 rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<rav::BlockTask>& logical, rav::BlockTask** out, int* n);

@@ -118,6 +118,19 @@ void launch_coarse_gj_step(double* M, long long nb, long long k, int* piv, doubl
 void launch_coarse_colswap(double* M, long long nb, const int* piv, hipStream_t s);
 void launch_coarse_gemv(const double* Minv, long long nb, long long n0, const double* b, double* x,
                         hipStream_t s);
+void launch_features(const GridDev* G, long long npatch, const double* incl, int n_incl, double eta_out,
+                     double eta_in, float* F, hipStream_t s);
+void launch_mlp_forward(const float* theta, const float* F, long long n, float* omega, hipStream_t s);
+int mlp_backward_blocks(long long n);
+void launch_mlp_backward(const float* theta, const float* F, const double* gom, long long n, double* partial,
+                         double* grad, hipStream_t s);
+void launch_adam(float* theta, double* m, double* v, const double* grad, double lr, int t, hipStream_t s);
+void launch_rav_grad(const GridDev* G, long long npatch, const double* r, const double* lam, double* gom,
+                     hipStream_t s);
+void launch_rav_transpose(const GridDev* G, long long npatch, const double* lam, const float* omega, double* Y,
+                          hipStream_t s);
+void launch_patch_gather(const GridDev* G, long long n, const double* Y, double* z, hipStream_t s);
+void launch_axpby(double a, const double* x, double b, double* y, long long n, hipStream_t s);
 void launch_owner(const GridDev* G, int kind, long long n, int* owner, hipStream_t s);
 void launch_copy(double* dst, const double* src, long long n, hipStream_t s);
 void launch_fill(double* dst, double v, long long n, hipStream_t s);

@@ -119,3 +119,21 @@ CONFIGS = {
     "2d-1024": dict(dim=2, n_cells=1024, n_levels=8, seed=1005, dmask=ALL_DIRICHLET_2D,
                     eta_out=1.0, contrast=1e4),
 }
+
+
+#: Parameter count of the per-patch damping network 16 -> 64 -> 64 -> 1:
+#: W1 (64x16), b1 (64), W2 (64x64), b2 (64), w3 (64), b3 (1), stored in that
+#: order, matrices row-major (output index slow).
+MLP_SIZES = ((64, 16), (64,), (64, 64), (64,), (64,), (1,))
+MLP_NPARAM = sum(int(np.prod(s)) for s in MLP_SIZES)
+
+
+def mlp_init(seed: int, out_bias: float = -0.16, out_scale: float = 0.01) -> np.ndarray:
+    """He-normal draws for W1, W2, small normal draws for w3, zero hidden biases
+    and a fixed output bias (float32, flat)."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.standard_normal((64, 16)) * np.sqrt(2.0 / 16)
+    w2 = rng.standard_normal((64, 64)) * np.sqrt(2.0 / 64)
+    w3 = rng.standard_normal(64) * out_scale
+    parts = [w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3, np.array([out_bias])]
+    return np.concatenate(parts).astype(np.float32)
