@@ -143,6 +143,16 @@ rav_status rav_vcycle(rav_ctx* ctx, double* x_dev, const double* b_dev);
 rav_status rav_solve(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit,
                      int* iters, double* rel_res);
 
+/* Krylov acceleration (Sec. 4 notes multigrid "can also be used as a
+ * preconditioner in a Krylov subspace solver"): restarted flexible GMRES(restart),
+ * right-preconditioned by one V(nu_pre, nu_post) cycle from a zero guess.
+ * maxit bounds the number of preconditioner applications (V-cycles); stops
+ * when the true residual ||b - L x||_2 <= rtol ||b - L x_0||_2.  Allocates
+ * 2*restart+3 work vectors of the finest level for the duration of the call.
+ * Same return convention as rav_solve; *iters counts V-cycles. */
+rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit, int restart,
+                           int* iters, double* rel_res);
+
 /* Change damping and smoothing steps without refactoring. */
 rav_status rav_set_params(rav_ctx* ctx, double omega, int nu_pre, int nu_post);
 

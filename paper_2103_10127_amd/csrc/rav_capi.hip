@@ -354,6 +354,8 @@ static void vcycle_level(rav_ctx* ctx, int l) {
   smooth_level(ctx, l, ctx->desc.nu_post);
 }
 
+void rav_vcycle_finest(rav_ctx* ctx) { vcycle_level(ctx, (int)ctx->lv.size() - 1); }
+
 rav_status rav_read_norm(rav_ctx* ctx, double* out) {
   CK(hipMemcpyAsync(ctx->h_norm, ctx->d_norm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   CK(hipStreamSynchronize(ctx->stream));

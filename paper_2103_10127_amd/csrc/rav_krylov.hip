@@ -1,0 +1,167 @@
+// Krylov acceleration of the multigrid solver: restarted, right-preconditioned
+// flexible GMRES whose preconditioner is one V-cycle (with zero initial guess)
+// of the context's smoother (the paper notes that multigrid "can also be used
+// as a preconditioner in a Krylov subspace solver", Sec. 4).  The Arnoldi
+// coefficients stay in device memory; one small read-back per iteration feeds
+// the Givens update of the least-squares residual on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "rav_ctx.h"
+
+using namespace rav;
+
+namespace rav {
+void launch_dot(const double* a, const double* b, long long n, double* partial, double* out, int take_sqrt,
+                hipStream_t s);
+void launch_axpy_dev(double* y, const double* x, const double* c, double sign, long long n, hipStream_t s);
+void launch_div_dev(double* y, const double* x, const double* c, long long n, hipStream_t s);
+void launch_axpby_h(double a, const double* x, double b, double* y, long long n, hipStream_t s);
+}  // namespace rav
+
+// Internal: one V-cycle of the context on its finest level (defined in rav_capi.hip).
+void rav_vcycle_finest(rav_ctx* ctx);
+
+#define KCK(expr)                                                              \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);            \
+      return e_ == hipErrorOutOfMemory ? RAV_ENOMEM : RAV_EDEVICE;             \
+    }                                                                          \
+  } while (0)
+
+extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit,
+                                      int restart, int* iters, double* rel_res) {
+  if (!ctx || !x_dev || !b_dev || !(rtol > 0.0) || maxit < 0 || restart < 1 || restart > 200) return RAV_EINVAL;
+  if (!ctx->factored) { ctx->err = "rav_factor_patches has not been called"; return RAV_EINVAL; }
+  const int lf = (int)ctx->lv.size() - 1;
+  LevelHost& L = ctx->lv[lf];
+  const long long n = L.hd.g.n;
+  const int m = restart;
+  hipStream_t s = ctx->stream;
+  std::vector<double*> V(m + 1, nullptr), Z(m, nullptr);
+  double *xk = nullptr, *bk = nullptr, *partial = nullptr, *hdev = nullptr, *hhost = nullptr;
+  rav_status result = RAV_OK;
+  auto cleanup = [&]() {
+    for (double* p : V) (void)hipFree(p);
+    for (double* p : Z) (void)hipFree(p);
+    (void)hipFree(xk); (void)hipFree(bk); (void)hipFree(partial); (void)hipFree(hdev);
+    if (hhost) (void)hipHostFree(hhost);
+  };
+  auto alloc = [&]() -> rav_status {
+    for (double*& p : V) KCK(hipMalloc((void**)&p, sizeof(double) * n));
+    for (double*& p : Z) KCK(hipMalloc((void**)&p, sizeof(double) * n));
+    KCK(hipMalloc((void**)&xk, sizeof(double) * n));
+    KCK(hipMalloc((void**)&bk, sizeof(double) * n));
+    KCK(hipMalloc((void**)&partial, sizeof(double) * 1024));
+    KCK(hipMalloc((void**)&hdev, sizeof(double) * (m + 2) * (m + 1)));
+    KCK(hipHostMalloc((void**)&hhost, sizeof(double) * (m + 2), hipHostMallocDefault));
+    return RAV_OK;
+  };
+  if ((result = alloc()) != RAV_OK) { cleanup(); return result; }
+  launch_copy(xk, x_dev, n, s);
+  launch_copy(bk, b_dev, n, s);
+  // residual of the current iterate into L.r (norm in ctx->d_norm)
+  auto true_residual = [&](double* nrm) -> rav_status {
+    launch_copy(L.hd.x, xk, n, s);
+    launch_copy(L.hd.b, bk, n, s);
+    rav_residual_level(ctx, lf, true);
+    return rav_read_norm(ctx, nrm);
+  };
+  double beta0 = 0.0;
+  if ((result = true_residual(&beta0)) != RAV_OK) { cleanup(); return result; }
+  if (!std::isfinite(beta0)) { cleanup(); ctx->err = "initial residual is not finite"; return RAV_EDIVERGED; }
+  int total = 0;
+  double res = beta0;
+  result = RAV_NOT_CONVERGED;
+  if (beta0 == 0.0) result = RAV_OK;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  while (result == RAV_NOT_CONVERGED && total < maxit) {
+    double beta = 0.0;
+    if (total > 0) {
+      rav_status st = true_residual(&beta);
+      if (st != RAV_OK) { cleanup(); return st; }
+      res = beta;
+      if (!std::isfinite(beta) || beta > 1e3 * beta0) { result = RAV_EDIVERGED; break; }
+      if (beta <= rtol * beta0) { result = RAV_OK; break; }
+    } else {
+      beta = beta0;
+    }
+    // V_0 = r / beta
+    launch_axpby_h(1.0 / beta, L.hd.r, 0.0, V[0], n, s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < m && total < maxit; ++j) {
+      // Z_j = M V_j (one V-cycle from zero)
+      launch_copy(L.hd.b, V[j], n, s);
+      launch_fill(L.hd.x, 0.0, n, s);
+      rav_vcycle_finest(ctx);
+      launch_copy(Z[j], L.hd.x, n, s);
+      // w = L Z_j  (residual with b = 0 gives -L Z_j)
+      launch_fill(L.hd.b, 0.0, n, s);
+      rav_residual_level(ctx, lf, false);
+      double* w = V[j + 1];
+      launch_axpby_h(-1.0, L.hd.r, 0.0, w, n, s);
+      // modified Gram-Schmidt, coefficients h[i][j] in device memory
+      for (int i = 0; i <= j; ++i) {
+        double* hij = hdev + (size_t)j * (m + 2) + i;
+        launch_dot(w, V[i], n, partial, hij, 0, s);
+        launch_axpy_dev(w, V[i], hij, -1.0, n, s);
+      }
+      double* hn = hdev + (size_t)j * (m + 2) + j + 1;
+      launch_dot(w, w, n, partial, hn, 1, s);
+      launch_div_dev(w, w, hn, n, s);
+      KCK(hipGetLastError());
+      KCK(hipMemcpyAsync(hhost, hdev + (size_t)j * (m + 2), sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s));
+      KCK(hipStreamSynchronize(s));
+      ++total;
+      for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = hhost[i];
+      // apply previous rotations to column j, then a new one
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      }
+      const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+      const double rr = std::hypot(a, c);
+      cs[j] = rr > 0.0 ? a / rr : 1.0;
+      sn[j] = rr > 0.0 ? c / rr : 0.0;
+      H[(size_t)j * m + j] = rr;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      res = std::fabs(g[j + 1]);
+      jend = j + 1;
+      if (!std::isfinite(res)) { result = RAV_EDIVERGED; break; }
+      if (res <= rtol * beta0 || hhost[j + 1] == 0.0) break;
+    }
+    if (result == RAV_EDIVERGED) break;
+    // y = R^{-1} g, x += Z y
+    for (int i = jend - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int k = i + 1; k < jend; ++k) t -= H[(size_t)i * m + k] * y[k];
+      y[i] = H[(size_t)i * m + i] != 0.0 ? t / H[(size_t)i * m + i] : 0.0;
+    }
+    for (int i = 0; i < jend; ++i) launch_axpby_h(y[i], Z[i], 1.0, xk, n, s);
+    if (res <= rtol * beta0) {
+      double beta_true = 0.0;
+      rav_status st = true_residual(&beta_true);
+      if (st != RAV_OK) { cleanup(); return st; }
+      res = beta_true;
+      if (beta_true <= rtol * beta0) result = RAV_OK;
+    }
+  }
+  launch_copy(x_dev, xk, n, s);
+  KCK(hipGetLastError());
+  KCK(hipStreamSynchronize(s));
+  if (iters) *iters = total;
+  if (rel_res) *rel_res = beta0 > 0.0 ? res / beta0 : 0.0;
+  if (result == RAV_EDIVERGED) ctx->err = "GMRES residual diverged";
+  cleanup();
+  return result;
+}
