@@ -46,18 +46,6 @@ def sum_owned_times_patch(N: int) -> int:
     return int(np.sum(n_i * o_i))
 
 
-def nnz_free_2d(N: int) -> int:
-    """Structural nonzeros of the all-Dirichlet 2D operator on free rows and
-    columns.  Every block is a tensor product of 1D counts: velocity-velocity
-    (same component), velocity-pressure and its transpose."""
-    a = np.arange(1, 2 * N)                                # free 1D velocity positions
-    w = np.where(a % 2 == 0, 2, 1)
-    cv = np.minimum(a + w, 2 * N - 1) - np.maximum(a - w, 1) + 1
-    lo = a // 2 - 1 + a % 2
-    cp = np.minimum(lo + 2 - a % 2, N) - np.maximum(lo, 0) + 1
-    return int(2 * cv.sum() ** 2 + 2 * 2 * cp.sum() ** 2)
-
-
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,9 +163,8 @@ def main():
 
     # Algorithmic bytes (per launch, finest level).
     sum_on = sum_owned_times_patch(N)
-    nnz = nnz_free_2d(N)
     apply_bytes = 8 * sum_on + 8 * n_fine + 16 * n_free          # W rows + r read + x read/write
-    resid_bytes = 8 * nnz + 24 * n_fine                            # values + x, b read + r write
+    resid_bytes = 24 * n_fine + 8 * N * N                          # x, b read + r write + one coefficient per cell
     sweep_s = 1e-3 * (ms_res + ms_apply)
     sweep_rate = n_fine / sweep_s
     roof_apply = apply_bytes / (1e-3 * ms_apply) / 1e9

@@ -58,16 +58,10 @@ __global__ __launch_bounds__(256) void k_eta(const GridDev* G, const double* inc
   uniform[e] = uni ? 1 : 0;
 }
 
+// Viscous cell matrix entry by Gauss quadrature with the per-point viscosity (h = 1).
 template <int DIM>
-__device__ __forceinline__ double cell_stiffness(const double* etaq, const unsigned char* uniform,
-                                                 long long cell, const int* la, const int* lb) {
+__device__ __forceinline__ double cell_stiffness_q(const double* etaq, long long cell, const int* la, const int* lb) {
   constexpr int NQ = ipow(3, DIM);
-  int ia = 0, ib = 0, st = 1;
-  for (int d = 0; d < DIM; ++d) { ia += la[d] * st; ib += lb[d] * st; st *= 3; }
-  if (uniform[cell]) {
-    double aref = DIM == 2 ? c_ref.aref2[ia][ib] : c_ref.aref3[ia][ib];
-    return etaq[cell * NQ] * aref;
-  }
   double s = 0.0;
   for (int q = 0; q < NQ; ++q) {
     int qd[3], qq = q;
@@ -84,6 +78,19 @@ __device__ __forceinline__ double cell_stiffness(const double* etaq, const unsig
     s += w * etaq[cell * NQ + q] * gg;
   }
   return s;
+}
+
+template <int DIM>
+__device__ __forceinline__ double cell_stiffness(const double* etaq, const unsigned char* uniform,
+                                                 long long cell, const int* la, const int* lb) {
+  constexpr int NQ = ipow(3, DIM);
+  int ia = 0, ib = 0, st = 1;
+  for (int d = 0; d < DIM; ++d) { ia += la[d] * st; ib += lb[d] * st; st *= 3; }
+  if (uniform[cell]) {
+    double aref = DIM == 2 ? c_ref.aref2[ia][ib] : c_ref.aref3[ia][ib];
+    return etaq[cell * NQ] * aref;
+  }
+  return cell_stiffness_q<DIM>(etaq, cell, la, lb);
 }
 
 template <int DIM>
@@ -338,7 +345,50 @@ __global__ __launch_bounds__(256) void k_rhs_gather(const GridDev* G, const doub
   b[i] = s;
 }
 
+// Per-cell coefficients of the matrix-free residual: ceta[e] = h^(d-2) eta_e
+// for cells with one viscosity, -(1 + i) for the i-th cut cell (cut_idx[e] = i).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_cell_scale(const GridDev* G, long long ncell, const double* etaq,
+                                                     const int* cut_idx, double* ceta) {
+  constexpr int NQ = ipow(3, DIM);
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= ncell) return;
+  const double hA = DIM == 2 ? 1.0 : G->h;
+  const int ci = cut_idx[e];
+  ceta[e] = ci < 0 ? hA * etaq[e * NQ] : -(1.0 + (double)ci);
+}
+
+// Full viscous cell matrices of the cut cells: cutA[(i * NV + a) * NV + b], one thread per entry.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_cut_matrices(const GridDev* G, const double* etaq, const int* cut_cells,
+                                                       int ncut, double* cutA) {
+  constexpr int NV = ipow(3, DIM);
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= (long long)ncut * NV * NV) return;
+  const int i = (int)(t / (NV * NV)), ab = (int)(t % (NV * NV));
+  int la[3] = {0, 0, 0}, lb[3] = {0, 0, 0};
+  for (int d = 0, a = ab / NV, b = ab % NV; d < DIM; ++d) { la[d] = a % 3; lb[d] = b % 3; a /= 3; b /= 3; }
+  const double hA = DIM == 2 ? 1.0 : G->h;
+  cutA[t] = hA * cell_stiffness_q<DIM>(etaq, cut_cells[i], la, lb);
+}
+
 static inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_cell_coef(int dim, long long ncell, const GridDev* G, const double* etaq, const int* cut_idx,
+                      const int* cut_cells, int ncut, double* ceta, double* cutA, hipStream_t s) {
+  const long long nv2 = dim == 2 ? 81 : 729;
+  if (dim == 2) {
+    hipLaunchKernelGGL(k_cell_scale<2>, dim3(nblk(ncell, 256)), dim3(256), 0, s, G, ncell, etaq, cut_idx, ceta);
+    if (ncut > 0)
+      hipLaunchKernelGGL(k_cut_matrices<2>, dim3(nblk(ncut * nv2, 256)), dim3(256), 0, s, G, etaq, cut_cells, ncut,
+                         cutA);
+  } else {
+    hipLaunchKernelGGL(k_cell_scale<3>, dim3(nblk(ncell, 256)), dim3(256), 0, s, G, ncell, etaq, cut_idx, ceta);
+    if (ncut > 0)
+      hipLaunchKernelGGL(k_cut_matrices<3>, dim3(nblk(ncut * nv2, 256)), dim3(256), 0, s, G, etaq, cut_cells, ncut,
+                         cutA);
+  }
+}
 
 void launch_assemble(int dim, long long ncell, const GridDev* G, const BlockTask* tasks, int ntasks,
                      const double* incl, int n_incl, double eta_out, double eta_in, double* etaq,

@@ -54,13 +54,6 @@ __global__ __launch_bounds__(KB) void k_div_dev(double* __restrict__ y, const do
   for (long long i = blockIdx.x * (long long)KB + threadIdx.x; i < n; i += (long long)gridDim.x * KB) y[i] = x[i] * inv;
 }
 
-// y = a * x + b * y with host scalars
-__global__ __launch_bounds__(KB) void k_axpby_h(double a, const double* __restrict__ x, double b, double* __restrict__ y,
-                                                 long long n) {
-  for (long long i = blockIdx.x * (long long)KB + threadIdx.x; i < n; i += (long long)gridDim.x * KB)
-    y[i] = a * x[i] + b * y[i];
-}
-
 static inline unsigned kgrid(long long n) {
   long long b = (n + KB - 1) / KB;
   return (unsigned)(b < KBLOCKS ? (b < 1 ? 1 : b) : KBLOCKS);
@@ -77,9 +70,6 @@ void launch_axpy_dev(double* y, const double* x, const double* c, double sign, l
 }
 void launch_div_dev(double* y, const double* x, const double* c, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_div_dev, dim3(kgrid(n)), dim3(KB), 0, s, y, x, c, n);
-}
-void launch_axpby_h(double a, const double* x, double b, double* y, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpby_h, dim3(kgrid(n)), dim3(KB), 0, s, a, x, b, y, n);
 }
 
 }  // namespace rav

@@ -261,10 +261,11 @@ __global__ __launch_bounds__(256) void k_patch_gather(const GridDev* __restrict_
 }
 
 // y = a * x + b * y
+// y = a x + b y; with b == 0 the old y is not read (it may be uninitialised).
 __global__ __launch_bounds__(256) void k_axpby(double a, const double* __restrict__ x, double b, double* __restrict__ y,
                                                 long long n) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a * x[i] + b * y[i];
+  if (i < n) y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
 }
 
 static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }

@@ -1,116 +1,388 @@
-// Residual r = b - L x on the free rows (eq. 10), with an optional partial
-// sum of r^2 per block for the stopping test (Sec. 4), plus small utility
-// kernels (norm reduction, copy, fill, owner map).
+// Residual r = b - L x (eq. 10) evaluated cell by cell without reading the
+// assembled operator.
 //
-// One thread per operator row.  Every block covers rows of a single ELL
-// segment, so all lanes of a wavefront share the stencil shape (compile-time
-// per node parity type) and read the slot-major values coalesced.
+// On a uniform grid every cell matrix of the divergence block is the same
+// (B_e = -h^(d-1) x reference), and the viscous cell matrix is
+// A_e = h^(d-2) eta_e x reference wherever the viscosity is constant on the
+// cell; only cells cut by an inclusion keep a full stored A_e.  The reference
+// matrices are the closed-form tensor products of the 1D Q2 stiffness/mass and
+// Q1-Q2 coupling integrals:
+//   K = 1/3 [[7,-8,1],[-8,16,-8],[1,-8,7]],  M = 1/30 [[4,2,-1],[2,16,2],[-1,2,4]],
+//   G[k][a] = int psi_k phi_a' = [[-5/6, 2/3, 1/6], [-1/6, -2/3, 5/6]],
+//   H[k][a] = int psi_k phi_a  = [[1/6, 1/3, 0], [0, 1/3, 1/6]].
+// A thread owns one velocity node (both/all components) or one pressure
+// vertex and gathers the contributions of the cells around it, so the sweep
+// reads x, b, one coefficient per cell and the few cut-cell matrices instead
+// of ~25 operator values per DoF.  Columns on masked (Dirichlet) nodes
+// contribute nothing, exactly as the assembled operator drops them.  The
+// per-cell coefficient is h^(d-2) eta_e, or -(1 + i) for the i-th cut cell
+// whose full viscous matrix (h^(d-2) included) is cutA[i].
 #include <hip/hip_runtime.h>
 
 #include "rav_internal.h"
 
 namespace rav {
 
-template <int DIM, int TY>
-__device__ __forceinline__ double res_velocity(const GridDev& gd, int s, long long row, bool& masked) {
-  const Geo& g = gd.g;
-  const int c = s >> DIM;
-  int a[3] = {0, 0, 0};
-  vel_row_node(g, TY, row, a);
-  masked = node_dirichlet(g, a);
-  const long long base = node_lin(g, a);
-  const long long gi = c * g.nV + base;
-  if (masked) { gd.r[gi] = 0.0; return 0.0; }
-  const long long rows = gd.seg_rows[s];
-  const double* __restrict__ v = gd.vals + gd.seg_off[s] + row;
-  const double* __restrict__ xc = gd.x + c * g.nV;
-  const double* __restrict__ xp = gd.x + DIM * g.nV;
-  constexpr int W0 = (TY & 1) ? 1 : 2;
-  constexpr int W1 = ((TY >> 1) & 1) ? 1 : 2;
-  constexpr int W2 = DIM == 3 ? (((TY >> 2) & 1) ? 1 : 2) : 0;
-  const int twoN = 2 * g.N;
-  const long long nn = g.nn, nn2 = g.nn * g.nn;
-  double acc = 0.0;
-  int slot = 0;
-#pragma unroll 1
-  for (int oz = -W2; oz <= W2; ++oz) {
-#pragma unroll 1
-    for (int oy = -W1; oy <= W1; ++oy) {
-#pragma unroll
-      for (int ox = -W0; ox <= W0; ++ox) {
-        bool ok = a[0] + ox >= 0 && a[0] + ox <= twoN && a[1] + oy >= 0 && a[1] + oy <= twoN;
-        if (DIM == 3) ok = ok && a[2] + oz >= 0 && a[2] + oz <= twoN;
-        const double val = v[(long long)slot * rows];
-        const double xv = ok ? xc[base + ox + nn * oy + nn2 * oz] : 0.0;
-        acc += val * xv;
-        ++slot;
-      }
+__host__ __device__ constexpr double k1(int a, int b) {
+  return a == b ? (a == 1 ? 16.0 / 3.0 : 7.0 / 3.0) : ((a == 1 || b == 1) ? -8.0 / 3.0 : 1.0 / 3.0);
+}
+__host__ __device__ constexpr double m1(int a, int b) {
+  return a == b ? (a == 1 ? 16.0 / 30.0 : 4.0 / 30.0) : ((a == 1 || b == 1) ? 2.0 / 30.0 : -1.0 / 30.0);
+}
+__host__ __device__ constexpr double g1(int k, int a) {
+  return k == 0 ? (a == 0 ? -5.0 / 6.0 : a == 1 ? 2.0 / 3.0 : 1.0 / 6.0)
+                : (a == 0 ? -1.0 / 6.0 : a == 1 ? -2.0 / 3.0 : 5.0 / 6.0);
+}
+__host__ __device__ constexpr double h1(int k, int a) {
+  return k == 0 ? (a == 0 ? 1.0 / 6.0 : a == 1 ? 1.0 / 3.0 : 0.0) : (a == 0 ? 0.0 : a == 1 ? 1.0 / 3.0 : 1.0 / 6.0);
+}
+// Reference viscous cell matrix (h = 1, eta = 1): sum_c K(a_c,b_c) prod_{d != c} M(a_d,b_d).
+template <int DIM>
+__host__ __device__ constexpr double aref(int la, int lb) {
+  double s = 0.0;
+  for (int c = 0; c < DIM; ++c) {
+    double p = 1.0;
+    int a = la, b = lb;
+    for (int d = 0; d < DIM; ++d) {
+      p *= (d == c) ? k1(a % 3, b % 3) : m1(a % 3, b % 3);
+      a /= 3;
+      b /= 3;
     }
+    s += p;
   }
-  constexpr int M0 = 3 - (TY & 1), M1 = 3 - ((TY >> 1) & 1), M2 = DIM == 3 ? 3 - ((TY >> 2) & 1) : 1;
-  const int lo0 = (a[0] >> 1) - 1 + (TY & 1);
-  const int lo1 = (a[1] >> 1) - 1 + ((TY >> 1) & 1);
-  const int lo2 = DIM == 3 ? (a[2] >> 1) - 1 + ((TY >> 2) & 1) : 0;
-  const long long np1 = g.np1, np12 = g.np1 * g.np1;
-#pragma unroll 1
-  for (int jz = 0; jz < M2; ++jz) {
-#pragma unroll 1
-    for (int jy = 0; jy < M1; ++jy) {
-#pragma unroll
-      for (int jx = 0; jx < M0; ++jx) {
-        const int k0 = lo0 + jx, k1 = lo1 + jy, k2 = lo2 + jz;
-        bool ok = k0 >= 0 && k0 <= g.N && k1 >= 0 && k1 <= g.N;
-        if (DIM == 3) ok = ok && k2 >= 0 && k2 <= g.N;
-        const double val = v[(long long)slot * rows];
-        const double xv = ok ? xp[k0 + np1 * k1 + np12 * k2] : 0.0;
-        acc += val * xv;
-        ++slot;
-      }
-    }
+  return s;
+}
+// Reference divergence cell matrix (h = 1): -G(k_c,a_c) prod_{d != c} H(k_d,a_d).
+template <int DIM>
+__host__ __device__ constexpr double bref(int c, int la, int lk) {
+  double p = -1.0;
+  int a = la, k = lk;
+  for (int d = 0; d < DIM; ++d) {
+    p *= (d == c) ? g1(k & 1, a % 3) : h1(k & 1, a % 3);
+    a /= 3;
+    k >>= 1;
   }
-  const double r = gd.b[gi] - acc;
-  gd.r[gi] = r;
-  return r;
+  return p;
 }
 
 template <int DIM>
-__device__ __forceinline__ double res_pressure(const GridDev& gd, long long row) {
+struct Tabs {
+  double A[ipow(3, DIM) * ipow(3, DIM)];
+  double B[DIM * ipow(3, DIM) * ipow(2, DIM)];
+  constexpr Tabs() : A(), B() {
+    for (int a = 0; a < ipow(3, DIM); ++a)
+      for (int b = 0; b < ipow(3, DIM); ++b) A[a * ipow(3, DIM) + b] = aref<DIM>(a, b);
+    for (int c = 0; c < DIM; ++c)
+      for (int a = 0; a < ipow(3, DIM); ++a)
+        for (int k = 0; k < ipow(2, DIM); ++k) B[(c * ipow(3, DIM) + a) * ipow(2, DIM) + k] = bref<DIM>(c, a, k);
+  }
+};
+__constant__ const Tabs<2> c_tab2 = Tabs<2>();
+__constant__ const Tabs<3> c_tab3 = Tabs<3>();
+
+template <int DIM>
+__device__ __forceinline__ const Tabs<DIM>& tabs();
+template <>
+__device__ __forceinline__ const Tabs<2>& tabs<2>() { return c_tab2; }
+template <>
+__device__ __forceinline__ const Tabs<3>& tabs<3>() { return c_tab3; }
+
+// Global-memory views of the level vectors (the descriptor holds generic
+// pointers; the explicit address space gives global instead of flat loads).
+typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ gcdouble* gview(const double* p) { return (gcdouble*)p; }
+__device__ __forceinline__ gdouble* gview(double* p) { return (gdouble*)p; }
+// Element idx of a level vector (level sizes stay below 2^28 elements, so the
+// byte offset is a 32-bit value added to a wave-uniform base address).
+__device__ __forceinline__ double ld(gcdouble* base, unsigned idx) {
+  typedef __attribute__((address_space(1))) const char gcchar;
+  return *(gcdouble*)((gcchar*)base + (idx << 3));
+}
+
+// Half-grid position a_d + o_d holds a free velocity node in dimension d:
+// inside the grid and not on a masked side.
+__device__ __forceinline__ bool free_coord(const Geo& g, int d, int v) {
+  return v >= 0 && v <= 2 * g.N && !coord_dirichlet(g, d, v);
+}
+
+// Velocity node a of parity type TY (all components).  Cells around the node:
+// per dimension one cell (odd position, local index 1) or two (even position,
+// local index 2 in the lower cell, 0 in the upper one).  The row is a stencil
+// over the unique column nodes a + o, |o_d| <= W_d, and pressure vertices
+// lo + j; the coefficient of a column is the sum over the cells that contain
+// it of (cell coefficient) x (reference entry), the reference entries folding
+// into immediates.  All cell coefficients and column values are loaded up
+// front at clamped (in-range) addresses; missing cells get coefficient 0 and
+// columns outside the grid or on a masked side are replaced by 0 with a
+// select, so every path is branch-free except the correction for cut cells
+// (whose full matrices replace the scaled reference).
+template <int DIM, int TY>
+__device__ __forceinline__ double res_node(const GridDev& gd, long long row) {
+  constexpr int NV = ipow(3, DIM), NP = ipow(2, DIM);
+  constexpr int NE0 = (TY & 1) ? 1 : 2, NE1 = ((TY >> 1) & 1) ? 1 : 2;
+  constexpr int NE2 = DIM == 3 ? (((TY >> 2) & 1) ? 1 : 2) : 1;
+  constexpr int NE = NE0 * NE1 * NE2;
+  constexpr int W0 = (TY & 1) ? 1 : 2, W1 = ((TY >> 1) & 1) ? 1 : 2;
+  constexpr int W2 = DIM == 3 ? (((TY >> 2) & 1) ? 1 : 2) : 0;
+  constexpr int M0 = 3 - (TY & 1), M1 = 3 - ((TY >> 1) & 1), M2 = DIM == 3 ? 3 - ((TY >> 2) & 1) : 1;
   const Geo& g = gd.g;
-  const int s = pressure_segment(DIM);
-  int k[3] = {0, 0, 0};
-  vert_of(g, row, k);
-  const long long rows = gd.seg_rows[s];
-  const double* __restrict__ v = gd.vals + gd.seg_off[s] + row;
-  const int twoN = 2 * g.N;
-  const long long nn = g.nn, nn2 = g.nn * g.nn;
-  int a[3] = {2 * k[0], 2 * k[1], DIM == 3 ? 2 * k[2] : 0};
-  const long long base = a[0] + nn * a[1] + nn2 * a[2];
-  constexpr int WZ = DIM == 3 ? 2 : 0;
-  double acc = 0.0;
-#pragma unroll 1
-  for (int c = 0; c < DIM; ++c) {
-    const double* __restrict__ xc = gd.x + c * g.nV;
-    int slot = c * ipow(5, DIM);
-#pragma unroll 1
-    for (int oz = -WZ; oz <= WZ; ++oz) {
-#pragma unroll 1
-      for (int oy = -2; oy <= 2; ++oy) {
+  const Tabs<DIM>& T = tabs<DIM>();
+  gcdouble* __restrict__ X = gview(gd.x);
+  gdouble* __restrict__ R = gview(gd.r);
+  int a[3] = {0, 0, 0};
+  vel_row_node(g, TY, row, a);
+  const long long base = node_lin(g, a);
+  if (node_dirichlet(g, a)) {
 #pragma unroll
-        for (int ox = -2; ox <= 2; ++ox) {
-          bool ok = a[0] + ox >= 0 && a[0] + ox <= twoN && a[1] + oy >= 0 && a[1] + oy <= twoN;
-          if (DIM == 3) ok = ok && a[2] + oz >= 0 && a[2] + oz <= twoN;
-          const double val = v[(long long)slot * rows];
-          const double xv = ok ? xc[base + ox + nn * oy + nn2 * oz] : 0.0;
-          acc += val * xv;
-          ++slot;
+    for (int c = 0; c < DIM; ++c) R[c * g.nV + base] = 0.0;
+    return 0.0;
+  }
+  const int N = g.N;
+  const long long nn = g.nn, nn2 = g.nn * g.nn, np1 = g.np1, np12 = g.np1 * g.np1, nV = g.nV;
+  // cells: coefficient (0 when missing or cut), existence, cut index
+  double cef[NE];
+  bool okc[NE];
+  long long cut_row[NE];
+  bool anycut = false;
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int eo[3] = {i % NE0, (i / NE0) % NE1, i / (NE0 * NE1)};
+    int E[3] = {0, 0, 0}, la = 0;
+    bool ok = true;
+#pragma unroll
+    for (int d = 0, st = 1; d < DIM; ++d, st *= 3) {
+      const bool odd = (TY >> d) & 1;
+      E[d] = odd ? (a[d] - 1) >> 1 : (a[d] >> 1) - 1 + eo[d];
+      la += (odd ? 1 : 2 - 2 * eo[d]) * st;
+      ok = ok && E[d] >= 0 && E[d] < N;
+      E[d] = min(max(E[d], 0), N - 1);
+    }
+    const double ce = gd.ceta[E[0] + (long long)N * (E[1] + (long long)N * (DIM == 3 ? E[2] : 0))];
+    okc[i] = ok;
+    cef[i] = ok && ce >= 0.0 ? ce : 0.0;
+    const bool cut = ok && ce < 0.0;
+    cut_row[i] = cut ? ((long long)(-ce) - 1) * (NV * NV) + la * NV : -1;
+    anycut = anycut || cut;
+  }
+  // columns per dimension and offset: free flag and clamped (in-range) position
+  bool fv[2][5];
+  unsigned cpos[2][5];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) {
+      fv[d][o + 2] = free_coord(g, d, a[d] + o);
+      cpos[d][o + 2] = (unsigned)min(max(a[d] + o, 0), 2 * N) * (d == 0 ? 1u : (unsigned)nn);
+    }
+  }
+  double acc[DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
+#pragma unroll(DIM == 3 ? 1 : DIM)
+  for (int c = 0; c < DIM; ++c) {
+    gcdouble* __restrict__ xc = X + c * nV;
+    double sc = 0.0;
+#pragma unroll(DIM == 3 ? 1 : 8)
+    for (int oz = -W2; oz <= W2; ++oz) {
+#pragma unroll
+      for (int oy = -W1; oy <= W1; ++oy) {
+#pragma unroll
+        for (int ox = -W0; ox <= W0; ++ox) {
+          const int o[3] = {ox, oy, oz};
+          bool fr = fv[0][ox + 2] && fv[1][oy + 2];
+          unsigned lin = cpos[0][ox + 2] + cpos[1][oy + 2];
+          if (DIM == 3) {
+            fr = fr && free_coord(g, 2, a[2] + oz);
+            lin += (unsigned)min(max(a[2] + oz, 0), 2 * N) * (unsigned)nn2;
+          }
+          const double xv = ld(xc, lin);
+          double coef = 0.0;
+#pragma unroll
+          for (int i = 0; i < NE; ++i) {
+            const int eo[3] = {i % NE0, (i / NE0) % NE1, i / (NE0 * NE1)};
+            int la = 0, lb = 0;
+            bool in = true;
+#pragma unroll
+            for (int d = 0, st = 1; d < DIM; ++d, st *= 3) {
+              const int l = ((TY >> d) & 1) ? 1 : 2 - 2 * eo[d];
+              la += l * st;
+              lb += (l + o[d]) * st;
+              in = in && l + o[d] >= 0 && l + o[d] <= 2;
+            }
+            if (in) coef += cef[i] * T.A[la * NV + lb];
+          }
+          sc += (fr ? coef : 0.0) * xv;
+        }
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < DIM; ++cc) acc[cc] += cc == c ? sc : 0.0;   // register select, no indexed array
+  }
+  // pressure columns k = lo + j, lo_d = (a_d >> 1) - 1 + (a_d & 1), j_d < M_d
+  double accB[DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) accB[c] = 0.0;
+  int lo[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) lo[d] = (a[d] >> 1) - 1 + ((TY >> d) & 1);
+  gcdouble* __restrict__ XP = X + DIM * nV;
+  const unsigned pstr[3] = {1u, (unsigned)np1, (unsigned)np12};
+#pragma unroll(DIM == 3 ? 1 : 8)
+  for (int jz = 0; jz < M2; ++jz) {
+#pragma unroll
+    for (int jy = 0; jy < M1; ++jy) {
+#pragma unroll
+      for (int jx = 0; jx < M0; ++jx) {
+        const int j[3] = {jx, jy, jz};
+        bool in_grid = true;
+        unsigned lin = 0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const int k = lo[d] + j[d];
+          in_grid = in_grid && k >= 0 && k <= N;
+          lin += (unsigned)min(max(k, 0), N) * pstr[d];
+        }
+        const double pv = ld(XP, lin);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          double coef = 0.0;
+#pragma unroll
+          for (int i = 0; i < NE; ++i) {
+            const int eo[3] = {i % NE0, (i / NE0) % NE1, i / (NE0 * NE1)};
+            int la = 0, lk = 0;
+            bool in = true;
+#pragma unroll
+            for (int d = 0, st = 1; d < DIM; ++d, st *= 3) {
+              const bool odd = (TY >> d) & 1;
+              la += (odd ? 1 : 2 - 2 * eo[d]) * st;
+              const int kl = j[d] - (odd ? 0 : eo[d]);   // vertex index inside the cell
+              in = in && kl >= 0 && kl <= 1;
+              lk |= (kl & 1) << d;
+            }
+            if (in) coef += okc[i] ? T.B[(c * NV + la) * NP + lk] : 0.0;
+          }
+          accB[c] += (in_grid ? coef : 0.0) * pv;
         }
       }
     }
   }
-  const long long gi = DIM * g.nV + row;
-  const double r = gd.b[gi] - acc;
-  gd.r[gi] = r;
-  return r;
+  // cut cells: full cell matrix rows (rare, divergent)
+  if (anycut) {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      if (cut_row[i] < 0) continue;
+      const int eo[3] = {i % NE0, (i / NE0) % NE1, i / (NE0 * NE1)};
+      int E2[3] = {0, 0, 0};
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) E2[d] = ((TY >> d) & 1) ? a[d] - 1 : a[d] - 2 + 2 * eo[d];
+      gcdouble* __restrict__ Ae = gview(gd.cutA) + cut_row[i];
+#pragma unroll(DIM == 3 ? 9 : NV)
+      for (int lb = 0; lb < NV; ++lb) {
+        const int b[3] = {E2[0] + lb % 3, E2[1] + (lb / 3) % 3, DIM == 3 ? E2[2] + lb / 9 : 0};
+        bool fr = true;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) fr = fr && !coord_dirichlet(g, d, b[d]);
+        const double w = Ae[lb];
+        const long long lin = b[0] + nn * b[1] + nn2 * b[2];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          const double xv = X[c * nV + lin];
+          acc[c] += w * (fr ? xv : 0.0);
+        }
+      }
+    }
+  }
+  const double hB = DIM == 2 ? gd.h : gd.h * gd.h;
+  gcdouble* __restrict__ Bv = gview(gd.b);
+  double sq = 0.0;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const long long gi = c * nV + base;
+    const double r = Bv[gi] - (acc[c] + hB * accB[c]);
+    R[gi] = r;
+    sq += r * r;
+  }
+  return sq;
+}
+
+// Pressure row of vertex k: divergence of the velocity over the (up to 2^d)
+// cells around the vertex (cell k - 1 + eo, local vertex 1 - eo), as a stencil
+// over the nodes 2k + o, |o_d| <= 2, with constant coefficients; missing cells
+// and masked or outside columns contribute nothing (selects, no branches).
+template <int DIM>
+__device__ __forceinline__ double res_pres(const GridDev& gd, long long row) {
+  constexpr int NV = ipow(3, DIM), NP = ipow(2, DIM);
+  const Geo& g = gd.g;
+  const Tabs<DIM>& T = tabs<DIM>();
+  gcdouble* __restrict__ X = gview(gd.x);
+  int k[3] = {0, 0, 0};
+  vert_of(g, row, k);
+  const int N = g.N;
+  const long long nn = g.nn, nV = g.nV;
+  bool okc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int E = k[d] - 1 + ((i >> d) & 1);
+      ok = ok && E >= 0 && E < N;
+    }
+    okc[i] = ok;
+  }
+  bool fv[2][5];
+  unsigned cpos[2][5];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) {
+      fv[d][o + 2] = free_coord(g, d, 2 * k[d] + o);
+      cpos[d][o + 2] = (unsigned)min(max(2 * k[d] + o, 0), 2 * N) * (d == 0 ? 1u : (unsigned)nn);
+    }
+  }
+  double acc = 0.0;
+#pragma unroll(DIM == 3 ? 1 : DIM)
+  for (int c = 0; c < DIM; ++c) {
+    gcdouble* __restrict__ xc = X + c * nV;
+#pragma unroll(DIM == 3 ? 1 : 8)
+    for (int oz = (DIM == 3 ? -2 : 0); oz <= (DIM == 3 ? 2 : 0); ++oz) {
+#pragma unroll
+      for (int oy = -2; oy <= 2; ++oy) {
+#pragma unroll
+        for (int ox = -2; ox <= 2; ++ox) {
+          const int o[3] = {ox, oy, oz};
+          bool fr = fv[0][ox + 2] && fv[1][oy + 2];
+          unsigned lin = cpos[0][ox + 2] + cpos[1][oy + 2];
+          if (DIM == 3) {
+            fr = fr && free_coord(g, 2, 2 * k[2] + oz);
+            lin += (unsigned)min(max(2 * k[2] + oz, 0), 2 * N) * (unsigned)(nn * nn);
+          }
+          const double xv = ld(xc, lin);
+          double coef = 0.0;
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            int lb = 0, lk = 0;
+            bool in = true;
+#pragma unroll
+            for (int d = 0, st = 1; d < DIM; ++d, st *= 3) {
+              const int eo = (i >> d) & 1, l = o[d] + 2 - 2 * eo;
+              in = in && l >= 0 && l <= 2;
+              lb += l * st;
+              lk |= (1 - eo) << d;
+            }
+            if (in) coef += okc[i] ? T.B[(c * NV + lb) * NP + lk] : 0.0;
+          }
+          acc += (fr ? coef : 0.0) * xv;
+        }
+      }
+    }
+  }
+  const double hB = DIM == 2 ? gd.h : gd.h * gd.h;
+  const long long gi = DIM * nV + row;
+  const double r = gview(gd.b)[gi] - hB * acc;
+  gview(gd.r)[gi] = r;
+  return r * r;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -119,36 +391,39 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Block task part: velocity parity type t (0 .. 2^d - 1) or 2^d for pressure rows.
 template <int DIM>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_residual(const GridDev* __restrict__ G,
-                                                     const BlockTask* __restrict__ tasks,
-                                                     double* __restrict__ partials) {
+__device__ __forceinline__ void residual_block(const GridDev* __restrict__ G, const BlockTask* __restrict__ tasks,
+                                               double* __restrict__ partials) {
   const BlockTask t = tasks[blockIdx.x];
-  if (t.grid < 0) return;   // padding block of the XCD permutation (whole block)
-  if (grid_idle(G[t.grid])) return;
+  if (t.grid < 0) return;
+  const GridDev& gd = G[t.grid];
+  if (grid_idle(gd)) return;
   double sq = 0.0;
-  {
-    const GridDev& gd = G[t.grid];
-    const int s = t.part;
-    const long long row = t.start + threadIdx.x;
-    if (row < gd.seg_rows[s]) {
-      double r = 0.0;
-      bool masked = false;
-      if (s == pressure_segment(DIM)) {
-        r = res_pressure<DIM>(gd, row);
-      } else {
-        switch (s & ((1 << DIM) - 1)) {
-          case 0: r = res_velocity<DIM, 0>(gd, s, row, masked); break;
-          case 1: r = res_velocity<DIM, 1>(gd, s, row, masked); break;
-          case 2: r = res_velocity<DIM, 2>(gd, s, row, masked); break;
-          case 3: r = res_velocity<DIM, 3>(gd, s, row, masked); break;
-          case 4: r = res_velocity<DIM, 4>(gd, s, row, masked); break;
-          case 5: r = res_velocity<DIM, 5>(gd, s, row, masked); break;
-          case 6: r = res_velocity<DIM, 6>(gd, s, row, masked); break;
-          default: r = res_velocity<DIM, 7>(gd, s, row, masked); break;
-        }
+  const long long row = t.start + threadIdx.x;
+  const int part = t.part;
+  const long long rows = part == (1 << DIM) ? gd.g.nP : seg_rows(gd.g, part);
+  if (row < rows) {
+    if constexpr (DIM == 2) {
+      switch (part) {
+        case 0: sq = res_node<2, 0>(gd, row); break;
+        case 1: sq = res_node<2, 1>(gd, row); break;
+        case 2: sq = res_node<2, 2>(gd, row); break;
+        case 3: sq = res_node<2, 3>(gd, row); break;
+        default: sq = res_pres<2>(gd, row); break;
       }
-      sq = r * r;
+    } else {
+      switch (part) {
+        case 0: sq = res_node<3, 0>(gd, row); break;
+        case 1: sq = res_node<3, 1>(gd, row); break;
+        case 2: sq = res_node<3, 2>(gd, row); break;
+        case 3: sq = res_node<3, 3>(gd, row); break;
+        case 4: sq = res_node<3, 4>(gd, row); break;
+        case 5: sq = res_node<3, 5>(gd, row); break;
+        case 6: sq = res_node<3, 6>(gd, row); break;
+        case 7: sq = res_node<3, 7>(gd, row); break;
+        default: sq = res_pres<3>(gd, row); break;
+      }
     }
   }
   if (partials == nullptr) return;
@@ -163,112 +438,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   }
 }
 
-// Deterministic sum of partials[first .. first+count) into out[0].
-__global__ __launch_bounds__(256) void k_norm_finalize(const double* __restrict__ partials, int first,
-                                                        int count, double* __restrict__ out) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < count; i += 256) s += partials[first + i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = red[0];
+__global__ __launch_bounds__(BLOCK) void k_residual2(const GridDev* __restrict__ G, const BlockTask* __restrict__ tasks,
+                                                     double* __restrict__ partials) {
+  residual_block<2>(G, tasks, partials);
 }
-
-// One block per problem: out[g] = sum of partials[first[g] .. first[g] + count[g]).
-__global__ __launch_bounds__(256) void k_norm_finalize_batch(const double* __restrict__ partials,
-                                                              const int* __restrict__ first,
-                                                              const int* __restrict__ count,
-                                                              double* __restrict__ out) {
-  __shared__ double red[256];
-  const int gidx = blockIdx.x;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < count[gidx]; i += 256) s += partials[first[gidx] + i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[gidx] = red[0];
-}
-
-// Batched copy: task = (problem, block of 256 entries).
-__global__ __launch_bounds__(256) void k_copy_batch(double* const* __restrict__ dst, const double* const* __restrict__ src,
-                                                     const long long* __restrict__ n,
-                                                     const BlockTask* __restrict__ tasks) {
-  const BlockTask t = tasks[blockIdx.x];
-  if (t.grid < 0) return;
-  const long long i = t.start + threadIdx.x;
-  if (i < n[t.grid]) dst[t.grid][i] = src[t.grid][i];
-}
-
-__global__ __launch_bounds__(256) void k_copy(double* __restrict__ dst, const double* __restrict__ src, long long n) {
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] = src[i];
-}
-
-__global__ __launch_bounds__(256) void k_fill(double* __restrict__ dst, double v, long long n) {
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] = v;
-}
-
-__global__ __launch_bounds__(256) void k_owner(const GridDev* __restrict__ G, int kind, long long n,
-                                                int* __restrict__ owner) {
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const Geo& g = G->g;
-  if (i < g.dim * g.nV) {
-    int a[3] = {0, 0, 0};
-    long long nl_;
-    split_vel(g, i, &nl_);
-    node_of(g, nl_, a);
-    if (node_dirichlet(g, a)) { owner[i] = -1; return; }
-  }
-  owner[i] = (int)owner_of(g, kind, i);
+__global__ __launch_bounds__(BLOCK) void k_residual3(const GridDev* __restrict__ G, const BlockTask* __restrict__ tasks,
+                                                     double* __restrict__ partials) {
+  residual_block<3>(G, tasks, partials);
 }
 
 void launch_residual(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, double* partials,
                      hipStream_t s) {
-  if (dim == 2)
-    hipLaunchKernelGGL(k_residual<2>, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, partials);
-  else
-    hipLaunchKernelGGL(k_residual<3>, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, partials);
-}
-
-void launch_norm_finalize_batch(const double* partials, const int* first, const int* count, int ngrids,
-                                double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_finalize_batch, dim3(ngrids), dim3(256), 0, s, partials, first, count, out);
-}
-
-void launch_copy_batch(double* const* dst, const double* const* src, const long long* n, const BlockTask* tasks,
-                       int ntasks, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy_batch, dim3(ntasks), dim3(256), 0, s, dst, src, n, tasks);
-}
-
-void launch_norm_finalize(const double* partials, int first, int count, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, partials, first, count, out);
-}
-
-static inline unsigned grid_for(long long n) {
-  long long b = (n + 255) / 256;
-  if (b > 65536) b = 65536;
-  return (unsigned)(b < 1 ? 1 : b);
-}
-
-void launch_copy(double* dst, const double* src, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n);
-}
-void launch_fill(double* dst, double v, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, dst, v, n);
-}
-void launch_owner(const GridDev* G, int kind, long long n, int* owner, hipStream_t s) {
-  hipLaunchKernelGGL(k_owner, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, kind, n, owner);
+  if (dim == 2) hipLaunchKernelGGL(k_residual2, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, partials);
+  else hipLaunchKernelGGL(k_residual3, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, partials);
 }
 
 }  // namespace rav

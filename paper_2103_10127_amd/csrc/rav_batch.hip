@@ -125,7 +125,7 @@ static rav_status build_plans(rav_batch* B) {
     const Geo& g0 = gds[0].g;
     std::vector<BlockTask> rt, pt, res;
     for (int i = 0; i < ng; ++i)
-      for (int s = 0; s < n_segments(B->dim); ++s) append_tiles(res, i, s, gds[i].seg_rows[s], BLOCK);
+      append_residual_tiles(res, i, gds[i].g);
     if ((st = upload(B, res, &P.res, &P.n_res)) != RAV_OK) return st;
     if (d > 0) {
       for (int i = 0; i < ng; ++i) append_tiles(rt, i, 0, gds[i].gc.n, BLOCK);
@@ -157,7 +157,7 @@ static rav_status build_plans(rav_batch* B) {
       if ((int)B->sub[p]->lv.size() - 1 != d) continue;
       P.top.push_back(i);
       const int f = (int)tr.size();
-      for (int s = 0; s < n_segments(B->dim); ++s) append_tiles(tr, i, s, gds[i].seg_rows[s], BLOCK);
+      append_residual_tiles(tr, i, gds[i].g);
       first.push_back(f);
       count.push_back((int)tr.size() - f);
       pid.push_back(p);

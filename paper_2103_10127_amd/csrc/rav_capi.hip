@@ -113,6 +113,37 @@ void append_tiles(std::vector<BlockTask>& out, int grid, int part, long long n, 
     out.push_back(t);
   }
 }
+
+void append_residual_tiles(std::vector<BlockTask>& out, int grid, const Geo& g) {
+  // Tiles of all node types are ordered by the half-grid row (then plane) of
+  // their first row, so the contiguous tile range an XCD receives covers one
+  // band of the grid for every type and the band of x stays in that XCD's L2.
+  struct Keyed { long long key; BlockTask t; };
+  std::vector<Keyed> kt;
+  const int np = (1 << g.dim) + 1;
+  for (int part = 0; part < np; ++part) {
+    const bool pres = part == (1 << g.dim);
+    const long long rows = pres ? g.nP : seg_rows(g, part);
+    for (long long r0 = 0; r0 < rows; r0 += BLOCK) {
+      int a[3] = {0, 0, 0};
+      if (pres) {
+        vert_of(g, r0, a);
+        for (int d = 0; d < g.dim; ++d) a[d] *= 2;
+      } else {
+        vel_row_node(g, part, r0, a);
+      }
+      const long long key = ((long long)a[2] * (2 * g.N + 1) + a[1]) * 16 + part;
+      BlockTask t{};
+      t.grid = grid; t.part = part; t.start = r0;
+      kt.push_back({key, t});
+    }
+  }
+  std::stable_sort(kt.begin(), kt.end(), [](const Keyed& x, const Keyed& y) { return x.key < y.key; });
+  for (Keyed& k : kt) {
+    k.t.logical = (int)out.size();
+    out.push_back(k.t);
+  }
+}
 }  // namespace rav
 
 static rav_status set_err(rav_ctx* ctx, rav_status st, const std::string& msg) {
@@ -162,14 +193,8 @@ static rav_status build_level(rav_ctx* ctx, int l) {
   CK(hipMemsetAsync(h.r, 0, sizeof(double) * g.n, ctx->stream));
   CK(hipMalloc((void**)&L.dd, sizeof(GridDev)));
   L.npatch = n_patches(g, D.patch);
-  // residual tiles: one block of 256 rows of a single segment
   std::vector<BlockTask> tiles;
-  for (int s = 0; s < nseg; ++s)
-    for (long long r0 = 0; r0 < h.seg_rows[s]; r0 += BLOCK) {
-      BlockTask t{};
-      t.grid = 0; t.part = s; t.start = r0; t.logical = (int)tiles.size();
-      tiles.push_back(t);
-    }
+  append_residual_tiles(tiles, 0, g);
   L.n_res_tiles = (int)tiles.size();
   rav_status st = rav_upload_tasks(ctx, tiles, &L.res_tasks, &L.n_res_tasks);
   if (st != RAV_OK) return st;
@@ -235,10 +260,32 @@ static rav_status build_level(rav_ctx* ctx, int l) {
                   ctx->stream);
   CK(hipGetLastError());
   CK(hipStreamSynchronize(ctx->stream));
+  // matrix-free residual coefficients: cells cut by an inclusion keep their cell matrix
+  std::vector<unsigned char> hu(ncell);
+  CK(hipMemcpy(hu.data(), uni, ncell, hipMemcpyDeviceToHost));
+  std::vector<int> cut_idx(ncell, -1), cut_cells;
+  for (long long e = 0; e < ncell; ++e)
+    if (!hu[e]) { cut_idx[e] = (int)cut_cells.size(); cut_cells.push_back((int)e); }
+  L.ncut = (long long)cut_cells.size();
+  const long long nv2 = D.dim == 2 ? 81 : 729;
+  int *d_cut_idx = nullptr, *d_cut_cells = nullptr;
+  CK(hipMalloc((void**)&L.ceta, sizeof(double) * ncell));
+  CK(hipMalloc((void**)&L.cutA, sizeof(double) * std::max<long long>(L.ncut * nv2, 1)));
+  CK(hipMalloc((void**)&d_cut_idx, sizeof(int) * ncell));
+  CK(hipMalloc((void**)&d_cut_cells, sizeof(int) * std::max<long long>(L.ncut, 1)));
+  CK(hipMemcpy(d_cut_idx, cut_idx.data(), sizeof(int) * ncell, hipMemcpyHostToDevice));
+  if (L.ncut) CK(hipMemcpy(d_cut_cells, cut_cells.data(), sizeof(int) * L.ncut, hipMemcpyHostToDevice));
+  launch_cell_coef(D.dim, ncell, L.dd, etaq, d_cut_idx, d_cut_cells, (int)L.ncut, L.ceta, L.cutA, ctx->stream);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(ctx->stream));
+  CK(hipFree(d_cut_idx));
+  CK(hipFree(d_cut_cells));
   CK(hipFree(etaq));
   CK(hipFree(uni));
   CK(hipFree(atd));
-  return RAV_OK;
+  h.ceta = L.ceta;
+  h.cutA = L.cutA;
+  return rav_upload_desc(ctx, L);
 }
 
 static rav_status build_coarse(rav_ctx* ctx) {
@@ -920,6 +967,7 @@ rav_status rav_destroy(rav_ctx* ctx) {
     for (int i = 0; i < h.nbk; ++i) (void)hipFree(h.bk[i].W);
     (void)hipFree(L.dd); (void)hipFree(L.res_tasks); (void)hipFree(L.partials);
     (void)hipFree(L.rtasks); (void)hipFree(L.ptasks);
+    (void)hipFree(L.ceta); (void)hipFree(L.cutA);
     for (ApplyLaunch& a : L.apply) (void)hipFree(a.tasks);
   }
   (void)hipFree(ctx->d_incl); (void)hipFree(ctx->Minv); (void)hipFree(ctx->d_status);

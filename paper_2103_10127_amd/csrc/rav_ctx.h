@@ -27,6 +27,9 @@ struct LevelHost {
   GridDev hd{};
   GridDev* dd = nullptr;
   long long nvals = 0;
+  double* ceta = nullptr;        // per-cell coefficients of the matrix-free residual
+  double* cutA = nullptr;        // cell matrices of the cut cells
+  long long ncut = 0;
   BlockTask* res_tasks = nullptr;
   int n_res_tasks = 0;
   int n_res_tiles = 0;
@@ -46,6 +49,10 @@ std::vector<BlockTask> xcd_order(const std::vector<BlockTask>& logical);
 
 // Logical tiles of `per_block` items over [0, n) for one grid.
 void append_tiles(std::vector<BlockTask>& out, int grid, int part, long long n, int per_block);
+
+// Residual tiles of one grid: BLOCK rows of one velocity node parity type
+// (part = t, all components) or of the pressure rows (part = 2^d).
+void append_residual_tiles(std::vector<BlockTask>& out, int grid, const Geo& g);
 
 }  // namespace rav
 

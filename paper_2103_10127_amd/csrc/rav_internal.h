@@ -39,6 +39,11 @@ struct GridDev {
   double* b;             // level right-hand side
   double* r;             // level residual
   double* vals;          // ELL operator values
+  // per-cell coefficients of the matrix-free residual: h^(d-2) eta for cells
+  // with one viscosity at all Gauss points, -(1 + i) for the i-th cut cell,
+  // whose full viscous cell matrix (h^(d-2) included) is cutA[i][a][b]
+  const double* ceta;
+  const double* cutA;
   long long seg_off[MAX_SEG];
   long long seg_rows[MAX_SEG];
   // coarser level (transfer target), valid when has_coarse
@@ -93,8 +98,12 @@ void launch_assemble(int dim, long long ncell, const GridDev* G, const BlockTask
                      unsigned char* uni, hipStream_t s);
 void launch_rhs(int dim, const GridDev* Gh, const GridDev* Gd, const double* params, double* fq,
                 double* b, hipStream_t s);
+// Residual tiles: part = velocity node parity type t (rows of seg_rows(g, t))
+// or 2^d for the pressure rows.
 void launch_residual(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, double* partials,
                      hipStream_t s);
+void launch_cell_coef(int dim, long long ncell, const GridDev* G, const double* etaq, const int* cut_idx,
+                      const int* cut_cells, int ncut, double* ceta, double* cutA, hipStream_t s);
 void launch_norm_finalize(const double* partials, int first, int count, double* out, hipStream_t s);
 void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const GridDev* G, const BlockTask* tasks,
                       int ntasks, hipStream_t s);

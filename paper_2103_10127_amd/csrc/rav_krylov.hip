@@ -19,7 +19,6 @@ void launch_dot(const double* a, const double* b, long long n, double* partial, 
                 hipStream_t s);
 void launch_axpy_dev(double* y, const double* x, const double* c, double sign, long long n, hipStream_t s);
 void launch_div_dev(double* y, const double* x, const double* c, long long n, hipStream_t s);
-void launch_axpby_h(double a, const double* x, double b, double* y, long long n, hipStream_t s);
 }  // namespace rav
 
 // Internal: one V-cycle of the context on its finest level (defined in rav_capi.hip).
@@ -92,7 +91,7 @@ extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double*
       beta = beta0;
     }
     // V_0 = r / beta
-    launch_axpby_h(1.0 / beta, L.hd.r, 0.0, V[0], n, s);
+    launch_axpby(1.0 / beta, L.hd.r, 0.0, V[0], n, s);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jend = 0;
@@ -106,7 +105,7 @@ extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double*
       launch_fill(L.hd.b, 0.0, n, s);
       rav_residual_level(ctx, lf, false);
       double* w = V[j + 1];
-      launch_axpby_h(-1.0, L.hd.r, 0.0, w, n, s);
+      launch_axpby(-1.0, L.hd.r, 0.0, w, n, s);
       // modified Gram-Schmidt, coefficients h[i][j] in device memory
       for (int i = 0; i <= j; ++i) {
         double* hij = hdev + (size_t)j * (m + 2) + i;
@@ -147,7 +146,7 @@ extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double*
       for (int k = i + 1; k < jend; ++k) t -= H[(size_t)i * m + k] * y[k];
       y[i] = H[(size_t)i * m + i] != 0.0 ? t / H[(size_t)i * m + i] : 0.0;
     }
-    for (int i = 0; i < jend; ++i) launch_axpby_h(y[i], Z[i], 1.0, xk, n, s);
+    for (int i = 0; i < jend; ++i) launch_axpby(y[i], Z[i], 1.0, xk, n, s);
     if (res <= rtol * beta0) {
       double beta_true = 0.0;
       rav_status st = true_residual(&beta_true);
