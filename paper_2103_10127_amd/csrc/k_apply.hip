@@ -3,7 +3,7 @@
 // RAV (eq. 13, Sec. 4.3): x[owned(i)] += omega_i W_i r[I_i] where W_i holds the
 //   owned rows of L_i^{-1}.  One lane per patch: the lane gathers r at the
 //   patch's columns (the overlapping reads of neighbouring lanes hit the
-//   caches) and streams its W_i with 16-byte loads from the patch-interleaved
+//   caches) and streams its W_i with 16-byte loads from the chunk-major
 //   layout, so a wavefront reads 1 KiB contiguously per load.  Owned sets
 //   partition the DoFs, so the scatter needs no atomics and no colouring.
 //   Low-precision W (FP32/BF16) is expanded to FP32 and accumulated in FP32;
@@ -78,6 +78,93 @@ __device__ __forceinline__ long long patch_col(const Geo& g, const int* k, int l
   return DIM * g.nV + vert_lin(g, v);
 }
 
+// ---- RAV apply: column and owned-DoF maps with compile-time dimension ------
+typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) const char gcchar;
+
+// Level sizes held in registers by the apply kernel.
+struct ColMap {
+  unsigned nn, nV, np1, twoN;
+  unsigned dmask;
+};
+
+// Global index of local column l of the patch anchored at k.  Vertex-patch
+// columns outside the grid are clamped to an in-range node: the owned inverse
+// rows are exactly zero there (padding columns of the local matrix are unit
+// rows and columns), and r at the clamped node is a finite residual, so the
+// product contributes nothing.  Element-patch columns are always inside.
+// With a wave-uniform l the decoding stays on the scalar unit.
+template <int DIM, int KIND>
+__device__ __forceinline__ unsigned col_index(const ColMap& cm, const int* k, int l) {
+  constexpr int NN = KIND == KIND_VERTEX ? ipow(5, DIM) : ipow(3, DIM);
+  if (l < DIM * NN) {
+    const int c = l / NN;
+    int r = l - c * NN;
+    unsigned lin = 0, st = 1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int a;
+      if (KIND == KIND_VERTEX) {
+        a = 2 * k[d] + r % 5 - 2;
+        a = min(max(a, 0), (int)cm.twoN);
+        r /= 5;
+      } else {
+        a = 2 * k[d] + r % 3;
+        r /= 3;
+      }
+      lin += st * (unsigned)a;
+      st *= cm.nn;
+    }
+    return (unsigned)c * cm.nV + lin;
+  }
+  int r = l - DIM * NN;
+  unsigned lin = 0, st = 1;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    lin += st * (unsigned)(k[d] + (KIND == KIND_VERTEX ? 0 : (r & 1)));
+    r >>= 1;
+    st *= cm.np1;
+  }
+  return (unsigned)DIM * cm.nV + lin;
+}
+
+// Global index of local DoF l of the patch (compile-time l), -1 for padding
+// (outside the grid or on a masked side).
+template <int DIM, int KIND>
+__device__ __forceinline__ long long own_index(const ColMap& cm, const int* k, int l) {
+  constexpr int NN = KIND == KIND_VERTEX ? ipow(5, DIM) : ipow(3, DIM);
+  if (l < DIM * NN) {
+    const int c = l / NN;
+    int r = l - c * NN;
+    unsigned lin = 0, st = 1;
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int a = KIND == KIND_VERTEX ? 2 * k[d] + r % 5 - 2 : 2 * k[d] + r % 3;
+      r /= KIND == KIND_VERTEX ? 5 : 3;
+      ok = ok && a >= 0 && a <= (int)cm.twoN;
+      ok = ok && !(((cm.dmask >> (2 * d)) & 1u) && a == 0) && !(((cm.dmask >> (2 * d + 1)) & 1u) && a == (int)cm.twoN);
+      lin += st * (unsigned)a;
+      st *= cm.nn;
+    }
+    return ok ? (long long)((unsigned)c * cm.nV + lin) : -1;
+  }
+  int r = l - DIM * NN;
+  unsigned lin = 0, st = 1;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    lin += st * (unsigned)(k[d] + (KIND == KIND_VERTEX ? 0 : (r & 1)));
+    r >>= 1;
+    st *= cm.np1;
+  }
+  return (long long)((unsigned)DIM * cm.nV + lin);
+}
+
+__device__ __forceinline__ double ldr(gcdouble* base, unsigned idx) {
+  return *(gcdouble*)((gcchar*)base + ((size_t)idx << 3));
+}
+
 __host__ __device__ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 
 // Columns are processed in groups of G = V / gcd(nown, V) so that every group
@@ -85,10 +172,10 @@ __host__ __device__ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_
 // code, bounded registers), the chunks inside a group and the ragged tail are
 // unrolled at compile time.  SPLIT lanes share one patch (column groups dealt
 // round-robin, partial sums combined with shuffles): SPLIT = 1 streams the
-// large levels, SPLIT = 8 shortens the dependent load chain on small levels
-// where too few wavefronts exist to hide memory latency.
+// large levels, SPLIT = 8 and 32 shorten the dependent load chain on smaller
+// levels where too few wavefronts exist to hide memory latency.
 template <int DIM, int KIND, int CLS, typename WT, int SPLIT>
-__global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__ G,
+__global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply(const GridDev* __restrict__ G,
                                                       const BlockTask* __restrict__ tasks) {
   typedef typename WTraits<WT>::acc_t acc_t;
   typedef typename WTraits<WT>::vec_t vec_t;
@@ -112,9 +199,11 @@ __global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__
   const Geo& g = gd.g;
   int k[3] = {0, 0, 0};
   bucket_anchor(g, KIND, CLS, p, k);
-  const double* __restrict__ r = gd.r;
-  const vec_t* __restrict__ W = reinterpret_cast<const vec_t*>(bk.W) + p;
-  const long long cs = bk.count_pad;   // chunk stride in vectors
+  const ColMap cm{(unsigned)g.nn, (unsigned)g.nV, (unsigned)g.np1, 2u * (unsigned)g.N, g.dmask};
+  gcdouble* __restrict__ r = (gcdouble*)gd.r;
+  typedef __attribute__((address_space(1))) const vec_t gcvec;
+  gcvec* __restrict__ W = (gcvec*)bk.W + w_vec(bk, p, 0);
+  const long long cs = bk.count_pad;   // chunk stride in vectors (chunk-major layout)
   acc_t acc[NOWN];
 #pragma unroll
   for (int j = 0; j < NOWN; ++j) acc[j] = acc_t(0);
@@ -125,10 +214,7 @@ __global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__
     for (int i = 0; i < CPG; ++i) w[i] = __builtin_nontemporal_load(W + (long long)(gi * CPG + i) * cs);
     acc_t rv[GC];
 #pragma unroll
-    for (int q = 0; q < GC; ++q) {
-      const long long col = patch_col<DIM, KIND>(g, k, gi * GC + q);
-      rv[q] = col >= 0 ? acc_t(r[col]) : acc_t(0);
-    }
+    for (int q = 0; q < GC; ++q) rv[q] = acc_t(ldr(r, col_index<DIM, KIND>(cm, k, gi * GC + q)));
 #pragma unroll
     for (int i = 0; i < CPG; ++i) {
 #pragma unroll
@@ -145,10 +231,7 @@ __global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__
       for (int i = 0; i < TAIL_CH; ++i) w[i] = __builtin_nontemporal_load(W + (long long)(NG * CPG + i) * cs);
       acc_t rv[TAIL];
 #pragma unroll
-      for (int q = 0; q < TAIL; ++q) {
-        const long long col = patch_col<DIM, KIND>(g, k, NG * GC + q);
-        rv[q] = col >= 0 ? acc_t(r[col]) : acc_t(0);
-      }
+      for (int q = 0; q < TAIL; ++q) rv[q] = acc_t(ldr(r, col_index<DIM, KIND>(cm, k, NG * GC + q)));
 #pragma unroll
       for (int el = 0; el < TAIL_E; ++el) acc[el % NOWN] += vec_elem<WT>(w[el / V], el % V) * rv[el / NOWN];
     }
@@ -161,13 +244,11 @@ __global__ __launch_bounds__(BLOCK) void k_rav_apply(const GridDev* __restrict__
     }
   }
   const double om = gd.omega_patch ? (double)gd.omega_patch[patch_lin(g, KIND, k)] : gd.omega;
-  double* __restrict__ x = gd.x;
+  gdouble* __restrict__ x = (gdouble*)gd.x;
 #pragma unroll
   for (int j = 0; j < NOWN; ++j) {
     if (SPLIT > 1 && (j % SPLIT) != sl) continue;
-    const int l = bucket_own_local(DIM, KIND, CLS, j);
-    int comp, node[3];
-    const long long gi = patch_local_dof(g, KIND, k, l, &comp, node);
+    const long long gi = own_index<DIM, KIND>(cm, k, bucket_own_local(DIM, KIND, CLS, j));
     if (gi >= 0) x[gi] += om * (double)acc[j];
   }
 }
@@ -176,10 +257,10 @@ template <int DIM, int KIND, typename WT, int SPLIT>
 static void launch_apply_t(int cls, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
 #define RAV_APPLY_CASE(C)                                                                                 \
   case C:                                                                                                \
-    hipLaunchKernelGGL((k_rav_apply<DIM, KIND, C, WT, SPLIT>), dim3(ntasks), dim3(BLOCK), 0, s, G, tasks); \
+    hipLaunchKernelGGL((k_rav_apply<DIM, KIND, C, WT, SPLIT>), dim3(ntasks), dim3(apply_block(SPLIT)), 0, s, G, tasks); \
     break;
   if constexpr (KIND == KIND_VERTEX) {
-    hipLaunchKernelGGL((k_rav_apply<DIM, KIND, 0, WT, SPLIT>), dim3(ntasks), dim3(BLOCK), 0, s, G, tasks);
+    hipLaunchKernelGGL((k_rav_apply<DIM, KIND, 0, WT, SPLIT>), dim3(ntasks), dim3(apply_block(SPLIT)), 0, s, G, tasks);
   } else if constexpr (DIM == 2) {
     switch (cls) {
       RAV_APPLY_CASE(0)
@@ -221,7 +302,8 @@ static void launch_apply_s(int dim, int kind, int cls, int prec, const GridDev* 
 
 void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const GridDev* G, const BlockTask* tasks,
                       int ntasks, hipStream_t s) {
-  if (split > 1) launch_apply_s<APPLY_SPLIT>(dim, kind, cls, prec, G, tasks, ntasks, s);
+  if (split == APPLY_SPLIT_SMALL) launch_apply_s<APPLY_SPLIT_SMALL>(dim, kind, cls, prec, G, tasks, ntasks, s);
+  else if (split > 1) launch_apply_s<APPLY_SPLIT>(dim, kind, cls, prec, G, tasks, ntasks, s);
   else launch_apply_s<1>(dim, kind, cls, prec, G, tasks, ntasks, s);
 }
 

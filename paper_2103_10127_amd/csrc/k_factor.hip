@@ -153,7 +153,7 @@ __global__ __launch_bounds__(64) void k_factor(const GridDev* __restrict__ G, in
     const int l = bucket_own_local(DIM, KIND, cls, j);
     for (int c = lane; c < NPAD; c += 64) {
       const long long e = (long long)c * nown + j;
-      store_w(W, (e / V) * bk.wstride + p * V + e % V, A[l * LD + c]);
+      store_w(W, w_vec(bk, p, e / V) * V + e % V, A[l * LD + c]);
     }
   }
 }

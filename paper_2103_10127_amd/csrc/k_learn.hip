@@ -166,10 +166,10 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, double*
 }
 
 // ---- adjoint pieces of the RAV sweep (2D vertex patches, FP64 rows) ---------
-// Owned-row entry e of patch p in the chunk-interleaved FP64 layout (V = 2).
+// Owned-row entry e of patch p in the tile-major FP64 layout (V = 2).
 __device__ __forceinline__ double wrow(const Bucket& bk, long long p, int e) {
   const double* W = reinterpret_cast<const double*>(bk.W);
-  return W[(long long)(e >> 1) * bk.wstride + p * 2 + (e & 1)];
+  return W[w_vec(bk, p, e >> 1) * 2 + (e & 1)];
 }
 
 __device__ __forceinline__ long long vcol(const Geo& g, const int* k, int c) {

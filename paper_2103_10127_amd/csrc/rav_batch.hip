@@ -128,8 +128,8 @@ static rav_status build_plans(rav_batch* B) {
       append_residual_tiles(res, i, gds[i].g);
     if ((st = upload(B, res, &P.res, &P.n_res)) != RAV_OK) return st;
     if (d > 0) {
-      for (int i = 0; i < ng; ++i) append_tiles(rt, i, 0, gds[i].gc.n, BLOCK);
-      for (int i = 0; i < ng; ++i) append_tiles(pt, i, 0, gds[i].g.n, BLOCK);
+      for (int i = 0; i < ng; ++i) append_residual_tiles(rt, i, gds[i].gc);
+      for (int i = 0; i < ng; ++i) append_residual_tiles(pt, i, gds[i].g);
       if ((st = upload(B, rt, &P.rtask, &P.n_rtask)) != RAV_OK) return st;
       if ((st = upload(B, pt, &P.ptask, &P.n_ptask)) != RAV_OK) return st;
       // one apply launch per bucket class; every problem at this depth has the same buckets
@@ -138,9 +138,9 @@ static rav_status build_plans(rav_batch* B) {
         ApplyLaunch al;
         al.bucket = bi;
         al.cls = gds[0].bk[bi].cls;
-        al.split = total < SPLIT_BELOW ? APPLY_SPLIT : 1;
+        al.split = apply_split(total, SPLIT_BELOW);
         std::vector<BlockTask> at;
-        for (int i = 0; i < ng; ++i) append_tiles(at, i, bi, gds[i].bk[bi].count, BLOCK / al.split);
+        for (int i = 0; i < ng; ++i) append_tiles(at, i, bi, gds[i].bk[bi].count, apply_block(al.split) / al.split);
         if ((st = upload(B, at, &al.tasks, &al.ntasks)) != RAV_OK) return st;
         P.apply.push_back(al);
       }

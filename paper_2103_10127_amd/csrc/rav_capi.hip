@@ -201,8 +201,8 @@ static rav_status build_level(rav_ctx* ctx, int l) {
   if (l > 0) {
     const Geo gc = make_geo(D.dim, N / 2, D.bc_dirichlet_mask);
     std::vector<BlockTask> rt, pt;
-    append_tiles(rt, 0, 0, gc.n, BLOCK);
-    append_tiles(pt, 0, 0, g.n, BLOCK);
+    append_residual_tiles(rt, 0, gc);
+    append_residual_tiles(pt, 0, g);
     st = rav_upload_tasks(ctx, rt, &L.rtasks, &L.n_rtasks);
     if (st != RAV_OK) return st;
     st = rav_upload_tasks(ctx, pt, &L.ptasks, &L.n_ptasks);
@@ -223,8 +223,8 @@ static rav_status build_level(rav_ctx* ctx, int l) {
       ApplyLaunch al;
       al.bucket = h.nbk;
       al.cls = B.cls;
-      al.split = cnt < ctx->split_below ? APPLY_SPLIT : 1;
-      const int per_block = BLOCK / al.split;
+      al.split = apply_split(cnt, ctx->split_below);
+      const int per_block = apply_block(al.split) / al.split;
       std::vector<BlockTask> at;
       for (long long p0 = 0; p0 < cnt; p0 += per_block) {
         BlockTask t{};
@@ -515,9 +515,8 @@ rav_status rav_factor_patches(rav_ctx* ctx) {
       for (int bi = 0; bi < h.nbk; ++bi) {
         Bucket& B = h.bk[bi];
         B.nchunk = ((long long)npad * B.nown + V - 1) / V;
-        B.wstride = B.count_pad * V;
         if (!B.W) {
-          const size_t bytes = esz * (size_t)B.nchunk * (size_t)B.wstride;
+          const size_t bytes = esz * (size_t)V * (size_t)B.nchunk * (size_t)B.count_pad;
           CK(hipMalloc(&B.W, bytes));
           CK(hipMemsetAsync(B.W, 0, bytes, ctx->stream));
         }
@@ -842,8 +841,7 @@ rav_status rav_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* ou
   std::vector<double> W((size_t)B.nchunk * V);
   std::vector<unsigned char> chunk(16);
   for (long long m = 0; m < B.nchunk; ++m) {
-    CK(hipMemcpy(chunk.data(), (const char*)B.W + esz * (size_t)(m * B.wstride + pos * V), 16,
-                 hipMemcpyDeviceToHost));
+    CK(hipMemcpy(chunk.data(), (const char*)B.W + 16 * (size_t)w_vec(B, pos, m), 16, hipMemcpyDeviceToHost));
     for (int v = 0; v < V; ++v) {
       double val;
       if (esz == 8) { double t; std::memcpy(&t, chunk.data() + 8 * v, 8); val = t; }

@@ -19,9 +19,14 @@ struct ApplyLaunch {
   int ntasks = 0;
 };
 
-// Buckets with fewer patches than this run the split apply variant unless the
-// set-up autotuner measured otherwise.
+// Buckets with fewer patches than SPLIT_BELOW run the split apply variant
+// (APPLY_SPLIT lanes per patch), below SPLIT_BELOW / 60 the one with
+// APPLY_SPLIT_SMALL lanes per patch: with few wavefronts in flight, splitting a
+// patch over more lanes shortens the dependent load chain of each lane.
 constexpr long long SPLIT_BELOW = 120000;
+inline int apply_split(long long count, long long split_below) {
+  return count < split_below / 60 ? APPLY_SPLIT_SMALL : count < split_below ? APPLY_SPLIT : 1;
+}
 
 struct LevelHost {
   GridDev hd{};
@@ -36,9 +41,9 @@ struct LevelHost {
   double* partials = nullptr;
   std::vector<ApplyLaunch> apply;
   long long npatch = 0;
-  BlockTask* rtasks = nullptr;   // restriction: tiles over the coarser level's DoFs
+  BlockTask* rtasks = nullptr;   // restriction: node-type tiles over the coarser level
   int n_rtasks = 0;
-  BlockTask* ptasks = nullptr;   // prolongation: tiles over this level's DoFs
+  BlockTask* ptasks = nullptr;   // prolongation: node-type tiles over this level
   int n_ptasks = 0;
 };
 
@@ -50,8 +55,9 @@ std::vector<BlockTask> xcd_order(const std::vector<BlockTask>& logical);
 // Logical tiles of `per_block` items over [0, n) for one grid.
 void append_tiles(std::vector<BlockTask>& out, int grid, int part, long long n, int per_block);
 
-// Residual tiles of one grid: BLOCK rows of one velocity node parity type
-// (part = t, all components) or of the pressure rows (part = 2^d).
+// Node-type tiles of one grid (residual, restriction onto it, prolongation
+// onto it): BLOCK rows of one velocity node parity type (part = t, all
+// components) or of the pressure rows (part = 2^d).
 void append_residual_tiles(std::vector<BlockTask>& out, int grid, const Geo& g);
 
 }  // namespace rav

@@ -11,24 +11,36 @@ constexpr int MAX_SEG = 25;      // 3 components x 8 parity types + pressure
 constexpr int MAX_BUCKETS = 8;
 constexpr int MAX_INCL = 64;
 constexpr int BLOCK = 256;       // threads per block of the streaming kernels
-constexpr int APPLY_SPLIT = 8;   // lanes per patch of the small-level RAV apply
+constexpr int APPLY_SPLIT = 8;   // lanes per patch of the mid-size-level RAV apply
+constexpr int APPLY_SPLIT_SMALL = 32;   // lanes per patch on the smallest levels
+// Threads per block of the RAV apply: one-wavefront blocks keep the tail of a
+// streaming launch short (a straggling block holds one wavefront of work); the
+// 8-lane split variant runs best with 256-thread blocks.
+constexpr int APPLY_BLOCK_MAX = 256;
+__host__ __device__ constexpr int apply_block(int split) { return split == APPLY_SPLIT ? 256 : 64; }
 
 enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
 
 // Owned inverse rows of one bucket of patches (same owned pattern).
 // Entry e = c * nown + j (column c of the padded patch, owned row j) of patch p
-// lives at W[(e / V) * wstride + p * V + e % V] with V = 16 bytes / element
-// size, so a wavefront streaming one chunk of 64 patches reads 1 KiB
-// contiguously.
+// lives in 16-byte vector m = e / V (V = 16 bytes / element size), slot e % V.
+// Vectors are chunk-major: vector m of patch p is vector m * count_pad + p, so
+// a wavefront reads 1 KiB contiguously per load and the wavefronts of a launch,
+// which advance through the chunks at similar rates, sweep W plane by plane
+// (close to one sequential stream, the access order HBM serves fastest).
 struct Bucket {
   int cls;
   int nown;
   long long count;       // patches in the bucket
   long long count_pad;   // rounded up to a multiple of 64
   long long nchunk;      // ceil(npad * nown / V)
-  long long wstride;     // count_pad * V (elements)
   void* W;
 };
+
+// Index (in 16-byte vectors) of vector m of patch p.
+__host__ __device__ __forceinline__ long long w_vec(const Bucket& bk, long long p, long long m) {
+  return m * bk.count_pad + p;
+}
 
 // One level of one problem, resident in device memory.
 struct GridDev {
