@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=8000, help="patches in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=20000, help="patches in the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch the plain copy kernel on 1 GiB (for HBM counter scaling)")
     return ap.parse_args()
@@ -169,6 +169,9 @@ def main():
     sweep_rate = n_fine / sweep_s
     roof_apply = apply_bytes / (1e-3 * ms_apply) / 1e9
     roof_res = resid_bytes / (1e-3 * ms_res) / 1e9
+    # HBM bytes per apply launch from the committed PMC summary (None once the kernel changed)
+    from paper_2103_10127_amd.profiling import read_traffic
+    traffic = read_traffic(os.path.join(ROOT, "profiles", "rav_apply_2d512_fp64_traffic.md"))
 
     out = {
         "metric": "RAV smoothed DoFs/s (whole V(2,2) solve to a 1e-8 residual reduction)",
@@ -186,7 +189,7 @@ def main():
                   "pct_hbm_peak": 100.0 * (apply_bytes + resid_bytes) / sweep_s / 1e9 / HBM_PEAK_GBS},
         "roofline": {"bound": "hbm", "kernel": "k_rav_apply<2,VERTEX,0,double> (512x512 level)",
                      "achieved": roof_apply, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": roof_apply / HBM_PEAK_GBS, "traffic": None,
+                     "frac": roof_apply / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": apply_bytes},
         "roofline_residual": {"bound": "hbm", "achieved": roof_res, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": roof_res / HBM_PEAK_GBS, "algorithmic_bytes": resid_bytes},

@@ -2,6 +2,14 @@
 
     python -m paper_2103_10127_amd.profiling trace <kernel_trace.csv> [--match NAME]
     python -m paper_2103_10127_amd.profiling counters <counter_collection.csv> [--match NAME]
+    python -m paper_2103_10127_amd.profiling traffic <fetch.csv> <write.csv> --match NAME
+
+`traffic` turns one FETCH_SIZE and one WRITE_SIZE collection (separate runs,
+both including the 1 GiB copy of `bench.py --copy-calibration`) into HBM bytes
+per launch of the largest-grid launch group of the matched kernel: each counter
+is scaled by (bytes the copy moves) / (what the counter reads for the copy).
+The summary records a hash of the kernel's sources; `bench.py` reports the
+traffic only while the sources still hash to it.
 
 A kernel is launched on every level of the hierarchy with a different grid
 size, so launches are grouped by (kernel name, grid size): the group with the
@@ -80,10 +88,64 @@ def counter_summary(path: str, match: str | None = None):
     return out
 
 
+COPY_GRID = 16777216          # launch grid of the 1 GiB calibration copy
+COPY_KIB = (1 << 30) / 1024   # bytes the copy reads (and writes), in KiB
+TRAFFIC_SOURCES = ("csrc/k_apply.hip", "csrc/rav_internal.h", "csrc/rav_index.h")
+
+
+def sources_hash() -> str:
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(here, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, match: str) -> dict:
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = counter_summary(path)
+        copy = [r for r in rows if "k_copy" in r["kernel"] and r["grid"] == COPY_GRID]
+        kern = [r for r in rows if match in r["kernel"]]
+        if not copy or not kern:
+            raise SystemExit(f"{path}: calibration copy or kernel '{match}' missing")
+        k = max(kern, key=lambda r: r["grid"])
+        factor = COPY_KIB / copy[0][counter]
+        out[counter] = dict(kernel=k["kernel"], grid=k["grid"], dispatches=k["dispatches"],
+                            kib=k[counter], copy_kib=copy[0][counter], factor=factor,
+                            bytes=k[counter] * factor * 1024)
+    out["traffic_bytes"] = out["FETCH_SIZE"]["bytes"] + out["WRITE_SIZE"]["bytes"]
+    out["sources_sha256"] = sources_hash()
+    return out
+
+
+def read_traffic(path: str):
+    """Traffic per launch from a committed summary, or None when it is missing
+    or the kernel sources changed since the counters were taken."""
+    import os
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("    "):
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("sources_sha256") != sources_hash():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "counters"])
+    ap.add_argument("mode", choices=["trace", "counters", "traffic"])
     ap.add_argument("path")
+    ap.add_argument("path2", nargs="?")
     ap.add_argument("--match", default=None)
     ap.add_argument("--top", type=int, default=25)
     a = ap.parse_args()
@@ -93,9 +155,19 @@ def main():
         for r in res[: a.top]:
             print(f"{r['calls']:6d} {r['grid']:9d} {r['avg_us']:10.2f} {r['median_us']:10.2f} "
                   f"{r['total_us']:11.1f}  {_short(r['kernel'])}")
-    else:
+    elif a.mode == "counters":
         for r in counter_summary(a.path, a.match)[: a.top]:
             print(r)
+    else:
+        t = traffic_summary(a.path, a.path2, a.match)
+        f, w = t["FETCH_SIZE"], t["WRITE_SIZE"]
+        print(f"kernel: {f['kernel']} (grid {f['grid']}, {f['dispatches']} dispatches averaged)")
+        for c, r in (("FETCH_SIZE", f), ("WRITE_SIZE", w)):
+            print(f"{c}: {r['kib']:.1f} KiB per dispatch; copy of 1 GiB reads {r['copy_kib']:.1f} KiB"
+                  f" -> factor {r['factor']:.4f} -> {r['bytes'] / 1e6:.2f} MB")
+        print()
+        print(f"    traffic_bytes_per_launch: {t['traffic_bytes']:.0f}")
+        print(f"    sources_sha256: {t['sources_sha256']}")
 
 
 if __name__ == "__main__":
