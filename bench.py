@@ -46,6 +46,18 @@ def sum_owned_times_patch(N: int) -> int:
     return int(np.sum(n_i * o_i))
 
 
+def sum_owned_times_patch_3d_element(N: int) -> int:
+    """sum_i (owned rows x patch columns) of all-Dirichlet 3D element patches.
+    Per axis a cell at e has 3 - [e=0] - [e=N-1] free velocity positions, owns
+    2 - [e=0] of them and 1 + [e=N-1] pressure positions; n_i = 3 prod c + 8,
+    owned_i = 3 prod o + prod p, and each product term sums separably."""
+    e = np.arange(N)
+    lo, hi = (e == 0).astype(np.int64), (e == N - 1).astype(np.int64)
+    c, o, p = 3 - lo - hi, 2 - lo, 1 + hi
+    S = lambda f: int(f.sum())
+    return 9 * S(c * o) ** 3 + 3 * S(c * p) ** 3 + 24 * S(o) ** 3 + 8 * S(p) ** 3
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +68,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=20000, help="patches in the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch the plain copy kernel on 1 GiB (for HBM counter scaling)")
+    ap.add_argument("--workload", default="2d-512", choices=["2d-512", "3d-64", "2d-1024", "batch256"],
+                    help="2d-512: the headline solve (default); 3d-64: finest-level element-patch sweep; "
+                         "2d-1024: inclusions at contrast 1e4, GMRES + V-cycle; batch256: 256 problems")
     return ap.parse_args()
 
 
@@ -112,6 +127,9 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "2d-512":
+        {"3d-64": bench_3d, "2d-1024": bench_1024, "batch256": bench_batch}[args.workload](args)
+        return
     import torch
     from paper_2103_10127_amd import Hierarchy
 
@@ -233,6 +251,170 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(out))
+
+
+def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": "synthetic (seeded manufactured-solution forcing)", "config": config}
+    out.update(extra)
+    print(json.dumps(out))
+
+
+def bench_3d(args):
+    """Finest-level RAV sweep (residual + apply) of the 3D element-patch workload.
+    Element patches with a continuous Q1 pressure give no convergent V-cycle, so
+    this workload is measured per sweep (rates only), for FP64/FP32/BF16 rows."""
+    import torch
+    from paper_2103_10127_amd import Hierarchy
+    cfg = ri.CONFIGS["3d-64"]
+    N, nl = cfg["n_cells"], cfg["n_levels"]
+    reps = max(args.steps, 5)
+    res = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        t0 = time.perf_counter()
+        H = Hierarchy(dim=3, n_cells=N, n_levels=nl, dmask=cfg["dmask"], kind="element", omega=0.5,
+                      precision=prec)
+        H.factor()
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        n_fine, n_free = H.dofs(nl - 1)
+        b = torch.zeros(n_fine, dtype=torch.float64, device="cuda")
+        H.assemble_rhs(ri.mms_params(3, cfg["seed"]), b)
+        x = torch.zeros_like(b)
+        H.time_sweep(nl - 1, max(args.warmup, 1), x, b)
+        ms_res, ms_apply = H.time_sweep(nl - 1, reps, x, b)
+        res[prec] = dict(ms_residual=ms_res, ms_apply=ms_apply, setup_s=round(setup, 3))
+        H.close()
+    esz = {"fp64": 8, "fp32": 4, "bf16": 2}
+    sum_on = sum_owned_times_patch_3d_element(N)
+    for prec, r in res.items():
+        r["apply_GBs"] = (esz[prec] * sum_on + 8 * n_fine + 16 * n_free) / (1e-3 * r["ms_apply"]) / 1e9
+    f = res["fp64"]
+    apply_bytes = 8 * sum_on + 8 * n_fine + 16 * n_free
+    resid_bytes = 24 * n_fine + 8 * N ** 3
+    sweep_ms = f["ms_residual"] + f["ms_apply"]
+    _line("RAV smoothed DoFs/s (finest-level sweep: residual + apply)", n_fine / (1e-3 * sweep_ms), "DoF/s",
+          reps, max(args.warmup, 1), sweep_ms, "f64",
+          {"workload": "3D Taylor-Hood Q2/Q1 64^3, 5 levels, RAV element patches, one finest-level sweep",
+           "dofs": n_fine, "patches": N ** 3, "sum_owned_x_cols": sum_on},
+          roofline={"bound": "hbm", "kernel": "k_rav_apply<3,ELEMENT,*,double> (64^3 level, 8 buckets)",
+                    "achieved": apply_bytes / (1e-3 * f["ms_apply"]) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": apply_bytes / (1e-3 * f["ms_apply"]) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                    "algorithmic_bytes": apply_bytes},
+          roofline_residual={"bound": "hbm", "achieved": resid_bytes / (1e-3 * f["ms_residual"]) / 1e9,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "algorithmic_bytes": resid_bytes},
+          precisions=res)
+
+
+def bench_1024(args):
+    """2D 1024^2 with inclusions at contrast 1e4: the finest-level RAV sweep rate
+    (FP64 and BF16 rows), plus the outcome of the solvers on this problem: plain
+    RAV V(2,2) cycles and FGMRES(30) right-preconditioned by one V-cycle both fail
+    to converge at this contrast (the coarse-grid correction amplifies the
+    residual; see the findings in the design notes), which is recorded rather
+    than hidden."""
+    import torch
+    from paper_2103_10127_amd import Hierarchy
+    cfg = ri.CONFIGS["2d-1024"]
+    N, nl = cfg["n_cells"], cfg["n_levels"]
+    incl = ri.inclusions(cfg["seed"])
+    reps = max(args.steps, 5)
+    res = {}
+    gm = vc = None
+    for prec in ("fp64", "bf16"):
+        t0 = time.perf_counter()
+        H = Hierarchy(dim=2, n_cells=N, n_levels=nl, dmask=cfg["dmask"], omega=0.66, eta_out=cfg["eta_out"],
+                      eta_in=cfg["contrast"], inclusions=incl, precision=prec)
+        H.factor()
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        n_fine, n_free = H.dofs(nl - 1)
+        b = torch.zeros(n_fine, dtype=torch.float64, device="cuda")
+        H.assemble_rhs(ri.mms_params(2, cfg["seed"]), b)
+        x = torch.zeros_like(b)
+        H.time_sweep(nl - 1, max(args.warmup, 1), x, b)
+        ms_res, ms_apply = H.time_sweep(nl - 1, reps, x, b)
+        res[prec] = dict(ms_residual=ms_res, ms_apply=ms_apply, setup_s=round(setup, 3))
+        if prec == "fp64":
+            x.zero_()
+            st, it, rel = H.solve(x, b, 1e-8, 30)
+            vc = {"status": st, "cycles": it, "rel_residual": rel}
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, it, rel = H.solve_gmres(x, b, 1e-8, 150, 30)
+            torch.cuda.synchronize()
+            gm = {"status": st, "iterations": it, "rel_residual": rel, "ms": 1e3 * (time.perf_counter() - t0)}
+        H.close()
+    esz = {"fp64": 8, "bf16": 2}
+    sum_on = sum_owned_times_patch(N)
+    for prec, r in res.items():
+        r["apply_GBs"] = (esz[prec] * sum_on + 8 * n_fine + 16 * n_free) / (1e-3 * r["ms_apply"]) / 1e9
+    f = res["fp64"]
+    apply_bytes = 8 * sum_on + 8 * n_fine + 16 * n_free
+    sweep_ms = f["ms_residual"] + f["ms_apply"]
+    _line("RAV smoothed DoFs/s (finest-level sweep: residual + apply)", n_fine / (1e-3 * sweep_ms), "DoF/s",
+          reps, max(args.warmup, 1), sweep_ms, "f64",
+          {"workload": "2D Taylor-Hood Q2/Q1 1024x1024, 8 levels, inclusions at viscosity contrast 1e4, "
+                       "one finest-level RAV sweep (omega 0.66)",
+           "dofs": n_fine, "levels": nl, "inclusions": len(incl)},
+          roofline={"bound": "hbm", "kernel": "k_rav_apply<2,VERTEX,0,double> (1024x1024 level)",
+                    "achieved": apply_bytes / (1e-3 * f["ms_apply"]) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": apply_bytes / (1e-3 * f["ms_apply"]) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                    "algorithmic_bytes": apply_bytes},
+          precisions=res, vcycle_solve=vc, gmres_solve=gm)
+
+
+def bench_batch(args):
+    """256 independent 2D problems (fine grids 64/128/256, coarsest 16^2, 1-8
+    inclusions each at contrast 1e3) advanced together: one step = one batched
+    V(2,2) cycle of all problems (one launch per stage for the whole batch).
+    Plain V-cycles do not converge at this contrast, so the rate of cycles is
+    measured, not a time to 1e-8."""
+    import torch
+    from paper_2103_10127_amd.capi import Batch
+    cfg = ri.CONFIGS["batch256"]
+    sizes = ri.batch_sizes(cfg["n_problems"], cfg["seed"])
+    probs = [dict(dim=2, n_cells=int(n), n_levels=ri.levels_to(int(n), cfg["coarsest"]), dmask=cfg["dmask"],
+                  eta_out=cfg["eta_out"], eta_in=cfg["contrast"], inclusions=ri.inclusions(cfg["seed"] + i),
+                  omega=0.66) for i, n in enumerate(sizes)]
+    t0 = time.perf_counter()
+    B = Batch(probs)
+    B.factor()
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    xs, bs = [], []
+    for i, p in enumerate(probs):
+        n, _ = B.dofs(i)
+        bb = torch.zeros(n, dtype=torch.float64, device="cuda")
+        B.assemble_rhs(i, ri.mms_params(2, cfg["seed"] + i), bb)
+        bs.append(bb)
+        xs.append(torch.zeros_like(bb))
+    for _ in range(max(args.warmup, 1)):
+        B.vcycle(xs, bs)
+    for x in xs:
+        x.zero_()
+    steps = max(args.steps, 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.vcycle(xs, bs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    smoothed = 0
+    for p in probs:
+        for l in range(1, p["n_levels"]):
+            n_l = p["n_cells"] >> (p["n_levels"] - 1 - l)
+            smoothed += 2 * 2 * (2 * (2 * n_l + 1) ** 2 + (n_l + 1) ** 2)
+    total = sum(B.dofs(i)[0] for i in range(len(probs)))
+    B.close()
+    _line("RAV smoothed DoFs/s (batched V(2,2) cycles)", smoothed / dt, "DoF/s", steps, max(args.warmup, 1),
+          1e3 * dt, "f64",
+          {"workload": "256 independent 2D Q2/Q1 problems (fine 64/128/256, coarsest 16x16), 1-8 inclusions "
+                       "each at contrast 1e3, one batched RAV V(2,2) cycle per step",
+           "problems": len(probs), "dofs_total": total},
+          setup_s=round(setup, 3))
 
 
 if __name__ == "__main__":
