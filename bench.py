@@ -68,9 +68,13 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=20000, help="patches in the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch the plain copy kernel on 1 GiB (for HBM counter scaling)")
-    ap.add_argument("--workload", default="2d-512", choices=["2d-512", "3d-64", "2d-1024", "batch256"],
+    ap.add_argument("--workload", default="2d-512",
+                    choices=["2d-512", "3d-64", "2d-1024", "batch256", "learned"],
                     help="2d-512: the headline solve (default); 3d-64: finest-level element-patch sweep; "
-                         "2d-1024: inclusions at contrast 1e4, GMRES + V-cycle; batch256: 256 problems")
+                         "2d-1024: inclusions at contrast 1e4; batch256: 256 problems; learned: per-patch "
+                         "damping trained on small problems, evaluated on 512^2 problems with inclusions")
+    ap.add_argument("--train-steps", type=int, default=800)
+    ap.add_argument("--train-lr", type=float, default=3e-3)
     return ap.parse_args()
 
 
@@ -128,7 +132,8 @@ def main():
               "(the sharding design is described in DESIGN.md).", file=sys.stderr)
         sys.exit(2)
     if args.workload != "2d-512":
-        {"3d-64": bench_3d, "2d-1024": bench_1024, "batch256": bench_batch}[args.workload](args)
+        {"3d-64": bench_3d, "2d-1024": bench_1024, "batch256": bench_batch,
+         "learned": bench_learned}[args.workload](args)
         return
     import torch
     from paper_2103_10127_amd import Hierarchy
@@ -415,6 +420,70 @@ def bench_batch(args):
                        "each at contrast 1e3, one batched RAV V(2,2) cycle per step",
            "problems": len(probs), "dofs_total": total},
           setup_s=round(setup, 3))
+
+
+def bench_learned(args):
+    """Learned per-patch damping: the network is trained on two-level 32^2 and
+    64^2 problems with inclusions at contrast 10 (inclusion seeds 3000-3015),
+    then held-out 512^2 problems (7 levels, seeds 4000-4003, contrast 10) are
+    solved to 1e-8 with fixed omega (0.66 and 0.8) and with the learned
+    per-patch omega.  value = smoothed DoFs/s of the learned-omega solves."""
+    import torch
+    from paper_2103_10127_amd import Hierarchy
+    from paper_2103_10127_amd.capi import MLP
+    from paper_2103_10127_amd.learn import train
+    contrast = 10.0
+    train_probs = [dict(dim=2, n_cells=n, n_levels=2, dmask=ri.ALL_DIRICHLET_2D, eta_out=1.0, eta_in=contrast,
+                        inclusions=ri.inclusions(3000 + i), omega=0.66)
+                   for i, n in enumerate([32] * 10 + [64] * 6)]
+    t0 = time.perf_counter()
+    theta, losses = train(train_probs, steps=args.train_steps, lr=args.train_lr, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    net = MLP(theta)
+    N, nl = 512, 7
+    rows, tot = [], {"fixed 0.66": [0.0, 0], "fixed 0.8": [0.0, 0], "learned": [0.0, 0]}
+    for seed in range(4000, 4004):
+        H = Hierarchy(dim=2, n_cells=N, n_levels=nl, dmask=ri.ALL_DIRICHLET_2D, eta_out=1.0, eta_in=contrast,
+                      inclusions=ri.inclusions(seed), omega=0.66)
+        H.factor()
+        n_fine, _ = H.dofs(nl - 1)
+        level_n = [H.dofs(l)[0] for l in range(nl)]
+        per_cycle = sum(2 * 2 * level_n[l] for l in range(1, nl))
+        b = torch.zeros(n_fine, dtype=torch.float64, device="cuda")
+        H.assemble_rhs(ri.mms_params(2, seed), b)
+        x = torch.zeros_like(b)
+        row = {"seed": seed}
+        for label in ("fixed 0.66", "fixed 0.8", "learned"):
+            if label == "learned":
+                H.learn_set_omega(net)
+            else:
+                H.learn_set_omega(None)
+                H.set_params(0.66 if label == "fixed 0.66" else 0.8, 2, 2)
+            x.zero_()
+            H.solve(x, b, 1e-8, 200)
+            x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, it, rel = H.solve(x, b, 1e-8, 200)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            row[label] = {"status": st, "cycles": it, "ms": 1e3 * dt}
+            if st == 0:
+                tot[label][0] += dt
+                tot[label][1] += it * per_cycle
+        rows.append(row)
+        H.close()
+    net.close()
+    rate = {k: (v[1] / v[0] if v[0] > 0 else None) for k, v in tot.items()}
+    ms = 1e3 * tot["learned"][0] / len(rows)
+    _line("RAV smoothed DoFs/s (whole V(2,2) solve to a 1e-8 residual reduction, learned per-patch omega)",
+          rate["learned"], "DoF/s", len(rows), 1, ms, "f64",
+          {"workload": "2D Taylor-Hood Q2/Q1 512x512, 7 levels, 1-8 inclusions at contrast 10 (4 held-out "
+                       "problems), RAV V(2,2); network trained on 16 two-level 32^2/64^2 problems",
+           "train_steps": args.train_steps, "train_lr": args.train_lr},
+          train_s=round(train_s, 2), loss_first=float(np.mean(losses[:32])), loss_last=float(np.mean(losses[-32:])),
+          rate_by_omega=rate, problems=rows)
 
 
 if __name__ == "__main__":
