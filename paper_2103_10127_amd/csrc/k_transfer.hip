@@ -6,7 +6,9 @@
 // the Q1 pressure basis (1/2, 1, 1/2).  The d-dimensional weights are tensor
 // products.  Restriction is P^T.  Both are gathers (one thread per output
 // node, all components) so no atomics are needed; masked DoFs are skipped
-// (their residual and correction are zero).
+// (their residual and correction are zero).  Restriction starts the coarse
+// level from x_c = 0, so it also writes the coarse residual r_c = b_c and the
+// coarse level's first smoothing sweep needs no residual launch.
 #include <hip/hip_runtime.h>
 
 #include "rav_internal.h"
@@ -71,6 +73,7 @@ __device__ __forceinline__ void restrict_node(const GridDev& gd, long long row) 
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
     gd.bc[c * gc.nV + cb] = s[c];
+    gd.rc[c * gc.nV + cb] = s[c];
     gd.xc[c * gc.nV + cb] = 0.0;
   }
 }
@@ -105,6 +108,7 @@ __device__ __forceinline__ void restrict_pres(const GridDev& gd, long long row) 
   }
   const long long i = DIM * gc.nV + row;
   gd.bc[i] = s;
+  gd.rc[i] = s;
   gd.xc[i] = 0.0;
 }
 

@@ -173,28 +173,33 @@ static rav_status build_plans(rav_batch* B) {
   return RAV_OK;
 }
 
-static void smooth_depth(rav_batch* B, int d, int sweeps) {
+// r_valid: every level at this depth holds its current residual (levels
+// entered through restriction always do; top levels after a norm evaluation).
+static bool smooth_depth(rav_batch* B, int d, int sweeps, bool r_valid) {
   DepthPlan& P = B->depth[d];
   for (int s = 0; s < sweeps; ++s) {
-    launch_residual(B->dim, P.dG, P.res, P.n_res, nullptr, B->stream);
+    if (!r_valid) launch_residual(B->dim, P.dG, P.res, P.n_res, nullptr, B->stream);
     for (const ApplyLaunch& al : P.apply)
       launch_rav_apply(B->dim, B->kind, al.cls, B->prec, al.split, P.dG, al.tasks, al.ntasks, B->stream);
+    r_valid = false;
   }
+  return r_valid;
 }
 
-static void batch_vcycle(rav_batch* B) {
+// One batched V-cycle; top_valid: the top levels' residuals are current.
+static void batch_vcycle(rav_batch* B, bool top_valid) {
   const int dmax = (int)B->depth.size() - 1;
   for (int d = dmax; d >= 1; --d) {
     DepthPlan& P = B->depth[d];
-    smooth_depth(B, d, B->nu_pre);
-    launch_residual(B->dim, P.dG, P.res, P.n_res, nullptr, B->stream);
+    if (!smooth_depth(B, d, B->nu_pre, top_valid || P.top.empty()))
+      launch_residual(B->dim, P.dG, P.res, P.n_res, nullptr, B->stream);
     launch_restrict(B->dim, P.dG, P.rtask, P.n_rtask, B->stream);
   }
   launch_coarse_gemv_batch(B->depth[0].dG, B->depth[0].coarse, B->depth[0].n_coarse, B->stream);
   for (int d = 1; d <= dmax; ++d) {
     DepthPlan& P = B->depth[d];
     launch_prolong(B->dim, P.dG, P.ptask, P.n_ptask, B->stream);
-    smooth_depth(B, d, B->nu_post);
+    smooth_depth(B, d, B->nu_post, false);
   }
 }
 
@@ -332,7 +337,7 @@ rav_status rav_batch_vcycle(rav_batch* B, double* const* x, const double* const*
   if (st != RAV_OK) return st;
   if ((st = copy_user(B, xi.data(), x)) != RAV_OK) return st;
   if ((st = copy_user(B, bi.data(), b)) != RAV_OK) return st;
-  batch_vcycle(B);
+  batch_vcycle(B, false);
   std::vector<const double*> xs(xi.begin(), xi.end());
   if ((st = copy_user(B, const_cast<double* const*>(x), xs.data())) != RAV_OK) return st;
   BCK(hipStreamSynchronize(B->stream));
@@ -366,7 +371,7 @@ rav_status rav_batch_solve(rav_batch* B, double* const* x, const double* const* 
   int k = 0;
   while (k < maxit && std::count(act.begin(), act.end(), 1) > 0) {
     if ((st = set_active(B, act)) != RAV_OK) return st;
-    batch_vcycle(B);
+    batch_vcycle(B, true);   // top residuals are current from the norm evaluation
     std::vector<double> nk;
     if ((st = batch_norms(B, nk)) != RAV_OK) return st;
     ++k;

@@ -373,35 +373,43 @@ static void mv_sweep(rav_ctx* ctx, int l) {
   }
 }
 
-static void smooth_level(rav_ctx* ctx, int l, int sweeps) {
+// `r_valid`: the level's r already holds b - L x for the current x (after a
+// norm evaluation, or after restriction onto the level); the first sweep then
+// skips its residual launch.  Returns whether r is still current afterwards.
+static bool smooth_level(rav_ctx* ctx, int l, int sweeps, bool r_valid) {
   for (int s = 0; s < sweeps; ++s) {
     if (ctx->desc.smoother == RAV_SMOOTHER_MV) {
       mv_sweep(ctx, l);
     } else {
-      const bool timed = prof_mark(ctx, l, ctx->prof_res, ctx->prof_nres, true);
-      rav_residual_level(ctx, l, false);
-      if (timed) prof_mark(ctx, l, ctx->prof_res, ctx->prof_nres, false);
+      if (!r_valid) {
+        const bool timed = prof_mark(ctx, l, ctx->prof_res, ctx->prof_nres, true);
+        rav_residual_level(ctx, l, false);
+        if (timed) prof_mark(ctx, l, ctx->prof_res, ctx->prof_nres, false);
+      }
       rav_apply_level(ctx, l);
     }
+    r_valid = false;
   }
+  return r_valid;
 }
 
 static void coarse_solve_level(rav_ctx* ctx) {
   launch_coarse_gemv_batch(ctx->lv[0].dd, ctx->coarse_tasks, ctx->n_coarse_tasks, ctx->stream);
 }
 
-static void vcycle_level(rav_ctx* ctx, int l) {
+// One V-cycle on level l; r_valid as for smooth_level (levels below the top
+// are entered through restriction, which leaves their residual current).
+static void vcycle_level(rav_ctx* ctx, int l, bool r_valid) {
   if (l == 0) { coarse_solve_level(ctx); return; }
   LevelHost& L = ctx->lv[l];
-  smooth_level(ctx, l, ctx->desc.nu_pre);
-  rav_residual_level(ctx, l, false);
+  if (!smooth_level(ctx, l, ctx->desc.nu_pre, r_valid)) rav_residual_level(ctx, l, false);
   launch_restrict(ctx->desc.dim, L.dd, L.rtasks, L.n_rtasks, ctx->stream);
-  vcycle_level(ctx, l - 1);
+  vcycle_level(ctx, l - 1, true);
   launch_prolong(ctx->desc.dim, L.dd, L.ptasks, L.n_ptasks, ctx->stream);
-  smooth_level(ctx, l, ctx->desc.nu_post);
+  smooth_level(ctx, l, ctx->desc.nu_post, false);
 }
 
-void rav_vcycle_finest(rav_ctx* ctx) { vcycle_level(ctx, (int)ctx->lv.size() - 1); }
+void rav_vcycle_finest(rav_ctx* ctx) { vcycle_level(ctx, (int)ctx->lv.size() - 1, false); }
 
 rav_status rav_read_norm(rav_ctx* ctx, double* out) {
   CK(hipMemcpyAsync(ctx->h_norm, ctx->d_norm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -486,6 +494,7 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
     L.hd.gc = ctx->lv[l - 1].hd.g;
     L.hd.xc = ctx->lv[l - 1].hd.x;
     L.hd.bc = ctx->lv[l - 1].hd.b;
+    L.hd.rc = ctx->lv[l - 1].hd.r;
     rav_status st = rav_upload_desc(ctx, L);
     if (st != RAV_OK) return fail(st);
   }
@@ -612,7 +621,7 @@ rav_status rav_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const doub
   const long long n = L.hd.g.n;
   launch_copy(L.hd.x, x, n, ctx->stream);
   launch_copy(L.hd.b, b, n, ctx->stream);
-  smooth_level(ctx, level, sweeps);
+  smooth_level(ctx, level, sweeps, false);
   launch_copy(x, L.hd.x, n, ctx->stream);
   CK(hipGetLastError());
   return RAV_OK;
@@ -654,7 +663,7 @@ rav_status rav_vcycle(rav_ctx* ctx, double* x, const double* b) {
   const long long n = L.hd.g.n;
   launch_copy(L.hd.x, x, n, ctx->stream);
   launch_copy(L.hd.b, b, n, ctx->stream);
-  vcycle_level(ctx, lf);
+  vcycle_level(ctx, lf, false);
   launch_copy(x, L.hd.x, n, ctx->stream);
   CK(hipGetLastError());
   return RAV_OK;
@@ -683,7 +692,7 @@ rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int 
   ctx->fell_back = 0;
   while (result == RAV_NOT_CONVERGED && k < maxit) {
     const double rprev = rk;
-    vcycle_level(ctx, lf);
+    vcycle_level(ctx, lf, true);   // r of the finest level is current from the norm evaluation
     rav_residual_level(ctx, lf, true);
     st = rav_read_norm(ctx, &rk);
     if (st != RAV_OK) return st;

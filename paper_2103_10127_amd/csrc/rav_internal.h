@@ -63,6 +63,7 @@ struct GridDev {
   Geo gc;
   double* xc;
   double* bc;
+  double* rc;            // coarser level's residual: restriction also writes it (x_c = 0, so r_c = b_c)
   // smoother data
   int nbk;
   Bucket bk[MAX_BUCKETS];
