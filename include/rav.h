@@ -91,7 +91,10 @@ typedef struct rav_ctx rav_ctx;
  * grids", Sec. 4) in FP64, and the coarse direct solver (Sec. 2: LU to machine
  * accuracy).  With Dirichlet velocity on every side the coarse solve uses the
  * bordered system [[L_0, e],[e^T, 0]], e = (0, 1_p), i.e. zero-mean pressure.
- * hip_stream: a hipStream_t or NULL.  On success *out owns all device memory. */
+ * hip_stream: a hipStream_t or NULL.  On success *out owns all device memory.
+ * RAV_EINVAL (before any device work) also when the coarsest grid has more than
+ * 16383 DoFs: its dense inverse would exceed 2 GB (2D up to 32x32, 3D up to
+ * 8x8x8 cells on the coarsest level). */
 rav_status rav_create(const rav_problem_desc* desc, void* hip_stream, rav_ctx** out);
 
 /* Factors every local system L_i = R_i L R_i^T (Sec. 3) on every smoothed

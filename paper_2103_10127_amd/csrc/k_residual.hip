@@ -447,6 +447,310 @@ __global__ __launch_bounds__(BLOCK) void k_residual3(const GridDev* __restrict__
   residual_block<3>(G, tasks, partials);
 }
 
+// ---- 2D residual staged through LDS ------------------------------------------
+// Large 2D levels: one block per tile of RT_X x RT_Y cells.  The block first
+// loads the tile's velocity nodes, pressure vertices and cell coefficients with
+// a two-node halo into LDS (row-contiguous, coalesced loads), then evaluates
+// the rows of the nodes the tile owns, one node parity type per round so that
+// a wavefront shares one compile-time stencil, reading every column value
+// from LDS.  A tile owns velocity nodes a_d in [2 x0_d, 2 x0_d + 2 RT_d) and
+// pressure vertices k_d in [x0_d, x0_d + RT_d), plus the last node layer
+// (a_d = 2N, k_d = N) in the last tile of each direction.  The row formulas
+// are those of res_node / res_pres.
+constexpr int RT_X = 32, RT_Y = 8;
+constexpr int RW_X = 2 * RT_X + 5, RW_Y = 2 * RT_Y + 5;   // velocity window (node a = 2 x0 - 2 + index)
+constexpr int RP_X = RT_X + 3, RP_Y = RT_Y + 3;           // pressure window (vertex k = x0 - 1 + index)
+constexpr int RC_X = RT_X + 2, RC_Y = RT_Y + 2;           // cell window (cell E = x0 - 1 + index)
+
+struct TileLds {
+  double xs[2][RW_Y][RW_X];
+  double ps[RP_Y][RP_X];
+  double cs[RC_Y][RC_X];
+};
+
+template <int TY>
+__device__ __forceinline__ double res_node_lds(const GridDev& gd, const TileLds& S, int x0, int y0, int a0, int a1) {
+  constexpr int NV = 9, NP = 4;
+  constexpr int NE0 = (TY & 1) ? 1 : 2, NE1 = ((TY >> 1) & 1) ? 1 : 2, NE = NE0 * NE1;
+  constexpr int W0 = (TY & 1) ? 1 : 2, W1 = ((TY >> 1) & 1) ? 1 : 2;
+  constexpr int M0 = 3 - (TY & 1), M1 = 3 - ((TY >> 1) & 1);
+  const Geo& g = gd.g;
+  const Tabs<2>& T = tabs<2>();
+  const int a[3] = {a0, a1, 0};
+  const long long nn = g.nn, nV = g.nV;
+  const long long base = a0 + nn * a1;
+  gdouble* __restrict__ R = gview(gd.r);
+  if (node_dirichlet(g, a)) {
+    R[base] = 0.0;
+    R[nV + base] = 0.0;
+    return 0.0;
+  }
+  const int N = g.N;
+  double cef[NE];
+  bool okc[NE];
+  long long cut_row[NE];
+  bool anycut = false;
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int eo[2] = {i % NE0, i / NE0};
+    int E[2], la = 0;
+    bool ok = true;
+#pragma unroll
+    for (int d = 0, st = 1; d < 2; ++d, st *= 3) {
+      const bool odd = (TY >> d) & 1;
+      E[d] = odd ? (a[d] - 1) >> 1 : (a[d] >> 1) - 1 + eo[d];
+      la += (odd ? 1 : 2 - 2 * eo[d]) * st;
+      ok = ok && E[d] >= 0 && E[d] < N;
+    }
+    const double ce = S.cs[E[1] - (y0 - 1)][E[0] - (x0 - 1)];
+    okc[i] = ok;
+    cef[i] = ok && ce >= 0.0 ? ce : 0.0;
+    const bool cut = ok && ce < 0.0;
+    cut_row[i] = cut ? ((long long)(-ce) - 1) * (NV * NV) + la * NV : -1;
+    anycut = anycut || cut;
+  }
+  bool fv[2][5];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) fv[d][o + 2] = free_coord(g, d, a[d] + o);
+  }
+  const int lx = a0 - (2 * x0 - 2), ly = a1 - (2 * y0 - 2);
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int oy = -W1; oy <= W1; ++oy) {
+#pragma unroll
+    for (int ox = -W0; ox <= W0; ++ox) {
+      const int o[2] = {ox, oy};
+      double coef = 0.0;
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int eo[2] = {i % NE0, i / NE0};
+        int la = 0, lb = 0;
+        bool in = true;
+#pragma unroll
+        for (int d = 0, st = 1; d < 2; ++d, st *= 3) {
+          const int l = ((TY >> d) & 1) ? 1 : 2 - 2 * eo[d];
+          la += l * st;
+          lb += (l + o[d]) * st;
+          in = in && l + o[d] >= 0 && l + o[d] <= 2;
+        }
+        if (in) coef += cef[i] * T.A[la * NV + lb];
+      }
+      coef = fv[0][ox + 2] && fv[1][oy + 2] ? coef : 0.0;
+      acc[0] += coef * S.xs[0][ly + oy][lx + ox];
+      acc[1] += coef * S.xs[1][ly + oy][lx + ox];
+    }
+  }
+  double accB[2] = {0.0, 0.0};
+  const int lo[2] = {(a0 >> 1) - 1 + (TY & 1), (a1 >> 1) - 1 + ((TY >> 1) & 1)};
+#pragma unroll
+  for (int jy = 0; jy < M1; ++jy) {
+#pragma unroll
+    for (int jx = 0; jx < M0; ++jx) {
+      const int j[2] = {jx, jy};
+      const int k0 = lo[0] + jx, k1 = lo[1] + jy;
+      const bool in_grid = k0 >= 0 && k0 <= N && k1 >= 0 && k1 <= N;
+      const double pv = S.ps[k1 - (y0 - 1)][k0 - (x0 - 1)];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double coef = 0.0;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+          const int eo[2] = {i % NE0, i / NE0};
+          int la = 0, lk = 0;
+          bool in = true;
+#pragma unroll
+          for (int d = 0, st = 1; d < 2; ++d, st *= 3) {
+            const bool odd = (TY >> d) & 1;
+            la += (odd ? 1 : 2 - 2 * eo[d]) * st;
+            const int kl = j[d] - (odd ? 0 : eo[d]);
+            in = in && kl >= 0 && kl <= 1;
+            lk |= (kl & 1) << d;
+          }
+          if (in) coef += okc[i] ? T.B[(c * NV + la) * NP + lk] : 0.0;
+        }
+        accB[c] += (in_grid ? coef : 0.0) * pv;
+      }
+    }
+  }
+  if (anycut) {
+    gcdouble* __restrict__ X = gview(gd.x);
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      if (cut_row[i] < 0) continue;
+      const int eo[2] = {i % NE0, i / NE0};
+      int E2[2];
+#pragma unroll
+      for (int d = 0; d < 2; ++d) E2[d] = ((TY >> d) & 1) ? a[d] - 1 : a[d] - 2 + 2 * eo[d];
+      gcdouble* __restrict__ Ae = gview(gd.cutA) + cut_row[i];
+#pragma unroll
+      for (int lb = 0; lb < NV; ++lb) {
+        const int b0 = E2[0] + lb % 3, b1 = E2[1] + lb / 3;
+        const bool fr = !coord_dirichlet(g, 0, b0) && !coord_dirichlet(g, 1, b1);
+        const double w = Ae[lb];
+        const long long lin = b0 + nn * b1;
+        acc[0] += w * (fr ? X[lin] : 0.0);
+        acc[1] += w * (fr ? X[nV + lin] : 0.0);
+      }
+    }
+  }
+  const double hB = gd.h;
+  gcdouble* __restrict__ Bv = gview(gd.b);
+  double sq = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const long long gi = c * nV + base;
+    const double r = Bv[gi] - (acc[c] + hB * accB[c]);
+    R[gi] = r;
+    sq += r * r;
+  }
+  return sq;
+}
+
+__device__ __forceinline__ double res_pres_lds(const GridDev& gd, const TileLds& S, int x0, int y0, int k0, int k1) {
+  constexpr int NV = 9, NP = 4;
+  const Geo& g = gd.g;
+  const Tabs<2>& T = tabs<2>();
+  const int N = g.N;
+  const int k[2] = {k0, k1};
+  bool okc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int E = k[d] - 1 + ((i >> d) & 1);
+      ok = ok && E >= 0 && E < N;
+    }
+    okc[i] = ok;
+  }
+  bool fv[2][5];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) fv[d][o + 2] = free_coord(g, d, 2 * k[d] + o);
+  }
+  const int lx = 2 * k0 - (2 * x0 - 2), ly = 2 * k1 - (2 * y0 - 2);
+  double acc = 0.0;
+#pragma unroll
+  for (int oy = -2; oy <= 2; ++oy) {
+#pragma unroll
+    for (int ox = -2; ox <= 2; ++ox) {
+      const int o[2] = {ox, oy};
+      const bool fr = fv[0][ox + 2] && fv[1][oy + 2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double coef = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          int lb = 0, lk = 0;
+          bool in = true;
+#pragma unroll
+          for (int d = 0, st = 1; d < 2; ++d, st *= 3) {
+            const int eo = (i >> d) & 1, l = o[d] + 2 - 2 * eo;
+            in = in && l >= 0 && l <= 2;
+            lb += l * st;
+            lk |= (1 - eo) << d;
+          }
+          if (in) coef += okc[i] ? T.B[(c * NV + lb) * NP + lk] : 0.0;
+        }
+        acc += (fr ? coef : 0.0) * S.xs[c][ly + oy][lx + ox];
+      }
+    }
+  }
+  const long long gi = 2 * g.nV + k0 + g.np1 * k1;
+  const double r = gview(gd.b)[gi] - gd.h * acc;
+  gview(gd.r)[gi] = r;
+  return r * r;
+}
+
+template <int TY>
+__device__ __forceinline__ double tile_round(const GridDev& gd, const TileLds& S, int x0, int y0, bool last_x,
+                                             bool last_y) {
+  const int cx = RT_X + ((last_x && !(TY & 1)) ? 1 : 0);
+  const int cy = RT_Y + ((last_y && !((TY >> 1) & 1)) ? 1 : 0);
+  double sq = 0.0;
+  for (int i = threadIdx.x; i < cx * cy; i += BLOCK) {
+    const int ix = i % cx, iy = i / cx;
+    sq += res_node_lds<TY>(gd, S, x0, y0, 2 * (x0 + ix) + (TY & 1), 2 * (y0 + iy) + ((TY >> 1) & 1));
+  }
+  return sq;
+}
+
+// Hardware block b works on tile (b mod 8) T/8 + b/8 of the row-major tile
+// order (T a multiple of 8), so each XCD sweeps one band of tile rows.
+__global__ __launch_bounds__(BLOCK) void k_residual_tiled2(const GridDev* __restrict__ G, double* __restrict__ partials) {
+  __shared__ TileLds S;
+  const GridDev& gd = *G;
+  const Geo& g = gd.g;
+  const int N = g.N;
+  const int ntx = N / RT_X, nty = N / RT_Y, T = ntx * nty;
+  const int b = blockIdx.x;
+  const int lt = (b % 8) * (T / 8) + b / 8;
+  const int tx = lt % ntx, ty = lt / ntx;
+  const int x0 = tx * RT_X, y0 = ty * RT_Y;
+  const bool last_x = tx == ntx - 1, last_y = ty == nty - 1;
+  {
+    gcdouble* __restrict__ X = gview(gd.x);
+    const unsigned nn = (unsigned)g.nn, nV = (unsigned)g.nV, np1 = (unsigned)g.np1;
+    const int twoN = 2 * N;
+#pragma unroll
+    for (int i = threadIdx.x; i < 2 * RW_Y * RW_X; i += BLOCK) {
+      const int c = i / (RW_Y * RW_X), rem = i - c * (RW_Y * RW_X);
+      const int yy = rem / RW_X, xx = rem - yy * RW_X;
+      const unsigned gx = (unsigned)min(max(2 * x0 - 2 + xx, 0), twoN);
+      const unsigned gy = (unsigned)min(max(2 * y0 - 2 + yy, 0), twoN);
+      S.xs[c][yy][xx] = ld(X, (unsigned)c * nV + gx + nn * gy);
+    }
+#pragma unroll
+    for (int i = threadIdx.x; i < RP_Y * RP_X; i += BLOCK) {
+      const int yy = i / RP_X, xx = i - yy * RP_X;
+      const unsigned gx = (unsigned)min(max(x0 - 1 + xx, 0), N), gy = (unsigned)min(max(y0 - 1 + yy, 0), N);
+      S.ps[yy][xx] = ld(X, 2u * nV + gx + np1 * gy);
+    }
+#pragma unroll
+    for (int i = threadIdx.x; i < RC_Y * RC_X; i += BLOCK) {
+      const int yy = i / RC_X, xx = i - yy * RC_X;
+      const unsigned gx = (unsigned)min(max(x0 - 1 + xx, 0), N - 1), gy = (unsigned)min(max(y0 - 1 + yy, 0), N - 1);
+      S.cs[yy][xx] = ld(gview(gd.ceta), gx + (unsigned)N * gy);
+    }
+  }
+  __syncthreads();
+  double sq = tile_round<0>(gd, S, x0, y0, last_x, last_y);
+  sq += tile_round<1>(gd, S, x0, y0, last_x, last_y);
+  sq += tile_round<2>(gd, S, x0, y0, last_x, last_y);
+  sq += tile_round<3>(gd, S, x0, y0, last_x, last_y);
+  {
+    const int cx = RT_X + (last_x ? 1 : 0), cy = RT_Y + (last_y ? 1 : 0);
+    for (int i = threadIdx.x; i < cx * cy; i += BLOCK) {
+      const int ix = i % cx, iy = i / cx;
+      sq += res_pres_lds(gd, S, x0, y0, x0 + ix, y0 + iy);
+    }
+  }
+  if (partials == nullptr) return;
+  __shared__ double red[BLOCK / 64];
+  sq = wave_sum(sq);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s2 = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w) s2 += red[w];
+    partials[lt] = s2;
+  }
+}
+
+// Tiles hold 1280 rows each: below 1024 tiles (N < 512) too few blocks run to
+// hide the serial rounds, and the node-type kernel is faster.
+bool residual_tiled_ok(int dim, int N) {
+  return dim == 2 && N >= 512 && N % RT_X == 0 && N % RT_Y == 0 && ((N / RT_X) * (N / RT_Y)) % 8 == 0;
+}
+int residual_tiles(int N) { return (N / RT_X) * (N / RT_Y); }
+
+void launch_residual_tiled(const GridDev* G, int N, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_tiled2, dim3(residual_tiles(N)), dim3(BLOCK), 0, s, G, partials);
+}
+
 void launch_residual(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, double* partials,
                      hipStream_t s) {
   if (dim == 2) hipLaunchKernelGGL(k_residual2, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, partials);

@@ -208,7 +208,8 @@ static rav_status build_level(rav_ctx* ctx, int l) {
     st = rav_upload_tasks(ctx, pt, &L.ptasks, &L.n_ptasks);
     if (st != RAV_OK) return st;
   }
-  CK(hipMalloc((void**)&L.partials, sizeof(double) * std::max(L.n_res_tiles, 1)));
+  const int n_part = std::max(L.n_res_tiles, residual_tiled_ok(D.dim, N) ? residual_tiles(N) : 1);
+  CK(hipMalloc((void**)&L.partials, sizeof(double) * n_part));
   // patch buckets (smoothed levels only)
   if (l > 0) {
     const int nbk = n_buckets(D.dim, D.patch);
@@ -296,6 +297,9 @@ static rav_status build_coarse(rav_ctx* ctx) {
   ctx->bordered = all_dir ? 1 : 0;
   ctx->nb = g.n + ctx->bordered;
   const long long nb = ctx->nb;
+  if (nb > MAX_COARSE)
+    return set_err(ctx, RAV_EINVAL, "the coarsest grid has " + std::to_string(nb) + " unknowns; its dense direct "
+                   "solve is limited to " + std::to_string(MAX_COARSE) + " (use more levels)");
   CK(hipMalloc((void**)&ctx->Minv, sizeof(double) * nb * nb));
   CK(hipMalloc((void**)&ctx->d_piv, sizeof(int) * nb));
   CK(hipMalloc((void**)&ctx->d_colk, sizeof(double) * nb));
@@ -323,6 +327,12 @@ static rav_status build_coarse(rav_ctx* ctx) {
 // ---- device sequences -------------------------------------------------------
 void rav_residual_level(rav_ctx* ctx, int l, bool with_norm) {
   LevelHost& L = ctx->lv[l];
+  const int N = L.hd.g.N;
+  if (residual_tiled_ok(ctx->desc.dim, N)) {
+    launch_residual_tiled(L.dd, N, with_norm ? L.partials : nullptr, ctx->stream);
+    if (with_norm) launch_norm_finalize(L.partials, 0, residual_tiles(N), ctx->d_norm, ctx->stream);
+    return;
+  }
   launch_residual(ctx->desc.dim, L.dd, L.res_tasks, L.n_res_tasks, with_norm ? L.partials : nullptr, ctx->stream);
   if (with_norm) launch_norm_finalize(L.partials, 0, L.n_res_tiles, ctx->d_norm, ctx->stream);
 }
@@ -440,6 +450,15 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
   if (d->n_levels < 2) return set_err(nullptr, RAV_EINVAL, "n_levels must be >= 2");
   if (d->n_levels > 20 || d->n_cells <= 0 || d->n_cells % (1 << (d->n_levels - 1)))
     return set_err(nullptr, RAV_EINVAL, "n_cells must be divisible by 2^(n_levels-1)");
+  {
+    const long long n0 = d->n_cells >> (d->n_levels - 1);
+    long long nv = 1, np = 1;
+    for (int k = 0; k < d->dim; ++k) { nv *= 2 * n0 + 1; np *= n0 + 1; }
+    if (d->dim * nv + np + 1 > MAX_COARSE)
+      return set_err(nullptr, RAV_EINVAL, "coarsest grid too large for the dense direct solve (" +
+                     std::to_string(d->dim * nv + np) + " DoFs, limit " + std::to_string(MAX_COARSE) +
+                     "): use more levels");
+  }
   if (!(d->omega > 0.0) || d->nu_pre < 0 || d->nu_post < 0)
     return set_err(nullptr, RAV_EINVAL, "omega must be > 0 and smoothing steps >= 0");
   if (!(d->eta_out > 0.0) || !(d->eta_in > 0.0)) return set_err(nullptr, RAV_EINVAL, "viscosities must be > 0");

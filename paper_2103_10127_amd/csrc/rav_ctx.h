@@ -24,6 +24,10 @@ struct ApplyLaunch {
 // APPLY_SPLIT_SMALL lanes per patch: with few wavefronts in flight, splitting a
 // patch over more lanes shortens the dependent load chain of each lane.
 constexpr long long SPLIT_BELOW = 120000;
+
+// Largest coarsest-level system (unknowns incl. the pressure border) solved by
+// the dense direct solver: 2 GB of FP64 inverse (2D 32x32 and 3D 8x8x8 fit).
+constexpr long long MAX_COARSE = 16384;
 inline int apply_split(long long count, long long split_below) {
   return count < split_below / 60 ? APPLY_SPLIT_SMALL : count < split_below ? APPLY_SPLIT : 1;
 }

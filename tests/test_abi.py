@@ -26,10 +26,13 @@ def test_library_exports_every_header_symbol():
     ("dim", 4, -1), ("n_levels", 1, -1), ("n_cells", 30, -1), ("omega", 0.0, -1),
     ("nu_pre", -1, -1), ("eta_out", -1.0, -1), ("bc_dirichlet_mask", 0x100, -1),
     ("n_incl", 70, -1), ("smoother", 7, -1), ("inv_precision", 5, -1),
+    ("n_levels", 2, -1),   # with n_cells = 512 (set below): a 256x256 coarsest grid is too large
 ])
 def test_invalid_descriptor_rejected_without_device(field, value, status):
     d = capi.make_desc(dim=2, n_cells=32, n_levels=3)
     setattr(d, field, value)
+    if (field, value) == ("n_levels", 2):
+        d.n_cells = 512
     h = ctypes.c_void_p()
     st = capi.lib().rav_create(ctypes.byref(d), None, ctypes.byref(h))
     assert st == status

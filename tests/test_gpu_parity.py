@@ -91,6 +91,28 @@ def test_rhs_matches_oracle(dim, N, nl, seed):
     gh.close()
 
 
+@pytest.mark.parametrize("dm", [ri.ALL_DIRICHLET_2D, ri.OUTFLOW_2D])
+def test_residual_large_2d_levels(dm):
+    """Level N = 512 takes the LDS-tiled residual, N = 128 and 256 the node-type
+    one: every row against the oracle, with inclusions at contrast 1e3 (cut
+    cells in interior and last tiles), an open side, and x nonzero on masked
+    nodes (masked columns must contribute nothing)."""
+    incl = ri.inclusions(1234)
+    print(f"[gpu] tiled residual dm={dm}", flush=True)
+    gh = Hierarchy(dim=2, n_cells=512, n_levels=7, dmask=dm, eta_in=1e3, inclusions=incl)
+    for level in (4, 5, 6):
+        lv = mg.Level(2, 512 >> (6 - level), dm, pt.VERTEX, 1.0, 1e3, incl, smooth=False)
+        g = lv.grid
+        x = ri.random_vector(g.n, 40 + level)
+        b = ri.random_vector(g.n, 50 + level) * g.free
+        ro = sm.residual(lv.L, x, b, g.free)
+        rd = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+        nrm = gh.residual(level, dev(x), dev(b), rd, norm=True)
+        assert rel(host(rd), ro) <= 1e-13, level
+        assert abs(nrm - np.linalg.norm(ro)) <= 1e-12 * np.linalg.norm(ro), level
+    gh.close()
+
+
 @pytest.mark.parametrize("case", SMALL + ["2d-vertex-40"])
 def test_residual_and_norm(case):
     c = CASES[case]
