@@ -88,3 +88,40 @@ def test_batch_rejects_mismatched_coarsest():
     probs[1]["n_levels"] = 2   # coarsest 16 instead of 8
     with pytest.raises(RavError):
         Batch(probs)
+
+
+def test_full_batch_vcycle_sampled_against_oracle():
+    """The 256-problem batch workload as bench.py builds it (fine grids
+    64/128/256, coarsest 16x16, 1-8 inclusions each at contrast 1e3): one
+    batched V(2,2) cycle from x = 0, and for sampled 64x64 and 128x128
+    problems the right-hand side and the iterate against the oracle's V-cycle."""
+    cfg = ri.CONFIGS["batch256"]
+    sizes = ri.batch_sizes(cfg["n_problems"], cfg["seed"])
+    probs = [dict(dim=2, n_cells=int(n), n_levels=ri.levels_to(int(n), cfg["coarsest"]), dmask=cfg["dmask"],
+                  eta_out=cfg["eta_out"], eta_in=cfg["contrast"], inclusions=ri.inclusions(cfg["seed"] + i),
+                  omega=0.66) for i, n in enumerate(sizes)]
+    print("[gpu] 256-problem batch create", flush=True)
+    B = Batch(probs)
+    B.factor()
+    xs, bs = [], []
+    for i, p in enumerate(probs):
+        n, _ = B.dofs(i)
+        b = torch.zeros(n, dtype=torch.float64, device="cuda")
+        B.assemble_rhs(i, ri.mms_params(2, cfg["seed"] + i), b)
+        bs.append(b)
+        xs.append(torch.zeros_like(b))
+    B.vcycle(xs, bs)
+    torch.cuda.synchronize()
+    picks = [int(np.nonzero(sizes == 64)[0][0]), int(np.nonzero(sizes == 64)[0][-1]),
+             int(np.nonzero(sizes == 128)[0][0])]
+    for i in picks:
+        p = probs[i]
+        print(f"[gpu] oracle problem {i} N={p['n_cells']}", flush=True)
+        H = mg.Hierarchy(2, p["n_cells"], p["n_levels"], p["dmask"], 0, 1.0, p["eta_in"], p["inclusions"])
+        g = H.finest.grid
+        bo = A.assemble_rhs(g, ri.mms_params(2, cfg["seed"] + i))
+        assert np.abs(bs[i].cpu().numpy() - bo).max() <= 1e-12 * np.abs(bo).max(), i
+        xo = H.vcycle(np.zeros(g.n), bo, "rav", 0.66, 2)
+        xg = xs[i].cpu().numpy()
+        assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo), i
+    B.close()
