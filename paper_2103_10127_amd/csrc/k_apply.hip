@@ -253,6 +253,77 @@ __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply(const GridDev* __
   }
 }
 
+// Row-parallel RAV apply for tiny buckets: one wavefront per patch, lane j
+// accumulates owned rows j and j + 64 over the patch columns.  The column loop
+// is wave-uniform (the r value of a column is one broadcast load), so the
+// per-lane state is two accumulators however many rows the bucket owns.
+template <typename WT> __device__ __forceinline__ double w_elem(const WT* W, long long i);
+template <> __device__ __forceinline__ double w_elem<double>(const double* W, long long i) {
+  return ((gcdouble*)W)[i];
+}
+template <> __device__ __forceinline__ double w_elem<float>(const float* W, long long i) {
+  return (double)((__attribute__((address_space(1))) const float*)W)[i];
+}
+template <> __device__ __forceinline__ double w_elem<bf16_t>(const bf16_t* W, long long i) {
+  const unsigned short u = ((__attribute__((address_space(1))) const unsigned short*)W)[i];
+  return (double)__uint_as_float((unsigned)u << 16);
+}
+
+template <int DIM, int KIND, typename WT>
+__global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_rows(const GridDev* __restrict__ G,
+                                                                   const BlockTask* __restrict__ tasks) {
+  constexpr int NPAD = patch_npad(DIM, KIND);
+  constexpr int V = WTraits<WT>::V;
+  const BlockTask t = tasks[blockIdx.x];
+  if (t.grid < 0) return;
+  const GridDev& gd = G[t.grid];
+  if (grid_idle(gd)) return;
+  const Bucket& bk = gd.bk[t.part];
+  const long long p = t.start + (threadIdx.x >> 6);
+  if (p >= bk.count) return;   // whole wavefronts leave together
+  const int j = threadIdx.x & 63;
+  const Geo& g = gd.g;
+  int k[3] = {0, 0, 0};
+  bucket_anchor(g, KIND, bk.cls, p, k);
+  const ColMap cm{(unsigned)g.nn, (unsigned)g.nV, (unsigned)g.np1, 2u * (unsigned)g.N, g.dmask};
+  gcdouble* __restrict__ r = (gcdouble*)gd.r;
+  const WT* __restrict__ W = reinterpret_cast<const WT*>(bk.W);
+  const int nown = bk.nown;
+  const long long cp = bk.count_pad;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll 16
+  for (int c = 0; c < NPAD; ++c) {
+    const double rv = ldr(r, col_index<DIM, KIND>(cm, k, c));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      // unconditional load at a clamped row (no branch, so the unrolled loads stay in flight)
+      const int jj = j + 64 * h;
+      const long long e = (long long)c * nown + min(jj, nown - 1);
+      const double w = w_elem<WT>(W, ((e / V) * cp + p) * V + e % V);
+      acc[h] += jj < nown ? w * rv : 0.0;
+    }
+  }
+  const double om = gd.omega_patch ? (double)gd.omega_patch[patch_lin(g, KIND, k)] : gd.omega;
+  gdouble* __restrict__ x = (gdouble*)gd.x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int jj = j + 64 * h;
+    if (jj >= nown) continue;
+    const long long gi = own_index<DIM, KIND>(cm, k, bucket_own_local(DIM, KIND, bk.cls, jj));
+    if (gi >= 0) x[gi] += om * acc[h];
+  }
+}
+
+template <int DIM, int KIND>
+static void launch_apply_rows(int prec, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
+  if (prec == P_FP64)
+    hipLaunchKernelGGL((k_rav_apply_rows<DIM, KIND, double>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks);
+  else if (prec == P_FP32)
+    hipLaunchKernelGGL((k_rav_apply_rows<DIM, KIND, float>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks);
+  else
+    hipLaunchKernelGGL((k_rav_apply_rows<DIM, KIND, bf16_t>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks);
+}
+
 template <int DIM, int KIND, typename WT, int SPLIT>
 static void launch_apply_t(int cls, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
 #define RAV_APPLY_CASE(C)                                                                                 \
@@ -302,6 +373,12 @@ static void launch_apply_s(int dim, int kind, int cls, int prec, const GridDev* 
 
 void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const GridDev* G, const BlockTask* tasks,
                       int ntasks, hipStream_t s) {
+  if (split == APPLY_ROWS) {
+    if (dim == 2 && kind == KIND_VERTEX) launch_apply_rows<2, KIND_VERTEX>(prec, G, tasks, ntasks, s);
+    else if (dim == 2) launch_apply_rows<2, KIND_ELEMENT>(prec, G, tasks, ntasks, s);
+    else launch_apply_rows<3, KIND_ELEMENT>(prec, G, tasks, ntasks, s);
+    return;
+  }
   if (split == APPLY_SPLIT_SMALL) launch_apply_s<APPLY_SPLIT_SMALL>(dim, kind, cls, prec, G, tasks, ntasks, s);
   else if (split > 1) launch_apply_s<APPLY_SPLIT>(dim, kind, cls, prec, G, tasks, ntasks, s);
   else launch_apply_s<1>(dim, kind, cls, prec, G, tasks, ntasks, s);

@@ -29,6 +29,7 @@ constexpr long long SPLIT_BELOW = 120000;
 // the dense direct solver: 2 GB of FP64 inverse (2D 32x32 and 3D 8x8x8 fit).
 constexpr long long MAX_COARSE = 16384;
 inline int apply_split(long long count, long long split_below) {
+  if (count <= 64) return APPLY_ROWS;
   return count < split_below / 60 ? APPLY_SPLIT_SMALL : count < split_below ? APPLY_SPLIT : 1;
 }
 

@@ -17,7 +17,13 @@ constexpr int APPLY_SPLIT_SMALL = 32;   // lanes per patch on the smallest level
 // streaming launch short (a straggling block holds one wavefront of work); the
 // 8-lane split variant runs best with 256-thread blocks.
 constexpr int APPLY_BLOCK_MAX = 256;
-__host__ __device__ constexpr int apply_block(int split) { return split == APPLY_SPLIT ? 256 : 64; }
+// Buckets of at most 64 patches (3D element patches on top edges and the top
+// corner: up to 89 owned rows each) use the row-parallel apply: one wavefront
+// per patch, one lane per owned row.
+constexpr int APPLY_ROWS = 64;
+__host__ __device__ constexpr int apply_block(int split) {
+  return split == APPLY_SPLIT || split == APPLY_ROWS ? 256 : 64;
+}
 
 enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
 
