@@ -165,6 +165,19 @@ rav_status rav_upload_desc(rav_ctx* ctx, LevelHost& L) {
   return RAV_OK;
 }
 
+// Apply tiles of one bucket for the given lanes-per-patch variant.
+static rav_status make_apply_tasks(rav_ctx* ctx, ApplyLaunch& al, long long count, int split) {
+  const int per_block = apply_block(split) / split;
+  std::vector<BlockTask> at;
+  for (long long p0 = 0; p0 < count; p0 += per_block) {
+    BlockTask t{};
+    t.grid = 0; t.part = al.bucket; t.start = p0; t.logical = (int)at.size();
+    at.push_back(t);
+  }
+  al.split = split;
+  return rav_upload_tasks(ctx, at, &al.tasks, &al.ntasks);
+}
+
 static rav_status build_level(rav_ctx* ctx, int l) {
   const rav_problem_desc& D = ctx->desc;
   LevelHost& L = ctx->lv[l];
@@ -224,15 +237,7 @@ static rav_status build_level(rav_ctx* ctx, int l) {
       ApplyLaunch al;
       al.bucket = h.nbk;
       al.cls = B.cls;
-      al.split = apply_split(cnt, ctx->split_below);
-      const int per_block = apply_block(al.split) / al.split;
-      std::vector<BlockTask> at;
-      for (long long p0 = 0; p0 < cnt; p0 += per_block) {
-        BlockTask t{};
-        t.grid = 0; t.part = h.nbk; t.start = p0; t.logical = (int)at.size();
-        at.push_back(t);
-      }
-      st = rav_upload_tasks(ctx, at, &al.tasks, &al.ntasks);
+      st = make_apply_tasks(ctx, al, cnt, apply_split(cnt, ctx->split_below));
       if (st != RAV_OK) return st;
       L.apply.push_back(al);
       ++h.nbk;
@@ -523,6 +528,78 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
   return RAV_OK;
 }
 
+}  // extern "C"
+
+// Set-up autotuner of the RAV apply: for every bucket of more than 64 patches
+// the 1-, 8- and 32-lanes-per-patch variants are timed (HIP events, mean of
+// three launches after one warm-up, on the level's own vectors, which every
+// solve overwrites) and the fastest is kept.  RAV_AUTOTUNE=0 keeps the
+// size-based choice.
+static rav_status autotune_apply(rav_ctx* ctx) {
+  if (ctx->desc.smoother != RAV_SMOOTHER_RAV) return RAV_OK;
+  if (const char* e = std::getenv("RAV_AUTOTUNE"))
+    if (std::string(e) == "0") return RAV_OK;
+  const rav_problem_desc& D = ctx->desc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  rav_status result = RAV_OK;
+  for (size_t l = 1; l < ctx->lv.size() && result == RAV_OK; ++l) {
+    LevelHost& L = ctx->lv[l];
+    for (ApplyLaunch& al : L.apply) {
+      const long long cnt = L.hd.bk[al.bucket].count;
+      if (cnt <= 64) continue;
+      float best_ms = 0.0f;
+      ApplyLaunch best = al;
+      bool have = false;
+      for (int split : {1, APPLY_SPLIT, APPLY_SPLIT_SMALL}) {
+        ApplyLaunch cand = al;
+        if (split == al.split) {
+          cand = al;
+        } else if ((result = make_apply_tasks(ctx, cand, cnt, split)) != RAV_OK) {
+          break;
+        }
+        auto run = [&]() {
+          launch_rav_apply(D.dim, D.patch, cand.cls, ctx->prec, cand.split, L.dd, cand.tasks, cand.ntasks,
+                           ctx->stream);
+        };
+        run();
+        (void)hipEventRecord(e0, ctx->stream);
+        for (int r = 0; r < 3; ++r) run();
+        (void)hipEventRecord(e1, ctx->stream);
+        if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) {
+          ctx->err = "apply autotuning launch failed";
+          result = RAV_EDEVICE;
+          break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (!have || ms < best_ms) {
+          if (have && best.tasks != al.tasks) (void)hipFree(best.tasks);
+          best = cand;
+          best_ms = ms;
+          have = true;
+        } else if (cand.tasks != al.tasks) {
+          (void)hipFree(cand.tasks);
+        }
+      }
+      if (result != RAV_OK) {
+        if (have && best.tasks != al.tasks) (void)hipFree(best.tasks);
+        break;
+      }
+      if (best.tasks != al.tasks) {
+        (void)hipFree(al.tasks);
+        al = best;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return result;
+}
+
+extern "C" {
+
 rav_status rav_factor_patches(rav_ctx* ctx) {
   if (!ctx) return RAV_EINVAL;
   const rav_problem_desc& D = ctx->desc;
@@ -569,7 +646,7 @@ rav_status rav_factor_patches(rav_ctx* ctx) {
                      "zero pivot in patch " + std::to_string(stv) + " on level " + std::to_string(l));
   }
   ctx->factored = 1;
-  return RAV_OK;
+  return autotune_apply(ctx);
 }
 
 rav_status rav_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free) {
