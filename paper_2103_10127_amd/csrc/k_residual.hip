@@ -740,15 +740,369 @@ __global__ __launch_bounds__(BLOCK) void k_residual_tiled2(const GridDev* __rest
   }
 }
 
+// ---- 3D residual staged through LDS ------------------------------------------
+// Large 3D levels: one block per tile of Q_X x Q_Y x Q_Z cells.  Pressures and
+// cell coefficients of the tile (with halo) are staged once, the velocity
+// window one component at a time (the viscous block acts on each component
+// separately, so a component-c velocity row needs only x_c and the
+// pressures); pressure rows accumulate their divergence over the three
+// component stages in registers.  Masked and outside columns are staged as
+// zeros, so no row tests its columns.  Rows of nodes whose cells all exist and
+// share one coefficient use the assembled reference stencil times that
+// coefficient; other rows (free boundary sides, viscosity jumps, cut cells)
+// sum cell by cell.
+constexpr int Q_X = 8, Q_Y = 8, Q_Z = 4;
+constexpr int QW_X = 2 * Q_X + 5, QW_Y = 2 * Q_Y + 5, QW_Z = 2 * Q_Z + 5;   // node a = 2 x0 - 2 + l
+constexpr int QP_X = Q_X + 3, QP_Y = Q_Y + 3, QP_Z = Q_Z + 3;             // vertex k = x0 - 1 + index
+constexpr int QC_X = Q_X + 2, QC_Y = Q_Y + 2, QC_Z = Q_Z + 2;             // cell E = x0 - 1 + index
+// Velocity window layout: per dimension the even positions l first, then the
+// odd ones, so the nodes of one parity type (one round) sit at consecutive
+// addresses; rows are padded to 24 doubles (8 times an odd number), which
+// spreads the 8 x 8 nodes of a wave over all banks.
+constexpr int QE_X = (QW_X + 1) / 2, QE_Y = (QW_Y + 1) / 2, QE_Z = (QW_Z + 1) / 2;
+constexpr int QR = 24, QPL = QW_Y * QR;
+
+__host__ __device__ constexpr int qperm(int l, int half) { return (l & 1) ? half + (l >> 1) : (l >> 1); }
+__device__ __forceinline__ int qidx(int lz, int ly, int lx) {
+  return qperm(lz, QE_Z) * QPL + qperm(ly, QE_Y) * QR + qperm(lx, QE_X);
+}
+// Position of l + o relative to l >> 1 in the permuted order, for l of parity t.
+__host__ __device__ constexpr int qoff(int t, int o, int half) { return (((t + o) & 1) ? half : 0) + ((t + o + 4) >> 1) - 2; }
+
+// Assembled reference stencils of a node whose cells all exist and share one
+// coefficient (offsets o, |o_d| <= 2, index (o_z+2)*25 + (o_y+2)*5 + o_x+2):
+// viscous rows per parity type, divergence entries of velocity rows per type
+// and component (pressure vertex lo + j, index j_z*9 + j_y*3 + j_x) and
+// divergence rows per component.
+struct Sten3 {
+  double vel[8][125];
+  double velB[8][3][27];
+  double pres[3][125];
+  constexpr Sten3() : vel(), velB(), pres() {
+    for (int ty = 0; ty < 8; ++ty) {
+      const int ne[3] = {(ty & 1) ? 1 : 2, ((ty >> 1) & 1) ? 1 : 2, ((ty >> 2) & 1) ? 1 : 2};
+      for (int i = 0; i < ne[0] * ne[1] * ne[2]; ++i) {
+        const int eo[3] = {i % ne[0], (i / ne[0]) % ne[1], i / (ne[0] * ne[1])};
+        int l[3] = {0, 0, 0};
+        for (int d = 0; d < 3; ++d) l[d] = ((ty >> d) & 1) ? 1 : 2 - 2 * eo[d];
+        const int la = l[0] + 3 * l[1] + 9 * l[2];
+        for (int lb = 0; lb < 27; ++lb) {
+          const int o[3] = {lb % 3 - l[0], (lb / 3) % 3 - l[1], lb / 9 - l[2]};
+          vel[ty][(o[2] + 2) * 25 + (o[1] + 2) * 5 + o[0] + 2] += aref<3>(la, lb);
+        }
+        for (int c = 0; c < 3; ++c)
+          for (int lk = 0; lk < 8; ++lk) {
+            int j[3] = {0, 0, 0};
+            for (int d = 0; d < 3; ++d) j[d] = ((lk >> d) & 1) + (((ty >> d) & 1) ? 0 : eo[d]);
+            velB[ty][c][j[2] * 9 + j[1] * 3 + j[0]] += bref<3>(c, la, lk);
+          }
+      }
+    }
+    for (int i = 0; i < 8; ++i) {
+      int lk = 0;
+      for (int d = 0; d < 3; ++d) lk |= (1 - ((i >> d) & 1)) << d;
+      for (int lb = 0; lb < 27; ++lb) {
+        int o[3] = {0, 0, 0};
+        for (int d = 0, t = lb; d < 3; ++d, t /= 3) o[d] = t % 3 - 2 + 2 * ((i >> d) & 1);
+        for (int c = 0; c < 3; ++c) pres[c][(o[2] + 2) * 25 + (o[1] + 2) * 5 + o[0] + 2] += bref<3>(c, lb, lk);
+      }
+    }
+  }
+};
+__constant__ const Sten3 c_sten3 = Sten3();
+
+struct Tile3Lds {
+  double xs[QW_Z * QPL];
+  double ps[QP_Z][QP_Y][QP_X];
+  double cs[QC_Z][QC_Y][QC_X];
+  double cv[8][125];   // assembled viscous stencils per parity type
+  double cp[3][125];   // divergence rows per component
+};
+
+struct Tile3 {
+  int x0[3];
+  bool last[3];
+};
+
+// Velocity row (component c) of node a of parity type TY.  The staged window
+// holds 0 at masked and outside columns, so rows need no column checks.
+template <int TY>
+__device__ __forceinline__ double res3_vel(const GridDev& gd, const Tile3Lds& S, const Tile3& tl, int c,
+                                           const int* a) {
+  constexpr int NV = 27, NP = 8;
+  constexpr int T0 = TY & 1, T1 = (TY >> 1) & 1, T2 = (TY >> 2) & 1;
+  constexpr int NE0 = T0 ? 1 : 2, NE1 = T1 ? 1 : 2, NE2 = T2 ? 1 : 2;
+  constexpr int NE = NE0 * NE1 * NE2;
+  constexpr int W0 = T0 ? 1 : 2, W1 = T1 ? 1 : 2, W2 = T2 ? 1 : 2;
+  constexpr int M[3] = {3 - T0, 3 - T1, 3 - T2};
+  const Geo& g = gd.g;
+  const int N = g.N;
+  const long long gi = c * g.nV + a[0] + g.nn * (a[1] + g.nn * (long long)a[2]);
+  if (node_dirichlet(g, a)) {
+    gview(gd.r)[gi] = 0.0;
+    return 0.0;
+  }
+  const Tabs<3>& T = tabs<3>();
+  const int l[3] = {a[0] - (2 * tl.x0[0] - 2), a[1] - (2 * tl.x0[1] - 2), a[2] - (2 * tl.x0[2] - 2)};
+  // cells around the node (window-relative indices are in range even for missing cells)
+  double ce[NE];
+  bool fast = true;
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int eo[3] = {i % NE0, (i / NE0) % NE1, i / (NE0 * NE1)};
+    int E[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      E[d] = ((TY >> d) & 1) ? (a[d] - 1) >> 1 : (a[d] >> 1) - 1 + eo[d];
+      ok = ok && E[d] >= 0 && E[d] < N;
+    }
+    ce[i] = ok ? S.cs[E[2] - (tl.x0[2] - 1)][E[1] - (tl.x0[1] - 1)][E[0] - (tl.x0[0] - 1)] : 0.0;
+    fast = fast && ok && ce[i] > 0.0 && ce[i] == ce[0];
+  }
+  const int lo[3] = {(a[0] >> 1) - 1 + T0 - (tl.x0[0] - 1), (a[1] >> 1) - 1 + T1 - (tl.x0[1] - 1),
+                     (a[2] >> 1) - 1 + T2 - (tl.x0[2] - 1)};
+  double acc = 0.0, accB = 0.0;
+  if (fast) {
+    const double* __restrict__ cv = S.cv[TY];
+    const double* __restrict__ xb = S.xs + (l[2] >> 1) * QPL + (l[1] >> 1) * QR + (l[0] >> 1);
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll 1
+    for (int oz = -W2; oz <= W2; ++oz) {
+      const double* __restrict__ xz = xb + qoff(T2, oz, QE_Z) * QPL;
+      const double* __restrict__ cz = cv + (oz + 2) * 25;
+#pragma unroll
+      for (int oy = -W1; oy <= W1; ++oy) {
+#pragma unroll
+        for (int ox = -W0; ox <= W0; ++ox) {
+          const double t = cz[(oy + 2) * 5 + ox + 2] * xz[qoff(T1, oy, QE_Y) * QR + qoff(T0, ox, QE_X)];
+          if ((oy + 2) & 1) a1 += t;
+          else a0 += t;
+        }
+      }
+    }
+    acc = ce[0] * (a0 + a1);
+    const double* __restrict__ Sb = c_sten3.velB[TY][c];
+#pragma unroll
+    for (int jz = 0; jz < M[2]; ++jz) {
+#pragma unroll
+      for (int jy = 0; jy < M[1]; ++jy) {
+#pragma unroll
+        for (int jx = 0; jx < M[0]; ++jx) accB += Sb[jz * 9 + jy * 3 + jx] * S.ps[lo[2] + jz][lo[1] + jy][lo[0] + jx];
+      }
+    }
+  } else {
+    // cell by cell: missing cells (coefficient 0) are skipped, cut cells use their stored matrices
+#pragma unroll 1
+    for (int i = 0; i < NE; ++i) {
+      const double cei = ce[i];
+      if (cei == 0.0) continue;
+      const int eo[3] = {i % NE0, (i / NE0) % NE1, i / (NE0 * NE1)};
+      int la3[3], pz[3], py[3], px[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) la3[d] = ((TY >> d) & 1) ? 1 : 2 - 2 * eo[d];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {   // permuted positions of the cell's nodes (window index l - la + q)
+        pz[q] = qperm(l[2] - la3[2] + q, QE_Z) * QPL;
+        py[q] = qperm(l[1] - la3[1] + q, QE_Y) * QR;
+        px[q] = qperm(l[0] - la3[0] + q, QE_X);
+      }
+      const int la = la3[0] + 3 * la3[1] + 9 * la3[2];
+      double sc = 0.0;
+      if (cei > 0.0) {
+#pragma unroll
+        for (int lb = 0; lb < NV; ++lb) sc += T.A[la * NV + lb] * S.xs[pz[lb / 9] + py[(lb / 3) % 3] + px[lb % 3]];
+        sc *= cei;
+      } else {
+        gcdouble* __restrict__ Ae = gview(gd.cutA) + ((long long)(-cei) - 1) * (NV * NV) + la * NV;
+#pragma unroll
+        for (int lb = 0; lb < NV; ++lb) sc += Ae[lb] * S.xs[pz[lb / 9] + py[(lb / 3) % 3] + px[lb % 3]];
+      }
+      acc += sc;
+      const int p0[3] = {lo[0] + (T0 ? 0 : eo[0]), lo[1] + (T1 ? 0 : eo[1]), lo[2] + (T2 ? 0 : eo[2])};
+#pragma unroll
+      for (int lk = 0; lk < NP; ++lk)
+        accB += T.B[(c * NV + la) * NP + lk] * S.ps[p0[2] + (lk >> 2)][p0[1] + ((lk >> 1) & 1)][p0[0] + (lk & 1)];
+    }
+  }
+  const double r = gview(gd.b)[gi] - (acc + gd.h * gd.h * accB);
+  gview(gd.r)[gi] = r;
+  return r * r;
+}
+
+// Component-c part of the divergence row of pressure vertex k (without h^2).
+__device__ __forceinline__ double res3_pres_part(const Tile3Lds& S, const Tile3& tl, int N, int c, const int* k) {
+  const int l[3] = {2 * k[0] - (2 * tl.x0[0] - 2), 2 * k[1] - (2 * tl.x0[1] - 2), 2 * k[2] - (2 * tl.x0[2] - 2)};
+  double acc = 0.0;
+  if (k[0] >= 1 && k[0] < N && k[1] >= 1 && k[1] < N && k[2] >= 1 && k[2] < N) {
+    const double* __restrict__ xb = S.xs + (l[2] >> 1) * QPL + (l[1] >> 1) * QR + (l[0] >> 1);
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll 1
+    for (int oz = -2; oz <= 2; ++oz) {
+      const double* __restrict__ xz = xb + qoff(0, oz, QE_Z) * QPL;
+      const double* __restrict__ cz = S.cp[c] + (oz + 2) * 25;
+#pragma unroll
+      for (int oy = -2; oy <= 2; ++oy) {
+#pragma unroll
+        for (int ox = -2; ox <= 2; ++ox) {
+          const double t = cz[(oy + 2) * 5 + ox + 2] * xz[qoff(0, oy, QE_Y) * QR + qoff(0, ox, QE_X)];
+          if ((oy + 2) & 1) a1 += t;
+          else a0 += t;
+        }
+      }
+    }
+    acc = a0 + a1;
+  } else {
+    const Tabs<3>& T = tabs<3>();
+#pragma unroll 1
+    for (int i = 0; i < 8; ++i) {
+      int pz[3], py[3], px[3], lk = 0;
+      bool ok = true;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int eo = (i >> d) & 1, E = k[d] - 1 + eo;
+        ok = ok && E >= 0 && E < N;
+        lk |= (1 - eo) << d;
+      }
+      if (!ok) continue;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {   // the cell's first node is at window index l - 2 + 2 eo
+        pz[q] = qperm(l[2] - 2 + 2 * ((i >> 2) & 1) + q, QE_Z) * QPL;
+        py[q] = qperm(l[1] - 2 + 2 * ((i >> 1) & 1) + q, QE_Y) * QR;
+        px[q] = qperm(l[0] - 2 + 2 * (i & 1) + q, QE_X);
+      }
+#pragma unroll
+      for (int lb = 0; lb < 27; ++lb)
+        acc += T.B[(c * 27 + lb) * 8 + lk] * S.xs[pz[lb / 9] + py[(lb / 3) % 3] + px[lb % 3]];
+    }
+  }
+  return acc;
+}
+
+template <int TY>
+__device__ __forceinline__ double tile3_round(const GridDev& gd, const Tile3Lds& S, const Tile3& tl, int c) {
+  const int cx = Q_X + ((tl.last[0] && !(TY & 1)) ? 1 : 0);
+  const int cy = Q_Y + ((tl.last[1] && !((TY >> 1) & 1)) ? 1 : 0);
+  const int cz = Q_Z + ((tl.last[2] && !((TY >> 2) & 1)) ? 1 : 0);
+  double sq = 0.0;
+  for (int i = threadIdx.x; i < cx * cy * cz; i += BLOCK) {
+    const int ix = i % cx, iy = (i / cx) % cy, iz = i / (cx * cy);
+    const int a[3] = {2 * (tl.x0[0] + ix) + (TY & 1), 2 * (tl.x0[1] + iy) + ((TY >> 1) & 1),
+                      2 * (tl.x0[2] + iz) + ((TY >> 2) & 1)};
+    sq += res3_vel<TY>(gd, S, tl, c, a);
+  }
+  return sq;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_residual_tiled3(const GridDev* __restrict__ G, double* __restrict__ partials) {
+  __shared__ Tile3Lds S;
+  const GridDev& gd = *G;
+  const Geo& g = gd.g;
+  const int N = g.N;
+  const int ntx = N / Q_X, nty = N / Q_Y, ntz = N / Q_Z, T = ntx * nty * ntz;
+  const int b = blockIdx.x;
+  const int lt = (b % 8) * (T / 8) + b / 8;
+  const int tx = lt % ntx, ty = (lt / ntx) % nty, tz = lt / (ntx * nty);
+  Tile3 tl;
+  tl.x0[0] = tx * Q_X; tl.x0[1] = ty * Q_Y; tl.x0[2] = tz * Q_Z;
+  tl.last[0] = tx == ntx - 1; tl.last[1] = ty == nty - 1; tl.last[2] = tz == ntz - 1;
+  gcdouble* __restrict__ X = gview(gd.x);
+  const unsigned nn = (unsigned)g.nn, nV = (unsigned)g.nV, np1 = (unsigned)g.np1;
+  const int twoN = 2 * N;
+  for (int i = threadIdx.x; i < 8 * 125; i += BLOCK) S.cv[i / 125][i % 125] = c_sten3.vel[i / 125][i % 125];
+  for (int i = threadIdx.x; i < 3 * 125; i += BLOCK) S.cp[i / 125][i % 125] = c_sten3.pres[i / 125][i % 125];
+#pragma unroll
+  for (int i = threadIdx.x; i < QP_Z * QP_Y * QP_X; i += BLOCK) {
+    const int zz = i / (QP_Y * QP_X), yy = (i / QP_X) % QP_Y, xx = i % QP_X;
+    const int kx = tl.x0[0] - 1 + xx, ky = tl.x0[1] - 1 + yy, kz = tl.x0[2] - 1 + zz;
+    const unsigned gx = (unsigned)min(max(kx, 0), N), gy = (unsigned)min(max(ky, 0), N), gz = (unsigned)min(max(kz, 0), N);
+    const bool in = kx >= 0 && kx <= N && ky >= 0 && ky <= N && kz >= 0 && kz <= N;
+    const double v = ld(X, 3u * nV + gx + np1 * (gy + np1 * gz));
+    S.ps[zz][yy][xx] = in ? v : 0.0;
+  }
+#pragma unroll
+  for (int i = threadIdx.x; i < QC_Z * QC_Y * QC_X; i += BLOCK) {
+    const int zz = i / (QC_Y * QC_X), yy = (i / QC_X) % QC_Y, xx = i % QC_X;
+    const int ex = tl.x0[0] - 1 + xx, ey = tl.x0[1] - 1 + yy, ez = tl.x0[2] - 1 + zz;
+    const unsigned gx = (unsigned)min(max(ex, 0), N - 1), gy = (unsigned)min(max(ey, 0), N - 1),
+                   gz = (unsigned)min(max(ez, 0), N - 1);
+    const bool in = ex >= 0 && ex < N && ey >= 0 && ey < N && ez >= 0 && ez < N;
+    const double v = ld(gview(gd.ceta), gx + (unsigned)N * (gy + (unsigned)N * gz));
+    S.cs[zz][yy][xx] = in ? v : 0.0;
+  }
+  // pressure rows owned by this thread (at most two: 9 x 9 x 5 in a last tile)
+  const int pcx = Q_X + (tl.last[0] ? 1 : 0), pcy = Q_Y + (tl.last[1] ? 1 : 0), pcz = Q_Z + (tl.last[2] ? 1 : 0);
+  const int npr = pcx * pcy * pcz;
+  double pacc[2] = {0.0, 0.0};
+  double sq = 0.0;
+#pragma unroll 1
+  for (int c = 0; c < 3; ++c) {
+    __syncthreads();   // previous component's window no longer read
+#pragma unroll
+    for (int i = threadIdx.x; i < QW_Z * QW_Y * QW_X; i += BLOCK) {
+      const int zz = i / (QW_Y * QW_X), yy = (i / QW_X) % QW_Y, xx = i % QW_X;
+      const int ax = 2 * tl.x0[0] - 2 + xx, ay = 2 * tl.x0[1] - 2 + yy, az = 2 * tl.x0[2] - 2 + zz;
+      const unsigned gx = (unsigned)min(max(ax, 0), twoN), gy = (unsigned)min(max(ay, 0), twoN),
+                     gz = (unsigned)min(max(az, 0), twoN);
+      const bool fr = free_coord(g, 0, ax) && free_coord(g, 1, ay) && free_coord(g, 2, az);
+      const double v = ld(X, (unsigned)c * nV + gx + nn * (gy + nn * gz));
+      S.xs[qidx(zz, yy, xx)] = fr ? v : 0.0;   // masked and outside columns drop out of every row
+    }
+    __syncthreads();
+    sq += tile3_round<0>(gd, S, tl, c);
+    sq += tile3_round<1>(gd, S, tl, c);
+    sq += tile3_round<2>(gd, S, tl, c);
+    sq += tile3_round<3>(gd, S, tl, c);
+    sq += tile3_round<4>(gd, S, tl, c);
+    sq += tile3_round<5>(gd, S, tl, c);
+    sq += tile3_round<6>(gd, S, tl, c);
+    sq += tile3_round<7>(gd, S, tl, c);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = threadIdx.x + q * BLOCK;
+      if (i < npr) {
+        const int k[3] = {tl.x0[0] + i % pcx, tl.x0[1] + (i / pcx) % pcy, tl.x0[2] + i / (pcx * pcy)};
+        pacc[q] += res3_pres_part(S, tl, N, c, k);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = threadIdx.x + q * BLOCK;
+    if (i < npr) {
+      const int k[3] = {tl.x0[0] + i % pcx, tl.x0[1] + (i / pcx) % pcy, tl.x0[2] + i / (pcx * pcy)};
+      const long long gi = 3 * g.nV + k[0] + g.np1 * (k[1] + g.np1 * (long long)k[2]);
+      const double r = gview(gd.b)[gi] - gd.h * gd.h * pacc[q];
+      gview(gd.r)[gi] = r;
+      sq += r * r;
+    }
+  }
+  if (partials == nullptr) return;
+  __shared__ double red[BLOCK / 64];
+  sq = wave_sum(sq);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s2 = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w) s2 += red[w];
+    partials[lt] = s2;
+  }
+}
+
 // Tiles hold 1280 rows each: below 1024 tiles (N < 512) too few blocks run to
 // hide the serial rounds, and the node-type kernel is faster.
+// 3D: tiles of 8 x 8 x 4 cells, used from 1024 tiles (N >= 64) on.
 bool residual_tiled_ok(int dim, int N) {
-  return dim == 2 && N >= 512 && N % RT_X == 0 && N % RT_Y == 0 && ((N / RT_X) * (N / RT_Y)) % 8 == 0;
+  if (dim == 2) return N >= 512 && N % RT_X == 0 && N % RT_Y == 0 && ((N / RT_X) * (N / RT_Y)) % 8 == 0;
+  return N >= 64 && N % Q_X == 0 && N % Q_Y == 0 && N % Q_Z == 0 && ((N / Q_X) * (N / Q_Y) * (N / Q_Z)) % 8 == 0;
 }
-int residual_tiles(int N) { return (N / RT_X) * (N / RT_Y); }
+int residual_tiles(int dim, int N) {
+  return dim == 2 ? (N / RT_X) * (N / RT_Y) : (N / Q_X) * (N / Q_Y) * (N / Q_Z);
+}
 
-void launch_residual_tiled(const GridDev* G, int N, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual_tiled2, dim3(residual_tiles(N)), dim3(BLOCK), 0, s, G, partials);
+void launch_residual_tiled(int dim, const GridDev* G, int N, double* partials, hipStream_t s) {
+  if (dim == 2) hipLaunchKernelGGL(k_residual_tiled2, dim3(residual_tiles(2, N)), dim3(BLOCK), 0, s, G, partials);
+  else hipLaunchKernelGGL(k_residual_tiled3, dim3(residual_tiles(3, N)), dim3(BLOCK), 0, s, G, partials);
 }
 
 void launch_residual(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, double* partials,

@@ -221,7 +221,7 @@ static rav_status build_level(rav_ctx* ctx, int l) {
     st = rav_upload_tasks(ctx, pt, &L.ptasks, &L.n_ptasks);
     if (st != RAV_OK) return st;
   }
-  const int n_part = std::max(L.n_res_tiles, residual_tiled_ok(D.dim, N) ? residual_tiles(N) : 1);
+  const int n_part = std::max(L.n_res_tiles, residual_tiled_ok(D.dim, N) ? residual_tiles(D.dim, N) : 1);
   CK(hipMalloc((void**)&L.partials, sizeof(double) * n_part));
   // patch buckets (smoothed levels only)
   if (l > 0) {
@@ -334,8 +334,8 @@ void rav_residual_level(rav_ctx* ctx, int l, bool with_norm) {
   LevelHost& L = ctx->lv[l];
   const int N = L.hd.g.N;
   if (residual_tiled_ok(ctx->desc.dim, N)) {
-    launch_residual_tiled(L.dd, N, with_norm ? L.partials : nullptr, ctx->stream);
-    if (with_norm) launch_norm_finalize(L.partials, 0, residual_tiles(N), ctx->d_norm, ctx->stream);
+    launch_residual_tiled(ctx->desc.dim, L.dd, N, with_norm ? L.partials : nullptr, ctx->stream);
+    if (with_norm) launch_norm_finalize(L.partials, 0, residual_tiles(ctx->desc.dim, N), ctx->d_norm, ctx->stream);
     return;
   }
   launch_residual(ctx->desc.dim, L.dd, L.res_tasks, L.n_res_tasks, with_norm ? L.partials : nullptr, ctx->stream);

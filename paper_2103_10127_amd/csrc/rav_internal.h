@@ -121,10 +121,10 @@ void launch_rhs(int dim, const GridDev* Gh, const GridDev* Gd, const double* par
 // or 2^d for the pressure rows.
 void launch_residual(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, double* partials,
                      hipStream_t s);
-// Large 2D levels (N >= 512): the residual staged through LDS, one block per tile of cells.
+// Large levels (2D N >= 512, 3D N >= 64): the residual staged through LDS, one block per tile of cells.
 bool residual_tiled_ok(int dim, int N);
-int residual_tiles(int N);
-void launch_residual_tiled(const GridDev* G, int N, double* partials, hipStream_t s);
+int residual_tiles(int dim, int N);
+void launch_residual_tiled(int dim, const GridDev* G, int N, double* partials, hipStream_t s);
 void launch_cell_coef(int dim, long long ncell, const GridDev* G, const double* etaq, const int* cut_idx,
                       const int* cut_cells, int ncut, double* ceta, double* cutA, hipStream_t s);
 void launch_norm_finalize(const double* partials, int first, int count, double* out, hipStream_t s);

@@ -81,6 +81,15 @@ def inclusions(seed: int, n_min: int = 1, n_max: int = 8,
     return np.stack([cx, cy, rad], axis=1).astype(np.float64)
 
 
+def spheres(seed: int, count: int = 6, c_lo: float = 0.15, c_hi: float = 0.85,
+            r_lo: float = 0.05, r_hi: float = 0.15) -> np.ndarray:
+    """Spherical inclusions as a (count, 4) array of (cx, cy, cz, radius)."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(c_lo, c_hi, (count, 3))
+    rad = rng.uniform(r_lo, r_hi, count)
+    return np.concatenate([c, rad[:, None]], axis=1).astype(np.float64)
+
+
 def random_vector(n: int, seed: int) -> np.ndarray:
     """Standard-normal float64 vector (initial iterates, test right-hand sides)."""
     return np.random.default_rng(seed).standard_normal(n)

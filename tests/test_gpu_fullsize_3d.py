@@ -1,7 +1,10 @@
 """Full-size parity on the 3D workload (Q2/Q1 64x64x64, 5 levels, RAV element
 patches, all-Dirichlet velocity): sampled outputs that the oracle computes one
 by one from its row-wise assembly, its element load vectors and its 1D
-interpolation matrices (the full 6.7M-DoF operator is not formed)."""
+interpolation matrices (the full 6.7M-DoF operator is not formed).  A second
+64^3 grid with a natural boundary on x = 1 and spherical inclusions at
+viscosity contrast 1e3 checks the residual rows that take the general path of
+the tiled kernel (boundary nodes with missing cells, cut cells)."""
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -75,8 +78,65 @@ def test_residual_sampled_rows(h3d, grid):
     h3d.residual(NL - 1, torch.from_numpy(x).cuda(), torch.from_numpy(b).cuda(), r)
     rg = r.cpu().numpy()
     rng = np.random.default_rng(84)
-    for i in rng.choice(g.n, 300, replace=False):
+    for i in np.concatenate([rng.choice(g.n, 300, replace=False), _rows_on_planes(g, rng, 1000)]):
         row = A.matrix_row(g, int(i))
+        ro = b[i] - _row_dot(row, x) if g.free[i] else 0.0
+        amax = max(1.0, np.abs(list(row.values()) or [1]).max())
+        assert abs(rg[i] - ro) <= 1e-12 * (1 + abs(ro)) * amax, i
+
+
+def _rows_on_planes(g, rng, count):
+    """Velocity and pressure rows on the x = 0 and x = 1 sides and on the
+    seams between 8 x 8 x 4-cell tiles (cell index multiples of 8, 8, 4)."""
+    out = []
+    for _ in range(count):
+        kind = rng.integers(0, 4)
+        a = rng.integers(0, 2 * N + 1, 3)
+        if kind == 0:
+            a[0] = rng.choice([0, 1, 2, 2 * N - 2, 2 * N - 1, 2 * N])
+        elif kind == 1:
+            d = rng.integers(0, 3)
+            step = 8 if d < 2 else 4
+            a[d] = min(2 * N, 2 * step * rng.integers(0, N // step + 1) + rng.integers(-2, 3))
+            a[d] = max(a[d], 0)
+        if kind == 3:
+            k = a // 2
+            if rng.integers(0, 2):
+                k[0] = rng.choice([0, N])
+            out.append(g.pres(k))
+        else:
+            out.append(g.vel(int(rng.integers(0, 3)), a))
+    return np.asarray(out)
+
+
+@pytest.fixture(scope="module")
+def h3d_incl():
+    print("[gpu] 64^3 grid, outflow side, spherical inclusions at contrast 1e3", flush=True)
+    G = Hierarchy(dim=3, n_cells=N, n_levels=NL, dmask=ri.OUTFLOW_3D, kind="element", omega=OMEGA,
+                  eta_in=1e3, inclusions=ri.spheres(1004))
+    yield G
+    G.close()
+
+
+def test_residual_rows_outflow_and_inclusions(h3d_incl):
+    incl = ri.spheres(1004)
+    g = Grid(3, N, ri.OUTFLOW_3D)
+    eta = A.viscosity(g, RefElement(3), g.elements(), 1.0, 1e3, incl)
+    cut = np.nonzero(eta.min(1) != eta.max(1))[0]
+    assert len(cut) > 100
+    x = ri.random_vector(g.n, 92) * g.free
+    b = ri.random_vector(g.n, 93) * g.free
+    r = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    h3d_incl.residual(NL - 1, torch.from_numpy(x).cuda(), torch.from_numpy(b).cuda(), r)
+    rg = r.cpu().numpy()
+    rng = np.random.default_rng(94)
+    near = []
+    for e in rng.choice(cut, 1000):
+        ec = np.array([e % N, (e // N) % N, e // (N * N)])
+        near.append(g.vel(int(rng.integers(0, 3)), 2 * ec + rng.integers(0, 3, 3)))
+    rows = np.concatenate([rng.choice(g.n, 1000, replace=False), near, _rows_on_planes(g, rng, 1500)])
+    for i in rows:
+        row = A.matrix_row(g, int(i), 1.0, 1e3, incl)
         ro = b[i] - _row_dot(row, x) if g.free[i] else 0.0
         amax = max(1.0, np.abs(list(row.values()) or [1]).max())
         assert abs(rg[i] - ro) <= 1e-12 * (1 + abs(ro)) * amax, i
