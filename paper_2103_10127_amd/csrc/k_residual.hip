@@ -769,54 +769,48 @@ __device__ __forceinline__ int qidx(int lz, int ly, int lx) {
 // Position of l + o relative to l >> 1 in the permuted order, for l of parity t.
 __host__ __device__ constexpr int qoff(int t, int o, int half) { return (((t + o) & 1) ? half : 0) + ((t + o + 4) >> 1) - 2; }
 
-// Assembled reference stencils of a node whose cells all exist and share one
-// coefficient (offsets o, |o_d| <= 2, index (o_z+2)*25 + (o_y+2)*5 + o_x+2):
-// viscous rows per parity type, divergence entries of velocity rows per type
-// and component (pressure vertex lo + j, index j_z*9 + j_y*3 + j_x) and
-// divergence rows per component.
-struct Sten3 {
-  double vel[8][125];
-  double velB[8][3][27];
-  double pres[3][125];
-  constexpr Sten3() : vel(), velB(), pres() {
-    for (int ty = 0; ty < 8; ++ty) {
-      const int ne[3] = {(ty & 1) ? 1 : 2, ((ty >> 1) & 1) ? 1 : 2, ((ty >> 2) & 1) ? 1 : 2};
-      for (int i = 0; i < ne[0] * ne[1] * ne[2]; ++i) {
-        const int eo[3] = {i % ne[0], (i / ne[0]) % ne[1], i / (ne[0] * ne[1])};
-        int l[3] = {0, 0, 0};
-        for (int d = 0; d < 3; ++d) l[d] = ((ty >> d) & 1) ? 1 : 2 - 2 * eo[d];
-        const int la = l[0] + 3 * l[1] + 9 * l[2];
-        for (int lb = 0; lb < 27; ++lb) {
-          const int o[3] = {lb % 3 - l[0], (lb / 3) % 3 - l[1], lb / 9 - l[2]};
-          vel[ty][(o[2] + 2) * 25 + (o[1] + 2) * 5 + o[0] + 2] += aref<3>(la, lb);
-        }
-        for (int c = 0; c < 3; ++c)
-          for (int lk = 0; lk < 8; ++lk) {
-            int j[3] = {0, 0, 0};
-            for (int d = 0; d < 3; ++d) j[d] = ((lk >> d) & 1) + (((ty >> d) & 1) ? 0 : eo[d]);
-            velB[ty][c][j[2] * 9 + j[1] * 3 + j[0]] += bref<3>(c, la, lk);
-          }
-      }
-    }
-    for (int i = 0; i < 8; ++i) {
-      int lk = 0;
-      for (int d = 0; d < 3; ++d) lk |= (1 - ((i >> d) & 1)) << d;
-      for (int lb = 0; lb < 27; ++lb) {
-        int o[3] = {0, 0, 0};
-        for (int d = 0, t = lb; d < 3; ++d, t /= 3) o[d] = t % 3 - 2 + 2 * ((i >> d) & 1);
-        for (int c = 0; c < 3; ++c) pres[c][(o[2] + 2) * 25 + (o[1] + 2) * 5 + o[0] + 2] += bref<3>(c, lb, lk);
-      }
-    }
-  }
-};
-__constant__ const Sten3 c_sten3 = Sten3();
+// With all cells around a node present and one coefficient, the assembled
+// viscous row is sum_c (K in dimension c) x (M in the others), K and M the 1D
+// stiffness and mass rows summed over the node's cells in each dimension
+// (node of parity t, column offset o, |o| <= 2; odd nodes reach |o| <= 1).
+__host__ __device__ constexpr double st1(bool stiff, int t, int o) {
+  return t ? ((o >= -1 && o <= 1) ? (stiff ? k1(1, 1 + o) : m1(1, 1 + o)) : 0.0)
+           : ((o <= 0 ? (stiff ? k1(2, 2 + o) : m1(2, 2 + o)) : 0.0) + (o >= 0 ? (stiff ? k1(0, o) : m1(0, o)) : 0.0));
+}
+// st1 for an offset known only at run time (any offset; 0 beyond the reach).
+__device__ __forceinline__ double st1_at(bool stiff, int t, int o) {
+  double r = 0.0;
+#pragma unroll
+  for (int k = -2; k <= 2; ++k) r = o == k ? st1(stiff, t, k) : r;
+  return r;
+}
+// Element dz + 2 of a 5-entry factor, dz in [-2, 2] known at run time.
+__device__ __forceinline__ double pz_at(const double* f, int dz) {
+  double r = f[0];
+#pragma unroll
+  for (int k = -1; k <= 2; ++k) r = dz == k ? f[k + 2] : r;
+  return r;
+}
+
+// The divergence block factorizes over dimensions: summed over the cells around
+// a node, an entry is -prod_d F_d, with F_d the 1D factor G (d = component) or
+// H (other dimensions) summed over the node's cells in that dimension.
+// Velocity node of parity t, pressure vertex lo + j (even: j < 3, odd: j < 2):
+__host__ __device__ constexpr double ga1(int t, int j) {
+  return t ? (j < 2 ? g1(j, 1) : 0.0) : (j == 0 ? g1(0, 2) : j == 1 ? g1(1, 2) + g1(0, 0) : g1(1, 0));
+}
+__host__ __device__ constexpr double ha1(int t, int j) {
+  return t ? (j < 2 ? h1(j, 1) : 0.0) : (j == 0 ? h1(0, 2) : j == 1 ? h1(1, 2) + h1(0, 0) : h1(1, 0));
+}
+// Pressure vertex k, velocity node 2k + o (|o| <= 2):
+__host__ __device__ constexpr double gv1(int o) { return (o <= 0 ? g1(1, o + 2) : 0.0) + (o >= 0 ? g1(0, o) : 0.0); }
+__host__ __device__ constexpr double hv1(int o) { return (o <= 0 ? h1(1, o + 2) : 0.0) + (o >= 0 ? h1(0, o) : 0.0); }
 
 struct Tile3Lds {
   double xs[QW_Z * QPL];
   double ps[QP_Z][QP_Y][QP_X];
   double cs[QC_Z][QC_Y][QC_X];
-  double cv[8][125];   // assembled viscous stencils per parity type
-  double cp[3][125];   // divergence rows per component
+  double pl[Q_Z][Q_Y][Q_X];   // divergence rows of interior vertices, summed over the components
 };
 
 struct Tile3 {
@@ -824,17 +818,93 @@ struct Tile3 {
   bool last[3];
 };
 
-// Velocity row (component c) of node a of parity type TY.  The staged window
-// holds 0 at masked and outside columns, so rows need no column checks.
+// (z, y, x) position of element i of an NZ x NY x NX box, advanced by BLOCK
+// elements per step without divisions.
+template <int NZ, int NY, int NX>
+struct BoxWalk {
+  int z, y, x;
+  __device__ explicit BoxWalk(int i) : z(i / (NY * NX)), y((i / NX) % NY), x(i % NX) {}
+  __device__ void step() {
+    constexpr int dz = BLOCK / (NY * NX), dy = (BLOCK / NX) % NY, dx = BLOCK % NX;
+    x += dx;
+    const int cx = x >= NX ? 1 : 0;
+    x -= cx * NX;
+    y += dy + cx;
+    const int cy = y >= NY ? 1 : 0;
+    y -= cy * NY;
+    z += dz + cy;
+  }
+};
+static_assert(12 * QW_X <= BLOCK && 24 >= QW_Y, "two window rows per thread");
+
+// Staging of one velocity component's window: thread t < 12 QW_X owns window
+// column xx = t mod QW_X of rows y0 = t / QW_X and y0 + 12 and loads them in
+// every plane (all loads issued before any is used; positions off the grid
+// read a clamped in-range address).
+struct XRows {
+  unsigned gxy[2];   // x + nn y of the two rows (clamped)
+  int lxy[2];        // their window positions (permuted order)
+  bool fxy[2];       // x and y free and inside
+  bool ok[2];        // row exists
+};
+
+__device__ __forceinline__ XRows tile3_rows(const Geo& g, const Tile3& tl) {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));   // recomputed per component rather than held across the rows
+  const int twoN = 2 * g.N;
+  const int xx = t % QW_X, y0 = t / QW_X;
+  const int ax = 2 * tl.x0[0] - 2 + xx;
+  const unsigned gx = (unsigned)min(max(ax, 0), twoN);
+  const bool fx = free_coord(g, 0, ax);
+  XRows R;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int yy = y0 + 12 * r, ay = 2 * tl.x0[1] - 2 + yy;
+    R.ok[r] = t < 12 * QW_X && yy < QW_Y;
+    R.gxy[r] = gx + (unsigned)g.nn * (unsigned)min(max(ay, 0), twoN);
+    R.lxy[r] = qperm(min(yy, QW_Y - 1), QE_Y) * QR + qperm(xx, QE_X);
+    R.fxy[r] = fx & free_coord(g, 1, ay);
+  }
+  return R;
+}
+
+__device__ __forceinline__ void tile3_load_x(const GridDev& gd, const Tile3& tl, int c, const XRows& R,
+                                             double (*v)[QW_Z]) {
+  const Geo& g = gd.g;
+  const unsigned nn2 = (unsigned)g.nn * (unsigned)g.nn;
+  gcdouble* __restrict__ X = gview(gd.x) + (size_t)c * g.nV;
+#pragma unroll
+  for (int z = 0; z < QW_Z; ++z) {
+    const unsigned zo = nn2 * (unsigned)min(max(2 * tl.x0[2] - 2 + z, 0), 2 * g.N);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) v[r][z] = ld(X, (R.ok[r] ? R.gxy[r] : R.gxy[0]) + zo);
+  }
+}
+
+// Masked and outside columns are stored as zeros: they drop out of every row.
+__device__ __forceinline__ void tile3_store_x(const Geo& g, const Tile3& tl, const XRows& R, const double (*v)[QW_Z],
+                                              double* xs) {
+#pragma unroll
+  for (int z = 0; z < QW_Z; ++z) {
+    const bool fz = free_coord(g, 2, 2 * tl.x0[2] - 2 + z);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+      if (R.ok[r]) xs[qperm(z, QE_Z) * QPL + R.lxy[r]] = (R.fxy[r] & fz) ? v[r][z] : 0.0;
+  }
+}
+
+// Velocity row (component c) of node a of parity type TY, cell by cell: the
+// rows the column pass leaves (masked nodes, free sides with missing cells,
+// viscosity jumps, cut cells with their stored matrices).  The staged window
+// holds 0 at masked and outside columns, so no column is tested.
 template <int TY>
-__device__ __forceinline__ double res3_vel(const GridDev& gd, const Tile3Lds& S, const Tile3& tl, int c,
-                                           const int* a) {
+__device__ __noinline__ double res3_vel_cells(const GridDev& gd, const Tile3Lds& S, const Tile3& tl, int c,
+                                              int a0, int a1, int a2) {
   constexpr int NV = 27, NP = 8;
   constexpr int T0 = TY & 1, T1 = (TY >> 1) & 1, T2 = (TY >> 2) & 1;
   constexpr int NE0 = T0 ? 1 : 2, NE1 = T1 ? 1 : 2, NE2 = T2 ? 1 : 2;
   constexpr int NE = NE0 * NE1 * NE2;
-  constexpr int W0 = T0 ? 1 : 2, W1 = T1 ? 1 : 2, W2 = T2 ? 1 : 2;
-  constexpr int M[3] = {3 - T0, 3 - T1, 3 - T2};
+  const int a[3] = {a0, a1, a2};
   const Geo& g = gd.g;
   const int N = g.N;
   const long long gi = c * g.nV + a[0] + g.nn * (a[1] + g.nn * (long long)a[2]);
@@ -842,159 +912,283 @@ __device__ __forceinline__ double res3_vel(const GridDev& gd, const Tile3Lds& S,
     gview(gd.r)[gi] = 0.0;
     return 0.0;
   }
+  const double bv = gview(gd.b)[gi];
   const Tabs<3>& T = tabs<3>();
   const int l[3] = {a[0] - (2 * tl.x0[0] - 2), a[1] - (2 * tl.x0[1] - 2), a[2] - (2 * tl.x0[2] - 2)};
-  // cells around the node (window-relative indices are in range even for missing cells)
-  double ce[NE];
-  bool fast = true;
-#pragma unroll
+  const int lo[3] = {(a[0] >> 1) - 1 + T0 - (tl.x0[0] - 1), (a[1] >> 1) - 1 + T1 - (tl.x0[1] - 1),
+                     (a[2] >> 1) - 1 + T2 - (tl.x0[2] - 1)};
+  double acc = 0.0, accB = 0.0;
+#pragma unroll 1
   for (int i = 0; i < NE; ++i) {
     const int eo[3] = {i % NE0, (i / NE0) % NE1, i / (NE0 * NE1)};
-    int E[3];
+    int E[3], la3[3];
     bool ok = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       E[d] = ((TY >> d) & 1) ? (a[d] - 1) >> 1 : (a[d] >> 1) - 1 + eo[d];
       ok = ok && E[d] >= 0 && E[d] < N;
+      la3[d] = ((TY >> d) & 1) ? 1 : 2 - 2 * eo[d];
     }
-    ce[i] = ok ? S.cs[E[2] - (tl.x0[2] - 1)][E[1] - (tl.x0[1] - 1)][E[0] - (tl.x0[0] - 1)] : 0.0;
-    fast = fast && ok && ce[i] > 0.0 && ce[i] == ce[0];
+    if (!ok) continue;
+    const double cei = S.cs[E[2] - (tl.x0[2] - 1)][E[1] - (tl.x0[1] - 1)][E[0] - (tl.x0[0] - 1)];
+    int pz[3], py[3], px[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {   // permuted positions of the cell's nodes (window index l - la + q)
+      pz[q] = qperm(l[2] - la3[2] + q, QE_Z) * QPL;
+      py[q] = qperm(l[1] - la3[1] + q, QE_Y) * QR;
+      px[q] = qperm(l[0] - la3[0] + q, QE_X);
+    }
+    const int la = la3[0] + 3 * la3[1] + 9 * la3[2];
+    double sc = 0.0;
+    if (cei > 0.0) {
+#pragma unroll
+      for (int lb = 0; lb < NV; ++lb) sc += T.A[la * NV + lb] * S.xs[pz[lb / 9] + py[(lb / 3) % 3] + px[lb % 3]];
+      sc *= cei;
+    } else {
+      gcdouble* __restrict__ Ae = gview(gd.cutA) + ((long long)(-cei) - 1) * (NV * NV) + la * NV;
+#pragma unroll
+      for (int lb = 0; lb < NV; ++lb) sc += Ae[lb] * S.xs[pz[lb / 9] + py[(lb / 3) % 3] + px[lb % 3]];
+    }
+    acc += sc;
+    const int p0[3] = {lo[0] + (T0 ? 0 : eo[0]), lo[1] + (T1 ? 0 : eo[1]), lo[2] + (T2 ? 0 : eo[2])};
+#pragma unroll
+    for (int lk = 0; lk < NP; ++lk)
+      accB += T.B[(c * NV + la) * NP + lk] * S.ps[p0[2] + (lk >> 2)][p0[1] + ((lk >> 1) & 1)][p0[0] + (lk & 1)];
   }
-  const int lo[3] = {(a[0] >> 1) - 1 + T0 - (tl.x0[0] - 1), (a[1] >> 1) - 1 + T1 - (tl.x0[1] - 1),
-                     (a[2] >> 1) - 1 + T2 - (tl.x0[2] - 1)};
-  double acc = 0.0, accB = 0.0;
-  if (fast) {
-    const double* __restrict__ cv = S.cv[TY];
-    const double* __restrict__ xb = S.xs + (l[2] >> 1) * QPL + (l[1] >> 1) * QR + (l[0] >> 1);
-    double a0 = 0.0, a1 = 0.0;
-#pragma unroll 1
-    for (int oz = -W2; oz <= W2; ++oz) {
-      const double* __restrict__ xz = xb + qoff(T2, oz, QE_Z) * QPL;
-      const double* __restrict__ cz = cv + (oz + 2) * 25;
-#pragma unroll
-      for (int oy = -W1; oy <= W1; ++oy) {
-#pragma unroll
-        for (int ox = -W0; ox <= W0; ++ox) {
-          const double t = cz[(oy + 2) * 5 + ox + 2] * xz[qoff(T1, oy, QE_Y) * QR + qoff(T0, ox, QE_X)];
-          if ((oy + 2) & 1) a1 += t;
-          else a0 += t;
-        }
-      }
-    }
-    acc = ce[0] * (a0 + a1);
-    const double* __restrict__ Sb = c_sten3.velB[TY][c];
-#pragma unroll
-    for (int jz = 0; jz < M[2]; ++jz) {
-#pragma unroll
-      for (int jy = 0; jy < M[1]; ++jy) {
-#pragma unroll
-        for (int jx = 0; jx < M[0]; ++jx) accB += Sb[jz * 9 + jy * 3 + jx] * S.ps[lo[2] + jz][lo[1] + jy][lo[0] + jx];
-      }
-    }
-  } else {
-    // cell by cell: missing cells (coefficient 0) are skipped, cut cells use their stored matrices
-#pragma unroll 1
-    for (int i = 0; i < NE; ++i) {
-      const double cei = ce[i];
-      if (cei == 0.0) continue;
-      const int eo[3] = {i % NE0, (i / NE0) % NE1, i / (NE0 * NE1)};
-      int la3[3], pz[3], py[3], px[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) la3[d] = ((TY >> d) & 1) ? 1 : 2 - 2 * eo[d];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {   // permuted positions of the cell's nodes (window index l - la + q)
-        pz[q] = qperm(l[2] - la3[2] + q, QE_Z) * QPL;
-        py[q] = qperm(l[1] - la3[1] + q, QE_Y) * QR;
-        px[q] = qperm(l[0] - la3[0] + q, QE_X);
-      }
-      const int la = la3[0] + 3 * la3[1] + 9 * la3[2];
-      double sc = 0.0;
-      if (cei > 0.0) {
-#pragma unroll
-        for (int lb = 0; lb < NV; ++lb) sc += T.A[la * NV + lb] * S.xs[pz[lb / 9] + py[(lb / 3) % 3] + px[lb % 3]];
-        sc *= cei;
-      } else {
-        gcdouble* __restrict__ Ae = gview(gd.cutA) + ((long long)(-cei) - 1) * (NV * NV) + la * NV;
-#pragma unroll
-        for (int lb = 0; lb < NV; ++lb) sc += Ae[lb] * S.xs[pz[lb / 9] + py[(lb / 3) % 3] + px[lb % 3]];
-      }
-      acc += sc;
-      const int p0[3] = {lo[0] + (T0 ? 0 : eo[0]), lo[1] + (T1 ? 0 : eo[1]), lo[2] + (T2 ? 0 : eo[2])};
-#pragma unroll
-      for (int lk = 0; lk < NP; ++lk)
-        accB += T.B[(c * NV + la) * NP + lk] * S.ps[p0[2] + (lk >> 2)][p0[1] + ((lk >> 1) & 1)][p0[0] + (lk & 1)];
-    }
-  }
-  const double r = gview(gd.b)[gi] - (acc + gd.h * gd.h * accB);
+  const double r = bv - (acc + gd.h * gd.h * accB);
   gview(gd.r)[gi] = r;
   return r * r;
 }
 
-// Component-c part of the divergence row of pressure vertex k (without h^2).
-__device__ __forceinline__ double res3_pres_part(const Tile3Lds& S, const Tile3& tl, int N, int c, const int* k) {
-  const int l[3] = {2 * k[0] - (2 * tl.x0[0] - 2), 2 * k[1] - (2 * tl.x0[1] - 2), 2 * k[2] - (2 * tl.x0[2] - 2)};
-  double acc = 0.0;
-  if (k[0] >= 1 && k[0] < N && k[1] >= 1 && k[1] < N && k[2] >= 1 && k[2] < N) {
-    const double* __restrict__ xb = S.xs + (l[2] >> 1) * QPL + (l[1] >> 1) * QR + (l[0] >> 1);
-    double a0 = 0.0, a1 = 0.0;
-#pragma unroll 1
-    for (int oz = -2; oz <= 2; ++oz) {
-      const double* __restrict__ xz = xb + qoff(0, oz, QE_Z) * QPL;
-      const double* __restrict__ cz = S.cp[c] + (oz + 2) * 25;
+// Component-c part of the divergence row of pressure vertex k (without h^2)
+// for the vertices the column pass leaves (grid boundary, last-tile extras).
+// The cells around a vertex that exist form a product set over dimensions, so
+// the row keeps the factorized form, each 1D factor summed over the vertex's
+// existing cells in that dimension.
+__device__ __noinline__ double res3_pres_sep(const Tile3Lds& S, const Tile3& tl, int N, int c, int k0, int k1, int k2) {
+  const int k[3] = {k0, k1, k2};
+  double f[3][5];
 #pragma unroll
-      for (int oy = -2; oy <= 2; ++oy) {
+  for (int d = 0; d < 3; ++d) {
+    const bool lo = k[d] >= 1, hi = k[d] <= N - 1;   // cells k - 1 and k
 #pragma unroll
-        for (int ox = -2; ox <= 2; ++ox) {
-          const double t = cz[(oy + 2) * 5 + ox + 2] * xz[qoff(0, oy, QE_Y) * QR + qoff(0, ox, QE_X)];
-          if ((oy + 2) & 1) a1 += t;
-          else a0 += t;
-        }
-      }
-    }
-    acc = a0 + a1;
-  } else {
-    const Tabs<3>& T = tabs<3>();
-#pragma unroll 1
-    for (int i = 0; i < 8; ++i) {
-      int pz[3], py[3], px[3], lk = 0;
-      bool ok = true;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int eo = (i >> d) & 1, E = k[d] - 1 + eo;
-        ok = ok && E >= 0 && E < N;
-        lk |= (1 - eo) << d;
-      }
-      if (!ok) continue;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {   // the cell's first node is at window index l - 2 + 2 eo
-        pz[q] = qperm(l[2] - 2 + 2 * ((i >> 2) & 1) + q, QE_Z) * QPL;
-        py[q] = qperm(l[1] - 2 + 2 * ((i >> 1) & 1) + q, QE_Y) * QR;
-        px[q] = qperm(l[0] - 2 + 2 * (i & 1) + q, QE_X);
-      }
-#pragma unroll
-      for (int lb = 0; lb < 27; ++lb)
-        acc += T.B[(c * 27 + lb) * 8 + lk] * S.xs[pz[lb / 9] + py[(lb / 3) % 3] + px[lb % 3]];
+    for (int o = -2; o <= 2; ++o) {
+      const double gl = o <= 0 ? g1(1, o + 2) : 0.0, gh = o >= 0 ? g1(0, o) : 0.0;
+      const double hl = o <= 0 ? h1(1, o + 2) : 0.0, hh = o >= 0 ? h1(0, o) : 0.0;
+      f[d][o + 2] = d == c ? (lo ? gl : 0.0) + (hi ? gh : 0.0) : (lo ? hl : 0.0) + (hi ? hh : 0.0);
     }
   }
-  return acc;
+  const int l[3] = {2 * k[0] - (2 * tl.x0[0] - 2), 2 * k[1] - (2 * tl.x0[1] - 2), 2 * k[2] - (2 * tl.x0[2] - 2)};
+  double acc = 0.0;
+#pragma unroll 1
+  for (int oz = -2; oz <= 2; ++oz) {
+    const int pz = qperm(l[2] + oz, QE_Z) * QPL;
+    double az = 0.0;
+#pragma unroll
+    for (int oy = -2; oy <= 2; ++oy) {
+      const int py = pz + qperm(l[1] + oy, QE_Y) * QR;
+      double ay = 0.0;
+#pragma unroll
+      for (int ox = -2; ox <= 2; ++ox) ay += f[0][ox + 2] * S.xs[py + qperm(l[0] + ox, QE_X)];
+      az += f[1][oy + 2] * ay;
+    }
+    acc += (oz == -2 ? f[2][0] : oz == -1 ? f[2][1] : oz == 0 ? f[2][2] : oz == 1 ? f[2][3] : f[2][4]) * az;
+  }
+  return -acc;
 }
 
-template <int TY>
-__device__ __forceinline__ double tile3_round(const GridDev& gd, const Tile3Lds& S, const Tile3& tl, int c) {
-  const int cx = Q_X + ((tl.last[0] && !(TY & 1)) ? 1 : 0);
-  const int cy = Q_Y + ((tl.last[1] && !((TY >> 1) & 1)) ? 1 : 0);
-  const int cz = Q_Z + ((tl.last[2] && !((TY >> 2) & 1)) ? 1 : 0);
+// Column pass of one wave: nodes of xy parity type TXY, one (x, y) column of
+// the tile per lane, all 2 Q_Z nodes of the column in registers.  Window
+// planes are read once and each feeds every node whose stencil reaches it
+// (assembled stencil constants times the node's cell coefficient); the
+// divergence entries use the factorized form plane by plane.  The wave of
+// type 0 also accumulates the divergence rows of the interior pressure
+// vertices of its columns (the same 5 x 5 plane values) into LDS.  Rows that
+// are not uniform go to the cell-by-cell path.
+template <int TXY>
+__device__ __forceinline__ double tile3_columns(const GridDev& gd, Tile3Lds& S, const Tile3& tl, int c, int lane) {
+  constexpr int TX = TXY & 1, TYY = TXY >> 1;
+  constexpr int W0 = TX ? 1 : 2, W1 = TYY ? 1 : 2;
+  constexpr int NX0 = TX ? 1 : 2, NY0 = TYY ? 1 : 2;
+  constexpr int M0 = 3 - TX, M1 = 3 - TYY;
+  constexpr int NZN = 2 * Q_Z;   // nodes per column (az = 2 z0 + j)
+  const Geo& g = gd.g;
+  const int N = g.N;
+  const int ix = lane & 7, iy = lane >> 3;
+  const int ax = 2 * (tl.x0[0] + ix) + TX, ay = 2 * (tl.x0[1] + iy) + TYY;
+  const long long zst = g.nn * g.nn;
+  const long long col = c * g.nV + ax + g.nn * ay + zst * (2 * tl.x0[2]);
+  double bv[NZN];
+#pragma unroll
+  for (int j = 0; j < NZN; ++j) bv[j] = gview(gd.b)[col + zst * j];
+  // per plane of cells: the coefficient shared by the column's cells (0 when
+  // they differ, are cut or missing)
+  double cz[QC_Z];
+#pragma unroll
+  for (int e = 0; e < QC_Z; ++e) {
+    const double v0 = S.cs[e][iy + (TYY ? 1 : 0)][ix + (TX ? 1 : 0)];
+    bool u = v0 > 0.0;
+#pragma unroll
+    for (int ey = 0; ey < NY0; ++ey)
+#pragma unroll
+      for (int ex = 0; ex < NX0; ++ex) u &= S.cs[e][iy + (TYY ? 1 : ey)][ix + (TX ? 1 : ex)] == v0;   // no short circuit
+    cz[e] = u ? v0 : 0.0;
+  }
+  // divergence factors of this component
+  double fx[3], fy[3], fz[2][3], px[5], py[5], pz[5];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    fx[j] = c == 0 ? ga1(TX, j) : ha1(TX, j);
+    fy[j] = c == 1 ? ga1(TYY, j) : ha1(TYY, j);
+    fz[0][j] = c == 2 ? ga1(0, j) : ha1(0, j);
+    fz[1][j] = c == 2 ? ga1(1, j) : ha1(1, j);
+  }
+#pragma unroll
+  for (int o = 0; o < 5; ++o) {
+    px[o] = c == 0 ? gv1(o - 2) : hv1(o - 2);
+    py[o] = c == 1 ? gv1(o - 2) : hv1(o - 2);
+    pz[o] = c == 2 ? gv1(o - 2) : hv1(o - 2);
+  }
+  // viscous part: window planes p = 0 .. 2 Q_Z + 3 (node j sits on plane j + 2).
+  // Per plane, A1 = (M_y x M_x) v and A2 = (K_y x M_x + M_y x K_x) v; node j
+  // then takes K_z(dz) A1 + M_z(dz) A2 (zero outside its reach).  The plane
+  // loop stays rolled: one plane's values are live at a time.
+  double acc[NZN], pq[Q_Z];
+#pragma unroll
+  for (int j = 0; j < NZN; ++j) acc[j] = 0.0;
+#pragma unroll
+  for (int m = 0; m < Q_Z; ++m) pq[m] = 0.0;
+#pragma unroll 1
+  for (int p = 0; p < NZN + 4; ++p) {
+    const double* __restrict__ xp = S.xs + qperm(p, QE_Z) * QPL + (iy + 1) * QR + (ix + 1);
+    double v[2 * W1 + 1][2 * W0 + 1];
+#pragma unroll
+    for (int oy = -W1; oy <= W1; ++oy)
+#pragma unroll
+      for (int ox = -W0; ox <= W0; ++ox) v[oy + W1][ox + W0] = xp[qoff(TYY, oy, QE_Y) * QR + qoff(TX, ox, QE_X)];
+    double A1 = 0.0, A2 = 0.0;
+#pragma unroll
+    for (int oy = -W1; oy <= W1; ++oy) {
+      double rm = 0.0, rk = 0.0;
+#pragma unroll
+      for (int ox = -W0; ox <= W0; ++ox) {
+        rm += st1(false, TX, ox) * v[oy + W1][ox + W0];
+        rk += st1(true, TX, ox) * v[oy + W1][ox + W0];
+      }
+      A1 += st1(false, TYY, oy) * rm;
+      A2 += st1(true, TYY, oy) * rm + st1(false, TYY, oy) * rk;
+    }
+#pragma unroll
+    for (int j = 0; j < NZN; ++j) {
+      const int dz = p - (j + 2);   // uniform: the coefficients are scalar selects
+      acc[j] += st1_at(true, j & 1, dz) * A1 + st1_at(false, j & 1, dz) * A2;
+    }
+    if constexpr (TXY == 0) {
+      double q = 0.0;
+#pragma unroll
+      for (int oy = 0; oy < 5; ++oy) {
+        double rx = 0.0;
+#pragma unroll
+        for (int ox = 0; ox < 5; ++ox) rx += px[ox] * v[oy][ox];
+        q += py[oy] * rx;
+      }
+#pragma unroll
+      for (int m = 0; m < Q_Z; ++m) {
+        const int dz = p - (2 * m + 2);
+        pq[m] += ((dz >= -2 && dz <= 2) ? pz_at(pz, dz) : 0.0) * q;
+      }
+    }
+  }
+  if constexpr (TXY == 0) {
+    const bool ixy = tl.x0[0] + ix >= 1 && tl.x0[0] + ix <= N - 1 && tl.x0[1] + iy >= 1 && tl.x0[1] + iy <= N - 1;
+#pragma unroll
+    for (int m = 0; m < Q_Z; ++m) {
+      const int kz = tl.x0[2] + m;   // sums of boundary vertices are not used
+      S.pl[m][iy][ix] += (ixy && kz >= 1 && kz <= N - 1) ? pq[m] : 0.0;
+    }
+  }
+  // divergence part: pressure planes kp (vertex z0 - 1 + kp); node j uses lo .. lo + M2 - 1
+  double accB[NZN];
+#pragma unroll
+  for (int j = 0; j < NZN; ++j) accB[j] = 0.0;
+#pragma unroll
+  for (int kp = 0; kp < Q_Z + 2; ++kp) {
+    double P = 0.0;
+#pragma unroll
+    for (int jy = 0; jy < M1; ++jy) {
+      double rr = 0.0;
+#pragma unroll
+      for (int jx = 0; jx < M0; ++jx) rr += fx[jx] * S.ps[kp][iy + TYY + jy][ix + TX + jx];
+      P += fy[jy] * rr;
+    }
+#pragma unroll
+    for (int j = 0; j < NZN; ++j) {
+      const int jz = kp - ((j >> 1) + (j & 1)), M2 = (j & 1) ? 2 : 3;
+      if (jz >= 0 && jz < M2) accB[j] += fz[j & 1][jz] * P;
+    }
+  }
+  // rows
+  const double h2 = gd.h * gd.h;
+  const bool dxy = coord_dirichlet(g, 0, ax) || coord_dirichlet(g, 1, ay);
+  gdouble* __restrict__ R = gview(gd.r);
   double sq = 0.0;
-  for (int i = threadIdx.x; i < cx * cy * cz; i += BLOCK) {
-    const int ix = i % cx, iy = (i / cx) % cy, iz = i / (cx * cy);
-    const int a[3] = {2 * (tl.x0[0] + ix) + (TY & 1), 2 * (tl.x0[1] + iy) + ((TY >> 1) & 1),
-                      2 * (tl.x0[2] + iz) + ((TY >> 2) & 1)};
-    sq += res3_vel<TY>(gd, S, tl, c, a);
+  unsigned slow = 0;
+#pragma unroll
+  for (int j = 0; j < NZN; ++j) {
+    // branch-free: every row is stored here (rows of the cell-by-cell path are
+    // overwritten below), so the column sums stay in registers and are not
+    // sunk into per-node branches
+    const bool dir = dxy || coord_dirichlet(g, 2, 2 * tl.x0[2] + j);
+    const double ce = (j & 1) ? cz[(j + 1) >> 1] : cz[j >> 1];
+    const bool fast = ce > 0.0 && ((j & 1) || cz[(j >> 1) + 1] == ce);
+    double r = bv[j] - (ce * acc[j] - h2 * accB[j]);
+    asm volatile("" : "+v"(r));   // evaluated here for every node (not moved under a branch on dir)
+    r = dir ? 0.0 : r;
+    R[col + zst * j] = r;
+    sq += (!dir && fast) ? r * r : 0.0;
+    slow |= (!dir && !fast) ? 1u << j : 0u;
+  }
+#pragma unroll 1
+  for (int j = 0; j < NZN; ++j) {
+    if (!((slow >> j) & 1u)) continue;
+    if (j & 1) sq += res3_vel_cells<TXY | 4>(gd, S, tl, c, ax, ay, 2 * tl.x0[2] + j);
+    else sq += res3_vel_cells<TXY>(gd, S, tl, c, ax, ay, 2 * tl.x0[2] + j);
   }
   return sq;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_residual_tiled3(const GridDev* __restrict__ G, double* __restrict__ partials) {
+// Velocity nodes of a last tile outside its 2 Q_X x 2 Q_Y x 2 Q_Z core (on
+// the upper grid sides): the slabs ix = Q_X, iy = Q_Y (ix < Q_X) and iz = Q_Z
+// (ix < Q_X, iy < Q_Y) of the type's node box.
+template <int TY>
+__device__ __forceinline__ double tile3_extras(const GridDev& gd, const Tile3Lds& S, const Tile3& tl, int c) {
+  const int ex = (tl.last[0] && !(TY & 1)) ? 1 : 0, ey = (tl.last[1] && !((TY >> 1) & 1)) ? 1 : 0,
+            ez = (tl.last[2] && !((TY >> 2) & 1)) ? 1 : 0;
+  const int cy = Q_Y + ey, cz = Q_Z + ez;
+  const int n0 = ex * cy * cz, n1 = ey * Q_X * cz, n2 = ez * Q_X * Q_Y;
+  const Geo& g = gd.g;
+  double sq = 0.0;
+  for (int i = threadIdx.x; i < n0 + n1 + n2; i += BLOCK) {
+    int ix, iy, iz;
+    if (i < n0) {
+      ix = Q_X; iy = i % cy; iz = i / cy;
+    } else if (i < n0 + n1) {
+      const int t = i - n0;
+      ix = t % Q_X; iy = Q_Y; iz = t / Q_X;
+    } else {
+      const int t = i - n0 - n1;
+      ix = t % Q_X; iy = t / Q_X; iz = Q_Z;
+    }
+    const int a[3] = {2 * (tl.x0[0] + ix) + (TY & 1), 2 * (tl.x0[1] + iy) + ((TY >> 1) & 1),
+                      2 * (tl.x0[2] + iz) + ((TY >> 2) & 1)};
+    if (node_dirichlet(g, a)) gview(gd.r)[c * g.nV + a[0] + g.nn * (a[1] + g.nn * (long long)a[2])] = 0.0;
+    else sq += res3_vel_cells<TY>(gd, S, tl, c, a[0], a[1], a[2]);
+  }
+  return sq;
+}
+
+// Two blocks per CU (LDS bound): at most 256 registers per lane.
+__global__ __launch_bounds__(BLOCK, 2) void k_residual_tiled3(const GridDev* __restrict__ G, double* __restrict__ partials) {
   __shared__ Tile3Lds S;
   const GridDev& gd = *G;
   const Geo& g = gd.g;
@@ -1007,72 +1201,109 @@ __global__ __launch_bounds__(BLOCK) void k_residual_tiled3(const GridDev* __rest
   tl.x0[0] = tx * Q_X; tl.x0[1] = ty * Q_Y; tl.x0[2] = tz * Q_Z;
   tl.last[0] = tx == ntx - 1; tl.last[1] = ty == nty - 1; tl.last[2] = tz == ntz - 1;
   gcdouble* __restrict__ X = gview(gd.x);
-  const unsigned nn = (unsigned)g.nn, nV = (unsigned)g.nV, np1 = (unsigned)g.np1;
-  const int twoN = 2 * N;
-  for (int i = threadIdx.x; i < 8 * 125; i += BLOCK) S.cv[i / 125][i % 125] = c_sten3.vel[i / 125][i % 125];
-  for (int i = threadIdx.x; i < 3 * 125; i += BLOCK) S.cp[i / 125][i % 125] = c_sten3.pres[i / 125][i % 125];
+  const unsigned nV = (unsigned)g.nV, np1 = (unsigned)g.np1;
+  {
+    constexpr int NPW = QP_Z * QP_Y * QP_X, NCW = QC_Z * QC_Y * QC_X;
+    constexpr int PPER = (NPW + BLOCK - 1) / BLOCK, CPER = (NCW + BLOCK - 1) / BLOCK;
+    double pv[PPER], cv[CPER];
+    BoxWalk<QP_Z, QP_Y, QP_X> wp(threadIdx.x);
 #pragma unroll
-  for (int i = threadIdx.x; i < QP_Z * QP_Y * QP_X; i += BLOCK) {
-    const int zz = i / (QP_Y * QP_X), yy = (i / QP_X) % QP_Y, xx = i % QP_X;
-    const int kx = tl.x0[0] - 1 + xx, ky = tl.x0[1] - 1 + yy, kz = tl.x0[2] - 1 + zz;
-    const unsigned gx = (unsigned)min(max(kx, 0), N), gy = (unsigned)min(max(ky, 0), N), gz = (unsigned)min(max(kz, 0), N);
-    const bool in = kx >= 0 && kx <= N && ky >= 0 && ky <= N && kz >= 0 && kz <= N;
-    const double v = ld(X, 3u * nV + gx + np1 * (gy + np1 * gz));
-    S.ps[zz][yy][xx] = in ? v : 0.0;
-  }
+    for (int q = 0; q < PPER; ++q) {
+      const unsigned gx = (unsigned)min(max(tl.x0[0] - 1 + wp.x, 0), N), gy = (unsigned)min(max(tl.x0[1] - 1 + wp.y, 0), N),
+                     gz = (unsigned)min(max(tl.x0[2] - 1 + wp.z, 0), N);
+      pv[q] = ld(X, 3u * nV + gx + np1 * (gy + np1 * gz));
+      wp.step();
+    }
+    BoxWalk<QC_Z, QC_Y, QC_X> wc(threadIdx.x);
 #pragma unroll
-  for (int i = threadIdx.x; i < QC_Z * QC_Y * QC_X; i += BLOCK) {
-    const int zz = i / (QC_Y * QC_X), yy = (i / QC_X) % QC_Y, xx = i % QC_X;
-    const int ex = tl.x0[0] - 1 + xx, ey = tl.x0[1] - 1 + yy, ez = tl.x0[2] - 1 + zz;
-    const unsigned gx = (unsigned)min(max(ex, 0), N - 1), gy = (unsigned)min(max(ey, 0), N - 1),
-                   gz = (unsigned)min(max(ez, 0), N - 1);
-    const bool in = ex >= 0 && ex < N && ey >= 0 && ey < N && ez >= 0 && ez < N;
-    const double v = ld(gview(gd.ceta), gx + (unsigned)N * (gy + (unsigned)N * gz));
-    S.cs[zz][yy][xx] = in ? v : 0.0;
+    for (int q = 0; q < CPER; ++q) {
+      const unsigned gx = (unsigned)min(max(tl.x0[0] - 1 + wc.x, 0), N - 1),
+                     gy = (unsigned)min(max(tl.x0[1] - 1 + wc.y, 0), N - 1),
+                     gz = (unsigned)min(max(tl.x0[2] - 1 + wc.z, 0), N - 1);
+      cv[q] = ld(gview(gd.ceta), gx + (unsigned)N * (gy + (unsigned)N * gz));
+      wc.step();
+    }
+    static_assert(Q_X * Q_Y * Q_Z == BLOCK, "one pressure sum per thread");
+    (&S.pl[0][0][0])[threadIdx.x] = 0.0;
+    BoxWalk<QP_Z, QP_Y, QP_X> wp2(threadIdx.x);
+#pragma unroll
+    for (int q = 0; q < PPER; ++q) {
+      if (q < PPER - 1 || threadIdx.x + q * BLOCK < NPW) {
+        const int kx = tl.x0[0] - 1 + wp2.x, ky = tl.x0[1] - 1 + wp2.y, kz = tl.x0[2] - 1 + wp2.z;
+        const bool in = kx >= 0 && kx <= N && ky >= 0 && ky <= N && kz >= 0 && kz <= N;
+        S.ps[wp2.z][wp2.y][wp2.x] = in ? pv[q] : 0.0;
+      }
+      wp2.step();
+    }
+    BoxWalk<QC_Z, QC_Y, QC_X> wc2(threadIdx.x);
+#pragma unroll
+    for (int q = 0; q < CPER; ++q) {
+      if (q < CPER - 1 || threadIdx.x + q * BLOCK < NCW) {
+        const int ex = tl.x0[0] - 1 + wc2.x, ey = tl.x0[1] - 1 + wc2.y, ez = tl.x0[2] - 1 + wc2.z;
+        const bool in = ex >= 0 && ex < N && ey >= 0 && ey < N && ez >= 0 && ez < N;
+        S.cs[wc2.z][wc2.y][wc2.x] = in ? cv[q] : 0.0;
+      }
+      wc2.step();
+    }
   }
-  // pressure rows owned by this thread (at most two: 9 x 9 x 5 in a last tile)
+  // pressure rows of this thread (at most two: 9 x 9 x 5 in a last tile); the
+  // interior ones of the core come from the column passes, the others are
+  // summed cell by cell here
   const int pcx = Q_X + (tl.last[0] ? 1 : 0), pcy = Q_Y + (tl.last[1] ? 1 : 0), pcz = Q_Z + (tl.last[2] ? 1 : 0);
   const int npr = pcx * pcy * pcz;
-  double pacc[2] = {0.0, 0.0};
+  double pacc[2] = {0.0, 0.0}, pb[2] = {0.0, 0.0};
+  int pk[2][3];
+  bool pcol[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = threadIdx.x + q * BLOCK;
+    const int ix = i % pcx, iy = (i / pcx) % pcy, iz = i / (pcx * pcy);
+    pk[q][0] = tl.x0[0] + ix; pk[q][1] = tl.x0[1] + iy; pk[q][2] = tl.x0[2] + iz;
+    pcol[q] = ix < Q_X && iy < Q_Y && iz < Q_Z && pk[q][0] >= 1 && pk[q][0] <= N - 1 && pk[q][1] >= 1 &&
+              pk[q][1] <= N - 1 && pk[q][2] >= 1 && pk[q][2] <= N - 1;
+    if (i < npr) pb[q] = gview(gd.b)[3 * g.nV + pk[q][0] + g.np1 * (pk[q][1] + g.np1 * (long long)pk[q][2])];
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double sq = 0.0;
 #pragma unroll 1
   for (int c = 0; c < 3; ++c) {
-    __syncthreads();   // previous component's window no longer read
-#pragma unroll
-    for (int i = threadIdx.x; i < QW_Z * QW_Y * QW_X; i += BLOCK) {
-      const int zz = i / (QW_Y * QW_X), yy = (i / QW_X) % QW_Y, xx = i % QW_X;
-      const int ax = 2 * tl.x0[0] - 2 + xx, ay = 2 * tl.x0[1] - 2 + yy, az = 2 * tl.x0[2] - 2 + zz;
-      const unsigned gx = (unsigned)min(max(ax, 0), twoN), gy = (unsigned)min(max(ay, 0), twoN),
-                     gz = (unsigned)min(max(az, 0), twoN);
-      const bool fr = free_coord(g, 0, ax) && free_coord(g, 1, ay) && free_coord(g, 2, az);
-      const double v = ld(X, (unsigned)c * nV + gx + nn * (gy + nn * gz));
-      S.xs[qidx(zz, yy, xx)] = fr ? v : 0.0;   // masked and outside columns drop out of every row
+    {
+      const XRows R = tile3_rows(g, tl);
+      double xv[2][QW_Z];
+      tile3_load_x(gd, tl, c, R, xv);
+      __syncthreads();   // previous component's window no longer read
+      tile3_store_x(g, tl, R, xv, S.xs);
     }
     __syncthreads();
-    sq += tile3_round<0>(gd, S, tl, c);
-    sq += tile3_round<1>(gd, S, tl, c);
-    sq += tile3_round<2>(gd, S, tl, c);
-    sq += tile3_round<3>(gd, S, tl, c);
-    sq += tile3_round<4>(gd, S, tl, c);
-    sq += tile3_round<5>(gd, S, tl, c);
-    sq += tile3_round<6>(gd, S, tl, c);
-    sq += tile3_round<7>(gd, S, tl, c);
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int i = threadIdx.x + q * BLOCK;
-      if (i < npr) {
-        const int k[3] = {tl.x0[0] + i % pcx, tl.x0[1] + (i / pcx) % pcy, tl.x0[2] + i / (pcx * pcy)};
-        pacc[q] += res3_pres_part(S, tl, N, c, k);
-      }
+    switch ((wave + c) & 3) {   // xy parity types rotate over the waves from one component to the next
+      case 0: sq += tile3_columns<0>(gd, S, tl, c, lane); break;
+      case 1: sq += tile3_columns<1>(gd, S, tl, c, lane); break;
+      case 2: sq += tile3_columns<2>(gd, S, tl, c, lane); break;
+      default: sq += tile3_columns<3>(gd, S, tl, c, lane); break;
     }
+    if (tl.last[0] || tl.last[1] || tl.last[2]) {
+      sq += tile3_extras<0>(gd, S, tl, c);
+      sq += tile3_extras<1>(gd, S, tl, c);
+      sq += tile3_extras<2>(gd, S, tl, c);
+      sq += tile3_extras<3>(gd, S, tl, c);
+      sq += tile3_extras<4>(gd, S, tl, c);
+      sq += tile3_extras<5>(gd, S, tl, c);
+      sq += tile3_extras<6>(gd, S, tl, c);
+      sq += tile3_extras<7>(gd, S, tl, c);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (threadIdx.x + q * BLOCK < npr && !pcol[q]) pacc[q] += res3_pres_sep(S, tl, N, c, pk[q][0], pk[q][1], pk[q][2]);
   }
+  __syncthreads();   // column sums of the pressure rows complete
+  const double h2 = gd.h * gd.h;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int i = threadIdx.x + q * BLOCK;
     if (i < npr) {
-      const int k[3] = {tl.x0[0] + i % pcx, tl.x0[1] + (i / pcx) % pcy, tl.x0[2] + i / (pcx * pcy)};
-      const long long gi = 3 * g.nV + k[0] + g.np1 * (k[1] + g.np1 * (long long)k[2]);
-      const double r = gview(gd.b)[gi] - gd.h * gd.h * pacc[q];
+      const long long gi = 3 * g.nV + pk[q][0] + g.np1 * (pk[q][1] + g.np1 * (long long)pk[q][2]);
+      const double r = pcol[q] ? pb[q] + h2 * S.pl[pk[q][2] - tl.x0[2]][pk[q][1] - tl.x0[1]][pk[q][0] - tl.x0[0]]
+                               : pb[q] - h2 * pacc[q];
       gview(gd.r)[gi] = r;
       sq += r * r;
     }
