@@ -777,21 +777,6 @@ __host__ __device__ constexpr double st1(bool stiff, int t, int o) {
   return t ? ((o >= -1 && o <= 1) ? (stiff ? k1(1, 1 + o) : m1(1, 1 + o)) : 0.0)
            : ((o <= 0 ? (stiff ? k1(2, 2 + o) : m1(2, 2 + o)) : 0.0) + (o >= 0 ? (stiff ? k1(0, o) : m1(0, o)) : 0.0));
 }
-// st1 for an offset known only at run time (any offset; 0 beyond the reach).
-__device__ __forceinline__ double st1_at(bool stiff, int t, int o) {
-  double r = 0.0;
-#pragma unroll
-  for (int k = -2; k <= 2; ++k) r = o == k ? st1(stiff, t, k) : r;
-  return r;
-}
-// Element dz + 2 of a 5-entry factor, dz in [-2, 2] known at run time.
-__device__ __forceinline__ double pz_at(const double* f, int dz) {
-  double r = f[0];
-#pragma unroll
-  for (int k = -1; k <= 2; ++k) r = dz == k ? f[k + 2] : r;
-  return r;
-}
-
 // The divergence block factorizes over dimensions: summed over the cells around
 // a node, an entry is -prod_d F_d, with F_d the 1D factor G (d = component) or
 // H (other dimensions) summed over the node's cells in that dimension.
@@ -805,6 +790,31 @@ __host__ __device__ constexpr double ha1(int t, int j) {
 // Pressure vertex k, velocity node 2k + o (|o| <= 2):
 __host__ __device__ constexpr double gv1(int o) { return (o <= 0 ? g1(1, o + 2) : 0.0) + (o >= 0 ? g1(0, o) : 0.0); }
 __host__ __device__ constexpr double hv1(int o) { return (o <= 0 ? h1(1, o + 2) : 0.0) + (o >= 0 ? h1(0, o) : 0.0); }
+
+// z factors of the column pass, per window plane p (rolled loop, scalar loads):
+// K_z and M_z of node j (z = 2 z0 + j) at offset p - j - 2, and the divergence
+// z factor of component c for vertex m (z0 + m) at offset p - 2 m - 2; zero
+// outside a node's or vertex's reach.
+struct ZCoef {
+  double km[2 * Q_Z + 4][2 * Q_Z][2];
+  double pz[3][2 * Q_Z + 4][Q_Z];
+  constexpr ZCoef() : km(), pz() {
+    for (int p = 0; p < 2 * Q_Z + 4; ++p) {
+      for (int j = 0; j < 2 * Q_Z; ++j) {
+        const int dz = p - j - 2;
+        const bool in = dz >= -2 && dz <= 2;
+        km[p][j][0] = in ? st1(true, j & 1, dz) : 0.0;
+        km[p][j][1] = in ? st1(false, j & 1, dz) : 0.0;
+      }
+      for (int m = 0; m < Q_Z; ++m) {
+        const int dz = p - 2 * m - 2;
+        const bool in = dz >= -2 && dz <= 2;
+        for (int c = 0; c < 3; ++c) pz[c][p][m] = in ? (c == 2 ? gv1(dz) : hv1(dz)) : 0.0;
+      }
+    }
+  }
+};
+__constant__ const ZCoef c_zcoef = ZCoef();
 
 struct Tile3Lds {
   double xs[QW_Z * QPL];
@@ -1035,7 +1045,7 @@ __device__ __forceinline__ double tile3_columns(const GridDev& gd, Tile3Lds& S, 
     cz[e] = u ? v0 : 0.0;
   }
   // divergence factors of this component
-  double fx[3], fy[3], fz[2][3], px[5], py[5], pz[5];
+  double fx[3], fy[3], fz[2][3], px[5], py[5];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     fx[j] = c == 0 ? ga1(TX, j) : ha1(TX, j);
@@ -1047,7 +1057,6 @@ __device__ __forceinline__ double tile3_columns(const GridDev& gd, Tile3Lds& S, 
   for (int o = 0; o < 5; ++o) {
     px[o] = c == 0 ? gv1(o - 2) : hv1(o - 2);
     py[o] = c == 1 ? gv1(o - 2) : hv1(o - 2);
-    pz[o] = c == 2 ? gv1(o - 2) : hv1(o - 2);
   }
   // viscous part: window planes p = 0 .. 2 Q_Z + 3 (node j sits on plane j + 2).
   // Per plane, A1 = (M_y x M_x) v and A2 = (K_y x M_x + M_y x K_x) v; node j
@@ -1078,11 +1087,9 @@ __device__ __forceinline__ double tile3_columns(const GridDev& gd, Tile3Lds& S, 
       A1 += st1(false, TYY, oy) * rm;
       A2 += st1(true, TYY, oy) * rm + st1(false, TYY, oy) * rk;
     }
+    const double(*__restrict__ km)[2] = c_zcoef.km[p];
 #pragma unroll
-    for (int j = 0; j < NZN; ++j) {
-      const int dz = p - (j + 2);   // uniform: the coefficients are scalar selects
-      acc[j] += st1_at(true, j & 1, dz) * A1 + st1_at(false, j & 1, dz) * A2;
-    }
+    for (int j = 0; j < NZN; ++j) acc[j] += km[j][0] * A1 + km[j][1] * A2;
     if constexpr (TXY == 0) {
       double q = 0.0;
 #pragma unroll
@@ -1092,20 +1099,15 @@ __device__ __forceinline__ double tile3_columns(const GridDev& gd, Tile3Lds& S, 
         for (int ox = 0; ox < 5; ++ox) rx += px[ox] * v[oy][ox];
         q += py[oy] * rx;
       }
+      const double* __restrict__ zc = c_zcoef.pz[c][p];
 #pragma unroll
-      for (int m = 0; m < Q_Z; ++m) {
-        const int dz = p - (2 * m + 2);
-        pq[m] += ((dz >= -2 && dz <= 2) ? pz_at(pz, dz) : 0.0) * q;
-      }
+      for (int m = 0; m < Q_Z; ++m) pq[m] += zc[m] * q;
     }
   }
   if constexpr (TXY == 0) {
-    const bool ixy = tl.x0[0] + ix >= 1 && tl.x0[0] + ix <= N - 1 && tl.x0[1] + iy >= 1 && tl.x0[1] + iy <= N - 1;
+    // the sums of vertices this pass does not own are not used (plain adds, no branches)
 #pragma unroll
-    for (int m = 0; m < Q_Z; ++m) {
-      const int kz = tl.x0[2] + m;   // sums of boundary vertices are not used
-      S.pl[m][iy][ix] += (ixy && kz >= 1 && kz <= N - 1) ? pq[m] : 0.0;
-    }
+    for (int m = 0; m < Q_Z; ++m) S.pl[m][iy][ix] += pq[m];
   }
   // divergence part: pressure planes kp (vertex z0 - 1 + kp); node j uses lo .. lo + M2 - 1
   double accB[NZN];
@@ -1171,7 +1173,7 @@ __device__ __forceinline__ double tile3_extras(const GridDev& gd, const Tile3Lds
   for (int i = threadIdx.x; i < n0 + n1 + n2; i += BLOCK) {
     int ix, iy, iz;
     if (i < n0) {
-      ix = Q_X; iy = i % cy; iz = i / cy;
+      ix = Q_X; iy = ey ? i % (Q_Y + 1) : i % Q_Y; iz = ey ? i / (Q_Y + 1) : i / Q_Y;
     } else if (i < n0 + n1) {
       const int t = i - n0;
       ix = t % Q_X; iy = Q_Y; iz = t / Q_X;
@@ -1259,8 +1261,11 @@ __global__ __launch_bounds__(BLOCK, 2) void k_residual_tiled3(const GridDev* __r
     const int i = threadIdx.x + q * BLOCK;
     const int ix = i % pcx, iy = (i / pcx) % pcy, iz = i / (pcx * pcy);
     pk[q][0] = tl.x0[0] + ix; pk[q][1] = tl.x0[1] + iy; pk[q][2] = tl.x0[2] + iz;
-    pcol[q] = ix < Q_X && iy < Q_Y && iz < Q_Z && pk[q][0] >= 1 && pk[q][0] <= N - 1 && pk[q][1] >= 1 &&
-              pk[q][1] <= N - 1 && pk[q][2] >= 1 && pk[q][2] <= N - 1;
+    // core vertices take the column sums: interior ones, and those on a lower
+    // grid side that is masked (the missing cell's terms multiply only
+    // outside or masked window values, which are staged as zeros)
+    pcol[q] = ix < Q_X && iy < Q_Y && iz < Q_Z && (pk[q][0] >= 1 || coord_dirichlet(g, 0, 0)) &&
+              (pk[q][1] >= 1 || coord_dirichlet(g, 1, 0)) && (pk[q][2] >= 1 || coord_dirichlet(g, 2, 0));
     if (i < npr) pb[q] = gview(gd.b)[3 * g.nV + pk[q][0] + g.np1 * (pk[q][1] + g.np1 * (long long)pk[q][2])];
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
