@@ -175,8 +175,7 @@ __host__ __device__ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_
 // large levels, SPLIT = 8 and 32 shorten the dependent load chain on smaller
 // levels where too few wavefronts exist to hide memory latency.
 template <int DIM, int KIND, int CLS, typename WT, int SPLIT>
-__global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply(const GridDev* __restrict__ G,
-                                                      const BlockTask* __restrict__ tasks) {
+__device__ __forceinline__ void rav_apply_body(const GridDev* __restrict__ G, const BlockTask t) {
   typedef typename WTraits<WT>::acc_t acc_t;
   typedef typename WTraits<WT>::vec_t vec_t;
   constexpr int V = WTraits<WT>::V;
@@ -188,7 +187,6 @@ __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply(const GridDev* __
   constexpr int TAIL = NPAD - NG * GC;        // leftover columns
   constexpr int TAIL_E = TAIL * NOWN;
   constexpr int TAIL_CH = (TAIL_E + V - 1) / V;
-  const BlockTask t = tasks[blockIdx.x];
   if (t.grid < 0) return;
   const GridDev& gd = G[t.grid];
   if (grid_idle(gd)) return;
@@ -253,6 +251,12 @@ __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply(const GridDev* __
   }
 }
 
+template <int DIM, int KIND, int CLS, typename WT, int SPLIT>
+__global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply(const GridDev* __restrict__ G,
+                                                      const BlockTask* __restrict__ tasks) {
+  rav_apply_body<DIM, KIND, CLS, WT, SPLIT>(G, tasks[blockIdx.x]);
+}
+
 // Row-parallel RAV apply for tiny buckets: one wavefront per patch, lane j
 // accumulates owned rows j and j + 64 over the patch columns.  The column loop
 // is wave-uniform (the r value of a column is one broadcast load), so the
@@ -270,11 +274,9 @@ template <> __device__ __forceinline__ double w_elem<bf16_t>(const bf16_t* W, lo
 }
 
 template <int DIM, int KIND, typename WT>
-__global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_rows(const GridDev* __restrict__ G,
-                                                                   const BlockTask* __restrict__ tasks) {
+__device__ __forceinline__ void rav_apply_rows_body(const GridDev* __restrict__ G, const BlockTask t) {
   constexpr int NPAD = patch_npad(DIM, KIND);
   constexpr int V = WTraits<WT>::V;
-  const BlockTask t = tasks[blockIdx.x];
   if (t.grid < 0) return;
   const GridDev& gd = G[t.grid];
   if (grid_idle(gd)) return;
@@ -312,6 +314,66 @@ __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_rows(const GridDe
     const long long gi = own_index<DIM, KIND>(cm, k, bucket_own_local(DIM, KIND, bk.cls, jj));
     if (gi >= 0) x[gi] += om * acc[h];
   }
+}
+
+template <int DIM, int KIND, typename WT>
+__global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_rows(const GridDev* __restrict__ G,
+                                                                   const BlockTask* __restrict__ tasks) {
+  rav_apply_rows_body<DIM, KIND, WT>(G, tasks[blockIdx.x]);
+}
+
+// The boundary buckets of a level in one launch: each block runs the variant
+// its task names (pad = APPLY_SPLIT or APPLY_ROWS, both 256-thread blocks) for
+// its bucket's class.  Separate launches of these small, latency-bound buckets
+// ran one after another with a launch gap each.
+template <int DIM, int KIND, typename WT>
+__global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_multi(const GridDev* __restrict__ G,
+                                                                    const BlockTask* __restrict__ tasks) {
+  const BlockTask t = tasks[blockIdx.x];
+  if (t.grid < 0) return;
+  if (t.pad == APPLY_ROWS) {
+    rav_apply_rows_body<DIM, KIND, WT>(G, t);
+    return;
+  }
+  const int cls = G[t.grid].bk[t.part].cls;
+  if constexpr (DIM == 3 && KIND == KIND_ELEMENT) {
+    switch (cls) {
+      case 0: rav_apply_body<3, KIND_ELEMENT, 0, WT, APPLY_SPLIT>(G, t); break;
+      case 1: rav_apply_body<3, KIND_ELEMENT, 1, WT, APPLY_SPLIT>(G, t); break;
+      case 2: rav_apply_body<3, KIND_ELEMENT, 2, WT, APPLY_SPLIT>(G, t); break;
+      case 3: rav_apply_body<3, KIND_ELEMENT, 3, WT, APPLY_SPLIT>(G, t); break;
+      case 4: rav_apply_body<3, KIND_ELEMENT, 4, WT, APPLY_SPLIT>(G, t); break;
+      case 5: rav_apply_body<3, KIND_ELEMENT, 5, WT, APPLY_SPLIT>(G, t); break;
+      case 6: rav_apply_body<3, KIND_ELEMENT, 6, WT, APPLY_SPLIT>(G, t); break;
+      default: rav_apply_body<3, KIND_ELEMENT, 7, WT, APPLY_SPLIT>(G, t); break;
+    }
+  } else if constexpr (KIND == KIND_ELEMENT) {
+    switch (cls) {
+      case 0: rav_apply_body<2, KIND_ELEMENT, 0, WT, APPLY_SPLIT>(G, t); break;
+      case 1: rav_apply_body<2, KIND_ELEMENT, 1, WT, APPLY_SPLIT>(G, t); break;
+      case 2: rav_apply_body<2, KIND_ELEMENT, 2, WT, APPLY_SPLIT>(G, t); break;
+      default: rav_apply_body<2, KIND_ELEMENT, 3, WT, APPLY_SPLIT>(G, t); break;
+    }
+  } else {
+    rav_apply_body<DIM, KIND, 0, WT, APPLY_SPLIT>(G, t);
+  }
+}
+
+void launch_rav_apply_multi(int dim, int kind, int prec, const GridDev* G, const BlockTask* tasks, int ntasks,
+                            hipStream_t s) {
+#define RAV_MULTI(D, K)                                                                                      \
+  do {                                                                                                       \
+    if (prec == P_FP64)                                                                                      \
+      hipLaunchKernelGGL((k_rav_apply_multi<D, K, double>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks); \
+    else if (prec == P_FP32)                                                                                 \
+      hipLaunchKernelGGL((k_rav_apply_multi<D, K, float>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks);  \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_rav_apply_multi<D, K, bf16_t>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks); \
+  } while (0)
+  if (dim == 2 && kind == KIND_VERTEX) RAV_MULTI(2, KIND_VERTEX);
+  else if (dim == 2) RAV_MULTI(2, KIND_ELEMENT);
+  else RAV_MULTI(3, KIND_ELEMENT);
+#undef RAV_MULTI
 }
 
 template <int DIM, int KIND>

@@ -360,7 +360,9 @@ void rav_apply_level(rav_ctx* ctx, int l) {
   const bool timed = prof_mark(ctx, l, ctx->prof_app, ctx->prof_napp, true);
   if (D.smoother == RAV_SMOOTHER_RAV) {
     for (const ApplyLaunch& al : L.apply)
-      launch_rav_apply(D.dim, D.patch, al.cls, ctx->prec, al.split, L.dd, al.tasks, al.ntasks, ctx->stream);
+      if (!al.merged)
+        launch_rav_apply(D.dim, D.patch, al.cls, ctx->prec, al.split, L.dd, al.tasks, al.ntasks, ctx->stream);
+    if (L.n_multi > 0) launch_rav_apply_multi(D.dim, D.patch, ctx->prec, L.dd, L.multi_tasks, L.n_multi, ctx->stream);
   } else if (D.smoother == RAV_SMOOTHER_AV) {
     launch_av_apply(D.dim, D.patch, L.dd, L.npatch, ctx->stream);
     launch_av_gather(D.dim, D.patch, L.dd, L.hd.g.n, ctx->stream);
@@ -535,6 +537,38 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
 // three launches after one warm-up, on the level's own vectors, which every
 // solve overwrites) and the fastest is kept.  RAV_AUTOTUNE=0 keeps the
 // size-based choice.
+// Buckets of a level that run 256-thread blocks (APPLY_SPLIT lanes per patch
+// or the row-parallel variant) go into one merged launch when there are at
+// least two of them: the 3D boundary buckets (faces, edges, corner) are small
+// and latency-bound, and separate launches serialize their tails.
+static rav_status merge_apply(rav_ctx* ctx) {
+  for (size_t l = 1; l < ctx->lv.size(); ++l) {
+    LevelHost& L = ctx->lv[l];
+    std::vector<BlockTask> mt;
+    int nb = 0;
+    for (ApplyLaunch& al : L.apply) al.merged = false;
+    for (const ApplyLaunch& al : L.apply) nb += (al.split == APPLY_SPLIT || al.split == APPLY_ROWS) ? 1 : 0;
+    if (nb < 2) continue;
+    for (ApplyLaunch& al : L.apply) {
+      if (al.split != APPLY_SPLIT && al.split != APPLY_ROWS) continue;
+      const long long cnt = L.hd.bk[al.bucket].count;
+      const int per_block = apply_block(al.split) / (al.split == APPLY_ROWS ? 64 : al.split);
+      for (long long p0 = 0; p0 < cnt; p0 += per_block) {
+        BlockTask t{};
+        t.grid = 0; t.part = al.bucket; t.start = p0; t.logical = (int)mt.size(); t.pad = al.split;
+        mt.push_back(t);
+      }
+      al.merged = true;
+    }
+    (void)hipFree(L.multi_tasks);
+    L.multi_tasks = nullptr;
+    L.n_multi = 0;
+    const rav_status st = rav_upload_tasks(ctx, mt, &L.multi_tasks, &L.n_multi);
+    if (st != RAV_OK) return st;
+  }
+  return RAV_OK;
+}
+
 static rav_status autotune_apply(rav_ctx* ctx) {
   if (ctx->desc.smoother != RAV_SMOOTHER_RAV) return RAV_OK;
   if (const char* e = std::getenv("RAV_AUTOTUNE"))
@@ -646,7 +680,8 @@ rav_status rav_factor_patches(rav_ctx* ctx) {
                      "zero pivot in patch " + std::to_string(stv) + " on level " + std::to_string(l));
   }
   ctx->factored = 1;
-  return autotune_apply(ctx);
+  const rav_status st = autotune_apply(ctx);
+  return st != RAV_OK ? st : merge_apply(ctx);
 }
 
 rav_status rav_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free) {
@@ -1072,6 +1107,7 @@ rav_status rav_destroy(rav_ctx* ctx) {
     (void)hipFree(L.rtasks); (void)hipFree(L.ptasks);
     (void)hipFree(L.ceta); (void)hipFree(L.cutA);
     for (ApplyLaunch& a : L.apply) (void)hipFree(a.tasks);
+    (void)hipFree(L.multi_tasks);
   }
   (void)hipFree(ctx->d_incl); (void)hipFree(ctx->Minv); (void)hipFree(ctx->d_status);
   (void)hipFree(ctx->d_piv); (void)hipFree(ctx->d_colk); (void)hipFree(ctx->d_norm);

@@ -17,6 +17,7 @@ struct ApplyLaunch {
   int split = 1;
   BlockTask* tasks = nullptr;
   int ntasks = 0;
+  bool merged = false;   // launched within the level's merged launch
 };
 
 // Buckets with fewer patches than SPLIT_BELOW run the split apply variant
@@ -45,6 +46,8 @@ struct LevelHost {
   int n_res_tiles = 0;
   double* partials = nullptr;
   std::vector<ApplyLaunch> apply;
+  BlockTask* multi_tasks = nullptr;   // merged launch of the buckets marked merged
+  int n_multi = 0;
   long long npatch = 0;
   BlockTask* rtasks = nullptr;   // restriction: node-type tiles over the coarser level
   int n_rtasks = 0;
