@@ -574,6 +574,8 @@ static rav_status autotune_apply(rav_ctx* ctx) {
   if (const char* e = std::getenv("RAV_AUTOTUNE"))
     if (std::string(e) == "0") return RAV_OK;
   const rav_problem_desc& D = ctx->desc;
+  const char* lg = std::getenv("RAV_AUTOTUNE_LOG");   // "1": print every candidate's time to stderr
+  const bool log = lg && std::string(lg) == "1";
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
@@ -608,6 +610,8 @@ static rav_status autotune_apply(rav_ctx* ctx) {
         }
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, e0, e1);
+        if (log) std::fprintf(stderr, "rav autotune: level %zu bucket %d (%lld patches) split %d: %.1f us\n", l,
+                              al.bucket, cnt, split, 1e3f * ms / 3.0f);
         if (!have || ms < best_ms) {
           if (have && best.tasks != al.tasks) (void)hipFree(best.tasks);
           best = cand;
