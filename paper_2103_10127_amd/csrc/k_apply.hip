@@ -442,6 +442,7 @@ void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const Gri
     return;
   }
   if (split == APPLY_SPLIT_SMALL) launch_apply_s<APPLY_SPLIT_SMALL>(dim, kind, cls, prec, G, tasks, ntasks, s);
+  else if (split == 4) launch_apply_s<4>(dim, kind, cls, prec, G, tasks, ntasks, s);
   else if (split > 1) launch_apply_s<APPLY_SPLIT>(dim, kind, cls, prec, G, tasks, ntasks, s);
   else launch_apply_s<1>(dim, kind, cls, prec, G, tasks, ntasks, s);
 }

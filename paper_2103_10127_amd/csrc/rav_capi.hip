@@ -533,7 +533,7 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
 }  // extern "C"
 
 // Set-up autotuner of the RAV apply: for every bucket of more than 64 patches
-// the 1-, 8- and 32-lanes-per-patch variants are timed (HIP events, mean of
+// the 1-, 4-, 8- and 32-lanes-per-patch variants are timed (HIP events, mean of
 // three launches after one warm-up, on the level's own vectors, which every
 // solve overwrites) and the fastest is kept.  RAV_AUTOTUNE=0 keeps the
 // size-based choice.
@@ -588,7 +588,7 @@ static rav_status autotune_apply(rav_ctx* ctx) {
       float best_ms = 0.0f;
       ApplyLaunch best = al;
       bool have = false;
-      for (int split : {1, APPLY_SPLIT, APPLY_SPLIT_SMALL}) {
+      for (int split : {1, 4, APPLY_SPLIT, APPLY_SPLIT_SMALL}) {
         ApplyLaunch cand = al;
         if (split == al.split) {
           cand = al;
