@@ -344,6 +344,23 @@ void rav_residual_level(rav_ctx* ctx, int l, bool with_norm) {
 
 static bool prof_mark(rav_ctx* ctx, int l, std::vector<hipEvent_t>& ev, int& n, bool start) {
   if (ctx->prof_level != l) return false;
+  if (ctx->prof_capture) {   // markers inside the profiled cycle graph
+    const bool res = &ev == &ctx->prof_res;
+    std::vector<hipEvent_t>& gev = res ? ctx->gprof_res : ctx->gprof_app;
+    int& gn = res ? ctx->gprof_nres : ctx->gprof_napp;
+    if (start) {
+      while ((int)gev.size() < 2 * (gn + 1)) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return false;
+        gev.push_back(e);
+      }
+      (void)hipEventRecord(gev[2 * gn], ctx->stream);
+    } else {
+      (void)hipEventRecord(gev[2 * gn + 1], ctx->stream);
+      ++gn;
+    }
+    return true;
+  }
   if (start) {
     if (n >= ctx->prof_max) return false;
     (void)hipEventRecord(ev[2 * n], ctx->stream);
@@ -427,6 +444,84 @@ static void vcycle_level(rav_ctx* ctx, int l, bool r_valid) {
 }
 
 void rav_vcycle_finest(rav_ctx* ctx) { vcycle_level(ctx, (int)ctx->lv.size() - 1, false); }
+
+void rav_drop_graph(rav_ctx* ctx) {
+  if (ctx->cycle_exec) (void)hipGraphExecDestroy(ctx->cycle_exec);
+  if (ctx->prof_exec) (void)hipGraphExecDestroy(ctx->prof_exec);
+  ctx->cycle_exec = ctx->prof_exec = nullptr;
+  ctx->prof_exec_level = -1;
+}
+
+// One solve cycle: V-cycle from a current finest residual, then the new
+// finest residual and its squared norm in d_norm.  Replayed from a graph when
+// possible; with profiling markers active (their events count launches on the
+// host) the launches are issued directly.
+static bool capture_cycle(rav_ctx* ctx, hipGraphExec_t* out) {
+  const int lf = (int)ctx->lv.size() - 1;
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    vcycle_level(ctx, lf, true);
+    rav_residual_level(ctx, lf, true);
+    ok = hipStreamEndCapture(ctx->stream, &g) == hipSuccess && g != nullptr;
+  }
+  if (ok) ok = hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (!ok) {
+    (void)hipGetLastError();
+    *out = nullptr;
+  }
+  return ok;
+}
+
+static void solve_cycle(rav_ctx* ctx) {
+  const int lf = (int)ctx->lv.size() - 1;
+  static const bool graphs = [] {
+    const char* e = std::getenv("RAV_GRAPH");
+    return !(e && std::string(e) == "0");
+  }();
+  if (graphs && !ctx->graph_failed) {
+    const bool prof = ctx->prof_level >= 0;
+    if (prof && ctx->prof_exec && ctx->prof_exec_level != ctx->prof_level) rav_drop_graph(ctx);
+    hipGraphExec_t* ex = prof ? &ctx->prof_exec : &ctx->cycle_exec;
+    if (!*ex) {
+      if (prof) {
+        ctx->gprof_nres = ctx->gprof_napp = 0;
+        ctx->prof_capture = true;
+      }
+      const bool ok = capture_cycle(ctx, ex);
+      ctx->prof_capture = false;
+      if (prof) ctx->prof_exec_level = ctx->prof_level;
+      if (!ok) ctx->graph_failed = true;   // issue the launches directly from now on
+    }
+    if (*ex && hipGraphLaunch(*ex, ctx->stream) == hipSuccess) return;
+    (void)hipGetLastError();
+    rav_drop_graph(ctx);
+    ctx->graph_failed = true;
+  }
+  vcycle_level(ctx, lf, true);
+  rav_residual_level(ctx, lf, true);
+}
+
+// After a replay of the profiled cycle (stream synchronized): add its marker
+// intervals to the profile sums.
+static void collect_graph_profile(rav_ctx* ctx) {
+  if (ctx->prof_level < 0 || !ctx->prof_exec) return;
+  for (int i = 0; i < ctx->gprof_nres; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->gprof_res[2 * i], ctx->gprof_res[2 * i + 1]) == hipSuccess) {
+      ctx->prof_sum_res += ms;
+      ++ctx->prof_cnt_res;
+    }
+  }
+  for (int i = 0; i < ctx->gprof_napp; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->gprof_app[2 * i], ctx->gprof_app[2 * i + 1]) == hipSuccess) {
+      ctx->prof_sum_app += ms;
+      ++ctx->prof_cnt_app;
+    }
+  }
+}
 
 rav_status rav_read_norm(rav_ctx* ctx, double* out) {
   CK(hipMemcpyAsync(ctx->h_norm, ctx->d_norm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -640,6 +735,7 @@ extern "C" {
 
 rav_status rav_factor_patches(rav_ctx* ctx) {
   if (!ctx) return RAV_EINVAL;
+  rav_drop_graph(ctx);
   const rav_problem_desc& D = ctx->desc;
   const bool full = D.smoother != RAV_SMOOTHER_RAV;
   const int npad = patch_npad(D.dim, D.patch);
@@ -827,10 +923,10 @@ rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int 
   ctx->fell_back = 0;
   while (result == RAV_NOT_CONVERGED && k < maxit) {
     const double rprev = rk;
-    vcycle_level(ctx, lf, true);   // r of the finest level is current from the norm evaluation
-    rav_residual_level(ctx, lf, true);
+    solve_cycle(ctx);   // r of the finest level is current from the norm evaluation
     st = rav_read_norm(ctx, &rk);
     if (st != RAV_OK) return st;
+    collect_graph_profile(ctx);
     ++k;
     if (ctx->fallback_rho > 0.0 && !ctx->fell_back && rk > ctx->fallback_rho * rprev) {
       // the per-patch weights reduce the residual less than the fixed-omega
@@ -861,6 +957,7 @@ rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int 
 
 rav_status rav_set_params(rav_ctx* ctx, double omega, int nu_pre, int nu_post) {
   if (!ctx || !(omega > 0.0) || nu_pre < 0 || nu_post < 0) return RAV_EINVAL;
+  rav_drop_graph(ctx);
   ctx->desc.omega = omega;
   ctx->desc.nu_pre = nu_pre;
   ctx->desc.nu_post = nu_post;
@@ -1067,6 +1164,8 @@ rav_status rav_profile_begin(rav_ctx* ctx, int level, int max_launches) {
   for (auto& e : ctx->prof_app) CK(hipEventCreate(&e));
   ctx->prof_max = max_launches;
   ctx->prof_nres = ctx->prof_napp = 0;
+  ctx->prof_sum_res = ctx->prof_sum_app = 0.0;
+  ctx->prof_cnt_res = ctx->prof_cnt_app = 0;
   ctx->prof_level = level;
   return RAV_OK;
 }
@@ -1086,9 +1185,12 @@ rav_status rav_profile_end(rav_ctx* ctx, float* avg_res, float* avg_app, int* n_
     CK(hipEventElapsedTime(&ms, ctx->prof_app[2 * i], ctx->prof_app[2 * i + 1]));
     ta += ms;
   }
-  if (avg_res) *avg_res = ctx->prof_nres ? (float)(tr / ctx->prof_nres) : 0.f;
-  if (avg_app) *avg_app = ctx->prof_napp ? (float)(ta / ctx->prof_napp) : 0.f;
-  if (n_app) *n_app = ctx->prof_napp;
+  tr += ctx->prof_sum_res;
+  ta += ctx->prof_sum_app;
+  const long long nr = ctx->prof_nres + ctx->prof_cnt_res, na = ctx->prof_napp + ctx->prof_cnt_app;
+  if (avg_res) *avg_res = nr ? (float)(tr / nr) : 0.f;
+  if (avg_app) *avg_app = na ? (float)(ta / na) : 0.f;
+  if (n_app) *n_app = (int)na;
   return RAV_OK;
 }
 
@@ -1101,6 +1203,7 @@ rav_status rav_stream_copy(void* stream, double* dst, const double* src, long n)
 rav_status rav_destroy(rav_ctx* ctx) {
   if (!ctx) return RAV_OK;
   (void)hipStreamSynchronize(ctx->stream);
+  rav_drop_graph(ctx);
   if (ctx->learn_free) ctx->learn_free(ctx);
   for (LevelHost& L : ctx->lv) {
     GridDev& h = L.hd;
@@ -1117,6 +1220,8 @@ rav_status rav_destroy(rav_ctx* ctx) {
   (void)hipFree(ctx->d_piv); (void)hipFree(ctx->d_colk); (void)hipFree(ctx->d_norm);
   (void)hipFree(ctx->coarse_tasks);
   if (ctx->h_norm) (void)hipHostFree(ctx->h_norm);
+  for (auto& e : ctx->gprof_res) if (e) (void)hipEventDestroy(e);
+  for (auto& e : ctx->gprof_app) if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->prof_res) if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->prof_app) if (e) (void)hipEventDestroy(e);
   delete ctx;

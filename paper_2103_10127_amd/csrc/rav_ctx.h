@@ -101,6 +101,20 @@ struct rav_ctx {
   // fall back to the scalar omega when a cycle reduces the residual by less than this factor (0 = off)
   double fallback_rho = 0.0;
   int fell_back = 0;
+  // one V-cycle plus the finest residual and its norm, captured from the
+  // stream on the first solve cycle and replayed for the others (RAV_GRAPH=0
+  // disables); dropped whenever parameters, factors or tasks change
+  hipGraphExec_t cycle_exec = nullptr;
+  bool graph_failed = false;
+  // the same cycle captured with the profiling markers of prof_level: its
+  // event pairs are re-recorded by every replay and read after each cycle
+  hipGraphExec_t prof_exec = nullptr;
+  int prof_exec_level = -1;
+  bool prof_capture = false;
+  std::vector<hipEvent_t> gprof_res, gprof_app;   // marker events inside prof_exec
+  int gprof_nres = 0, gprof_napp = 0;
+  double prof_sum_res = 0.0, prof_sum_app = 0.0;  // accumulated from prof_exec replays
+  long long prof_cnt_res = 0, prof_cnt_app = 0;
 };
 
 // Shared helpers (rav_capi.hip).
@@ -108,4 +122,5 @@ rav_status rav_upload_desc(rav_ctx* ctx, rav::LevelHost& L);
 void rav_residual_level(rav_ctx* ctx, int l, bool with_norm);
 void rav_apply_level(rav_ctx* ctx, int l);
 rav_status rav_read_norm(rav_ctx* ctx, double* out);
+void rav_drop_graph(rav_ctx* ctx);   // forget the captured solve cycle
 rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<rav::BlockTask>& logical, rav::BlockTask** out, int* n);
