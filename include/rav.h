@@ -100,7 +100,10 @@ rav_status rav_create(const rav_problem_desc* desc, void* hip_stream, rav_ctx** 
 /* Factors every local system L_i = R_i L R_i^T (Sec. 3) on every smoothed
  * level with partial pivoting in FP64 and stores, for RAV, the owned rows of
  * L_i^{-1} (Sec. 4.3) in the context's precision, for AV/MV the full inverse.
- * RAV_ESINGULAR if a pivot is zero (rav_last_error names level and patch). */
+ * RAV_ESINGULAR if a pivot is zero (rav_last_error names level and patch).
+ * For RAV it then times the lanes-per-patch variants of the apply on every
+ * bucket and keeps the fastest (environment: RAV_AUTOTUNE=0 keeps a size rule,
+ * RAV_AUTOTUNE_LOG=1 prints the timings to stderr). */
 rav_status rav_factor_patches(rav_ctx* ctx);
 
 /* DoF counts of a level: all entries (including masked) and free entries. */
@@ -142,7 +145,10 @@ rav_status rav_vcycle(rav_ctx* ctx, double* x_dev, const double* b_dev);
 /* V-cycles from the given x_dev until ||b - L x||_2 <= rtol ||b - L x_0||_2
  * (Sec. 4: reduction by 1e8) or maxit cycles.  One FP64 norm is read back per
  * cycle.  Returns RAV_OK, RAV_NOT_CONVERGED or RAV_EDIVERGED; *iters and
- * *rel_res (final ||r|| / ||r_0||) are set in every case. */
+ * *rel_res (final ||r|| / ||r_0||) are set in every case.  The cycle is
+ * captured from the context's stream into a HIP graph on first use and
+ * replayed (same launches, same results; RAV_GRAPH=0 in the environment
+ * launches directly); rav_set_params and rav_factor_patches drop it. */
 rav_status rav_solve(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit,
                      int* iters, double* rel_res);
 
