@@ -692,28 +692,53 @@ __global__ __launch_bounds__(BLOCK) void k_residual_tiled2(const GridDev* __rest
   const int x0 = tx * RT_X, y0 = ty * RT_Y;
   const bool last_x = tx == ntx - 1, last_y = ty == nty - 1;
   {
+    // every load of the tile is issued before any is stored (a loop that
+    // stored each value before the next load waited out one memory latency
+    // per element)
     gcdouble* __restrict__ X = gview(gd.x);
     const unsigned nn = (unsigned)g.nn, nV = (unsigned)g.nV, np1 = (unsigned)g.np1;
     const int twoN = 2 * N;
+    constexpr int NXW = 2 * RW_Y * RW_X, XPER = (NXW + BLOCK - 1) / BLOCK;
+    constexpr int NPW = RP_Y * RP_X, PPER = (NPW + BLOCK - 1) / BLOCK;
+    constexpr int NCW = RC_Y * RC_X, CPER = (NCW + BLOCK - 1) / BLOCK;
+    double xv[XPER], pv[PPER], cv[CPER];
 #pragma unroll
-    for (int i = threadIdx.x; i < 2 * RW_Y * RW_X; i += BLOCK) {
+    for (int q = 0; q < XPER; ++q) {
+      const int i = min((int)threadIdx.x + q * BLOCK, NXW - 1);
       const int c = i / (RW_Y * RW_X), rem = i - c * (RW_Y * RW_X);
       const int yy = rem / RW_X, xx = rem - yy * RW_X;
       const unsigned gx = (unsigned)min(max(2 * x0 - 2 + xx, 0), twoN);
       const unsigned gy = (unsigned)min(max(2 * y0 - 2 + yy, 0), twoN);
-      S.xs[c][yy][xx] = ld(X, (unsigned)c * nV + gx + nn * gy);
+      xv[q] = ld(X, (unsigned)c * nV + gx + nn * gy);
     }
 #pragma unroll
-    for (int i = threadIdx.x; i < RP_Y * RP_X; i += BLOCK) {
+    for (int q = 0; q < PPER; ++q) {
+      const int i = min((int)threadIdx.x + q * BLOCK, NPW - 1);
       const int yy = i / RP_X, xx = i - yy * RP_X;
       const unsigned gx = (unsigned)min(max(x0 - 1 + xx, 0), N), gy = (unsigned)min(max(y0 - 1 + yy, 0), N);
-      S.ps[yy][xx] = ld(X, 2u * nV + gx + np1 * gy);
+      pv[q] = ld(X, 2u * nV + gx + np1 * gy);
     }
 #pragma unroll
-    for (int i = threadIdx.x; i < RC_Y * RC_X; i += BLOCK) {
+    for (int q = 0; q < CPER; ++q) {
+      const int i = min((int)threadIdx.x + q * BLOCK, NCW - 1);
       const int yy = i / RC_X, xx = i - yy * RC_X;
       const unsigned gx = (unsigned)min(max(x0 - 1 + xx, 0), N - 1), gy = (unsigned)min(max(y0 - 1 + yy, 0), N - 1);
-      S.cs[yy][xx] = ld(gview(gd.ceta), gx + (unsigned)N * gy);
+      cv[q] = ld(gview(gd.ceta), gx + (unsigned)N * gy);
+    }
+#pragma unroll
+    for (int q = 0; q < XPER; ++q) {
+      const int i = (int)threadIdx.x + q * BLOCK;
+      if (i < NXW) (&S.xs[0][0][0])[i] = xv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < PPER; ++q) {
+      const int i = (int)threadIdx.x + q * BLOCK;
+      if (i < NPW) (&S.ps[0][0])[i] = pv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < CPER; ++q) {
+      const int i = (int)threadIdx.x + q * BLOCK;
+      if (i < NCW) (&S.cs[0][0])[i] = cv[q];
     }
   }
   __syncthreads();
