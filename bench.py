@@ -128,8 +128,8 @@ print(json.dumps(dict(sweep_s=best, n=int(g.n))))
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(no collectives, no sharding of the grid).", file=sys.stderr)
         sys.exit(2)
     if args.workload != "2d-512":
         {"3d-64": bench_3d, "2d-1024": bench_1024, "batch256": bench_batch,
