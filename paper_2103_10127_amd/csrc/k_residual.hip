@@ -1013,18 +1013,19 @@ __device__ __noinline__ double res3_pres_sep(const Tile3Lds& S, const Tile3& tl,
       f[d][o + 2] = d == c ? (lo ? gl : 0.0) + (hi ? gh : 0.0) : (lo ? hl : 0.0) + (hi ? hh : 0.0);
     }
   }
-  const int l[3] = {2 * k[0] - (2 * tl.x0[0] - 2), 2 * k[1] - (2 * tl.x0[1] - 2), 2 * k[2] - (2 * tl.x0[2] - 2)};
+  // window position 2 k + o: l = 2 k - (2 x0 - 2) is even, so o fixes the
+  // parity half and the offsets from l / 2 are compile-time (qoff)
+  const double* __restrict__ xb = S.xs + (k[2] - tl.x0[2] + 1) * QPL + (k[1] - tl.x0[1] + 1) * QR + (k[0] - tl.x0[0] + 1);
   double acc = 0.0;
 #pragma unroll 1
   for (int oz = -2; oz <= 2; ++oz) {
-    const int pz = qperm(l[2] + oz, QE_Z) * QPL;
+    const double* __restrict__ xz = xb + qoff(0, oz, QE_Z) * QPL;
     double az = 0.0;
 #pragma unroll
     for (int oy = -2; oy <= 2; ++oy) {
-      const int py = pz + qperm(l[1] + oy, QE_Y) * QR;
       double ay = 0.0;
 #pragma unroll
-      for (int ox = -2; ox <= 2; ++ox) ay += f[0][ox + 2] * S.xs[py + qperm(l[0] + ox, QE_X)];
+      for (int ox = -2; ox <= 2; ++ox) ay += f[0][ox + 2] * xz[qoff(0, oy, QE_Y) * QR + qoff(0, ox, QE_X)];
       az += f[1][oy + 2] * ay;
     }
     acc += (oz == -2 ? f[2][0] : oz == -1 ? f[2][1] : oz == 0 ? f[2][2] : oz == 1 ? f[2][3] : f[2][4]) * az;
@@ -1214,6 +1215,31 @@ __device__ __forceinline__ double tile3_extras(const GridDev& gd, const Tile3Lds
   return sq;
 }
 
+// Upper-side nodes of a last tile when every upper side it touches is masked:
+// all of them are Dirichlet rows, zero in every component (one pass).
+__device__ __noinline__ void tile3_extras_zero(const GridDev& gd, const Tile3& tl) {
+  const Geo& g = gd.g;
+  const int twoN = 2 * g.N;
+  const int ny = 2 * Q_Y + (tl.last[1] ? 1 : 0), nz = 2 * Q_Z + (tl.last[2] ? 1 : 0);
+  const int n0 = tl.last[0] ? ny * nz : 0, n1 = tl.last[1] ? 2 * Q_X * nz : 0, n2 = tl.last[2] ? 4 * Q_X * Q_Y : 0;
+  gdouble* __restrict__ R = gview(gd.r);
+  for (int i = threadIdx.x; i < n0 + n1 + n2; i += BLOCK) {
+    int ax, ay, az;
+    if (i < n0) {
+      ax = twoN; ay = 2 * tl.x0[1] + i % ny; az = 2 * tl.x0[2] + i / ny;
+    } else if (i < n0 + n1) {
+      const int t = i - n0;
+      ax = 2 * tl.x0[0] + t % (2 * Q_X); ay = twoN; az = 2 * tl.x0[2] + t / (2 * Q_X);
+    } else {
+      const int t = i - n0 - n1;
+      ax = 2 * tl.x0[0] + t % (2 * Q_X); ay = 2 * tl.x0[1] + t / (2 * Q_X); az = twoN;
+    }
+    const long long base = ax + g.nn * (ay + g.nn * (long long)az);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R[c * g.nV + base] = 0.0;
+  }
+}
+
 // Two blocks per CU (LDS bound): at most 256 registers per lane.
 __global__ __launch_bounds__(BLOCK, 2) void k_residual_tiled3(const GridDev* __restrict__ G, double* __restrict__ partials) {
   __shared__ Tile3Lds S;
@@ -1311,7 +1337,12 @@ __global__ __launch_bounds__(BLOCK, 2) void k_residual_tiled3(const GridDev* __r
       case 2: sq += tile3_columns<2>(gd, S, tl, c, lane); break;
       default: sq += tile3_columns<3>(gd, S, tl, c, lane); break;
     }
-    if (tl.last[0] || tl.last[1] || tl.last[2]) {
+    const bool upper_masked = (!tl.last[0] || coord_dirichlet(g, 0, 2 * N)) &&
+                              (!tl.last[1] || coord_dirichlet(g, 1, 2 * N)) &&
+                              (!tl.last[2] || coord_dirichlet(g, 2, 2 * N));
+    if ((tl.last[0] || tl.last[1] || tl.last[2]) && upper_masked) {
+      if (c == 0) tile3_extras_zero(gd, tl);
+    } else if (tl.last[0] || tl.last[1] || tl.last[2]) {
       sq += tile3_extras<0>(gd, S, tl, c);
       sq += tile3_extras<1>(gd, S, tl, c);
       sq += tile3_extras<2>(gd, S, tl, c);
