@@ -457,10 +457,17 @@ __global__ __launch_bounds__(BLOCK) void k_residual3(const GridDev* __restrict__
 // pressure vertices k_d in [x0_d, x0_d + RT_d), plus the last node layer
 // (a_d = 2N, k_d = N) in the last tile of each direction.  The row formulas
 // are those of res_node / res_pres.
+// Window positions in parity-split order: per dimension the even positions l
+// first, then the odd ones, so nodes of one parity sit at consecutive addresses.
+__host__ __device__ constexpr int qperm(int l, int half) { return (l & 1) ? half + (l >> 1) : (l >> 1); }
+// Position of l + o relative to l >> 1 in the permuted order, for l of parity t.
+__host__ __device__ constexpr int qoff(int t, int o, int half) { return (((t + o) & 1) ? half : 0) + ((t + o + 4) >> 1) - 2; }
+
 constexpr int RT_X = 32, RT_Y = 8;
 constexpr int RW_X = 2 * RT_X + 5, RW_Y = 2 * RT_Y + 5;   // velocity window (node a = 2 x0 - 2 + index)
 constexpr int RP_X = RT_X + 3, RP_Y = RT_Y + 3;           // pressure window (vertex k = x0 - 1 + index)
 constexpr int RC_X = RT_X + 2, RC_Y = RT_Y + 2;           // cell window (cell E = x0 - 1 + index)
+constexpr int RE_X = (RW_X + 1) / 2;                       // x positions in parity-split order (evens first)
 
 struct TileLds {
   double xs[2][RW_Y][RW_X];
@@ -538,8 +545,8 @@ __device__ __forceinline__ double res_node_lds(const GridDev& gd, const TileLds&
         if (in) coef += cef[i] * T.A[la * NV + lb];
       }
       coef = fv[0][ox + 2] && fv[1][oy + 2] ? coef : 0.0;
-      acc[0] += coef * S.xs[0][ly + oy][lx + ox];
-      acc[1] += coef * S.xs[1][ly + oy][lx + ox];
+      acc[0] += coef * S.xs[0][ly + oy][(lx >> 1) + qoff(TY & 1, ox, RE_X)];
+      acc[1] += coef * S.xs[1][ly + oy][(lx >> 1) + qoff(TY & 1, ox, RE_X)];
     }
   }
   double accB[2] = {0.0, 0.0};
@@ -655,7 +662,7 @@ __device__ __forceinline__ double res_pres_lds(const GridDev& gd, const TileLds&
           }
           if (in) coef += okc[i] ? T.B[(c * NV + lb) * NP + lk] : 0.0;
         }
-        acc += (fr ? coef : 0.0) * S.xs[c][ly + oy][lx + ox];
+        acc += (fr ? coef : 0.0) * S.xs[c][ly + oy][(lx >> 1) + qoff(0, ox, RE_X)];
       }
     }
   }
@@ -728,7 +735,11 @@ __global__ __launch_bounds__(BLOCK) void k_residual_tiled2(const GridDev* __rest
 #pragma unroll
     for (int q = 0; q < XPER; ++q) {
       const int i = (int)threadIdx.x + q * BLOCK;
-      if (i < NXW) (&S.xs[0][0][0])[i] = xv[q];
+      if (i < NXW) {
+        const int c = i / (RW_Y * RW_X), rem = i - c * (RW_Y * RW_X);
+        const int yy = rem / RW_X, xx = rem - yy * RW_X;
+        S.xs[c][yy][qperm(xx, RE_X)] = xv[q];   // one parity type's nodes contiguous: no bank conflicts
+      }
     }
 #pragma unroll
     for (int q = 0; q < PPER; ++q) {
@@ -787,12 +798,9 @@ constexpr int QC_X = Q_X + 2, QC_Y = Q_Y + 2, QC_Z = Q_Z + 2;             // cel
 constexpr int QE_X = (QW_X + 1) / 2, QE_Y = (QW_Y + 1) / 2, QE_Z = (QW_Z + 1) / 2;
 constexpr int QR = 24, QPL = QW_Y * QR;
 
-__host__ __device__ constexpr int qperm(int l, int half) { return (l & 1) ? half + (l >> 1) : (l >> 1); }
 __device__ __forceinline__ int qidx(int lz, int ly, int lx) {
   return qperm(lz, QE_Z) * QPL + qperm(ly, QE_Y) * QR + qperm(lx, QE_X);
 }
-// Position of l + o relative to l >> 1 in the permuted order, for l of parity t.
-__host__ __device__ constexpr int qoff(int t, int o, int half) { return (((t + o) & 1) ? half : 0) + ((t + o + 4) >> 1) - 2; }
 
 // With all cells around a node present and one coefficient, the assembled
 // viscous row is sum_c (K in dimension c) x (M in the others), K and M the 1D
