@@ -487,6 +487,8 @@ __device__ __forceinline__ double res_node_lds(const GridDev& gd, const TileLds&
   const long long nn = g.nn, nV = g.nV;
   const long long base = a0 + nn * a1;
   gdouble* __restrict__ R = gview(gd.r);
+  // right-hand sides first: their latency overlaps the row's arithmetic
+  const double bv0 = gview(gd.b)[base], bv1 = gview(gd.b)[nV + base];
   if (node_dirichlet(g, a)) {
     R[base] = 0.0;
     R[nV + base] = 0.0;
@@ -603,12 +605,11 @@ __device__ __forceinline__ double res_node_lds(const GridDev& gd, const TileLds&
     }
   }
   const double hB = gd.h;
-  gcdouble* __restrict__ Bv = gview(gd.b);
   double sq = 0.0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const long long gi = c * nV + base;
-    const double r = Bv[gi] - (acc[c] + hB * accB[c]);
+    const double r = (c == 0 ? bv0 : bv1) - (acc[c] + hB * accB[c]);
     R[gi] = r;
     sq += r * r;
   }
@@ -618,6 +619,8 @@ __device__ __forceinline__ double res_node_lds(const GridDev& gd, const TileLds&
 __device__ __forceinline__ double res_pres_lds(const GridDev& gd, const TileLds& S, int x0, int y0, int k0, int k1) {
   constexpr int NV = 9, NP = 4;
   const Geo& g = gd.g;
+  const long long gi = 2 * g.nV + k0 + g.np1 * k1;
+  const double bv = gview(gd.b)[gi];   // issued first
   const Tabs<2>& T = tabs<2>();
   const int N = g.N;
   const int k[2] = {k0, k1};
@@ -666,8 +669,7 @@ __device__ __forceinline__ double res_pres_lds(const GridDev& gd, const TileLds&
       }
     }
   }
-  const long long gi = 2 * g.nV + k0 + g.np1 * k1;
-  const double r = gview(gd.b)[gi] - gd.h * acc;
+  const double r = bv - gd.h * acc;
   gview(gd.r)[gi] = r;
   return r * r;
 }
