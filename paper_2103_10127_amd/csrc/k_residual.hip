@@ -133,6 +133,9 @@ __device__ __forceinline__ double res_node(const GridDev& gd, long long row) {
   int a[3] = {0, 0, 0};
   vel_row_node(g, TY, row, a);
   const long long base = node_lin(g, a);
+  double bv[DIM];   // right-hand sides first: their latency overlaps the row's arithmetic
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) bv[c] = gview(gd.b)[c * g.nV + base];
   if (node_dirichlet(g, a)) {
 #pragma unroll
     for (int c = 0; c < DIM; ++c) R[c * g.nV + base] = 0.0;
@@ -294,12 +297,11 @@ __device__ __forceinline__ double res_node(const GridDev& gd, long long row) {
     }
   }
   const double hB = DIM == 2 ? gd.h : gd.h * gd.h;
-  gcdouble* __restrict__ Bv = gview(gd.b);
   double sq = 0.0;
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
     const long long gi = c * nV + base;
-    const double r = Bv[gi] - (acc[c] + hB * accB[c]);
+    const double r = bv[c] - (acc[c] + hB * accB[c]);
     R[gi] = r;
     sq += r * r;
   }
@@ -320,6 +322,7 @@ __device__ __forceinline__ double res_pres(const GridDev& gd, long long row) {
   vert_of(g, row, k);
   const int N = g.N;
   const long long nn = g.nn, nV = g.nV;
+  const double bv = gview(gd.b)[DIM * nV + row];   // issued first
   bool okc[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
@@ -380,7 +383,7 @@ __device__ __forceinline__ double res_pres(const GridDev& gd, long long row) {
   }
   const double hB = DIM == 2 ? gd.h : gd.h * gd.h;
   const long long gi = DIM * nV + row;
-  const double r = gview(gd.b)[gi] - hB * acc;
+  const double r = bv - hB * acc;
   gview(gd.r)[gi] = r;
   return r * r;
 }
