@@ -202,6 +202,21 @@ __device__ __forceinline__ void rav_apply_body(const GridDev* __restrict__ G, co
   typedef __attribute__((address_space(1))) const vec_t gcvec;
   gcvec* __restrict__ W = (gcvec*)bk.W + w_vec(bk, p, 0);
   const long long cs = bk.count_pad;   // chunk stride in vectors (chunk-major layout)
+  // Patches with few owned rows read their x entries and weight up front: no
+  // other patch writes them, and the update at the end then waits on nothing.
+  constexpr bool XPRE = NOWN <= 12;
+  gdouble* __restrict__ x = (gdouble*)gd.x;
+  int xi[XPRE ? NOWN : 1];   // level vectors hold fewer than 2^28 entries
+  double xo[XPRE ? NOWN : 1];
+  double om = 0.0;
+  if constexpr (XPRE) {
+#pragma unroll
+    for (int j = 0; j < NOWN; ++j) {
+      xi[j] = (int)own_index<DIM, KIND>(cm, k, bucket_own_local(DIM, KIND, CLS, j));
+      xo[j] = (xi[j] >= 0 && (SPLIT == 1 || (j % SPLIT) == sl)) ? x[xi[j]] : 0.0;
+    }
+    om = gd.omega_patch ? (double)gd.omega_patch[patch_lin(g, KIND, k)] : gd.omega;
+  }
   acc_t acc[NOWN];
 #pragma unroll
   for (int j = 0; j < NOWN; ++j) acc[j] = acc_t(0);
@@ -241,13 +256,20 @@ __device__ __forceinline__ void rav_apply_body(const GridDev* __restrict__ G, co
       for (int o = SPLIT / 2; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o, SPLIT);
     }
   }
-  const double om = gd.omega_patch ? (double)gd.omega_patch[patch_lin(g, KIND, k)] : gd.omega;
-  gdouble* __restrict__ x = (gdouble*)gd.x;
+  if constexpr (XPRE) {
 #pragma unroll
-  for (int j = 0; j < NOWN; ++j) {
-    if (SPLIT > 1 && (j % SPLIT) != sl) continue;
-    const long long gi = own_index<DIM, KIND>(cm, k, bucket_own_local(DIM, KIND, CLS, j));
-    if (gi >= 0) x[gi] += om * (double)acc[j];
+    for (int j = 0; j < NOWN; ++j) {
+      if (SPLIT > 1 && (j % SPLIT) != sl) continue;
+      if (xi[j] >= 0) x[xi[j]] = xo[j] + om * (double)acc[j];
+    }
+  } else {
+    om = gd.omega_patch ? (double)gd.omega_patch[patch_lin(g, KIND, k)] : gd.omega;
+#pragma unroll
+    for (int j = 0; j < NOWN; ++j) {
+      if (SPLIT > 1 && (j % SPLIT) != sl) continue;
+      const long long gi = own_index<DIM, KIND>(cm, k, bucket_own_local(DIM, KIND, CLS, j));
+      if (gi >= 0) x[gi] += om * (double)acc[j];
+    }
   }
 }
 
