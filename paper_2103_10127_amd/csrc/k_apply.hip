@@ -344,10 +344,36 @@ __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_rows(const GridDe
   rav_apply_rows_body<DIM, KIND, WT>(G, tasks[blockIdx.x]);
 }
 
-// The boundary buckets of a level in one launch: each block runs the variant
-// its task names (pad = APPLY_SPLIT or APPLY_ROWS, both 256-thread blocks) for
-// its bucket's class.  Separate launches of these small, latency-bound buckets
+// The boundary buckets of a level in one launch of 256-thread blocks: each
+// block runs the variant its task names (pad = 4 or APPLY_SPLIT lanes per
+// patch, or APPLY_ROWS) for its bucket's class.  Separate launches of these small, latency-bound buckets
 // ran one after another with a launch gap each.
+template <int DIM, int KIND, typename WT, int SPLIT>
+__device__ __forceinline__ void multi_body(const GridDev* __restrict__ G, const BlockTask t) {
+  const int cls = G[t.grid].bk[t.part].cls;
+  if constexpr (DIM == 3 && KIND == KIND_ELEMENT) {
+    switch (cls) {
+      case 0: rav_apply_body<3, KIND_ELEMENT, 0, WT, SPLIT>(G, t); break;
+      case 1: rav_apply_body<3, KIND_ELEMENT, 1, WT, SPLIT>(G, t); break;
+      case 2: rav_apply_body<3, KIND_ELEMENT, 2, WT, SPLIT>(G, t); break;
+      case 3: rav_apply_body<3, KIND_ELEMENT, 3, WT, SPLIT>(G, t); break;
+      case 4: rav_apply_body<3, KIND_ELEMENT, 4, WT, SPLIT>(G, t); break;
+      case 5: rav_apply_body<3, KIND_ELEMENT, 5, WT, SPLIT>(G, t); break;
+      case 6: rav_apply_body<3, KIND_ELEMENT, 6, WT, SPLIT>(G, t); break;
+      default: rav_apply_body<3, KIND_ELEMENT, 7, WT, SPLIT>(G, t); break;
+    }
+  } else if constexpr (KIND == KIND_ELEMENT) {
+    switch (cls) {
+      case 0: rav_apply_body<2, KIND_ELEMENT, 0, WT, SPLIT>(G, t); break;
+      case 1: rav_apply_body<2, KIND_ELEMENT, 1, WT, SPLIT>(G, t); break;
+      case 2: rav_apply_body<2, KIND_ELEMENT, 2, WT, SPLIT>(G, t); break;
+      default: rav_apply_body<2, KIND_ELEMENT, 3, WT, SPLIT>(G, t); break;
+    }
+  } else {
+    rav_apply_body<DIM, KIND, 0, WT, SPLIT>(G, t);
+  }
+}
+
 template <int DIM, int KIND, typename WT>
 __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_multi(const GridDev* __restrict__ G,
                                                                     const BlockTask* __restrict__ tasks) {
@@ -357,28 +383,8 @@ __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_multi(const GridD
     rav_apply_rows_body<DIM, KIND, WT>(G, t);
     return;
   }
-  const int cls = G[t.grid].bk[t.part].cls;
-  if constexpr (DIM == 3 && KIND == KIND_ELEMENT) {
-    switch (cls) {
-      case 0: rav_apply_body<3, KIND_ELEMENT, 0, WT, APPLY_SPLIT>(G, t); break;
-      case 1: rav_apply_body<3, KIND_ELEMENT, 1, WT, APPLY_SPLIT>(G, t); break;
-      case 2: rav_apply_body<3, KIND_ELEMENT, 2, WT, APPLY_SPLIT>(G, t); break;
-      case 3: rav_apply_body<3, KIND_ELEMENT, 3, WT, APPLY_SPLIT>(G, t); break;
-      case 4: rav_apply_body<3, KIND_ELEMENT, 4, WT, APPLY_SPLIT>(G, t); break;
-      case 5: rav_apply_body<3, KIND_ELEMENT, 5, WT, APPLY_SPLIT>(G, t); break;
-      case 6: rav_apply_body<3, KIND_ELEMENT, 6, WT, APPLY_SPLIT>(G, t); break;
-      default: rav_apply_body<3, KIND_ELEMENT, 7, WT, APPLY_SPLIT>(G, t); break;
-    }
-  } else if constexpr (KIND == KIND_ELEMENT) {
-    switch (cls) {
-      case 0: rav_apply_body<2, KIND_ELEMENT, 0, WT, APPLY_SPLIT>(G, t); break;
-      case 1: rav_apply_body<2, KIND_ELEMENT, 1, WT, APPLY_SPLIT>(G, t); break;
-      case 2: rav_apply_body<2, KIND_ELEMENT, 2, WT, APPLY_SPLIT>(G, t); break;
-      default: rav_apply_body<2, KIND_ELEMENT, 3, WT, APPLY_SPLIT>(G, t); break;
-    }
-  } else {
-    rav_apply_body<DIM, KIND, 0, WT, APPLY_SPLIT>(G, t);
-  }
+  if (t.pad == 4) multi_body<DIM, KIND, WT, 4>(G, t);
+  else multi_body<DIM, KIND, WT, APPLY_SPLIT>(G, t);
 }
 
 void launch_rav_apply_multi(int dim, int kind, int prec, const GridDev* G, const BlockTask* tasks, int ntasks,

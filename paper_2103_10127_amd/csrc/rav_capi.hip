@@ -632,9 +632,9 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
 // three launches after one warm-up, on the level's own vectors, which every
 // solve overwrites) and the fastest is kept.  RAV_AUTOTUNE=0 keeps the
 // size-based choice.
-// Buckets of a level that run 256-thread blocks (APPLY_SPLIT lanes per patch
-// or the row-parallel variant) go into one merged launch when there are at
-// least two of them: the 3D boundary buckets (faces, edges, corner) are small
+// Buckets of a level on the 4- or APPLY_SPLIT-lanes-per-patch or the
+// row-parallel variant go into one merged launch of 256-thread blocks when
+// there are at least two of them: the 3D boundary buckets (faces, edges, corner) are small
 // and latency-bound, and separate launches serialize their tails.
 static rav_status merge_apply(rav_ctx* ctx) {
   for (size_t l = 1; l < ctx->lv.size(); ++l) {
@@ -642,12 +642,13 @@ static rav_status merge_apply(rav_ctx* ctx) {
     std::vector<BlockTask> mt;
     int nb = 0;
     for (ApplyLaunch& al : L.apply) al.merged = false;
-    for (const ApplyLaunch& al : L.apply) nb += (al.split == APPLY_SPLIT || al.split == APPLY_ROWS) ? 1 : 0;
+    auto mergeable = [](int split) { return split == 4 || split == APPLY_SPLIT || split == APPLY_ROWS; };
+    for (const ApplyLaunch& al : L.apply) nb += mergeable(al.split) ? 1 : 0;
     if (nb < 2) continue;
     for (ApplyLaunch& al : L.apply) {
-      if (al.split != APPLY_SPLIT && al.split != APPLY_ROWS) continue;
+      if (!mergeable(al.split)) continue;
       const long long cnt = L.hd.bk[al.bucket].count;
-      const int per_block = apply_block(al.split) / (al.split == APPLY_ROWS ? 64 : al.split);
+      const int per_block = APPLY_BLOCK_MAX / (al.split == APPLY_ROWS ? 64 : al.split);
       for (long long p0 = 0; p0 < cnt; p0 += per_block) {
         BlockTask t{};
         t.grid = 0; t.part = al.bucket; t.start = p0; t.logical = (int)mt.size(); t.pad = al.split;
