@@ -348,7 +348,11 @@ __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_rows(const GridDe
 // block runs the variant its task names (pad = 4 or APPLY_SPLIT lanes per
 // patch, or APPLY_ROWS) for its bucket's class.  Separate launches of these small, latency-bound buckets
 // ran one after another with a launch gap each.
-template <int DIM, int KIND, typename WT, int SPLIT>
+// EDGES = false leaves out the column-group bodies of the 3D edge and corner
+// classes (3, 5, 6, 7: up to 28 owned rows), whose registers would set the
+// whole launch's occupancy; the host then sends no column-group task of those
+// classes (their buckets, at most N - 1 patches, go row-parallel up to N = 65).
+template <int DIM, int KIND, typename WT, int SPLIT, bool EDGES>
 __device__ __forceinline__ void multi_body(const GridDev* __restrict__ G, const BlockTask t) {
   const int cls = G[t.grid].bk[t.part].cls;
   if constexpr (DIM == 3 && KIND == KIND_ELEMENT) {
@@ -356,11 +360,17 @@ __device__ __forceinline__ void multi_body(const GridDev* __restrict__ G, const 
       case 0: rav_apply_body<3, KIND_ELEMENT, 0, WT, SPLIT>(G, t); break;
       case 1: rav_apply_body<3, KIND_ELEMENT, 1, WT, SPLIT>(G, t); break;
       case 2: rav_apply_body<3, KIND_ELEMENT, 2, WT, SPLIT>(G, t); break;
-      case 3: rav_apply_body<3, KIND_ELEMENT, 3, WT, SPLIT>(G, t); break;
       case 4: rav_apply_body<3, KIND_ELEMENT, 4, WT, SPLIT>(G, t); break;
-      case 5: rav_apply_body<3, KIND_ELEMENT, 5, WT, SPLIT>(G, t); break;
-      case 6: rav_apply_body<3, KIND_ELEMENT, 6, WT, SPLIT>(G, t); break;
-      default: rav_apply_body<3, KIND_ELEMENT, 7, WT, SPLIT>(G, t); break;
+      default:
+        if constexpr (EDGES) {
+          switch (cls) {
+            case 3: rav_apply_body<3, KIND_ELEMENT, 3, WT, SPLIT>(G, t); break;
+            case 5: rav_apply_body<3, KIND_ELEMENT, 5, WT, SPLIT>(G, t); break;
+            case 6: rav_apply_body<3, KIND_ELEMENT, 6, WT, SPLIT>(G, t); break;
+            default: rav_apply_body<3, KIND_ELEMENT, 7, WT, SPLIT>(G, t); break;
+          }
+        }
+        break;
     }
   } else if constexpr (KIND == KIND_ELEMENT) {
     switch (cls) {
@@ -374,7 +384,7 @@ __device__ __forceinline__ void multi_body(const GridDev* __restrict__ G, const 
   }
 }
 
-template <int DIM, int KIND, typename WT>
+template <int DIM, int KIND, typename WT, bool EDGES>
 __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_multi(const GridDev* __restrict__ G,
                                                                     const BlockTask* __restrict__ tasks) {
   const BlockTask t = tasks[blockIdx.x];
@@ -383,24 +393,25 @@ __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_multi(const GridD
     rav_apply_rows_body<DIM, KIND, WT>(G, t);
     return;
   }
-  if (t.pad == 4) multi_body<DIM, KIND, WT, 4>(G, t);
-  else multi_body<DIM, KIND, WT, APPLY_SPLIT>(G, t);
+  if (t.pad == 4) multi_body<DIM, KIND, WT, 4, EDGES>(G, t);
+  else multi_body<DIM, KIND, WT, APPLY_SPLIT, EDGES>(G, t);
 }
 
-void launch_rav_apply_multi(int dim, int kind, int prec, const GridDev* G, const BlockTask* tasks, int ntasks,
-                            hipStream_t s) {
-#define RAV_MULTI(D, K)                                                                                      \
+void launch_rav_apply_multi(int dim, int kind, int prec, bool edges, const GridDev* G, const BlockTask* tasks,
+                            int ntasks, hipStream_t s) {
+#define RAV_MULTI(D, K, E)                                                                                   \
   do {                                                                                                       \
     if (prec == P_FP64)                                                                                      \
-      hipLaunchKernelGGL((k_rav_apply_multi<D, K, double>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks); \
+      hipLaunchKernelGGL((k_rav_apply_multi<D, K, double, E>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks); \
     else if (prec == P_FP32)                                                                                 \
-      hipLaunchKernelGGL((k_rav_apply_multi<D, K, float>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks);  \
+      hipLaunchKernelGGL((k_rav_apply_multi<D, K, float, E>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks);  \
     else                                                                                                     \
-      hipLaunchKernelGGL((k_rav_apply_multi<D, K, bf16_t>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks); \
+      hipLaunchKernelGGL((k_rav_apply_multi<D, K, bf16_t, E>), dim3(ntasks), dim3(APPLY_BLOCK_MAX), 0, s, G, tasks); \
   } while (0)
-  if (dim == 2 && kind == KIND_VERTEX) RAV_MULTI(2, KIND_VERTEX);
-  else if (dim == 2) RAV_MULTI(2, KIND_ELEMENT);
-  else RAV_MULTI(3, KIND_ELEMENT);
+  if (dim == 2 && kind == KIND_VERTEX) RAV_MULTI(2, KIND_VERTEX, true);
+  else if (dim == 2) RAV_MULTI(2, KIND_ELEMENT, true);
+  else if (edges) RAV_MULTI(3, KIND_ELEMENT, true);
+  else RAV_MULTI(3, KIND_ELEMENT, false);
 #undef RAV_MULTI
 }
 

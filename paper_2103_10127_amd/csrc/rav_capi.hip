@@ -379,7 +379,8 @@ void rav_apply_level(rav_ctx* ctx, int l) {
     for (const ApplyLaunch& al : L.apply)
       if (!al.merged)
         launch_rav_apply(D.dim, D.patch, al.cls, ctx->prec, al.split, L.dd, al.tasks, al.ntasks, ctx->stream);
-    if (L.n_multi > 0) launch_rav_apply_multi(D.dim, D.patch, ctx->prec, L.dd, L.multi_tasks, L.n_multi, ctx->stream);
+    if (L.n_multi > 0)
+      launch_rav_apply_multi(D.dim, D.patch, ctx->prec, L.multi_edges, L.dd, L.multi_tasks, L.n_multi, ctx->stream);
   } else if (D.smoother == RAV_SMOOTHER_AV) {
     launch_av_apply(D.dim, D.patch, L.dd, L.npatch, ctx->stream);
     launch_av_gather(D.dim, D.patch, L.dd, L.hd.g.n, ctx->stream);
@@ -641,6 +642,7 @@ static rav_status merge_apply(rav_ctx* ctx) {
     LevelHost& L = ctx->lv[l];
     std::vector<BlockTask> mt;
     int nb = 0;
+    L.multi_edges = false;
     for (ApplyLaunch& al : L.apply) al.merged = false;
     auto mergeable = [](int split) { return split == 4 || split == APPLY_SPLIT || split == APPLY_ROWS; };
     for (const ApplyLaunch& al : L.apply) nb += mergeable(al.split) ? 1 : 0;
@@ -655,6 +657,8 @@ static rav_status merge_apply(rav_ctx* ctx) {
         mt.push_back(t);
       }
       al.merged = true;
+      const int cls = L.hd.bk[al.bucket].cls;
+      if (ctx->desc.dim == 3 && al.split != APPLY_ROWS && (cls == 3 || cls >= 5)) L.multi_edges = true;
     }
     (void)hipFree(L.multi_tasks);
     L.multi_tasks = nullptr;

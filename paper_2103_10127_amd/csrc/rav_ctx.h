@@ -48,6 +48,7 @@ struct LevelHost {
   std::vector<ApplyLaunch> apply;
   BlockTask* multi_tasks = nullptr;   // merged launch of the buckets marked merged
   int n_multi = 0;
+  bool multi_edges = false;           // it holds column-group tasks of 3D edge or corner classes
   long long npatch = 0;
   BlockTask* rtasks = nullptr;   // restriction: node-type tiles over the coarser level
   int n_rtasks = 0;

@@ -131,9 +131,10 @@ void launch_norm_finalize(const double* partials, int first, int count, double* 
 void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const GridDev* G, const BlockTask* tasks,
                       int ntasks, hipStream_t s);
 // Several buckets of one level in one launch (tasks carry the variant in pad:
-// APPLY_SPLIT or APPLY_ROWS).
-void launch_rav_apply_multi(int dim, int kind, int prec, const GridDev* G, const BlockTask* tasks, int ntasks,
-                            hipStream_t s);
+// 4, APPLY_SPLIT or APPLY_ROWS).  edges: some task runs a 3D edge or corner
+// class (3, 5, 6, 7) on a column-group variant.
+void launch_rav_apply_multi(int dim, int kind, int prec, bool edges, const GridDev* G, const BlockTask* tasks,
+                            int ntasks, hipStream_t s);
 void launch_factor(int dim, int kind, int cls, int prec, int full, const GridDev* G, long long count,
                    int bucket, int* status, hipStream_t s);
 void launch_av_apply(int dim, int kind, const GridDev* G, long long npatch, hipStream_t s);
