@@ -351,7 +351,7 @@ static bool prof_mark(rav_ctx* ctx, int l, std::vector<hipEvent_t>& ev, int& n, 
     if (start) {
       while ((int)gev.size() < 2 * (gn + 1)) {
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return false;
         gev.push_back(e);
       }
       (void)hipEventRecord(gev[2 * gn], ctx->stream);
@@ -1165,8 +1165,10 @@ rav_status rav_profile_begin(rav_ctx* ctx, int level, int max_launches) {
   for (auto& e : ctx->prof_app) (void)hipEventDestroy(e);
   ctx->prof_res.assign(2 * (size_t)max_launches, nullptr);
   ctx->prof_app.assign(2 * (size_t)max_launches, nullptr);
-  for (auto& e : ctx->prof_res) CK(hipEventCreate(&e));
-  for (auto& e : ctx->prof_app) CK(hipEventCreate(&e));
+  // timing markers only: no system-scope fence (the host reads them after a
+  // stream synchronisation, which orders everything before it)
+  for (auto& e : ctx->prof_res) CK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+  for (auto& e : ctx->prof_app) CK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   ctx->prof_max = max_launches;
   ctx->prof_nres = ctx->prof_napp = 0;
   ctx->prof_sum_res = ctx->prof_sum_app = 0.0;
