@@ -7,9 +7,12 @@
 
 namespace rav {
 
-// Deterministic sum of partials[first .. first+count) into out[0].
+// Deterministic sum of partials[first .. first+count) into out[0], and into
+// host_out[0] (pinned host memory the host reads after a stream
+// synchronisation, which spares a copy) when host_out is not null.
 __global__ __launch_bounds__(256) void k_norm_finalize(const double* __restrict__ partials, int first,
-                                                        int count, double* __restrict__ out) {
+                                                        int count, double* __restrict__ out,
+                                                        double* __restrict__ host_out) {
   __shared__ double red[256];
   double s = 0.0;
   for (int i = threadIdx.x; i < count; i += 256) s += partials[first + i];
@@ -19,7 +22,10 @@ __global__ __launch_bounds__(256) void k_norm_finalize(const double* __restrict_
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    if (host_out) host_out[0] = red[0];
+  }
 }
 
 // One block per problem: out[g] = sum of partials[first[g] .. first[g] + count[g]).
@@ -87,8 +93,9 @@ void launch_copy_batch(double* const* dst, const double* const* src, const long 
   hipLaunchKernelGGL(k_copy_batch, dim3(ntasks), dim3(256), 0, s, dst, src, n, tasks);
 }
 
-void launch_norm_finalize(const double* partials, int first, int count, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, partials, first, count, out);
+void launch_norm_finalize(const double* partials, int first, int count, double* out, double* host_out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, s, partials, first, count, out, host_out);
 }
 
 static inline unsigned grid_for(long long n) {

@@ -335,11 +335,12 @@ void rav_residual_level(rav_ctx* ctx, int l, bool with_norm) {
   const int N = L.hd.g.N;
   if (residual_tiled_ok(ctx->desc.dim, N)) {
     launch_residual_tiled(ctx->desc.dim, L.dd, N, with_norm ? L.partials : nullptr, ctx->stream);
-    if (with_norm) launch_norm_finalize(L.partials, 0, residual_tiles(ctx->desc.dim, N), ctx->d_norm, ctx->stream);
+    if (with_norm) launch_norm_finalize(L.partials, 0, residual_tiles(ctx->desc.dim, N), ctx->d_norm, ctx->h_norm_dev,
+                                         ctx->stream);
     return;
   }
   launch_residual(ctx->desc.dim, L.dd, L.res_tasks, L.n_res_tasks, with_norm ? L.partials : nullptr, ctx->stream);
-  if (with_norm) launch_norm_finalize(L.partials, 0, L.n_res_tiles, ctx->d_norm, ctx->stream);
+  if (with_norm) launch_norm_finalize(L.partials, 0, L.n_res_tiles, ctx->d_norm, ctx->h_norm_dev, ctx->stream);
 }
 
 static bool prof_mark(rav_ctx* ctx, int l, std::vector<hipEvent_t>& ev, int& n, bool start) {
@@ -525,7 +526,7 @@ static void collect_graph_profile(rav_ctx* ctx) {
 }
 
 rav_status rav_read_norm(rav_ctx* ctx, double* out) {
-  CK(hipMemcpyAsync(ctx->h_norm, ctx->d_norm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  // the norm kernel also wrote the value into pinned host memory
   CK(hipStreamSynchronize(ctx->stream));
   *out = std::sqrt(*ctx->h_norm);
   return RAV_OK;
@@ -594,6 +595,8 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
     e = hipMalloc((void**)&ctx->d_norm, sizeof(double));
     if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
     e = hipHostMalloc((void**)&ctx->h_norm, sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
+    e = hipHostGetDevicePointer((void**)&ctx->h_norm_dev, ctx->h_norm, 0);
     if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
     std::vector<double> inc(4 * std::max(d->n_incl, 1), 0.0);
     for (int i = 0; i < d->n_incl; ++i) {

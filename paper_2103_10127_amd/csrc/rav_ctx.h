@@ -84,7 +84,8 @@ struct rav_ctx {
   int* d_piv = nullptr;
   double* d_colk = nullptr;
   double* d_norm = nullptr;
-  double* h_norm = nullptr;   // pinned
+  double* h_norm = nullptr;       // pinned; the norm kernel writes it through h_norm_dev
+  double* h_norm_dev = nullptr;
   int factored = 0;
   int prec = rav::P_FP64;
   long long split_below = rav::SPLIT_BELOW;

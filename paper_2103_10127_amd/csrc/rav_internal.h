@@ -127,7 +127,8 @@ int residual_tiles(int dim, int N);
 void launch_residual_tiled(int dim, const GridDev* G, int N, double* partials, hipStream_t s);
 void launch_cell_coef(int dim, long long ncell, const GridDev* G, const double* etaq, const int* cut_idx,
                       const int* cut_cells, int ncut, double* ceta, double* cutA, hipStream_t s);
-void launch_norm_finalize(const double* partials, int first, int count, double* out, hipStream_t s);
+void launch_norm_finalize(const double* partials, int first, int count, double* out, double* host_out,
+                          hipStream_t s);
 void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const GridDev* G, const BlockTask* tasks,
                       int ntasks, hipStream_t s);
 // Several buckets of one level in one launch (tasks carry the variant in pad:

@@ -215,7 +215,7 @@ static rav_status ensure_twogrid(rav_ctx* ctx, int nu) {
 static double residual_sq(rav_ctx* ctx, GridDev* D, rav_status* st) {
   LevelHost& L = ctx->lv[1];
   launch_residual(2, D, L.res_tasks, L.n_res_tasks, L.partials, ctx->stream);
-  launch_norm_finalize(L.partials, 0, L.n_res_tiles, ctx->d_norm, ctx->stream);
+  launch_norm_finalize(L.partials, 0, L.n_res_tiles, ctx->d_norm, ctx->h_norm_dev, ctx->stream);
   double v = 0.0;
   *st = rav_read_norm(ctx, &v);
   return v * v;
