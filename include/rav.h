@@ -213,7 +213,8 @@ rav_status rav_time_sweep(rav_ctx* ctx, int level, int reps, double* x_dev, cons
 
 /* Kernel timing during ordinary calls: after rav_profile_begin, every smoother
  * residual launch and patch-apply launch on `level` (up to max_launches of
- * each) is bracketed by HIP events recorded on the context stream.
+ * each) is bracketed by HIP events recorded on the context stream (timing-only
+ * events without a system-scope cache fence, so they add little to the run).
  * rav_profile_end synchronises, stops recording and returns the average
  * duration in ms of the residual launches, of the apply launches (all buckets
  * of one sweep count as one launch) and how many apply launches were timed. */
