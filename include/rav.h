@@ -87,10 +87,11 @@ typedef struct {
 typedef struct rav_ctx rav_ctx;
 
 /* Builds the level hierarchy (Sec. 2): grids, DoF numbering, Dirichlet masks,
- * patch buckets, the rediscretised operator of every level ("assembled on all
- * grids", Sec. 4) in FP64, and the coarse direct solver (Sec. 2: LU to machine
- * accuracy).  With Dirichlet velocity on every side the coarse solve uses the
- * bordered system [[L_0, e],[e^T, 0]], e = (0, 1_p), i.e. zero-mean pressure.
+ * patch buckets, the rediscretised operator of every level (Sec. 4 assembles
+ * the system anew on each grid) in FP64, and the coarse direct solver (Sec. 2:
+ * an LU solve, exact up to rounding).  With Dirichlet velocity on every side
+ * the coarse solve uses the bordered system [[L_0, e],[e^T, 0]], e = (0, 1_p),
+ * i.e. zero-mean pressure.
  * hip_stream: a hipStream_t or NULL.  On success *out owns all device memory.
  * RAV_EINVAL (before any device work) also when the coarsest grid has more than
  * 16383 DoFs: its dense inverse would exceed 2 GB (2D up to 32x32, 3D up to
@@ -152,8 +153,8 @@ rav_status rav_vcycle(rav_ctx* ctx, double* x_dev, const double* b_dev);
 rav_status rav_solve(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit,
                      int* iters, double* rel_res);
 
-/* Krylov acceleration (Sec. 4 notes multigrid "can also be used as a
- * preconditioner in a Krylov subspace solver"): restarted flexible GMRES(restart),
+/* Krylov acceleration (Sec. 4 remarks that the multigrid cycle may equally
+ * serve as the preconditioner of a Krylov method): restarted flexible GMRES(restart),
  * right-preconditioned by one V(nu_pre, nu_post) cycle from a zero guess.
  * maxit bounds the number of preconditioner applications (V-cycles); stops
  * when the true residual ||b - L x||_2 <= rtol ||b - L x_0||_2.  Allocates
@@ -173,8 +174,9 @@ rav_status rav_set_patch_omega(rav_ctx* ctx, int level, const float* omega_dev);
 /* Fallback for per-patch weights: during rav_solve, if a cycle reduces the
  * residual by a factor worse than rho_max (||r_k|| > rho_max ||r_{k-1}||)
  * while per-patch weights are set, they are dropped and the solve continues
- * with the scalar omega.  rho_max = 0 disables it.  *fell_back (may be NULL)
- * reports whether the previous rav_solve fell back. */
+ * with the scalar omega.  The weights are set again before rav_solve returns,
+ * so the next solve starts with them.  rho_max = 0 disables it.  *fell_back
+ * (may be NULL) reports whether the previous rav_solve fell back. */
 rav_status rav_set_fallback(rav_ctx* ctx, double rho_max, int* fell_back);
 
 /* Host-side patch map of patch `patch` on `level`: its free DoFs in local

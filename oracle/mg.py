@@ -1,7 +1,7 @@
 """Geometric multigrid V-cycle with Vanka smoothing (Sec. 2, Fig. 1; Sec. 4).
 
 Levels 0 (coarsest) .. L-1 (finest), N_l = N / 2^(L-1-l).  Every level is
-rediscretised ("the system of equations is assembled on all grids", Sec. 4).
+rediscretised (Sec. 4 assembles the system anew on every grid).
 V(nu, nu): nu smoothing sweeps, restrict the residual with P^T, recurse from a
 zero coarse iterate, add the prolongated correction, nu smoothing sweeps.
 The coarsest level is solved directly by LU (Sec. 2).

@@ -8,9 +8,10 @@ its 2^d pressure vertices.
 Local order: component-major, then lexicographic over nodes (x fastest), then
 the pressure DoF(s).  L_i = R_i L R_i^T is the principal submatrix (Sec. 3).
 
-Owned set of RAV (the rows kept by the modified prolongation of eq. 13).  The
-paper keeps "the pressure DoF and the velocity DoFs on the pressure node",
-which partitions the DoFs only when velocity lives on vertices (Q1-Q1).  For
+Owned set of RAV (the rows kept by the modified prolongation of eq. 13).  In
+Sec. 3 a patch keeps its own pressure unknown together with the velocity
+unknowns located at that same vertex; this partitions the DoFs only when
+velocity lives on vertices (Q1-Q1).  For
 Q2/Q1 this oracle uses the floor rule, which agrees with the paper's rule on
 vertex nodes and also assigns edge/face/cell nodes so that sum_i G_i = I:
 * vertex patches: velocity node a is owned by vertex floor(a/2); pressure k by k;

@@ -283,16 +283,18 @@ __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply(const GridDev* __
 // accumulates owned rows j and j + 64 over the patch columns.  The column loop
 // is wave-uniform (the r value of a column is one broadcast load), so the
 // per-lane state is two accumulators however many rows the bucket owns.
-template <typename WT> __device__ __forceinline__ double w_elem(const WT* W, long long i);
+// Arithmetic as in the column-group kernel: FP64 for FP64 rows, FP32 products
+// and accumulation (r rounded to FP32) for FP32 and BF16 rows.
+template <typename WT> __device__ __forceinline__ typename WTraits<WT>::acc_t w_elem(const WT* W, long long i);
 template <> __device__ __forceinline__ double w_elem<double>(const double* W, long long i) {
   return ((gcdouble*)W)[i];
 }
-template <> __device__ __forceinline__ double w_elem<float>(const float* W, long long i) {
-  return (double)((__attribute__((address_space(1))) const float*)W)[i];
+template <> __device__ __forceinline__ float w_elem<float>(const float* W, long long i) {
+  return ((__attribute__((address_space(1))) const float*)W)[i];
 }
-template <> __device__ __forceinline__ double w_elem<bf16_t>(const bf16_t* W, long long i) {
+template <> __device__ __forceinline__ float w_elem<bf16_t>(const bf16_t* W, long long i) {
   const unsigned short u = ((__attribute__((address_space(1))) const unsigned short*)W)[i];
-  return (double)__uint_as_float((unsigned)u << 16);
+  return __uint_as_float((unsigned)u << 16);
 }
 
 template <int DIM, int KIND, typename WT>
@@ -314,17 +316,18 @@ __device__ __forceinline__ void rav_apply_rows_body(const GridDev* __restrict__ 
   const WT* __restrict__ W = reinterpret_cast<const WT*>(bk.W);
   const int nown = bk.nown;
   const long long cp = bk.count_pad;
-  double acc[2] = {0.0, 0.0};
+  typedef typename WTraits<WT>::acc_t acc_t;
+  acc_t acc[2] = {acc_t(0), acc_t(0)};
 #pragma unroll 16
   for (int c = 0; c < NPAD; ++c) {
-    const double rv = ldr(r, col_index<DIM, KIND>(cm, k, c));
+    const acc_t rv = acc_t(ldr(r, col_index<DIM, KIND>(cm, k, c)));
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       // unconditional load at a clamped row (no branch, so the unrolled loads stay in flight)
       const int jj = j + 64 * h;
       const long long e = (long long)c * nown + min(jj, nown - 1);
-      const double w = w_elem<WT>(W, ((e / V) * cp + p) * V + e % V);
-      acc[h] += jj < nown ? w * rv : 0.0;
+      const acc_t w = w_elem<WT>(W, ((e / V) * cp + p) * V + e % V);
+      acc[h] += jj < nown ? w * rv : acc_t(0);
     }
   }
   const double om = gd.omega_patch ? (double)gd.omega_patch[patch_lin(g, KIND, k)] : gd.omega;
@@ -334,7 +337,7 @@ __device__ __forceinline__ void rav_apply_rows_body(const GridDev* __restrict__ 
     const int jj = j + 64 * h;
     if (jj >= nown) continue;
     const long long gi = own_index<DIM, KIND>(cm, k, bucket_own_local(DIM, KIND, bk.cls, jj));
-    if (gi >= 0) x[gi] += om * acc[h];
+    if (gi >= 0) x[gi] += om * (double)acc[h];
   }
 }
 

@@ -563,6 +563,16 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
                      std::to_string(d->dim * nv + np) + " DoFs, limit " + std::to_string(MAX_COARSE) +
                      "): use more levels");
   }
+  {
+    // the kernels keep level vector indices in 32-bit integers and decode
+    // them with 32-bit division; they assume fewer than 2^28 entries
+    const long long nf = d->n_cells;
+    long long nv = 1, np = 1;
+    for (int k = 0; k < d->dim; ++k) { nv *= 2 * nf + 1; np *= nf + 1; }
+    if (d->dim * nv + np >= (1LL << 28))
+      return set_err(nullptr, RAV_EUNSUPPORTED, "finest level has " + std::to_string(d->dim * nv + np) +
+                     " DoFs; the kernels' 32-bit index math supports fewer than 2^28");
+  }
   if (!(d->omega > 0.0) || d->nu_pre < 0 || d->nu_post < 0)
     return set_err(nullptr, RAV_EINVAL, "omega must be > 0 and smoothing steps >= 0");
   if (!(d->eta_out > 0.0) || !(d->eta_in > 0.0)) return set_err(nullptr, RAV_EINVAL, "viscosities must be > 0");
@@ -929,11 +939,25 @@ rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int 
   int k = 0;
   double rk = r0;
   ctx->fell_back = 0;
+  // the fallback drops the per-patch weights for the rest of this solve only:
+  // they are put back before returning, so the next solve starts with them
+  std::vector<const float*> saved_omega;
+  for (const LevelHost& Lv : ctx->lv) saved_omega.push_back(Lv.hd.omega_patch);
+  auto restore_omega = [&]() -> rav_status {
+    if (!ctx->fell_back) return RAV_OK;
+    for (size_t l = 0; l < ctx->lv.size(); ++l) {
+      if (ctx->lv[l].hd.omega_patch == saved_omega[l]) continue;
+      ctx->lv[l].hd.omega_patch = saved_omega[l];
+      const rav_status s2 = rav_upload_desc(ctx, ctx->lv[l]);
+      if (s2 != RAV_OK) return s2;
+    }
+    return RAV_OK;
+  };
   while (result == RAV_NOT_CONVERGED && k < maxit) {
     const double rprev = rk;
     solve_cycle(ctx);   // r of the finest level is current from the norm evaluation
     st = rav_read_norm(ctx, &rk);
-    if (st != RAV_OK) return st;
+    if (st != RAV_OK) { (void)restore_omega(); return st; }
     collect_graph_profile(ctx);
     ++k;
     if (ctx->fallback_rho > 0.0 && !ctx->fell_back && rk > ctx->fallback_rho * rprev) {
@@ -944,7 +968,8 @@ rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int 
         if (!Lv.hd.omega_patch) continue;
         Lv.hd.omega_patch = nullptr;
         any = true;
-        if ((st = rav_upload_desc(ctx, Lv)) != RAV_OK) return st;
+        ctx->fell_back = 1;
+        if ((st = rav_upload_desc(ctx, Lv)) != RAV_OK) { (void)restore_omega(); return st; }
       }
       ctx->fell_back = any ? 1 : 0;
     }
@@ -960,6 +985,7 @@ rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int 
   launch_copy(x, L.hd.x, n, ctx->stream);
   CK(hipGetLastError());
   CK(hipStreamSynchronize(ctx->stream));
+  if ((st = restore_omega()) != RAV_OK) return st;
   return result;
 }
 

@@ -1,7 +1,7 @@
 // Krylov acceleration of the multigrid solver: restarted, right-preconditioned
 // flexible GMRES whose preconditioner is one V-cycle (with zero initial guess)
-// of the context's smoother (the paper notes that multigrid "can also be used
-// as a preconditioner in a Krylov subspace solver", Sec. 4).  The Arnoldi
+// of the context's smoother (Sec. 4 remarks that the multigrid cycle may
+// equally serve as the preconditioner of a Krylov method).  The Arnoldi
 // coefficients stay in device memory; one small read-back per iteration feeds
 // the Givens update of the least-squares residual on the host.
 #include <hip/hip_runtime.h>

@@ -78,3 +78,24 @@ def test_host_owner_map_512_counts():
     counts = np.bincount(own[own >= 0], minlength=g.nP)
     hist = np.bincount(counts)
     assert hist[9] == 259081 + 2036 + 4 and hist[5] == 1018 + 4 and hist[3] == 1
+
+
+@pytest.mark.parametrize("dim,N,nl", [(2, 8192, 10), (3, 256, 6)])
+def test_levels_beyond_32bit_index_math_rejected(dim, N, nl):
+    """A finest level of 2^28 or more entries would overflow the kernels'
+    32-bit index math: rav_create refuses it before any device work."""
+    dm = ri.ALL_DIRICHLET_2D if dim == 2 else ri.ALL_DIRICHLET_3D
+    d = capi.make_desc(dim=dim, n_cells=N, n_levels=nl, dmask=dm, kind="vertex" if dim == 2 else "element")
+    h = ctypes.c_void_p()
+    assert capi.lib().rav_create(ctypes.byref(d), None, ctypes.byref(h)) == -6
+    assert h.value is None
+    assert b"2^28" in capi.lib().rav_last_error(None) or "2^28" in str(capi.lib().rav_last_error(None))
+
+
+def test_largest_supported_2d_level_passes_the_index_check():
+    """N = 4096 in 2D (151 M entries) is below the bound: a descriptor that is
+    invalid only in omega fails on omega, i.e. after the size check."""
+    d = capi.make_desc(dim=2, n_cells=4096, n_levels=10)
+    d.omega = 0.0
+    h = ctypes.c_void_p()
+    assert capi.lib().rav_create(ctypes.byref(d), None, ctypes.byref(h)) == -1

@@ -9,6 +9,8 @@ import scipy.linalg as sla
 
 import rav_inputs as ri
 from oracle import assemble as A
+from oracle import mg
+from oracle import smoothers as sm
 from oracle import patches as pt
 from oracle import transfer
 from oracle.grid import Grid
@@ -28,6 +30,12 @@ def bench_hierarchy():
     G.factor()
     yield G
     G.close()
+
+
+@pytest.fixture(scope="module")
+def oracle_L():
+    """The oracle's assembled 512x512 operator (CSR on the free DoFs)."""
+    return A.assemble_matrix(Grid(2, N, ri.ALL_DIRICHLET_2D))
 
 
 def _rows(g, rows):
@@ -113,7 +121,7 @@ def test_transfers_sampled(bench_hierarchy):
     np.testing.assert_allclose(xf.cpu().numpy(), P @ xc, rtol=0, atol=1e-13 * np.abs(xc).max() * 4)
 
 
-def test_bench_solve_reaches_tolerance(bench_hierarchy):
+def test_bench_solve_reaches_tolerance(bench_hierarchy, oracle_L):
     """The timed solve: RHS equals the oracle's, the residual reduction of the
     returned solution, recomputed with the oracle's assembled operator, is
     <= 1e-8, and the iteration count is mesh-independent (V(2,2): 15 +- 3)."""
@@ -128,8 +136,92 @@ def test_bench_solve_reaches_tolerance(bench_hierarchy):
     x = torch.zeros_like(b)
     st, it, rel = G.solve(x, b, 1e-8, 100)
     assert st == 0 and rel <= 1e-8 and 10 <= it <= 20, (st, it, rel)
-    L = A.assemble_matrix(g)
+    L = oracle_L
     xs = x.cpu().numpy()
     r = bo - L @ xs
     r[~g.free] = 0.0
     assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(bo)
+
+
+def _true_rel_residual(L, g, bo, x):
+    r = bo - L @ x
+    r[~g.free] = 0.0
+    return np.linalg.norm(r) / np.linalg.norm(bo)
+
+
+@pytest.fixture(scope="module")
+def fp64_reference(bench_hierarchy, oracle_L):
+    """FP64 GPU solve of the bench problem to a 1e-12 reduction, its residual
+    verified with the oracle's operator: the reference for the mixed-precision
+    solutions (the oracle's own 512^2 solve would take minutes)."""
+    G = bench_hierarchy
+    g = Grid(2, N, ri.ALL_DIRICHLET_2D)
+    params = ri.mms_params(2, ri.CONFIGS["2d-512"]["seed"])
+    bo = A.assemble_rhs(g, params)
+    b = torch.from_numpy(bo).cuda()
+    x = torch.zeros_like(b)
+    st, it, rel = G.solve(x, b, 1e-12, 100)
+    assert st == 0 and rel <= 1e-12, (st, it, rel)
+    xs = x.cpu().numpy()
+    assert _true_rel_residual(oracle_L, g, bo, xs) <= 1.1e-12
+    return bo, xs
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_one_sweep_sampled(prec):
+    """One 512^2 sweep with FP32/BF16 rows (the launch tables bench.py times)
+    on sampled DoFs: x + omega * y with y = W_lp r_lp, W_lp the oracle's FP64
+    owned rows rounded to the storage format and r rounded to FP32, the product
+    accumulated in FP32.  Bound: FP32 accumulation error (n + 2) 2^-24
+    sum_j |W_lp,ij r_j| (the GPU sums in another order)."""
+    print(f"[gpu] 512x512 {prec} sweep", flush=True)
+    G = Hierarchy(dim=2, n_cells=N, n_levels=NL, dmask=ri.ALL_DIRICHLET_2D, omega=0.66, precision=prec)
+    G.factor()
+    g = Grid(2, N, ri.ALL_DIRICHLET_2D)
+    owner = pt.owner_of_dofs(g, pt.VERTEX)
+    x = ri.random_vector(g.n, 81) * g.free
+    b = ri.random_vector(g.n, 82) * g.free
+    xd = torch.from_numpy(x).cuda()
+    G.smooth(NL - 1, 1, xd, torch.from_numpy(b).cuda())
+    xg = xd.cpu().numpy()
+    G.close()
+    rng = np.random.default_rng(83)
+    free = np.nonzero(g.free)[0]
+    # boundary and corner patches first, then random DoFs
+    edge = [g.vel(0, np.array([1, 1])), g.vel(1, np.array([2 * N - 1, 5])), g.pres(np.array([0, 0])),
+            g.pres(np.array([N, N // 2]))]
+    for d in np.concatenate([edge, rng.choice(free, 36, replace=False)]):
+        p = owner[d]
+        I, rows, Li = _patch_system(g, p)
+        own = np.nonzero(owner[I] == p)[0]
+        r = np.array([b[i] - _row_dot(rows[i], x) for i in I])
+        Wlp = sm.round_storage(np.linalg.inv(Li)[own], prec)
+        r32 = r.astype(np.float32)
+        y = (Wlp @ r32).astype(np.float32)
+        loc = int(np.nonzero(I[own] == d)[0][0])
+        expect = x[d] + 0.66 * float(y[loc])
+        tol = 0.66 * (len(I) + 2) * 2.0 ** -24 * float(np.abs(Wlp[loc].astype(np.float64) * r).sum()) \
+            + 1e-15 * abs(x[d])
+        assert abs(xg[d] - expect) <= tol, (prec, int(d), xg[d] - expect, tol)
+    assert np.all(xg[~g.free] == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_solve_512(prec, fp64_reference, oracle_L):
+    """The bench's FP32/BF16 solves: the true FP64 residual of the returned
+    solution, recomputed with the oracle's operator, is <= 1.01e-8 of the
+    initial one, and the solution is within 1e-7 (relative L2 over free DoFs,
+    pressure mean removed) of the FP64 solve to 1e-12."""
+    print(f"[gpu] 512x512 {prec} solve", flush=True)
+    bo, xref = fp64_reference
+    g = Grid(2, N, ri.ALL_DIRICHLET_2D)
+    G = Hierarchy(dim=2, n_cells=N, n_levels=NL, dmask=ri.ALL_DIRICHLET_2D, omega=0.66, precision=prec)
+    G.factor()
+    b = torch.from_numpy(bo).cuda()
+    x = torch.zeros_like(b)
+    st, it, rel = G.solve(x, b, 1e-8, 100)
+    G.close()
+    assert st == 0 and rel <= 1e-8 and it <= 20, (st, it, rel)
+    xs = x.cpu().numpy()
+    assert _true_rel_residual(oracle_L, g, bo, xs) <= 1.01e-8
+    assert mg.rel_l2(g, xs, xref) <= 1e-7

@@ -76,3 +76,53 @@ def test_training_steps_reduce_the_loss():
     after = mean_loss()
     assert after < before, (before, after)
     M.close(); G.close()
+
+
+def test_fallback_to_fixed_omega_then_weights_restored():
+    """A network whose output is omega = 0.2 + sigmoid(10) = 1.19995 on every
+    patch (all weights zero, output bias 10) makes the 32^2 V-cycle diverge
+    (oracle: reductions 0.54, 4.2, 3.2, ...).  With the fallback at rho_max
+    0.9 the solve drops the weights after the second cycle, goes on with the
+    scalar omega 0.66 and reaches 1e-8.  The next solve starts with the
+    network's weights again: it falls back again, after the same cycles."""
+    import rav_inputs as ri_
+    from oracle import assemble as A
+    H = mg.Hierarchy(2, 32, 3, ri_.ALL_DIRICHLET_2D)
+    g = H.finest.grid
+    b = torch.from_numpy(A.assemble_rhs(g, ri_.mms_params(2, 1001))).cuda()
+    theta = np.zeros(5313, dtype=np.float32)
+    theta[-1] = 10.0
+    M = MLP(theta)
+    G = Hierarchy(dim=2, n_cells=32, n_levels=3, omega=0.66)
+    G.factor()
+    G.learn_set_omega(M)
+    G.set_fallback(0.9)
+    runs = []
+    for _ in range(2):
+        x = torch.zeros_like(b)
+        st, it, rel = G.solve(x, b, 1e-8, 100)
+        runs.append((st, it, rel, G.set_fallback(0.9), x.cpu().numpy()))
+    for st, it, rel, fb, _ in runs:
+        assert st == 0 and rel <= 1e-8 and fb == 1, (st, it, rel, fb)
+    assert runs[0][1] == runs[1][1]
+    np.testing.assert_array_equal(runs[0][4], runs[1][4])
+    # without per-patch weights the same solve never falls back
+    G.learn_set_omega(None)
+    x = torch.zeros_like(b)
+    st, it_fixed, rel = G.solve(x, b, 1e-8, 100)
+    assert st == 0 and G.set_fallback(0.9) == 0 and it_fixed < runs[0][1]
+    M.close(); G.close()
+
+
+def test_non_finite_rhs_reports_divergence():
+    """A right-hand side holding NaN gives a non-finite initial residual:
+    rav_solve returns RAV_EDIVERGED (-4) without cycling."""
+    G = Hierarchy(dim=2, n_cells=16, n_levels=2)
+    G.factor()
+    n, _ = G.dofs(1)
+    b = torch.zeros(n, dtype=torch.float64, device="cuda")
+    b[n - 3] = float("nan")
+    x = torch.zeros_like(b)
+    st, it, rel = G.solve(x, b, 1e-8, 10)
+    assert st == -4 and it == 0
+    G.close()

@@ -285,6 +285,15 @@ def test_mixed_precision_solution(prec):
     gh.close()
 
 
+def _storage_ulp(W, prec):
+    """Spacing of the storage format at |W_ij|: 2^(e - 23) for FP32, 2^(e - 7)
+    for BF16, e = floor(log2 |W_ij|); 0 where W_ij = 0."""
+    a = np.abs(np.asarray(W, dtype=np.float64))
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    ulp = np.exp2(e - (23 if prec == "fp32" else 7))
+    return np.where(a > 0, ulp, 0.0)
+
+
 def test_low_precision_rows_are_rounded_fp64_rows():
     """Stored FP32/BF16 rows equal the FP64 rows rounded once (RNE)."""
     H = _oracle("2d-vertex-dir")
@@ -296,6 +305,11 @@ def test_low_precision_rows_are_rounded_fp64_rows():
         for i in range(0, ps.count, 7):
             Wo = sm.owned_rows(lv.lus[i], ps.owned[i], len(ps.dofs[i]))
             Wg = gh.patch_inverse(1, i)
-            np.testing.assert_allclose(Wg, sm.round_storage(Wo, prec).astype(np.float64),
-                                       rtol=0, atol=(2 ** -20 if prec == "fp32" else 2 ** -7) * np.abs(Wo).max())
+            # per entry: at most one storage ulp of |W_ij| (a rounding decision
+            # may flip where the GPU's FP64 row differs from the oracle's in
+            # the last bits), plus that FP64 difference for tiny entries
+            expect = sm.round_storage(Wo, prec).astype(np.float64)
+            ulp = _storage_ulp(Wo, prec)
+            tol = ulp + 1e-12 * np.abs(Wo).max()
+            assert np.all(np.abs(Wg - expect) <= tol), (prec, i, np.max(np.abs(Wg - expect) / tol))
         gh.close()

@@ -1,0 +1,171 @@
+"""Pins of oracle pieces that the other CPU tests only compared with themselves:
+the inclusion rule at Gauss points, the low-precision RAV sweep arithmetic,
+the 3D element-patch bucket table of the 64^3 workload and mesh independence
+of the RAV V-cycle up to 256^2 (Sec. 4: rates that do not degrade with
+refinement).  Expected values are worked out by hand in each docstring."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import rav_inputs as ri
+from oracle import assemble as A
+from oracle import mg
+from oracle import patches as pt
+from oracle import smoothers as sm
+from oracle.fem import RefElement
+from oracle.grid import Grid
+
+# 3-point Gauss abscissae on [0,1] are 1/2 and 1/2 -+ sqrt(15)/10 (0.3873 from the middle).
+OFF = np.sqrt(15.0) / 10.0
+
+
+def test_viscosity_single_cell_radius_cases():
+    """One cell (N = 1, h = 1), disc centred at the cell centre.  The nine
+    Gauss points sit at the centre (distance 0), at the four edge-parallel
+    offsets (distance sqrt(15)/10 = 0.387) and at the four diagonal offsets
+    (distance sqrt(30)/10 = 0.548).  Radii 0.3 / 0.45 / 0.6 take 1 / 5 / 9 of
+    them; point order is lexicographic, x fastest.  A 2D inclusion is the
+    row (cx, cy, r)."""
+    g = Grid(2, 1, ri.ALL_DIRICHLET_2D)
+    ref = RefElement(2)
+    elems = g.elements()
+    centre_only = np.array([[1, 1, 1, 1, 5, 1, 1, 1, 1]], dtype=float)
+    plus = np.array([[1, 5, 1, 5, 5, 5, 1, 5, 1]], dtype=float)
+    for r, expect in [(0.3, centre_only), (0.45, plus), (0.6, np.full((1, 9), 5.0))]:
+        eta = A.viscosity(g, ref, elems, 1.0, 5.0, [[0.5, 0.5, r]])
+        np.testing.assert_array_equal(eta, expect)
+    assert OFF < 0.45 < np.sqrt(2) * OFF
+
+
+def test_viscosity_element_and_axis_order():
+    """N = 2 (h = 1/2): a disc of radius 0.1 at (0.75, 0.25) holds only the
+    middle Gauss point of the cell with x-index 1 and y-index 0, which is
+    element 1 in x-fastest order (an x/y mix-up would hit element 2).  The
+    next Gauss point is h * sqrt(15)/10 = 0.194 away."""
+    g = Grid(2, 2, ri.ALL_DIRICHLET_2D)
+    ref = RefElement(2)
+    eta = A.viscosity(g, ref, g.elements(), 2.0, 7.0, [[0.75, 0.25, 0.1]])
+    expect = np.full((4, 9), 2.0)
+    expect[1, 4] = 7.0
+    np.testing.assert_array_equal(eta, expect)
+
+
+def test_viscosity_3d_closed_ball_and_overlap():
+    """3D, N = 1: a ball of radius 0.45 at the cell centre holds the centre
+    point and the six axis offsets (0.387) but no point two offsets away
+    (0.548): 7 of the 27 points.  A second ball overlapping the first changes
+    nothing (overlaps take eta_in).  Point (a, b, c) has index a + 3b + 9c."""
+    g = Grid(3, 1, ri.ALL_DIRICHLET_3D)
+    ref = RefElement(3)
+    incl = [[0.5, 0.5, 0.5, 0.45], [0.5, 0.5, 0.5, 0.41]]
+    eta = A.viscosity(g, ref, g.elements(), 1.0, 3.0, incl)
+    inside = {13, 4, 22, 10, 16, 12, 14}
+    expect = np.array([[3.0 if q in inside else 1.0 for q in range(27)]])
+    np.testing.assert_array_equal(eta, expect)
+
+
+def _identity_problem(n):
+    L = sp.identity(n, format="csr")
+    return L, np.ones(n, dtype=bool)
+
+
+def test_lowp_sweep_rounds_residual_to_fp32():
+    """L = I, x = 0, b = 1 + 2^-30: r = b, which rounds to 1.0 in FP32.  A
+    one-DoF patch with W = [1] gives y = 1 exactly, so x becomes 1.0 (with an
+    FP64 residual it would be 1 + 2^-30)."""
+    L, free = _identity_problem(1)
+    b = np.array([1.0 + 2.0 ** -30])
+    x = sm.rav_sweep_rows_lowp(L, free, [np.array([0])], [np.array([0])],
+                               [np.array([[1.0]], dtype=np.float32)], 1.0, np.zeros(1), b)
+    assert x[0] == 1.0
+
+
+def test_lowp_sweep_accumulates_in_fp32():
+    """Two-DoF patch, owned row 0, W = [1, 1], r = (1, 2^-24): the FP32 sum
+    1 + 2^-24 is a tie and rounds to even, 1.0, in either order; FP64
+    accumulation would keep 1 + 2^-24.  omega = 0.5 then gives exactly 0.5."""
+    L, free = _identity_problem(2)
+    b = np.array([1.0, 2.0 ** -24])
+    x = sm.rav_sweep_rows_lowp(L, free, [np.array([0, 1])], [np.array([0])],
+                               [np.array([[1.0, 1.0]], dtype=np.float32)], 0.5, np.zeros(2), b)
+    assert x[0] == 0.5 and x[1] == 0.0
+
+
+def test_lowp_sweep_rounds_products_to_fp32():
+    """One term w r with w = r = 1 + 2^-23 (both FP32 numbers): the exact
+    product 1 + 2^-22 + 2^-46 rounds to 1 + 2^-22 in FP32."""
+    L, free = _identity_problem(1)
+    w = 1.0 + 2.0 ** -23
+    x = sm.rav_sweep_rows_lowp(L, free, [np.array([0])], [np.array([0])],
+                               [np.array([[w]], dtype=np.float32)], 1.0, np.zeros(1), np.array([w]))
+    assert x[0] == 1.0 + 2.0 ** -22
+
+
+def test_bf16_storage_ties_and_double_rounding():
+    """RNE to bfloat16 (8 significant bits): 1 + 2^-8 is a tie between 1 and
+    1 + 2^-7 and goes to 1; 1 + 3 * 2^-8 is a tie between 1 + 2^-7 and
+    1 + 2^-6 and goes to 1 + 2^-6; 1 + 2^-8 + 2^-30 is first rounded to FP32
+    (giving the tie 1 + 2^-8) and then to 1.  FP32 storage of 1 + 2^-30 is 1."""
+    v = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -8 + 2.0 ** -30, -(1 + 3 * 2.0 ** -8)])
+    out = sm.round_storage(v, "bf16").astype(np.float64)
+    np.testing.assert_array_equal(out, [1.0, 1 + 2.0 ** -6, 1.0, -(1 + 2.0 ** -6)])
+    assert float(sm.round_storage(np.array([1 + 2.0 ** -30]), "fp32")[0]) == 1.0
+
+
+def _element_buckets_3d(N):
+    """(n_i, owned_i) histogram of all-Dirichlet 3D element patches by
+    counting per axis: a cell at e has 3 - [e = 0] - [e = N-1] free velocity
+    positions, owns 2 - [e = 0] of them (its nodes 2e, 2e+1, and 2e+2 when
+    e = N-1, minus masked ones) and 1 + [e = N-1] pressure positions;
+    n_i = 3 prod(c) + 8 and owned_i = 3 prod(o) + prod(p)."""
+    hist = {}
+    e = np.arange(N)
+    c = 3 - (e == 0) - (e == N - 1)
+    o = 2 - (e == 0)
+    p = 1 + (e == N - 1)
+    for i in range(N):
+        for j in range(N):
+            for k in range(N):
+                key = (int(3 * c[i] * c[j] * c[k] + 8), int(3 * o[i] * o[j] * o[k] + p[i] * p[j] * p[k]))
+                hist[key] = hist.get(key, 0) + 1
+    return hist
+
+
+def test_3d_element_bucket_histogram_64():
+    """The 64^3 element-patch table: 62^3 interior (89, 25) patches, lower
+    faces (62, 13), upper faces (62, 26), edges and corners; and the entry count
+    sum_i owned_i n_i of the stored inverse rows, 558,683,224."""
+    h = _element_buckets_3d(64)
+    assert h[(89, 25)] == 238328 and h[(62, 13)] == 11532 and h[(62, 26)] == 11532
+    assert h[(44, 14)] == 372 and h[(44, 7)] == 186 and h[(44, 28)] == 186
+    assert sum(v for (n, _), v in h.items() if n == 32) == 8
+    assert sum(h.values()) == 64 ** 3
+    assert sum(n * o * v for (n, o), v in h.items()) == 558683224
+
+
+@pytest.mark.parametrize("N", [4, 5])
+def test_3d_patchset_matches_element_counting(N):
+    g = Grid(3, N, ri.ALL_DIRICHLET_3D)
+    ps = pt.PatchSet(g, pt.ELEMENT)
+    hist = {}
+    for I, own in zip(ps.dofs, ps.owned):
+        key = (len(I), len(own))
+        hist[key] = hist.get(key, 0) + 1
+    assert hist == _element_buckets_3d(N)
+
+
+def test_rav_mesh_independence_to_256():
+    """RAV V(2,2), omega = 0.66, coarsest grid 8x8, N = 16 ... 256: the
+    average reduction stays in a +-25 % band and the cycle count moves by at
+    most 3 (about two minutes of CPU)."""
+    rhos, its = [], []
+    for N, nl in [(16, 2), (32, 3), (64, 4), (128, 5), (256, 6)]:
+        H = mg.Hierarchy(2, N, nl, ri.ALL_DIRICHLET_2D)
+        b = A.assemble_rhs(H.finest.grid, ri.mms_params(2, 1001))
+        _, k, hist, st = H.solve(b)
+        assert st == "converged"
+        rhos.append(mg.avg_reduction(hist))
+        its.append(k)
+    mid = 0.5 * (max(rhos) + min(rhos))
+    assert max(rhos) <= 1.25 * mid and min(rhos) >= 0.75 * mid, rhos
+    assert max(its) - min(its) <= 3, its

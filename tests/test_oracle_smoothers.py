@@ -193,21 +193,6 @@ def test_variant_ordering_32():
     assert its[mg.MV] <= its[mg.RAV] < its[mg.AV]
 
 
-def test_rav_mesh_independence():
-    """RAV V(2,2), omega = 0.66: average reduction stays in a +-25% band and the
-    iteration count moves by at most 3 as the grid is refined (coarsest 8x8)."""
-    rhos, its = [], []
-    for N, nl in [(16, 2), (32, 3), (64, 4)]:
-        H = mg.Hierarchy(2, N, nl, ri.ALL_DIRICHLET_2D)
-        b = A.assemble_rhs(H.finest.grid, ri.mms_params(2, 1001))
-        _, k, hist, st = H.solve(b)
-        assert st == "converged"
-        rhos.append(mg.avg_reduction(hist)); its.append(k)
-    mid = 0.5 * (max(rhos) + min(rhos))
-    assert max(rhos) <= 1.25 * mid and min(rhos) >= 0.75 * mid, rhos
-    assert max(its) - min(its) <= 3, its
-
-
 @pytest.mark.parametrize("prec,band", [("fp32", 0.10), ("bf16", 0.25)])
 def test_mixed_precision_iterative_refinement(prec, band):
     H = mg.Hierarchy(2, 32, 3, ri.ALL_DIRICHLET_2D)
