@@ -151,19 +151,20 @@ def _true_rel_residual(L, g, bo, x):
 
 @pytest.fixture(scope="module")
 def fp64_reference(bench_hierarchy, oracle_L):
-    """FP64 GPU solve of the bench problem to a 1e-12 reduction, its residual
-    verified with the oracle's operator: the reference for the mixed-precision
-    solutions (the oracle's own 512^2 solve would take minutes)."""
+    """FP64 GPU solve of the bench problem to a 1e-11 reduction (the FP64
+    residual stagnates near 1e-12 at this size), its residual verified with
+    the oracle's operator: the reference for the mixed-precision solutions
+    (the oracle's own 512^2 solve would take minutes)."""
     G = bench_hierarchy
     g = Grid(2, N, ri.ALL_DIRICHLET_2D)
     params = ri.mms_params(2, ri.CONFIGS["2d-512"]["seed"])
     bo = A.assemble_rhs(g, params)
     b = torch.from_numpy(bo).cuda()
     x = torch.zeros_like(b)
-    st, it, rel = G.solve(x, b, 1e-12, 100)
-    assert st == 0 and rel <= 1e-12, (st, it, rel)
+    st, it, rel = G.solve(x, b, 1e-11, 100)
+    assert st == 0 and rel <= 1e-11, (st, it, rel)
     xs = x.cpu().numpy()
-    assert _true_rel_residual(oracle_L, g, bo, xs) <= 1.1e-12
+    assert _true_rel_residual(oracle_L, g, bo, xs) <= 1.1e-11
     return bo, xs
 
 
@@ -211,7 +212,7 @@ def test_mixed_solve_512(prec, fp64_reference, oracle_L):
     """The bench's FP32/BF16 solves: the true FP64 residual of the returned
     solution, recomputed with the oracle's operator, is <= 1.01e-8 of the
     initial one, and the solution is within 1e-7 (relative L2 over free DoFs,
-    pressure mean removed) of the FP64 solve to 1e-12."""
+    pressure mean removed) of the FP64 solve to 1e-11."""
     print(f"[gpu] 512x512 {prec} solve", flush=True)
     bo, xref = fp64_reference
     g = Grid(2, N, ri.ALL_DIRICHLET_2D)
