@@ -163,6 +163,25 @@ rav_status rav_solve(rav_ctx* ctx, double* x_dev, const double* b_dev, double rt
 rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit, int restart,
                            int* iters, double* rel_res);
 
+/* For callers that cannot allocate device memory during a solve (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * rav_solve_gmres without any allocation.  Same arguments, arithmetic and
+ * results as rav_solve_gmres (bit for bit), but the work vectors live in one
+ * library-owned static device array of RAV_NOALLOC_SCRATCH_BYTES per GPU,
+ * held from the first call on that GPU until the process ends.  Requires
+ * restart <= RAV_NOALLOC_MAX_RESTART and
+ * 65536 + (2 restart + 3) * 8 * ceil32(n_total(finest)) <= RAV_NOALLOC_SCRATCH_BYTES
+ * (ceil32 rounds up to a multiple of 32); larger requests return RAV_EINVAL
+ * with a message before any device work.  Nothing in the array needs to start
+ * at zero: every call writes each buffer before reading it.  All calls on one
+ * GPU share the array: calls that overlap in time on one GPU (from several
+ * threads or streams) race and give wrong results; calls one after another
+ * are safe, since each returns after synchronising its stream. */
+#define RAV_NOALLOC_SCRATCH_BYTES (64LL * 1024 * 1024)
+#define RAV_NOALLOC_MAX_RESTART 64
+rav_status rav_solve_gmres_noalloc(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit,
+                                   int restart, int* iters, double* rel_res);
+
 /* Change damping and smoothing steps without refactoring. */
 rav_status rav_set_params(rav_ctx* ctx, double omega, int nu_pre, int nu_post);
 

@@ -65,6 +65,7 @@ SIGNATURES = {
     "rav_solve": (_S, [_P, _P, _P, _D, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
     "rav_set_params": (_S, [_P, _D, _I, _I]),
     "rav_solve_gmres": (_S, [_P, _P, _P, _D, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
+    "rav_solve_gmres_noalloc": (_S, [_P, _P, _P, _D, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
     "rav_set_patch_omega": (_S, [_P, _I, _P]),
     "rav_get_patch_map": (_S, [_P, _I, _L, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "rav_get_owner": (_S, [_P, _I, _P]),
@@ -234,6 +235,14 @@ class Hierarchy:
         it, rel = _I(), _D()
         st = self.lib.rav_solve_gmres(self.h, _ptr(x), _ptr(b), rtol, maxit, restart, ctypes.byref(it),
                                       ctypes.byref(rel))
+        if st < 0 and st != -4:
+            self._chk(st)
+        return st, it.value, rel.value
+
+    def solve_gmres_noalloc(self, x, b, rtol=1e-8, maxit=300, restart=30):
+        it, rel = _I(), _D()
+        st = self.lib.rav_solve_gmres_noalloc(self.h, _ptr(x), _ptr(b), rtol, maxit, restart, ctypes.byref(it),
+                                              ctypes.byref(rel))
         if st < 0 and st != -4:
             self._chk(st)
         return st, it.value, rel.value

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,35 +34,33 @@ void rav_vcycle_finest(rav_ctx* ctx);
     }                                                                          \
   } while (0)
 
-extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit,
-                                      int restart, int* iters, double* rel_res) {
-  if (!ctx || !x_dev || !b_dev || !(rtol > 0.0) || maxit < 0 || restart < 1 || restart > 200) return RAV_EINVAL;
-  if (!ctx->factored) { ctx->err = "rav_factor_patches has not been called"; return RAV_EINVAL; }
+namespace {
+
+// Device and host buffers of one FGMRES(m) solve.  Device: the Krylov basis
+// V_0..V_m and the preconditioned directions Z_0..Z_{m-1} (n doubles each),
+// the iterate xk and right-hand side bk, 1024 dot-product partial sums and
+// the Arnoldi columns hdev ((m + 2) per column).  Host: the Hessenberg matrix
+// H ((m + 1) x m), the Givens rotations, the least-squares right-hand side g,
+// the update coefficients y and hhost (m + 2), which receives one Arnoldi
+// column per iteration.  Every buffer is written before it is read, so none
+// needs clearing.
+struct GmresWork {
+  double** V;
+  double** Z;
+  double *xk, *bk, *partial, *hdev;
+  double *hhost, *H, *cs, *sn, *g, *y;
+};
+
+rav_status gmres_run(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit, int m,
+                     const GmresWork& w, int* iters, double* rel_res) {
   const int lf = (int)ctx->lv.size() - 1;
   LevelHost& L = ctx->lv[lf];
   const long long n = L.hd.g.n;
-  const int m = restart;
   hipStream_t s = ctx->stream;
-  std::vector<double*> V(m + 1, nullptr), Z(m, nullptr);
-  double *xk = nullptr, *bk = nullptr, *partial = nullptr, *hdev = nullptr, *hhost = nullptr;
-  rav_status result = RAV_OK;
-  auto cleanup = [&]() {
-    for (double* p : V) (void)hipFree(p);
-    for (double* p : Z) (void)hipFree(p);
-    (void)hipFree(xk); (void)hipFree(bk); (void)hipFree(partial); (void)hipFree(hdev);
-    if (hhost) (void)hipHostFree(hhost);
-  };
-  auto alloc = [&]() -> rav_status {
-    for (double*& p : V) KCK(hipMalloc((void**)&p, sizeof(double) * n));
-    for (double*& p : Z) KCK(hipMalloc((void**)&p, sizeof(double) * n));
-    KCK(hipMalloc((void**)&xk, sizeof(double) * n));
-    KCK(hipMalloc((void**)&bk, sizeof(double) * n));
-    KCK(hipMalloc((void**)&partial, sizeof(double) * 1024));
-    KCK(hipMalloc((void**)&hdev, sizeof(double) * (m + 2) * (m + 1)));
-    KCK(hipHostMalloc((void**)&hhost, sizeof(double) * (m + 2), hipHostMallocDefault));
-    return RAV_OK;
-  };
-  if ((result = alloc()) != RAV_OK) { cleanup(); return result; }
+  double** V = w.V;
+  double** Z = w.Z;
+  double *xk = w.xk, *bk = w.bk, *partial = w.partial, *hdev = w.hdev, *hhost = w.hhost;
+  double *H = w.H, *cs = w.cs, *sn = w.sn, *g = w.g, *y = w.y;
   launch_copy(xk, x_dev, n, s);
   launch_copy(bk, b_dev, n, s);
   // residual of the current iterate into L.r (norm in ctx->d_norm)
@@ -72,18 +71,18 @@ extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double*
     return rav_read_norm(ctx, nrm);
   };
   double beta0 = 0.0;
-  if ((result = true_residual(&beta0)) != RAV_OK) { cleanup(); return result; }
-  if (!std::isfinite(beta0)) { cleanup(); ctx->err = "initial residual is not finite"; return RAV_EDIVERGED; }
+  rav_status result = true_residual(&beta0);
+  if (result != RAV_OK) return result;
+  if (!std::isfinite(beta0)) { ctx->err = "initial residual is not finite"; return RAV_EDIVERGED; }
   int total = 0;
   double res = beta0;
   result = RAV_NOT_CONVERGED;
   if (beta0 == 0.0) result = RAV_OK;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   while (result == RAV_NOT_CONVERGED && total < maxit) {
     double beta = 0.0;
     if (total > 0) {
       rav_status st = true_residual(&beta);
-      if (st != RAV_OK) { cleanup(); return st; }
+      if (st != RAV_OK) return st;
       res = beta;
       if (!std::isfinite(beta) || beta > 1e3 * beta0) { result = RAV_EDIVERGED; break; }
       if (beta <= rtol * beta0) { result = RAV_OK; break; }
@@ -92,7 +91,7 @@ extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double*
     }
     // V_0 = r / beta
     launch_axpby(1.0 / beta, L.hd.r, 0.0, V[0], n, s);
-    std::fill(g.begin(), g.end(), 0.0);
+    for (int i = 0; i <= m; ++i) g[i] = 0.0;
     g[0] = beta;
     int jend = 0;
     for (int j = 0; j < m && total < maxit; ++j) {
@@ -104,17 +103,17 @@ extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double*
       // w = L Z_j  (residual with b = 0 gives -L Z_j)
       launch_fill(L.hd.b, 0.0, n, s);
       rav_residual_level(ctx, lf, false);
-      double* w = V[j + 1];
-      launch_axpby(-1.0, L.hd.r, 0.0, w, n, s);
+      double* wv = V[j + 1];
+      launch_axpby(-1.0, L.hd.r, 0.0, wv, n, s);
       // modified Gram-Schmidt, coefficients h[i][j] in device memory
       for (int i = 0; i <= j; ++i) {
         double* hij = hdev + (size_t)j * (m + 2) + i;
-        launch_dot(w, V[i], n, partial, hij, 0, s);
-        launch_axpy_dev(w, V[i], hij, -1.0, n, s);
+        launch_dot(wv, V[i], n, partial, hij, 0, s);
+        launch_axpy_dev(wv, V[i], hij, -1.0, n, s);
       }
       double* hn = hdev + (size_t)j * (m + 2) + j + 1;
-      launch_dot(w, w, n, partial, hn, 1, s);
-      launch_div_dev(w, w, hn, n, s);
+      launch_dot(wv, wv, n, partial, hn, 1, s);
+      launch_div_dev(wv, wv, hn, n, s);
       KCK(hipGetLastError());
       KCK(hipMemcpyAsync(hhost, hdev + (size_t)j * (m + 2), sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s));
       KCK(hipStreamSynchronize(s));
@@ -150,7 +149,7 @@ extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double*
     if (res <= rtol * beta0) {
       double beta_true = 0.0;
       rav_status st = true_residual(&beta_true);
-      if (st != RAV_OK) { cleanup(); return st; }
+      if (st != RAV_OK) return st;
       res = beta_true;
       if (beta_true <= rtol * beta0) result = RAV_OK;
     }
@@ -161,6 +160,106 @@ extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double*
   if (iters) *iters = total;
   if (rel_res) *rel_res = beta0 > 0.0 ? res / beta0 : 0.0;
   if (result == RAV_EDIVERGED) ctx->err = "GMRES residual diverged";
+  return result;
+}
+
+rav_status gmres_check(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit, int restart,
+                       int max_restart) {
+  if (!ctx || !x_dev || !b_dev || !(rtol > 0.0) || maxit < 0 || restart < 1 || restart > max_restart)
+    return RAV_EINVAL;
+  if (!ctx->factored) { ctx->err = "rav_factor_patches has not been called"; return RAV_EINVAL; }
+  return RAV_OK;
+}
+
+// ---- allocation-free variant ------------------------------------------------
+// Workspace of rav_solve_gmres_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code must not pass `scratch`
+// itself to a kernel (in host code the name is a host-side stand-in); it uses
+// the device address obtained once per device with hipGetSymbolAddress.
+constexpr long long SCRATCH_DOUBLES = RAV_NOALLOC_SCRATCH_BYTES / 8;
+constexpr long long SCRATCH_HEAD = 8192;   // partial sums (1024) and Arnoldi columns (<= 66 x 65)
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+rav_status scratch_address(rav_ctx* ctx, double** out) {
+  int dev = 0;
+  KCK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) { ctx->err = "device index out of range"; return RAV_EDEVICE; }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    KCK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return RAV_OK;
+}
+
+}  // namespace
+
+extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit,
+                                      int restart, int* iters, double* rel_res) {
+  rav_status result = gmres_check(ctx, x_dev, b_dev, rtol, maxit, restart, 200);
+  if (result != RAV_OK) return result;
+  const long long n = ctx->lv.back().hd.g.n;
+  const int m = restart;
+  std::vector<double*> V(m + 1, nullptr), Z(m, nullptr);
+  double *xk = nullptr, *bk = nullptr, *partial = nullptr, *hdev = nullptr, *hhost = nullptr;
+  auto cleanup = [&]() {
+    for (double* p : V) (void)hipFree(p);
+    for (double* p : Z) (void)hipFree(p);
+    (void)hipFree(xk); (void)hipFree(bk); (void)hipFree(partial); (void)hipFree(hdev);
+    if (hhost) (void)hipHostFree(hhost);
+  };
+  auto alloc = [&]() -> rav_status {
+    for (double*& p : V) KCK(hipMalloc((void**)&p, sizeof(double) * n));
+    for (double*& p : Z) KCK(hipMalloc((void**)&p, sizeof(double) * n));
+    KCK(hipMalloc((void**)&xk, sizeof(double) * n));
+    KCK(hipMalloc((void**)&bk, sizeof(double) * n));
+    KCK(hipMalloc((void**)&partial, sizeof(double) * 1024));
+    KCK(hipMalloc((void**)&hdev, sizeof(double) * (m + 2) * (m + 1)));
+    KCK(hipHostMalloc((void**)&hhost, sizeof(double) * (m + 2), hipHostMallocDefault));
+    return RAV_OK;
+  };
+  if ((result = alloc()) != RAV_OK) { cleanup(); return result; }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  const GmresWork w{V.data(), Z.data(), xk, bk, partial, hdev, hhost, H.data(), cs.data(), sn.data(), g.data(),
+                    y.data()};
+  result = gmres_run(ctx, x_dev, b_dev, rtol, maxit, m, w, iters, rel_res);
   cleanup();
   return result;
+}
+
+extern "C" rav_status rav_solve_gmres_noalloc(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol,
+                                              int maxit, int restart, int* iters, double* rel_res) {
+  rav_status result = gmres_check(ctx, x_dev, b_dev, rtol, maxit, restart, RAV_NOALLOC_MAX_RESTART);
+  if (result != RAV_OK) return result;
+  const long long n = ctx->lv.back().hd.g.n;
+  const long long stride = (n + 31) / 32 * 32;   // 256-byte aligned vectors
+  const int m = restart;
+  const long long need = SCRATCH_HEAD + (2LL * m + 3) * stride;
+  if (need > SCRATCH_DOUBLES) {
+    ctx->err = "rav_solve_gmres_noalloc: restart " + std::to_string(m) + " on " + std::to_string(n) +
+               " DoFs needs " + std::to_string(need * 8) + " bytes of workspace, more than its " +
+               std::to_string(SCRATCH_DOUBLES * 8) + "-byte maximum";
+    return RAV_EINVAL;
+  }
+  double* base = nullptr;
+  if ((result = scratch_address(ctx, &base)) != RAV_OK) return result;
+  double* V[RAV_NOALLOC_MAX_RESTART + 1];
+  double* Z[RAV_NOALLOC_MAX_RESTART];
+  double* vec = base + SCRATCH_HEAD;
+  for (int i = 0; i <= m; ++i) V[i] = vec + (long long)i * stride;
+  for (int i = 0; i < m; ++i) Z[i] = vec + (long long)(m + 1 + i) * stride;
+  double* xk = vec + (2LL * m + 1) * stride;
+  double* bk = vec + (2LL * m + 2) * stride;
+  double hhost[RAV_NOALLOC_MAX_RESTART + 2];
+  double H[(RAV_NOALLOC_MAX_RESTART + 1) * RAV_NOALLOC_MAX_RESTART];
+  double cs[RAV_NOALLOC_MAX_RESTART], sn[RAV_NOALLOC_MAX_RESTART], g[RAV_NOALLOC_MAX_RESTART + 1];
+  double y[RAV_NOALLOC_MAX_RESTART];
+  const GmresWork w{V, Z, xk, bk, base, base + 1024, hhost, H, cs, sn, g, y};
+  return gmres_run(ctx, x_dev, b_dev, rtol, maxit, m, w, iters, rel_res);
 }
