@@ -58,7 +58,8 @@ typedef enum {
 typedef enum { RAV_SMOOTHER_RAV = 0, RAV_SMOOTHER_AV = 1, RAV_SMOOTHER_MV = 2 } rav_smoother;
 
 /* Vertex patches: pressure vertex k plus every velocity DoF coupled to it by
- * B^T (Sec. 3).  Element patches: the velocity and pressure DoFs of one cell. */
+ * B^T (Sec. 3): 51 local DoFs in 2D, 376 in 3D (3D: RAV only).  Element
+ * patches: the velocity and pressure DoFs of one cell (2D 22, 3D 89). */
 typedef enum { RAV_PATCH_VERTEX = 0, RAV_PATCH_ELEMENT = 1 } rav_patch_kind;
 
 /* Storage precision of the patch inverse rows used by RAV (the outer
@@ -77,7 +78,7 @@ typedef struct {
   double eta_out, eta_in;       /* viscosity outside / inside inclusions, > 0   */
   int n_incl;                   /* number of inclusions (0..64)                  */
   const rav_inclusion* incl;    /* host array, copied by rav_create              */
-  rav_patch_kind patch;         /* 2D: VERTEX; 3D: ELEMENT                       */
+  rav_patch_kind patch;         /* VERTEX or ELEMENT                             */
   rav_smoother smoother;
   double omega;                 /* damping, > 0 (Sec. 4: 0.66 RAV/MV, 0.1 AV)    */
   int nu_pre, nu_post;          /* smoothing steps, >= 0                         */
@@ -99,9 +100,14 @@ typedef struct rav_ctx rav_ctx;
 rav_status rav_create(const rav_problem_desc* desc, void* hip_stream, rav_ctx** out);
 
 /* Factors every local system L_i = R_i L R_i^T (Sec. 3) on every smoothed
- * level with partial pivoting in FP64 and stores, for RAV, the owned rows of
- * L_i^{-1} (Sec. 4.3) in the context's precision, for AV/MV the full inverse.
- * RAV_ESINGULAR if a pivot is zero (rav_last_error names level and patch).
+ * level in FP64 and stores, for RAV, the owned rows of L_i^{-1} (Sec. 4.3) in
+ * the context's precision, for AV/MV the full inverse.  The inverse is formed
+ * by block elimination: the velocity block of L_i is the same symmetric
+ * positive definite scalar block K_i for every component, so one elimination
+ * on K_i (no pivoting) and the Schur complement of the pressure block give
+ * L_i^{-1} exactly up to rounding.  RAV_ESINGULAR if a pivot of K_i is not
+ * positive or the Schur complement is singular (rav_last_error names level
+ * and patch).
  * For RAV it then times the lanes-per-patch variants of the apply on every
  * bucket and keeps the fastest (environment: RAV_AUTOTUNE=0 keeps a size rule,
  * RAV_AUTOTUNE_LOG=1 prints the timings to stderr). */
@@ -200,7 +206,7 @@ rav_status rav_set_fallback(rav_ctx* ctx, double rho_max, int* fell_back);
 
 /* Host-side patch map of patch `patch` on `level`: its free DoFs in local
  * order (component-major, lexicographic nodes, pressure last) into dofs_host
- * (capacity >= 128), their count into *n, and owned_host[j] = 1 if the DoF is
+ * (capacity >= 376), their count into *n, and owned_host[j] = 1 if the DoF is
  * owned by the patch (restricted prolongation of eq. 13), else 0. */
 rav_status rav_get_patch_map(const rav_ctx* ctx, int level, long patch, int* dofs_host, int* n,
                              int* owned_host);

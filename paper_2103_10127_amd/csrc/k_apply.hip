@@ -413,6 +413,7 @@ void launch_rav_apply_multi(int dim, int kind, int prec, bool edges, const GridD
   } while (0)
   if (dim == 2 && kind == KIND_VERTEX) RAV_MULTI(2, KIND_VERTEX, true);
   else if (dim == 2) RAV_MULTI(2, KIND_ELEMENT, true);
+  else if (kind == KIND_VERTEX) RAV_MULTI(3, KIND_VERTEX, true);
   else if (edges) RAV_MULTI(3, KIND_ELEMENT, true);
   else RAV_MULTI(3, KIND_ELEMENT, false);
 #undef RAV_MULTI
@@ -472,6 +473,7 @@ static void launch_apply_s(int dim, int kind, int cls, int prec, const GridDev* 
                            int ntasks, hipStream_t s) {
   if (dim == 2 && kind == KIND_VERTEX) launch_apply_k<2, KIND_VERTEX, SPLIT>(cls, prec, G, tasks, ntasks, s);
   else if (dim == 2) launch_apply_k<2, KIND_ELEMENT, SPLIT>(cls, prec, G, tasks, ntasks, s);
+  else if (kind == KIND_VERTEX) launch_apply_k<3, KIND_VERTEX, SPLIT>(cls, prec, G, tasks, ntasks, s);
   else launch_apply_k<3, KIND_ELEMENT, SPLIT>(cls, prec, G, tasks, ntasks, s);
 }
 
@@ -480,6 +482,7 @@ void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const Gri
   if (split == APPLY_ROWS) {
     if (dim == 2 && kind == KIND_VERTEX) launch_apply_rows<2, KIND_VERTEX>(prec, G, tasks, ntasks, s);
     else if (dim == 2) launch_apply_rows<2, KIND_ELEMENT>(prec, G, tasks, ntasks, s);
+    else if (kind == KIND_VERTEX) launch_apply_rows<3, KIND_VERTEX>(prec, G, tasks, ntasks, s);
     else launch_apply_rows<3, KIND_ELEMENT>(prec, G, tasks, ntasks, s);
     return;
   }

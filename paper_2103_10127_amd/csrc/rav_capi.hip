@@ -582,8 +582,9 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
   if (d->patch != RAV_PATCH_VERTEX && d->patch != RAV_PATCH_ELEMENT) return set_err(nullptr, RAV_EINVAL, "bad patch kind");
   if (d->smoother < RAV_SMOOTHER_RAV || d->smoother > RAV_SMOOTHER_MV) return set_err(nullptr, RAV_EINVAL, "bad smoother");
   if (d->inv_precision < RAV_FP64 || d->inv_precision > RAV_BF16) return set_err(nullptr, RAV_EINVAL, "bad precision");
-  if (d->dim == 3 && d->patch == RAV_PATCH_VERTEX)
-    return set_err(nullptr, RAV_EUNSUPPORTED, "3D vertex patches (376 DoFs) are not supported; use element patches");
+  if (d->dim == 3 && d->patch == RAV_PATCH_VERTEX && d->smoother != RAV_SMOOTHER_RAV)
+    return set_err(nullptr, RAV_EUNSUPPORTED, "3D vertex patches (376 DoFs) are provided for RAV only: AV/MV "
+                   "would store full 376x376 inverses");
   if (d->smoother != RAV_SMOOTHER_RAV && d->inv_precision != RAV_FP64)
     return set_err(nullptr, RAV_EUNSUPPORTED, "low-precision inverses are provided for RAV only");
 

@@ -43,7 +43,9 @@ def test_invalid_descriptor_rejected_without_device(field, value, status):
 def test_unsupported_combinations():
     lib = capi.lib()
     h = ctypes.c_void_p()
-    d = capi.make_desc(dim=3, n_cells=8, n_levels=2, dmask=ri.ALL_DIRICHLET_3D, kind="vertex")
+    d = capi.make_desc(dim=3, n_cells=8, n_levels=2, dmask=ri.ALL_DIRICHLET_3D, kind="vertex", smoother="av")
+    assert lib.rav_create(ctypes.byref(d), None, ctypes.byref(h)) == -6
+    d = capi.make_desc(dim=3, n_cells=8, n_levels=2, dmask=ri.ALL_DIRICHLET_3D, kind="vertex", smoother="mv")
     assert lib.rav_create(ctypes.byref(d), None, ctypes.byref(h)) == -6
     d = capi.make_desc(smoother="av", precision="bf16")
     assert lib.rav_create(ctypes.byref(d), None, ctypes.byref(h)) == -6
@@ -52,6 +54,7 @@ def test_unsupported_combinations():
 @pytest.mark.parametrize("dim,N,nl,kind,dm", [
     (2, 16, 3, "vertex", ri.ALL_DIRICHLET_2D), (2, 12, 2, "vertex", ri.OUTFLOW_2D),
     (3, 4, 2, "element", ri.ALL_DIRICHLET_3D), (3, 6, 2, "element", ri.OUTFLOW_3D),
+    (3, 4, 2, "vertex", ri.ALL_DIRICHLET_3D), (3, 4, 2, "vertex", ri.OUTFLOW_3D),
     (2, 10, 2, "element", ri.ALL_DIRICHLET_2D)])
 def test_host_maps_match_oracle(dim, N, nl, kind, dm):
     d = capi.make_desc(dim=dim, n_cells=N, n_levels=nl, dmask=dm, kind=kind)
