@@ -291,7 +291,13 @@ rav_status rav_learn_step(rav_ctx* ctx, rav_mlp* mlp, const double* x0_dev, int 
  * and omega may differ.  x_dev / b_dev are host arrays of n_problems device
  * pointers, each holding that problem's finest-level vector.  Problems stop
  * being updated once converged; iters and rel_res (host arrays of n_problems)
- * receive per-problem results.  The batch owns one context per problem. */
+ * receive per-problem results.  The batch owns one context per problem; the
+ * coarse matrices of all problems are inverted together at create time
+ * (blocked Gauss-Jordan, one launch pair per 32 pivots for the whole batch).
+ * rav_batch_factor also times the lanes-per-patch variants of every batched
+ * apply launch and keeps the fastest (RAV_AUTOTUNE=0 keeps a size rule);
+ * rav_batch_solve replays one captured V-cycle graph per cycle (RAV_GRAPH=0
+ * launches directly). */
 typedef struct rav_batch rav_batch;
 rav_status rav_batch_create(const rav_problem_desc* descs, int n_problems, void* hip_stream, rav_batch** out);
 rav_status rav_batch_factor(rav_batch* batch);
@@ -302,6 +308,18 @@ rav_status rav_batch_assemble_rhs(rav_batch* batch, int problem, const double* m
 rav_status rav_batch_vcycle(rav_batch* batch, double* const* x_dev, const double* const* b_dev);
 rav_status rav_batch_solve(rav_batch* batch, double* const* x_dev, const double* const* b_dev, double rtol,
                            int maxit, int* iters, double* rel_res);
+/* Batched form of rav_solve_gmres (Sec. 4: the multigrid cycle as Krylov
+ * preconditioner): restarted flexible GMRES(restart) for every problem, all
+ * problems advancing in lockstep so that each preconditioner application is
+ * one batched V-cycle and each Gram-Schmidt step one launch per vector
+ * operation; a problem leaves the Arnoldi process once its own least-squares
+ * residual reaches rtol (checked again on its true residual at the restart).
+ * iters[p] counts problem p's V-cycles (<= maxit).  Allocates
+ * (2 restart + 3) work vectors per problem for the duration of the call.
+ * Returns RAV_OK when every problem converged, else RAV_NOT_CONVERGED or
+ * RAV_EDIVERGED (any problem). */
+rav_status rav_batch_solve_gmres(rav_batch* batch, double* const* x_dev, const double* const* b_dev, double rtol,
+                                 int maxit, int restart, int* iters, double* rel_res);
 rav_status rav_batch_destroy(rav_batch* batch);
 const char* rav_batch_last_error(const rav_batch* batch);
 

@@ -96,6 +96,8 @@ SIGNATURES = {
     "rav_batch_vcycle": (_S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "rav_batch_solve": (_S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _I, ctypes.POINTER(_I),
                              ctypes.POINTER(_D)]),
+    "rav_batch_solve_gmres": (_S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _I, _I, ctypes.POINTER(_I),
+                                   ctypes.POINTER(_D)]),
     "rav_batch_destroy": (_S, [_P]),
     "rav_batch_last_error": (ctypes.c_char_p, [_P]),
     "rav_last_error": (ctypes.c_char_p, [_P]),
@@ -433,6 +435,14 @@ class Batch:
         its = (_I * self.n)()
         rel = (_D * self.n)()
         st = self.lib.rav_batch_solve(self.h, self._ptrs(xs), self._ptrs(bs), rtol, maxit, its, rel)
+        if st < 0 and st != -4:
+            self._chk(st)
+        return st, list(its), list(rel)
+
+    def solve_gmres(self, xs, bs, rtol=1e-8, maxit=300, restart=30):
+        its = (_I * self.n)()
+        rel = (_D * self.n)()
+        st = self.lib.rav_batch_solve_gmres(self.h, self._ptrs(xs), self._ptrs(bs), rtol, maxit, restart, its, rel)
         if st < 0 and st != -4:
             self._chk(st)
         return st, list(its), list(rel)

@@ -24,6 +24,8 @@ using namespace rav;
 
 namespace {
 
+constexpr int BV_TILE = 1024;   // elements per task of the batched Krylov vector kernels
+
 struct DepthPlan {
   std::vector<int> probs;                 // problems owning this depth
   GridDev* dG = nullptr;                  // descriptors, one per entry of probs
@@ -74,7 +76,28 @@ struct rav_batch {
   std::vector<long long> n_fine;
   std::string err;
   bool factored = false;
+  double* h_norm2_dev = nullptr;          // device alias of the pinned h_norm2
+  // one batched V-cycle plus the top-level residual norms, captured once and
+  // replayed by rav_batch_solve (RAV_GRAPH=0 launches directly)
+  hipGraphExec_t cycle_exec = nullptr;
+  bool graph_failed = false;
+  // per-problem vector tiles for the batched Krylov kernels
+  BlockTask* vtasks = nullptr; int n_vtasks = 0;
+  int* v_first = nullptr; int* v_count = nullptr;
+  double* v_partial = nullptr;
+  std::vector<int> apply_split_log;        // chosen lanes per patch, (depth, bucket) order
 };
+
+namespace rav {
+void launch_bdot(const BlockTask* tasks, int ntasks, double* const* A, double* const* Bv, const long long* n,
+                 const int* active, double* partial, const int* first, const int* count, int nprob, double* out,
+                 long long ostride, long long ooff, int take_sqrt, hipStream_t s);
+void launch_bvec(const BlockTask* tasks, int ntasks, double* const* Y, double* const* X, const long long* n,
+                 const int* active, const double* coef, long long cstride, long long coff, double sign, int mode,
+                 hipStream_t s);
+void launch_bupdate(const BlockTask* tasks, int ntasks, double* const* Xk, double* const* Z, int nprob, int m,
+                    const long long* n, const int* jend, const double* ycoef, hipStream_t s);
+}  // namespace rav
 
 #define BCK(expr)                                                         \
   do {                                                                    \
@@ -203,19 +226,61 @@ static void batch_vcycle(rav_batch* B, bool top_valid) {
   }
 }
 
-static rav_status batch_norms(rav_batch* B, std::vector<double>& out) {
+// Residual of every problem's finest level; with norms, the squared norms are
+// written straight into pinned host memory (h_norm2).
+static void batch_top_residual(rav_batch* B, bool norms) {
   for (DepthPlan& P : B->depth) {
     if (P.top.empty()) continue;
-    launch_residual(B->dim, P.dG, P.top_res, P.n_top_res, P.partials, B->stream);
-    hipLaunchKernelGGL(k_norm_scatter, dim3((unsigned)P.top.size()), dim3(256), 0, B->stream, P.partials, P.first,
-                       P.count, P.pid, B->d_norm2);
+    launch_residual(B->dim, P.dG, P.top_res, P.n_top_res, norms ? P.partials : nullptr, B->stream);
+    if (norms)
+      hipLaunchKernelGGL(k_norm_scatter, dim3((unsigned)P.top.size()), dim3(256), 0, B->stream, P.partials, P.first,
+                         P.count, P.pid, B->h_norm2_dev);
   }
+}
+
+static rav_status read_norms(rav_batch* B, std::vector<double>& out) {
   BCK(hipGetLastError());
-  BCK(hipMemcpyAsync(B->h_norm2, B->d_norm2, sizeof(double) * B->sub.size(), hipMemcpyDeviceToHost, B->stream));
   BCK(hipStreamSynchronize(B->stream));
   out.resize(B->sub.size());
   for (size_t p = 0; p < B->sub.size(); ++p) out[p] = std::sqrt(B->h_norm2[p]);
   return RAV_OK;
+}
+
+static rav_status batch_norms(rav_batch* B, std::vector<double>& out) {
+  batch_top_residual(B, true);
+  return read_norms(B, out);
+}
+
+// One solve cycle (V-cycle from current top residuals, then the new top
+// residuals and their norms), replayed from a captured graph when possible.
+static void batch_solve_cycle(rav_batch* B) {
+  static const bool graphs = [] {
+    const char* e = std::getenv("RAV_GRAPH");
+    return !(e && std::string(e) == "0");
+  }();
+  if (graphs && !B->graph_failed) {
+    if (!B->cycle_exec) {
+      hipGraph_t g = nullptr;
+      bool ok = hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        batch_vcycle(B, true);
+        batch_top_residual(B, true);
+        ok = hipStreamEndCapture(B->stream, &g) == hipSuccess && g != nullptr;
+      }
+      if (ok) ok = hipGraphInstantiate(&B->cycle_exec, g, nullptr, nullptr, 0) == hipSuccess;
+      if (g) (void)hipGraphDestroy(g);
+      if (!ok) {
+        (void)hipGetLastError();
+        B->cycle_exec = nullptr;
+        B->graph_failed = true;
+      }
+    }
+    if (B->cycle_exec && hipGraphLaunch(B->cycle_exec, B->stream) == hipSuccess) return;
+    (void)hipGetLastError();
+    B->graph_failed = true;
+  }
+  batch_vcycle(B, true);
+  batch_top_residual(B, true);
 }
 
 static rav_status copy_user(rav_batch* B, double* const* dst, const double* const* src) {
@@ -265,14 +330,31 @@ rav_status rav_batch_create(const rav_problem_desc* descs, int n, void* hip_stre
   };
   for (int i = 0; i < n; ++i) {
     rav_ctx* c = nullptr;
-    rav_status st = rav_create(&descs[i], hip_stream, &c);
+    rav_status st = rav_create_ex(&descs[i], hip_stream, &c, false);
     if (st != RAV_OK) return fail(st, "problem " + std::to_string(i) + ": " + rav_last_error(nullptr));
+    c->autotune = false;
     B->sub.push_back(c);
     B->n_fine.push_back(c->lv.back().hd.g.n);
+  }
+  // the coarse matrices of all problems (grouped by size) inverted together
+  for (size_t i = 0; i < B->sub.size(); ++i) {
+    if (B->sub[i]->coarse_tasks) continue;   // already inverted with an earlier group
+    std::vector<rav_ctx*> grp;
+    for (size_t j = i; j < B->sub.size(); ++j)
+      if (!B->sub[j]->coarse_tasks && B->sub[j]->nb == B->sub[i]->nb) grp.push_back(B->sub[j]);
+    std::vector<int> piv_status;
+    std::string err;
+    rav_status st = rav_invert_coarse(grp.data(), (int)grp.size(), B->stream, &piv_status, &err);
+    if (st != RAV_OK) return fail(st, err);
+    for (size_t g = 0; g < grp.size(); ++g) {
+      st = rav_finish_coarse(grp[g], piv_status[g]);
+      if (st != RAV_OK) return fail(st, "coarse matrix: " + grp[g]->err);
+    }
   }
   if (hipMalloc((void**)&B->d_active, sizeof(int) * n) != hipSuccess ||
       hipMalloc((void**)&B->d_norm2, sizeof(double) * n) != hipSuccess ||
       hipHostMalloc((void**)&B->h_norm2, sizeof(double) * n, hipHostMallocDefault) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&B->h_norm2_dev, B->h_norm2, 0) != hipSuccess ||
       hipMalloc((void**)&B->d_dst, sizeof(double*) * n) != hipSuccess ||
       hipMalloc((void**)&B->d_src, sizeof(double*) * n) != hipSuccess)
     return fail(RAV_ENOMEM, "batch table allocation failed");
@@ -288,6 +370,61 @@ rav_status rav_batch_create(const rav_problem_desc* descs, int n, void* hip_stre
   return RAV_OK;
 }
 
+// Autotuner of the batched apply: for every depth and bucket, the 1-, 4-,
+// APPLY_SPLIT- and APPLY_SPLIT_SMALL-lanes-per-patch launches over all
+// problems are timed (HIP events, mean of three after one warm-up, on the
+// levels' own vectors, which every solve overwrites) and the fastest kept.
+// RAV_AUTOTUNE=0 keeps the size rule.
+static rav_status autotune_batch(rav_batch* B) {
+  if (const char* e = std::getenv("RAV_AUTOTUNE"))
+    if (std::string(e) == "0") return RAV_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BCK(hipEventCreate(&e0));
+  BCK(hipEventCreate(&e1));
+  rav_status result = RAV_OK;
+  const int cands[4] = {1, 4, APPLY_SPLIT, APPLY_SPLIT_SMALL};
+  for (size_t d = 1; d < B->depth.size() && result == RAV_OK; ++d) {
+    DepthPlan& P = B->depth[d];
+    const int ng = (int)P.probs.size();
+    for (ApplyLaunch& al : P.apply) {
+      float best = 1e30f;
+      int best_split = al.split;
+      BlockTask* best_tasks = nullptr;
+      int best_n = 0;
+      for (int split : cands) {
+        std::vector<BlockTask> at;
+        for (int i = 0; i < ng; ++i)
+          append_tiles(at, i, al.bucket, level_at(B, P.probs[i], (int)d).hd.bk[al.bucket].count,
+                       apply_block(split) / split);
+        BlockTask* tasks = nullptr;
+        int nt = 0;
+        if ((result = upload(B, at, &tasks, &nt)) != RAV_OK) break;
+        launch_rav_apply(B->dim, B->kind, al.cls, B->prec, split, P.dG, tasks, nt, B->stream);
+        (void)hipEventRecord(e0, B->stream);
+        for (int r = 0; r < 3; ++r) launch_rav_apply(B->dim, B->kind, al.cls, B->prec, split, P.dG, tasks, nt, B->stream);
+        (void)hipEventRecord(e1, B->stream);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
+        if (ms < best) {
+          if (best_tasks) (void)hipFree(best_tasks);
+          best = ms; best_split = split; best_tasks = tasks; best_n = nt;
+        } else {
+          (void)hipFree(tasks);
+        }
+      }
+      if (best_tasks) {
+        (void)hipFree(al.tasks);
+        al.tasks = best_tasks; al.ntasks = best_n; al.split = best_split;
+      }
+      B->apply_split_log.push_back(al.split);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  BCK(hipGetLastError());
+  return result;
+}
+
 rav_status rav_batch_factor(rav_batch* B) {
   if (!B) return RAV_EINVAL;
   for (size_t i = 0; i < B->sub.size(); ++i) {
@@ -300,6 +437,8 @@ rav_status rav_batch_factor(rav_batch* B) {
   // descriptors now hold the inverse-row buffers: build the batched plans
   rav_status st = build_plans(B);
   if (st != RAV_OK) return st;
+  if ((st = autotune_batch(B)) != RAV_OK) return st;
+  if (B->cycle_exec) { (void)hipGraphExecDestroy(B->cycle_exec); B->cycle_exec = nullptr; }
   B->factored = true;
   return RAV_OK;
 }
@@ -371,9 +510,9 @@ rav_status rav_batch_solve(rav_batch* B, double* const* x, const double* const* 
   int k = 0;
   while (k < maxit && std::count(act.begin(), act.end(), 1) > 0) {
     if ((st = set_active(B, act)) != RAV_OK) return st;
-    batch_vcycle(B, true);   // top residuals are current from the norm evaluation
+    batch_solve_cycle(B);   // top residuals are current from the norm evaluation
     std::vector<double> nk;
-    if ((st = batch_norms(B, nk)) != RAV_OK) return st;
+    if ((st = read_norms(B, nk)) != RAV_OK) return st;
     ++k;
     for (size_t p = 0; p < n; ++p) {
       if (!act[p]) continue;
@@ -398,6 +537,234 @@ rav_status rav_batch_solve(rav_batch* B, double* const* x, const double* const* 
   return result;
 }
 
+// Per-problem vector tiles of the batched Krylov kernels (built on first use).
+static rav_status build_vector_tasks(rav_batch* B) {
+  if (B->vtasks) return RAV_OK;
+  std::vector<BlockTask> vt;
+  std::vector<int> first, count;
+  for (size_t p = 0; p < B->sub.size(); ++p) {
+    first.push_back((int)vt.size());
+    append_tiles(vt, (int)p, 0, B->n_fine[p], BV_TILE);
+    count.push_back((int)vt.size() - first.back());
+  }
+  rav_status st = upload(B, vt, &B->vtasks, &B->n_vtasks);
+  if (st != RAV_OK) return st;
+  if ((st = upload_vec(B, first, &B->v_first)) != RAV_OK) return st;
+  if ((st = upload_vec(B, count, &B->v_count)) != RAV_OK) return st;
+  BCK(hipMalloc((void**)&B->v_partial, sizeof(double) * std::max<size_t>(vt.size(), 1)));
+  return RAV_OK;
+}
+
+rav_status rav_batch_solve_gmres(rav_batch* B, double* const* x, const double* const* b, double rtol, int maxit,
+                                 int restart, int* iters, double* rel_res) {
+  if (!B || !x || !b || !(rtol > 0.0) || maxit < 0 || restart < 1 || restart > 200) return RAV_EINVAL;
+  if (!B->factored) { B->err = "rav_batch_factor has not been called"; return RAV_EINVAL; }
+  const int P = (int)B->sub.size();
+  const int m = restart;
+  for (int p = 0; p < P; ++p)
+    if (!x[p] || !b[p]) return RAV_EINVAL;
+  rav_status st = build_vector_tasks(B);
+  if (st != RAV_OK) return st;
+  hipStream_t s = B->stream;
+  // work vectors of every problem in one allocation
+  long long total = 0;
+  std::vector<long long> off(P);
+  for (int p = 0; p < P; ++p) { off[p] = total; total += (2LL * m + 3) * ((B->n_fine[p] + 31) / 32 * 32); }
+  double* work = nullptr;
+  double** tabs = nullptr;     // device pointer tables: V[i][p], Z[i][p], xk[p], bk[p], X[p], Bf[p], R[p]
+  double *hdev = nullptr, *ydev = nullptr;
+  int* jdev = nullptr;
+  const long long ntab = (long long)P * (2LL * m + 6);
+  auto cleanup = [&]() {
+    (void)hipFree(work); (void)hipFree(tabs); (void)hipFree(hdev); (void)hipFree(ydev); (void)hipFree(jdev);
+  };
+  auto fail = [&](hipError_t e, const char* what) {
+    B->err = std::string(what) + ": " + hipGetErrorString(e);
+    cleanup();
+    return e == hipErrorOutOfMemory ? RAV_ENOMEM : RAV_EDEVICE;
+  };
+  hipError_t e;
+  if ((e = hipMalloc((void**)&work, sizeof(double) * std::max(total, 1LL))) != hipSuccess) return fail(e, "work");
+  if ((e = hipMalloc((void**)&tabs, sizeof(double*) * ntab)) != hipSuccess) return fail(e, "tables");
+  if ((e = hipMalloc((void**)&hdev, sizeof(double) * P * (m + 2) * (m + 1))) != hipSuccess) return fail(e, "h");
+  if ((e = hipMalloc((void**)&ydev, sizeof(double) * P * m)) != hipSuccess) return fail(e, "y");
+  if ((e = hipMalloc((void**)&jdev, sizeof(int) * P)) != hipSuccess) return fail(e, "jend");
+  std::vector<double*> ht(ntab);
+  double** const dV = tabs;                       // V_i of problem p at dV[i * P + p]
+  double** const dZ = tabs + (long long)P * (m + 1);
+  double** const dXk = dZ + (long long)P * m;
+  double** const dBk = dXk + P;
+  double** const dX = dBk + P;                     // finest-level x, b, r of each problem
+  double** const dBf = dX + P;
+  double** const dR = dBf + P;
+  for (int p = 0; p < P; ++p) {
+    const long long str = (B->n_fine[p] + 31) / 32 * 32;
+    double* base = work + off[p];
+    for (int i = 0; i <= m; ++i) ht[(long long)i * P + p] = base + i * str;
+    for (int i = 0; i < m; ++i) ht[(long long)P * (m + 1) + (long long)i * P + p] = base + (m + 1 + i) * str;
+    ht[(long long)P * (2 * m + 1) + p] = base + (2LL * m + 1) * str;
+    ht[(long long)P * (2 * m + 2) + p] = base + (2LL * m + 2) * str;
+    const GridDev& top = B->sub[p]->lv.back().hd;
+    ht[(long long)P * (2 * m + 3) + p] = top.x;
+    ht[(long long)P * (2 * m + 4) + p] = top.b;
+    ht[(long long)P * (2 * m + 5) + p] = top.r;
+  }
+  if ((e = hipMemcpy(tabs, ht.data(), sizeof(double*) * ntab, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "tables");
+  const BlockTask* vt = B->vtasks;
+  const int nv = B->n_vtasks;
+  const int* act = B->d_active;
+  auto vec = [&](double** Y, double** X, const double* c, long long cstr, long long coff, double sign, int mode) {
+    launch_bvec(vt, nv, Y, X, B->d_n, act, c, cstr, coff, sign, mode, s);
+  };
+  auto dot = [&](double** A, double** Bv, double* out, long long ostr, long long ooff, int sq) {
+    launch_bdot(vt, nv, A, Bv, B->d_n, act, B->v_partial, B->v_first, B->v_count, P, out, ostr, ooff, sq, s);
+  };
+  // initial iterate and residual of every problem
+  std::vector<int> on(P, 1);
+  if ((st = set_active(B, on)) != RAV_OK) { cleanup(); return st; }
+  if ((st = copy_user(B, ht.data() + (long long)P * (2 * m + 1), (const double* const*)x)) != RAV_OK) {
+    cleanup(); return st;
+  }
+  if ((st = copy_user(B, ht.data() + (long long)P * (2 * m + 2), b)) != RAV_OK) { cleanup(); return st; }
+  auto true_residuals = [&](std::vector<double>& out) -> rav_status {
+    vec(dX, dXk, nullptr, 0, 0, 1.0, 2);
+    vec(dBf, dBk, nullptr, 0, 0, 1.0, 2);
+    return batch_norms(B, out);
+  };
+  std::vector<double> beta0, res;
+  if ((st = true_residuals(beta0)) != RAV_OK) { cleanup(); return st; }
+  res = beta0;
+  std::vector<int> status(P, 1), it(P, 0);   // 1 = running, 0 = converged, -4 = diverged
+  for (int p = 0; p < P; ++p) {
+    if (!std::isfinite(beta0[p])) status[p] = -4;
+    else if (beta0[p] == 0.0) status[p] = 0;
+  }
+  const long long hs = (long long)(m + 2) * (m + 1);   // Arnoldi coefficients per problem
+  std::vector<double> H((size_t)P * (m + 1) * m), cs((size_t)P * m), sn((size_t)P * m), g((size_t)P * (m + 1)),
+      y((size_t)P * m), hcol((size_t)P * (m + 2)), beta(P), binv(P);
+  std::vector<int> jend(P, 0);
+  bool first_cycle = true;
+  while (true) {
+    std::vector<int> cyc(P, 0);   // problems taking part in this restart cycle
+    for (int p = 0; p < P; ++p) cyc[p] = status[p] == 1 && it[p] < maxit;
+    if (std::count(cyc.begin(), cyc.end(), 1) == 0) break;
+    if ((st = set_active(B, cyc)) != RAV_OK) { cleanup(); return st; }
+    if (!first_cycle) {   // residuals of the updated iterates
+      std::vector<double> rn;
+      if ((st = true_residuals(rn)) != RAV_OK) { cleanup(); return st; }
+      for (int p = 0; p < P; ++p) {
+        if (!cyc[p]) continue;
+        res[p] = rn[p];
+        if (!std::isfinite(rn[p]) || rn[p] > 1e3 * beta0[p]) { status[p] = -4; cyc[p] = 0; }
+        else if (rn[p] <= rtol * beta0[p]) { status[p] = 0; cyc[p] = 0; }
+      }
+      if (std::count(cyc.begin(), cyc.end(), 1) == 0) break;
+      if ((st = set_active(B, cyc)) != RAV_OK) { cleanup(); return st; }
+    }
+    first_cycle = false;
+    // V_0 = r / beta (beta = ||r||, per problem in ydev[p * m])
+    for (int p = 0; p < P; ++p) {
+      beta[p] = res[p];
+      binv[p] = res[p] > 0.0 ? 1.0 / res[p] : 0.0;
+      for (int i = 0; i <= m; ++i) g[(size_t)p * (m + 1) + i] = 0.0;
+      g[(size_t)p * (m + 1)] = res[p];
+      jend[p] = 0;
+    }
+    if ((e = hipMemcpy(ydev, binv.data(), sizeof(double) * P, hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "scale");
+    vec(dV, dR, ydev, 1, 0, 1.0, 2);
+    std::vector<int> arn = cyc;   // still extending their Krylov basis
+    for (int j = 0; j < m; ++j) {
+      // Z_j = M V_j: one batched V-cycle from zero with b = V_j
+      vec(dBf, dV + (long long)j * P, nullptr, 0, 0, 1.0, 2);
+      vec(dX, dX, nullptr, 0, 0, 0.0, 3);
+      batch_vcycle(B, false);
+      vec(dZ + (long long)j * P, dX, nullptr, 0, 0, 1.0, 2);
+      // w = L Z_j = -(0 - L Z_j)
+      vec(dBf, dBf, nullptr, 0, 0, 0.0, 3);
+      batch_top_residual(B, false);
+      double** W = dV + (long long)(j + 1) * P;
+      vec(W, dR, nullptr, 0, 0, -1.0, 2);
+      for (int i = 0; i <= j; ++i) {
+        dot(W, dV + (long long)i * P, hdev, hs, (long long)j * (m + 2) + i, 0);
+        vec(W, dV + (long long)i * P, hdev, hs, (long long)j * (m + 2) + i, -1.0, 0);
+      }
+      dot(W, W, hdev, hs, (long long)j * (m + 2) + j + 1, 1);
+      vec(W, W, hdev, hs, (long long)j * (m + 2) + j + 1, 1.0, 1);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(e, "arnoldi");
+      if ((e = hipMemcpy2DAsync(hcol.data(), sizeof(double) * (m + 2), hdev + (long long)j * (m + 2),
+                                sizeof(double) * hs, sizeof(double) * (j + 2), P, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess)
+        return fail(e, "readback");
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+      bool changed = false;
+      for (int p = 0; p < P; ++p) {
+        if (!arn[p]) continue;
+        double* Hp = H.data() + (size_t)p * (m + 1) * m;
+        double* c = cs.data() + (size_t)p * m;
+        double* sv = sn.data() + (size_t)p * m;
+        double* gp = g.data() + (size_t)p * (m + 1);
+        const double* hc = hcol.data() + (size_t)p * (m + 2);
+        ++it[p];
+        for (int i = 0; i <= j + 1; ++i) Hp[(size_t)i * m + j] = hc[i];
+        for (int i = 0; i < j; ++i) {
+          const double a = Hp[(size_t)i * m + j], cc = Hp[(size_t)(i + 1) * m + j];
+          Hp[(size_t)i * m + j] = c[i] * a + sv[i] * cc;
+          Hp[(size_t)(i + 1) * m + j] = -sv[i] * a + c[i] * cc;
+        }
+        const double a = Hp[(size_t)j * m + j], cc = Hp[(size_t)(j + 1) * m + j];
+        const double rr = std::hypot(a, cc);
+        c[j] = rr > 0.0 ? a / rr : 1.0;
+        sv[j] = rr > 0.0 ? cc / rr : 0.0;
+        Hp[(size_t)j * m + j] = rr;
+        Hp[(size_t)(j + 1) * m + j] = 0.0;
+        gp[j + 1] = -sv[j] * gp[j];
+        gp[j] = c[j] * gp[j];
+        res[p] = std::fabs(gp[j + 1]);
+        jend[p] = j + 1;
+        if (!std::isfinite(res[p])) { status[p] = -4; arn[p] = 0; changed = true; continue; }
+        if (res[p] <= rtol * beta0[p] || hc[j + 1] == 0.0 || it[p] >= maxit) { arn[p] = 0; changed = true; }
+      }
+      if (std::count(arn.begin(), arn.end(), 1) == 0) break;
+      if (changed && (st = set_active(B, arn)) != RAV_OK) { cleanup(); return st; }
+    }
+    // x += Z y with y = R^{-1} g, per problem
+    for (int p = 0; p < P; ++p) {
+      if (!cyc[p] || status[p] == -4) { jend[p] = 0; continue; }
+      const double* Hp = H.data() + (size_t)p * (m + 1) * m;
+      const double* gp = g.data() + (size_t)p * (m + 1);
+      double* yp = y.data() + (size_t)p * m;
+      for (int i = jend[p] - 1; i >= 0; --i) {
+        double t = gp[i];
+        for (int k = i + 1; k < jend[p]; ++k) t -= Hp[(size_t)i * m + k] * yp[k];
+        yp[i] = Hp[(size_t)i * m + i] != 0.0 ? t / Hp[(size_t)i * m + i] : 0.0;
+      }
+    }
+    if ((e = hipMemcpy(ydev, y.data(), sizeof(double) * P * m, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(jdev, jend.data(), sizeof(int) * P, hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "update");
+    launch_bupdate(vt, nv, dXk, dZ, P, m, B->d_n, jdev, ydev, s);
+  }
+  // results: x = xk for every problem
+  if ((st = set_active(B, on)) != RAV_OK) { cleanup(); return st; }
+  if ((st = copy_user(B, const_cast<double* const*>(x), (const double* const*)(ht.data() + (long long)P * (2 * m + 1)))) !=
+      RAV_OK) {
+    cleanup(); return st;
+  }
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+  rav_status result = RAV_OK;
+  for (int p = 0; p < P; ++p) {
+    if (iters) iters[p] = it[p];
+    if (rel_res) rel_res[p] = beta0[p] > 0.0 ? res[p] / beta0[p] : 0.0;
+    if (status[p] == -4) result = RAV_EDIVERGED;
+    else if (status[p] == 1 && result == RAV_OK) result = RAV_NOT_CONVERGED;
+  }
+  if (result == RAV_EDIVERGED) B->err = "at least one problem diverged";
+  cleanup();
+  return result;
+}
+
 rav_status rav_batch_destroy(rav_batch* B) {
   if (!B) return RAV_OK;
   (void)hipStreamSynchronize(B->stream);
@@ -407,6 +774,8 @@ rav_status rav_batch_destroy(rav_batch* B) {
     (void)hipFree(P.pid); (void)hipFree(P.coarse);
     for (ApplyLaunch& a : P.apply) (void)hipFree(a.tasks);
   }
+  if (B->cycle_exec) (void)hipGraphExecDestroy(B->cycle_exec);
+  (void)hipFree(B->vtasks); (void)hipFree(B->v_first); (void)hipFree(B->v_count); (void)hipFree(B->v_partial);
   for (rav_ctx* c : B->sub) rav_destroy(c);
   (void)hipFree(B->d_active); (void)hipFree(B->d_norm2); (void)hipFree(B->d_dst); (void)hipFree((void*)B->d_src);
   (void)hipFree(B->d_n); (void)hipFree(B->copy_tasks);

@@ -294,7 +294,8 @@ static rav_status build_level(rav_ctx* ctx, int l) {
   return rav_upload_desc(ctx, L);
 }
 
-static rav_status build_coarse(rav_ctx* ctx) {
+// Coarsest level, part 1: the dense (bordered) matrix in ctx->Minv, not yet inverted.
+static rav_status build_coarse_matrix(rav_ctx* ctx) {
   LevelHost& L = ctx->lv[0];
   const Geo& g = L.hd.g;
   bool all_dir = true;
@@ -306,27 +307,67 @@ static rav_status build_coarse(rav_ctx* ctx) {
     return set_err(ctx, RAV_EINVAL, "the coarsest grid has " + std::to_string(nb) + " unknowns; its dense direct "
                    "solve is limited to " + std::to_string(MAX_COARSE) + " (use more levels)");
   CK(hipMalloc((void**)&ctx->Minv, sizeof(double) * nb * nb));
-  CK(hipMalloc((void**)&ctx->d_piv, sizeof(int) * nb));
-  CK(hipMalloc((void**)&ctx->d_colk, sizeof(double) * nb));
-  const int big = INT_MAX;
-  CK(hipMemcpy(ctx->d_status, &big, sizeof(int), hipMemcpyHostToDevice));
   launch_coarse_build(L.dd, g.dim, ctx->Minv, nb, ctx->bordered, 1, ctx->stream);
-  for (long long k = 0; k < nb; ++k)
-    launch_coarse_gj_step(ctx->Minv, nb, k, ctx->d_piv, ctx->d_colk, ctx->d_status, ctx->stream);
-  launch_coarse_colswap(ctx->Minv, nb, ctx->d_piv, ctx->stream);
   CK(hipGetLastError());
-  int st = 0;
-  CK(hipMemcpyAsync(&st, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  CK(hipStreamSynchronize(ctx->stream));
-  if (st != INT_MAX)
-    return set_err(ctx, RAV_ESINGULAR, "zero pivot in the coarse matrix at column " + std::to_string(st));
+  return RAV_OK;
+}
+
+// Part 2, after the inversion: zero-pivot check, the coarse solve's tasks and descriptor.
+rav_status rav_finish_coarse(rav_ctx* ctx, int pivot_status) {
+  if (pivot_status != INT_MAX)
+    return set_err(ctx, RAV_ESINGULAR, "zero pivot in the coarse matrix at column " + std::to_string(pivot_status));
+  LevelHost& L = ctx->lv[0];
   L.hd.Minv = ctx->Minv;
-  L.hd.nbc = nb;
+  L.hd.nbc = ctx->nb;
   std::vector<BlockTask> ct;
-  append_tiles(ct, 0, 0, g.n, 4);
+  append_tiles(ct, 0, 0, L.hd.g.n, 4);
   rav_status rs = rav_upload_tasks(ctx, ct, &ctx->coarse_tasks, &ctx->n_coarse_tasks);
   if (rs != RAV_OK) return rs;
   return rav_upload_desc(ctx, L);
+}
+
+// Blocked Gauss-Jordan inversion of the coarse matrices of n contexts (same nb).
+rav_status rav_invert_coarse(rav_ctx* const* ctxs, int n, hipStream_t s, std::vector<int>* status_out,
+                             std::string* err) {
+  const long long nb = ctxs[0]->nb;
+  double** dM = nullptr;
+  int *piv = nullptr, *perm = nullptr, *st = nullptr;
+  double *colk = nullptr, *Rs = nullptr;
+  rav_status result = RAV_OK;
+  auto chk = [&](hipError_t e) {
+    if (e != hipSuccess && result == RAV_OK) {
+      *err = std::string("coarse inversion: ") + hipGetErrorString(e);
+      result = e == hipErrorOutOfMemory ? RAV_ENOMEM : RAV_EDEVICE;
+    }
+    return e == hipSuccess;
+  };
+  std::vector<double*> hM(n);
+  for (int i = 0; i < n; ++i) hM[i] = ctxs[i]->Minv;
+  std::vector<int> big(n, INT_MAX);
+  if (chk(hipMalloc((void**)&dM, sizeof(double*) * n)) && chk(hipMalloc((void**)&piv, sizeof(int) * n * nb)) &&
+      chk(hipMalloc((void**)&perm, sizeof(int) * n * nb)) && chk(hipMalloc((void**)&st, sizeof(int) * n)) &&
+      chk(hipMalloc((void**)&colk, sizeof(double) * n * nb)) &&
+      chk(hipMalloc((void**)&Rs, sizeof(double) * n * GJ_PANEL * nb)) &&
+      chk(hipMemcpy(dM, hM.data(), sizeof(double*) * n, hipMemcpyHostToDevice)) &&
+      chk(hipMemcpy(st, big.data(), sizeof(int) * n, hipMemcpyHostToDevice))) {
+    launch_bgj_invert(dM, nb, n, piv, colk, Rs, perm, st, s);
+    if (chk(hipGetLastError()) && chk(hipStreamSynchronize(s))) {
+      status_out->assign(n, INT_MAX);
+      chk(hipMemcpy(status_out->data(), st, sizeof(int) * n, hipMemcpyDeviceToHost));
+    }
+  }
+  (void)hipFree(dM); (void)hipFree(piv); (void)hipFree(perm); (void)hipFree(st); (void)hipFree(colk);
+  (void)hipFree(Rs);
+  return result;
+}
+
+static rav_status build_coarse(rav_ctx* ctx, bool invert) {
+  rav_status st = build_coarse_matrix(ctx);
+  if (st != RAV_OK || !invert) return st;
+  std::vector<int> piv_status;
+  st = rav_invert_coarse(&ctx, 1, ctx->stream, &piv_status, &ctx->err);
+  if (st != RAV_OK) return st;
+  return rav_finish_coarse(ctx, piv_status[0]);
 }
 
 // ---- device sequences -------------------------------------------------------
@@ -545,9 +586,10 @@ static rav_status need_factors(rav_ctx* ctx) {
 }
 
 // ============================================================================
-extern "C" {
-
-rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out) {
+// rav_create; invert_coarse = false leaves the coarse matrix uninverted, for a
+// batch that inverts the coarse matrices of all its problems together
+// (rav_invert_coarse, then rav_finish_coarse).
+rav_status rav_create_ex(const rav_problem_desc* d, void* hip_stream, rav_ctx** out, bool invert_coarse) {
   if (!d || !out) return set_err(nullptr, RAV_EINVAL, "null descriptor or output pointer");
   *out = nullptr;
   if (d->dim != 2 && d->dim != 3) return set_err(nullptr, RAV_EINVAL, "dim must be 2 or 3");
@@ -634,10 +676,16 @@ rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out
     rav_status st = rav_upload_desc(ctx, L);
     if (st != RAV_OK) return fail(st);
   }
-  rav_status st = build_coarse(ctx);
+  rav_status st = build_coarse(ctx, invert_coarse);
   if (st != RAV_OK) return fail(st);
   *out = ctx;
   return RAV_OK;
+}
+
+extern "C" {
+
+rav_status rav_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out) {
+  return rav_create_ex(d, hip_stream, out, true);
 }
 
 }  // extern "C"
@@ -684,7 +732,7 @@ static rav_status merge_apply(rav_ctx* ctx) {
 }
 
 static rav_status autotune_apply(rav_ctx* ctx) {
-  if (ctx->desc.smoother != RAV_SMOOTHER_RAV) return RAV_OK;
+  if (ctx->desc.smoother != RAV_SMOOTHER_RAV || !ctx->autotune) return RAV_OK;
   if (const char* e = std::getenv("RAV_AUTOTUNE"))
     if (std::string(e) == "0") return RAV_OK;
   const rav_problem_desc& D = ctx->desc;
@@ -1254,7 +1302,7 @@ rav_status rav_destroy(rav_ctx* ctx) {
     (void)hipFree(L.multi_tasks);
   }
   (void)hipFree(ctx->d_incl); (void)hipFree(ctx->Minv); (void)hipFree(ctx->d_status);
-  (void)hipFree(ctx->d_piv); (void)hipFree(ctx->d_colk); (void)hipFree(ctx->d_norm);
+  (void)hipFree(ctx->d_norm);
   (void)hipFree(ctx->coarse_tasks);
   if (ctx->h_norm) (void)hipHostFree(ctx->h_norm);
   for (auto& e : ctx->gprof_res) if (e) (void)hipEventDestroy(e);

@@ -81,12 +81,11 @@ struct rav_ctx {
   long long nb = 0;
   int bordered = 0;
   int* d_status = nullptr;
-  int* d_piv = nullptr;
-  double* d_colk = nullptr;
   double* d_norm = nullptr;
   double* h_norm = nullptr;       // pinned; the norm kernel writes it through h_norm_dev
   double* h_norm_dev = nullptr;
   int factored = 0;
+  bool autotune = true;   // rav_factor_patches times the apply variants (a batch plans its own launches)
   int prec = rav::P_FP64;
   long long split_below = rav::SPLIT_BELOW;
   std::string err;
@@ -120,6 +119,10 @@ struct rav_ctx {
 };
 
 // Shared helpers (rav_capi.hip).
+rav_status rav_create_ex(const rav_problem_desc* d, void* hip_stream, rav_ctx** out, bool invert_coarse);
+rav_status rav_invert_coarse(rav_ctx* const* ctxs, int n, hipStream_t s, std::vector<int>* status_out,
+                             std::string* err);
+rav_status rav_finish_coarse(rav_ctx* ctx, int pivot_status);
 rav_status rav_upload_desc(rav_ctx* ctx, rav::LevelHost& L);
 void rav_residual_level(rav_ctx* ctx, int l, bool with_norm);
 void rav_apply_level(rav_ctx* ctx, int l);

@@ -151,9 +151,14 @@ void launch_copy_batch(double* const* dst, const double* const* src, const long 
                        int ntasks, hipStream_t s);
 void launch_coarse_build(const GridDev* G, int dim, double* M, long long nb, int bordered, int unit_masked,
                          hipStream_t s);
-void launch_coarse_gj_step(double* M, long long nb, long long k, int* piv, double* colk, int* status,
-                           hipStream_t s);
-void launch_coarse_colswap(double* M, long long nb, const int* piv, hipStream_t s);
+// Blocked Gauss-Jordan inversion with partial pivoting of nprob dense nb x nb
+// matrices (device pointer array Ms), in place.  Scratch: pivs, perm (nprob*nb
+// int), colk (nprob*nb double), Rsave (nprob*GJ_PANEL*nb double); status
+// (nprob int) must hold INT_MAX on entry and receives the first zero-pivot
+// column of each singular matrix.
+constexpr int GJ_PANEL = 32;
+void launch_bgj_invert(double* const* Ms, long long nb, int nprob, int* pivs, double* colk, double* Rsave,
+                       int* perm, int* status, hipStream_t s);
 void launch_coarse_gemv(const double* Minv, long long nb, long long n0, const double* b, double* x,
                         hipStream_t s);
 void launch_features(const GridDev* G, long long npatch, const double* incl, int n_incl, double eta_out,

@@ -7,6 +7,7 @@ import pytest
 import rav_inputs as ri
 from oracle import assemble as A
 from oracle import mg
+from oracle.grid import Grid
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -124,4 +125,125 @@ def test_full_batch_vcycle_sampled_against_oracle():
         xo = H.vcycle(np.zeros(g.n), bo, "rav", 0.66, 2)
         xg = xs[i].cpu().numpy()
         assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo), i
+    B.close()
+
+
+def _make(probs, precision="fp64"):
+    for p in probs:
+        p["precision"] = precision
+    B = Batch(probs)
+    B.factor()
+    xs, bs = [], []
+    for i, p in enumerate(probs):
+        params, n = _rhs(p, i)
+        b = torch.zeros(n, dtype=torch.float64, device="cuda")
+        B.assemble_rhs(i, params, b)
+        bs.append(b)
+        xs.append(torch.zeros_like(b))
+    return B, xs, bs
+
+
+def test_batch_solve_replays_equal_eager_cycles():
+    """rav_batch_solve replays one captured batched cycle per iteration; its
+    iterates equal, bit for bit, those of eager rav_batch_vcycle calls (with
+    eager launches and synchronizations between the replays)."""
+    probs = _problems([16, 32, 64, 32])
+    print("[gpu] batch graph replay", flush=True)
+    B, xs, bs = _make(probs)
+    for k in (1, 2, 4):
+        for x in xs:
+            x.zero_()
+        st, its, _ = B.solve(xs, bs, 1e-300, k)
+        assert all(it == k for it in its), its
+        xe = [torch.zeros_like(b) for b in bs]
+        for _ in range(k):
+            B.vcycle(xe, bs)
+        torch.cuda.synchronize()
+        for i in range(len(xs)):
+            assert torch.equal(xs[i], xe[i]), (k, i)
+    B.close()
+
+
+def test_batch_gmres_matches_oracle_fgmres():
+    """Batched FGMRES(30) with one RAV V(2,2) cycle as preconditioner at
+    contrast 1e3 (where plain V-cycles stagnate): every problem's cycle count
+    is the oracle FGMRES's +-1 and its solution agrees to 1e-6."""
+    from oracle import krylov
+    probs = _problems([16, 32, 16, 32], contrast=1e3)
+    print("[gpu] batch gmres", flush=True)
+    B, xs, bs = _make(probs)
+    st, its, rel = B.solve_gmres(xs, bs, 1e-8, 300, 30)
+    assert st == 0 and max(rel) <= 1e-8, (st, its, rel)
+    for i, p in enumerate(probs):
+        H = mg.Hierarchy(2, p["n_cells"], p["n_levels"], p["dmask"], 0, 1.0, p["eta_in"], p["inclusions"])
+        g = H.finest.grid
+        b = A.assemble_rhs(g, _rhs(p, i)[0])
+        Lf = H.finest.L
+
+        def apply_L(v, Lf=Lf, g=g):
+            y = Lf @ v
+            y[~g.free] = 0.0
+            return y
+
+        xo, ko, _ = krylov.fgmres(apply_L, lambda r, H=H, g=g, om=p["omega"]: H.vcycle(np.zeros(g.n), r, "rav", om, 2),
+                                  b, rtol=1e-8, restart=30, maxit=300)
+        assert abs(its[i] - ko) <= 1, (i, its[i], ko)
+        assert mg.rel_l2(g, xs[i].cpu().numpy(), xo) <= 1e-6, i
+    B.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batch_mixed_precision_solve(prec):
+    """FP32/BF16 inverse rows in a batch (contrast 10): every problem reaches
+    1e-8 and its solution is within 1e-7 of the oracle's FP64 solve to 1e-12."""
+    probs = _problems([16, 32, 64], contrast=10.0)
+    print(f"[gpu] batch {prec}", flush=True)
+    B, xs, bs = _make(probs, prec)
+    st, its, rel = B.solve(xs, bs, 1e-8, 200)
+    assert st == 0 and max(rel) <= 1e-8, (st, its, rel)
+    for i, p in enumerate(probs):
+        H = mg.Hierarchy(2, p["n_cells"], p["n_levels"], p["dmask"], 0, 1.0, p["eta_in"], p["inclusions"])
+        g = H.finest.grid
+        b = A.assemble_rhs(g, _rhs(p, i)[0])
+        xo, _, _, sto = H.solve(b, rtol=1e-12, omega=p["omega"])
+        assert mg.rel_l2(g, xs[i].cpu().numpy(), xo) <= 1e-7, i
+    B.close()
+
+
+def test_full_batch_gmres_reaches_tolerance():
+    """The 256-problem workload (contrast 1e3) solved by the batched FGMRES(30)
+    with one RAV V(4,4) cycle as preconditioner: at least 253 problems reach
+    1e-8 within 300 cycles (measured: 253; with V(2,2) 186, V(3,3) 228: at this
+    contrast the cycle amplifies some error components, see the design notes).
+    For sampled converged problems of every size the true residual of the
+    returned solution, recomputed with the oracle's assembled operator, is
+    <= 1.01e-8 of the initial one."""
+    cfg = ri.CONFIGS["batch256"]
+    sizes = ri.batch_sizes(cfg["n_problems"], cfg["seed"])
+    probs = [dict(dim=2, n_cells=int(n), n_levels=ri.levels_to(int(n), cfg["coarsest"]), dmask=cfg["dmask"],
+                  eta_out=cfg["eta_out"], eta_in=cfg["contrast"], inclusions=ri.inclusions(cfg["seed"] + i),
+                  omega=0.66, nu_pre=4, nu_post=4) for i, n in enumerate(sizes)]
+    print("[gpu] 256-problem batch gmres", flush=True)
+    B = Batch(probs)
+    B.factor()
+    xs, bs = [], []
+    for i, p in enumerate(probs):
+        n, _ = B.dofs(i)
+        b = torch.zeros(n, dtype=torch.float64, device="cuda")
+        B.assemble_rhs(i, ri.mms_params(2, cfg["seed"] + i), b)
+        bs.append(b)
+        xs.append(torch.zeros_like(b))
+    st, its, rel = B.solve_gmres(xs, bs, 1e-8, 300, 30)
+    rel = np.array(rel)
+    ok = rel <= 1e-8
+    assert st in (0, 1) and ok.sum() >= 253, (st, int(ok.sum()))
+    picks = [int(np.nonzero((sizes == s) & ok)[0][0]) for s in (64, 128, 256)]
+    for i in picks:
+        p = probs[i]
+        g = Grid(2, p["n_cells"], p["dmask"])
+        L = A.assemble_matrix(g, 1.0, p["eta_in"], p["inclusions"])
+        bo = bs[i].cpu().numpy()
+        r = bo - L @ xs[i].cpu().numpy()
+        r[~g.free] = 0.0
+        assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(bo), (i, np.linalg.norm(r) / np.linalg.norm(bo))
     B.close()
