@@ -83,6 +83,11 @@ typedef struct {
   double omega;                 /* damping, > 0 (Sec. 4: 0.66 RAV/MV, 0.1 AV)    */
   int nu_pre, nu_post;          /* smoothing steps, >= 0                         */
   rav_precision inv_precision;  /* RAV only; AV/MV store FP64 full inverses      */
+  int coarse_galerkin;          /* 0: every level rediscretised (Sec. 4); 1: the
+                                   viscous block of each coarser level is the
+                                   Galerkin product P^T A P of the finest one
+                                   (cell integrals by the finest grid's Gauss
+                                   points; equal to 0 at constant viscosity) */
 } rav_problem_desc;
 
 typedef struct rav_ctx rav_ctx;

@@ -32,9 +32,9 @@ RAV, AV, MV = "rav", "av", "mv"
 
 
 class Level:
-    def __init__(self, dim, N, dmask, kind, eta_out, eta_in, incl, smooth=True):
+    def __init__(self, dim, N, dmask, kind, eta_out, eta_in, incl, smooth=True, L=None):
         self.grid = Grid(dim, N, dmask)
-        self.L = assemble_matrix(self.grid, eta_out, eta_in, incl)
+        self.L = assemble_matrix(self.grid, eta_out, eta_in, incl) if L is None else L
         self.free = self.grid.free
         self.kind = kind
         self.P = None
@@ -54,17 +54,30 @@ class Level:
 
 
 class Hierarchy:
+    """coarse='rediscretised' assembles every level (Sec. 4); coarse='galerkin'
+    takes L_{l-1} = P_l^T L_l P_l from the finest level down (the variational
+    coarse operator, here only as a literal sparse triple product)."""
+
     def __init__(self, dim, n_cells, n_levels, dmask, kind=VERTEX,
-                 eta_out=1.0, eta_in=1.0, incl=None):
+                 eta_out=1.0, eta_in=1.0, incl=None, coarse="rediscretised"):
         if n_cells % (2 ** (n_levels - 1)):
             raise ValueError("n_cells must be divisible by 2^(n_levels-1)")
+        if coarse not in ("rediscretised", "galerkin"):
+            raise ValueError(coarse)
         self.dim = dim
+        Ns = [n_cells // 2 ** (n_levels - 1 - l) for l in range(n_levels)]
+        grids = [Grid(dim, N, dmask) for N in Ns]
+        Ps = [None] + [prolongation(grids[l], grids[l - 1]) for l in range(1, n_levels)]
+        Ls = [None] * n_levels
+        if coarse == "galerkin":
+            Ls[-1] = assemble_matrix(grids[-1], eta_out, eta_in, incl)
+            for l in range(n_levels - 1, 0, -1):
+                Ls[l - 1] = (Ps[l].T @ Ls[l] @ Ps[l]).tocsr()
         self.levels = []
         for l in range(n_levels):
-            N = n_cells // 2 ** (n_levels - 1 - l)
-            self.levels.append(Level(dim, N, dmask, kind, eta_out, eta_in, incl, smooth=l > 0))
+            self.levels.append(Level(dim, Ns[l], dmask, kind, eta_out, eta_in, incl, smooth=l > 0, L=Ls[l]))
         for l in range(1, n_levels):
-            self.levels[l].P = prolongation(self.levels[l].grid, self.levels[l - 1].grid)
+            self.levels[l].P = Ps[l]
         self._coarse_setup()
 
     @property

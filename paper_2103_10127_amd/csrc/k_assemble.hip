@@ -22,9 +22,29 @@ void set_ref_tables(const RefTables& t, hipStream_t s) {
 
 // ---- viscosity at the Gauss points of every cell ---------------------------
 // etaq[cell * nq + q]; uniform[cell] = 1 when all nq values are equal.
+// Viscosity at a point: eta_in inside any inclusion (closed disc/ball), else eta_out.
+template <int DIM>
+__device__ __forceinline__ double eta_at(const double* x, const double* incl, int n_incl, double eta_out,
+                                         double eta_in) {
+#pragma clang fp contract(off)
+  bool inside = false;
+  for (int i = 0; i < n_incl; ++i) {
+    const double* ic = incl + 4 * i;
+    double d2 = 0.0;
+    for (int d = 0; d < DIM; ++d) { double dd = x[d] - ic[d]; d2 = d2 + dd * dd; }
+    double rad = ic[3];
+    inside = inside || (d2 <= rad * rad);
+  }
+  return inside ? eta_in : eta_out;
+}
+
+// R = 1: the cell's own 3^d Gauss points.  R > 1 (Galerkin coarse operator):
+// the Gauss points of the R^d finest-grid cells inside the cell; the cell is
+// uniform when they all see one viscosity, and then every entry of etaq is
+// that value (non-uniform cells use their integrated cell matrix instead).
 template <int DIM>
 __global__ __launch_bounds__(256) void k_eta(const GridDev* G, const double* incl, int n_incl,
-                                              double eta_out, double eta_in, double* etaq,
+                                              double eta_out, double eta_in, int R, double* etaq,
                                               unsigned char* uniform) {
 #pragma clang fp contract(off)
   constexpr int NQ = ipow(3, DIM);
@@ -38,22 +58,37 @@ __global__ __launch_bounds__(256) void k_eta(const GridDev* G, const double* inc
   const double h = G->h;
   bool uni = true;
   double first = 0.0;
-  for (int q = 0; q < NQ; ++q) {
-    int qq = q;
-    double x[3];
-    for (int d = 0; d < DIM; ++d) { x[d] = ((double)E[d] + c_ref.gt[qq % 3]) * h; qq /= 3; }
-    bool inside = false;
-    for (int i = 0; i < n_incl; ++i) {
-      const double* ic = incl + 4 * i;
-      double d2 = 0.0;
-      for (int d = 0; d < DIM; ++d) { double dd = x[d] - ic[d]; d2 = d2 + dd * dd; }
-      double rad = ic[3];
-      inside = inside || (d2 <= rad * rad);
+  if (R == 1) {
+    for (int q = 0; q < NQ; ++q) {
+      int qq = q;
+      double x[3];
+      for (int d = 0; d < DIM; ++d) { x[d] = ((double)E[d] + c_ref.gt[qq % 3]) * h; qq /= 3; }
+      const double v = eta_at<DIM>(x, incl, n_incl, eta_out, eta_in);
+      etaq[e * NQ + q] = v;
+      if (q == 0) first = v;
+      uni = uni && (v == first);
     }
-    double v = inside ? eta_in : eta_out;
-    etaq[e * NQ + q] = v;
-    if (q == 0) first = v;
-    uni = uni && (v == first);
+  } else {
+    const double hf = h / R;   // finest-grid cell size
+    long long nsub = 1;
+    for (int d = 0; d < DIM; ++d) nsub *= R;
+    for (long long sidx = 0; sidx < nsub && uni; ++sidx) {
+      long long ss = sidx;
+      int S[3] = {0, 0, 0};
+      for (int d = 0; d < DIM; ++d) { S[d] = (int)(ss % R); ss /= R; }
+      for (int q = 0; q < NQ; ++q) {
+        int qq = q;
+        double x[3];
+        for (int d = 0; d < DIM; ++d) {
+          x[d] = ((double)E[d] * R + S[d] + c_ref.gt[qq % 3]) * hf;
+          qq /= 3;
+        }
+        const double v = eta_at<DIM>(x, incl, n_incl, eta_out, eta_in);
+        if (sidx == 0 && q == 0) first = v;
+        uni = uni && (v == first);
+      }
+    }
+    for (int q = 0; q < NQ; ++q) etaq[e * NQ + q] = first;
   }
   uniform[e] = uni ? 1 : 0;
 }
@@ -80,17 +115,21 @@ __device__ __forceinline__ double cell_stiffness_q(const double* etaq, long long
   return s;
 }
 
+// h^(d-2) times the viscous cell matrix entry: the reference matrix times the
+// cell's viscosity, or the stored matrix of a cut cell (h^(d-2) included).
 template <int DIM>
 __device__ __forceinline__ double cell_stiffness(const double* etaq, const unsigned char* uniform,
+                                                 const int* cut_idx, const double* cutA, double hA,
                                                  long long cell, const int* la, const int* lb) {
   constexpr int NQ = ipow(3, DIM);
+  constexpr int NV = ipow(3, DIM);
   int ia = 0, ib = 0, st = 1;
   for (int d = 0; d < DIM; ++d) { ia += la[d] * st; ib += lb[d] * st; st *= 3; }
   if (uniform[cell]) {
     double aref = DIM == 2 ? c_ref.aref2[ia][ib] : c_ref.aref3[ia][ib];
-    return etaq[cell * NQ] * aref;
+    return hA * (etaq[cell * NQ] * aref);
   }
-  return cell_stiffness_q<DIM>(etaq, cell, la, lb);
+  return cutA[((long long)cut_idx[cell] * NV + ia) * NV + ib];
 }
 
 template <int DIM>
@@ -112,7 +151,8 @@ __device__ __forceinline__ void common_cells(int a, int b, int N, int& lo, int& 
 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_assemble(const GridDev* G, const BlockTask* tasks,
-                                                   const double* etaq, const unsigned char* uniform) {
+                                                   const double* etaq, const unsigned char* uniform,
+                                                   const int* cut_idx, const double* cutA) {
   const BlockTask t = tasks[blockIdx.x];
   if (t.grid < 0) return;
   const GridDev& gd = G[t.grid];
@@ -180,7 +220,7 @@ __global__ __launch_bounds__(256) void k_assemble(const GridDev* G, const BlockT
                 int la[3], lb[3];
                 for (int d = 0; d < DIM; ++d) { la[d] = a[d] - 2 * E[d]; lb[d] = b[d] - 2 * E[d]; }
                 long long cell = ex + (long long)N * (ey + (long long)N * ez);
-                v += hA * cell_stiffness<DIM>(etaq, uniform, cell, la, lb);
+                v += cell_stiffness<DIM>(etaq, uniform, cut_idx, cutA, hA, cell, la, lb);
               }
         }
       } else {
@@ -372,34 +412,107 @@ __global__ __launch_bounds__(256) void k_cut_matrices(const GridDev* G, const do
   cutA[t] = hA * cell_stiffness_q<DIM>(etaq, cut_cells[i], la, lb);
 }
 
+// Galerkin form of a cut cell's viscous matrix on a coarse level: the integral
+// over the cell by the Gauss rules of its R^d finest-grid sub-cells, with the
+// coarse Q2 basis evaluated at those points (for nested spaces this is the
+// cell's share of P^T L_fine P).  One thread per entry.
+__device__ __forceinline__ void q2_at(double t, double* v, double* dv) {
+  v[0] = (1 - t) * (1 - 2 * t); v[1] = 4 * t * (1 - t); v[2] = t * (2 * t - 1);
+  dv[0] = 4 * t - 3; dv[1] = 4 - 8 * t; dv[2] = 4 * t - 1;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_cut_matrices_galerkin(const GridDev* G, const int* cut_cells, int ncut,
+                                                                int R, const double* incl, int n_incl,
+                                                                double eta_out, double eta_in, double* cutA) {
+  constexpr int NV = ipow(3, DIM);
+  constexpr int NQ = ipow(3, DIM);
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= (long long)ncut * NV * NV) return;
+  const int i = (int)(t / (NV * NV)), ab = (int)(t % (NV * NV));
+  int la[3] = {0, 0, 0}, lb[3] = {0, 0, 0};
+  for (int d = 0, a = ab / NV, b = ab % NV; d < DIM; ++d) { la[d] = a % 3; lb[d] = b % 3; a /= 3; b /= 3; }
+  const Geo& g = G->g;
+  int E[3] = {0, 0, 0};
+  long long ct = cut_cells[i];
+  for (int d = 0; d < DIM; ++d) { E[d] = (int)(ct % g.N); ct /= g.N; }
+  const double hf = G->h / R;
+  long long nsub = 1;
+  double wsub = 1.0;
+  for (int d = 0; d < DIM; ++d) { nsub *= R; wsub /= R; }
+  double s = 0.0;
+  for (long long sidx = 0; sidx < nsub; ++sidx) {
+    long long ss = sidx;
+    int S[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) { S[d] = (int)(ss % R); ss /= R; }
+    for (int q = 0; q < NQ; ++q) {
+      int qq = q;
+      double x[3], va[3], vb[3], da[3], db[3], w = wsub;
+      for (int d = 0; d < DIM; ++d) {
+        const int qd = qq % 3;
+        qq /= 3;
+        const double xi = ((double)S[d] + c_ref.gt[qd]) / R;   // position in the coarse cell
+        x[d] = ((double)E[d] * R + S[d] + c_ref.gt[qd]) * hf;
+        w *= c_ref.gw[qd];
+        double v3[3], d3[3];
+        q2_at(xi, v3, d3);
+        va[d] = v3[la[d]]; da[d] = d3[la[d]];
+        vb[d] = v3[lb[d]]; db[d] = d3[lb[d]];
+      }
+      double gg = 0.0;
+      for (int c = 0; c < DIM; ++c) {
+        double p = 1.0;
+        for (int d = 0; d < DIM; ++d) p *= d == c ? da[d] * db[d] : va[d] * vb[d];
+        gg += p;
+      }
+      s += w * eta_at<DIM>(x, incl, n_incl, eta_out, eta_in) * gg;
+    }
+  }
+  const double hA = DIM == 2 ? 1.0 : G->h;
+  cutA[t] = hA * s;
+}
+
 static inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+void launch_eta(int dim, long long ncell, const GridDev* G, const double* incl, int n_incl, double eta_out,
+                double eta_in, int R, double* etaq, unsigned char* uni, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(k_eta<2>, dim3(nblk(ncell, 256)), dim3(256), 0, s, G, incl, n_incl, eta_out, eta_in, R, etaq,
+                       uni);
+  else
+    hipLaunchKernelGGL(k_eta<3>, dim3(nblk(ncell, 256)), dim3(256), 0, s, G, incl, n_incl, eta_out, eta_in, R, etaq,
+                       uni);
+}
+
 void launch_cell_coef(int dim, long long ncell, const GridDev* G, const double* etaq, const int* cut_idx,
-                      const int* cut_cells, int ncut, double* ceta, double* cutA, hipStream_t s) {
+                      const int* cut_cells, int ncut, int R, const double* incl, int n_incl, double eta_out,
+                      double eta_in, double* ceta, double* cutA, hipStream_t s) {
   const long long nv2 = dim == 2 ? 81 : 729;
   if (dim == 2) {
     hipLaunchKernelGGL(k_cell_scale<2>, dim3(nblk(ncell, 256)), dim3(256), 0, s, G, ncell, etaq, cut_idx, ceta);
-    if (ncut > 0)
+    if (ncut > 0 && R == 1)
       hipLaunchKernelGGL(k_cut_matrices<2>, dim3(nblk(ncut * nv2, 256)), dim3(256), 0, s, G, etaq, cut_cells, ncut,
                          cutA);
+    else if (ncut > 0)
+      hipLaunchKernelGGL(k_cut_matrices_galerkin<2>, dim3(nblk(ncut * nv2, 256)), dim3(256), 0, s, G, cut_cells, ncut,
+                         R, incl, n_incl, eta_out, eta_in, cutA);
   } else {
     hipLaunchKernelGGL(k_cell_scale<3>, dim3(nblk(ncell, 256)), dim3(256), 0, s, G, ncell, etaq, cut_idx, ceta);
-    if (ncut > 0)
+    if (ncut > 0 && R == 1)
       hipLaunchKernelGGL(k_cut_matrices<3>, dim3(nblk(ncut * nv2, 256)), dim3(256), 0, s, G, etaq, cut_cells, ncut,
                          cutA);
+    else if (ncut > 0)
+      hipLaunchKernelGGL(k_cut_matrices_galerkin<3>, dim3(nblk(ncut * nv2, 256)), dim3(256), 0, s, G, cut_cells, ncut,
+                         R, incl, n_incl, eta_out, eta_in, cutA);
   }
 }
 
-void launch_assemble(int dim, long long ncell, const GridDev* G, const BlockTask* tasks, int ntasks,
-                     const double* incl, int n_incl, double eta_out, double eta_in, double* etaq,
-                     unsigned char* uni, hipStream_t s) {
-  if (dim == 2) {
-    hipLaunchKernelGGL(k_eta<2>, dim3(nblk(ncell, 256)), dim3(256), 0, s, G, incl, n_incl, eta_out, eta_in, etaq, uni);
-    hipLaunchKernelGGL(k_assemble<2>, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, etaq, uni);
-  } else {
-    hipLaunchKernelGGL(k_eta<3>, dim3(nblk(ncell, 256)), dim3(256), 0, s, G, incl, n_incl, eta_out, eta_in, etaq, uni);
-    hipLaunchKernelGGL(k_assemble<3>, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, etaq, uni);
-  }
+void launch_assemble(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, const double* etaq,
+                     const unsigned char* uni, const int* cut_idx, const double* cutA, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(k_assemble<2>, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, etaq, uni, cut_idx, cutA);
+  else
+    hipLaunchKernelGGL(k_assemble<3>, dim3(ntasks), dim3(BLOCK), 0, s, G, tasks, etaq, uni, cut_idx, cutA);
 }
 
 void launch_rhs(int dim, const GridDev* Gh, const GridDev* Gd, const double* params, double* fq, double* b,

@@ -262,11 +262,13 @@ static rav_status build_level(rav_ctx* ctx, int l) {
   int natd = 0;
   st = rav_upload_tasks(ctx, at, &atd, &natd);
   if (st != RAV_OK) return st;
-  launch_assemble(D.dim, ncell, L.dd, atd, natd, ctx->d_incl, D.n_incl, D.eta_out, D.eta_in, etaq, uni,
-                  ctx->stream);
+  // Galerkin coarse operators: cell integrals by the finest grid's Gauss points
+  const int R = D.coarse_galerkin ? (1 << (D.n_levels - 1 - l)) : 1;
+  launch_eta(D.dim, ncell, L.dd, ctx->d_incl, D.n_incl, D.eta_out, D.eta_in, R, etaq, uni, ctx->stream);
   CK(hipGetLastError());
   CK(hipStreamSynchronize(ctx->stream));
-  // matrix-free residual coefficients: cells cut by an inclusion keep their cell matrix
+  // cells cut by an inclusion keep their full viscous cell matrix (matrix-free
+  // residual and operator assembly); the others one coefficient
   std::vector<unsigned char> hu(ncell);
   CK(hipMemcpy(hu.data(), uni, ncell, hipMemcpyDeviceToHost));
   std::vector<int> cut_idx(ncell, -1), cut_cells;
@@ -281,7 +283,9 @@ static rav_status build_level(rav_ctx* ctx, int l) {
   CK(hipMalloc((void**)&d_cut_cells, sizeof(int) * std::max<long long>(L.ncut, 1)));
   CK(hipMemcpy(d_cut_idx, cut_idx.data(), sizeof(int) * ncell, hipMemcpyHostToDevice));
   if (L.ncut) CK(hipMemcpy(d_cut_cells, cut_cells.data(), sizeof(int) * L.ncut, hipMemcpyHostToDevice));
-  launch_cell_coef(D.dim, ncell, L.dd, etaq, d_cut_idx, d_cut_cells, (int)L.ncut, L.ceta, L.cutA, ctx->stream);
+  launch_cell_coef(D.dim, ncell, L.dd, etaq, d_cut_idx, d_cut_cells, (int)L.ncut, R, ctx->d_incl, D.n_incl,
+                   D.eta_out, D.eta_in, L.ceta, L.cutA, ctx->stream);
+  launch_assemble(D.dim, L.dd, atd, natd, etaq, uni, d_cut_idx, L.cutA, ctx->stream);
   CK(hipGetLastError());
   CK(hipStreamSynchronize(ctx->stream));
   CK(hipFree(d_cut_idx));
@@ -621,6 +625,8 @@ rav_status rav_create_ex(const rav_problem_desc* d, void* hip_stream, rav_ctx** 
   if (d->n_incl < 0 || d->n_incl > MAX_INCL || (d->n_incl > 0 && !d->incl))
     return set_err(nullptr, RAV_EINVAL, "n_incl must be in [0, 64] with a valid array");
   if (d->bc_dirichlet_mask >> (2 * d->dim)) return set_err(nullptr, RAV_EINVAL, "bc mask has bits beyond 2*dim");
+  if (d->coarse_galerkin != 0 && d->coarse_galerkin != 1)
+    return set_err(nullptr, RAV_EINVAL, "coarse_galerkin must be 0 or 1");
   if (d->patch != RAV_PATCH_VERTEX && d->patch != RAV_PATCH_ELEMENT) return set_err(nullptr, RAV_EINVAL, "bad patch kind");
   if (d->smoother < RAV_SMOOTHER_RAV || d->smoother > RAV_SMOOTHER_MV) return set_err(nullptr, RAV_EINVAL, "bad smoother");
   if (d->inv_precision < RAV_FP64 || d->inv_precision > RAV_BF16) return set_err(nullptr, RAV_EINVAL, "bad precision");

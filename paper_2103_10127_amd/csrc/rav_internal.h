@@ -112,9 +112,13 @@ struct RefTables {
 // ---- kernel launchers (defined in the .hip files) --------------------------
 void set_ref_tables(const RefTables& t, hipStream_t s);
 
-void launch_assemble(int dim, long long ncell, const GridDev* G, const BlockTask* tasks, int ntasks,
-                     const double* incl, int n_incl, double eta_out, double eta_in, double* etaq,
-                     unsigned char* uni, hipStream_t s);
+// Viscosity per Gauss point and per-cell uniformity; R > 1 samples the Gauss
+// points of the R^d finest-grid cells inside each cell (Galerkin coarse operator).
+void launch_eta(int dim, long long ncell, const GridDev* G, const double* incl, int n_incl, double eta_out,
+                double eta_in, int R, double* etaq, unsigned char* uni, hipStream_t s);
+// ELL operator values; non-uniform cells take their stored cell matrix cutA[cut_idx[cell]].
+void launch_assemble(int dim, const GridDev* G, const BlockTask* tasks, int ntasks, const double* etaq,
+                     const unsigned char* uni, const int* cut_idx, const double* cutA, hipStream_t s);
 void launch_rhs(int dim, const GridDev* Gh, const GridDev* Gd, const double* params, double* fq,
                 double* b, hipStream_t s);
 // Residual tiles: part = velocity node parity type t (rows of seg_rows(g, t))
@@ -126,7 +130,8 @@ bool residual_tiled_ok(int dim, int N);
 int residual_tiles(int dim, int N);
 void launch_residual_tiled(int dim, const GridDev* G, int N, double* partials, hipStream_t s);
 void launch_cell_coef(int dim, long long ncell, const GridDev* G, const double* etaq, const int* cut_idx,
-                      const int* cut_cells, int ncut, double* ceta, double* cutA, hipStream_t s);
+                      const int* cut_cells, int ncut, int R, const double* incl, int n_incl, double eta_out,
+                      double eta_in, double* ceta, double* cutA, hipStream_t s);
 void launch_norm_finalize(const double* partials, int first, int count, double* out, double* host_out,
                           hipStream_t s);
 void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const GridDev* G, const BlockTask* tasks,
