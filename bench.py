@@ -65,41 +65,42 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=20000, help="patches in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=12000, help="patches in the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch the plain copy kernel on 1 GiB (for HBM counter scaling)")
     ap.add_argument("--workload", default="2d-512",
-                    choices=["2d-512", "3d-64", "2d-1024", "batch256", "learned"],
+                    choices=["2d-512", "3d-64", "3d-64-vertex", "2d-1024", "batch256", "learned", "smoothers"],
                     help="2d-512: the headline solve (default); 3d-64: finest-level element-patch sweep; "
-                         "2d-1024: inclusions at contrast 1e4; batch256: 256 problems; learned: per-patch "
-                         "damping trained on small problems, evaluated on 512^2 problems with inclusions")
+                         "3d-64-vertex: 64^3 solve with vertex patches; 2d-1024: inclusions at contrast 1e4; "
+                         "batch256: 256 problems; learned: per-patch damping trained on small problems, "
+                         "evaluated on 512^2 problems with inclusions; smoothers: RAV/AV/MV cost per cycle, "
+                         "cycles and time to 1e-8 on 32^2 (damping sweep) and 512^2")
     ap.add_argument("--train-steps", type=int, default=800)
     ap.add_argument("--train-lr", type=float, default=3e-3)
     return ap.parse_args()
 
 
-def cpu_baseline(sample: int) -> dict:
-    """Oracle RAV sweep on the 512x512 level, timed on a bounded sample (one
-    thread).  Runs in a child process with single-threaded BLAS."""
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    code = f"""
+_CPU_SWEEP = """
 import json, time, sys
 import numpy as np, scipy.linalg as sla
-sys.path.insert(0, {ROOT!r})
+sys.path.insert(0, {root!r})
 import rav_inputs as ri
 from oracle import assemble as A, patches as pt, smoothers as sm
 from oracle.grid import Grid
+part, nparts, sample = {part}, {nparts}, {sample}
 g = Grid(2, 512, ri.ALL_DIRICHLET_2D)
 L = A.assemble_matrix(g)
 owner = pt.owner_of_dofs(g, pt.VERTEX)
 rng = np.random.default_rng(7)
-idx = np.sort(rng.choice(g.nP, {sample}, replace=False))
+idx = np.sort(rng.choice(g.nP, sample, replace=False))[part::nparts]
 dofs = [pt.patch_dofs(g, pt.VERTEX, int(i)) for i in idx]
 lus = sm.factor(L, dofs)
 own = [np.nonzero(owner[I] == i)[0] for I, i in zip(dofs, idx)]
 x = ri.random_vector(g.n, 1) * g.free
 b = ri.random_vector(g.n, 2) * g.free
-best = None
+print("ready", flush=True)
+sys.stdin.readline()
+best_r = best_p = None
 for rep in range(5):
     t0 = time.perf_counter()
     r = sm.residual(L, x, b, g.free)
@@ -109,20 +110,103 @@ for rep in range(5):
         y = sla.lu_solve(lu, r[I])
         dx[I[o]] += 0.66 * y[o]
     t2 = time.perf_counter()
-    sweep = (t1 - t0) + (t2 - t1) * g.nP / len(idx)
-    best = sweep if best is None else min(best, sweep)
-print(json.dumps(dict(sweep_s=best, n=int(g.n))))
+    best_r = (t1 - t0) if best_r is None else min(best_r, t1 - t0)
+    best_p = (t2 - t1) if best_p is None else min(best_p, t2 - t1)
+print(json.dumps(dict(resid_s=best_r, patch_s=best_p, npatch=len(idx), n=int(g.n))))
 """
+
+_CPU_SOLVE = """
+import json, time, sys
+sys.path.insert(0, {root!r})
+import rav_inputs as ri
+from oracle import assemble as A, mg
+t0 = time.perf_counter()
+H = mg.Hierarchy(2, 32, 3, ri.ALL_DIRICHLET_2D)
+b = A.assemble_rhs(H.finest.grid, ri.mms_params(2, 1001))
+t1 = time.perf_counter()
+x, k, hist, st = H.solve(b)
+t2 = time.perf_counter()
+H.vcycle(x * 0, b)
+t3 = time.perf_counter()
+print(json.dumps(dict(setup_s=t1 - t0, solve_s=t2 - t1, vcycle_s=t3 - t2, iters=k, status=st, n=int(H.finest.grid.n))))
+"""
+
+
+def _host_info() -> dict:
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["nproc_affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["ram_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return info
+
+
+def _single_thread_env():
+    return dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+
+
+def _cpu_sweep(sample: int, nparts: int) -> dict:
+    """The oracle's RAV sweep of the 512x512 level on `sample` patches, split
+    over `nparts` single-threaded processes that run at the same time (the
+    residual is timed in every process; the slowest one counts)."""
+    procs = [subprocess.Popen([sys.executable, "-c", _CPU_SWEEP.format(root=ROOT, part=i, nparts=nparts,
+                                                                          sample=sample)],
+                              env=_single_thread_env(), stdin=subprocess.PIPE, stdout=subprocess.PIPE,
+                              stderr=subprocess.PIPE, text=True) for i in range(nparts)]
+    for p in procs:   # all set up, then all timed together
+        if p.stdout.readline().strip() != "ready":
+            return {"error": p.stderr.read()[-400:]}
+    for p in procs:
+        p.stdin.write("go\n")
+        p.stdin.flush()
+    res = []
+    for p in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            return {"error": err[-400:]}
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    n = res[0]["n"]
+    patch_s = max(r["patch_s"] / r["npatch"] for r in res) * sum(r["npatch"] for r in res) / nparts
+    sweep_s = max(r["resid_s"] for r in res) + patch_s * (513 * 513) / sample
+    return {"sweep_s": sweep_s, "n": n}
+
+
+def cpu_baseline(sample: int) -> dict:
+    """The FP64 oracle on the host cores, bounded: one RAV sweep of the 512x512
+    level (residual over all DoFs + LU solves of `sample` sampled patches,
+    scaled to all 263,169) on one core and on all cores, and the whole 32x32
+    solve (3 levels, V(2,2), to 1e-8) on one core."""
     t0 = time.time()
-    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True)
-    if out.returncode != 0:
-        return {"error": out.stderr[-400:]}
-    res = json.loads(out.stdout.strip().splitlines()[-1])
-    return {"value": res["n"] / res["sweep_s"], "unit": "DoF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one FP64 RAV sweep of the 512x512 level (residual SpMV over all "
-                       f"{res['n']} DoFs + LU solves of {sample} of {513 * 513} vertex patches, "
-                       f"scaled to all patches; best of 5, single-threaded scipy)"),
-            "wall_s": round(time.time() - t0, 1)}
+    host = _host_info()
+    ncores = max(1, host.get("nproc_affinity", host["nproc"] or 1))
+    one = _cpu_sweep(sample, 1)
+    if "error" in one:
+        return one
+    allc = _cpu_sweep(sample, ncores) if ncores > 1 else one
+    out = subprocess.run([sys.executable, "-c", _CPU_SOLVE.format(root=ROOT)], env=_single_thread_env(),
+                         capture_output=True, text=True)
+    solve32 = json.loads(out.stdout.strip().splitlines()[-1]) if out.returncode == 0 else {"error": out.stderr[-400:]}
+    res = {"value": one["n"] / one["sweep_s"], "unit": "DoF/s", "cores": 1, "kind": "oracle",
+           "sample": (f"one FP64 RAV sweep of the 512x512 level (residual SpMV over all {one['n']} DoFs + LU "
+                      f"solves of {sample} of {513 * 513} vertex patches, scaled to all patches; best of 5, "
+                      f"single-threaded scipy)"),
+           "all_cores": {"value": allc.get("n", one["n"]) / allc["sweep_s"] if "sweep_s" in allc else None,
+                         "cores": ncores,
+                         "how": "the same sample split over one single-threaded process per core, run together"},
+           "solve_32x32_one_core": solve32, "host": host, "wall_s": None}
+    res["wall_s"] = round(time.time() - t0, 1)
+    return res
 
 
 def main():
@@ -132,8 +216,8 @@ def main():
               "(no collectives, no sharding of the grid).", file=sys.stderr)
         sys.exit(2)
     if args.workload != "2d-512":
-        {"3d-64": bench_3d, "2d-1024": bench_1024, "batch256": bench_batch,
-         "learned": bench_learned}[args.workload](args)
+        {"3d-64": bench_3d, "3d-64-vertex": bench_3d_vertex, "2d-1024": bench_1024, "batch256": bench_batch,
+         "learned": bench_learned, "smoothers": bench_smoothers}[args.workload](args)
         return
     import torch
     from paper_2103_10127_amd import Hierarchy
@@ -312,6 +396,129 @@ def bench_3d(args):
           precisions=res)
 
 
+def sum_owned_times_patch_3d_vertex(N: int) -> int:
+    """sum_i (owned rows x patch columns) of all-Dirichlet 3D vertex patches:
+    per axis a vertex k sees c(k) free node positions in [2k-2, 2k+2] and owns
+    o(k) free positions in {2k, 2k+1}; n_i = 3 prod c + 1, owned_i = 3 prod o + 1."""
+    k = np.arange(N + 1)
+    c = np.minimum(2 * k + 2, 2 * N - 1) - np.maximum(2 * k - 2, 1) + 1
+    o = np.maximum(np.minimum(2 * k + 1, 2 * N - 1) - np.maximum(2 * k, 1) + 1, 0)
+    C = c[:, None, None] * c[None, :, None] * c[None, None, :]
+    O = o[:, None, None] * o[None, :, None] * o[None, None, :]
+    return int(np.sum((3 * C + 1) * (3 * O + 1)))
+
+
+def bench_3d_vertex(args):
+    """The 64^3 workload with pressure-vertex patches (376 local DoFs): the RAV
+    V(2,2) solve from x0 = 0 to a 1e-8 reduction in FP64, FP32 and BF16 rows
+    (element patches give no convergent cycle).  value = smoothed DoFs/s of
+    the FP64 solve; roofline: the finest-level apply with HIP events."""
+    import torch
+    from paper_2103_10127_amd import Hierarchy
+    cfg = ri.CONFIGS["3d-64"]
+    N, nl = cfg["n_cells"], cfg["n_levels"]
+    steps = max(args.steps // 2, 2)
+    esz = {"fp64": 8, "fp32": 4, "bf16": 2}
+    sum_on = sum_owned_times_patch_3d_vertex(N)
+    res = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        t0 = time.perf_counter()
+        H = Hierarchy(dim=3, n_cells=N, n_levels=nl, dmask=cfg["dmask"], kind="vertex", omega=0.66, precision=prec)
+        H.factor()
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        n_fine, n_free = H.dofs(nl - 1)
+        level_n = [H.dofs(l)[0] for l in range(nl)]
+        b = torch.zeros(n_fine, dtype=torch.float64, device="cuda")
+        H.assemble_rhs(ri.mms_params(3, cfg["seed"]), b)
+        x = torch.zeros_like(b)
+        H.solve(x, b, 1e-8, 60)
+        H.profile_begin(nl - 1, 4096)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for _ in range(steps):
+            x.zero_()
+            st, it, rel = H.solve(x, b, 1e-8, 60)
+            if st != 0:
+                raise RuntimeError(f"3D vertex solve {prec}: status {st}, {it} cycles, rel {rel}")
+            its.append(it)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ms_res, ms_apply, n_app = H.profile_end()
+        apply_bytes = esz[prec] * sum_on + 8 * n_fine + 16 * n_free
+        res[prec] = dict(time_to_1e_8_ms=1e3 * dt, iters=int(np.median(its)), setup_s=round(setup, 3),
+                         ms_apply=ms_apply, ms_residual=ms_res, apply_GBs=apply_bytes / (1e-3 * ms_apply) / 1e9,
+                         smoothed_dofs_per_s=int(np.median(its)) * sum(4 * level_n[l] for l in range(1, nl)) / dt)
+        H.close()
+    f = res["fp64"]
+    apply_bytes = 8 * sum_on + 8 * n_fine + 16 * n_free
+    _line("RAV smoothed DoFs/s (whole V(2,2) solve to a 1e-8 residual reduction)", f["smoothed_dofs_per_s"], "DoF/s",
+          steps, 1, f["time_to_1e_8_ms"], "f64",
+          {"workload": "3D Taylor-Hood Q2/Q1 64^3, 5 levels, RAV with pressure-vertex patches (376 DoFs), V(2,2) "
+                       "omega 0.66, solve from x0=0 to ||r|| <= 1e-8 ||r0||",
+           "dofs": n_fine, "patches": (N + 1) ** 3, "sum_owned_x_cols": sum_on},
+          time_to_1e_8_ms=f["time_to_1e_8_ms"], iters=f["iters"],
+          roofline={"bound": "hbm", "kernel": "k_rav_apply<3,VERTEX,0,double> (64^3 level)",
+                    "achieved": f["apply_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": f["apply_GBs"] / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": apply_bytes},
+          precisions=res)
+
+
+def bench_smoothers(args):
+    """The paper's cost comparison (Sec. 4.3, eq. 15): per smoother, the time of
+    one V(2,2) cycle, the cycles to a 1e-8 reduction and the total time, on the
+    32x32 workload for the damping sweep omega in {0.5, 0.6, 0.66, 0.7, 0.8, 0.9,
+    1.0} plus AV at 0.1, and on the 512x512 workload for RAV 0.66, MV 0.66 and
+    AV 0.1.  value = the 512^2 RAV solve's smoothed DoFs/s."""
+    import torch
+    from paper_2103_10127_amd import Hierarchy
+
+    def run(N, nl, smoother, omega, maxit):
+        H = Hierarchy(dim=2, n_cells=N, n_levels=nl, dmask=ri.ALL_DIRICHLET_2D, smoother=smoother, omega=omega)
+        t0 = time.perf_counter()
+        H.factor()
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        n, _ = H.dofs(nl - 1)
+        level_n = [H.dofs(l)[0] for l in range(nl)]
+        b = torch.zeros(n, dtype=torch.float64, device="cuda")
+        H.assemble_rhs(ri.mms_params(2, 1001 if N == 32 else 1002), b)
+        x = torch.zeros_like(b)
+        H.solve(x, b, 1e-8, maxit)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it, rel = H.solve(x, b, 1e-8, maxit)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            H.vcycle(x, b)
+        torch.cuda.synchronize()
+        cyc = (time.perf_counter() - t0) / reps
+        H.close()
+        status = {0: "converged", 1: "maxit", -4: "diverged"}.get(st, str(st))
+        return {"smoother": smoother, "omega": omega, "status": status, "cycles": it, "rel_res": rel,
+                "ms_per_cycle": 1e3 * cyc, "ms_total": 1e3 * total if st == 0 else None, "setup_s": round(setup, 3),
+                "smoothed_per_cycle": sum(4 * level_n[l] for l in range(1, nl))}
+
+    sweep = []
+    for sm_ in ("rav", "mv", "av"):
+        for om in (0.5, 0.6, 0.66, 0.7, 0.8, 0.9, 1.0) + ((0.1,) if sm_ == "av" else ()):
+            sweep.append(run(32, 3, sm_, om, 300))
+    big = [run(512, 7, "rav", 0.66, 100), run(512, 7, "mv", 0.66, 100), run(512, 7, "av", 0.1, 300)]
+    r = big[0]
+    _line("RAV smoothed DoFs/s (whole V(2,2) solve to a 1e-8 residual reduction)",
+          r["cycles"] * r["smoothed_per_cycle"] / (1e-3 * r["ms_total"]), "DoF/s", 1, 1, r["ms_total"], "f64",
+          {"workload": "RAV vs MV vs AV: 2D Q2/Q1 32x32 (3 levels, omega swept) and 512x512 (7 levels), V(2,2), "
+                       "solve from x0=0 to 1e-8"},
+          cost_512=big, damping_sweep_32=sweep)
+
+
 def bench_1024(args):
     """2D 1024^2 with inclusions at contrast 1e4: the finest-level RAV sweep rate
     (FP64 and BF16 rows), plus the outcome of the solvers on this problem: plain
@@ -373,29 +580,49 @@ def bench_1024(args):
 
 def bench_batch(args):
     """256 independent 2D problems (fine grids 64/128/256, coarsest 16^2, 1-8
-    inclusions each at contrast 1e3) advanced together: one step = one batched
-    V(2,2) cycle of all problems (one launch per stage for the whole batch).
-    Plain V-cycles do not converge at this contrast, so the rate of cycles is
-    measured, not a time to 1e-8."""
+    inclusions each at contrast 1e3) advanced together.  value = smoothed
+    DoFs/s of one batched V(2,2) cycle of all problems (one launch per stage for
+    the whole batch, captured cycle).  At this contrast plain V-cycles do not
+    converge for most problems, so the time to 1e-8 is measured with the
+    batched FGMRES(30) preconditioned by one cycle, for V(2,2), V(4,4), V(3,3)
+    with Galerkin coarse operators and V(4,4) with BF16 rows; each entry
+    reports how many of the 256 problems reached 1e-8 within 300 cycles."""
     import torch
     from paper_2103_10127_amd.capi import Batch
     cfg = ri.CONFIGS["batch256"]
     sizes = ri.batch_sizes(cfg["n_problems"], cfg["seed"])
-    probs = [dict(dim=2, n_cells=int(n), n_levels=ri.levels_to(int(n), cfg["coarsest"]), dmask=cfg["dmask"],
-                  eta_out=cfg["eta_out"], eta_in=cfg["contrast"], inclusions=ri.inclusions(cfg["seed"] + i),
-                  omega=0.66) for i, n in enumerate(sizes)]
-    t0 = time.perf_counter()
-    B = Batch(probs)
-    B.factor()
-    torch.cuda.synchronize()
-    setup = time.perf_counter() - t0
-    xs, bs = [], []
-    for i, p in enumerate(probs):
-        n, _ = B.dofs(i)
-        bb = torch.zeros(n, dtype=torch.float64, device="cuda")
-        B.assemble_rhs(i, ri.mms_params(2, cfg["seed"] + i), bb)
-        bs.append(bb)
-        xs.append(torch.zeros_like(bb))
+
+    def make(nu, galerkin=False, precision="fp64"):
+        probs = [dict(dim=2, n_cells=int(n), n_levels=ri.levels_to(int(n), cfg["coarsest"]), dmask=cfg["dmask"],
+                      eta_out=cfg["eta_out"], eta_in=cfg["contrast"], inclusions=ri.inclusions(cfg["seed"] + i),
+                      omega=0.66, nu_pre=nu, nu_post=nu, galerkin=galerkin, precision=precision)
+                 for i, n in enumerate(sizes)]
+        t0 = time.perf_counter()
+        B = Batch(probs)
+        B.factor()
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        xs, bs = [], []
+        for i in range(len(probs)):
+            n, _ = B.dofs(i)
+            bb = torch.zeros(n, dtype=torch.float64, device="cuda")
+            B.assemble_rhs(i, ri.mms_params(2, cfg["seed"] + i), bb)
+            bs.append(bb)
+            xs.append(torch.zeros_like(bb))
+        return B, probs, xs, bs, setup
+
+    def gmres(B, xs, bs):
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, its, rel = B.solve_gmres(xs, bs, 1e-8, 300, 30)
+        torch.cuda.synchronize()
+        rel = np.asarray(rel)
+        return {"converged": int((rel <= 1e-8).sum()), "of": len(rel), "ms": 1e3 * (time.perf_counter() - t0),
+                "cycles_median": float(np.median(its)), "cycles_max": int(max(its))}
+
+    B, probs, xs, bs, setup = make(2)
     for _ in range(max(args.warmup, 1)):
         B.vcycle(xs, bs)
     for x in xs:
@@ -413,13 +640,20 @@ def bench_batch(args):
             n_l = p["n_cells"] >> (p["n_levels"] - 1 - l)
             smoothed += 2 * 2 * (2 * (2 * n_l + 1) ** 2 + (n_l + 1) ** 2)
     total = sum(B.dofs(i)[0] for i in range(len(probs)))
+    solves = {"fgmres30_v22": gmres(B, xs, bs)}
     B.close()
+    for label, nu, gal, prec in (("fgmres30_v44", 4, False, "fp64"), ("fgmres30_v33_galerkin", 3, True, "fp64"),
+                                 ("fgmres30_v44_bf16", 4, False, "bf16")):
+        B, _, xs, bs, st_s = make(nu, gal, prec)
+        solves[label] = gmres(B, xs, bs)
+        solves[label]["setup_s"] = round(st_s, 3)
+        B.close()
     _line("RAV smoothed DoFs/s (batched V(2,2) cycles)", smoothed / dt, "DoF/s", steps, max(args.warmup, 1),
           1e3 * dt, "f64",
           {"workload": "256 independent 2D Q2/Q1 problems (fine 64/128/256, coarsest 16x16), 1-8 inclusions "
                        "each at contrast 1e3, one batched RAV V(2,2) cycle per step",
            "problems": len(probs), "dofs_total": total},
-          setup_s=round(setup, 3))
+          setup_s=round(setup, 3), solves=solves)
 
 
 def bench_learned(args):
