@@ -11,10 +11,16 @@ value = smoothed DoFs per second over the whole solve: every RAV sweep on
 every level counts its level's DoFs, divided by the wall time of the solve
 (transfers, coarse solves and the per-cycle norm readback included).
 
+The owned rows of each local inverse are stored in the factored form by
+default (RAV_FACTORED: owned rows of the scalar viscous block's inverse, z and
+the Schur complement inverse; the same rows up to rounding, 151 values per
+patch instead of 459); --format rows stores the rows themselves.
+
 Extra fields: per-step iterations, the finest-level sweep rate and its HBM
-fraction, FP32/BF16 inverse-row solves, a roofline object for the dominant
-kernel (the finest-level RAV apply, timed with HIP events on the launch stream
-during the timed solves) and the CPU oracle timed on a bounded sample.
+fraction, the other storage formats and FP32/BF16 solves, a roofline object for
+the dominant kernel (the finest-level RAV apply, timed with HIP events on the
+launch stream during the timed solves) and the CPU oracle timed on a bounded
+sample.
 """
 from __future__ import annotations
 
@@ -64,7 +70,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the other storage formats and precisions")
+    ap.add_argument("--format", default="factored", choices=["factored", "rows"],
+                    help="storage of the owned inverse rows for the headline FP64 solve")
     ap.add_argument("--cpu-sample", type=int, default=12000, help="patches in the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch the plain copy kernel on 1 GiB (for HBM counter scaling)")
@@ -228,15 +236,15 @@ def main():
     torch.cuda.set_device(0)
     params = ri.mms_params(2, cfg["seed"])
 
-    def setup(prec):
+    def setup(prec, fmt):
         t0 = time.perf_counter()
         H = Hierarchy(dim=2, n_cells=N, n_levels=nl, dmask=cfg["dmask"], smoother="rav", omega=omega,
-                      nu_pre=nu, nu_post=nu, precision=prec)
+                      nu_pre=nu, nu_post=nu, precision=prec, inv_format=fmt)
         H.factor()
         torch.cuda.synchronize()
         return H, time.perf_counter() - t0
 
-    H, setup_s = setup("fp64")
+    H, setup_s = setup("fp64", args.format)
     n_fine, n_free = H.dofs(nl - 1)
     level_n = [H.dofs(l)[0] for l in range(nl)]
     b = torch.zeros(n_fine, dtype=torch.float64, device="cuda")
@@ -268,9 +276,16 @@ def main():
     ms_step = 1e3 * dt / args.steps
     ms_res, ms_apply, n_apply = prof
 
-    # Algorithmic bytes (per launch, finest level).
+    # Algorithmic bytes (per launch, finest level): the stored inverse data of
+    # every patch (owned rows, or the factored form's 151 values per patch),
+    # r read once, x read and written on free DoFs.
     sum_on = sum_owned_times_patch(N)
-    apply_bytes = 8 * sum_on + 8 * n_fine + 16 * n_free          # W rows + r read + x read/write
+    fact_vals = 25 * 6 + 1
+
+    def w_entries(fmt):
+        return sum_on if fmt == "rows" else fact_vals * (N + 1) ** 2
+
+    apply_bytes = 8 * w_entries(args.format) + 8 * n_fine + 16 * n_free
     resid_bytes = 24 * n_fine + 8 * N * N                          # x, b read + r write + one coefficient per cell
     sweep_s = 1e-3 * (ms_res + ms_apply)
     sweep_rate = n_fine / sweep_s
@@ -278,7 +293,8 @@ def main():
     roof_res = resid_bytes / (1e-3 * ms_res) / 1e9
     # HBM bytes per apply launch from the committed PMC summary (None once the kernel changed)
     from paper_2103_10127_amd.profiling import read_traffic
-    traffic = read_traffic(os.path.join(ROOT, "profiles", "rav_apply_2d512_fp64_traffic.md"))
+    traffic = read_traffic(os.path.join(ROOT, "profiles", "rav_apply_fact_2d512_fp64_traffic.md"
+                                        if args.format == "factored" else "rav_apply_2d512_fp64_traffic.md"))
 
     out = {
         "metric": "RAV smoothed DoFs/s (whole V(2,2) solve to a 1e-8 residual reduction)",
@@ -288,13 +304,14 @@ def main():
         "config": {"workload": "2D Taylor-Hood Q2/Q1 Stokes 512x512, 7 levels, RAV V(2,2) omega 0.66, "
                                "solve from x0=0 to ||r|| <= 1e-8 ||r0||",
                    "dofs": n_fine, "levels": nl, "smoother": "rav", "nu": [nu, nu], "omega": omega,
-                   "inverse_rows": "fp64"},
+                   "inverse_precision": "fp64", "inverse_format": args.format},
         "time_to_1e-8_ms": ms_step, "iters": int(np.median(iters)),
         "setup_s": round(setup_s, 3),
         "sweep": {"level": "512x512", "ms_residual": ms_res, "ms_apply": ms_apply,
                   "dofs_per_s": sweep_rate, "launches_timed": n_apply,
                   "pct_hbm_peak": 100.0 * (apply_bytes + resid_bytes) / sweep_s / 1e9 / HBM_PEAK_GBS},
-        "roofline": {"bound": "hbm", "kernel": "k_rav_apply<2,VERTEX,0,double> (512x512 level)",
+        "roofline": {"bound": "hbm", "kernel": ("k_rav_apply_fact<2,double,1>" if args.format == "factored"
+                                                else "k_rav_apply<2,VERTEX,0,double,1>") + " (512x512 level)",
                      "achieved": roof_apply, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": roof_apply / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": apply_bytes},
@@ -321,19 +338,23 @@ def main():
 
     if not args.no_mixed:
         H.close()
-        mixed = {}
-        for prec in ("fp32", "bf16"):
-            Hm, st_s = setup(prec)
-            run(Hm, 1)
-            dtm, itm, pm = run(Hm, max(1, args.steps // 2), profile=True)
-            k = max(1, args.steps // 2)
-            mixed[prec] = {"time_to_1e-8_ms": 1e3 * dtm / k, "iters": int(np.median(itm)),
-                           "dofs_per_s": sum(itm) * smoothed_per_cycle / dtm,
-                           "ms_apply": pm[1], "ms_residual": pm[0], "setup_s": round(st_s, 3),
-                           "apply_GBs": ((2 if prec == "bf16" else 4) * sum_on + 8 * n_fine + 16 * n_free)
-                           / (1e-3 * pm[1]) / 1e9}
-            Hm.close()
-        out["mixed"] = mixed
+        variants = {}
+        esz = {"fp64": 8, "fp32": 4, "bf16": 2}
+        for fmt in ("factored", "rows"):
+            for prec in ("fp64", "fp32", "bf16"):
+                if fmt == args.format and prec == "fp64":
+                    continue
+                Hm, st_s = setup(prec, fmt)
+                run(Hm, 1)
+                k = max(1, args.steps // 2)
+                dtm, itm, pm = run(Hm, k, profile=True)
+                variants[f"{fmt}_{prec}"] = {
+                    "time_to_1e-8_ms": 1e3 * dtm / k, "iters": int(np.median(itm)),
+                    "dofs_per_s": sum(itm) * smoothed_per_cycle / dtm, "ms_apply": pm[1], "ms_residual": pm[0],
+                    "setup_s": round(st_s, 3),
+                    "apply_GBs": (esz[prec] * w_entries(fmt) + 8 * n_fine + 16 * n_free) / (1e-3 * pm[1]) / 1e9}
+                Hm.close()
+        out["variants"] = variants
     else:
         H.close()
 
@@ -420,10 +441,14 @@ def bench_3d_vertex(args):
     steps = max(args.steps // 2, 2)
     esz = {"fp64": 8, "fp32": 4, "bf16": 2}
     sum_on = sum_owned_times_patch_3d_vertex(N)
+    fact_entries = (125 * 11 + 1) * (N + 1) ** 3
     res = {}
-    for prec in ("fp64", "fp32", "bf16"):
+    runs = [(args.format, "fp64")] + [(args.format, p) for p in ("fp32", "bf16")] + \
+        [("rows" if args.format == "factored" else "factored", "fp64")]
+    for fmt, prec in runs:
         t0 = time.perf_counter()
-        H = Hierarchy(dim=3, n_cells=N, n_levels=nl, dmask=cfg["dmask"], kind="vertex", omega=0.66, precision=prec)
+        H = Hierarchy(dim=3, n_cells=N, n_levels=nl, dmask=cfg["dmask"], kind="vertex", omega=0.66, precision=prec,
+                      inv_format=fmt)
         H.factor()
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
@@ -446,20 +471,21 @@ def bench_3d_vertex(args):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         ms_res, ms_apply, n_app = H.profile_end()
-        apply_bytes = esz[prec] * sum_on + 8 * n_fine + 16 * n_free
-        res[prec] = dict(time_to_1e_8_ms=1e3 * dt, iters=int(np.median(its)), setup_s=round(setup, 3),
+        apply_bytes = esz[prec] * (sum_on if fmt == "rows" else fact_entries) + 8 * n_fine + 16 * n_free
+        res[f"{fmt}_{prec}"] = dict(time_to_1e_8_ms=1e3 * dt, iters=int(np.median(its)), setup_s=round(setup, 3),
                          ms_apply=ms_apply, ms_residual=ms_res, apply_GBs=apply_bytes / (1e-3 * ms_apply) / 1e9,
                          smoothed_dofs_per_s=int(np.median(its)) * sum(4 * level_n[l] for l in range(1, nl)) / dt)
         H.close()
-    f = res["fp64"]
-    apply_bytes = 8 * sum_on + 8 * n_fine + 16 * n_free
+    f = res[f"{args.format}_fp64"]
+    apply_bytes = 8 * (sum_on if args.format == "rows" else fact_entries) + 8 * n_fine + 16 * n_free
     _line("RAV smoothed DoFs/s (whole V(2,2) solve to a 1e-8 residual reduction)", f["smoothed_dofs_per_s"], "DoF/s",
           steps, 1, f["time_to_1e_8_ms"], "f64",
           {"workload": "3D Taylor-Hood Q2/Q1 64^3, 5 levels, RAV with pressure-vertex patches (376 DoFs), V(2,2) "
                        "omega 0.66, solve from x0=0 to ||r|| <= 1e-8 ||r0||",
-           "dofs": n_fine, "patches": (N + 1) ** 3, "sum_owned_x_cols": sum_on},
+           "dofs": n_fine, "patches": (N + 1) ** 3, "sum_owned_x_cols": sum_on, "inverse_format": args.format},
           time_to_1e_8_ms=f["time_to_1e_8_ms"], iters=f["iters"],
-          roofline={"bound": "hbm", "kernel": "k_rav_apply<3,VERTEX,0,double> (64^3 level)",
+          roofline={"bound": "hbm", "kernel": ("k_rav_apply_fact<3,double,1>" if args.format == "factored" else
+                                               "k_rav_apply<3,VERTEX,0,double,1>") + " (64^3 level)",
                     "achieved": f["apply_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": f["apply_GBs"] / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": apply_bytes},
           precisions=res)

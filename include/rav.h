@@ -66,6 +66,16 @@ typedef enum { RAV_PATCH_VERTEX = 0, RAV_PATCH_ELEMENT = 1 } rav_patch_kind;
  * residual, local factorisation and coarse solve are always FP64). */
 typedef enum { RAV_FP64 = 0, RAV_FP32 = 1, RAV_BF16 = 2 } rav_precision;
 
+/* How RAV stores the owned rows of each L_i^{-1} (Sec. 4.3).  RAV_ROWS: the
+ * owned rows themselves (owned DoFs x patch DoFs).  RAV_FACTORED (vertex
+ * patches): the same rows through the block structure of L_i, whose velocity
+ * block is the same scalar block K_i for every component and whose pressure
+ * block is one unknown: the owned rows of K_i^{-1}, z = K_i^{-1} B_i and the
+ * scalar Schur complement inverse, from which the apply forms the owned rows'
+ * product with r exactly up to rounding (151 stored values per 2D patch
+ * instead of 459, 1,376 per 3D patch instead of 9,400). */
+typedef enum { RAV_ROWS = 0, RAV_FACTORED = 1 } rav_inv_format;
+
 /* Circular (2D: cx, cy, r) or spherical (3D: cx, cy, cz, r) inclusion. */
 typedef struct { double cx, cy, cz, r; } rav_inclusion;
 
@@ -88,6 +98,7 @@ typedef struct {
                                    Galerkin product P^T A P of the finest one
                                    (cell integrals by the finest grid's Gauss
                                    points; equal to 0 at constant viscosity) */
+  rav_inv_format inv_format;    /* RAV storage of the owned inverse rows          */
 } rav_problem_desc;
 
 typedef struct rav_ctx rav_ctx;

@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "RAV_OK", 1: "RAV_NOT_CONVERGED", -1: "RAV_EINVAL", -2: "RAV_
 SMOOTHERS = {"rav": 0, "av": 1, "mv": 2}
 KINDS = {"vertex": 0, "element": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+FORMATS = {"rows": 0, "factored": 1}
 
 
 class RavError(RuntimeError):
@@ -40,7 +41,8 @@ class RavProblemDesc(ctypes.Structure):
                 ("bc_dirichlet_mask", ctypes.c_uint), ("eta_out", ctypes.c_double), ("eta_in", ctypes.c_double),
                 ("n_incl", ctypes.c_int), ("incl", ctypes.POINTER(RavInclusion)), ("patch", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
-                ("nu_post", ctypes.c_int), ("inv_precision", ctypes.c_int), ("coarse_galerkin", ctypes.c_int)]
+                ("nu_post", ctypes.c_int), ("inv_precision", ctypes.c_int), ("coarse_galerkin", ctypes.c_int),
+                ("inv_format", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -150,7 +152,7 @@ class Hierarchy:
 
     def __init__(self, dim=2, n_cells=32, n_levels=3, dmask=0b1111, kind="vertex", smoother="rav",
                  omega=0.66, nu_pre=2, nu_post=2, precision="fp64", eta_out=1.0, eta_in=1.0,
-                 inclusions=None, stream=None, galerkin=False):
+                 inclusions=None, stream=None, galerkin=False, inv_format="rows"):
         self.lib = lib()
         incl = np.zeros((0, 4)) if inclusions is None else np.asarray(inclusions, dtype=np.float64)
         if incl.size and incl.shape[1] == dim + 1:   # (cx, cy[, cz], r) -> (cx, cy, cz, r)
@@ -164,7 +166,7 @@ class Hierarchy:
         self.desc = RavProblemDesc(dim, n_cells, n_levels, dmask, eta_out, eta_in, len(incl),
                                    ctypes.cast(self._incl, ctypes.POINTER(RavInclusion)), KINDS[kind],
                                    SMOOTHERS[smoother], omega, nu_pre, nu_post, PRECISIONS[precision],
-                                   1 if galerkin else 0)
+                                   1 if galerkin else 0, FORMATS[inv_format])
         self.stream = _stream() if stream is None else stream
         h = _P()
         st = self.lib.rav_create(ctypes.byref(self.desc), self.stream, ctypes.byref(h))
@@ -384,7 +386,8 @@ class Batch:
                                            ctypes.cast(arr, ctypes.POINTER(RavInclusion)),
                                            KINDS[p.get("kind", "vertex")], SMOOTHERS["rav"], p.get("omega", 0.66),
                                            p.get("nu_pre", 2), p.get("nu_post", 2),
-                                           PRECISIONS[p.get("precision", "fp64")], 1 if p.get("galerkin") else 0)
+                                           PRECISIONS[p.get("precision", "fp64")], 1 if p.get("galerkin") else 0,
+                                           FORMATS[p.get("inv_format", "rows")])
         self.n = n
         self.stream = _stream() if stream is None else stream
         h = _P()
@@ -450,10 +453,11 @@ class Batch:
 
 
 def make_desc(dim=2, n_cells=32, n_levels=3, dmask=0b1111, kind="vertex", smoother="rav", omega=0.66,
-              nu_pre=2, nu_post=2, precision="fp64", eta_out=1.0, eta_in=1.0, galerkin=False):
+              nu_pre=2, nu_post=2, precision="fp64", eta_out=1.0, eta_in=1.0, galerkin=False, inv_format="rows"):
     """Descriptor without inclusions (for the host-only map functions)."""
     return RavProblemDesc(dim, n_cells, n_levels, dmask, eta_out, eta_in, 0, None, KINDS[kind],
-                          SMOOTHERS[smoother], omega, nu_pre, nu_post, PRECISIONS[precision], 1 if galerkin else 0)
+                          SMOOTHERS[smoother], omega, nu_pre, nu_post, PRECISIONS[precision], 1 if galerkin else 0,
+                          FORMATS[inv_format])
 
 
 def map_patch(desc, level, patch):

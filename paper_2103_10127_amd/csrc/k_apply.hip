@@ -279,6 +279,141 @@ __global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply(const GridDev* __
   rav_apply_body<DIM, KIND, CLS, WT, SPLIT>(G, tasks[blockIdx.x]);
 }
 
+// ---- RAV apply from the factored inverse (vertex patches) --------------------
+// With A_i = I_d (x) K and one pressure (k_factor's block structure) the owned
+// rows of L_i^{-1} applied to r_i are
+//   u = S^{-1} (z^T r_u - r_p),   y_c[a] = sum_j K^{-1}[a][j] r_c[j] + z_c[a] u,   y_p = -u
+// for the owned nodes a, with z = K^{-1} B.  Stored per patch, node-major (see
+// fact_nvals): 151 values for a 2D vertex patch instead of the 459 of its
+// owned rows, 1,376 for a 3D one instead of 9,400, so the stream of W, which
+// bounds the sweep, is 3x (2D) to 7x (3D) shorter.  Nodes are processed in
+// groups that start on a 16-byte chunk boundary, as the columns of the
+// row-format kernel; SPLIT lanes share a patch the same way.
+template <typename WT>
+__device__ __forceinline__ typename WTraits<WT>::acc_t fact_elem(
+    const __attribute__((address_space(1))) typename WTraits<WT>::vec_t* __restrict__ W, long long cs, int e) {
+  constexpr int V = WTraits<WT>::V;
+  return vec_elem<WT>(__builtin_nontemporal_load(W + (long long)(e / V) * cs), e % V);
+}
+
+template <int DIM, typename WT, int SPLIT>
+__device__ __forceinline__ void rav_apply_fact_body(const GridDev* __restrict__ G, const BlockTask t) {
+  typedef typename WTraits<WT>::acc_t acc_t;
+  typedef typename WTraits<WT>::vec_t vec_t;
+  constexpr int KIND = KIND_VERTEX;
+  constexpr int V = WTraits<WT>::V;
+  constexpr int NN = fact_nn(DIM);
+  constexpr int NO = fact_nown_nodes(DIM);    // owned nodes
+  constexpr int GV = fact_per_node(DIM);      // values per node
+  constexpr int GN = V / gcd_c(GV, V);        // nodes per group
+  constexpr int CPG = GN * GV / V;            // 16-byte chunks per group
+  constexpr int NG = NN / GN;
+  constexpr int TAILN = NN - NG * GN;
+  constexpr int TAIL_E = TAILN * GV;
+  constexpr int TAIL_CH = (TAIL_E + V - 1) / V;
+  constexpr int SINV = NN * GV;               // element index of S^{-1}
+  if (t.grid < 0) return;
+  const GridDev& gd = G[t.grid];
+  if (grid_idle(gd)) return;
+  const Bucket& bk = gd.bk[t.part];
+  const int sl = SPLIT > 1 ? (int)(threadIdx.x % SPLIT) : 0;
+  const long long p = t.start + threadIdx.x / SPLIT;
+  if (p >= bk.count) return;   // whole groups of SPLIT lanes leave together
+  const Geo& g = gd.g;
+  int k[3] = {0, 0, 0};
+  bucket_anchor(g, KIND, 0, p, k);
+  const ColMap cm{(unsigned)g.nn, (unsigned)g.nV, (unsigned)g.np1, 2u * (unsigned)g.N, g.dmask};
+  gcdouble* __restrict__ r = (gcdouble*)gd.r;
+  typedef __attribute__((address_space(1))) const vec_t gcvec;
+  gcvec* __restrict__ W = (gcvec*)bk.W + w_vec(bk, p, 0);
+  const long long cs = bk.count_pad;
+  acc_t y[DIM][NO], tz = acc_t(0);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+#pragma unroll
+    for (int a = 0; a < NO; ++a) y[c][a] = acc_t(0);
+#pragma unroll 1
+  for (int gi = sl; gi < NG; gi += SPLIT) {
+    vec_t w[CPG];
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) w[i] = __builtin_nontemporal_load(W + (long long)(gi * CPG + i) * cs);
+    acc_t rv[GN][DIM];
+#pragma unroll
+    for (int i = 0; i < GN; ++i)
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) rv[i][c] = acc_t(ldr(r, col_index<DIM, KIND>(cm, k, c * NN + gi * GN + i)));
+#pragma unroll
+    for (int el = 0; el < GN * GV; ++el) {
+      const int i = el / GV, q = el % GV;
+      const acc_t v = vec_elem<WT>(w[el / V], el % V);
+      if (q < NO) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) y[c][q] += v * rv[i][c];
+      } else {
+        tz += v * rv[i][q - NO];
+      }
+    }
+  }
+  if constexpr (TAILN > 0) {
+    if (sl == SPLIT - 1) {
+      vec_t w[TAIL_CH];
+#pragma unroll
+      for (int i = 0; i < TAIL_CH; ++i) w[i] = __builtin_nontemporal_load(W + (long long)(NG * CPG + i) * cs);
+      acc_t rv[TAILN][DIM];
+#pragma unroll
+      for (int i = 0; i < TAILN; ++i)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) rv[i][c] = acc_t(ldr(r, col_index<DIM, KIND>(cm, k, c * NN + NG * GN + i)));
+#pragma unroll
+      for (int el = 0; el < TAIL_E; ++el) {
+        const int i = el / GV, q = el % GV;
+        const acc_t v = vec_elem<WT>(w[el / V], el % V);
+        if (q < NO) {
+#pragma unroll
+          for (int c = 0; c < DIM; ++c) y[c][q] += v * rv[i][c];
+        } else {
+          tz += v * rv[i][q - NO];
+        }
+      }
+    }
+  }
+  if constexpr (SPLIT > 1) {
+#pragma unroll
+    for (int o = SPLIT / 2; o > 0; o >>= 1) {
+      tz += __shfl_xor(tz, o, SPLIT);
+#pragma unroll
+      for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int a = 0; a < NO; ++a) y[c][a] += __shfl_xor(y[c][a], o, SPLIT);
+    }
+  }
+  // u = S^{-1} (z^T r_u - r_p); then the owned rows get z_c[a] u
+  const acc_t u = fact_elem<WT>(W, cs, SINV) * (tz - acc_t(ldr(r, col_index<DIM, KIND>(cm, k, DIM * NN))));
+  const double om = gd.omega_patch ? (double)gd.omega_patch[patch_lin(g, KIND, k)] : gd.omega;
+  gdouble* __restrict__ x = (gdouble*)gd.x;
+#pragma unroll
+  for (int j = 0; j <= DIM * NO; ++j) {
+    if (SPLIT > 1 && (j % SPLIT) != sl) continue;
+    const int l = bucket_own_local(DIM, KIND, 0, j);
+    acc_t val;
+    if (j < DIM * NO) {
+      const int c = j / NO, a = j % NO;
+      const int node = bucket_own_local(DIM, KIND, 0, a);   // component 0: local index = node
+      val = y[c][a] + fact_elem<WT>(W, cs, node * GV + NO + c) * u;
+    } else {
+      val = -u;
+    }
+    const long long gi = own_index<DIM, KIND>(cm, k, l);
+    if (gi >= 0) x[gi] += om * (double)val;
+  }
+}
+
+template <int DIM, typename WT, int SPLIT>
+__global__ __launch_bounds__(APPLY_BLOCK_MAX) void k_rav_apply_fact(const GridDev* __restrict__ G,
+                                                                   const BlockTask* __restrict__ tasks) {
+  rav_apply_fact_body<DIM, WT, SPLIT>(G, tasks[blockIdx.x]);
+}
+
 // Row-parallel RAV apply for tiny buckets: one wavefront per patch, lane j
 // accumulates owned rows j and j + 64 over the patch columns.  The column loop
 // is wave-uniform (the r value of a column is one broadcast load), so the
@@ -477,8 +612,29 @@ static void launch_apply_s(int dim, int kind, int cls, int prec, const GridDev* 
   else launch_apply_k<3, KIND_ELEMENT, SPLIT>(cls, prec, G, tasks, ntasks, s);
 }
 
+template <int DIM, int SPLIT>
+static void launch_fact_k(int prec, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
+  const dim3 grid(ntasks), blk(apply_block(SPLIT));
+  if (prec == P_FP64) hipLaunchKernelGGL((k_rav_apply_fact<DIM, double, SPLIT>), grid, blk, 0, s, G, tasks);
+  else if (prec == P_FP32) hipLaunchKernelGGL((k_rav_apply_fact<DIM, float, SPLIT>), grid, blk, 0, s, G, tasks);
+  else hipLaunchKernelGGL((k_rav_apply_fact<DIM, bf16_t, SPLIT>), grid, blk, 0, s, G, tasks);
+}
+
+template <int SPLIT>
+static void launch_fact_s(int dim, int prec, const GridDev* G, const BlockTask* tasks, int ntasks, hipStream_t s) {
+  if (dim == 2) launch_fact_k<2, SPLIT>(prec, G, tasks, ntasks, s);
+  else launch_fact_k<3, SPLIT>(prec, G, tasks, ntasks, s);
+}
+
 void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const GridDev* G, const BlockTask* tasks,
-                      int ntasks, hipStream_t s) {
+                      int ntasks, hipStream_t s, int factored) {
+  if (factored) {   // vertex patches; tiny buckets take the widest split (no row-parallel variant)
+    if (split == APPLY_SPLIT_SMALL || split == APPLY_ROWS) launch_fact_s<APPLY_SPLIT_SMALL>(dim, prec, G, tasks, ntasks, s);
+    else if (split == 4) launch_fact_s<4>(dim, prec, G, tasks, ntasks, s);
+    else if (split > 1) launch_fact_s<APPLY_SPLIT>(dim, prec, G, tasks, ntasks, s);
+    else launch_fact_s<1>(dim, prec, G, tasks, ntasks, s);
+    return;
+  }
   if (split == APPLY_ROWS) {
     if (dim == 2 && kind == KIND_VERTEX) launch_apply_rows<2, KIND_VERTEX>(prec, G, tasks, ntasks, s);
     else if (dim == 2) launch_apply_rows<2, KIND_ELEMENT>(prec, G, tasks, ntasks, s);

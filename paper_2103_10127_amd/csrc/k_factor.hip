@@ -208,6 +208,23 @@ __global__ __launch_bounds__((FactorShape<DIM, KIND>::NT)) void k_factor(const G
   const Bucket& bk = gd.bk[bucket];
   constexpr int V = 16 / (int)sizeof(WT);
   WT* W = reinterpret_cast<WT*>(bk.W);
+  if constexpr (KIND == KIND_VERTEX) {
+    if (bk.factored) {   // owned rows of K^{-1}, z = K^{-1} B and S^{-1} (layout of fact_nvals)
+      constexpr int NO = fact_nown_nodes(DIM), GV = fact_per_node(DIM);
+#pragma unroll 1
+      for (int e = tid; e < fact_nvals(DIM); e += NT) {
+        double v;
+        if (e < NN * GV) {
+          const int j = e / GV, q = e - j * GV;
+          v = q < NO ? M[bucket_own_local(DIM, KIND, 0, q) * LD + j] : M[j * LD + NN + (q - NO)];
+        } else {
+          v = Sm[0];
+        }
+        store_w(W, w_vec(bk, p, e / V) * V + e % V, v);
+      }
+      return;
+    }
+  }
   const int nown = bk.nown;
 #pragma unroll 1
   for (int e = tid; e < NPAD * nown; e += NT) {

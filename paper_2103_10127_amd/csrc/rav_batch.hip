@@ -162,6 +162,7 @@ static rav_status build_plans(rav_batch* B) {
         al.bucket = bi;
         al.cls = gds[0].bk[bi].cls;
         al.split = apply_split(total, SPLIT_BELOW);
+        if (gds[0].bk[bi].factored && al.split == APPLY_ROWS) al.split = APPLY_SPLIT_SMALL;
         std::vector<BlockTask> at;
         for (int i = 0; i < ng; ++i) append_tiles(at, i, bi, gds[i].bk[bi].count, apply_block(al.split) / al.split);
         if ((st = upload(B, at, &al.tasks, &al.ntasks)) != RAV_OK) return st;
@@ -203,7 +204,8 @@ static bool smooth_depth(rav_batch* B, int d, int sweeps, bool r_valid) {
   for (int s = 0; s < sweeps; ++s) {
     if (!r_valid) launch_residual(B->dim, P.dG, P.res, P.n_res, nullptr, B->stream);
     for (const ApplyLaunch& al : P.apply)
-      launch_rav_apply(B->dim, B->kind, al.cls, B->prec, al.split, P.dG, al.tasks, al.ntasks, B->stream);
+      launch_rav_apply(B->dim, B->kind, al.cls, B->prec, al.split, P.dG, al.tasks, al.ntasks, B->stream,
+                       level_at(B, P.probs[0], d).hd.bk[al.bucket].factored);
     r_valid = false;
   }
   return r_valid;
@@ -308,9 +310,11 @@ rav_status rav_batch_create(const rav_problem_desc* descs, int n, void* hip_stre
   const int coarsest = d0.n_cells >> (d0.n_levels - 1);
   for (int i = 0; i < n; ++i) {
     const rav_problem_desc& d = descs[i];
-    if (d.dim != d0.dim || d.patch != d0.patch || d.inv_precision != d0.inv_precision || d.nu_pre != d0.nu_pre ||
+    if (d.dim != d0.dim || d.patch != d0.patch || d.inv_precision != d0.inv_precision ||
+        d.inv_format != d0.inv_format || d.nu_pre != d0.nu_pre ||
         d.nu_post != d0.nu_post) {
-      g_batch_error = "all problems of a batch must share dim, patch kind, precision and smoothing steps";
+      g_batch_error = "all problems of a batch must share dim, patch kind, precision, inverse format and smoothing "
+                      "steps";
       return RAV_EINVAL;
     }
     if (d.smoother != RAV_SMOOTHER_RAV) { g_batch_error = "batched solves use the RAV smoother"; return RAV_EUNSUPPORTED; }
@@ -399,9 +403,11 @@ static rav_status autotune_batch(rav_batch* B) {
         BlockTask* tasks = nullptr;
         int nt = 0;
         if ((result = upload(B, at, &tasks, &nt)) != RAV_OK) break;
-        launch_rav_apply(B->dim, B->kind, al.cls, B->prec, split, P.dG, tasks, nt, B->stream);
+        const int fac = level_at(B, P.probs[0], (int)d).hd.bk[al.bucket].factored;
+        launch_rav_apply(B->dim, B->kind, al.cls, B->prec, split, P.dG, tasks, nt, B->stream, fac);
         (void)hipEventRecord(e0, B->stream);
-        for (int r = 0; r < 3; ++r) launch_rav_apply(B->dim, B->kind, al.cls, B->prec, split, P.dG, tasks, nt, B->stream);
+        for (int r = 0; r < 3; ++r)
+          launch_rav_apply(B->dim, B->kind, al.cls, B->prec, split, P.dG, tasks, nt, B->stream, fac);
         (void)hipEventRecord(e1, B->stream);
         float ms = 0.f;
         if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;

@@ -234,10 +234,13 @@ static rav_status build_level(rav_ctx* ctx, int l) {
       B.nown = bucket_nown(D.dim, D.patch, B.cls);
       B.count = cnt;
       B.count_pad = (cnt + 63) / 64 * 64;
+      B.factored = D.inv_format == RAV_FACTORED ? 1 : 0;
       ApplyLaunch al;
       al.bucket = h.nbk;
       al.cls = B.cls;
-      st = make_apply_tasks(ctx, al, cnt, apply_split(cnt, ctx->split_below));
+      int split = apply_split(cnt, ctx->split_below);
+      if (B.factored && split == APPLY_ROWS) split = APPLY_SPLIT_SMALL;   // no row-parallel factored kernel
+      st = make_apply_tasks(ctx, al, cnt, split);
       if (st != RAV_OK) return st;
       L.apply.push_back(al);
       ++h.nbk;
@@ -424,7 +427,8 @@ void rav_apply_level(rav_ctx* ctx, int l) {
   if (D.smoother == RAV_SMOOTHER_RAV) {
     for (const ApplyLaunch& al : L.apply)
       if (!al.merged)
-        launch_rav_apply(D.dim, D.patch, al.cls, ctx->prec, al.split, L.dd, al.tasks, al.ntasks, ctx->stream);
+        launch_rav_apply(D.dim, D.patch, al.cls, ctx->prec, al.split, L.dd, al.tasks, al.ntasks, ctx->stream,
+                         L.hd.bk[al.bucket].factored);
     if (L.n_multi > 0)
       launch_rav_apply_multi(D.dim, D.patch, ctx->prec, L.multi_edges, L.dd, L.multi_tasks, L.n_multi, ctx->stream);
   } else if (D.smoother == RAV_SMOOTHER_AV) {
@@ -635,6 +639,10 @@ rav_status rav_create_ex(const rav_problem_desc* d, void* hip_stream, rav_ctx** 
                    "would store full 376x376 inverses");
   if (d->smoother != RAV_SMOOTHER_RAV && d->inv_precision != RAV_FP64)
     return set_err(nullptr, RAV_EUNSUPPORTED, "low-precision inverses are provided for RAV only");
+  if (d->inv_format != RAV_ROWS && d->inv_format != RAV_FACTORED)
+    return set_err(nullptr, RAV_EINVAL, "bad inverse format");
+  if (d->inv_format == RAV_FACTORED && (d->smoother != RAV_SMOOTHER_RAV || d->patch != RAV_PATCH_VERTEX))
+    return set_err(nullptr, RAV_EUNSUPPORTED, "the factored inverse format is provided for RAV with vertex patches");
 
   rav_ctx* ctx = new rav_ctx();
   ctx->desc = *d;
@@ -765,7 +773,7 @@ static rav_status autotune_apply(rav_ctx* ctx) {
         }
         auto run = [&]() {
           launch_rav_apply(D.dim, D.patch, cand.cls, ctx->prec, cand.split, L.dd, cand.tasks, cand.ntasks,
-                           ctx->stream);
+                           ctx->stream, L.hd.bk[cand.bucket].factored);
         };
         run();
         (void)hipEventRecord(e0, ctx->stream);
@@ -826,7 +834,7 @@ rav_status rav_factor_patches(rav_ctx* ctx) {
       const size_t esz = ctx->prec == P_FP64 ? 8 : ctx->prec == P_FP32 ? 4 : 2;
       for (int bi = 0; bi < h.nbk; ++bi) {
         Bucket& B = h.bk[bi];
-        B.nchunk = ((long long)npad * B.nown + V - 1) / V;
+        B.nchunk = ((B.factored ? (long long)fact_nvals(D.dim) : (long long)npad * B.nown) + V - 1) / V;
         if (!B.W) {
           const size_t bytes = esz * (size_t)V * (size_t)B.nchunk * (size_t)B.count_pad;
           CK(hipMalloc(&B.W, bytes));
@@ -1180,12 +1188,33 @@ rav_status rav_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* ou
       W[(size_t)m * V + v] = val;
     }
   }
+  // entry (owned row j, padded column c) of the owned rows of L_i^{-1}
+  auto entry = [&](int j, int c) -> double {
+    if (!B.factored) return W[(size_t)c * B.nown + j];
+    // factored vertex patch: rows from K^{-1}[owned, :], z = K^{-1} B and S^{-1}
+    const int NN = fact_nn(g.dim), NO = fact_nown_nodes(g.dim), GV = fact_per_node(g.dim);
+    const double sinv = W[(size_t)NN * GV];
+    auto z = [&](int comp, int node) { return W[(size_t)node * GV + NO + comp]; };
+    const int l = bucket_own_local(g.dim, kind, cls, j);
+    const bool rv = l < g.dim * NN, cv = c < g.dim * NN;
+    if (rv) {
+      const int rc = l / NN, a = j % NO;
+      const int an = l % NN;
+      if (cv) {
+        const int cc = c / NN, b = c % NN;
+        return (rc == cc ? W[(size_t)b * GV + a] : 0.0) + z(rc, an) * sinv * z(cc, b);
+      }
+      return -z(rc, an) * sinv;
+    }
+    if (cv) return -sinv * z(c / NN, c % NN);
+    return sinv;
+  };
   int nr = 0;
   for (int j = 0; j < B.nown; ++j) {
     const int l = bucket_own_local(g.dim, kind, cls, j);
     int comp, node[3];
     if (patch_local_dof(g, kind, k, l, &comp, node) < 0) continue;
-    for (size_t c = 0; c < vcol.size(); ++c) out[(size_t)nr * vcol.size() + c] = W[(size_t)vcol[c] * B.nown + j];
+    for (size_t c = 0; c < vcol.size(); ++c) out[(size_t)nr * vcol.size() + c] = entry(j, vcol[c]);
     ++nr;
   }
   *rows = nr;

@@ -265,6 +265,16 @@ RAV_HDC int bucket_own_local(int dim, int kind, int m, int j) {
   }
   return dim * nv + l;
 }
+// Factored storage of a vertex patch's owned inverse rows (RAV_FACTORED):
+// with the local velocity block I_d (x) K and one pressure, the owned rows of
+// L_i^{-1} are determined by the owned rows of K^{-1} (2^d owned nodes x 5^d
+// nodes), Z = K^{-1} B (d x 5^d) and the scalar S^{-1}.  Values per node j:
+// [K^{-1}[own_0][j] .. K^{-1}[own_{2^d-1}][j], Z_0[j] .. Z_{d-1}[j]], then S^{-1}.
+RAV_HDC int fact_nn(int dim) { return ipow(5, dim); }
+RAV_HDC int fact_nown_nodes(int dim) { return ipow(2, dim); }
+RAV_HDC int fact_per_node(int dim) { return fact_nown_nodes(dim) + dim; }
+RAV_HDC int fact_nvals(int dim) { return fact_nn(dim) * fact_per_node(dim) + 1; }
+
 // Elements of bucket m: e_d = N-1 where bit d is set, e_d in [0, N-2] elsewhere.
 RAV_HD long long bucket_count(const Geo& g, int kind, int m) {
   if (kind == KIND_VERTEX) return g.nP;

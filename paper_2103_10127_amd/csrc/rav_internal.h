@@ -39,8 +39,9 @@ struct Bucket {
   int nown;
   long long count;       // patches in the bucket
   long long count_pad;   // rounded up to a multiple of 64
-  long long nchunk;      // ceil(npad * nown / V)
+  long long nchunk;      // ceil(values per patch / V): npad * nown, or fact_nvals(dim) when factored
   void* W;
+  int factored;          // W holds the factored form (vertex patches; see fact_nvals)
 };
 
 // Index (in 16-byte vectors) of vector m of patch p.
@@ -135,7 +136,7 @@ void launch_cell_coef(int dim, long long ncell, const GridDev* G, const double* 
 void launch_norm_finalize(const double* partials, int first, int count, double* out, double* host_out,
                           hipStream_t s);
 void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const GridDev* G, const BlockTask* tasks,
-                      int ntasks, hipStream_t s);
+                      int ntasks, hipStream_t s, int factored = 0);
 // Several buckets of one level in one launch (tasks carry the variant in pad:
 // 4, APPLY_SPLIT or APPLY_ROWS).  edges: some task runs a 3D edge or corner
 // class (3, 5, 6, 7) on a column-group variant.

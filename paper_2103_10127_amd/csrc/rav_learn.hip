@@ -229,7 +229,10 @@ rav_status rav_learn_twogrid(rav_ctx* ctx, const rav_mlp* M, const double* x0, i
   if (st != RAV_OK) return st;
   if (!M || !x0 || nu < 1 || nu > 8) return RAV_EINVAL;
   if (ctx->lv.size() != 2) { ctx->err = "the two-grid loss needs a 2-level context (exact coarse solve)"; return RAV_EINVAL; }
-  if (ctx->prec != P_FP64) { ctx->err = "training uses FP64 inverse rows"; return RAV_EUNSUPPORTED; }
+  if (ctx->prec != P_FP64 || ctx->desc.inv_format != RAV_ROWS) {
+    ctx->err = "training uses FP64 inverse rows (RAV_ROWS)";
+    return RAV_EUNSUPPORTED;
+  }
   if ((st = ensure_twogrid(ctx, nu)) != RAV_OK) return st;
   LearnState* S = state(ctx);
   LevelHost& Lf = ctx->lv[1];
