@@ -77,12 +77,14 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch the plain copy kernel on 1 GiB (for HBM counter scaling)")
     ap.add_argument("--workload", default="2d-512",
-                    choices=["2d-512", "3d-64", "3d-64-vertex", "2d-1024", "batch256", "learned", "smoothers"],
+                    choices=["2d-512", "3d-64", "3d-64-vertex", "2d-1024", "batch256", "learned", "smoothers",
+                             "cavity"],
                     help="2d-512: the headline solve (default); 3d-64: finest-level element-patch sweep; "
                          "3d-64-vertex: 64^3 solve with vertex patches; 2d-1024: inclusions at contrast 1e4; "
                          "batch256: 256 problems; learned: per-patch damping trained on small problems, "
                          "evaluated on 512^2 problems with inclusions; smoothers: RAV/AV/MV cost per cycle, "
-                         "cycles and time to 1e-8 on 32^2 (damping sweep) and 512^2")
+                         "cycles and time to 1e-8 on 32^2 (damping sweep) and 512^2; cavity: driven cavity, "
+                         "smoothing-steps and mesh studies")
     ap.add_argument("--train-steps", type=int, default=800)
     ap.add_argument("--train-lr", type=float, default=3e-3)
     return ap.parse_args()
@@ -225,7 +227,7 @@ def main():
         sys.exit(2)
     if args.workload != "2d-512":
         {"3d-64": bench_3d, "3d-64-vertex": bench_3d_vertex, "2d-1024": bench_1024, "batch256": bench_batch,
-         "learned": bench_learned, "smoothers": bench_smoothers}[args.workload](args)
+         "learned": bench_learned, "smoothers": bench_smoothers, "cavity": bench_cavity}[args.workload](args)
         return
     import torch
     from paper_2103_10127_amd import Hierarchy
@@ -545,6 +547,54 @@ def bench_smoothers(args):
           cost_512=big, damping_sweep_32=sweep)
 
 
+def bench_cavity(args):
+    """Driven cavity (Sec. 4.1): no-slip walls, lid velocity 1 on the top side,
+    no forcing, 2D Q2/Q1, coarsest grid 8x8.  (a) Smoothing-steps study on the
+    512x512 grid (7 levels; the study of Sec. 4.2, Fig. 7, done here on the
+    cavity): for nu = 1..6 pre- and post-smoothing steps, RAV and MV at 0.66 and
+    AV at 0.1, the cycles to 1e-8, the average reduction and the time.  (b) Mesh
+    study at nu = 3 (Sec. 4.1, Fig. 4-5): N = 32 ... 512.  value = smoothed
+    DoFs/s of the RAV V(3,3) solve at 512^2."""
+    import torch
+    from paper_2103_10127_amd import Hierarchy
+
+    def solve(N, smoother, omega, nu, maxit=100):
+        nl = int(np.log2(N // 8)) + 1
+        H = Hierarchy(dim=2, n_cells=N, n_levels=nl, dmask=ri.ALL_DIRICHLET_2D, smoother=smoother, omega=omega,
+                      nu_pre=nu, nu_post=nu, inv_format=args.format if smoother == "rav" else "rows")
+        H.factor()
+        n, _ = H.dofs(nl - 1)
+        level_n = [H.dofs(l)[0] for l in range(nl)]
+        b = torch.zeros(n, dtype=torch.float64, device="cuda")
+        H.assemble_rhs_lid(b, 1.0)
+        x = torch.zeros_like(b)
+        H.solve(x, b, 1e-8, min(maxit, 3))
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it, rel = H.solve(x, b, 1e-8, maxit)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        H.close()
+        status = {0: "converged", 1: "maxit", -4: "diverged"}.get(st, str(st))
+        return {"smoother": smoother, "omega": omega, "nu": nu, "N": N, "status": status, "cycles": it,
+                "rho_avg": rel ** (1.0 / it) if it > 0 and rel > 0 else None, "ms": 1e3 * dt,
+                "ms_per_cycle": 1e3 * dt / max(it, 1),
+                "smoothed_dofs": it * sum(2 * nu * level_n[l] for l in range(1, nl))}
+
+    study = [solve(512, sm_, om, nu) for nu in range(1, 7)
+             for sm_, om in (("rav", 0.66), ("mv", 0.66), ("av", 0.1))]
+    mesh = [solve(N, sm_, om, 3) for N in (32, 64, 128, 256, 512)
+            for sm_, om in (("rav", 0.66), ("mv", 0.66), ("av", 0.1))]
+    r = next(e for e in mesh if e["N"] == 512 and e["smoother"] == "rav")
+    _line("RAV smoothed DoFs/s (whole V(3,3) solve to a 1e-8 residual reduction)",
+          r["smoothed_dofs"] / (1e-3 * r["ms"]), "DoF/s", 1, 1, r["ms"], "f64",
+          {"workload": "2D driven cavity (lid velocity 1, no-slip walls), Taylor-Hood Q2/Q1, coarsest 8x8; "
+                       "smoothing-steps study at 512x512 and mesh study at nu = 3; RAV/MV omega 0.66, AV 0.1",
+           "inverse_format": args.format},
+          smoothing_steps_512=study, mesh_study_nu3=mesh)
+
+
 def bench_1024(args):
     """2D 1024^2 with inclusions at contrast 1e4: the finest-level RAV sweep rate
     (FP64 and BF16 rows), plus the outcome of the solvers on this problem: plain
@@ -621,7 +671,8 @@ def bench_batch(args):
     def make(nu, galerkin=False, precision="fp64"):
         probs = [dict(dim=2, n_cells=int(n), n_levels=ri.levels_to(int(n), cfg["coarsest"]), dmask=cfg["dmask"],
                       eta_out=cfg["eta_out"], eta_in=cfg["contrast"], inclusions=ri.inclusions(cfg["seed"] + i),
-                      omega=0.66, nu_pre=nu, nu_post=nu, galerkin=galerkin, precision=precision)
+                      omega=0.66, nu_pre=nu, nu_post=nu, galerkin=galerkin, precision=precision,
+                      inv_format=args.format)
                  for i, n in enumerate(sizes)]
         t0 = time.perf_counter()
         B = Batch(probs)
@@ -678,7 +729,7 @@ def bench_batch(args):
           1e3 * dt, "f64",
           {"workload": "256 independent 2D Q2/Q1 problems (fine 64/128/256, coarsest 16x16), 1-8 inclusions "
                        "each at contrast 1e3, one batched RAV V(2,2) cycle per step",
-           "problems": len(probs), "dofs_total": total},
+           "problems": len(probs), "dofs_total": total, "inverse_format": args.format},
           setup_s=round(setup, 3), solves=solves)
 
 
@@ -705,7 +756,7 @@ def bench_learned(args):
     rows, tot = [], {"fixed 0.66": [0.0, 0], "fixed 0.8": [0.0, 0], "learned": [0.0, 0]}
     for seed in range(4000, 4004):
         H = Hierarchy(dim=2, n_cells=N, n_levels=nl, dmask=ri.ALL_DIRICHLET_2D, eta_out=1.0, eta_in=contrast,
-                      inclusions=ri.inclusions(seed), omega=0.66)
+                      inclusions=ri.inclusions(seed), omega=0.66, inv_format=args.format)
         H.factor()
         n_fine, _ = H.dofs(nl - 1)
         level_n = [H.dofs(l)[0] for l in range(nl)]

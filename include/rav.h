@@ -143,6 +143,14 @@ rav_status rav_n_patches(const rav_ctx* ctx, int level, long* n_patches);
  * p = sum_k c_k prod cos(w pi x). */
 rav_status rav_assemble_rhs(rav_ctx* ctx, const double* mms_params_host, int n_params, double* b_dev);
 
+/* Driven cavity (Sec. 4.1): b_dev = -L[free, masked] u_D on the finest level,
+ * the right-hand side of the lifted problem for no-slip walls and the lid
+ * velocity u = (lid_u, 0) on the top side's nodes strictly between the corners
+ * (the corners belong to the walls), no forcing.  The solution of L x = b is
+ * the velocity minus u_D (masked entries stay 0).  2D only; the top side must
+ * be Dirichlet (bit 3 of bc_dirichlet_mask), else RAV_EINVAL. */
+rav_status rav_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev);
+
 /* r_dev = b_dev - L x_dev on free rows, 0 on masked rows (eq. 10).  If
  * norm_host is non-NULL it receives ||r||_2 (synchronises). */
 rav_status rav_residual(rav_ctx* ctx, int level, const double* x_dev, const double* b_dev,

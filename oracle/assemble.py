@@ -140,3 +140,30 @@ def matrix_row(grid: Grid, row: int, eta_out=1.0, eta_in=1.0, incl=None):
                     if grid.free[col]:
                         out[col] = out.get(col, 0.0) + Be[cc, la, lk]
     return out
+
+
+def lid_velocity(grid: Grid, U=1.0):
+    """Dirichlet data of the driven cavity (Sec. 4.1): horizontal velocity U on
+    the top side's nodes strictly between the corners, zero elsewhere (the
+    corners belong to the no-slip walls, so the data has no normal flux).
+    Full-length vector, nonzero only on masked DoFs."""
+    assert grid.dim == 2
+    u = np.zeros(grid.n)
+    a = grid.vnode
+    top = (a[:, 1] == 2 * grid.N) & (a[:, 0] > 0) & (a[:, 0] < 2 * grid.N)
+    u[: grid.nV][top] = U
+    u[grid.free] = 0.0   # only masked (Dirichlet) entries carry data
+    return u
+
+
+def dirichlet_lifting(grid: Grid, uD, eta_out=1.0, eta_in=1.0, incl=None):
+    """Right-hand side contribution of nonhomogeneous Dirichlet data uD (values
+    on masked DoFs): b = -L_all[free, masked] uD on free rows, zero on masked
+    rows, where L_all is the operator assembled with no DoF masked (eq. 6 with
+    the Dirichlet columns kept)."""
+    open_grid = Grid(grid.dim, grid.N, 0)
+    L_all = assemble_matrix(open_grid, eta_out, eta_in, incl)
+    ud = np.where(grid.free, 0.0, uD)
+    b = -(L_all @ ud)
+    b[~grid.free] = 0.0
+    return b

@@ -59,6 +59,7 @@ SIGNATURES = {
     "rav_n_patches": (_S, [_P, _I, ctypes.POINTER(_L)]),
     "rav_assemble_rhs": (_S, [_P, ctypes.POINTER(_D), _I, _P]),
     "rav_residual": (_S, [_P, _I, _P, _P, _P, ctypes.POINTER(_D)]),
+    "rav_assemble_rhs_lid": (_S, [_P, _D, _P]),
     "rav_smooth": (_S, [_P, _I, _I, _P, _P]),
     "rav_restrict": (_S, [_P, _I, _P, _P]),
     "rav_prolong_add": (_S, [_P, _I, _P, _P]),
@@ -207,6 +208,9 @@ class Hierarchy:
     def assemble_rhs(self, params, b):
         p = np.ascontiguousarray(params, dtype=np.float64)
         return self._chk(self.lib.rav_assemble_rhs(self.h, p.ctypes.data_as(ctypes.POINTER(_D)), len(p), _ptr(b)))
+
+    def assemble_rhs_lid(self, b, lid_u=1.0):
+        return self._chk(self.lib.rav_assemble_rhs_lid(self.h, lid_u, _ptr(b)))
 
     def residual(self, level, x, b, r, norm=False):
         nv = _D()

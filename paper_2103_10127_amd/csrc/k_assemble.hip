@@ -472,7 +472,60 @@ __global__ __launch_bounds__(256) void k_cut_matrices_galerkin(const GridDev* G,
   cutA[t] = hA * s;
 }
 
+// Driven-cavity lifting (2D): the right-hand side -L[free, masked] u_D for
+// the Dirichlet data u_D = (U, 0) on the top side's nodes strictly between the
+// corners.  Only the top row of cells couples to the lid: threads take the
+// x-velocity rows on the two node rows below the lid and the pressure rows on
+// the two vertex rows at the top; the viscous entries come from the level's
+// per-cell coefficients (reference matrix times h^(d-2) eta, or the stored cut
+// cell matrix), the divergence entries from the reference integrals.
+__global__ __launch_bounds__(256) void k_lift_lid(const GridDev* G, double U, double* b) {
+  const Geo& g = G->g;
+  const int N = g.N;
+  const long long nvel = 2LL * (2 * N + 1), npres = 2LL * (N + 1);
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nvel + npres) return;
+  const double hB = G->h;
+  double s = 0.0;
+  const int E1 = N - 1;   // the top row of cells
+  if (t < nvel) {
+    int a[3] = {(int)(t % (2 * N + 1)), 2 * N - 2 + (int)(t / (2 * N + 1)), 0};
+    if (node_dirichlet(g, a)) return;
+    for (int ex = max(ceil_half(a[0] - 2), 0); ex <= min(a[0] >> 1, N - 1); ++ex) {
+      const long long cell = ex + (long long)N * E1;
+      const int la[2] = {a[0] - 2 * ex, a[1] - 2 * E1};
+      const double ce = G->ceta[cell];
+      for (int bx = 0; bx < 3; ++bx) {
+        const int nbx = 2 * ex + bx;
+        if (nbx <= 0 || nbx >= 2 * N) continue;   // lid nodes only (corners are walls)
+        const int ia = la[0] + 3 * la[1], ib = bx + 3 * 2;
+        const double v = ce >= 0.0 ? ce * c_ref.aref2[ia][ib] : G->cutA[((long long)(-ce - 1.0) * 9 + ia) * 9 + ib];
+        s += v * U;
+      }
+    }
+    b[node_lin(g, a)] = -s;   // x-velocity row (component 0)
+    return;
+  }
+  const long long tp = t - nvel;
+  int k[3] = {(int)(tp % (N + 1)), N - 1 + (int)(tp / (N + 1)), 0};
+  for (int ex = max(k[0] - 1, 0); ex <= min(k[0], N - 1); ++ex) {
+    const int lk[2] = {k[0] - ex, k[1] - E1};
+    for (int bx = 0; bx < 3; ++bx) {
+      const int nbx = 2 * ex + bx;
+      if (nbx <= 0 || nbx >= 2 * N) continue;
+      const int lb[2] = {bx, 2};
+      s += hB * bref<2>(0, lb, lk) * U;
+    }
+  }
+  b[2 * g.nV + vert_lin(g, k)] = -s;
+}
+
 static inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_lift_lid(const GridDev* G, const Geo& g, double U, double* b, hipStream_t s) {
+  const long long nt = 2LL * (2 * g.N + 1) + 2LL * (g.N + 1);
+  hipLaunchKernelGGL(k_lift_lid, dim3(nblk(nt, 256)), dim3(256), 0, s, G, U, b);
+}
 
 void launch_eta(int dim, long long ncell, const GridDev* G, const double* incl, int n_incl, double eta_out,
                 double eta_in, int R, double* etaq, unsigned char* uni, hipStream_t s) {

@@ -913,6 +913,19 @@ rav_status rav_assemble_rhs(rav_ctx* ctx, const double* params, int n_params, do
   return RAV_OK;
 }
 
+rav_status rav_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev) {
+  if (!ctx || !b_dev || !std::isfinite(lid_u)) return RAV_EINVAL;
+  const rav_problem_desc& D = ctx->desc;
+  if (D.dim != 2 || !((D.bc_dirichlet_mask >> 3) & 1u))
+    return set_err(ctx, RAV_EINVAL, "the driven cavity needs a 2D grid with a Dirichlet top side (bit 3)");
+  LevelHost& L = ctx->lv.back();
+  launch_fill(b_dev, 0.0, L.hd.g.n, ctx->stream);
+  launch_lift_lid(L.dd, L.hd.g, lid_u, b_dev, ctx->stream);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(ctx->stream));
+  return RAV_OK;
+}
+
 rav_status rav_residual(rav_ctx* ctx, int level, const double* x, const double* b, double* r, double* norm) {
   if (check_level(ctx, level, false) != RAV_OK || !x || !b || !r) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];

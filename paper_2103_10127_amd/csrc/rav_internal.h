@@ -130,6 +130,8 @@ void launch_residual(int dim, const GridDev* G, const BlockTask* tasks, int ntas
 bool residual_tiled_ok(int dim, int N);
 int residual_tiles(int dim, int N);
 void launch_residual_tiled(int dim, const GridDev* G, int N, double* partials, hipStream_t s);
+// Driven-cavity lifting -L[free, masked] u_D (2D, u_D = (U, 0) on the lid) added into b.
+void launch_lift_lid(const GridDev* G, const Geo& g, double U, double* b, hipStream_t s);
 void launch_cell_coef(int dim, long long ncell, const GridDev* G, const double* etaq, const int* cut_idx,
                       const int* cut_cells, int ncut, int R, const double* incl, int n_incl, double eta_out,
                       double eta_in, double* ceta, double* cutA, hipStream_t s);

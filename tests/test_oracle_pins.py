@@ -264,3 +264,40 @@ def test_galerkin_cures_the_two_grid_divergence_at_contrast_1e3():
     r1 = _twogrid_rho(32, 1.0, incl, "rediscretised")
     r2 = _twogrid_rho(32, 1.0, incl, "galerkin")
     assert abs(r1 - r2) <= 1e-6 and r1 < 0.5
+
+
+def test_dirichlet_lifting_reproduces_couette_flow():
+    """Nonhomogeneous Dirichlet data through the lifting b = -L[free, masked] u_D:
+    with u_D = (y, 0) on the whole boundary the Stokes solution is the linear
+    shear flow u = (y, 0), p = const, which Q2 velocities represent exactly, so
+    the discrete solution equals it at every free node (solved to 1e-12)."""
+    N = 16
+    H = mg.Hierarchy(2, N, 3, ri.ALL_DIRICHLET_2D)
+    g = H.finest.grid
+    uD = np.zeros(g.n)
+    uD[: g.nV] = g.vnode[:, 1] / (2.0 * N)
+    b = A.dirichlet_lifting(g, uD)
+    assert abs(b[g.pressure_slice()].sum()) <= 1e-14   # no net flux through the boundary
+    x, _, _, st = H.solve(b, rtol=1e-12)
+    fr = g.free[: g.nV]
+    assert st == "converged"
+    assert np.abs(x[: g.nV][fr] - g.vnode[fr, 1] / (2.0 * N)).max() <= 1e-10
+    assert np.abs(x[g.nV: 2 * g.nV][g.free[g.nV: 2 * g.nV]]).max() <= 1e-10
+    assert np.ptp(x[g.pressure_slice()]) <= 1e-8
+
+
+def test_lid_data_is_flux_free_and_only_on_the_lid():
+    """Cavity data (Sec. 4.1): U on the top side's inner nodes, zero on the
+    corners and the walls; its lifting has zero pressure sum (the lid moves
+    tangentially) and touches only rows next to the top row of cells."""
+    g = Grid(2, 8, ri.ALL_DIRICHLET_2D)
+    u = A.lid_velocity(g, 2.5)
+    vals = u[: g.nV].reshape(17, 17)
+    assert np.all(vals[16, 1:16] == 2.5) and vals[16, 0] == 0.0 and vals[16, 16] == 0.0
+    assert np.count_nonzero(u) == 15
+    b = A.dirichlet_lifting(g, u)
+    assert abs(b[g.pressure_slice()].sum()) <= 1e-14
+    rows = np.nonzero(b)[0]
+    vel = rows[rows < g.nV]
+    assert np.all(g.vnode[vel, 1] >= 14)
+    assert np.all(b[g.nV: 2 * g.nV] == 0.0)
