@@ -1,0 +1,280 @@
+"""Pins of the stabilized Q1-Q1 oracle (Sec. 2, eqs. 5-8; Sec. 3, eq. 13)
+against values fixed by the mathematics: the Table 1 DoF count of the coarsest
+cavity grid, the textbook 9-point and 27-point bilinear/trilinear Laplace
+stencils in A and C, closed-form integrals for B and B^T, exactness of the
+interpolation and of the linear shear flow, second-order velocity
+convergence, the literal owned set, the Galerkin scaling of C, and a
+regression bound on the V-cycle counts under refinement."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+
+import rav_inputs as ri
+from oracle import mg
+from oracle import q1q1 as q
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_coarse_grid.txt")
+BETA = 0.1
+
+
+def _row(L, i):
+    r = L.getrow(i)
+    return dict(zip(r.indices.tolist(), r.data.tolist()))
+
+
+def test_table1_coarsest_grid_dof_count():
+    """Table 1, coarsest cavity grid: 64 elements and 243 = 3 * 81 DoFs (two
+    velocity components and the pressure on each of the 81 vertices)."""
+    rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
+    refinements, n_e, n_dof = map(int, rows[0])
+    N = 2 ** refinements
+    g = q.GridQ1(2, N, ri.ALL_DIRICHLET_2D)
+    assert N * N == n_e and g.n == n_dof
+
+
+def test_viscous_block_is_the_bilinear_laplace_stencil():
+    """Interior row of A (eta = 1): the 2D bilinear stencil is 8/3 at the
+    centre and -1/3 at each of the eight neighbours (h-independent); the 3D
+    trilinear one is h * (8/3 centre, 0 faces, -1/6 edges, -1/12 corners)."""
+    g = q.GridQ1(2, 8, ri.ALL_DIRICHLET_2D)
+    L = q.assemble_matrix(g, BETA)
+    v = np.array([3, 5])
+    row = _row(L, int(g.vel(1, v)))
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            expect = 8.0 / 3.0 if dx == dy == 0 else -1.0 / 3.0
+            assert abs(row.pop(int(g.vel(1, v + [dx, dy]))) - expect) <= 1e-14
+    assert all(c >= g.dim * g.nV for c in row)   # the rest are pressure columns
+    g3 = q.GridQ1(3, 4, ri.ALL_DIRICHLET_3D)
+    L3 = q.assemble_matrix(g3, BETA)
+    v = np.array([2, 2, 2])
+    row = _row(L3, int(g3.vel(2, v)))
+    h = g3.h
+    for off in np.ndindex(3, 3, 3):
+        o = np.array(off) - 1
+        nz = int(np.count_nonzero(o))
+        expect = h * {0: 8.0 / 3.0, 1: 0.0, 2: -1.0 / 6.0, 3: -1.0 / 12.0}[nz]
+        assert abs(row.pop(int(g3.vel(2, v + o)), 0.0) - expect) <= 1e-14
+    assert all(c >= 3 * g3.nV for c in row)
+
+
+def test_stabilization_block_stencil_and_constants():
+    """C = -beta diam^2 (grad q, grad p): an interior 2D row is -beta * 2h^2
+    times the bilinear stencil, a 3D row -beta * 3h^2 times the trilinear one;
+    every row of C sums to zero (constants are in its kernel)."""
+    for dim, N in ((2, 8), (3, 4)):
+        g = q.GridQ1(dim, N, (1 << 2 * dim) - 1)
+        L = q.assemble_matrix(g, BETA)
+        C = L[g.pressure_slice(), g.pressure_slice()]
+        assert np.abs(np.asarray(C.sum(axis=1))).max() <= 1e-15
+        assert abs(C - C.T).max() <= 1e-16
+        v = np.full(dim, 2)
+        k = int(g.vidx(v))
+        centre = C[k, k]
+        expect = -BETA * dim * g.h ** 2 * (8.0 / 3.0 if dim == 2 else 8.0 * g.h / 3.0)
+        assert abs(centre - expect) <= 1e-15
+        corner = C[k, int(g.vidx(v + 1))]
+        expect_c = -BETA * dim * g.h ** 2 * (-1.0 / 3.0 if dim == 2 else -g.h / 12.0)
+        assert abs(corner - expect_c) <= 1e-16
+
+
+def test_divergence_blocks_closed_forms():
+    """No DoF masked, h = 1/8.  For v = (x, 0), div v = 1, so the pressure row
+    j of B^T v is -int psi_j = -h^2 (interior), -h^2/2 (side), -h^2/4 (corner).
+    For v = (0, xy), div v = x and the interior row is -x_j h^2 (the hat
+    function's centroid is its vertex).  For q = x, the x-velocity row a of
+    B q is -int dphi_a/dx x = int phi_a = h^2 at interior vertices and the
+    y-velocity row is 0 (integration by parts; phi_a vanishes on the boundary)."""
+    g = q.GridQ1(2, 8, 0)
+    L = q.assemble_matrix(g, BETA)
+    h, nV = g.h, g.nV
+    x, y = g.vnode[:, 0] * h, g.vnode[:, 1] * h
+    onx = (g.vnode[:, 0] == 0) | (g.vnode[:, 0] == 8)
+    ony = (g.vnode[:, 1] == 0) | (g.vnode[:, 1] == 8)
+    area = h * h / (2.0 ** (onx.astype(int) + ony.astype(int)))
+    BT = L[2 * nV:, :2 * nV]
+    v = np.concatenate([x, np.zeros(nV)])
+    np.testing.assert_allclose(BT @ v, -area, rtol=0, atol=1e-15)
+    v = np.concatenate([np.zeros(nV), x * y])
+    inner = ~onx & ~ony
+    np.testing.assert_allclose((BT @ v)[inner], -x[inner] * h * h, rtol=0, atol=1e-15)
+    B = L[:2 * nV, 2 * nV:]
+    Bq = B @ x
+    np.testing.assert_allclose(Bq[:nV][inner], h * h, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Bq[nV:][inner], 0.0, rtol=0, atol=1e-15)
+
+
+def test_interpolation_exact_for_multilinear_functions():
+    """P maps the coarse nodal values of a bilinear (trilinear) function to
+    its fine nodal values, in every field; masked rows stay zero."""
+    for dim, N in ((2, 8), (3, 4)):
+        dm = 0
+        gf, gc = q.GridQ1(dim, N, dm), q.GridQ1(dim, N // 2, dm)
+        P = q.prolongation(gf, gc)
+
+        def f(g):
+            pts = g.vnode * g.h
+            vals = 1.0 + 2.0 * pts[:, 0] - 3.0 * pts[:, 1] + 5.0 * pts[:, 0] * pts[:, 1]
+            if dim == 3:
+                vals = vals * (1.0 - pts[:, 2])
+            return np.concatenate([vals * (c + 1) for c in range(dim + 1)])
+
+        np.testing.assert_allclose(P @ f(gc), f(gf), rtol=0, atol=1e-13)
+    gf, gc = q.GridQ1(2, 8, ri.ALL_DIRICHLET_2D), q.GridQ1(2, 4, ri.ALL_DIRICHLET_2D)
+    P = q.prolongation(gf, gc)
+    assert abs(P[~gf.free]).max() == 0 and abs(P[:, ~gc.free]).max() == 0
+
+
+def _solve_direct(g, L, b):
+    f = g.free
+    e = np.zeros(g.n)
+    e[g.pressure_slice()] = 1.0
+    M = sp.bmat([[L[f][:, f], sp.csc_matrix(e[f][:, None])], [sp.csc_matrix(e[f][None, :]), None]]).tocsc()
+    y = spl.spsolve(M, np.concatenate([b[f], [0.0]]))
+    x = np.zeros(g.n)
+    x[f] = y[:-1]
+    return x
+
+
+def test_velocity_converges_at_second_order():
+    """Manufactured solution, all-Dirichlet: the nodal velocity error falls by
+    about 4 per halving of h (Q1 interpolation order); a wrong sign or block
+    would stall it."""
+    par = ri.mms_params(2, 1001)
+    errs = []
+    for N in (8, 16, 32):
+        g = q.GridQ1(2, N, ri.ALL_DIRICHLET_2D)
+        x = _solve_direct(g, q.assemble_matrix(g, BETA), q.assemble_rhs(g, par))
+        errs.append(q.nodal_error(g, par, x))
+    eu = [e[0] for e in errs]
+    assert eu[0] / eu[1] > 3.5 and eu[1] / eu[2] > 3.8, eu
+    ep = [e[1] for e in errs]
+    assert ep[0] / ep[1] > 2.5 and ep[1] / ep[2] > 2.5, ep
+
+
+def test_linear_shear_flow_is_reproduced():
+    """Dirichlet data u = (y, 0) on the whole boundary through the lifting
+    b = -L[free, masked] u_D: the bilinear velocity space holds the Stokes
+    solution u = (y, 0), p = const exactly (and C p = 0), so the discrete
+    solution equals it; the lid data is flux free and sits on the top side's
+    inner vertices only."""
+    N = 8
+    g = q.GridQ1(2, N, ri.ALL_DIRICHLET_2D)
+    uD = np.zeros(g.n)
+    uD[: g.nV] = g.vnode[:, 1] * g.h
+    b = q.dirichlet_lifting(g, uD, BETA)
+    x = _solve_direct(g, q.assemble_matrix(g, BETA), b)
+    fr = g.free[: g.nV]
+    assert np.abs(x[: g.nV][fr] - g.vnode[fr, 1] * g.h).max() <= 1e-12
+    assert np.abs(x[g.nV: 2 * g.nV][fr]).max() <= 1e-12
+    assert np.abs(x[g.pressure_slice()]).max() <= 1e-12
+    u = q.lid_velocity(g, 1.0)
+    vals = u[: g.nV].reshape(N + 1, N + 1)
+    assert np.all(vals[N, 1:N] == 1.0) and np.count_nonzero(u) == N - 1
+    bl = q.dirichlet_lifting(g, u, BETA)
+    assert abs(bl[g.pressure_slice()].sum()) <= 1e-15
+
+
+def test_patches_and_literal_owned_set():
+    """Vertex patches hold 2*9 + 1 = 19 DoFs inside a 2D grid and 3*27 + 1 = 82
+    in 3D; a patch owns its pressure and the velocity at its own vertex (3 or 4
+    rows inside, 1 where the vertex velocity is masked); every free DoF is
+    owned exactly once and owned DoFs belong to the owning patch."""
+    for dim, N, full in ((2, 8, 19), (3, 4, 82)):
+        g = q.GridQ1(dim, N, (1 << 2 * dim) - 1)
+        ps = q.PatchSetQ1(g)
+        sizes = np.array([len(I) for I in ps.dofs])
+        inner = np.all((g.vnode >= 2) & (g.vnode <= N - 2), axis=1)
+        assert np.all(sizes[inner] == full)
+        cnt = np.zeros(g.n, int)
+        for k, (I, own) in enumerate(zip(ps.dofs, ps.owned)):
+            cnt[I[own]] += 1
+            on_wall = g.dirichlet_node[k]
+            assert len(own) == (1 if on_wall else dim + 1)
+            assert I[-1] == g.pres(g.vnode[k])
+        assert np.all(cnt[g.free] == 1) and np.all(cnt[~g.free] == 0)
+    # 2D 8x8 inner-vertex count pinned by hand: 81 vertices, 49 interior
+    assert int((~q.GridQ1(2, 8, 15).dirichlet_node).sum()) == 49
+
+
+def test_rav_sweep_is_the_dense_operator():
+    """Brute force on 4x4: one RAV sweep equals x - S L x with S the sum of
+    the owned rows of the dense patch inverses (eq. 13)."""
+    H = q.HierarchyQ1(2, 4, 2, ri.ALL_DIRICHLET_2D, BETA)
+    lv = H.finest
+    ps = lv.patches
+    M = mg.dense_smoother_operator(lv.L, lv.free, ps.dofs, ps.owned, lv.lus, 0.7, mg.RAV)
+    x = ri.random_vector(lv.grid.n, 7) * lv.free
+    y = H.smooth(1, x, np.zeros_like(x), mg.RAV, 0.7, 1)
+    np.testing.assert_allclose(y, M @ x, rtol=0, atol=1e-13)
+
+
+@pytest.mark.slow
+def test_vcycle_counts_on_refinement():
+    """RAV V(3,3), omega 0.66, coarsest 8x8, beta 0.1, from 16^2 to 128^2: the
+    rediscretised hierarchy converges on every grid but its count grows with
+    the depth (7, 10, 14, 19: the coarse levels' stabilization, 4x stronger
+    per level, departs from the fine operator's), the Galerkin hierarchy stays
+    within 6-11.  A regression bound on both, not a paper value."""
+    par = ri.mms_params(2, 1001)
+    for coarse, lo, hi in (("rediscretised", 6, 20), ("galerkin", 5, 12)):
+        its = []
+        for N in (16, 32, 64, 128):
+            H = q.HierarchyQ1(2, N, int(np.log2(N // 8)) + 1, ri.ALL_DIRICHLET_2D, BETA, coarse=coarse)
+            _, k, _, st = H.solve(q.assemble_rhs(H.finest.grid, par), 1e-8, 50, mg.RAV, 0.66, 3)
+            assert st == "converged", (coarse, N)
+            its.append(k)
+        assert lo <= min(its) and max(its) <= hi and its == sorted(its), (coarse, its)
+
+
+def test_galerkin_coarse_operator_scaling():
+    """Constant viscosity, nested spaces: P^T L_f P keeps the coarse viscous
+    and divergence blocks of rediscretisation (both forms are integrated
+    exactly and have no h in their coefficient) but its stabilization block is
+    the coarse one with the fine diameter, i.e. 1/4 of the rediscretised C
+    (diam^2 scales with h^2); in 3D as in 2D."""
+    for dim, N in ((2, 8), (3, 4)):
+        dm = (1 << 2 * dim) - 1
+        gf, gc = q.GridQ1(dim, N, dm), q.GridQ1(dim, N // 2, dm)
+        P = q.prolongation(gf, gc)
+        G = (P.T @ q.assemble_matrix(gf, BETA) @ P).tocsr()
+        R = q.assemble_matrix(gc, BETA).tocsr()
+        u = slice(0, dim * gc.nV)
+        p = gc.pressure_slice()
+        assert abs(G[u, u] - R[u, u]).max() <= 1e-14
+        assert abs(G[u, p] - R[u, p]).max() <= 1e-14
+        assert abs(G[p, p] - 0.25 * R[p, p]).max() <= 1e-16
+
+
+def test_galerkin_hierarchy_is_the_triple_product():
+    """HierarchyQ1(coarse='galerkin') holds P^T L P on every coarser level."""
+    H = q.HierarchyQ1(2, 16, 3, ri.ALL_DIRICHLET_2D, BETA, 1.0, 100.0, [[0.4, 0.6, 0.1]], coarse="galerkin")
+    for l in (2, 1):
+        lv = H.levels[l]
+        assert abs(H.levels[l - 1].L - (lv.P.T @ lv.L @ lv.P)).max() <= 1e-14
+
+
+def test_3d_two_grid_cycle_converges():
+    """3D, 8^3 on 4^3: RAV V(2,2), omega 0.66, converges to 1e-8 in fewer than
+    25 cycles (an operator error in 3D would stall or diverge)."""
+    H = q.HierarchyQ1(3, 8, 2, ri.ALL_DIRICHLET_3D, BETA)
+    b = q.assemble_rhs(H.finest.grid, ri.mms_params(3, 1003))
+    _, k, hist, st = H.solve(b, 1e-8, 40, mg.RAV, 0.66, 2)
+    assert st == "converged" and k < 25, (st, k)
+
+
+def test_matrix_row_equals_assembled_rows():
+    """The single-row assembly used for large grids reproduces every row of
+    the assembled operator (2D with an inclusion, 3D)."""
+    for dim, N, dm, incl in ((2, 6, ri.ALL_DIRICHLET_2D, [[0.4, 0.5, 0.2]]), (3, 3, ri.ALL_DIRICHLET_3D, None)):
+        g = q.GridQ1(dim, N, dm)
+        L = q.assemble_matrix(g, BETA, 1.0, 30.0, incl).tocsr()
+        for i in range(g.n):
+            row = q.matrix_row(g, i, BETA, 1.0, 30.0, incl)
+            ref = _row(L, i)
+            assert set(row) == set(ref), i
+            for c in row:
+                assert abs(row[c] - ref[c]) <= 1e-15, (i, c)
