@@ -77,14 +77,14 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch the plain copy kernel on 1 GiB (for HBM counter scaling)")
     ap.add_argument("--workload", default="2d-512",
-                    choices=["2d-512", "3d-64", "3d-64-vertex", "2d-1024", "batch256", "learned", "smoothers",
+                    choices=["2d-512", "3d-64", "3d-64-vertex", "2d-1024", "batch256", "learned", "smoothers", "q1q1",
                              "cavity"],
                     help="2d-512: the headline solve (default); 3d-64: finest-level element-patch sweep; "
                          "3d-64-vertex: 64^3 solve with vertex patches; 2d-1024: inclusions at contrast 1e4; "
                          "batch256: 256 problems; learned: per-patch damping trained on small problems, "
                          "evaluated on 512^2 problems with inclusions; smoothers: RAV/AV/MV cost per cycle, "
                          "cycles and time to 1e-8 on 32^2 (damping sweep) and 512^2; cavity: driven cavity, "
-                         "smoothing-steps and mesh studies")
+                         "smoothing-steps and mesh studies; q1q1: the stabilized Q1-Q1 driven cavity on 1024^2")
     ap.add_argument("--train-steps", type=int, default=800)
     ap.add_argument("--train-lr", type=float, default=3e-3)
     return ap.parse_args()
@@ -227,7 +227,8 @@ def main():
         sys.exit(2)
     if args.workload != "2d-512":
         {"3d-64": bench_3d, "3d-64-vertex": bench_3d_vertex, "2d-1024": bench_1024, "batch256": bench_batch,
-         "learned": bench_learned, "smoothers": bench_smoothers, "cavity": bench_cavity}[args.workload](args)
+         "learned": bench_learned, "smoothers": bench_smoothers, "cavity": bench_cavity,
+         "q1q1": bench_q1q1}[args.workload](args)
         return
     import torch
     from paper_2103_10127_amd import Hierarchy
@@ -593,6 +594,69 @@ def bench_cavity(args):
                        "smoothing-steps study at 512x512 and mesh study at nu = 3; RAV/MV omega 0.66, AV 0.1",
            "inverse_format": args.format},
           smoothing_steps_512=study, mesh_study_nu3=mesh)
+
+
+def bench_q1q1(args):
+    """The paper's own discretization, stabilized equal-order Q1-Q1 (eq. 8), with
+    the literal RAV owned set (pressure + co-located velocity, Sec. 3): the
+    driven cavity (Sec. 4.1) on 1024^2 (3,151,875 DoFs, close to the 3,063,075 of
+    the finest Table 1 grid), 8 levels down to Table 1's coarsest 8x8 grid (243
+    DoFs), RAV V(3,3) as in Sec. 4, omega 0.66, beta 0.05, factored inverse,
+    solved from 0 to a 1e-8 residual reduction.  Also: the Galerkin hierarchy,
+    a beta sweep, the finest-level residual/apply times with the apply's byte
+    roofline, and a 3D 64^3 cavity-like solve (all-Dirichlet, manufactured
+    forcing).  value = smoothed DoFs/s of the 2D rediscretised solve."""
+    import torch
+    from paper_2103_10127_amd import Hierarchy
+
+    def run(dim, N, nl, beta, gal, rhs, reps=3):
+        dm = ri.ALL_DIRICHLET_2D if dim == 2 else ri.ALL_DIRICHLET_3D
+        t0 = time.perf_counter()
+        H = Hierarchy(dim=dim, n_cells=N, n_levels=nl, dmask=dm, nu_pre=3, nu_post=3, omega=0.66,
+                      galerkin=gal, inv_format="factored", discretization="q1q1", beta=beta)
+        H.factor()
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        n, nfree = H.dofs(nl - 1)
+        level_n = [H.dofs(l)[0] for l in range(nl)]
+        b = torch.zeros(n, dtype=torch.float64, device="cuda")
+        if rhs == "lid":
+            H.assemble_rhs_lid(b, 1.0)
+        else:
+            H.assemble_rhs(ri.mms_params(dim, 1003), b)
+        x = torch.zeros_like(b)
+        H.solve(x, b, 1e-8, 3)
+        best = None
+        for _ in range(reps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, it, rel = H.solve(x, b, 1e-8, 200)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            best = dt if best is None else min(best, dt)
+        ms_res, ms_apply = H.time_sweep(nl - 1, 20, x, b)
+        H.close()
+        return {"dim": dim, "N": N, "levels": nl, "beta": beta, "coarse": "galerkin" if gal else "rediscretised",
+                "dofs": n, "status": {0: "converged", 1: "maxit", -4: "diverged"}.get(st, str(st)), "cycles": it,
+                "rho_avg": rel ** (1.0 / it) if it > 0 and rel > 0 else None, "ms": 1e3 * best,
+                "setup_s": round(setup, 3), "ms_residual": ms_res, "ms_apply": ms_apply,
+                "smoothed_dofs": it * sum(2 * 3 * level_n[l] for l in range(1, nl))}
+
+    main = run(2, 1024, 8, 0.05, False, "lid")
+    gal = run(2, 1024, 8, 0.05, True, "lid", reps=1)
+    sweep = [run(2, 1024, 8, beta, False, "lid", reps=1) for beta in (0.02, 0.1, 0.3, 1.0)]
+    three = run(3, 64, 5, 0.05, False, "mms")
+    nV = 1025 ** 2
+    apply_bytes = nV * (8 * (3 * 9 + 1) + 3 * 8 + 2 * 3 * 8)   # stored values, r once, x read and written
+    achieved = apply_bytes / (main["ms_apply"] * 1e-3) / 1e9
+    _line("RAV smoothed DoFs/s (whole V(3,3) solve to a 1e-8 residual reduction, stabilized Q1-Q1)",
+          main["smoothed_dofs"] / (1e-3 * main["ms"]), "DoF/s", 1, 1, main["ms"], "f64",
+          {"workload": "2D driven cavity, stabilized Q1-Q1 (beta 0.05), 1024x1024 (3,151,875 DoFs), 8 levels to "
+                       "the 8x8 grid, RAV with pressure + co-located velocity owned, V(3,3), omega 0.66, factored"},
+          roofline_apply={"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                          "frac": achieved / 8000.0, "bytes_per_launch": apply_bytes},
+          rediscretised=main, galerkin=gal, beta_sweep=sweep, three_d_64=three)
 
 
 def bench_1024(args):

@@ -1,6 +1,6 @@
 /*
  * rav.h - restricted additive Vanka (RAV) geometric multigrid for Taylor-Hood
- * Q2/Q1 Stokes systems on MI355X (gfx950).
+ * Q2/Q1 and stabilized Q1-Q1 Stokes systems on MI355X (gfx950).
  *
  * Method: S. Saberi, G. Meschke, A. Vogel, "A restricted additive Vanka
  * smoother for geometric multigrid", arXiv 2103.10127.
@@ -76,6 +76,19 @@ typedef enum { RAV_FP64 = 0, RAV_FP32 = 1, RAV_BF16 = 2 } rav_precision;
  * instead of 459, 1,376 per 3D patch instead of 9,400). */
 typedef enum { RAV_ROWS = 0, RAV_FACTORED = 1 } rav_inv_format;
 
+/* Discretization of the Stokes system (Sec. 2).  RAV_TAYLOR_HOOD: Q2
+ * velocity, Q1 pressure, C = 0 (eq. 6 for an inf-sup stable pair).
+ * RAV_Q1Q1_STAB: equal-order Q1 velocity and pressure with the stabilization
+ * block of eq. (8), C = -beta sum_e diam_e^2 (grad q, grad p)_e (diam of a
+ * d-cube of side h: sqrt(d) h), on the vertices of the grid; vertex patches
+ * hold p_k and every velocity DoF at the vertices of the cells around k
+ * (2D 19, 3D 82 DoFs) and RAV owns p_k and the velocity at k (Sec. 3, eq. 13).
+ * Q1-Q1 vectors have (d+1) (N+1)^d entries [u_1; ...; u_d; p], field f of
+ * vertex v at f (N+1)^d + lin(v); it is provided with RAV, vertex patches and
+ * FP64 inverses (either storage format); batches, FGMRES, the learned weights,
+ * profiling markers and rav_export_matrix return RAV_EUNSUPPORTED for it. */
+typedef enum { RAV_TAYLOR_HOOD = 0, RAV_Q1Q1_STAB = 1 } rav_discretization;
+
 /* Circular (2D: cx, cy, r) or spherical (3D: cx, cy, cz, r) inclusion. */
 typedef struct { double cx, cy, cz, r; } rav_inclusion;
 
@@ -99,6 +112,10 @@ typedef struct {
                                    (cell integrals by the finest grid's Gauss
                                    points; equal to 0 at constant viscosity) */
   rav_inv_format inv_format;    /* RAV storage of the owned inverse rows          */
+  rav_discretization discretization;
+  double beta;                  /* Q1-Q1 stabilization constant of eq. (8), > 0;
+                                   with coarse_galerkin = 1 every level uses the
+                                   finest diameter (the Galerkin product P^T C P) */
 } rav_problem_desc;
 
 typedef struct rav_ctx rav_ctx;

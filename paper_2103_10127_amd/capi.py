@@ -24,6 +24,7 @@ SMOOTHERS = {"rav": 0, "av": 1, "mv": 2}
 KINDS = {"vertex": 0, "element": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 FORMATS = {"rows": 0, "factored": 1}
+DISCRETIZATIONS = {"taylor-hood": 0, "q1q1": 1}
 
 
 class RavError(RuntimeError):
@@ -42,7 +43,7 @@ class RavProblemDesc(ctypes.Structure):
                 ("n_incl", ctypes.c_int), ("incl", ctypes.POINTER(RavInclusion)), ("patch", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("inv_precision", ctypes.c_int), ("coarse_galerkin", ctypes.c_int),
-                ("inv_format", ctypes.c_int)]
+                ("inv_format", ctypes.c_int), ("discretization", ctypes.c_int), ("beta", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -153,7 +154,8 @@ class Hierarchy:
 
     def __init__(self, dim=2, n_cells=32, n_levels=3, dmask=0b1111, kind="vertex", smoother="rav",
                  omega=0.66, nu_pre=2, nu_post=2, precision="fp64", eta_out=1.0, eta_in=1.0,
-                 inclusions=None, stream=None, galerkin=False, inv_format="rows"):
+                 inclusions=None, stream=None, galerkin=False, inv_format="rows", discretization="taylor-hood",
+                 beta=0.1):
         self.lib = lib()
         incl = np.zeros((0, 4)) if inclusions is None else np.asarray(inclusions, dtype=np.float64)
         if incl.size and incl.shape[1] == dim + 1:   # (cx, cy[, cz], r) -> (cx, cy, cz, r)
@@ -167,7 +169,8 @@ class Hierarchy:
         self.desc = RavProblemDesc(dim, n_cells, n_levels, dmask, eta_out, eta_in, len(incl),
                                    ctypes.cast(self._incl, ctypes.POINTER(RavInclusion)), KINDS[kind],
                                    SMOOTHERS[smoother], omega, nu_pre, nu_post, PRECISIONS[precision],
-                                   1 if galerkin else 0, FORMATS[inv_format])
+                                   1 if galerkin else 0, FORMATS[inv_format], DISCRETIZATIONS[discretization],
+                                   beta)
         self.stream = _stream() if stream is None else stream
         h = _P()
         st = self.lib.rav_create(ctypes.byref(self.desc), self.stream, ctypes.byref(h))
@@ -457,11 +460,12 @@ class Batch:
 
 
 def make_desc(dim=2, n_cells=32, n_levels=3, dmask=0b1111, kind="vertex", smoother="rav", omega=0.66,
-              nu_pre=2, nu_post=2, precision="fp64", eta_out=1.0, eta_in=1.0, galerkin=False, inv_format="rows"):
+              nu_pre=2, nu_post=2, precision="fp64", eta_out=1.0, eta_in=1.0, galerkin=False, inv_format="rows",
+              discretization="taylor-hood", beta=0.1):
     """Descriptor without inclusions (for the host-only map functions)."""
     return RavProblemDesc(dim, n_cells, n_levels, dmask, eta_out, eta_in, 0, None, KINDS[kind],
                           SMOOTHERS[smoother], omega, nu_pre, nu_post, PRECISIONS[precision], 1 if galerkin else 0,
-                          FORMATS[inv_format])
+                          FORMATS[inv_format], DISCRETIZATIONS[discretization], beta)
 
 
 def map_patch(desc, level, patch):

@@ -146,9 +146,27 @@ void append_residual_tiles(std::vector<BlockTask>& out, int grid, const Geo& g) 
 }
 }  // namespace rav
 
-static rav_status set_err(rav_ctx* ctx, rav_status st, const std::string& msg) {
+rav_status rav_set_error(rav_ctx* ctx, rav_status st, const std::string& msg) {
   if (ctx) ctx->err = msg; else g_create_error = msg;
   return st;
+}
+
+static rav_status set_err(rav_ctx* ctx, rav_status st, const std::string& msg) { return rav_set_error(ctx, st, msg); }
+
+// Status word, norm buffers (device and pinned host) and the inclusion table.
+rav_status rav_init_common(rav_ctx* ctx, const rav_problem_desc* d) {
+  CK(hipMalloc((void**)&ctx->d_status, sizeof(int)));
+  CK(hipMalloc((void**)&ctx->d_norm, sizeof(double)));
+  CK(hipHostMalloc((void**)&ctx->h_norm, sizeof(double), hipHostMallocDefault));
+  CK(hipHostGetDevicePointer((void**)&ctx->h_norm_dev, ctx->h_norm, 0));
+  std::vector<double> inc(4 * std::max(d->n_incl, 1), 0.0);
+  for (int i = 0; i < d->n_incl; ++i) {
+    const rav_inclusion& c = d->incl[i];
+    inc[4 * i + 0] = c.cx; inc[4 * i + 1] = c.cy; inc[4 * i + 2] = c.cz; inc[4 * i + 3] = c.r;
+  }
+  CK(hipMalloc((void**)&ctx->d_incl, sizeof(double) * inc.size()));
+  CK(hipMemcpy(ctx->d_incl, inc.data(), sizeof(double) * inc.size(), hipMemcpyHostToDevice));
+  return RAV_OK;
 }
 
 rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<BlockTask>& logical, BlockTask** out, int* n) {
@@ -600,6 +618,12 @@ static rav_status need_factors(rav_ctx* ctx) {
 rav_status rav_create_ex(const rav_problem_desc* d, void* hip_stream, rav_ctx** out, bool invert_coarse) {
   if (!d || !out) return set_err(nullptr, RAV_EINVAL, "null descriptor or output pointer");
   *out = nullptr;
+  if (d->discretization == RAV_Q1Q1_STAB) {
+    if (!invert_coarse)
+      return set_err(nullptr, RAV_EUNSUPPORTED, "batches are provided for the Taylor-Hood discretization");
+    return rav_q1_create(d, hip_stream, out);
+  }
+  if (d->discretization != RAV_TAYLOR_HOOD) return set_err(nullptr, RAV_EINVAL, "bad discretization");
   if (d->dim != 2 && d->dim != 3) return set_err(nullptr, RAV_EINVAL, "dim must be 2 or 3");
   if (d->n_levels < 2) return set_err(nullptr, RAV_EINVAL, "n_levels must be >= 2");
   if (d->n_levels > 20 || d->n_cells <= 0 || d->n_cells % (1 << (d->n_levels - 1)))
@@ -657,22 +681,8 @@ rav_status rav_create_ex(const rav_problem_desc* d, void* hip_stream, rav_ctx** 
     return st;
   };
   {
-    hipError_t e = hipMalloc((void**)&ctx->d_status, sizeof(int));
-    if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
-    e = hipMalloc((void**)&ctx->d_norm, sizeof(double));
-    if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
-    e = hipHostMalloc((void**)&ctx->h_norm, sizeof(double), hipHostMallocDefault);
-    if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
-    e = hipHostGetDevicePointer((void**)&ctx->h_norm_dev, ctx->h_norm, 0);
-    if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
-    std::vector<double> inc(4 * std::max(d->n_incl, 1), 0.0);
-    for (int i = 0; i < d->n_incl; ++i) {
-      const rav_inclusion& c = d->incl[i];
-      inc[4 * i + 0] = c.cx; inc[4 * i + 1] = c.cy; inc[4 * i + 2] = c.cz; inc[4 * i + 3] = c.r;
-    }
-    e = hipMalloc((void**)&ctx->d_incl, sizeof(double) * inc.size());
-    if (e == hipSuccess) e = hipMemcpy(ctx->d_incl, inc.data(), sizeof(double) * inc.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
+    const rav_status s0 = rav_init_common(ctx, d);
+    if (s0 != RAV_OK) return fail(s0);
   }
   set_ref_tables(make_tables(), ctx->stream);
   ctx->lv.resize(d->n_levels);
@@ -815,6 +825,7 @@ static rav_status autotune_apply(rav_ctx* ctx) {
 extern "C" {
 
 rav_status rav_factor_patches(rav_ctx* ctx) {
+  if (ctx && ctx->q1) return rav_q1_factor(ctx);
   if (!ctx) return RAV_EINVAL;
   rav_drop_graph(ctx);
   const rav_problem_desc& D = ctx->desc;
@@ -866,6 +877,7 @@ rav_status rav_factor_patches(rav_ctx* ctx) {
 }
 
 rav_status rav_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free) {
+  if (ctx && ctx->q1) return rav_q1_dofs(ctx, level, n_total, n_free);
   if (check_level(ctx, level, false) != RAV_OK) return RAV_EINVAL;
   const Geo& g = ctx->lv[level].hd.g;
   if (n_total) *n_total = (long)g.n;
@@ -882,18 +894,24 @@ rav_status rav_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free) 
 }
 
 rav_status rav_n_levels(const rav_ctx* ctx, int* n) {
+  if (ctx && ctx->q1 && n) {
+    *n = rav_q1_n_levels(ctx);
+    return RAV_OK;
+  }
   if (!ctx || !n) return RAV_EINVAL;
   *n = (int)ctx->lv.size();
   return RAV_OK;
 }
 
 rav_status rav_n_patches(const rav_ctx* ctx, int level, long* n) {
+  if (ctx && ctx->q1) return rav_q1_n_patches(ctx, level, n);
   if (check_level(ctx, level, false) != RAV_OK || !n) return RAV_EINVAL;
   *n = (long)ctx->lv[level].npatch;
   return RAV_OK;
 }
 
 rav_status rav_assemble_rhs(rav_ctx* ctx, const double* params, int n_params, double* b_dev) {
+  if (ctx && ctx->q1 && params && b_dev) return rav_q1_assemble_rhs(ctx, params, n_params, b_dev);
   if (!ctx || !params || !b_dev) return RAV_EINVAL;
   const int need = ctx->desc.dim == 2 ? 25 : 65;
   if (n_params != need) return set_err(ctx, RAV_EINVAL, "mms parameter array must have " + std::to_string(need) + " entries");
@@ -918,6 +936,7 @@ rav_status rav_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev) {
   const rav_problem_desc& D = ctx->desc;
   if (D.dim != 2 || !((D.bc_dirichlet_mask >> 3) & 1u))
     return set_err(ctx, RAV_EINVAL, "the driven cavity needs a 2D grid with a Dirichlet top side (bit 3)");
+  if (ctx->q1) return rav_q1_assemble_rhs_lid(ctx, lid_u, b_dev);
   LevelHost& L = ctx->lv.back();
   launch_fill(b_dev, 0.0, L.hd.g.n, ctx->stream);
   launch_lift_lid(L.dd, L.hd.g, lid_u, b_dev, ctx->stream);
@@ -927,6 +946,7 @@ rav_status rav_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev) {
 }
 
 rav_status rav_residual(rav_ctx* ctx, int level, const double* x, const double* b, double* r, double* norm) {
+  if (ctx && ctx->q1 && x && b && r) return rav_q1_residual(ctx, level, x, b, r, norm);
   if (check_level(ctx, level, false) != RAV_OK || !x || !b || !r) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   const long long n = L.hd.g.n;
@@ -940,6 +960,7 @@ rav_status rav_residual(rav_ctx* ctx, int level, const double* x, const double* 
 }
 
 rav_status rav_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const double* b) {
+  if (ctx && ctx->q1 && x && b && sweeps >= 0) return rav_q1_smooth(ctx, level, sweeps, x, b);
   if (check_level(ctx, level, true) != RAV_OK || !x || !b || sweeps < 0) return RAV_EINVAL;
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
@@ -953,6 +974,7 @@ rav_status rav_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const doub
 }
 
 rav_status rav_restrict(rav_ctx* ctx, int level, const double* rf, double* bc) {
+  if (ctx && ctx->q1 && rf && bc) return rav_q1_restrict(ctx, level, rf, bc);
   if (check_level(ctx, level, true) != RAV_OK || !rf || !bc) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   launch_copy(L.hd.r, rf, L.hd.g.n, ctx->stream);
@@ -963,6 +985,7 @@ rav_status rav_restrict(rav_ctx* ctx, int level, const double* rf, double* bc) {
 }
 
 rav_status rav_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf) {
+  if (ctx && ctx->q1 && xc && xf) return rav_q1_prolong_add(ctx, level, xc, xf);
   if (check_level(ctx, level, true) != RAV_OK || !xc || !xf) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   launch_copy(ctx->lv[level - 1].hd.x, xc, L.hd.gc.n, ctx->stream);
@@ -974,6 +997,7 @@ rav_status rav_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf
 }
 
 rav_status rav_coarse_solve(rav_ctx* ctx, const double* b0, double* x0) {
+  if (ctx && ctx->q1 && b0 && x0) return rav_q1_coarse_solve(ctx, b0, x0);
   if (!ctx || !b0 || !x0) return RAV_EINVAL;
   launch_coarse_gemv(ctx->Minv, ctx->nb, ctx->lv[0].hd.g.n, b0, x0, ctx->stream);
   CK(hipGetLastError());
@@ -981,6 +1005,7 @@ rav_status rav_coarse_solve(rav_ctx* ctx, const double* b0, double* x0) {
 }
 
 rav_status rav_vcycle(rav_ctx* ctx, double* x, const double* b) {
+  if (ctx && ctx->q1 && x && b) return rav_q1_vcycle(ctx, x, b);
   if (!ctx || !x || !b) return RAV_EINVAL;
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   const int lf = (int)ctx->lv.size() - 1;
@@ -997,6 +1022,7 @@ rav_status rav_vcycle(rav_ctx* ctx, double* x, const double* b) {
 rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int maxit, int* iters,
                      double* rel_res) {
   if (!ctx || !x || !b || !(rtol > 0.0) || maxit < 0) return RAV_EINVAL;
+  if (ctx->q1) return rav_q1_solve(ctx, x, b, rtol, maxit, iters, rel_res);
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   const int lf = (int)ctx->lv.size() - 1;
   LevelHost& L = ctx->lv[lf];
@@ -1071,6 +1097,7 @@ rav_status rav_set_params(rav_ctx* ctx, double omega, int nu_pre, int nu_post) {
   ctx->desc.omega = omega;
   ctx->desc.nu_pre = nu_pre;
   ctx->desc.nu_post = nu_post;
+  if (ctx->q1) return RAV_OK;
   for (LevelHost& L : ctx->lv) {
     L.hd.omega = omega;
     rav_status st = rav_upload_desc(ctx, L);
@@ -1087,6 +1114,7 @@ rav_status rav_set_fallback(rav_ctx* ctx, double rho_max, int* fell_back) {
 }
 
 rav_status rav_set_patch_omega(rav_ctx* ctx, int level, const float* omega_dev) {
+  if (ctx && ctx->q1) return set_err(ctx, RAV_EUNSUPPORTED, "per-patch weights are provided for Taylor-Hood");
   if (check_level(ctx, level, true) != RAV_OK) return RAV_EINVAL;
   ctx->lv[level].hd.omega_patch = omega_dev;
   return rav_upload_desc(ctx, ctx->lv[level]);
@@ -1121,12 +1149,14 @@ static rav_status desc_geo(const rav_problem_desc* d, int level, Geo* g) {
 }
 
 rav_status rav_map_patch(const rav_problem_desc* d, int level, long patch, int* dofs, int* n, int* owned) {
+  if (d && d->discretization == RAV_Q1Q1_STAB) return rav_q1_map_patch(d, level, patch, dofs, n, owned);
   Geo g;
   if (desc_geo(d, level, &g) != RAV_OK) return RAV_EINVAL;
   return map_patch_geo(g, d->patch, n_patches(g, d->patch), patch, dofs, n, owned);
 }
 
 rav_status rav_map_owner(const rav_problem_desc* d, int level, int* owner) {
+  if (d && d->discretization == RAV_Q1Q1_STAB) return rav_q1_map_owner(d, level, owner);
   Geo g;
   if (desc_geo(d, level, &g) != RAV_OK || !owner) return RAV_EINVAL;
   for (long long i = 0; i < g.n; ++i) {
@@ -1141,12 +1171,14 @@ rav_status rav_map_owner(const rav_problem_desc* d, int level, int* owner) {
 }
 
 rav_status rav_get_patch_map(const rav_ctx* ctx, int level, long patch, int* dofs, int* n, int* owned) {
+  if (ctx && ctx->q1) return rav_q1_get_patch_map(ctx, level, patch, dofs, n, owned);
   if (check_level(ctx, level, false) != RAV_OK) return RAV_EINVAL;
   const LevelHost& L = ctx->lv[level];
   return map_patch_geo(L.hd.g, ctx->desc.patch, L.npatch, patch, dofs, n, owned);
 }
 
 rav_status rav_get_owner(rav_ctx* ctx, int level, int* owner_dev) {
+  if (ctx && ctx->q1 && owner_dev) return rav_q1_get_owner(ctx, level, owner_dev);
   if (check_level(ctx, level, false) != RAV_OK || !owner_dev) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   launch_owner(L.dd, ctx->desc.patch, L.hd.g.n, owner_dev, ctx->stream);
@@ -1156,6 +1188,7 @@ rav_status rav_get_owner(rav_ctx* ctx, int level, int* owner_dev) {
 }
 
 rav_status rav_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* out, int* rows, int* cols) {
+  if (ctx && ctx->q1 && out && rows && cols) return rav_q1_get_patch_inverse(ctx, level, patch, out, rows, cols);
   if (check_level(ctx, level, true) != RAV_OK || !out || !rows || !cols) return RAV_EINVAL;
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
@@ -1236,6 +1269,7 @@ rav_status rav_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* ou
 }
 
 rav_status rav_export_matrix(rav_ctx* ctx, int level, double* out) {
+  if (ctx && ctx->q1) return set_err(ctx, RAV_EUNSUPPORTED, "dense export is provided for Taylor-Hood");
   if (check_level(ctx, level, false) != RAV_OK || !out) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   const long long n = L.hd.g.n;
@@ -1252,6 +1286,7 @@ rav_status rav_export_matrix(rav_ctx* ctx, int level, double* out) {
 
 rav_status rav_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const double* b, float* ms_res,
                           float* ms_apply) {
+  if (ctx && ctx->q1 && x && b && reps > 0) return rav_q1_time_sweep(ctx, level, reps, x, b, ms_res, ms_apply);
   if (check_level(ctx, level, true) != RAV_OK || !x || !b || reps <= 0) return RAV_EINVAL;
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   if (ctx->desc.smoother == RAV_SMOOTHER_MV) return set_err(ctx, RAV_EUNSUPPORTED, "MV has no separate residual kernel");
@@ -1286,6 +1321,7 @@ rav_status rav_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const do
 }
 
 rav_status rav_profile_begin(rav_ctx* ctx, int level, int max_launches) {
+  if (ctx && ctx->q1) return set_err(ctx, RAV_EUNSUPPORTED, "profiling markers are provided for Taylor-Hood");
   if (check_level(ctx, level, true) != RAV_OK || max_launches <= 0) return RAV_EINVAL;
   for (auto& e : ctx->prof_res) (void)hipEventDestroy(e);
   for (auto& e : ctx->prof_app) (void)hipEventDestroy(e);
@@ -1338,6 +1374,7 @@ rav_status rav_destroy(rav_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   rav_drop_graph(ctx);
   if (ctx->learn_free) ctx->learn_free(ctx);
+  rav_q1_free(ctx);
   for (LevelHost& L : ctx->lv) {
     GridDev& h = L.hd;
     (void)hipFree(h.x); (void)hipFree(h.b); (void)hipFree(h.r); (void)hipFree(h.vals);

@@ -71,8 +71,11 @@ void append_residual_tiles(std::vector<BlockTask>& out, int grid, const Geo& g);
 
 }  // namespace rav
 
+struct rav_q1_state;   // stabilized Q1-Q1 hierarchy (rav_q1.hip)
+
 struct rav_ctx {
   rav_problem_desc desc{};
+  rav_q1_state* q1 = nullptr;   // set for RAV_Q1Q1_STAB: the entry points route to rav_q1_*
   std::vector<rav_inclusion> incl;
   hipStream_t stream = nullptr;
   std::vector<rav::LevelHost> lv;
@@ -119,6 +122,8 @@ struct rav_ctx {
 };
 
 // Shared helpers (rav_capi.hip).
+rav_status rav_set_error(rav_ctx* ctx, rav_status st, const std::string& msg);   // ctx may be null
+rav_status rav_init_common(rav_ctx* ctx, const rav_problem_desc* d);   // status, norm, inclusion buffers
 rav_status rav_create_ex(const rav_problem_desc* d, void* hip_stream, rav_ctx** out, bool invert_coarse);
 rav_status rav_invert_coarse(rav_ctx* const* ctxs, int n, hipStream_t s, std::vector<int>* status_out,
                              std::string* err);
@@ -129,3 +134,28 @@ void rav_apply_level(rav_ctx* ctx, int l);
 rav_status rav_read_norm(rav_ctx* ctx, double* out);
 void rav_drop_graph(rav_ctx* ctx);   // forget the captured solve cycle
 rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<rav::BlockTask>& logical, rav::BlockTask** out, int* n);
+
+// Stabilized Q1-Q1 (rav_q1.hip), reached through the public entry points.
+rav_status rav_q1_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out);
+void rav_q1_free(rav_ctx* ctx);
+rav_status rav_q1_factor(rav_ctx* ctx);
+rav_status rav_q1_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free);
+int rav_q1_n_levels(const rav_ctx* ctx);
+rav_status rav_q1_n_patches(const rav_ctx* ctx, int level, long* n);
+rav_status rav_q1_assemble_rhs(rav_ctx* ctx, const double* params, int n_params, double* b_dev);
+rav_status rav_q1_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev);
+rav_status rav_q1_residual(rav_ctx* ctx, int level, const double* x, const double* b, double* r, double* norm);
+rav_status rav_q1_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const double* b);
+rav_status rav_q1_restrict(rav_ctx* ctx, int level, const double* rf, double* bc);
+rav_status rav_q1_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf);
+rav_status rav_q1_coarse_solve(rav_ctx* ctx, const double* b0, double* x0);
+rav_status rav_q1_vcycle(rav_ctx* ctx, double* x, const double* b);
+rav_status rav_q1_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int maxit, int* iters,
+                        double* rel_res);
+rav_status rav_q1_map_patch(const rav_problem_desc* d, int level, long patch, int* dofs, int* n, int* owned);
+rav_status rav_q1_map_owner(const rav_problem_desc* d, int level, int* owner);
+rav_status rav_q1_get_owner(rav_ctx* ctx, int level, int* owner_dev);
+rav_status rav_q1_get_patch_map(const rav_ctx* ctx, int level, long patch, int* dofs, int* n, int* owned);
+rav_status rav_q1_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* out, int* rows, int* cols);
+rav_status rav_q1_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const double* b, float* ms_res,
+                             float* ms_apply);

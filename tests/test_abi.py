@@ -102,3 +102,34 @@ def test_largest_supported_2d_level_passes_the_index_check():
     d.omega = 0.0
     h = ctypes.c_void_p()
     assert capi.lib().rav_create(ctypes.byref(d), None, ctypes.byref(h)) == -1
+
+
+@pytest.mark.parametrize("dim,N,nl,dm", [(2, 8, 2, ri.ALL_DIRICHLET_2D), (2, 12, 2, ri.OUTFLOW_2D),
+                                         (3, 4, 2, ri.OUTFLOW_3D)])
+def test_q1q1_host_maps_match_oracle(dim, N, nl, dm):
+    """Stabilized Q1-Q1 vertex patches (Sec. 3): patch DoF lists in local order
+    and the literal owned set (pressure + co-located velocity) against the oracle."""
+    from oracle import q1q1 as q
+    d = capi.make_desc(dim=dim, n_cells=N, n_levels=nl, dmask=dm, discretization="q1q1")
+    for level in range(nl):
+        g = q.GridQ1(dim, N >> (nl - 1 - level), dm)
+        ps = q.PatchSetQ1(g)
+        np.testing.assert_array_equal(capi.map_owner(d, level, g.n), ps.owner)
+        for i in range(ps.count):
+            dofs, owned = capi.map_patch(d, level, i)
+            np.testing.assert_array_equal(dofs, ps.dofs[i])
+            np.testing.assert_array_equal(np.nonzero(owned)[0], ps.owned[i])
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("beta", 0.0, -1), ("smoother", 1, -6), ("inv_precision", 2, -6), ("patch", 1, -6), ("discretization", 5, -1),
+    ("n_levels", 2, -1),   # with n_cells = 256: 3 * 129^2 coarsest unknowns exceed the dense solve
+])
+def test_q1q1_invalid_descriptors_rejected_without_device(field, value, status):
+    d = capi.make_desc(dim=2, n_cells=32, n_levels=3, discretization="q1q1")
+    setattr(d, field, value)
+    if (field, value) == ("n_levels", 2):
+        d.n_cells = 256
+    h = ctypes.c_void_p()
+    assert capi.lib().rav_create(ctypes.byref(d), None, ctypes.byref(h)) == status
+    assert h.value is None
