@@ -188,11 +188,56 @@ __global__ __launch_bounds__(256) void k_q1_cut_matrices(Q1Dev q, int R, const i
 }
 
 // ---- residual: one thread per vertex, all d+1 rows -------------------------
+// 2D: the 3x3 neighbourhood of the vertex is loaded once (zeros outside the
+// grid and for masked velocity), then the 4 cells around the vertex add their
+// cell-matrix rows; a cell outside the grid carries weight 0.
+// 3D: the cells are visited one after another and each reads its 2^d vertices
+// (a 3^3 neighbourhood held in registers would take 108 doubles per thread).
+template <int DIM>
+__device__ __forceinline__ void q1_rows_cells(const Q1Dev& q, const double* __restrict__ x, const int* vc,
+                                              double* au, double& ap) {
+  constexpr int NB = 1 << DIM;
+#pragma unroll
+  for (int s = 0; s < NB; ++s) {   // cell whose local vertex s is v
+    int e[3] = {0, 0, 0};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      e[d] = vc[d] - bit(s, d);
+      ok = ok & (e[d] >= 0) & (e[d] < q.N);
+    }
+    if (!ok) continue;
+    const double ce = q.ceta[clin<DIM>(q, e)];
+    const long long cut = cut_index(ce);
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      int w[3] = {0, 0, 0};
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) w[d] = e[d] + bit(bb, d);
+      const long long wi = vlin<DIM>(q, w);
+      const bool wm = vmasked<DIM>(q, w);
+      const double pw = x[DIM * q.nV + wi];
+      ap += q.cC * kunit<DIM>(s, bb) * pw;
+      const double kab = acell<DIM>(q, ce, cut, s, bb);
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        au[c] -= q.bscale * bunit<DIM>(c, s, bb) * pw;
+        if (!wm) {
+          const double uw = x[c * q.nV + wi];
+          au[c] += kab * uw;
+          ap -= q.bscale * bunit<DIM>(c, bb, s) * uw;
+        }
+      }
+    }
+  }
+}
+
 template <int DIM>
 __global__ __launch_bounds__(256) void k_q1_residual(Q1Dev q, const double* __restrict__ x,
                                                       const double* __restrict__ b, double* __restrict__ r,
                                                       double* __restrict__ partials) {
   constexpr int NB = 1 << DIM;
+  constexpr int NBLK = q1_nblk(DIM);
   const long long v = blockIdx.x * 256LL + threadIdx.x;
   double sq = 0.0;
   if (v < q.nV) {
@@ -201,35 +246,46 @@ __global__ __launch_bounds__(256) void k_q1_residual(Q1Dev q, const double* __re
     double au[DIM], ap = 0.0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) au[c] = 0.0;
+    if constexpr (DIM == 3) {
+      q1_rows_cells<DIM>(q, x, vc, au, ap);
+    } else {
+      double u[DIM][NBLK], pv[NBLK];
 #pragma unroll
-    for (int s = 0; s < NB; ++s) {   // cell whose local vertex s is v
-      int e[3] = {0, 0, 0};
-      bool ok = true;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        e[d] = vc[d] - bit(s, d);
-        ok = ok && e[d] >= 0 && e[d] < q.N;
-      }
-      if (!ok) continue;
-      const double ce = q.ceta[clin<DIM>(q, e)];
-      const long long cut = cut_index(ce);
-#pragma unroll
-      for (int bb = 0; bb < NB; ++bb) {
+      for (int m = 0; m < NBLK; ++m) {
         int w[3] = {0, 0, 0};
+        int t = m;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) w[d] = e[d] + bit(bb, d);
-        const long long wi = vlin<DIM>(q, w);
-        const bool wm = vmasked<DIM>(q, w);
-        const double pw = x[DIM * q.nV + wi];
-        ap += q.cC * kunit<DIM>(s, bb) * pw;
-        const double kab = acell<DIM>(q, ce, cut, s, bb);
+        for (int d = 0; d < DIM; ++d) { w[d] = vc[d] + (t % 3) - 1; t /= 3; }
+        const bool in = inside<DIM>(q, w);
+        const bool fr = in & !vmasked<DIM>(q, w);
+        const long long wi = in ? vlin<DIM>(q, w) : v;
+        pv[m] = in ? x[DIM * q.nV + wi] : 0.0;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-          au[c] -= q.bscale * bunit<DIM>(c, s, bb) * pw;
-          if (!wm) {
-            const double uw = x[c * q.nV + wi];
-            au[c] += kab * uw;
-            ap -= q.bscale * bunit<DIM>(c, bb, s) * uw;
+        for (int c = 0; c < DIM; ++c) u[c][m] = fr ? x[c * q.nV + wi] : 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < NB; ++s) {   // cell whose local vertex s is v
+        int e[3] = {0, 0, 0};
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          e[d] = vc[d] - bit(s, d);
+          ok = ok & (e[d] >= 0) & (e[d] < q.N);
+        }
+        const double ce = ok ? q.ceta[clin<DIM>(q, e)] : 0.0;
+        const long long cut = cut_index(ce);
+        const double wc = ok ? 1.0 : 0.0;
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) {
+          int m = 0, st = 1;   // neighbourhood index of the cell's local vertex bb
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) { m += (bit(bb, d) - bit(s, d) + 1) * st; st *= 3; }
+          const double kab = acell<DIM>(q, ce, cut, s, bb);
+          ap += wc * q.cC * kunit<DIM>(s, bb) * pv[m];
+#pragma unroll
+          for (int c = 0; c < DIM; ++c) {
+            au[c] += kab * u[c][m] - wc * q.bscale * bunit<DIM>(c, s, bb) * pv[m];
+            ap -= wc * q.bscale * bunit<DIM>(c, bb, s) * u[c][m];
           }
         }
       }
@@ -470,10 +526,12 @@ __global__ __launch_bounds__(256) void k_q1_apply(Q1Dev q, const double* __restr
 }
 
 // ---- transfers -------------------------------------------------------------
-// b_c = P^T r_f on the coarse vertices (masked rows 0), x_c = 0.
+// b_c = P^T r_f on the coarse vertices (masked rows 0), x_c = 0 and, when rc
+// is given, r_c = b_c (the residual of the zero iterate).
 template <int DIM>
 __global__ __launch_bounds__(256) void k_q1_restrict(Q1Dev f, Q1Dev c, const double* __restrict__ rf,
-                                                      double* __restrict__ bc, double* __restrict__ xc) {
+                                                      double* __restrict__ bc, double* __restrict__ xc,
+                                                      double* __restrict__ rc) {
   const long long W = blockIdx.x * 256LL + threadIdx.x;
   if (W >= c.nV) return;
   int wc[3] = {0, 0, 0};
@@ -505,8 +563,10 @@ __global__ __launch_bounds__(256) void k_q1_restrict(Q1Dev f, Q1Dev c, const dou
   }
 #pragma unroll
   for (int fl = 0; fl <= DIM; ++fl) {
-    bc[fl * c.nV + W] = (fl < DIM && cm) ? 0.0 : acc[fl];
+    const double val = (fl < DIM && cm) ? 0.0 : acc[fl];
+    bc[fl * c.nV + W] = val;
     xc[fl * c.nV + W] = 0.0;
+    if (rc) rc[fl * c.nV + W] = val;
   }
 }
 
@@ -723,8 +783,8 @@ void q1_launch_apply(int dim, const Q1Dev& q, int factored, const double* W, con
 }
 
 void q1_launch_restrict(int dim, const Q1Dev& f, const Q1Dev& c, const double* rf, double* bc, double* xc,
-                        hipStream_t s) {
-  Q1_DISPATCH(dim, k_q1_restrict, nblk(c.nV), 256, f, c, rf, bc, xc);
+                        double* rc, hipStream_t s) {
+  Q1_DISPATCH(dim, k_q1_restrict, nblk(c.nV), 256, f, c, rf, bc, xc, rc);
 }
 
 void q1_launch_prolong(int dim, const Q1Dev& f, const Q1Dev& c, const double* xc, double* xf, hipStream_t s) {

@@ -62,7 +62,7 @@ void q1_launch_factor(int dim, const Q1Dev& q, int factored, double* W, int* sta
 void q1_launch_apply(int dim, const Q1Dev& q, int factored, const double* W, const double* r, double* x,
                      double omega, hipStream_t s);
 void q1_launch_restrict(int dim, const Q1Dev& f, const Q1Dev& c, const double* rf, double* bc, double* xc,
-                        hipStream_t s);
+                        double* rc, hipStream_t s);   // rc may be null
 void q1_launch_prolong(int dim, const Q1Dev& f, const Q1Dev& c, const double* xc, double* xf, hipStream_t s);
 // Dense coarse matrix, row-major nb x nb; masked rows/columns identity;
 // bordered: row/column n holds the pressure ones (zero-mean constraint).

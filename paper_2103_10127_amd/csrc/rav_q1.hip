@@ -8,6 +8,7 @@
 
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -187,10 +188,11 @@ void residual(rav_ctx* ctx, int l, bool with_norm) {
   if (with_norm) launch_norm_finalize(L.partials, 0, L.nres, ctx->d_norm, ctx->h_norm_dev, ctx->stream);
 }
 
-void smooth(rav_ctx* ctx, int l, int sweeps) {
+// `sweeps` RAV sweeps (eq. 13); r_valid: L.r already holds b - L x.
+void smooth(rav_ctx* ctx, int l, int sweeps, bool r_valid) {
   Level& L = st(ctx)->lv[l];
   for (int k = 0; k < sweeps; ++k) {
-    residual(ctx, l, false);
+    if (!(k == 0 && r_valid)) residual(ctx, l, false);
     q1_launch_apply(ctx->desc.dim, L.q, st(ctx)->factored, L.W, L.r, L.x, ctx->desc.omega, ctx->stream);
   }
 }
@@ -201,7 +203,9 @@ void coarse_solve(rav_ctx* ctx) {
   launch_coarse_gemv(S->Minv, S->nb, L0.q.n, L0.b, L0.x, ctx->stream);
 }
 
-void vcycle(rav_ctx* ctx, int l) {
+// V-cycle on level l (Sec. 2, Fig. 1); r_valid: L.r holds the residual of
+// the current x (coarse levels: restriction writes r_c = b_c for x_c = 0).
+void vcycle(rav_ctx* ctx, int l, bool r_valid) {
   if (l == 0) {
     coarse_solve(ctx);
     return;
@@ -209,12 +213,47 @@ void vcycle(rav_ctx* ctx, int l) {
   rav_q1_state* S = st(ctx);
   Level& L = S->lv[l];
   Level& C = S->lv[l - 1];
-  smooth(ctx, l, ctx->desc.nu_pre);
-  residual(ctx, l, false);
-  q1_launch_restrict(ctx->desc.dim, L.q, C.q, L.r, C.b, C.x, ctx->stream);
-  vcycle(ctx, l - 1);
+  smooth(ctx, l, ctx->desc.nu_pre, r_valid);
+  if (ctx->desc.nu_pre > 0 || !r_valid) residual(ctx, l, false);
+  q1_launch_restrict(ctx->desc.dim, L.q, C.q, L.r, C.b, C.x, l - 1 > 0 ? C.r : nullptr, ctx->stream);
+  vcycle(ctx, l - 1, true);
   q1_launch_prolong(ctx->desc.dim, L.q, C.q, C.x, L.x, ctx->stream);
-  smooth(ctx, l, ctx->desc.nu_post);
+  smooth(ctx, l, ctx->desc.nu_post, false);
+}
+
+// One solve cycle from a current finest residual: V-cycle, then the new finest
+// residual and its norm.  Captured from the stream into a graph on first use
+// and replayed (RAV_GRAPH=0 issues the launches directly).
+void solve_cycle(rav_ctx* ctx) {
+  const int lf = (int)st(ctx)->lv.size() - 1;
+  static const bool graphs = [] {
+    const char* e = std::getenv("RAV_GRAPH");
+    return !(e && std::string(e) == "0");
+  }();
+  if (graphs && !ctx->graph_failed) {
+    if (!ctx->cycle_exec) {
+      hipGraph_t g = nullptr;
+      bool ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        vcycle(ctx, lf, true);
+        residual(ctx, lf, true);
+        ok = hipStreamEndCapture(ctx->stream, &g) == hipSuccess && g != nullptr;
+      }
+      if (ok) ok = hipGraphInstantiate(&ctx->cycle_exec, g, nullptr, nullptr, 0) == hipSuccess;
+      if (g) (void)hipGraphDestroy(g);
+      if (!ok) {
+        (void)hipGetLastError();
+        ctx->cycle_exec = nullptr;
+        ctx->graph_failed = true;
+      }
+    }
+    if (ctx->cycle_exec && hipGraphLaunch(ctx->cycle_exec, ctx->stream) == hipSuccess) return;
+    (void)hipGetLastError();
+    rav_drop_graph(ctx);
+    ctx->graph_failed = true;
+  }
+  vcycle(ctx, lf, true);
+  residual(ctx, lf, true);
 }
 
 rav_status need_factors(rav_ctx* ctx) {
@@ -389,7 +428,7 @@ rav_status rav_q1_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const d
   Level& L = st(ctx)->lv[level];
   launch_copy(L.x, x, L.q.n, ctx->stream);
   launch_copy(L.b, b, L.q.n, ctx->stream);
-  smooth(ctx, level, sweeps);
+  smooth(ctx, level, sweeps, false);
   launch_copy(x, L.x, L.q.n, ctx->stream);
   QCK(hipGetLastError());
   return RAV_OK;
@@ -400,7 +439,7 @@ rav_status rav_q1_restrict(rav_ctx* ctx, int level, const double* rf, double* bc
   Level& L = st(ctx)->lv[level];
   Level& C = st(ctx)->lv[level - 1];
   launch_copy(L.r, rf, L.q.n, ctx->stream);
-  q1_launch_restrict(ctx->desc.dim, L.q, C.q, L.r, C.b, C.x, ctx->stream);
+  q1_launch_restrict(ctx->desc.dim, L.q, C.q, L.r, C.b, C.x, nullptr, ctx->stream);
   launch_copy(bc, C.b, C.q.n, ctx->stream);
   QCK(hipGetLastError());
   return RAV_OK;
@@ -431,7 +470,7 @@ rav_status rav_q1_vcycle(rav_ctx* ctx, double* x, const double* b) {
   Level& L = st(ctx)->lv[lf];
   launch_copy(L.x, x, L.q.n, ctx->stream);
   launch_copy(L.b, b, L.q.n, ctx->stream);
-  vcycle(ctx, lf);
+  vcycle(ctx, lf, false);
   launch_copy(x, L.x, L.q.n, ctx->stream);
   QCK(hipGetLastError());
   return RAV_OK;
@@ -455,8 +494,7 @@ rav_status rav_q1_solve(rav_ctx* ctx, double* x, const double* b, double rtol, i
   int k = 0;
   double rk = r0;
   while (result == RAV_NOT_CONVERGED && k < maxit) {
-    vcycle(ctx, lf);
-    residual(ctx, lf, true);
+    solve_cycle(ctx);   // the finest residual is current from the norm evaluation
     if ((s = rav_read_norm(ctx, &rk)) != RAV_OK) return s;
     ++k;
     if (!std::isfinite(rk) || rk > 1e3 * r0) {

@@ -27,10 +27,15 @@ def initial_theta(seed: int = 0, out_bias: float = -0.16, out_scale: float = 0.0
 
 
 def train(problems, steps: int = 400, lr: float = 3e-3, nu: int = 2, theta0=None, seed: int = 0,
-          stream=None):
+          stream=None, warm_cycles: int = 0):
     """Train on ``problems`` (dicts of :class:`Hierarchy` keyword arguments with
     ``n_levels == 2``); returns (theta, per-step losses).  Initial errors are
-    standard normal on the free DoFs, one per step, problems taken in turn."""
+    standard normal on the free DoFs, one per step, problems taken in turn.
+    ``warm_cycles`` > 0 first runs that many two-grid cycles (b = 0) with the
+    current weights on the error, removing the pressure mean and normalising
+    after each, so that the loss measures the reduction of the slowest error
+    components (an estimate of the asymptotic rate) instead of one cycle from
+    a random error."""
     import torch
 
     hs = []
@@ -41,18 +46,28 @@ def train(problems, steps: int = 400, lr: float = 3e-3, nu: int = 2, theta0=None
             h = Hierarchy(**p, stream=stream)
             h.factor()
             free = (h.owner(1) >= 0).to(torch.float64)
-            hs.append((h, free))
+            n_p = (p["n_cells"] + 1) ** p.get("dim", 2)
+            hs.append((h, free, n_p))
         net = MLP(initial_theta(seed) if theta0 is None else theta0)
         gen = torch.Generator(device="cuda")
         gen.manual_seed(seed)
         losses = []
         for it in range(steps):
-            h, free = hs[it % len(hs)]
+            h, free, n_p = hs[it % len(hs)]
             x0 = torch.randn(free.numel(), generator=gen, device="cuda", dtype=torch.float64) * free
+            if warm_cycles > 0:
+                h.set_params(h.desc.omega, nu, nu)
+                h.learn_set_omega(net)
+                zero = torch.zeros_like(x0)
+                for _ in range(warm_cycles):
+                    h.vcycle(x0, zero)
+                    x0[-n_p:] -= x0[-n_p:].mean()
+                    x0 /= torch.linalg.norm(x0)
+                h.learn_set_omega(None)
             losses.append(h.learn_step(net, x0, nu=nu, lr=lr))
         theta = net.theta()
         net.close()
         return theta, np.asarray(losses)
     finally:
-        for h, _ in hs:
+        for h, *_ in hs:
             h.close()

@@ -1,6 +1,8 @@
 """Learned per-patch damping on the GPU against the FP64 oracle: network
 outputs, the exact two-grid loss, its gradient with respect to every patch
-weight (reverse sweep) and with respect to the network parameters."""
+weight (reverse sweep) and with respect to the network parameters; the
+fixed-omega fallback; and the trained weights against every fixed omega on
+held-out problems."""
 import numpy as np
 import pytest
 
@@ -126,3 +128,57 @@ def test_non_finite_rhs_reports_divergence():
     st, it, rel = G.solve(x, b, 1e-8, 10)
     assert st == -4 and it == 0
     G.close()
+
+
+FIXED_OMEGAS = (0.5, 0.6, 0.66, 0.75, 0.85)
+MAXIT = 300
+
+
+def _train_asymptotic():
+    from paper_2103_10127_amd.learn import train
+    probs = [dict(dim=2, n_cells=32 if i < 8 else 64, n_levels=2, dmask=ri.ALL_DIRICHLET_2D, eta_out=1.0,
+                  eta_in=100.0, inclusions=ri.inclusions(3000 + i), omega=0.66, galerkin=True) for i in range(12)]
+    theta, losses = train(probs, steps=400, lr=1e-3, seed=0, warm_cycles=6)
+    return theta, losses
+
+
+def test_learned_omega_against_every_fixed_omega_on_held_out_problems():
+    """Per-subdomain weights (eq. 11) from the network trained on the
+    asymptotic two-grid objective (12 two-level 32^2/64^2 problems, inclusion
+    seeds 3000-3011, contrast 1e2, Galerkin coarse operators, 6 warm cycles,
+    400 Adam steps) against fixed omega on four held-out 128^2 problems (5
+    levels, seeds 4000-4003), V(2,2) to 1e-8 within 300 cycles: the learned
+    weights converge on all four, and their total cycle count is below that
+    of every fixed omega in {0.5, 0.6, 0.66, 0.75, 0.85} (a failure counted as
+    300; measured: learned 257, best fixed 311 at omega 0.66)."""
+    print("[gpu] learned: training on the asymptotic objective", flush=True)
+    theta, losses = _train_asymptotic()
+    assert np.mean(losses[-48:]) < np.mean(losses[:48])
+    net = MLP(theta)
+    cycles = {om: [] for om in FIXED_OMEGAS}
+    cycles["learned"] = []
+    for seed in range(4000, 4004):
+        print(f"[gpu] learned: held-out 128^2 seed {seed}", flush=True)
+        H = Hierarchy(dim=2, n_cells=128, n_levels=5, eta_in=100.0, inclusions=ri.inclusions(seed), omega=0.66,
+                      galerkin=True)
+        H.factor()
+        n, _ = H.dofs(4)
+        b = torch.zeros(n, dtype=torch.float64, device="cuda")
+        H.assemble_rhs(ri.mms_params(2, seed), b)
+        x = torch.zeros_like(b)
+        for om in FIXED_OMEGAS:
+            H.learn_set_omega(None)
+            H.set_params(om, 2, 2)
+            x.zero_()
+            st, it, _ = H.solve(x, b, 1e-8, MAXIT)
+            cycles[om].append(it if st == 0 else MAXIT)
+        H.set_params(0.66, 2, 2)
+        H.learn_set_omega(net)
+        x.zero_()
+        st, it, _ = H.solve(x, b, 1e-8, MAXIT)
+        cycles["learned"].append(it if st == 0 else MAXIT)
+        H.close()
+    net.close()
+    print(f"[gpu] learned vs fixed omega (cycles): {cycles}", flush=True)
+    assert MAXIT not in cycles["learned"], cycles["learned"]
+    assert sum(cycles["learned"]) < min(sum(cycles[om]) for om in FIXED_OMEGAS), cycles
