@@ -649,10 +649,13 @@ void launch_rav_apply(int dim, int kind, int cls, int prec, int split, const Gri
 }
 
 // ---- AV ---------------------------------------------------------------------
-// One wavefront per patch; lane l owns local rows l and l + 64.
+// One wavefront per patch; lane l owns local rows l and l + 64.  The patch's
+// residual entries are loaded once, in parallel, into LDS; the column loop
+// then streams the inverse (one coalesced column per step) against them.
 template <int DIM, int KIND>
 __global__ __launch_bounds__(64) void k_av_apply(const GridDev* __restrict__ G, long long npatch) {
   constexpr int NPAD = patch_npad(DIM, KIND);
+  __shared__ double rs[NPAD];
   const long long p = blockIdx.x;
   if (p >= npatch) return;
   const GridDev& gd = *G;
@@ -661,10 +664,15 @@ __global__ __launch_bounds__(64) void k_av_apply(const GridDev* __restrict__ G, 
   patch_anchor(g, KIND, p, k);
   const double* __restrict__ Wi = gd.Winv + p * (long long)NPAD * NPAD;
   const int lane = threadIdx.x;
+  for (int l = lane; l < NPAD; l += 64) {
+    const long long gi = patch_col<DIM, KIND>(g, k, l);
+    rs[l] = gi >= 0 ? gd.r[gi] : 0.0;
+  }
+  __syncthreads();
   double y0 = 0.0, y1 = 0.0;
+#pragma unroll 4
   for (int c = 0; c < NPAD; ++c) {
-    const long long gi = patch_col<DIM, KIND>(g, k, c);
-    const double rc = gi >= 0 ? gd.r[gi] : 0.0;
+    const double rc = rs[c];
     if (lane < NPAD) y0 += Wi[c * NPAD + lane] * rc;
     if (lane + 64 < NPAD) y1 += Wi[c * NPAD + lane + 64] * rc;
   }
@@ -729,101 +737,6 @@ __global__ __launch_bounds__(256) void k_av_gather(const GridDev* __restrict__ G
   gd.x[i] += s;
 }
 
-// ---- MV ---------------------------------------------------------------------
-// Row `R` of L times x (runtime node type).
-template <int DIM>
-__device__ double row_times_x(const GridDev& gd, long long R) {
-  const Geo& g = gd.g;
-  double acc = 0.0;
-  if (R < DIM * g.nV) {
-    long long nl_;
-    const int c = split_vel(g, R, &nl_);
-    int a[3] = {0, 0, 0};
-    node_of(g, nl_, a);
-    const int t = node_type(g, a);
-    const int s = c * (1 << DIM) + t;
-    const long long rows = gd.seg_rows[s], row = vel_seg_row(g, t, a);
-    const double* v = gd.vals + gd.seg_off[s] + row;
-    int w[3] = {0, 0, 0}, m[3] = {1, 1, 1}, lo[3] = {0, 0, 0};
-    for (int d = 0; d < DIM; ++d) {
-      w[d] = a_halfwidth(t, d);
-      m[d] = 3 - ((t >> d) & 1);
-      lo[d] = (a[d] >> 1) - 1 + ((t >> d) & 1);
-    }
-    int slot = 0;
-    for (int oz = -w[2]; oz <= w[2]; ++oz)
-      for (int oy = -w[1]; oy <= w[1]; ++oy)
-        for (int ox = -w[0]; ox <= w[0]; ++ox, ++slot) {
-          int b[3] = {a[0] + ox, a[1] + oy, a[2] + oz};
-          if (node_inside(g, b)) acc += v[slot * rows] * gd.x[c * g.nV + node_lin(g, b)];
-        }
-    for (int jz = 0; jz < m[2]; ++jz)
-      for (int jy = 0; jy < m[1]; ++jy)
-        for (int jx = 0; jx < m[0]; ++jx, ++slot) {
-          int kk[3] = {lo[0] + jx, lo[1] + jy, lo[2] + jz};
-          bool ok = true;
-          for (int d = 0; d < DIM; ++d) ok = ok && kk[d] >= 0 && kk[d] <= g.N;
-          if (ok) acc += v[slot * rows] * gd.x[DIM * g.nV + vert_lin(g, kk)];
-        }
-    return acc;
-  }
-  const long long row = R - DIM * g.nV;
-  int k[3] = {0, 0, 0};
-  vert_of(g, row, k);
-  const int s = pressure_segment(DIM);
-  const long long rows = gd.seg_rows[s];
-  const double* v = gd.vals + gd.seg_off[s] + row;
-  const int wz = DIM == 3 ? 2 : 0;
-  int slot = 0;
-  for (int c = 0; c < DIM; ++c)
-    for (int oz = -wz; oz <= wz; ++oz)
-      for (int oy = -2; oy <= 2; ++oy)
-        for (int ox = -2; ox <= 2; ++ox, ++slot) {
-          int b[3] = {2 * k[0] + ox, 2 * k[1] + oy, DIM == 3 ? 2 * k[2] + oz : 0};
-          if (node_inside(g, b)) acc += v[slot * rows] * gd.x[c * g.nV + node_lin(g, b)];
-        }
-  return acc;
-}
-
-template <int DIM, int KIND>
-__global__ __launch_bounds__(64) void k_mv_colour(const GridDev* __restrict__ G, int colour, long long npc) {
-  constexpr int NPAD = patch_npad(DIM, KIND);
-  __shared__ double rl[NPAD];
-  __shared__ long long gl[NPAD];
-  const long long q = blockIdx.x;
-  if (q >= npc) return;
-  const GridDev& gd = *G;
-  const Geo& g = gd.g;
-  const int M = colour_modulus(KIND);
-  const int ext = KIND == KIND_VERTEX ? g.N + 1 : g.N;
-  int k[3] = {0, 0, 0};
-  long long rem = q;
-  int cc = colour;
-  for (int d = 0; d < DIM; ++d) {
-    const int cd = cc % M;
-    cc /= M;
-    const int cnt = (ext - cd + M - 1) / M;
-    k[d] = cd + M * (int)(rem % cnt);
-    rem /= cnt;
-  }
-  const long long p = patch_lin(g, KIND, k);
-  const int lane = threadIdx.x;
-  for (int l = lane; l < NPAD; l += 64) {
-    int comp, node[3];
-    const long long R = patch_local_dof(g, KIND, k, l, &comp, node);
-    gl[l] = R;
-    rl[l] = R >= 0 ? gd.b[R] - row_times_x<DIM>(gd, R) : 0.0;
-  }
-  __syncthreads();
-  const double* __restrict__ Wi = gd.Winv + p * (long long)NPAD * NPAD;
-  const double om = gd.omega_patch ? (double)gd.omega_patch[p] : gd.omega;
-  for (int l = lane; l < NPAD; l += 64) {
-    double y = 0.0;
-    for (int c = 0; c < NPAD; ++c) y += Wi[c * NPAD + l] * rl[c];
-    if (gl[l] >= 0) gd.x[gl[l]] += om * y;
-  }
-}
-
 void launch_av_apply(int dim, int kind, const GridDev* G, long long npatch, hipStream_t s) {
   if (dim == 2 && kind == KIND_VERTEX) hipLaunchKernelGGL((k_av_apply<2, KIND_VERTEX>), dim3(npatch), dim3(64), 0, s, G, npatch);
   else if (dim == 2) hipLaunchKernelGGL((k_av_apply<2, KIND_ELEMENT>), dim3(npatch), dim3(64), 0, s, G, npatch);
@@ -837,11 +750,5 @@ void launch_av_gather(int dim, int kind, const GridDev* G, long long n, hipStrea
   else hipLaunchKernelGGL((k_av_gather<3, KIND_ELEMENT>), dim3(nb), dim3(256), 0, s, G, n);
 }
 
-void launch_mv_colour(int dim, int kind, const GridDev* G, int colour, long long npc, hipStream_t s) {
-  if (npc <= 0) return;
-  if (dim == 2 && kind == KIND_VERTEX) hipLaunchKernelGGL((k_mv_colour<2, KIND_VERTEX>), dim3(npc), dim3(64), 0, s, G, colour, npc);
-  else if (dim == 2) hipLaunchKernelGGL((k_mv_colour<2, KIND_ELEMENT>), dim3(npc), dim3(64), 0, s, G, colour, npc);
-  else hipLaunchKernelGGL((k_mv_colour<3, KIND_ELEMENT>), dim3(npc), dim3(64), 0, s, G, colour, npc);
-}
 
 }  // namespace rav

@@ -117,8 +117,9 @@ __device__ __forceinline__ bool free_coord(const Geo& g, int d, int v) {
 // columns outside the grid or on a masked side are replaced by 0 with a
 // select, so every path is branch-free except the correction for cut cells
 // (whose full matrices replace the scaled reference).
-template <int DIM, int TY>
-__device__ __forceinline__ double res_node(const GridDev& gd, long long row) {
+// With OUT the row values go to out[c] (per component) instead of r.
+template <int DIM, int TY, bool OUT = false>
+__device__ __forceinline__ double res_node(const GridDev& gd, long long row, double* out = nullptr) {
   constexpr int NV = ipow(3, DIM), NP = ipow(2, DIM);
   constexpr int NE0 = (TY & 1) ? 1 : 2, NE1 = ((TY >> 1) & 1) ? 1 : 2;
   constexpr int NE2 = DIM == 3 ? (((TY >> 2) & 1) ? 1 : 2) : 1;
@@ -138,7 +139,10 @@ __device__ __forceinline__ double res_node(const GridDev& gd, long long row) {
   for (int c = 0; c < DIM; ++c) bv[c] = gview(gd.b)[c * g.nV + base];
   if (node_dirichlet(g, a)) {
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) R[c * g.nV + base] = 0.0;
+    for (int c = 0; c < DIM; ++c) {
+      if constexpr (OUT) out[c] = 0.0;
+      else R[c * g.nV + base] = 0.0;
+    }
     return 0.0;
   }
   const int N = g.N;
@@ -302,7 +306,8 @@ __device__ __forceinline__ double res_node(const GridDev& gd, long long row) {
   for (int c = 0; c < DIM; ++c) {
     const long long gi = c * nV + base;
     const double r = bv[c] - (acc[c] + hB * accB[c]);
-    R[gi] = r;
+    if constexpr (OUT) out[c] = r;
+    else R[gi] = r;
     sq += r * r;
   }
   return sq;
@@ -312,8 +317,8 @@ __device__ __forceinline__ double res_node(const GridDev& gd, long long row) {
 // cells around the vertex (cell k - 1 + eo, local vertex 1 - eo), as a stencil
 // over the nodes 2k + o, |o_d| <= 2, with constant coefficients; missing cells
 // and masked or outside columns contribute nothing (selects, no branches).
-template <int DIM>
-__device__ __forceinline__ double res_pres(const GridDev& gd, long long row) {
+template <int DIM, bool OUT = false>
+__device__ __forceinline__ double res_pres(const GridDev& gd, long long row, double* out = nullptr) {
   constexpr int NV = ipow(3, DIM), NP = ipow(2, DIM);
   const Geo& g = gd.g;
   const Tabs<DIM>& T = tabs<DIM>();
@@ -384,7 +389,8 @@ __device__ __forceinline__ double res_pres(const GridDev& gd, long long row) {
   const double hB = DIM == 2 ? gd.h : gd.h * gd.h;
   const long long gi = DIM * nV + row;
   const double r = bv - hB * acc;
-  gview(gd.r)[gi] = r;
+  if constexpr (OUT) *out = r;
+  else gview(gd.r)[gi] = r;
   return r * r;
 }
 
@@ -1401,6 +1407,109 @@ bool residual_tiled_ok(int dim, int N) {
   if (dim == 2) return N >= 512 && N % RT_X == 0 && N % RT_Y == 0 && ((N / RT_X) * (N / RT_Y)) % 8 == 0;
   return N >= 64 && N % Q_X == 0 && N % Q_Y == 0 && N % Q_Z == 0 && ((N / Q_X) * (N / Q_Y) * (N / Q_Z)) % 8 == 0;
 }
+// ---- MV: one colour of patches (eq. 11 in the colour order, eq. 15) --------
+// One 64-lane block per patch of the colour.  The residual on the patch rows
+// is evaluated from the current x with the row formulas of the residual
+// kernels (one lane per velocity node or pressure vertex of the patch, values
+// kept in LDS), then y = omega L_i^{-1} r_i from the stored full inverse and x
+// on the patch DoFs += y.  Patches of one colour share no residual rows and
+// none of them reads x where another writes (colouring), so the colour's
+// patches run concurrently and equal the sequential product in that order.
+template <int DIM, int TY>
+__device__ __forceinline__ void mv_node(const GridDev& gd, const int* a, double* out) {
+  (void)res_node<DIM, TY, true>(gd, vel_seg_row(gd.g, TY, a), out);
+}
+
+template <int DIM>
+__device__ __forceinline__ void mv_node_any(const GridDev& gd, const int* a, double* out) {
+  const int t = node_type(gd.g, a);
+  if constexpr (DIM == 2) {
+    switch (t) {
+      case 0: mv_node<2, 0>(gd, a, out); break;
+      case 1: mv_node<2, 1>(gd, a, out); break;
+      case 2: mv_node<2, 2>(gd, a, out); break;
+      default: mv_node<2, 3>(gd, a, out); break;
+    }
+  } else {
+    switch (t) {
+      case 0: mv_node<3, 0>(gd, a, out); break;
+      case 1: mv_node<3, 1>(gd, a, out); break;
+      case 2: mv_node<3, 2>(gd, a, out); break;
+      case 3: mv_node<3, 3>(gd, a, out); break;
+      case 4: mv_node<3, 4>(gd, a, out); break;
+      case 5: mv_node<3, 5>(gd, a, out); break;
+      case 6: mv_node<3, 6>(gd, a, out); break;
+      default: mv_node<3, 7>(gd, a, out); break;
+    }
+  }
+}
+
+template <int DIM, int KIND>
+__global__ __launch_bounds__(64) void k_mv_colour(const GridDev* __restrict__ G, int colour, long long npc) {
+  constexpr int NPAD = patch_npad(DIM, KIND);
+  constexpr int NNODE = KIND == KIND_VERTEX ? ipow(5, DIM) : ipow(3, DIM);   // velocity nodes
+  constexpr int NPV = KIND == KIND_VERTEX ? 1 : ipow(2, DIM);                // pressure vertices
+  static_assert(NNODE + NPV <= 64, "one lane per patch node");
+  __shared__ double rl[NPAD];
+  const long long q = blockIdx.x;
+  if (q >= npc) return;
+  const GridDev& gd = *G;
+  const Geo& g = gd.g;
+  const int M = colour_modulus(KIND);
+  const int ext = KIND == KIND_VERTEX ? g.N + 1 : g.N;
+  int k[3] = {0, 0, 0};
+  long long rem = q;
+  int cc = colour;
+  for (int d = 0; d < DIM; ++d) {
+    const int cd = cc % M;
+    cc /= M;
+    const int cnt = (ext - cd + M - 1) / M;
+    k[d] = cd + M * (int)(rem % cnt);
+    rem /= cnt;
+  }
+  const long long p = patch_lin(g, KIND, k);
+  const int lane = threadIdx.x;
+  if (lane < NNODE) {
+    int a[3] = {0, 0, 0}, m = lane;
+    for (int d = 0; d < DIM; ++d) {
+      a[d] = KIND == KIND_VERTEX ? 2 * k[d] + (m % 5) - 2 : 2 * k[d] + (m % 3);
+      m /= KIND == KIND_VERTEX ? 5 : 3;
+    }
+    double out[DIM];
+    if (node_inside(g, a)) {
+      mv_node_any<DIM>(gd, a, out);   // 0 on masked nodes
+    } else {
+      for (int c = 0; c < DIM; ++c) out[c] = 0.0;
+    }
+    for (int c = 0; c < DIM; ++c) rl[c * NNODE + lane] = out[c];
+  } else if (lane < NNODE + NPV) {
+    const int j = lane - NNODE;
+    int kk[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) kk[d] = KIND == KIND_VERTEX ? k[d] : k[d] + ((j >> d) & 1);
+    double out = 0.0;
+    (void)res_pres<DIM, true>(gd, vert_lin(g, kk), &out);
+    rl[DIM * NNODE + j] = out;
+  }
+  __syncthreads();
+  const double* __restrict__ Wi = gd.Winv + p * (long long)NPAD * NPAD;
+  const double om = gd.omega_patch ? (double)gd.omega_patch[p] : gd.omega;
+  for (int l = lane; l < NPAD; l += 64) {
+    double y = 0.0;
+#pragma unroll 4
+    for (int c = 0; c < NPAD; ++c) y += Wi[c * NPAD + l] * rl[c];
+    int comp, node[3];
+    const long long gi = patch_local_dof(g, KIND, k, l, &comp, node);
+    if (gi >= 0) gd.x[gi] += om * y;
+  }
+}
+
+void launch_mv_colour(int dim, int kind, const GridDev* G, int colour, long long npc, hipStream_t s) {
+  if (npc <= 0) return;
+  if (dim == 2 && kind == KIND_VERTEX) hipLaunchKernelGGL((k_mv_colour<2, KIND_VERTEX>), dim3(npc), dim3(64), 0, s, G, colour, npc);
+  else if (dim == 2) hipLaunchKernelGGL((k_mv_colour<2, KIND_ELEMENT>), dim3(npc), dim3(64), 0, s, G, colour, npc);
+  else hipLaunchKernelGGL((k_mv_colour<3, KIND_ELEMENT>), dim3(npc), dim3(64), 0, s, G, colour, npc);
+}
+
 int residual_tiles(int dim, int N) {
   return dim == 2 ? (N / RT_X) * (N / RT_Y) : (N / Q_X) * (N / Q_Y) * (N / Q_Z);
 }
