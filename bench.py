@@ -358,6 +358,7 @@ def main():
                     "apply_GBs": (esz[prec] * w_entries(fmt) + 8 * n_fine + 16 * n_free) / (1e-3 * pm[1]) / 1e9}
                 Hm.close()
         out["variants"] = variants
+        out["q1q1_cavity_1024"] = q1q1_summary()
     else:
         H.close()
 
@@ -594,6 +595,37 @@ def bench_cavity(args):
                        "smoothing-steps study at 512x512 and mesh study at nu = 3; RAV/MV omega 0.66, AV 0.1",
            "inverse_format": args.format},
           smoothing_steps_512=study, mesh_study_nu3=mesh)
+
+
+def q1q1_summary() -> dict:
+    """The paper's own discretization beside the headline: stabilized Q1-Q1
+    driven cavity on 1024^2 (3,151,875 DoFs), 8 levels, RAV V(3,3), omega
+    0.66, beta 0.05, factored inverse, solve to 1e-8 (best of 3)."""
+    import torch
+    from paper_2103_10127_amd import Hierarchy
+    N, nl = 1024, 8
+    H = Hierarchy(dim=2, n_cells=N, n_levels=nl, dmask=ri.ALL_DIRICHLET_2D, nu_pre=3, nu_post=3, omega=0.66,
+                  inv_format="factored", discretization="q1q1", beta=0.05)
+    H.factor()
+    n, _ = H.dofs(nl - 1)
+    level_n = [H.dofs(l)[0] for l in range(nl)]
+    b = torch.zeros(n, dtype=torch.float64, device="cuda")
+    H.assemble_rhs_lid(b, 1.0)
+    x = torch.zeros_like(b)
+    H.solve(x, b, 1e-8, 3)
+    best, st, it = None, None, 0
+    for _ in range(3):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it, _ = H.solve(x, b, 1e-8, 200)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    H.close()
+    return {"dofs": n, "status": "converged" if st == 0 else str(st), "cycles": it,
+            "time_to_1e-8_ms": 1e3 * best,
+            "smoothed_dofs_per_s": it * sum(6 * level_n[l] for l in range(1, nl)) / best}
 
 
 def bench_q1q1(args):
