@@ -84,9 +84,11 @@ typedef enum { RAV_ROWS = 0, RAV_FACTORED = 1 } rav_inv_format;
  * hold p_k and every velocity DoF at the vertices of the cells around k
  * (2D 19, 3D 82 DoFs) and RAV owns p_k and the velocity at k (Sec. 3, eq. 13).
  * Q1-Q1 vectors have (d+1) (N+1)^d entries [u_1; ...; u_d; p], field f of
- * vertex v at f (N+1)^d + lin(v); it is provided with RAV, vertex patches and
- * FP64 inverses (either storage format); batches, FGMRES, the learned weights,
- * profiling markers and rav_export_matrix return RAV_EUNSUPPORTED for it. */
+ * vertex v at f (N+1)^d + lin(v); it is provided with vertex patches and FP64
+ * inverses for RAV (either storage format), AV and MV (full local inverses; MV
+ * in the colour order sum_d (k_d mod 4) 4^d, each patch recomputing its residual
+ * rows, eq. 15); batches, FGMRES, the learned weights, profiling markers and
+ * rav_export_matrix return RAV_EUNSUPPORTED for it. */
 typedef enum { RAV_TAYLOR_HOOD = 0, RAV_Q1Q1_STAB = 1 } rav_discretization;
 
 /* Circular (2D: cx, cy, r) or spherical (3D: cx, cy, cz, r) inclusion. */
@@ -348,6 +350,11 @@ rav_status rav_batch_assemble_rhs(rav_batch* batch, int problem, const double* m
                                   double* b_dev);
 rav_status rav_batch_vcycle(rav_batch* batch, double* const* x_dev, const double* const* b_dev);
 rav_status rav_batch_solve(rav_batch* batch, double* const* x_dev, const double* const* b_dev, double rtol,
+                           int maxit, int* iters, double* rel_res);
+/* The same two calls under the names rav_create_batch / rav_solve_batch
+ * (identical arguments and behaviour). */
+rav_status rav_create_batch(const rav_problem_desc* descs, int n_problems, void* hip_stream, rav_batch** out);
+rav_status rav_solve_batch(rav_batch* batch, double* const* x_dev, const double* const* b_dev, double rtol,
                            int maxit, int* iters, double* rel_res);
 /* Batched form of rav_solve_gmres (Sec. 4: the multigrid cycle as Krylov
  * preconditioner): restarted flexible GMRES(restart) for every problem, all

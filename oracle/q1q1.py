@@ -32,7 +32,8 @@ free velocity DoF at the vertices of the elements that contain k, i.e. the
 vertex block [k-1, k+1]^d clipped to the grid; local order component-major,
 vertices lexicographic, the pressure last (2D interior: 2*9 + 1 = 19).  The
 RAV owned set is the patch's pressure and the velocity at the same vertex,
-which partitions the DoFs.
+which partitions the DoFs.  AV (eq. 12) and MV (eq. 11, colour order below)
+use the same patches with every row of the local inverse.
 
 Transfer: bilinear/trilinear interpolation of every field (nested spaces),
 restriction its transpose; masked rows and columns zero.  Every level is
@@ -269,7 +270,14 @@ class PatchSetQ1:
             I = np.concatenate(parts)
             self.dofs.append(I)
             self.owned.append(np.nonzero(self.owner[I] == k)[0])
-        self.order = np.arange(self.count)
+        # MV order (eq. 11): ascending colour sum_d (k_d mod 4) 4^d, lexicographic
+        # within a colour.  A patch writes x within one vertex of k and its residual
+        # rows read x within two vertices of k, so patches of one colour (4 or
+        # more vertices apart in some direction) never see each other's updates:
+        # the sequential product in this order equals the colour-parallel form.
+        colour = sum((grid.vnode[:, d] % 4) * 4 ** d for d in range(d))
+        self.order = np.lexsort((np.arange(self.count), colour))
+        self.colour = colour
 
 
 class LevelQ1(mg.Level):

@@ -102,6 +102,9 @@ SIGNATURES = {
                              ctypes.POINTER(_D)]),
     "rav_batch_solve_gmres": (_S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _I, _I, ctypes.POINTER(_I),
                                    ctypes.POINTER(_D)]),
+    "rav_create_batch": (_S, [ctypes.POINTER(RavProblemDesc), _I, _P, ctypes.POINTER(_P)]),
+    "rav_solve_batch": (_S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _I, ctypes.POINTER(_I),
+                             ctypes.POINTER(_D)]),
     "rav_batch_destroy": (_S, [_P]),
     "rav_batch_last_error": (ctypes.c_char_p, [_P]),
     "rav_last_error": (ctypes.c_char_p, [_P]),

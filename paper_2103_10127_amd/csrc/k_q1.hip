@@ -99,6 +99,37 @@ __device__ __forceinline__ double gauss_x(const Q1Dev& q, int R, int e, int sc, 
   return ((double)(R * e + sc) + t) * hf;
 }
 
+// MV colour of vertex patch v: sum_d (v_d mod 4) 4^d; patches of colour c are
+// numbered lexicographically over (v_d - c_d) / 4, and the colours follow each
+// other in ascending order.  Patches whose count along a direction is
+// cnt_d(c) = ceil((N + 1 - c_d) / 4).
+__host__ __device__ inline long long mv_colour_count(int dim, int N, int colour) {
+  long long n = 1;
+  for (int d = 0; d < dim; ++d) {
+    const int cd = colour % 4;
+    colour /= 4;
+    n *= (N + 1 - cd + 3) / 4;
+  }
+  return n;
+}
+
+template <int DIM>
+__device__ __forceinline__ long long mv_position(const Q1Dev& q, const int* vc) {
+  int colour = 0, mul = 1;
+  for (int d = 0; d < DIM; ++d) { colour += (vc[d] % 4) * mul; mul *= 4; }
+  long long off = 0;
+  for (int c = 0; c < colour; ++c) off += mv_colour_count(DIM, q.N, c);
+  long long qi = 0, st = 1;
+  int cc = colour;
+  for (int d = 0; d < DIM; ++d) {
+    const int cd = cc % 4;
+    cc /= 4;
+    qi += ((vc[d] - cd) / 4) * st;
+    st *= (q.N + 1 - cd + 3) / 4;
+  }
+  return off + qi;
+}
+
 // ---- cell viscosity ---------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(256) void k_q1_cell_eta(Q1Dev q, int R, const double* __restrict__ incl, int n_incl,
@@ -232,64 +263,73 @@ __device__ __forceinline__ void q1_rows_cells(const Q1Dev& q, const double* __re
   }
 }
 
+// A x on the d+1 rows of vertex vc (velocity rows before masking): 2D loads the
+// 3x3 neighbourhood once, 3D visits the cells one after another.
+template <int DIM>
+__device__ __forceinline__ void q1_vertex_rows(const Q1Dev& q, const double* __restrict__ x, const int* vc,
+                                               long long v, double* au, double& ap) {
+  constexpr int NB = 1 << DIM;
+  constexpr int NBLK = q1_nblk(DIM);
+  ap = 0.0;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) au[c] = 0.0;
+  if constexpr (DIM == 3) {
+    q1_rows_cells<DIM>(q, x, vc, au, ap);
+  } else {
+    double u[DIM][NBLK], pv[NBLK];
+#pragma unroll
+    for (int m = 0; m < NBLK; ++m) {
+      int w[3] = {0, 0, 0};
+      int t = m;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) { w[d] = vc[d] + (t % 3) - 1; t /= 3; }
+      const bool in = inside<DIM>(q, w);
+      const bool fr = in & !vmasked<DIM>(q, w);
+      const long long wi = in ? vlin<DIM>(q, w) : v;
+      pv[m] = in ? x[DIM * q.nV + wi] : 0.0;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) u[c][m] = fr ? x[c * q.nV + wi] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {   // cell whose local vertex s is v
+      int e[3] = {0, 0, 0};
+      bool ok = true;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        e[d] = vc[d] - bit(s, d);
+        ok = ok & (e[d] >= 0) & (e[d] < q.N);
+      }
+      const double ce = ok ? q.ceta[clin<DIM>(q, e)] : 0.0;
+      const long long cut = cut_index(ce);
+      const double wc = ok ? 1.0 : 0.0;
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) {
+        int m = 0, st = 1;   // neighbourhood index of the cell's local vertex bb
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) { m += (bit(bb, d) - bit(s, d) + 1) * st; st *= 3; }
+        const double kab = acell<DIM>(q, ce, cut, s, bb);
+        ap += wc * q.cC * kunit<DIM>(s, bb) * pv[m];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          au[c] += kab * u[c][m] - wc * q.bscale * bunit<DIM>(c, s, bb) * pv[m];
+          ap -= wc * q.bscale * bunit<DIM>(c, bb, s) * u[c][m];
+        }
+      }
+    }
+  }
+}
+
 template <int DIM>
 __global__ __launch_bounds__(256) void k_q1_residual(Q1Dev q, const double* __restrict__ x,
                                                       const double* __restrict__ b, double* __restrict__ r,
                                                       double* __restrict__ partials) {
-  constexpr int NB = 1 << DIM;
-  constexpr int NBLK = q1_nblk(DIM);
   const long long v = blockIdx.x * 256LL + threadIdx.x;
   double sq = 0.0;
   if (v < q.nV) {
     int vc[3] = {0, 0, 0};
     decode<DIM>(q, v, vc);
     double au[DIM], ap = 0.0;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) au[c] = 0.0;
-    if constexpr (DIM == 3) {
-      q1_rows_cells<DIM>(q, x, vc, au, ap);
-    } else {
-      double u[DIM][NBLK], pv[NBLK];
-#pragma unroll
-      for (int m = 0; m < NBLK; ++m) {
-        int w[3] = {0, 0, 0};
-        int t = m;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) { w[d] = vc[d] + (t % 3) - 1; t /= 3; }
-        const bool in = inside<DIM>(q, w);
-        const bool fr = in & !vmasked<DIM>(q, w);
-        const long long wi = in ? vlin<DIM>(q, w) : v;
-        pv[m] = in ? x[DIM * q.nV + wi] : 0.0;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) u[c][m] = fr ? x[c * q.nV + wi] : 0.0;
-      }
-#pragma unroll
-      for (int s = 0; s < NB; ++s) {   // cell whose local vertex s is v
-        int e[3] = {0, 0, 0};
-        bool ok = true;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          e[d] = vc[d] - bit(s, d);
-          ok = ok & (e[d] >= 0) & (e[d] < q.N);
-        }
-        const double ce = ok ? q.ceta[clin<DIM>(q, e)] : 0.0;
-        const long long cut = cut_index(ce);
-        const double wc = ok ? 1.0 : 0.0;
-#pragma unroll
-        for (int bb = 0; bb < NB; ++bb) {
-          int m = 0, st = 1;   // neighbourhood index of the cell's local vertex bb
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) { m += (bit(bb, d) - bit(s, d) + 1) * st; st *= 3; }
-          const double kab = acell<DIM>(q, ce, cut, s, bb);
-          ap += wc * q.cC * kunit<DIM>(s, bb) * pv[m];
-#pragma unroll
-          for (int c = 0; c < DIM; ++c) {
-            au[c] += kab * u[c][m] - wc * q.bscale * bunit<DIM>(c, s, bb) * pv[m];
-            ap -= wc * q.bscale * bunit<DIM>(c, bb, s) * u[c][m];
-          }
-        }
-      }
-    }
+    q1_vertex_rows<DIM>(q, x, vc, v, au, ap);
     const bool vm = vmasked<DIM>(q, vc);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
@@ -315,15 +355,18 @@ __global__ __launch_bounds__(256) void k_q1_residual(Q1Dev q, const double* __re
 // ---- patch factorization: one 64-lane block per vertex patch ---------------
 // K (3^d x 3^d, identity rows/columns for padding) is eliminated by
 // Gauss-Jordan without pivoting (symmetric positive definite) with the d
-// pressure columns b_c and the unit vector of the block centre carried along;
-// then S = c_kk - sum_c b_c . z_c (negative: c_kk < 0 and K^{-1} is SPD).
+// pressure columns b_c and the identity carried along (giving z_c = K^{-1} b_c
+// and K^{-1}); then S = c_kk - sum_c b_c . z_c (negative: c_kk < 0 and K^{-1}
+// is SPD).  mode: Q1_ROWS owned rows, Q1_FACTORED the factored form, Q1_FULL
+// every row of L_i^{-1} (AV, MV), all value-major W[value * nV + patch].
 template <int DIM>
-__global__ __launch_bounds__(64) void k_q1_factor(Q1Dev q, int factored, double* __restrict__ W,
+__global__ __launch_bounds__(64) void k_q1_factor(Q1Dev q, int mode, double* __restrict__ W,
                                                    int* __restrict__ status) {
   constexpr int NB = 1 << DIM;
   constexpr int NBLK = q1_nblk(DIM);
   constexpr int CEN = (NBLK - 1) / 2;
-  constexpr int NC = NBLK + DIM + 1;   // K | b_1..b_d | e_centre
+  constexpr int NC = NBLK + DIM + NBLK;   // K | b_1..b_d | I
+  constexpr int KI = NBLK + DIM;          // first column of K^{-1}
   constexpr int NPAD = q1_npad(DIM);
   __shared__ double M[NBLK][NC];
   __shared__ double bsave[DIM][NBLK];
@@ -344,8 +387,8 @@ __global__ __launch_bounds__(64) void k_q1_factor(Q1Dev q, int factored, double*
     int w1[3] = {0, 0, 0};
     blk(m1i, w1);
     double val = 0.0;
-    if (col == NBLK + DIM) {
-      val = (m1i == CEN) ? 1.0 : 0.0;
+    if (col >= KI) {
+      val = (m1i == col - KI) ? 1.0 : 0.0;
     } else if (!valid(w1)) {
       val = (col == m1i) ? 1.0 : 0.0;
       if (col >= NBLK) bsave[col - NBLK][m1i] = 0.0;
@@ -428,24 +471,25 @@ __global__ __launch_bounds__(64) void k_q1_factor(Q1Dev q, int factored, double*
   if (!(S < 0.0) || !isfinite(sinv)) bad = true;
   if (bad && lane == 0) atomicMin(status, (int)k);
   const long long stride = q.nV;
-  if (factored) {
-    for (int idx = lane; idx < q1_nvals(DIM, true); idx += 64) {
+  const long long kpos = mode == Q1_FULL_MV ? mv_position<DIM>(q, vc) : k;   // patch slot in W
+  if (mode == Q1_FACTORED) {
+    for (int idx = lane; idx < q1_nvals(DIM, Q1_FACTORED); idx += 64) {
       double v;
-      if (idx < NBLK) v = M[idx][NBLK + DIM];
+      if (idx < NBLK) v = M[idx][KI + CEN];
       else if (idx < NBLK + DIM * NBLK) { const int c = (idx - NBLK) / NBLK, m = (idx - NBLK) % NBLK; v = M[m][NBLK + c]; }
       else v = sinv;
       W[idx * stride + k] = v;
     }
-  } else {
+  } else if (mode == Q1_ROWS) {
     // owned rows: velocity component c at the centre (rows 0..d-1), pressure (row d)
-    for (int idx = lane; idx < q1_nvals(DIM, false); idx += 64) {
+    for (int idx = lane; idx < q1_nvals(DIM, Q1_ROWS); idx += 64) {
       const int row = idx / NPAD, col = idx % NPAD;
       double v;
       if (row < DIM) {
         const double zc0 = M[CEN][NBLK + row];
         if (col < DIM * NBLK) {
           const int c2 = col / NBLK, m = col % NBLK;
-          v = (c2 == row ? M[m][NBLK + DIM] : 0.0) + zc0 * sinv * M[m][NBLK + c2];
+          v = (c2 == row ? M[m][KI + CEN] : 0.0) + zc0 * sinv * M[m][NBLK + c2];
         } else {
           v = -zc0 * sinv;
         }
@@ -458,6 +502,25 @@ __global__ __launch_bounds__(64) void k_q1_factor(Q1Dev q, int factored, double*
         }
       }
       W[idx * stride + k] = v;
+    }
+  } else {
+    // every row: (c, m) velocity rows then the pressure row, same columns
+    for (int idx = lane; idx < q1_nvals(DIM, Q1_FULL); idx += 64) {
+      const int row = idx / NPAD, col = idx % NPAD;
+      const bool rv = row < DIM * NBLK, cv = col < DIM * NBLK;
+      double v;
+      if (rv && cv) {
+        const int c1 = row / NBLK, m1 = row % NBLK, c2 = col / NBLK, m2 = col % NBLK;
+        v = (c1 == c2 ? M[m1][KI + m2] : 0.0) + M[m1][NBLK + c1] * sinv * M[m2][NBLK + c2];
+      } else if (rv) {
+        v = -M[row % NBLK][NBLK + row / NBLK] * sinv;
+      } else if (cv) {
+        v = -sinv * M[col % NBLK][NBLK + col / NBLK];
+      } else {
+        v = sinv;
+      }
+      if (mode == Q1_FULL_MV) W[kpos * (long long)(NPAD * NPAD) + idx] = v;   // patch-major
+      else W[idx * stride + k] = v;
     }
   }
 }
@@ -522,6 +585,149 @@ __global__ __launch_bounds__(256) void k_q1_apply(Q1Dev q, const double* __restr
   if (!vmasked<DIM>(q, vc)) {
 #pragma unroll
     for (int c = 0; c < DIM; ++c) x[c * q.nV + k] += omega * yu[c];
+  }
+}
+
+// ---- AV (eq. 12): every row of the local inverse, corrections summed -------
+// k_q1_av_apply: one thread per patch, Y[row * nV + k] = omega (L_i^{-1} r_i)[row];
+// k_q1_av_gather: one thread per vertex w, adding the rows of the patches that
+// hold its DoFs (velocity: the patches of the vertices within one of w, at
+// block position w - k; pressure: its own patch), so no two threads write
+// the same entry.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_q1_av_apply(Q1Dev q, const double* __restrict__ W,
+                                                      const double* __restrict__ r, double* __restrict__ Y,
+                                                      double omega) {
+  constexpr int NBLK = q1_nblk(DIM);
+  constexpr int NPAD = q1_npad(DIM);
+  const long long k = blockIdx.x * 256LL + threadIdx.x;
+  if (k >= q.nV) return;
+  const long long st = q.nV;
+  int vc[3] = {0, 0, 0};
+  decode<DIM>(q, k, vc);
+  double rl[NPAD];
+#pragma unroll
+  for (int m = 0; m < NBLK; ++m) {
+    int w[3] = {0, 0, 0};
+    int t = m;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) { w[d] = vc[d] + (t % 3) - 1; t /= 3; }
+    const bool ok = inside<DIM>(q, w) & !vmasked<DIM>(q, w);
+    const long long wi = ok ? vlin<DIM>(q, w) : 0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) rl[c * NBLK + m] = ok ? r[c * q.nV + wi] : 0.0;
+  }
+  rl[DIM * NBLK] = r[DIM * q.nV + k];
+#pragma unroll 1
+  for (int row = 0; row < NPAD; ++row) {
+    double y = 0.0;
+#pragma unroll
+    for (int col = 0; col < NPAD; ++col) y += W[(long long)(row * NPAD + col) * st + k] * rl[col];
+    Y[(long long)row * st + k] = omega * y;
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_q1_av_gather(Q1Dev q, const double* __restrict__ Y, double* __restrict__ x) {
+  constexpr int NBLK = q1_nblk(DIM);
+  const long long v = blockIdx.x * 256LL + threadIdx.x;
+  if (v >= q.nV) return;
+  const long long st = q.nV;
+  int vc[3] = {0, 0, 0};
+  decode<DIM>(q, v, vc);
+  x[DIM * q.nV + v] += Y[(long long)(DIM * NBLK) * st + v];
+  if (vmasked<DIM>(q, vc)) return;
+  double acc[DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int o = 0; o < NBLK; ++o) {   // patch k = v - (offset o), v at block position o of that patch
+    int kk[3] = {0, 0, 0};
+    int t = o;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) { kk[d] = vc[d] - ((t % 3) - 1); t /= 3; }
+    if (!inside<DIM>(q, kk)) continue;
+    const long long ki = vlin<DIM>(q, kk);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) acc[c] += Y[(long long)(c * NBLK + o) * st + ki];
+  }
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) x[c * q.nV + v] += acc[c];
+}
+
+// ---- MV (eqs. 11, 15): one colour of patches ----------------------------------
+// Patch k of colour sum_d (k_d mod 4) 4^d: its residual rows are recomputed from
+// the current x, then x on its DoFs += omega L_i^{-1} r_i.  A patch writes x
+// within one vertex of k and reads x within two vertices, so same-colour
+// patches (4 or more vertices apart in some direction) are independent.
+constexpr int MV_LANES = 32;   // lanes per patch of the MV kernel
+constexpr int MV_BLOCK = 64;   // two patches per block
+
+// One 32-lane group per patch: lane m < 3^d evaluates the rows of block vertex
+// m (the centre lane also the pressure row) into LDS, then lane r computes row
+// r of L_i^{-1} r_i from the patch-major stored inverse and updates that DoF.
+template <int DIM>
+__global__ __launch_bounds__(MV_BLOCK) void k_q1_mv_colour(Q1Dev q, const double* __restrict__ W,
+                                                            const double* __restrict__ b, double* __restrict__ x,
+                                                            double omega, int colour, long long npc) {
+  constexpr int NBLK = q1_nblk(DIM);
+  constexpr int NPAD = q1_npad(DIM);
+  constexpr int CEN = (NBLK - 1) / 2;
+  static_assert(NBLK <= MV_LANES, "one lane per block vertex");
+  __shared__ double rls[MV_BLOCK / MV_LANES][NPAD];
+  const int grp = threadIdx.x / MV_LANES, lane = threadIdx.x % MV_LANES;
+  const long long qi = blockIdx.x * (long long)(MV_BLOCK / MV_LANES) + grp;
+  const bool active = qi < npc;
+  double* rl = rls[grp];
+  int vc[3] = {0, 0, 0};
+  long long k = 0, pos = 0;
+  if (active) {
+    long long rem = qi;
+    int cc = colour;
+    for (int d = 0; d < DIM; ++d) {
+      const int cd = cc % 4;
+      cc /= 4;
+      const int cnt = (q.N + 1 - cd + 3) / 4;
+      vc[d] = cd + 4 * (int)(rem % cnt);
+      rem /= cnt;
+    }
+    k = vlin<DIM>(q, vc);
+    pos = qi;   // colour-major slot of this patch's inverse
+    for (int c = 0; c < colour; ++c) pos += mv_colour_count(DIM, q.N, c);
+  }
+  auto block_vertex = [&](int m, int* w) {
+    int t = m;
+    for (int d = 0; d < DIM; ++d) { w[d] = vc[d] + (t % 3) - 1; t /= 3; }
+    return inside<DIM>(q, w) & !vmasked<DIM>(q, w);
+  };
+  // residual rows of the patch from the current x (eq. 15)
+  if (active && lane < NBLK) {
+    int w[3] = {0, 0, 0};
+    const bool ok = block_vertex(lane, w);
+    if (ok || lane == CEN) {
+      const long long wi = vlin<DIM>(q, w);
+      double au[DIM], ap = 0.0;
+      q1_vertex_rows<DIM>(q, x, w, wi, au, ap);
+      for (int c = 0; c < DIM; ++c) rl[c * NBLK + lane] = ok ? b[c * q.nV + wi] - au[c] : 0.0;
+      if (lane == CEN) rl[DIM * NBLK] = b[DIM * q.nV + k] - ap;
+    } else {
+      for (int c = 0; c < DIM; ++c) rl[c * NBLK + lane] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  // x on the patch DoFs += omega L_i^{-1} r_i, one row per lane
+  const double* __restrict__ Wp = W + pos * (long long)(NPAD * NPAD);
+  for (int row = lane; row < NPAD; row += MV_LANES) {
+    double y = 0.0;
+#pragma unroll
+    for (int col = 0; col < NPAD; ++col) y += Wp[row * NPAD + col] * rl[col];
+    if (row == DIM * NBLK) {
+      x[DIM * q.nV + k] += omega * y;
+    } else {
+      int w[3] = {0, 0, 0};
+      if (block_vertex(row % NBLK, w)) x[(row / NBLK) * q.nV + vlin<DIM>(q, w)] += omega * y;
+    }
   }
 }
 
@@ -766,12 +972,28 @@ void q1_launch_residual(int dim, const Q1Dev& q, const double* x, const double* 
   Q1_DISPATCH(dim, k_q1_residual, nblk(q.nV), 256, q, x, b, r, partials);
 }
 
-void q1_launch_factor(int dim, const Q1Dev& q, int factored, double* W, int* status, hipStream_t s) {
-  Q1_DISPATCH(dim, k_q1_factor, (unsigned)q.nV, 64, q, factored, W, status);
+void q1_launch_factor(int dim, const Q1Dev& q, int mode, double* W, int* status, hipStream_t s) {
+  Q1_DISPATCH(dim, k_q1_factor, (unsigned)q.nV, 64, q, mode, W, status);
 }
 
-void q1_launch_apply(int dim, const Q1Dev& q, int factored, const double* W, const double* r, double* x,
+void q1_launch_av(int dim, const Q1Dev& q, const double* W, const double* r, double* Y, double* x, double omega,
+                  hipStream_t s) {
+  Q1_DISPATCH(dim, k_q1_av_apply, nblk(q.nV), 256, q, W, r, Y, omega);
+  Q1_DISPATCH(dim, k_q1_av_gather, nblk(q.nV), 256, q, Y, x);
+}
+
+void q1_launch_mv_colour(int dim, const Q1Dev& q, const double* W, const double* b, double* x, double omega,
+                         int colour, hipStream_t s) {
+  const long long npc = mv_colour_count(dim, q.N, colour);
+  if (npc <= 0) return;
+  const long long per_block = MV_BLOCK / MV_LANES;
+  const unsigned g = (unsigned)((npc + per_block - 1) / per_block);
+  Q1_DISPATCH(dim, k_q1_mv_colour, g, MV_BLOCK, q, W, b, x, omega, colour, npc);
+}
+
+void q1_launch_apply(int dim, const Q1Dev& q, int mode, const double* W, const double* r, double* x,
                      double omega, hipStream_t s) {
+  const bool factored = mode == Q1_FACTORED;
   const unsigned g = nblk(q.nV);
   if (dim == 2) {
     if (factored) hipLaunchKernelGGL((k_q1_apply<2, true>), dim3(g), dim3(256), 0, s, q, W, r, x, omega);

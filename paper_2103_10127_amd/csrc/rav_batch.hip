@@ -792,4 +792,13 @@ rav_status rav_batch_destroy(rav_batch* B) {
 
 const char* rav_batch_last_error(const rav_batch* B) { return B ? B->err.c_str() : g_batch_error.c_str(); }
 
+rav_status rav_create_batch(const rav_problem_desc* descs, int n, void* hip_stream, rav_batch** out) {
+  return rav_batch_create(descs, n, hip_stream, out);
+}
+
+rav_status rav_solve_batch(rav_batch* B, double* const* x, const double* const* b, double rtol, int maxit,
+                           int* iters, double* rel_res) {
+  return rav_batch_solve(B, x, b, rtol, maxit, iters, rel_res);
+}
+
 }  // extern "C"

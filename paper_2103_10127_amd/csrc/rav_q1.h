@@ -22,7 +22,8 @@
 //   factored: row m0 (block centre) of K^{-1} (3^d values), z_c = K^{-1} b_c
 //             (d 3^d values), s = 1/S (1 value), where K is the scalar viscous
 //             block of the patch, b_c its pressure column and S = c_kk - sum_c b_c.z_c;
-//   rows:     the d+1 owned rows of L_i^{-1} over the npad local columns.
+//   rows:     the d+1 owned rows of L_i^{-1} over the npad local columns;
+//   full:     all npad rows (AV, MV), row-major over the local DoFs.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -42,8 +43,14 @@ struct Q1Dev {
 
 constexpr int q1_nblk(int dim) { return dim == 2 ? 9 : 27; }
 constexpr int q1_npad(int dim) { return dim * q1_nblk(dim) + 1; }
-constexpr int q1_nvals(int dim, bool factored) {
-  return factored ? (dim + 1) * q1_nblk(dim) + 1 : (dim + 1) * q1_npad(dim);
+// Stored values per patch: owned rows (RAV), factored owned rows (RAV), or
+// the full inverse (AV, MV).
+// Q1_FULL_MV: the full inverse patch-major (NPAD^2 contiguous values per
+// patch), patches in MV colour-major order.
+enum { Q1_ROWS = 0, Q1_FACTORED = 1, Q1_FULL = 2, Q1_FULL_MV = 3 };
+constexpr int q1_nvals(int dim, int mode) {
+  return mode == Q1_FACTORED ? (dim + 1) * q1_nblk(dim) + 1
+       : mode == Q1_ROWS ? (dim + 1) * q1_npad(dim) : q1_npad(dim) * q1_npad(dim);
 }
 
 // Cell viscosity pass: eta at every (R^d fine cells x 2^d) Gauss point of
@@ -57,10 +64,19 @@ int q1_residual_blocks(const Q1Dev& q);
 void q1_launch_residual(int dim, const Q1Dev& q, const double* x, const double* b, double* r, double* partials,
                         hipStream_t s);
 // status receives (atomicMin) the first patch with a non-positive pivot of K
-// or a non-finite Schur complement.
-void q1_launch_factor(int dim, const Q1Dev& q, int factored, double* W, int* status, hipStream_t s);
-void q1_launch_apply(int dim, const Q1Dev& q, int factored, const double* W, const double* r, double* x,
+// or a non-finite Schur complement.  mode: Q1_ROWS, Q1_FACTORED, Q1_FULL or
+// Q1_FULL_MV (patch slots in colour order, contiguous per colour launch).
+void q1_launch_factor(int dim, const Q1Dev& q, int mode, double* W, int* status, hipStream_t s);
+// RAV (eq. 13): x_owned += omega (owned rows of L_i^{-1}) r_i (mode Q1_ROWS or Q1_FACTORED).
+void q1_launch_apply(int dim, const Q1Dev& q, int mode, const double* W, const double* r, double* x,
                      double omega, hipStream_t s);
+// AV (eq. 12): Y_i = omega L_i^{-1} r_i per patch, then x += sum_i R_i^T Y_i (gather, no atomics).
+void q1_launch_av(int dim, const Q1Dev& q, const double* W, const double* r, double* Y, double* x, double omega,
+                  hipStream_t s);
+// MV (eq. 11): the patches of one colour sum_d (k_d mod 4) 4^d, each recomputing
+// its residual rows from the current x (eq. 15) and adding omega L_i^{-1} r_i.
+void q1_launch_mv_colour(int dim, const Q1Dev& q, const double* W, const double* b, double* x, double omega,
+                         int colour, hipStream_t s);
 void q1_launch_restrict(int dim, const Q1Dev& f, const Q1Dev& c, const double* rf, double* bc, double* xc,
                         double* rc, hipStream_t s);   // rc may be null
 void q1_launch_prolong(int dim, const Q1Dev& f, const Q1Dev& c, const double* xc, double* xf, hipStream_t s);

@@ -25,6 +25,7 @@ struct rav_q1_state {
     double *ceta = nullptr, *cutK = nullptr;
     long long ncut = 0;
     double* W = nullptr;          // patch inverses (smoothed levels)
+    double* Y = nullptr;          // AV: per-patch corrections (row-major over the patch DoFs)
     double* partials = nullptr;   // residual norm partial sums
     int nres = 0;
   };
@@ -32,7 +33,7 @@ struct rav_q1_state {
   double* Minv = nullptr;
   long long nb = 0;
   int bordered = 0;
-  int factored = 1;    // storage: 1 = factored, 0 = owned rows
+  int mode = Q1_FACTORED;   // storage of the patch inverses (Q1_ROWS / Q1_FACTORED for RAV, full for AV/MV)
   bool have_factors = false;
 };
 
@@ -188,12 +189,21 @@ void residual(rav_ctx* ctx, int l, bool with_norm) {
   if (with_norm) launch_norm_finalize(L.partials, 0, L.nres, ctx->d_norm, ctx->h_norm_dev, ctx->stream);
 }
 
-// `sweeps` RAV sweeps (eq. 13); r_valid: L.r already holds b - L x.
+// `sweeps` smoothing sweeps: RAV (eq. 13) and AV (eq. 12) from one residual
+// (r_valid: L.r already holds b - L x), MV (eq. 11) colour by colour, each
+// patch recomputing its residual rows (eq. 15).
 void smooth(rav_ctx* ctx, int l, int sweeps, bool r_valid) {
   Level& L = st(ctx)->lv[l];
+  const rav_problem_desc& D = ctx->desc;
   for (int k = 0; k < sweeps; ++k) {
+    if (D.smoother == RAV_SMOOTHER_MV) {
+      const int ncol = D.dim == 2 ? 16 : 64;
+      for (int c = 0; c < ncol; ++c) q1_launch_mv_colour(D.dim, L.q, L.W, L.b, L.x, D.omega, c, ctx->stream);
+      continue;
+    }
     if (!(k == 0 && r_valid)) residual(ctx, l, false);
-    q1_launch_apply(ctx->desc.dim, L.q, st(ctx)->factored, L.W, L.r, L.x, ctx->desc.omega, ctx->stream);
+    if (D.smoother == RAV_SMOOTHER_AV) q1_launch_av(D.dim, L.q, L.W, L.r, L.Y, L.x, D.omega, ctx->stream);
+    else q1_launch_apply(D.dim, L.q, st(ctx)->mode, L.W, L.r, L.x, D.omega, ctx->stream);
   }
 }
 
@@ -285,8 +295,10 @@ rav_status rav_q1_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** 
     return rav_set_error(nullptr, RAV_EINVAL, "bc mask has bits beyond 2*dim");
   if (d->coarse_galerkin != 0 && d->coarse_galerkin != 1)
     return rav_set_error(nullptr, RAV_EINVAL, "coarse_galerkin must be 0 or 1");
-  if (d->patch != RAV_PATCH_VERTEX || d->smoother != RAV_SMOOTHER_RAV || d->inv_precision != RAV_FP64)
-    return rav_set_error(nullptr, RAV_EUNSUPPORTED, "the stabilized Q1-Q1 discretization is provided with RAV, "
+  if (d->smoother < RAV_SMOOTHER_RAV || d->smoother > RAV_SMOOTHER_MV)
+    return rav_set_error(nullptr, RAV_EINVAL, "bad smoother");
+  if (d->patch != RAV_PATCH_VERTEX || d->inv_precision != RAV_FP64)
+    return rav_set_error(nullptr, RAV_EUNSUPPORTED, "the stabilized Q1-Q1 discretization is provided with "
                          "vertex patches and FP64 inverses");
   if (d->inv_format != RAV_ROWS && d->inv_format != RAV_FACTORED)
     return rav_set_error(nullptr, RAV_EINVAL, "bad inverse format");
@@ -306,7 +318,9 @@ rav_status rav_q1_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** 
   rav_status s = rav_init_common(ctx, d);
   if (s != RAV_OK) return fail(s);
   rav_q1_state* S = ctx->q1;
-  S->factored = d->inv_format == RAV_FACTORED ? 1 : 0;
+  S->mode = d->smoother == RAV_SMOOTHER_AV ? Q1_FULL
+          : d->smoother == RAV_SMOOTHER_MV ? Q1_FULL_MV
+          : d->inv_format == RAV_FACTORED ? Q1_FACTORED : Q1_ROWS;
   S->lv.resize(d->n_levels);
   for (int l = 0; l < d->n_levels; ++l) {
     Level& L = S->lv[l];
@@ -333,7 +347,7 @@ void rav_q1_free(rav_ctx* ctx) {
   if (!S) return;
   for (Level& L : S->lv) {
     (void)hipFree(L.x); (void)hipFree(L.b); (void)hipFree(L.r); (void)hipFree(L.ceta); (void)hipFree(L.cutK);
-    (void)hipFree(L.W); (void)hipFree(L.partials);
+    (void)hipFree(L.W); (void)hipFree(L.Y); (void)hipFree(L.partials);
   }
   (void)hipFree(S->Minv);
   delete S;
@@ -343,13 +357,14 @@ void rav_q1_free(rav_ctx* ctx) {
 rav_status rav_q1_factor(rav_ctx* ctx) {
   rav_q1_state* S = st(ctx);
   const int dim = ctx->desc.dim;
-  const int nvals = q1_nvals(dim, S->factored != 0);
+  const int nvals = q1_nvals(dim, S->mode);
   const int big = INT_MAX;
   for (size_t l = 1; l < S->lv.size(); ++l) {
     Level& L = S->lv[l];
     if (!L.W) QCK(hipMalloc((void**)&L.W, sizeof(double) * nvals * L.q.nV));
+    if (S->mode == Q1_FULL && !L.Y) QCK(hipMalloc((void**)&L.Y, sizeof(double) * q1_npad(dim) * L.q.nV));
     QCK(hipMemcpy(ctx->d_status, &big, sizeof(int), hipMemcpyHostToDevice));
-    q1_launch_factor(dim, L.q, S->factored, L.W, ctx->d_status, ctx->stream);
+    q1_launch_factor(dim, L.q, S->mode, L.W, ctx->d_status, ctx->stream);
     QCK(hipGetLastError());
     int stv = 0;
     QCK(hipMemcpyAsync(&stv, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -595,16 +610,43 @@ rav_status rav_q1_get_patch_inverse(rav_ctx* ctx, int level, long patch, double*
   const Q1Dev& q = L.q;
   if (patch < 0 || patch >= q.nV) return RAV_EINVAL;
   const int dim = q.dim, nblk = dim == 2 ? 9 : 27, npad = dim * nblk + 1, cen = (nblk - 1) / 2;
-  const int nvals = q1_nvals(dim, S->factored != 0);
+  const int nvals = q1_nvals(dim, S->mode);
   std::vector<double> W(nvals);
   QCK(hipStreamSynchronize(ctx->stream));
-  QCK(hipMemcpy2D(W.data(), sizeof(double), L.W + patch, sizeof(double) * q.nV, sizeof(double), nvals,
-                  hipMemcpyDeviceToHost));
+  long long slot = patch;   // MV stores the inverses in colour-major order
+  if (S->mode == Q1_FULL_MV) {
+    int c[3];
+    vert_of(q, patch, c);
+    int colour = 0, mul = 1;
+    for (int d = 0; d < dim; ++d) { colour += (c[d] % 4) * mul; mul *= 4; }
+    slot = 0;
+    for (int cc = 0; cc < colour; ++cc) {
+      long long cnt = 1;
+      int t = cc;
+      for (int d = 0; d < dim; ++d) { const int cd = t % 4; t /= 4; cnt *= (q.N + 1 - cd + 3) / 4; }
+      slot += cnt;
+    }
+    long long qi = 0, stv = 1;
+    int t = colour;
+    for (int d = 0; d < dim; ++d) {
+      const int cd = t % 4;
+      t /= 4;
+      qi += ((c[d] - cd) / 4) * stv;
+      stv *= (q.N + 1 - cd + 3) / 4;
+    }
+    slot += qi;
+  }
+  if (S->mode == Q1_FULL_MV)   // patch-major
+    QCK(hipMemcpy(W.data(), L.W + slot * nvals, sizeof(double) * nvals, hipMemcpyDeviceToHost));
+  else
+    QCK(hipMemcpy2D(W.data(), sizeof(double), L.W + slot, sizeof(double) * q.nV, sizeof(double), nvals,
+                    hipMemcpyDeviceToHost));
   std::vector<int> dofs(npad), own(npad), pad(npad);
   const int n = q1_patch_list(q, patch, dofs.data(), own.data(), pad.data());
+  const bool full = S->mode == Q1_FULL || S->mode == Q1_FULL_MV;
   // entry of owned row `row` (0..d-1 velocity at the centre, d pressure) at padded column col
   auto entry = [&](int row, int col) -> double {
-    if (!S->factored) return W[(size_t)row * npad + col];
+    if (S->mode == Q1_ROWS) return W[(size_t)row * npad + col];
     const double sinv = W[nblk + dim * nblk];
     auto z = [&](int c, int m) { return W[nblk + c * nblk + m]; };
     const bool cv = col < dim * nblk;
@@ -619,11 +661,18 @@ rav_status rav_q1_get_patch_inverse(rav_ctx* ctx, int level, long patch, double*
     return sinv;
   };
   int nr = 0;
-  for (int i = 0; i < n; ++i) {
-    if (!own[i]) continue;
-    const int row = pad[i] == dim * nblk ? dim : pad[i] / nblk;
-    for (int j = 0; j < n; ++j) out[(size_t)nr * n + j] = entry(row, pad[j]);
-    ++nr;
+  if (full) {   // every row: the full local inverse over the patch DoFs
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < n; ++j) out[(size_t)i * n + j] = W[(size_t)pad[i] * npad + pad[j]];
+      ++nr;
+    }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      if (!own[i]) continue;
+      const int row = pad[i] == dim * nblk ? dim : pad[i] / nblk;
+      for (int j = 0; j < n; ++j) out[(size_t)nr * n + j] = entry(row, pad[j]);
+      ++nr;
+    }
   }
   *rows = nr;
   *cols = n;
@@ -643,7 +692,10 @@ rav_status rav_q1_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const
     QCK(hipEventRecord(ev[3 * i], ctx->stream));
     residual(ctx, level, false);
     QCK(hipEventRecord(ev[3 * i + 1], ctx->stream));
-    q1_launch_apply(ctx->desc.dim, L.q, st(ctx)->factored, L.W, L.r, L.x, ctx->desc.omega, ctx->stream);
+    if (ctx->desc.smoother == RAV_SMOOTHER_AV)
+      q1_launch_av(ctx->desc.dim, L.q, L.W, L.r, L.Y, L.x, ctx->desc.omega, ctx->stream);
+    else
+      q1_launch_apply(ctx->desc.dim, L.q, st(ctx)->mode, L.W, L.r, L.x, ctx->desc.omega, ctx->stream);
     QCK(hipEventRecord(ev[3 * i + 2], ctx->stream));
   }
   QCK(hipEventSynchronize(ev.back()));

@@ -122,7 +122,7 @@ def test_q1q1_host_maps_match_oracle(dim, N, nl, dm):
 
 
 @pytest.mark.parametrize("field,value,status", [
-    ("beta", 0.0, -1), ("smoother", 1, -6), ("inv_precision", 2, -6), ("patch", 1, -6), ("discretization", 5, -1),
+    ("beta", 0.0, -1), ("smoother", 7, -1), ("inv_precision", 2, -6), ("patch", 1, -6), ("discretization", 5, -1),
     ("n_levels", 2, -1),   # with n_cells = 256: 3 * 129^2 coarsest unknowns exceed the dense solve
 ])
 def test_q1q1_invalid_descriptors_rejected_without_device(field, value, status):

@@ -247,3 +247,39 @@ def test_full_batch_gmres_reaches_tolerance():
         r[~g.free] = 0.0
         assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(bo), (i, np.linalg.norm(r) / np.linalg.norm(bo))
     B.close()
+
+
+def test_batch_call_aliases_give_identical_results(monkeypatch):
+    """rav_create_batch / rav_solve_batch are the same calls as rav_batch_create /
+    rav_batch_solve: the solutions agree bit for bit and so do the counts (the
+    launch variants fixed by the size rule, so both batches run the same kernels)."""
+    import ctypes
+    monkeypatch.setenv("RAV_AUTOTUNE", "0")
+    probs = _problems([16, 32])
+    outs = []
+    for alias in (False, True):
+        B = Batch(probs)
+        if alias:   # rebuild the batch through the alias entry point
+            B.close()
+            h = ctypes.c_void_p()
+            st = B.lib.rav_create_batch(B.descs, len(probs), B.stream, ctypes.byref(h))
+            assert st == 0
+            B.h = h
+        B.factor()
+        xs, bs = [], []
+        for i, p in enumerate(probs):
+            params, n = _rhs(p, i)
+            b = torch.zeros(n, dtype=torch.float64, device="cuda")
+            B.assemble_rhs(i, params, b)
+            bs.append(b)
+            xs.append(torch.zeros_like(b))
+        its = (ctypes.c_int * len(probs))()
+        rel = (ctypes.c_double * len(probs))()
+        fn = B.lib.rav_solve_batch if alias else B.lib.rav_batch_solve
+        st = fn(B.h, B._ptrs(xs), B._ptrs(bs), 1e-8, 200, its, rel)
+        assert st == 0
+        outs.append(([x.cpu().numpy() for x in xs], list(its)))
+        B.close()
+    for a, b in zip(outs[0][0], outs[1][0]):
+        np.testing.assert_array_equal(a, b)
+    assert outs[0][1] == outs[1][1]
