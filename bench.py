@@ -637,16 +637,17 @@ def bench_q1q1(args):
     solved from 0 to a 1e-8 residual reduction.  Also: the Galerkin hierarchy,
     a beta sweep, the finest-level residual/apply times with the apply's byte
     roofline, and a 3D 64^3 cavity-like solve (all-Dirichlet, manufactured
-    forcing), and RAV against MV (omega 0.66) and AV (omega 0.1) on the 1024^2
-    cavity (time per cycle, cycles, total).  value = smoothed DoFs/s of the 2D
-    rediscretised RAV solve."""
+    forcing), RAV against MV (omega 0.66) and AV (omega 0.1) on the 1024^2
+    cavity (time per cycle, cycles, total), the smoothing-steps study nu = 1..6
+    at 1024^2 and the mesh study N = 64..512 at nu = 3.  value = smoothed DoFs/s
+    of the 2D rediscretised RAV solve."""
     import torch
     from paper_2103_10127_amd import Hierarchy
 
-    def run(dim, N, nl, beta, gal, rhs, reps=3, smoother="rav", omega=0.66):
+    def run(dim, N, nl, beta, gal, rhs, reps=3, smoother="rav", omega=0.66, nu=3, sweep_times=True):
         dm = ri.ALL_DIRICHLET_2D if dim == 2 else ri.ALL_DIRICHLET_3D
         t0 = time.perf_counter()
-        H = Hierarchy(dim=dim, n_cells=N, n_levels=nl, dmask=dm, nu_pre=3, nu_post=3, omega=omega,
+        H = Hierarchy(dim=dim, n_cells=N, n_levels=nl, dmask=dm, nu_pre=nu, nu_post=nu, omega=omega,
                       smoother=smoother, galerkin=gal, inv_format="factored", discretization="q1q1", beta=beta)
         H.factor()
         torch.cuda.synchronize()
@@ -669,14 +670,14 @@ def bench_q1q1(args):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t1
             best = dt if best is None else min(best, dt)
-        ms_res, ms_apply = H.time_sweep(nl - 1, 20, x, b) if smoother != "mv" else (None, None)
+        ms_res, ms_apply = H.time_sweep(nl - 1, 20, x, b) if smoother != "mv" and sweep_times else (None, None)
         H.close()
         return {"dim": dim, "N": N, "levels": nl, "beta": beta, "coarse": "galerkin" if gal else "rediscretised",
                 "smoother": smoother, "omega": omega, "ms_per_cycle": 1e3 * best / max(it, 1),
                 "dofs": n, "status": {0: "converged", 1: "maxit", -4: "diverged"}.get(st, str(st)), "cycles": it,
                 "rho_avg": rel ** (1.0 / it) if it > 0 and rel > 0 else None, "ms": 1e3 * best,
                 "setup_s": round(setup, 3), "ms_residual": ms_res, "ms_apply": ms_apply,
-                "smoothed_dofs": it * sum(2 * 3 * level_n[l] for l in range(1, nl))}
+                "nu": nu, "smoothed_dofs": it * sum(2 * nu * level_n[l] for l in range(1, nl))}
 
     main = run(2, 1024, 8, 0.05, False, "lid")
     gal = run(2, 1024, 8, 0.05, True, "lid", reps=1)
@@ -685,6 +686,12 @@ def bench_q1q1(args):
     # the paper's comparison (Sec. 4.1, Fig. 5) on its own discretization: RAV vs MV vs AV
     smoothers = [main] + [run(2, 1024, 8, 0.05, False, "lid", reps=1, smoother=sm_, omega=om)
                           for sm_, om in (("mv", 0.66), ("av", 0.1))]
+    # smoothing steps (Sec. 4.2, Fig. 7) at 1024^2 and the mesh study at nu = 3
+    steps = [run(2, 1024, 8, 0.05, False, "lid", reps=1, smoother=sm_, omega=om, nu=nu, sweep_times=False)
+             for nu in range(1, 7) for sm_, om in (("rav", 0.66), ("mv", 0.66), ("av", 0.1))]
+    mesh = [run(2, N, int(np.log2(N // 8)) + 1, 0.05, False, "lid", reps=1, smoother=sm_, omega=om,
+                sweep_times=False)
+            for N in (64, 128, 256, 512) for sm_, om in (("rav", 0.66), ("mv", 0.66), ("av", 0.1))]
     nV = 1025 ** 2
     apply_bytes = nV * (8 * (3 * 9 + 1) + 3 * 8 + 2 * 3 * 8)   # stored values, r once, x read and written
     achieved = apply_bytes / (main["ms_apply"] * 1e-3) / 1e9
@@ -694,7 +701,8 @@ def bench_q1q1(args):
                        "the 8x8 grid, RAV with pressure + co-located velocity owned, V(3,3), omega 0.66, factored"},
           roofline_apply={"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                           "frac": achieved / 8000.0, "bytes_per_launch": apply_bytes},
-          rediscretised=main, galerkin=gal, beta_sweep=sweep, three_d_64=three, smoothers_1024=smoothers)
+          rediscretised=main, galerkin=gal, beta_sweep=sweep, three_d_64=three, smoothers_1024=smoothers,
+          smoothing_steps_1024=steps, mesh_study_nu3=mesh)
 
 
 def bench_1024(args):
