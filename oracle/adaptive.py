@@ -1,5 +1,7 @@
-"""Adaptively refined quadrilateral grids of the driven-cavity hierarchy
-(Sec. 4.1, Table 1; Sec. 2, Fig. 2).  Test infrastructure: plain Python/numpy.
+"""Vertex and hanging-node counts of the adaptively refined quadrilateral grids
+of the driven-cavity hierarchy (Sec. 4.1, Table 1; Sec. 2, Fig. 2).  Test
+infrastructure: plain Python/numpy.  The leaf lists themselves come from the
+input generator (rav_inputs.cavity_grids).
 
 A grid is a list of leaf cells of a quadtree over [0,1]^2 whose root level is
 the uniform 8 x 8 grid; a leaf is (x0, y0, s) in integer units of half the
@@ -23,34 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
-BASE = 8
-BANDS = (2, 3, 5, 8, 13, 19, 27, 31, 17)
-
-
-def cavity_grids(n_grids: int = 10, bands=BANDS):
-    """The hierarchy Omega^1 .. Omega^n as leaf arrays (n_leaves, 3) of
-    (x0, y0, s) in units of half the finest cell of the last grid."""
-    L = n_grids - 1
-    M = BASE << (L + 1)                    # lattice units per side
-    s0 = 1 << (L + 1)
-    ii, jj = np.meshgrid(np.arange(BASE), np.arange(BASE), indexing="ij")
-    leaves = np.stack([ii.ravel() * s0, jj.ravel() * s0, np.full(BASE * BASE, s0)], axis=1).astype(np.int64)
-    grids = [leaves]
-    for l in range(1, n_grids):
-        s = leaves[:, 2]
-        fine = s.min()
-        x0, y0 = leaves[:, 0], leaves[:, 1]
-        # distance to the boundary in finest-cell units, measured from the cell's near side
-        dist = np.minimum.reduce([x0, y0, M - (x0 + s), M - (y0 + s)]) // fine
-        refine = (s == fine) & (dist < bands[l - 1])
-        keep = leaves[~refine]
-        r = leaves[refine]
-        h = r[:, 2:3] // 2
-        kids = np.concatenate([np.concatenate([r[:, 0:1] + dx * h, r[:, 1:2] + dy * h, h], axis=1)
-                               for dx in (0, 1) for dy in (0, 1)])
-        leaves = np.concatenate([keep, kids])
-        grids.append(leaves)
-    return grids
+from rav_inputs import BANDS, BASE, cavity_grids, lattice  # noqa: F401  (the grids are inputs)
 
 
 def _points(leaves, which):

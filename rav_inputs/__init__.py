@@ -146,3 +146,45 @@ def mlp_init(seed: int, out_bias: float = -0.16, out_scale: float = 0.01) -> np.
     w3 = rng.standard_normal(64) * out_scale
     parts = [w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3, np.array([out_bias])]
     return np.concatenate(parts).astype(np.float32)
+
+
+# ---- adaptive cavity grids (Sec. 4.1, Table 1) -------------------------------
+# Leaf cells (x0, y0, s) of quadtrees over the unit square in integer lattice
+# units (lattice(n) per side).  Grid 1 is the uniform 8 x 8 grid; step l
+# refines every leaf of the current finest size within BANDS[l-1] such cells of
+# the boundary (a reading of the paper's "refined towards the boundary" that
+# gives the element counts of its grid table).
+BASE = 8
+BANDS = (2, 3, 5, 8, 13, 19, 27, 31, 17)
+
+
+def lattice(n_grids: int) -> int:
+    """Lattice units per side of the unit square for a hierarchy of n_grids."""
+    return BASE << n_grids
+
+
+def cavity_grids(n_grids: int = 10, bands=BANDS):
+    """The hierarchy Omega^1 .. Omega^n as leaf arrays (n_leaves, 3) of
+    (x0, y0, s) in units of half the finest cell of the last grid."""
+    M = lattice(n_grids)                   # lattice units per side
+    s0 = 1 << n_grids
+    ii, jj = np.meshgrid(np.arange(BASE), np.arange(BASE), indexing="ij")
+    leaves = np.stack([ii.ravel() * s0, jj.ravel() * s0, np.full(BASE * BASE, s0)], axis=1).astype(np.int64)
+    grids = [leaves]
+    for l in range(1, n_grids):
+        s = leaves[:, 2]
+        fine = s.min()
+        x0, y0 = leaves[:, 0], leaves[:, 1]
+        # distance to the boundary in finest-cell units, measured from the cell's near side
+        dist = np.minimum.reduce([x0, y0, M - (x0 + s), M - (y0 + s)]) // fine
+        refine = (s == fine) & (dist < bands[l - 1])
+        keep = leaves[~refine]
+        r = leaves[refine]
+        h = r[:, 2:3] // 2
+        kids = np.concatenate([np.concatenate([r[:, 0:1] + dx * h, r[:, 1:2] + dy * h, h], axis=1)
+                               for dx in (0, 1) for dy in (0, 1)])
+        leaves = np.concatenate([keep, kids])
+        grids.append(leaves)
+    return grids
+
+
