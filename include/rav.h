@@ -89,7 +89,7 @@ typedef enum { RAV_ROWS = 0, RAV_FACTORED = 1 } rav_inv_format;
  * in the colour order sum_d (k_d mod 4) 4^d, each patch recomputing its residual
  * rows, eq. 15); batches, FGMRES, the learned weights, profiling markers and
  * rav_export_matrix return RAV_EUNSUPPORTED for it. */
-typedef enum { RAV_TAYLOR_HOOD = 0, RAV_Q1Q1_STAB = 1 } rav_discretization;
+typedef enum { RAV_TAYLOR_HOOD = 0, RAV_Q1Q1_STAB = 1, RAV_Q1Q1_ADAPTIVE = 2 } rav_discretization;
 
 /* Circular (2D: cx, cy, r) or spherical (3D: cx, cy, cz, r) inclusion. */
 typedef struct { double cx, cy, cz, r; } rav_inclusion;
@@ -293,6 +293,62 @@ rav_status rav_profile_end(rav_ctx* ctx, float* avg_residual_ms, float* avg_appl
 
 /* Plain device copy of n doubles on hip_stream (bandwidth calibration). */
 rav_status rav_stream_copy(void* hip_stream, double* dst_dev, const double* src_dev, long n);
+
+/* ---- adaptively refined grids (Sec. 2, Fig. 2; Sec. 4.1, Table 1) ----------
+ * Stabilized Q1-Q1 (eq. 8, beta and the viscosity eta_out of the descriptor)
+ * on a hierarchy of quadtree grids over the unit square, each grid refining
+ * the previous one, with hanging nodes: a leaf corner at the midpoint of a
+ * larger neighbour's edge carries no unknown and takes the mean of that edge's
+ * endpoints, so the discrete space is the conforming Q1 space (Fig. 2).  The
+ * operator of every grid is assembled anew on that grid (Sec. 4) as
+ * L = T^T L_leaves T with T the constraint map.  Unknowns: [u_x; u_y; p] over
+ * the regular vertices (leaf corners that are not hanging), numbered
+ * lexicographically (y slowest); velocity is Dirichlet on the whole boundary
+ * (the driven cavity, rav_assemble_rhs_lid; bc_dirichlet_mask must be 0xF).
+ * Vanka patch i (one per regular vertex): p_i and the free velocity at the
+ * vertices of the leaves around vertex i, a hanging corner standing for the
+ * vertices that constrain it (at most 16 free vertices, else
+ * RAV_EUNSUPPORTED); RAV owns p_i and the velocity at i.  MV visits the
+ * patches colour by colour (greedy colouring in patch order: a patch takes
+ * the smallest colour of no earlier patch whose vertices meet the row pattern
+ * of its own vertices), which is the sequential sweep in that order.
+ *
+ * leaves_host: the leaves of all grids, coarsest first, as int32 triples
+ * (x0, y0, s) in lattice units (the unit square is lattice x lattice units;
+ * s an even power of two, x0 and y0 multiples of s); n_leaves_host[l] leaves
+ * for grid l, l < desc->n_levels.  Copied; the host arrays may be freed on
+ * return.  Every grid must tile the square, be 2:1 balanced and refine the
+ * previous one; the coarsest must have at most 16383 DoFs (dense direct
+ * solve).  desc: discretization RAV_Q1Q1_ADAPTIVE, dim 2, n_cells ignored,
+ * no inclusions, vertex patches, FP64, coarse_galerkin 0; inv_format is
+ * ignored (the owned rows are kept factored: row i of K_i^{-1}, K_i^{-1} b_c
+ * and the inverse Schur complement).  RAV_EINVAL with a message (before any
+ * device work) for grids that break these rules.  The context then serves
+ * rav_factor_patches, rav_dofs, rav_n_levels, rav_n_patches,
+ * rav_assemble_rhs_lid, rav_residual, rav_smooth, rav_restrict,
+ * rav_prolong_add, rav_coarse_solve, rav_vcycle, rav_solve, rav_set_params,
+ * rav_get_patch_map, rav_get_owner, rav_get_patch_inverse, rav_time_sweep and
+ * rav_destroy; the others return RAV_EUNSUPPORTED. */
+rav_status rav_create_adaptive(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
+                               long lattice, void* hip_stream, rav_ctx** out);
+/* Sizes of grid `level` into info_host[4]: regular vertices, stored operator
+ * entries (vertex pairs, padded to 64-vertex slices), stored patch entries,
+ * MV colours (0 on the coarsest grid). */
+rav_status rav_adaptive_level_info(const rav_ctx* ctx, int level, long* info_host);
+
+/* Host-only (touches no device, works without a GPU): the set-up that
+ * rav_create_adaptive performs for grid `level`, written out for checks.
+ * what = 0: the operator, dense row-major (*rows = *cols = n_total; masked
+ *           rows and columns zero);
+ * what = 1: the prolongation from grid level-1 (*rows = n_total(level),
+ *           *cols = n_total(level-1); masked velocity rows/columns zero);
+ * what = 2: the lid lifting for lid velocity 1 on this grid (*rows = n_total,
+ *           *cols = 1; rav_assemble_rhs_lid scales the finest one);
+ * what = 3: the MV colour of every patch (*rows = n_patches, *cols = 1).
+ * out_host NULL only reports the shape.  Same validation and errors as
+ * rav_create_adaptive. */
+rav_status rav_adaptive_host_export(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
+                                    long lattice, int level, int what, double* out_host, long* rows, long* cols);
 
 rav_status rav_destroy(rav_ctx* ctx);
 

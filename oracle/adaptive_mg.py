@@ -22,9 +22,9 @@ Vanka patches (Sec. 3): the patch of regular vertex i holds p_i and every free
 velocity unknown of the leaves around vertex i (the structural nonzeros of row
 i of B^T), a hanging corner standing for the regular vertices that constrain
 it (the paper's implicit inclusion of hanging nodes, Fig. 2); RAV owns p_i and
-the velocity at vertex i.  MV order: greedy colouring of the patch
-interaction graph (a patch may not write x where a same-colour patch reads
-it), colour-major.
+the velocity at vertex i.  MV order: greedy colouring in patch order by
+vertex sets (mv_colouring: a patch may not write x where a same-colour patch
+reads it), colour-major.
 
 Transfer between consecutive grids (each refines the previous): the coarse FE
 function evaluated at the fine regular vertices (bilinear on the coarse leaf
@@ -222,32 +222,56 @@ def prolongation(fine: AdaptiveGrid, coarse: AdaptiveGrid):
     return P
 
 
-def mv_colouring(dofs, L):
-    """Greedy colouring: patches i, j conflict when patch j's DoFs reach a row of
-    patch i through L (or the reverse); returns the colour of every patch."""
-    n = L.shape[0]
-    owner_rows = [set(I.tolist()) for I in dofs]
-    reach = []
-    Lc = L.tocsr()
-    for I in dofs:
-        cols = set(Lc[I].indices.tolist())
-        reach.append(cols | set(I.tolist()))
-    # patches that touch each DoF
-    touch = [[] for _ in range(n)]
-    for p, I in enumerate(dofs):
-        for d in I:
-            touch[d].append(p)
-    colour = -np.ones(len(dofs), dtype=np.int64)
-    for p in range(len(dofs)):
-        banned = set()
-        for d in reach[p]:
-            for q in touch[d]:
-                if colour[q] >= 0:
-                    banned.add(int(colour[q]))
+def leaf_vertex_sets(grid: AdaptiveGrid):
+    """V_e for every leaf: the regular vertices its corners depend on."""
+    cache = {}
+    sets = []
+    for li in range(len(grid.leaves)):
+        vs = set()
+        for a in range(4):
+            k = int(grid.corner_keys[li, a])
+            w = cache.get(k)
+            if w is None:
+                w = cache[k] = grid.weights(k)
+            vs.update(w.keys())
+        sets.append(vs)
+    return sets
+
+
+def mv_colouring(grid: AdaptiveGrid):
+    """Greedy colouring in patch order, by vertex sets (so that it does not
+    depend on which assembled entries happen to cancel): the row pattern of
+    vertex v is the union of V_e over the leaves with v in V_e; the vertex set
+    of patch i is the union of V_e over the leaves that have i as a corner
+    (masked vertices included); patch i takes the smallest colour not used by
+    an earlier patch whose vertex set meets the row pattern of one of patch
+    i's vertices.  Returns the colour of every patch."""
+    sets = leaf_vertex_sets(grid)
+    nV = grid.nV
+    rows = [set() for _ in range(nV)]
+    for vs in sets:
+        for v in vs:
+            rows[v] |= vs
+    pverts = [set() for _ in range(nV)]
+    for li in range(len(grid.leaves)):
+        for a in range(4):
+            i = grid.reg_index.get(int(grid.corner_keys[li, a]))
+            if i is not None:
+                pverts[i] |= sets[li]
+    holders = [[] for _ in range(nV)]
+    for i in range(nV):
+        for v in pverts[i]:
+            holders[v].append(i)
+    colour = -np.ones(nV, dtype=np.int64)
+    for i in range(nV):
+        reach = set()
+        for v in pverts[i]:
+            reach |= rows[v]
+        banned = {int(colour[q]) for u in reach for q in holders[u] if q < i}
         c = 0
         while c in banned:
             c += 1
-        colour[p] = c
+        colour[i] = c
     return colour
 
 
@@ -266,7 +290,7 @@ class AdaptiveLevel(mg.Level):
 
             ps = _PS()
             ps.dofs, ps.owned, ps.count = dofs, owned, len(dofs)
-            ps.colour = mv_colouring(dofs, self.L)
+            ps.colour = mv_colouring(grid)
             ps.order = np.lexsort((np.arange(ps.count), ps.colour))
             self.patches = ps
             self.lus = sm.factor(self.L, dofs)

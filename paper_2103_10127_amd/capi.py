@@ -24,7 +24,7 @@ SMOOTHERS = {"rav": 0, "av": 1, "mv": 2}
 KINDS = {"vertex": 0, "element": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 FORMATS = {"rows": 0, "factored": 1}
-DISCRETIZATIONS = {"taylor-hood": 0, "q1q1": 1}
+DISCRETIZATIONS = {"taylor-hood": 0, "q1q1": 1, "q1q1-adaptive": 2}
 
 
 class RavError(RuntimeError):
@@ -108,6 +108,11 @@ SIGNATURES = {
     "rav_batch_destroy": (_S, [_P]),
     "rav_batch_last_error": (ctypes.c_char_p, [_P]),
     "rav_last_error": (ctypes.c_char_p, [_P]),
+    "rav_create_adaptive": (_S, [ctypes.POINTER(RavProblemDesc), ctypes.POINTER(_I), ctypes.POINTER(_L), _L, _P,
+                                 ctypes.POINTER(_P)]),
+    "rav_adaptive_level_info": (_S, [_P, _I, ctypes.POINTER(_L)]),
+    "rav_adaptive_host_export": (_S, [ctypes.POINTER(RavProblemDesc), ctypes.POINTER(_I), ctypes.POINTER(_L), _L, _I,
+                                      _I, ctypes.POINTER(_D), ctypes.POINTER(_L), ctypes.POINTER(_L)]),
 }
 
 
@@ -329,6 +334,65 @@ class Hierarchy:
         a, c = ctypes.c_float(), ctypes.c_float()
         self._chk(self.lib.rav_time_sweep(self.h, level, reps, _ptr(x), _ptr(b), ctypes.byref(a), ctypes.byref(c)))
         return a.value, c.value
+
+
+def _adaptive_desc(n_grids, smoother, omega, nu_pre, nu_post, beta, eta):
+    return make_desc(dim=2, n_cells=0, n_levels=n_grids, dmask=0b1111, smoother=smoother, omega=omega,
+                     nu_pre=nu_pre, nu_post=nu_post, eta_out=eta, eta_in=eta, discretization="q1q1-adaptive",
+                     beta=beta)
+
+
+def _leaf_arrays(grids):
+    leaves = np.ascontiguousarray(np.concatenate([np.asarray(g, dtype=np.int32).reshape(-1, 3) for g in grids]))
+    counts = np.array([len(g) for g in grids], dtype=np.int64)
+    return leaves, counts
+
+
+class AdaptiveHierarchy(Hierarchy):
+    """Stabilized Q1-Q1 on a hierarchy of adaptively refined quadtree grids
+    (``rav_create_adaptive``): ``grids`` lists the leaf arrays (n, 3) of
+    (x0, y0, s), coarsest first, in units of ``lattice`` per side."""
+
+    def __init__(self, grids, lattice, smoother="rav", omega=0.66, nu_pre=2, nu_post=2, beta=0.05, eta=1.0,
+                 stream=None):
+        self.lib = lib()
+        self.desc = _adaptive_desc(len(grids), smoother, omega, nu_pre, nu_post, beta, eta)
+        leaves, counts = _leaf_arrays(grids)
+        self.stream = _stream() if stream is None else stream
+        h = _P()
+        st = self.lib.rav_create_adaptive(ctypes.byref(self.desc), leaves.ctypes.data_as(ctypes.POINTER(_I)),
+                                          counts.ctypes.data_as(ctypes.POINTER(_L)), int(lattice), self.stream,
+                                          ctypes.byref(h))
+        if st < 0:
+            raise RavError(st, self.lib.rav_last_error(None).decode())
+        self.h = h
+        self.dim, self.n_levels = 2, len(grids)
+
+    def level_info(self, level):
+        """(vertices, stored operator entries, stored patch entries, MV colours)."""
+        out = (_L * 4)()
+        self._chk(self.lib.rav_adaptive_level_info(self.h, level, out))
+        return tuple(int(v) for v in out)
+
+
+def adaptive_host_export(grids, lattice, level, what, beta=0.05, eta=1.0):
+    """Host-only set-up of one adaptive grid (``rav_adaptive_host_export``):
+    what = "operator" | "prolong" | "lid" | "colours"."""
+    kinds = {"operator": 0, "prolong": 1, "lid": 2, "colours": 3}
+    desc = _adaptive_desc(len(grids), "mv" if what == "colours" else "rav", 0.66, 2, 2, beta, eta)
+    leaves, counts = _leaf_arrays(grids)
+    rows, cols = _L(), _L()
+    args = (ctypes.byref(desc), leaves.ctypes.data_as(ctypes.POINTER(_I)), counts.ctypes.data_as(ctypes.POINTER(_L)),
+            int(lattice), level, kinds[what])
+    st = lib().rav_adaptive_host_export(*args, None, ctypes.byref(rows), ctypes.byref(cols))
+    if st < 0:
+        raise RavError(st, lib().rav_last_error(None).decode())
+    out = np.zeros((rows.value, cols.value))
+    st = lib().rav_adaptive_host_export(*args, out.ctypes.data_as(ctypes.POINTER(_D)), ctypes.byref(rows),
+                                        ctypes.byref(cols))
+    if st < 0:
+        raise RavError(st, lib().rav_last_error(None).decode())
+    return out if cols.value > 1 else out[:, 0]
 
 
 class MLP:

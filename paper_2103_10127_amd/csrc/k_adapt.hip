@@ -1,0 +1,411 @@
+// Kernels of the stabilized Q1-Q1 levels on adaptive quadtree grids (Sec. 2,
+// eqs. 5-8, Fig. 2) and of their Vanka smoothers (Sec. 3, eqs. 11-13).  The
+// operator and the patch lists are stored as described in rav_adapt.h.
+//
+// Every kernel gathers: a thread (or a lane group) owns what it writes, so no
+// atomics are needed and results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "rav_adapt.h"
+
+namespace rav {
+
+namespace {
+
+inline unsigned nblk(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+__device__ __forceinline__ double plane(const AdDev& a, int p, long long e) { return a.val[p * a.nnz + e]; }
+
+// Value of plane p at (row vertex v, column vertex j); 0 if j is not in the row.
+__device__ double lookup(const AdDev& a, int v, int j, int p) {
+  const int e0 = a.soff[v >> 6], w = (a.soff[(v >> 6) + 1] - e0) >> 6;
+  const int t = v & 63;
+  double out = 0.0;
+  for (int k = 0; k < w; ++k) {
+    const long long e = e0 + 64LL * k + t;
+    if (a.col[e] == j) out += plane(a, p, e);   // one entry per column; padding entries hold 0
+  }
+  return out;
+}
+
+// ---- residual: one thread per vertex, its three rows -------------------------
+__global__ __launch_bounds__(256) void k_ad_residual(AdDev a, const double* __restrict__ x,
+                                                     const double* __restrict__ b, double* __restrict__ r,
+                                                     double* __restrict__ partials) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int nV = a.nV;
+  double sq = 0.0;
+  if (i < nV) {
+    const int e0 = a.soff[i >> 6], w = (a.soff[(i >> 6) + 1] - e0) >> 6;
+    const int t = i & 63;
+    double su = 0.0, sv = 0.0, sp = 0.0;
+    for (int k = 0; k < w; ++k) {
+      const long long e = e0 + 64LL * k + t;
+      const int j = a.col[e];
+      const double uj = x[j], vj = x[nV + j], pj = x[2 * nV + j];
+      su += a.val[e] * uj + a.val[AD_BTX * a.nnz + e] * pj;
+      sv += a.val[e] * vj + a.val[AD_BTY * a.nnz + e] * pj;
+      sp += a.val[AD_BX * a.nnz + e] * uj + a.val[AD_BY * a.nnz + e] * vj + a.val[AD_C * a.nnz + e] * pj;
+    }
+    const bool vm = a.vmask[i] != 0;
+    const double ru = vm ? 0.0 : b[i] - su;
+    const double rv = vm ? 0.0 : b[nV + i] - sv;
+    const double rp = b[2 * nV + i] - sp;
+    r[i] = ru;
+    r[nV + i] = rv;
+    r[2 * nV + i] = rp;
+    sq = ru * ru + rv * rv + rp * rp;
+  }
+  if (!partials) return;
+  __shared__ double red[256];
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// ---- patch factorization: one 64-lane block per patch ------------------------
+// Gauss-Jordan elimination without pivoting on [K | b_x b_y | I] (K SPD,
+// padded to AD_NFMAX with identity rows), giving z_c = K^{-1} b_c and K^{-1};
+// then S = c - b_x.z_x - b_y.z_y (negative: c < 0 and K^{-1} SPD).
+constexpr int NF = AD_NFMAX;
+constexpr int NCOL = 2 * NF + 2;
+constexpr int KI = NF + 2;
+
+__global__ __launch_bounds__(64) void k_ad_factor(AdDev a, int mode, AdFactors f, int* __restrict__ status) {
+  __shared__ int verts[NF];
+  __shared__ double M[NF][NCOL];
+  __shared__ double bsave[2][NF];
+  __shared__ double fac[NF];
+  __shared__ double cii;
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int sl = i >> 6, t = i & 63;
+  const int p0 = a.poff[sl], w = (a.poff[sl + 1] - p0) >> 6;
+  if (lane < NF) verts[lane] = lane < w ? a.pv[p0 + 64 * lane + t] : -1;
+  __syncthreads();
+  for (int idx = lane; idx < NF * NCOL; idx += 64) {
+    const int row = idx / NCOL, c = idx % NCOL;
+    const int vr = verts[row];
+    double v;
+    if (c >= KI) {
+      v = (c - KI == row) ? 1.0 : 0.0;
+    } else if (vr < 0) {
+      v = (c == row) ? 1.0 : 0.0;
+    } else if (c < NF) {
+      const int vc = verts[c];
+      v = vc < 0 ? 0.0 : lookup(a, vr, vc, AD_A);
+    } else {
+      v = lookup(a, vr, i, c == NF ? AD_BTX : AD_BTY);
+    }
+    if (c == NF || c == NF + 1) bsave[c - NF][row] = v;
+    M[row][c] = v;
+  }
+  if (lane == 0) cii = lookup(a, i, i, AD_C);
+  __syncthreads();
+  bool bad = false;
+  for (int p = 0; p < NF; ++p) {
+    const double piv = M[p][p];
+    if (!(piv > 0.0)) bad = true;
+    const double inv = 1.0 / piv;
+    __syncthreads();
+    for (int j = lane; j < NCOL; j += 64) M[p][j] *= inv;
+    for (int r = lane; r < NF; r += 64) fac[r] = M[r][p];
+    __syncthreads();
+    for (int idx = lane; idx < NF * NCOL; idx += 64) {
+      const int r = idx / NCOL, j = idx % NCOL;
+      if (r != p) M[r][j] -= fac[r] * M[p][j];
+    }
+    __syncthreads();
+  }
+  double part = 0.0;
+  for (int idx = lane; idx < 2 * NF; idx += 64) {
+    const int c = idx / NF, m = idx % NF;
+    part += bsave[c][m] * M[m][NF + c];
+  }
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+  const double S = cii - part;
+  const double sinv = 1.0 / S;
+  if (!(S < 0.0) || !isfinite(sinv)) bad = true;
+  if (bad && lane == 0) atomicMin(status, i);
+  if (lane < w) {
+    const long long e = p0 + 64LL * lane + t;
+    f.zx[e] = M[lane][NF];
+    f.zy[e] = M[lane][NF + 1];
+  }
+  if (lane == 0) f.invS[i] = sinv;
+  if (mode == AD_RAV) {
+    const int ao = a.pown[i];
+    if (lane < w) f.kr[p0 + 64LL * lane + t] = ao >= 0 ? M[ao][KI + lane] : 0.0;
+  } else {
+    const long long k0 = a.koff[sl];
+    for (int idx = lane; idx < w * w; idx += 64) {
+      const int r = idx / w, c = idx % w;
+      f.kfull[k0 + 64LL * idx + t] = M[r][KI + c];
+    }
+  }
+}
+
+// ---- RAV apply: one thread per patch, owned rows from the factored form ------
+// y_p = (r_p - z_x.r_x - z_y.r_y) / S, u_c,i = (K^{-1} r_c)_i - z_c,i y_p
+// (eq. 13: only the owned DoFs p_i and u_i are written).
+__global__ __launch_bounds__(256) void k_ad_rav(AdDev a, AdFactors f, const double* __restrict__ r,
+                                                double* __restrict__ x, double omega) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int nV = a.nV;
+  if (i >= nV) return;
+  const int p0 = a.poff[i >> 6], w = (a.poff[(i >> 6) + 1] - p0) >> 6;
+  const int t = i & 63;
+  const int ao = a.pown[i];
+  double tz = 0.0, ku = 0.0, kv = 0.0, zxo = 0.0, zyo = 0.0;
+  for (int k = 0; k < w; ++k) {
+    const long long e = p0 + 64LL * k + t;
+    const int v = a.pv[e];
+    if (v < 0) break;
+    const double rx = r[v], ry = r[nV + v];
+    const double zx = f.zx[e], zy = f.zy[e], kr = f.kr[e];
+    tz += zx * rx + zy * ry;
+    ku += kr * rx;
+    kv += kr * ry;
+    if (k == ao) { zxo = zx; zyo = zy; }
+  }
+  const double yp = (r[2 * nV + i] - tz) * f.invS[i];
+  x[2 * nV + i] += omega * yp;
+  if (ao >= 0) {
+    x[i] += omega * (ku - zxo * yp);
+    x[nV + i] += omega * (kv - zyo * yp);
+  }
+}
+
+// ---- AV / MV: a group of AD_NFMAX lanes per patch ----------------------------
+// Lane k holds patch vertex k: r_x, r_y of that vertex (AV: read from r; MV:
+// recomputed from b and the current x, eq. 15), y_c,k = (K^{-1} r_c)_k - z_c,k y_p.
+// AV writes the corrections per patch slot; MV adds them to x at once.
+constexpr int GRP = AD_NFMAX;
+constexpr int GPB = 64 / GRP;   // patches per 64-lane block
+
+template <bool MV>
+__global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int* __restrict__ order, int first,
+                                                 int count, const double* __restrict__ rb, double* __restrict__ x,
+                                                 double* __restrict__ yx, double* __restrict__ yy,
+                                                 double* __restrict__ yp_out, double omega) {
+  __shared__ double srx[GPB][GRP], sry[GPB][GRP];
+  const int g = threadIdx.x / GRP, k = threadIdx.x % GRP;
+  const int q = blockIdx.x * GPB + g;
+  const bool live = q < count;
+  const int i = live ? (order ? order[first + q] : first + q) : 0;
+  const int nV = a.nV;
+  const int sl = i >> 6, t = i & 63;
+  const int p0 = a.poff[sl], w = (a.poff[sl + 1] - p0) >> 6;
+  const long long e = p0 + 64LL * k + t;
+  const int v = (live && k < w) ? a.pv[e] : -1;
+  double rx = 0.0, ry = 0.0;
+  if (v >= 0) {
+    if (MV) {
+      const int e0 = a.soff[v >> 6], vw = (a.soff[(v >> 6) + 1] - e0) >> 6;
+      const int vt = v & 63;
+      double su = 0.0, sv = 0.0;
+      for (int m = 0; m < vw; ++m) {
+        const long long ee = e0 + 64LL * m + vt;
+        const int j = a.col[ee];
+        const double pj = x[2 * nV + j];
+        su += a.val[ee] * x[j] + a.val[AD_BTX * a.nnz + ee] * pj;
+        sv += a.val[ee] * x[nV + j] + a.val[AD_BTY * a.nnz + ee] * pj;
+      }
+      rx = rb[v] - su;
+      ry = rb[nV + v] - sv;
+    } else {
+      rx = rb[v];
+      ry = rb[nV + v];
+    }
+  }
+  srx[g][k] = rx;
+  sry[g][k] = ry;
+  double rp = 0.0;
+  if (live && k == 0) {
+    if (MV) {
+      const int e0 = a.soff[sl], iw = (a.soff[sl + 1] - e0) >> 6;
+      double sp = 0.0;
+      for (int m = 0; m < iw; ++m) {
+        const long long ee = e0 + 64LL * m + t;
+        const int j = a.col[ee];
+        sp += a.val[AD_BX * a.nnz + ee] * x[j] + a.val[AD_BY * a.nnz + ee] * x[nV + j] +
+              a.val[AD_C * a.nnz + ee] * x[2 * nV + j];
+      }
+      rp = rb[2 * nV + i] - sp;
+    } else {
+      rp = rb[2 * nV + i];
+    }
+  }
+  __syncthreads();
+  double zx = 0.0, zy = 0.0, kx = 0.0, ky = 0.0;
+  if (v >= 0) {
+    zx = f.zx[e];
+    zy = f.zy[e];
+    const long long k0 = a.koff[sl] + 64LL * (k * w) + t;
+    for (int m = 0; m < w; ++m) {
+      const double kv = f.kfull[k0 + 64LL * m];
+      kx += kv * srx[g][m];
+      ky += kv * sry[g][m];
+    }
+  }
+  double tz = zx * rx + zy * ry;
+  for (int o = GRP / 2; o > 0; o >>= 1) tz += __shfl_xor(tz, o, GRP);
+  rp = __shfl(rp, 0, GRP);
+  const double yp = live ? (rp - tz) * f.invS[i] : 0.0;
+  const double ux = kx - zx * yp, uy = ky - zy * yp;
+  if (MV) {
+    if (v >= 0) {
+      x[v] += omega * ux;
+      x[nV + v] += omega * uy;
+    }
+    if (live && k == 0) x[2 * nV + i] += omega * yp;
+  } else {
+    if (live && k < w) {
+      yx[e] = ux;
+      yy[e] = uy;
+    }
+    if (live && k == 0) yp_out[i] = yp;
+  }
+}
+
+// AV gather: every DoF adds the corrections of the patches that hold it.
+__global__ __launch_bounds__(256) void k_ad_av_gather(AdDev a, const int* __restrict__ tsoff,
+                                                      const int* __restrict__ tpos, const double* __restrict__ yx,
+                                                      const double* __restrict__ yy, const double* __restrict__ yp,
+                                                      double* __restrict__ x, double omega) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  const int nV = a.nV;
+  if (v >= nV) return;
+  const int e0 = tsoff[v >> 6], w = (tsoff[(v >> 6) + 1] - e0) >> 6;
+  const int t = v & 63;
+  double su = 0.0, sv = 0.0;
+  for (int k = 0; k < w; ++k) {
+    const int s = tpos[e0 + 64 * k + t];
+    if (s < 0) break;
+    su += yx[s];
+    sv += yy[s];
+  }
+  if (a.vmask[v] == 0) {
+    x[v] += omega * su;
+    x[nV + v] += omega * sv;
+  }
+  x[2 * nV + v] += omega * yp[v];
+}
+
+// ---- transfers ---------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ad_prolong(AdDev f, AdDev c, const int* __restrict__ ptr,
+                                                    const int* __restrict__ idx, const double* __restrict__ w,
+                                                    const double* __restrict__ xc, double* __restrict__ xf) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= f.nV) return;
+  double su = 0.0, sv = 0.0, sp = 0.0;
+  for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+    const int j = idx[k];
+    const double wk = w[k];
+    const double fm = c.vmask[j] ? 0.0 : wk;
+    su += fm * xc[j];
+    sv += fm * xc[c.nV + j];
+    sp += wk * xc[2 * c.nV + j];
+  }
+  if (f.vmask[i] == 0) {
+    xf[i] += su;
+    xf[f.nV + i] += sv;
+  }
+  xf[2 * f.nV + i] += sp;
+}
+
+// bc = P^T rf; xc = 0 and (rc != NULL) rc = bc, the residual of xc = 0.
+__global__ __launch_bounds__(256) void k_ad_restrict(AdDev f, AdDev c, const int* __restrict__ ptr,
+                                                     const int* __restrict__ idx, const double* __restrict__ w,
+                                                     const double* __restrict__ rf, double* __restrict__ bc,
+                                                     double* __restrict__ xc, double* __restrict__ rc) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= c.nV) return;
+  double su = 0.0, sv = 0.0, sp = 0.0;
+  for (int k = ptr[j]; k < ptr[j + 1]; ++k) {
+    const int i = idx[k];
+    const double wk = w[k];
+    const double fm = f.vmask[i] ? 0.0 : wk;
+    su += fm * rf[i];
+    sv += fm * rf[f.nV + i];
+    sp += wk * rf[2 * f.nV + i];
+  }
+  if (c.vmask[j]) { su = 0.0; sv = 0.0; }
+  const int n = c.nV;
+  bc[j] = su; bc[n + j] = sv; bc[2 * n + j] = sp;
+  xc[j] = 0.0; xc[n + j] = 0.0; xc[2 * n + j] = 0.0;
+  if (rc) { rc[j] = su; rc[n + j] = sv; rc[2 * n + j] = sp; }
+}
+
+__global__ __launch_bounds__(256) void k_ad_scale(const double* __restrict__ src, double alpha,
+                                                  double* __restrict__ dst, long long n) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i < n) dst[i] = alpha * src[i];
+}
+
+__global__ __launch_bounds__(256) void k_ad_owner(AdDev a, int* __restrict__ owner) {
+  const long long d = blockIdx.x * 256LL + threadIdx.x;
+  if (d >= 3LL * a.nV) return;
+  const int v = (int)(d % a.nV);
+  const int field = (int)(d / a.nV);
+  const int masked = (int)(field < 2) & (int)(a.vmask[v] != 0);
+  owner[d] = v - masked * (v + 1);   // -1 for masked velocity, else the vertex's patch
+}
+
+}  // namespace
+
+int ad_residual_blocks(int nV) { return (int)nblk(nV); }
+
+void ad_launch_residual(const AdDev& a, const double* x, const double* b, double* r, double* partials,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_ad_residual, dim3(nblk(a.nV)), dim3(256), 0, s, a, x, b, r, partials);
+}
+
+void ad_launch_factor(const AdDev& a, int mode, AdFactors f, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_ad_factor, dim3((unsigned)a.nV), dim3(64), 0, s, a, mode, f, status);
+}
+
+void ad_launch_rav(const AdDev& a, AdFactors f, const double* r, double* x, double omega, hipStream_t s) {
+  hipLaunchKernelGGL(k_ad_rav, dim3(nblk(a.nV)), dim3(256), 0, s, a, f, r, x, omega);
+}
+
+void ad_launch_av(const AdDev& a, AdFactors f, const int* tsoff, const int* tpos, const double* r, double* yx,
+                  double* yy, double* yp, double* x, double omega, hipStream_t s) {
+  hipLaunchKernelGGL((k_ad_group<false>), dim3(nblk(a.nV, GPB)), dim3(64), 0, s, a, f, (const int*)nullptr, 0,
+                     a.nV, r, (double*)nullptr, yx, yy, yp, omega);
+  hipLaunchKernelGGL(k_ad_av_gather, dim3(nblk(a.nV)), dim3(256), 0, s, a, tsoff, tpos, yx, yy, yp, x, omega);
+}
+
+void ad_launch_mv(const AdDev& a, AdFactors f, const int* order, int first, int count, const double* b, double* x,
+                  double omega, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL((k_ad_group<true>), dim3(nblk(count, GPB)), dim3(64), 0, s, a, f, order, first, count, b, x,
+                     (double*)nullptr, (double*)nullptr, (double*)nullptr, omega);
+}
+
+void ad_launch_prolong(const AdDev& f, const AdDev& c, const int* ptr, const int* idx, const double* w,
+                       const double* xc, double* xf, hipStream_t s) {
+  hipLaunchKernelGGL(k_ad_prolong, dim3(nblk(f.nV)), dim3(256), 0, s, f, c, ptr, idx, w, xc, xf);
+}
+
+void ad_launch_restrict(const AdDev& f, const AdDev& c, const int* ptr, const int* idx, const double* w,
+                        const double* rf, double* bc, double* xc, double* rc, hipStream_t s) {
+  hipLaunchKernelGGL(k_ad_restrict, dim3(nblk(c.nV)), dim3(256), 0, s, f, c, ptr, idx, w, rf, bc, xc, rc);
+}
+
+void ad_launch_scale(const double* src, double alpha, double* dst, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_ad_scale, dim3(nblk(n)), dim3(256), 0, s, src, alpha, dst, n);
+}
+
+void ad_launch_owner(const AdDev& a, int* owner, hipStream_t s) {
+  hipLaunchKernelGGL(k_ad_owner, dim3(nblk(3LL * a.nV)), dim3(256), 0, s, a, owner);
+}
+
+}  // namespace rav

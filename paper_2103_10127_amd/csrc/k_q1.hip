@@ -10,37 +10,13 @@
 
 #include "rav_fields.h"
 #include "rav_q1.h"
+#include "rav_q1_unit.h"
 
 namespace rav {
 
 namespace {
 
-__host__ __device__ constexpr int bit(int a, int d) { return (a >> d) & 1; }
-__host__ __device__ constexpr double m1(int a, int b) { return a == b ? 1.0 / 3.0 : 1.0 / 6.0; }
-__host__ __device__ constexpr double s1(int a, int b) { return a == b ? 1.0 : -1.0; }
-__host__ __device__ constexpr double d1(int a) { return a == 0 ? -0.5 : 0.5; }
-
-// int grad phi_a . grad phi_b over the unit cell
-template <int DIM>
-__host__ __device__ constexpr double kunit(int a, int b) {
-  double s = 0.0;
-  for (int c = 0; c < DIM; ++c) {
-    double t = s1(bit(a, c), bit(b, c));
-    for (int d = 0; d < DIM; ++d)
-      if (d != c) t *= m1(bit(a, d), bit(b, d));
-    s += t;
-  }
-  return s;
-}
-
-// int d_c phi_a psi_k over the unit cell
-template <int DIM>
-__host__ __device__ constexpr double bunit(int c, int a, int k) {
-  double t = d1(bit(a, c));
-  for (int d = 0; d < DIM; ++d)
-    if (d != c) t *= m1(bit(a, d), bit(k, d));
-  return t;
-}
+using namespace q1unit;
 
 template <int DIM>
 __device__ __forceinline__ void decode(const Q1Dev& q, long long v, int* c) {

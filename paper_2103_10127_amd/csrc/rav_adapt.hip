@@ -1,0 +1,1200 @@
+// Host driver of stabilized Q1-Q1 on adaptively refined quadtree grids with
+// hanging nodes (Sec. 2, eqs. 5-8 and Fig. 2; Sec. 4.1, Table 1): the grid
+// topology, the hanging-node constraints, the conforming operator of every
+// grid (assembled once on the host), the Vanka patches, the grid transfers and
+// the coarse direct solve are set up here; smoothing (RAV, AV, MV), residuals,
+// transfers and V-cycles run in the kernels of k_adapt.hip.  The public entry
+// points of rav.h route here for contexts made by rav_create_adaptive.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "rav_adapt.h"
+#include "rav_ctx.h"
+#include "rav_q1_unit.h"
+
+using namespace rav;
+
+struct rav_ad_state {
+  struct Level {
+    AdDev dev{};
+    int nV = 0;
+    long long nfree = 0;
+    unsigned char* vmask = nullptr;
+    int *soff = nullptr, *col = nullptr;
+    double* val = nullptr;
+    int *poff = nullptr, *pv = nullptr, *pown = nullptr;
+    long long* koff = nullptr;
+    AdFactors fac{};
+    int *tsoff = nullptr, *tpos = nullptr;
+    double *yx = nullptr, *yy = nullptr, *yp = nullptr;
+    int* order = nullptr;               // MV: patches colour-major
+    std::vector<int> cstart;            // MV: colour c is order[cstart[c] .. cstart[c+1])
+    int *pptr = nullptr, *pidx = nullptr;   // prolongation from the next coarser grid (rows: this grid)
+    double* pw = nullptr;
+    int *rptr = nullptr, *ridx = nullptr;   // restriction to the next coarser grid (rows: that grid)
+    double* rw = nullptr;
+    double *x = nullptr, *b = nullptr, *r = nullptr, *partials = nullptr;
+    int nres = 0;
+    long long pnnz = 0, kfull_n = 0;
+    // host copies for the patch getters
+    std::vector<int> h_poff, h_pv, h_pown;
+  };
+  std::vector<Level> lv;
+  double* Minv = nullptr;
+  long long nb = 0;
+  double* blid = nullptr;   // finest grid: lid lifting for a lid velocity of 1
+  int mode = AD_RAV;
+  bool have_factors = false;
+};
+
+#define ACK(expr)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                  \
+      return e_ == hipErrorOutOfMemory ? RAV_ENOMEM : RAV_EDEVICE;                   \
+    }                                                                                \
+  } while (0)
+
+namespace {
+
+using Level = rav_ad_state::Level;
+
+struct Wt {
+  int v;
+  double w;
+};
+
+// ---- host set-up ---------------------------------------------------------------
+// Grid topology: regular vertices, hanging nodes and the regular-vertex weights
+// of every leaf corner (a hanging node is the mean of the two endpoints of the
+// coarse edge whose midpoint it is, applied recursively).
+struct Topo {
+  long long M = 0;
+  const int* leaf = nullptr;   // (x0, y0, s) per leaf
+  long long nl = 0;
+  std::vector<long long> reg, hang, ha, hb;
+  std::vector<int> cw_ptr;     // 4 nl + 1
+  std::vector<Wt> cw;
+  std::vector<std::vector<Wt>> hmemo;
+  std::vector<char> hstate;
+  std::string err;
+
+  long long key(long long x, long long y) const { return y * (M + 1) + x; }
+  int nV() const { return (int)reg.size(); }
+  int find_reg(long long k) const {
+    auto it = std::lower_bound(reg.begin(), reg.end(), k);
+    return (it != reg.end() && *it == k) ? (int)(it - reg.begin()) : -1;
+  }
+  int find_hang(long long k) const {
+    auto it = std::lower_bound(hang.begin(), hang.end(), k);
+    return (it != hang.end() && *it == k) ? (int)(it - hang.begin()) : -1;
+  }
+  static void merge_half(const std::vector<Wt>& a, const std::vector<Wt>& b, std::vector<Wt>& out) {
+    out.clear();
+    size_t i = 0, j = 0;
+    while (i < a.size() || j < b.size()) {
+      if (j == b.size() || (i < a.size() && a[i].v < b[j].v)) { out.push_back({a[i].v, 0.5 * a[i].w}); ++i; }
+      else if (i == a.size() || b[j].v < a[i].v) { out.push_back({b[j].v, 0.5 * b[j].w}); ++j; }
+      else { out.push_back({a[i].v, 0.5 * a[i].w + 0.5 * b[j].w}); ++i; ++j; }
+    }
+  }
+  bool weights(long long k, std::vector<Wt>& out, int depth = 0) {
+    const int r = find_reg(k);
+    if (r >= 0) { out.assign(1, Wt{r, 1.0}); return true; }
+    const int h = find_hang(k);
+    if (h < 0 || depth > 64) { err = "a leaf corner is neither a vertex nor a hanging node"; return false; }
+    if (hstate[h] == 2) { out = hmemo[h]; return true; }
+    if (hstate[h] == 1) { err = "cyclic hanging-node constraints"; return false; }
+    hstate[h] = 1;
+    std::vector<Wt> wa, wb;
+    if (!weights(ha[h], wa, depth + 1) || !weights(hb[h], wb, depth + 1)) return false;
+    merge_half(wa, wb, out);
+    hmemo[h] = out;
+    hstate[h] = 2;
+    return true;
+  }
+
+  bool build(const int* leaves, long long n, long long Mlat) {
+    leaf = leaves;
+    nl = n;
+    M = Mlat;
+    std::vector<long long> corners(4 * nl), mids(4 * nl);
+    for (long long e = 0; e < nl; ++e) {
+      const long long x0 = leaf[3 * e], y0 = leaf[3 * e + 1], s = leaf[3 * e + 2], h = s / 2;
+      for (int a = 0; a < 4; ++a) corners[4 * e + a] = key(x0 + (a & 1) * s, y0 + (a >> 1) * s);
+      mids[4 * e + 0] = key(x0 + h, y0);
+      mids[4 * e + 1] = key(x0 + h, y0 + s);
+      mids[4 * e + 2] = key(x0, y0 + h);
+      mids[4 * e + 3] = key(x0 + s, y0 + h);
+    }
+    std::vector<long long> cs = corners, ms = mids;
+    std::sort(cs.begin(), cs.end());
+    cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+    std::sort(ms.begin(), ms.end());
+    ms.erase(std::unique(ms.begin(), ms.end()), ms.end());
+    std::set_intersection(cs.begin(), cs.end(), ms.begin(), ms.end(), std::back_inserter(hang));
+    std::set_difference(cs.begin(), cs.end(), hang.begin(), hang.end(), std::back_inserter(reg));
+    // 2:1 balance: no corner lies at a quarter point of a leaf edge
+    for (long long e = 0; e < nl; ++e) {
+      const long long x0 = leaf[3 * e], y0 = leaf[3 * e + 1], s = leaf[3 * e + 2];
+      if (s < 4) continue;
+      for (int f = 1; f <= 3; f += 2) {
+        const long long q = s * f / 4;
+        const long long pts[4] = {key(x0 + q, y0), key(x0 + q, y0 + s), key(x0, y0 + q), key(x0 + s, y0 + q)};
+        for (long long p : pts)
+          if (std::binary_search(cs.begin(), cs.end(), p)) { err = "grid is not 2:1 balanced"; return false; }
+      }
+    }
+    ha.assign(hang.size(), -1);
+    hb.assign(hang.size(), -1);
+    for (long long e = 0; e < nl; ++e) {
+      const long long x0 = leaf[3 * e], y0 = leaf[3 * e + 1], s = leaf[3 * e + 2];
+      const long long ends[4][2] = {{key(x0, y0), key(x0 + s, y0)},
+                                    {key(x0, y0 + s), key(x0 + s, y0 + s)},
+                                    {key(x0, y0), key(x0, y0 + s)},
+                                    {key(x0 + s, y0), key(x0 + s, y0 + s)}};
+      for (int m = 0; m < 4; ++m) {
+        const int h = find_hang(mids[4 * e + m]);
+        if (h >= 0) { ha[h] = ends[m][0]; hb[h] = ends[m][1]; }
+      }
+    }
+    hmemo.assign(hang.size(), {});
+    hstate.assign(hang.size(), 0);
+    cw_ptr.assign(4 * nl + 1, 0);
+    cw.clear();
+    std::vector<Wt> tmp;
+    for (long long c = 0; c < 4 * nl; ++c) {
+      if (!weights(corners[c], tmp)) return false;
+      cw.insert(cw.end(), tmp.begin(), tmp.end());
+      cw_ptr[c + 1] = (int)cw.size();
+    }
+    return true;
+  }
+  void leaf_verts(long long e, std::vector<int>& out) const {
+    out.clear();
+    for (int c = cw_ptr[4 * e]; c < cw_ptr[4 * e + 4]; ++c) out.push_back(cw[c].v);
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+  }
+};
+
+// Host image of one level, uploaded as a whole.
+struct HostLevel {
+  int nV = 0;
+  std::vector<unsigned char> vmask;
+  std::vector<std::vector<int>> nbr;   // structural columns of every vertex row
+  std::vector<int> soff, col;
+  std::vector<double> val;             // 6 planes
+  long long nnz = 0;
+  std::vector<double> blid;            // lid lifting (finest grid)
+  // patches
+  std::vector<std::vector<int>> pall;  // all vertices of patch i (MV colouring)
+  std::vector<int> poff, pv, pown;
+  std::vector<long long> koff;
+  long long pnnz = 0;
+  std::vector<int> tsoff, tpos, order, cstart;
+  // prolongation from the next coarser grid
+  std::vector<int> pptr, pidx, rptr, ridx;
+  std::vector<double> pwt, rwt;
+};
+
+std::vector<int> sell_offsets(int n, const std::vector<int>& len) {
+  const int ns = (n + AD_SLICE - 1) / AD_SLICE;
+  std::vector<int> off(ns + 1, 0);
+  for (int s = 0; s < ns; ++s) {
+    int w = 0;
+    for (int t = 0; t < AD_SLICE && s * AD_SLICE + t < n; ++t) w = std::max(w, len[s * AD_SLICE + t]);
+    off[s + 1] = off[s] + AD_SLICE * w;
+  }
+  return off;
+}
+
+long long sell_slot(const std::vector<int>& off, int v, int k) {
+  return off[v / AD_SLICE] + (long long)AD_SLICE * k + (v % AD_SLICE);
+}
+
+// Conforming operator L = T^T L_corners T of one grid (rows and columns of
+// masked velocity zero) and, with `lid`, the lifting b = -L_all[:, masked] u_D
+// of the lid velocity u_x = 1 on the top side strictly between the corners.
+bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, std::string& err) {
+  const int nV = g.nV();
+  const long long M = g.M;
+  H.nV = nV;
+  H.vmask.assign(nV, 0);
+  std::vector<unsigned char> is_lid(nV, 0);
+  for (int v = 0; v < nV; ++v) {
+    const long long x = g.reg[v] % (M + 1), y = g.reg[v] / (M + 1);
+    H.vmask[v] = (x == 0 || y == 0 || x == M || y == M) ? 1 : 0;
+    is_lid[v] = (y == M && x > 0 && x < M) ? 1 : 0;
+  }
+  H.nbr.assign(nV, {});
+  std::vector<int> ve;
+  for (long long e = 0; e < g.nl; ++e) {
+    g.leaf_verts(e, ve);
+    for (int i : ve) H.nbr[i].insert(H.nbr[i].end(), ve.begin(), ve.end());
+  }
+  std::vector<int> len(nV);
+  for (int v = 0; v < nV; ++v) {
+    auto& r = H.nbr[v];
+    std::sort(r.begin(), r.end());
+    r.erase(std::unique(r.begin(), r.end()), r.end());
+    len[v] = (int)r.size();
+  }
+  H.soff = sell_offsets(nV, len);
+  if ((long long)H.soff.back() >= (long long)INT_MAX / 2) { err = "grid too large"; return false; }
+  H.nnz = H.soff.back();
+  H.col.assign(H.nnz, 0);
+  H.val.assign(6 * H.nnz, 0.0);
+  for (int v = 0; v < nV; ++v) {
+    const int w = (H.soff[v / AD_SLICE + 1] - H.soff[v / AD_SLICE]) / AD_SLICE;
+    for (int k = 0; k < w; ++k) H.col[sell_slot(H.soff, v, k)] = k < len[v] ? H.nbr[v][k] : v;
+  }
+  double Ar[4][4], Br[2][4][4], Cr[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      Ar[a][b] = q1unit::kunit<2>(a, b);
+      Cr[a][b] = q1unit::kunit<2>(a, b);
+      for (int c = 0; c < 2; ++c) Br[c][a][b] = q1unit::bunit<2>(c, a, b);
+    }
+  const long long P = H.nnz;
+  for (long long e = 0; e < g.nl; ++e) {
+    const double h = (double)g.leaf[3 * e + 2] / (double)M;
+    const double sB = -h, sC = -beta * 2.0 * h * h;
+    for (int a = 0; a < 4; ++a)
+      for (int ca = g.cw_ptr[4 * e + a]; ca < g.cw_ptr[4 * e + a + 1]; ++ca) {
+        const int i = g.cw[ca].v;
+        const double wi = g.cw[ca].w;
+        const auto& row = H.nbr[i];
+        for (int b = 0; b < 4; ++b)
+          for (int cb = g.cw_ptr[4 * e + b]; cb < g.cw_ptr[4 * e + b + 1]; ++cb) {
+            const int j = g.cw[cb].v;
+            const double ww = wi * g.cw[cb].w;
+            const int k = (int)(std::lower_bound(row.begin(), row.end(), j) - row.begin());
+            const long long s = sell_slot(H.soff, i, k);
+            H.val[AD_A * P + s] += ww * eta * Ar[a][b];
+            H.val[AD_BTX * P + s] += ww * sB * Br[0][a][b];
+            H.val[AD_BTY * P + s] += ww * sB * Br[1][a][b];
+            H.val[AD_BX * P + s] += ww * sB * Br[0][b][a];
+            H.val[AD_BY * P + s] += ww * sB * Br[1][b][a];
+            H.val[AD_C * P + s] += ww * sC * Cr[a][b];
+          }
+      }
+  }
+  if (lid) {
+    H.blid.assign(3LL * nV, 0.0);
+    for (int i = 0; i < nV; ++i)
+      for (int k = 0; k < len[i]; ++k) {
+        const int j = H.nbr[i][k];
+        if (!is_lid[j]) continue;
+        const long long s = sell_slot(H.soff, i, k);
+        if (!H.vmask[i]) H.blid[i] -= H.val[AD_A * P + s];
+        H.blid[2LL * nV + i] -= H.val[AD_BX * P + s];
+      }
+  }
+  for (int i = 0; i < nV; ++i)
+    for (int k = 0; k < len[i]; ++k) {
+      const int j = H.nbr[i][k];
+      const long long s = sell_slot(H.soff, i, k);
+      if (H.vmask[i]) { H.val[AD_A * P + s] = 0.0; H.val[AD_BTX * P + s] = 0.0; H.val[AD_BTY * P + s] = 0.0; }
+      if (H.vmask[j]) { H.val[AD_A * P + s] = 0.0; H.val[AD_BX * P + s] = 0.0; H.val[AD_BY * P + s] = 0.0; }
+    }
+  return true;
+}
+
+// Vanka patches (Sec. 3): patch i holds p_i and the free velocity at the
+// vertices of the leaves around vertex i (hanging corners through their
+// constraining vertices); RAV owns p_i and the velocity at i.  MV order: greedy
+// colouring in patch order, a patch taking the smallest colour of no earlier
+// patch whose vertex set meets the row pattern of its own vertices.
+bool build_patches(const Topo& g, HostLevel& H, std::string& err) {
+  const int nV = H.nV;
+  std::vector<std::vector<int>> touch(nV);
+  for (long long e = 0; e < g.nl; ++e) {
+    const long long x0 = g.leaf[3 * e], y0 = g.leaf[3 * e + 1], s = g.leaf[3 * e + 2];
+    for (int a = 0; a < 4; ++a) {
+      const int r = g.find_reg(g.key(x0 + (a & 1) * s, y0 + (a >> 1) * s));
+      if (r >= 0) touch[r].push_back((int)e);
+    }
+  }
+  H.pall.assign(nV, {});
+  std::vector<std::vector<int>> pfree(nV);
+  std::vector<int> len(nV);
+  for (int i = 0; i < nV; ++i) {
+    auto& V = H.pall[i];
+    for (int e : touch[i])
+      for (int c = g.cw_ptr[4 * e]; c < g.cw_ptr[4 * e + 4]; ++c) V.push_back(g.cw[c].v);
+    std::sort(V.begin(), V.end());
+    V.erase(std::unique(V.begin(), V.end()), V.end());
+    for (int v : V)
+      if (!H.vmask[v]) pfree[i].push_back(v);
+    len[i] = (int)pfree[i].size();
+    if (len[i] > AD_NFMAX) { err = "a patch has more than 16 free velocity vertices"; return false; }
+  }
+  H.poff = sell_offsets(nV, len);
+  H.pnnz = H.poff.back();
+  H.pv.assign(H.pnnz, -1);
+  H.pown.assign(nV, -1);
+  const int ns = (int)H.poff.size() - 1;
+  H.koff.assign(ns + 1, 0);
+  for (int s = 0; s < ns; ++s) {
+    const long long w = (H.poff[s + 1] - H.poff[s]) / AD_SLICE;
+    H.koff[s + 1] = H.koff[s] + AD_SLICE * w * w;
+  }
+  std::vector<std::vector<int>> tslots(nV);
+  for (int i = 0; i < nV; ++i)
+    for (int k = 0; k < len[i]; ++k) {
+      const int v = pfree[i][k];
+      const long long slot = sell_slot(H.poff, i, k);
+      H.pv[slot] = v;
+      if (v == i) H.pown[i] = k;
+      tslots[v].push_back((int)slot);
+    }
+  std::vector<int> tl(nV);
+  for (int v = 0; v < nV; ++v) tl[v] = (int)tslots[v].size();
+  H.tsoff = sell_offsets(nV, tl);
+  H.tpos.assign(H.tsoff.back(), -1);
+  for (int v = 0; v < nV; ++v)
+    for (int k = 0; k < tl[v]; ++k) H.tpos[sell_slot(H.tsoff, v, k)] = tslots[v][k];
+  // MV colouring
+  std::vector<std::vector<int>> holders(nV);   // patches whose vertex set holds v
+  for (int i = 0; i < nV; ++i)
+    for (int v : H.pall[i]) holders[v].push_back(i);
+  std::vector<int> colour(nV, -1), stamp(nV, -1);
+  int ncol = 0;
+  for (int i = 0; i < nV; ++i) {
+    uint64_t banned = 0;
+    for (int v : H.pall[i])
+      for (int u : H.nbr[v]) {
+        if (stamp[u] == i) continue;
+        stamp[u] = i;
+        for (int q : holders[u])
+          if (q < i) banned |= 1ull << colour[q];
+      }
+    int c = 0;
+    while (c < 64 && ((banned >> c) & 1ull)) ++c;
+    if (c >= 64) { err = "MV colouring needs more than 64 colours"; return false; }
+    colour[i] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  H.cstart.assign(ncol + 1, 0);
+  for (int i = 0; i < nV; ++i) ++H.cstart[colour[i] + 1];
+  for (int c = 0; c < ncol; ++c) H.cstart[c + 1] += H.cstart[c];
+  H.order.assign(nV, 0);
+  std::vector<int> fill(H.cstart.begin(), H.cstart.end() - 1);
+  for (int i = 0; i < nV; ++i) H.order[fill[colour[i]]++] = i;
+  return true;
+}
+
+// Transfer from the coarse grid: the coarse function at the fine vertices
+// (bilinear on a coarse leaf that contains the vertex, hanging coarse corners
+// through their constraints), and its transpose.
+bool build_transfer(const Topo& fine, const Topo& coarse, HostLevel& H, int nVc, std::string& err) {
+  const long long M = fine.M;
+  std::unordered_map<long long, int> cells;
+  cells.reserve((size_t)coarse.nl * 2);
+  int smin = INT_MAX;
+  auto ckey = [&](long long x0, long long y0, long long s) { return ((y0 * (M + 1)) + x0) * 64 + __builtin_ctzll(s); };
+  for (long long e = 0; e < coarse.nl; ++e) {
+    cells[ckey(coarse.leaf[3 * e], coarse.leaf[3 * e + 1], coarse.leaf[3 * e + 2])] = (int)e;
+    smin = std::min(smin, coarse.leaf[3 * e + 2]);
+  }
+  // nesting: every fine leaf lies in a coarse leaf at least as large
+  for (long long e = 0; e < fine.nl; ++e) {
+    const long long x0 = fine.leaf[3 * e], y0 = fine.leaf[3 * e + 1], s = fine.leaf[3 * e + 2];
+    bool found = false;
+    for (long long sc = s; sc <= M && !found; sc *= 2)
+      found = cells.count(ckey(x0 / sc * sc, y0 / sc * sc, sc)) > 0;
+    if (!found) { err = "grids are not nested (each grid must refine the previous one)"; return false; }
+  }
+  const int nV = fine.nV();
+  H.pptr.assign(nV + 1, 0);
+  H.pidx.clear();
+  H.pwt.clear();
+  std::vector<Wt> row;
+  for (int i = 0; i < nV; ++i) {
+    const long long px = fine.reg[i] % (M + 1), py = fine.reg[i] / (M + 1);
+    int li = -1;
+    long long x0 = 0, y0 = 0, sc = smin;
+    for (; sc <= M; sc *= 2) {
+      x0 = std::min(px / sc * sc, M - sc);
+      y0 = std::min(py / sc * sc, M - sc);
+      auto it = cells.find(ckey(x0, y0, sc));
+      if (it != cells.end()) { li = it->second; break; }
+    }
+    if (li < 0) { err = "a fine vertex lies in no coarse leaf"; return false; }
+    const double tx = (double)(px - x0) / (double)sc, ty = (double)(py - y0) / (double)sc;
+    row.clear();
+    for (int a = 0; a < 4; ++a) {
+      const double w = ((a & 1) ? tx : 1.0 - tx) * ((a >> 1) ? ty : 1.0 - ty);
+      if (w == 0.0) continue;
+      for (int c = coarse.cw_ptr[4 * li + a]; c < coarse.cw_ptr[4 * li + a + 1]; ++c) {
+        const int j = coarse.cw[c].v;
+        auto it = std::find_if(row.begin(), row.end(), [&](const Wt& t) { return t.v == j; });
+        if (it == row.end()) row.push_back({j, w * coarse.cw[c].w});
+        else it->w += w * coarse.cw[c].w;
+      }
+    }
+    std::sort(row.begin(), row.end(), [](const Wt& p, const Wt& q) { return p.v < q.v; });
+    for (const Wt& t : row) { H.pidx.push_back(t.v); H.pwt.push_back(t.w); }
+    H.pptr[i + 1] = (int)H.pidx.size();
+  }
+  H.rptr.assign(nVc + 1, 0);
+  for (int j : H.pidx) ++H.rptr[j + 1];
+  for (int j = 0; j < nVc; ++j) H.rptr[j + 1] += H.rptr[j];
+  H.ridx.assign(H.pidx.size(), 0);
+  H.rwt.assign(H.pidx.size(), 0.0);
+  std::vector<int> fill(H.rptr.begin(), H.rptr.end() - 1);
+  for (int i = 0; i < nV; ++i)
+    for (int k = H.pptr[i]; k < H.pptr[i + 1]; ++k) {
+      const int j = H.pidx[k];
+      H.ridx[fill[j]] = i;
+      H.rwt[fill[j]] = H.pwt[k];
+      ++fill[j];
+    }
+  return true;
+}
+
+bool check_leaves(const int* lv, long long n, long long M, std::string& err) {
+  std::unordered_set<long long> seen;
+  seen.reserve((size_t)n * 2);
+  long long area = 0;
+  auto k3 = [&](long long x0, long long y0, long long s) { return ((y0 * (M + 1)) + x0) * 64 + __builtin_ctzll(s); };
+  for (long long e = 0; e < n; ++e) {
+    const long long x0 = lv[3 * e], y0 = lv[3 * e + 1], s = lv[3 * e + 2];
+    if (s < 2 || (s & (s - 1)) || x0 < 0 || y0 < 0 || x0 % s || y0 % s || x0 + s > M || y0 + s > M) {
+      err = "leaf " + std::to_string(e) + " is not an aligned cell of even power-of-two size inside the square";
+      return false;
+    }
+    if (!seen.insert(k3(x0, y0, s)).second) { err = "duplicate leaf " + std::to_string(e); return false; }
+    area += s * s;
+  }
+  for (long long e = 0; e < n; ++e) {   // no leaf inside another
+    const long long x0 = lv[3 * e], y0 = lv[3 * e + 1], s = lv[3 * e + 2];
+    for (long long sc = 2 * s; sc <= M; sc *= 2)
+      if (seen.count(k3(x0 / sc * sc, y0 / sc * sc, sc))) { err = "overlapping leaves"; return false; }
+  }
+  if (area != M * M) { err = "leaves do not tile the unit square"; return false; }
+  return true;
+}
+
+template <class T>
+hipError_t upload(T** d, const std::vector<T>& h) {
+  *d = nullptr;
+  if (h.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)d, sizeof(T) * h.size());
+  if (e == hipSuccess) e = hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+rav_ad_state* st(const rav_ctx* ctx) { return ctx->ad; }
+
+rav_status check_lv(const rav_ctx* ctx, int level, bool smoothed) {
+  if (level < 0 || level >= (int)st(ctx)->lv.size()) return RAV_EINVAL;
+  if (smoothed && level == 0) return RAV_EINVAL;
+  return RAV_OK;
+}
+
+// ---- cycle -------------------------------------------------------------------
+void residual(rav_ctx* ctx, int l, bool with_norm) {
+  Level& L = st(ctx)->lv[l];
+  ad_launch_residual(L.dev, L.x, L.b, L.r, with_norm ? L.partials : nullptr, ctx->stream);
+  if (with_norm) launch_norm_finalize(L.partials, 0, L.nres, ctx->d_norm, ctx->h_norm_dev, ctx->stream);
+}
+
+void apply(rav_ctx* ctx, int l) {
+  Level& L = st(ctx)->lv[l];
+  const rav_problem_desc& D = ctx->desc;
+  if (D.smoother == RAV_SMOOTHER_AV)
+    ad_launch_av(L.dev, L.fac, L.tsoff, L.tpos, L.r, L.yx, L.yy, L.yp, L.x, D.omega, ctx->stream);
+  else
+    ad_launch_rav(L.dev, L.fac, L.r, L.x, D.omega, ctx->stream);
+}
+
+// RAV (eq. 13) and AV (eq. 12) from one residual each sweep (r_valid: L.r
+// already holds b - L x); MV (eq. 11) colour by colour, each patch recomputing
+// its residual rows (eq. 15).
+void smooth(rav_ctx* ctx, int l, int sweeps, bool r_valid) {
+  Level& L = st(ctx)->lv[l];
+  const rav_problem_desc& D = ctx->desc;
+  for (int k = 0; k < sweeps; ++k) {
+    if (D.smoother == RAV_SMOOTHER_MV) {
+      for (size_t c = 0; c + 1 < L.cstart.size(); ++c)
+        ad_launch_mv(L.dev, L.fac, L.order, L.cstart[c], L.cstart[c + 1] - L.cstart[c], L.b, L.x, D.omega,
+                     ctx->stream);
+      continue;
+    }
+    if (!(k == 0 && r_valid)) residual(ctx, l, false);
+    apply(ctx, l);
+  }
+}
+
+void coarse_solve(rav_ctx* ctx) {
+  rav_ad_state* S = st(ctx);
+  Level& L0 = S->lv[0];
+  launch_coarse_gemv(S->Minv, S->nb, 3LL * L0.nV, L0.b, L0.x, ctx->stream);
+}
+
+void restrict_to(rav_ctx* ctx, int l, double* rc) {
+  Level& L = st(ctx)->lv[l];
+  Level& C = st(ctx)->lv[l - 1];
+  ad_launch_restrict(L.dev, C.dev, L.rptr, L.ridx, L.rw, L.r, C.b, C.x, rc, ctx->stream);
+}
+
+void prolong(rav_ctx* ctx, int l) {
+  Level& L = st(ctx)->lv[l];
+  Level& C = st(ctx)->lv[l - 1];
+  ad_launch_prolong(L.dev, C.dev, L.pptr, L.pidx, L.pw, C.x, L.x, ctx->stream);
+}
+
+// V-cycle on level l (Sec. 2, Fig. 1); r_valid: L.r holds the residual of
+// the current x (coarse levels: restriction writes r_c = b_c for x_c = 0).
+void vcycle(rav_ctx* ctx, int l, bool r_valid) {
+  if (l == 0) {
+    coarse_solve(ctx);
+    return;
+  }
+  smooth(ctx, l, ctx->desc.nu_pre, r_valid);
+  if (ctx->desc.nu_pre > 0 || !r_valid) residual(ctx, l, false);
+  restrict_to(ctx, l, l - 1 > 0 ? st(ctx)->lv[l - 1].r : nullptr);
+  vcycle(ctx, l - 1, true);
+  prolong(ctx, l);
+  smooth(ctx, l, ctx->desc.nu_post, false);
+}
+
+void issue_cycle(rav_ctx* ctx) {
+  const int lf = (int)st(ctx)->lv.size() - 1;
+  vcycle(ctx, lf, true);
+  residual(ctx, lf, true);
+}
+
+rav_status need_factors(rav_ctx* ctx) {
+  if (!st(ctx)->have_factors) return rav_set_error(ctx, RAV_EINVAL, "rav_factor_patches has not been called");
+  return RAV_OK;
+}
+
+// Dense coarse matrix (masked rows and columns replaced by the identity) with
+// the zero-mean pressure border, inverted once on the device.
+rav_status build_coarse(rav_ctx* ctx, const HostLevel& H) {
+  rav_ad_state* S = st(ctx);
+  const long long n0 = 3LL * H.nV, nb = n0 + 1, nV = H.nV, P = H.nnz;
+  S->nb = nb;
+  std::vector<double> M((size_t)(nb * nb), 0.0);
+  for (int i = 0; i < H.nV; ++i) {
+    const int w = (int)H.nbr[i].size();
+    for (int k = 0; k < w; ++k) {
+      const int j = H.nbr[i][k];
+      const long long s = sell_slot(H.soff, i, k);
+      M[(size_t)(i * nb + j)] += H.val[AD_A * P + s];
+      M[(size_t)((nV + i) * nb + nV + j)] += H.val[AD_A * P + s];
+      M[(size_t)(i * nb + 2 * nV + j)] += H.val[AD_BTX * P + s];
+      M[(size_t)((nV + i) * nb + 2 * nV + j)] += H.val[AD_BTY * P + s];
+      M[(size_t)((2 * nV + i) * nb + j)] += H.val[AD_BX * P + s];
+      M[(size_t)((2 * nV + i) * nb + nV + j)] += H.val[AD_BY * P + s];
+      M[(size_t)((2 * nV + i) * nb + 2 * nV + j)] += H.val[AD_C * P + s];
+    }
+    if (H.vmask[i]) {
+      M[(size_t)(i * nb + i)] = 1.0;
+      M[(size_t)((nV + i) * nb + nV + i)] = 1.0;
+    }
+  }
+  for (long long j = 2 * nV; j < n0; ++j) {
+    M[(size_t)(n0 * nb + j)] = 1.0;
+    M[(size_t)(j * nb + n0)] = 1.0;
+  }
+  ACK(hipMalloc((void**)&S->Minv, sizeof(double) * nb * nb));
+  ACK(hipMemcpy(S->Minv, M.data(), sizeof(double) * nb * nb, hipMemcpyHostToDevice));
+  double** dM = nullptr;
+  int *piv = nullptr, *perm = nullptr, *pst = nullptr;
+  double *colk = nullptr, *Rs = nullptr;
+  const int big = INT_MAX;
+  ACK(hipMalloc((void**)&dM, sizeof(double*)));
+  ACK(hipMalloc((void**)&piv, sizeof(int) * nb));
+  ACK(hipMalloc((void**)&perm, sizeof(int) * nb));
+  ACK(hipMalloc((void**)&pst, sizeof(int)));
+  ACK(hipMalloc((void**)&colk, sizeof(double) * nb));
+  ACK(hipMalloc((void**)&Rs, sizeof(double) * GJ_PANEL * nb));
+  ACK(hipMemcpy(dM, &S->Minv, sizeof(double*), hipMemcpyHostToDevice));
+  ACK(hipMemcpy(pst, &big, sizeof(int), hipMemcpyHostToDevice));
+  launch_bgj_invert(dM, nb, 1, piv, colk, Rs, perm, pst, ctx->stream);
+  ACK(hipGetLastError());
+  int status = 0;
+  ACK(hipMemcpyAsync(&status, pst, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  ACK(hipStreamSynchronize(ctx->stream));
+  (void)hipFree(dM); (void)hipFree(piv); (void)hipFree(perm); (void)hipFree(pst); (void)hipFree(colk);
+  (void)hipFree(Rs);
+  if (status != INT_MAX)
+    return rav_set_error(ctx, RAV_ESINGULAR, "zero pivot in the coarse matrix at column " + std::to_string(status));
+  return RAV_OK;
+}
+
+rav_status upload_level(rav_ctx* ctx, Level& L, const HostLevel& H, bool smoothed, bool has_transfer) {
+  L.nV = H.nV;
+  long long masked = 0;
+  for (unsigned char m : H.vmask) masked += m;
+  L.nfree = 3LL * H.nV - 2 * masked;
+  ACK(upload(&L.vmask, H.vmask));
+  ACK(upload(&L.soff, H.soff));
+  ACK(upload(&L.col, H.col));
+  ACK(upload(&L.val, H.val));
+  const long long n = 3LL * H.nV;
+  ACK(hipMalloc((void**)&L.x, sizeof(double) * n));
+  ACK(hipMalloc((void**)&L.b, sizeof(double) * n));
+  ACK(hipMalloc((void**)&L.r, sizeof(double) * n));
+  ACK(hipMemset(L.x, 0, sizeof(double) * n));
+  ACK(hipMemset(L.b, 0, sizeof(double) * n));
+  ACK(hipMemset(L.r, 0, sizeof(double) * n));
+  L.nres = ad_residual_blocks(H.nV);
+  ACK(hipMalloc((void**)&L.partials, sizeof(double) * L.nres));
+  AdDev& a = L.dev;
+  a.nV = H.nV;
+  a.nslice = (int)H.soff.size() - 1;
+  a.nnz = H.nnz;
+  a.vmask = L.vmask;
+  a.soff = L.soff;
+  a.col = L.col;
+  a.val = L.val;
+  if (smoothed) {
+    ACK(upload(&L.poff, H.poff));
+    ACK(upload(&L.pv, H.pv));
+    ACK(upload(&L.pown, H.pown));
+    ACK(upload(&L.koff, H.koff));
+    ACK(upload(&L.tsoff, H.tsoff));
+    ACK(upload(&L.tpos, H.tpos));
+    ACK(upload(&L.order, H.order));
+    L.cstart = H.cstart;
+    L.pnnz = H.pnnz;
+    L.kfull_n = H.koff.back();
+    L.h_poff = H.poff;
+    L.h_pv = H.pv;
+    L.h_pown = H.pown;
+    a.pnnz = H.pnnz;
+    a.poff = L.poff;
+    a.pv = L.pv;
+    a.pown = L.pown;
+    a.koff = L.koff;
+  }
+  if (has_transfer) {
+    ACK(upload(&L.pptr, H.pptr));
+    ACK(upload(&L.pidx, H.pidx));
+    ACK(upload(&L.pw, H.pwt));
+    ACK(upload(&L.rptr, H.rptr));
+    ACK(upload(&L.ridx, H.ridx));
+    ACK(upload(&L.rw, H.rwt));
+  }
+  return RAV_OK;
+}
+
+rav_status check_desc(const rav_problem_desc* d, long lattice) {
+  if (d->discretization != RAV_Q1Q1_ADAPTIVE)
+    return rav_set_error(nullptr, RAV_EINVAL, "rav_create_adaptive needs discretization RAV_Q1Q1_ADAPTIVE");
+  if (d->dim != 2) return rav_set_error(nullptr, RAV_EUNSUPPORTED, "adaptive grids are provided in 2D");
+  if (d->n_levels < 2 || d->n_levels > 24) return rav_set_error(nullptr, RAV_EINVAL, "n_levels must be in [2, 24]");
+  if (lattice < 2 || lattice > (1L << 24) || (lattice & (lattice - 1)))
+    return rav_set_error(nullptr, RAV_EINVAL, "lattice must be a power of two in [2, 2^24]");
+  if (d->bc_dirichlet_mask != 0xFu)
+    return rav_set_error(nullptr, RAV_EUNSUPPORTED, "adaptive grids are provided with Dirichlet velocity on all sides");
+  if (!(d->beta > 0.0)) return rav_set_error(nullptr, RAV_EINVAL, "the stabilization constant beta must be > 0");
+  if (!(d->eta_out > 0.0)) return rav_set_error(nullptr, RAV_EINVAL, "viscosity must be > 0");
+  if (d->n_incl != 0) return rav_set_error(nullptr, RAV_EUNSUPPORTED, "adaptive grids use a constant viscosity");
+  if (!(d->omega > 0.0) || d->nu_pre < 0 || d->nu_post < 0)
+    return rav_set_error(nullptr, RAV_EINVAL, "omega must be > 0 and smoothing steps >= 0");
+  if (d->smoother < RAV_SMOOTHER_RAV || d->smoother > RAV_SMOOTHER_MV)
+    return rav_set_error(nullptr, RAV_EINVAL, "bad smoother");
+  if (d->patch != RAV_PATCH_VERTEX || d->inv_precision != RAV_FP64 || d->coarse_galerkin != 0)
+    return rav_set_error(nullptr, RAV_EUNSUPPORTED,
+                         "adaptive grids are provided with vertex patches, FP64 inverses and rediscretised levels");
+  if (d->inv_format != RAV_ROWS && d->inv_format != RAV_FACTORED)
+    return rav_set_error(nullptr, RAV_EINVAL, "bad inverse format");
+  return RAV_OK;
+}
+
+// Validates every grid and builds its topology.
+bool build_topos(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice,
+                 std::vector<Topo>& topo, std::string& err) {
+  const int nl = d->n_levels;
+  std::vector<long long> first(nl + 1, 0);
+  for (int l = 0; l < nl; ++l) {
+    if (n_leaves[l] <= 0) { err = "every grid needs leaves"; return false; }
+    first[l + 1] = first[l] + n_leaves[l];
+  }
+  topo.assign(nl, Topo());
+  for (int l = 0; l < nl; ++l) {
+    const int* lv = leaves + 3 * first[l];
+    std::string e2;
+    if (!check_leaves(lv, n_leaves[l], lattice, e2) || !topo[l].build(lv, n_leaves[l], lattice)) {
+      err = "grid " + std::to_string(l) + ": " + (e2.empty() ? topo[l].err : e2);
+      return false;
+    }
+  }
+  if (3LL * topo[0].nV() + 1 > MAX_COARSE) {
+    err = "coarsest grid too large for the dense direct solve";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+// ============================================================================
+rav_status rav_ad_create(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice,
+                         void* hip_stream, rav_ctx** out) {
+  if (!d || !leaves || !n_leaves || !out) return rav_set_error(nullptr, RAV_EINVAL, "null argument");
+  rav_status s0 = check_desc(d, lattice);
+  if (s0 != RAV_OK) return s0;
+  const int nl = d->n_levels;
+  std::vector<Topo> topo;
+  std::string err;
+  if (!build_topos(d, leaves, n_leaves, lattice, topo, err)) return rav_set_error(nullptr, RAV_EINVAL, err);
+
+  rav_ctx* ctx = new rav_ctx();
+  ctx->desc = *d;
+  ctx->desc.incl = nullptr;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->prec = P_FP64;
+  ctx->ad = new rav_ad_state();
+  auto fail = [&](rav_status s) {
+    rav_set_error(nullptr, s, ctx->err);
+    rav_destroy(ctx);
+    return s;
+  };
+  rav_status s = rav_init_common(ctx, d);
+  if (s != RAV_OK) return fail(s);
+  rav_ad_state* S = ctx->ad;
+  S->mode = d->smoother == RAV_SMOOTHER_RAV ? AD_RAV : AD_FULL;
+  S->lv.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    HostLevel H;
+    if (!assemble(topo[l], d->beta, d->eta_out, l == nl - 1, H, err)) {
+      ctx->err = err;
+      return fail(RAV_EINVAL);
+    }
+    if (l > 0) {
+      if (!build_patches(topo[l], H, err) || !build_transfer(topo[l], topo[l - 1], H, topo[l - 1].nV(), err)) {
+        ctx->err = "grid " + std::to_string(l) + ": " + err;
+        return fail(err.find("more than") != std::string::npos ? RAV_EUNSUPPORTED : RAV_EINVAL);
+      }
+    }
+    if ((s = upload_level(ctx, S->lv[l], H, l > 0, l > 0)) != RAV_OK) return fail(s);
+    if (l == nl - 1) {
+      hipError_t e = upload(&S->blid, H.blid);
+      if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
+    }
+    if (l == 0 && (s = build_coarse(ctx, H)) != RAV_OK) return fail(s);
+  }
+  *out = ctx;
+  return RAV_OK;
+}
+
+void rav_ad_free(rav_ctx* ctx) {
+  rav_ad_state* S = ctx->ad;
+  if (!S) return;
+  for (Level& L : S->lv) {
+    void* ptrs[] = {L.vmask, L.soff, L.col, L.val, L.poff, L.pv, L.pown, L.koff, L.fac.zx, L.fac.zy, L.fac.invS,
+                    L.fac.kr, L.fac.kfull, L.tsoff, L.tpos, L.yx, L.yy, L.yp, L.order, L.pptr, L.pidx, L.pw,
+                    L.rptr, L.ridx, L.rw, L.x, L.b, L.r, L.partials};
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  (void)hipFree(S->Minv);
+  (void)hipFree(S->blid);
+  delete S;
+  ctx->ad = nullptr;
+}
+
+rav_status rav_ad_factor(rav_ctx* ctx) {
+  rav_ad_state* S = st(ctx);
+  const int big = INT_MAX;
+  for (size_t l = 1; l < S->lv.size(); ++l) {
+    Level& L = S->lv[l];
+    if (!L.fac.zx) {
+      ACK(hipMalloc((void**)&L.fac.zx, sizeof(double) * L.pnnz));
+      ACK(hipMalloc((void**)&L.fac.zy, sizeof(double) * L.pnnz));
+      ACK(hipMalloc((void**)&L.fac.invS, sizeof(double) * L.nV));
+      if (S->mode == AD_RAV) {
+        ACK(hipMalloc((void**)&L.fac.kr, sizeof(double) * L.pnnz));
+      } else {
+        ACK(hipMalloc((void**)&L.fac.kfull, sizeof(double) * L.kfull_n));
+        ACK(hipMalloc((void**)&L.yx, sizeof(double) * L.pnnz));
+        ACK(hipMalloc((void**)&L.yy, sizeof(double) * L.pnnz));
+        ACK(hipMalloc((void**)&L.yp, sizeof(double) * L.nV));
+      }
+    }
+    ACK(hipMemcpy(ctx->d_status, &big, sizeof(int), hipMemcpyHostToDevice));
+    ad_launch_factor(L.dev, S->mode, L.fac, ctx->d_status, ctx->stream);
+    ACK(hipGetLastError());
+    int stv = 0;
+    ACK(hipMemcpyAsync(&stv, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    ACK(hipStreamSynchronize(ctx->stream));
+    if (stv != INT_MAX)
+      return rav_set_error(ctx, RAV_ESINGULAR,
+                           "singular local system in patch " + std::to_string(stv) + " on level " + std::to_string(l));
+  }
+  rav_drop_graph(ctx);
+  S->have_factors = true;
+  ctx->factored = 1;
+  return RAV_OK;
+}
+
+rav_status rav_ad_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free) {
+  if (check_lv(ctx, level, false) != RAV_OK) return RAV_EINVAL;
+  const Level& L = st(ctx)->lv[level];
+  if (n_total) *n_total = 3L * L.nV;
+  if (n_free) *n_free = (long)L.nfree;
+  return RAV_OK;
+}
+
+int rav_ad_n_levels(const rav_ctx* ctx) { return (int)st(ctx)->lv.size(); }
+
+rav_status rav_ad_n_patches(const rav_ctx* ctx, int level, long* n) {
+  if (check_lv(ctx, level, false) != RAV_OK || !n) return RAV_EINVAL;
+  *n = (long)st(ctx)->lv[level].nV;
+  return RAV_OK;
+}
+
+rav_status rav_ad_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev) {
+  const Level& L = st(ctx)->lv.back();
+  ad_launch_scale(st(ctx)->blid, lid_u, b_dev, 3LL * L.nV, ctx->stream);
+  ACK(hipGetLastError());
+  ACK(hipStreamSynchronize(ctx->stream));
+  return RAV_OK;
+}
+
+rav_status rav_ad_residual(rav_ctx* ctx, int level, const double* x, const double* b, double* r, double* norm) {
+  if (check_lv(ctx, level, false) != RAV_OK) return RAV_EINVAL;
+  Level& L = st(ctx)->lv[level];
+  const long long n = 3LL * L.nV;
+  launch_copy(L.x, x, n, ctx->stream);
+  launch_copy(L.b, b, n, ctx->stream);
+  residual(ctx, level, norm != nullptr);
+  launch_copy(r, L.r, n, ctx->stream);
+  ACK(hipGetLastError());
+  if (norm) return rav_read_norm(ctx, norm);
+  return RAV_OK;
+}
+
+rav_status rav_ad_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const double* b) {
+  if (check_lv(ctx, level, true) != RAV_OK) return RAV_EINVAL;
+  if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
+  Level& L = st(ctx)->lv[level];
+  const long long n = 3LL * L.nV;
+  launch_copy(L.x, x, n, ctx->stream);
+  launch_copy(L.b, b, n, ctx->stream);
+  smooth(ctx, level, sweeps, false);
+  launch_copy(x, L.x, n, ctx->stream);
+  ACK(hipGetLastError());
+  return RAV_OK;
+}
+
+rav_status rav_ad_restrict(rav_ctx* ctx, int level, const double* rf, double* bc) {
+  if (check_lv(ctx, level, true) != RAV_OK) return RAV_EINVAL;
+  Level& L = st(ctx)->lv[level];
+  Level& C = st(ctx)->lv[level - 1];
+  launch_copy(L.r, rf, 3LL * L.nV, ctx->stream);
+  restrict_to(ctx, level, nullptr);
+  launch_copy(bc, C.b, 3LL * C.nV, ctx->stream);
+  ACK(hipGetLastError());
+  return RAV_OK;
+}
+
+rav_status rav_ad_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf) {
+  if (check_lv(ctx, level, true) != RAV_OK) return RAV_EINVAL;
+  Level& L = st(ctx)->lv[level];
+  Level& C = st(ctx)->lv[level - 1];
+  launch_copy(C.x, xc, 3LL * C.nV, ctx->stream);
+  launch_copy(L.x, xf, 3LL * L.nV, ctx->stream);
+  prolong(ctx, level);
+  launch_copy(xf, L.x, 3LL * L.nV, ctx->stream);
+  ACK(hipGetLastError());
+  return RAV_OK;
+}
+
+rav_status rav_ad_coarse_solve(rav_ctx* ctx, const double* b0, double* x0) {
+  rav_ad_state* S = st(ctx);
+  launch_coarse_gemv(S->Minv, S->nb, 3LL * S->lv[0].nV, b0, x0, ctx->stream);
+  ACK(hipGetLastError());
+  return RAV_OK;
+}
+
+rav_status rav_ad_vcycle(rav_ctx* ctx, double* x, const double* b) {
+  if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
+  const int lf = (int)st(ctx)->lv.size() - 1;
+  Level& L = st(ctx)->lv[lf];
+  const long long n = 3LL * L.nV;
+  launch_copy(L.x, x, n, ctx->stream);
+  launch_copy(L.b, b, n, ctx->stream);
+  vcycle(ctx, lf, false);
+  launch_copy(x, L.x, n, ctx->stream);
+  ACK(hipGetLastError());
+  return RAV_OK;
+}
+
+rav_status rav_ad_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int maxit, int* iters,
+                        double* rel_res) {
+  if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
+  const int lf = (int)st(ctx)->lv.size() - 1;
+  Level& L = st(ctx)->lv[lf];
+  const long long n = 3LL * L.nV;
+  launch_copy(L.x, x, n, ctx->stream);
+  launch_copy(L.b, b, n, ctx->stream);
+  residual(ctx, lf, true);
+  double r0 = 0.0;
+  rav_status s = rav_read_norm(ctx, &r0);
+  if (s != RAV_OK) return s;
+  if (iters) *iters = 0;
+  if (rel_res) *rel_res = r0 > 0.0 ? 1.0 : 0.0;
+  if (!std::isfinite(r0)) return rav_set_error(ctx, RAV_EDIVERGED, "initial residual is not finite");
+  rav_status result = r0 == 0.0 ? RAV_OK : RAV_NOT_CONVERGED;
+  int k = 0;
+  double rk = r0;
+  while (result == RAV_NOT_CONVERGED && k < maxit) {
+    rav_graph_cycle(ctx, issue_cycle);   // the finest residual is current from the norm evaluation
+    if ((s = rav_read_norm(ctx, &rk)) != RAV_OK) return s;
+    ++k;
+    if (!std::isfinite(rk) || rk > 1e3 * r0) {
+      result = RAV_EDIVERGED;
+      ctx->err = "residual diverged at cycle " + std::to_string(k);
+    } else if (rk <= rtol * r0) {
+      result = RAV_OK;
+    }
+  }
+  if (iters) *iters = k;
+  if (rel_res) *rel_res = r0 > 0.0 ? rk / r0 : 0.0;
+  launch_copy(x, L.x, n, ctx->stream);
+  ACK(hipGetLastError());
+  ACK(hipStreamSynchronize(ctx->stream));
+  return result;
+}
+
+// Patch DoFs in local order: u_x of the free patch vertices (ascending), u_y of
+// the same vertices, p_i; owned: u_x,i, u_y,i (if free) and p_i.
+static int ad_patch_list(const Level& L, long long i, int* dofs, int* owned) {
+  const int nV = L.nV;
+  const long long sl = i / AD_SLICE, t = i % AD_SLICE;
+  const int w = (L.h_poff[sl + 1] - L.h_poff[sl]) / AD_SLICE;
+  std::vector<int> vs;
+  for (int k = 0; k < w; ++k) {
+    const int v = L.h_pv[L.h_poff[sl] + AD_SLICE * k + t];
+    if (v >= 0) vs.push_back(v);
+  }
+  int n = 0;
+  for (int c = 0; c < 2; ++c)
+    for (int v : vs) {
+      dofs[n] = c * nV + v;
+      if (owned) owned[n] = v == (int)i;
+      ++n;
+    }
+  dofs[n] = 2 * nV + (int)i;
+  if (owned) owned[n] = 1;
+  return n + 1;
+}
+
+rav_status rav_ad_get_owner(rav_ctx* ctx, int level, int* owner_dev) {
+  if (check_lv(ctx, level, false) != RAV_OK) return RAV_EINVAL;
+  ad_launch_owner(st(ctx)->lv[level].dev, owner_dev, ctx->stream);
+  ACK(hipGetLastError());
+  ACK(hipStreamSynchronize(ctx->stream));
+  return RAV_OK;
+}
+
+rav_status rav_ad_get_patch_map(const rav_ctx* ctx, int level, long patch, int* dofs, int* n, int* owned) {
+  if (check_lv(ctx, level, true) != RAV_OK || !dofs || !n) return RAV_EINVAL;
+  const Level& L = st(ctx)->lv[level];
+  if (patch < 0 || patch >= L.nV) return RAV_EINVAL;
+  *n = ad_patch_list(L, patch, dofs, owned);
+  return RAV_OK;
+}
+
+// Owned rows (RAV) or every row (AV, MV) of L_i^{-1} over the patch DoFs,
+// rebuilt from the factored values: with z_c = K^{-1} b_c and S,
+// L_i^{-1} = [[K^{-1} + z z^T / S, -z / S], [-z^T / S, 1 / S]] per component.
+rav_status rav_ad_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* out, int* rows, int* cols) {
+  if (check_lv(ctx, level, true) != RAV_OK) return RAV_EINVAL;
+  if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
+  rav_ad_state* S = st(ctx);
+  const Level& L = S->lv[level];
+  if (patch < 0 || patch >= L.nV) return RAV_EINVAL;
+  ACK(hipStreamSynchronize(ctx->stream));
+  const long long sl = patch / AD_SLICE, t = patch % AD_SLICE;
+  const int w = (L.h_poff[sl + 1] - L.h_poff[sl]) / AD_SLICE;
+  int nf = 0;
+  while (nf < w && L.h_pv[L.h_poff[sl] + AD_SLICE * nf + t] >= 0) ++nf;
+  std::vector<double> zx(nf), zy(nf), kin((size_t)nf * nf, 0.0);
+  double sinv = 0.0;
+  for (int k = 0; k < nf; ++k) {
+    const long long e = L.h_poff[sl] + AD_SLICE * k + t;
+    ACK(hipMemcpy(&zx[k], L.fac.zx + e, sizeof(double), hipMemcpyDeviceToHost));
+    ACK(hipMemcpy(&zy[k], L.fac.zy + e, sizeof(double), hipMemcpyDeviceToHost));
+  }
+  ACK(hipMemcpy(&sinv, L.fac.invS + patch, sizeof(double), hipMemcpyDeviceToHost));
+  const int ao = L.h_pown[patch];
+  std::vector<int> krow;   // rows of K^{-1} available
+  if (S->mode == AD_RAV) {
+    if (ao >= 0) {
+      for (int k = 0; k < nf; ++k)
+        ACK(hipMemcpy(&kin[(size_t)ao * nf + k], L.fac.kr + L.h_poff[sl] + AD_SLICE * k + t, sizeof(double),
+                      hipMemcpyDeviceToHost));
+      krow.push_back(ao);
+    }
+  } else {
+    long long k0 = 0;
+    std::vector<long long> koff(L.h_poff.size());
+    for (size_t s2 = 0; s2 + 1 < L.h_poff.size(); ++s2) {
+      const long long ww = (L.h_poff[s2 + 1] - L.h_poff[s2]) / AD_SLICE;
+      koff[s2 + 1] = koff[s2] + AD_SLICE * ww * ww;
+    }
+    k0 = koff[sl];
+    for (int a = 0; a < nf; ++a) {
+      for (int b = 0; b < nf; ++b)
+        ACK(hipMemcpy(&kin[(size_t)a * nf + b], L.fac.kfull + k0 + AD_SLICE * (long long)(a * w + b) + t,
+                      sizeof(double), hipMemcpyDeviceToHost));
+      krow.push_back(a);
+    }
+  }
+  const int n = 2 * nf + 1;
+  // entry of L_i^{-1} at local (row, col): velocity (c, m) = c nf + m, pressure 2 nf
+  auto entry = [&](int r, int c) -> double {
+    const bool rv = r < 2 * nf, cv = c < 2 * nf;
+    const int c1 = r < nf ? 0 : 1, m1 = r - c1 * nf, c2 = c < nf ? 0 : 1, m2 = c - c2 * nf;
+    const std::vector<double>& zr = c1 == 0 ? zx : zy;
+    const std::vector<double>& zc = c2 == 0 ? zx : zy;
+    if (rv && cv) return (c1 == c2 ? kin[(size_t)m1 * nf + m2] : 0.0) + zr[m1] * sinv * zc[m2];
+    if (rv) return -zr[m1] * sinv;
+    if (cv) return -sinv * zc[m2];
+    return sinv;
+  };
+  int nr = 0;
+  for (int r = 0; r < n; ++r) {
+    const bool own = r == 2 * nf || (ao >= 0 && (r == ao || r == nf + ao));
+    if (S->mode == AD_RAV && !own) continue;
+    for (int c = 0; c < n; ++c) out[(size_t)nr * n + c] = entry(r, c);
+    ++nr;
+  }
+  *rows = nr;
+  *cols = n;
+  return RAV_OK;
+}
+
+rav_status rav_ad_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const double* b, float* ms_res,
+                             float* ms_apply) {
+  if (check_lv(ctx, level, true) != RAV_OK) return RAV_EINVAL;
+  if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
+  Level& L = st(ctx)->lv[level];
+  const long long n = 3LL * L.nV;
+  launch_copy(L.x, x, n, ctx->stream);
+  launch_copy(L.b, b, n, ctx->stream);
+  std::vector<hipEvent_t> ev(3 * reps);
+  for (auto& e : ev) ACK(hipEventCreate(&e));
+  const bool mv = ctx->desc.smoother == RAV_SMOOTHER_MV;
+  for (int i = 0; i < reps; ++i) {
+    ACK(hipEventRecord(ev[3 * i], ctx->stream));
+    if (!mv) residual(ctx, level, false);
+    ACK(hipEventRecord(ev[3 * i + 1], ctx->stream));
+    if (mv) smooth(ctx, level, 1, false);
+    else apply(ctx, level);
+    ACK(hipEventRecord(ev[3 * i + 2], ctx->stream));
+  }
+  ACK(hipEventSynchronize(ev.back()));
+  double tr = 0.0, ta = 0.0;
+  for (int i = 0; i < reps; ++i) {
+    float a = 0.f, c = 0.f;
+    ACK(hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]));
+    ACK(hipEventElapsedTime(&c, ev[3 * i + 1], ev[3 * i + 2]));
+    tr += a;
+    ta += c;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (ms_res) *ms_res = (float)(tr / reps);
+  if (ms_apply) *ms_apply = (float)(ta / reps);
+  launch_copy(x, L.x, n, ctx->stream);
+  ACK(hipStreamSynchronize(ctx->stream));
+  return RAV_OK;
+}
+
+// Grid statistics for the host: vertices, operator entries (padded), MV colours.
+rav_status rav_ad_level_info(const rav_ctx* ctx, int level, long* info) {
+  if (check_lv(ctx, level, false) != RAV_OK || !info) return RAV_EINVAL;
+  const Level& L = st(ctx)->lv[level];
+  info[0] = L.nV;
+  info[1] = (long)L.dev.nnz;
+  info[2] = (long)L.pnnz;
+  info[3] = L.cstart.empty() ? 0 : (long)L.cstart.size() - 1;
+  return RAV_OK;
+}
+
+// Host-only set-up of one grid, for checks without a device.
+rav_status rav_ad_host_export(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice,
+                              int level, int what, double* out, long* rows, long* cols) {
+  if (!d || !leaves || !n_leaves || !rows || !cols) return rav_set_error(nullptr, RAV_EINVAL, "null argument");
+  rav_status s0 = check_desc(d, lattice);
+  if (s0 != RAV_OK) return s0;
+  if (level < 0 || level >= d->n_levels || what < 0 || what > 3 || (level == 0 && (what == 1 || what == 3)))
+    return rav_set_error(nullptr, RAV_EINVAL, "bad level or export kind");
+  std::vector<Topo> topo;
+  std::string err;
+  if (!build_topos(d, leaves, n_leaves, lattice, topo, err)) return rav_set_error(nullptr, RAV_EINVAL, err);
+  HostLevel H;
+  if (!assemble(topo[level], d->beta, d->eta_out, what == 2, H, err)) return rav_set_error(nullptr, RAV_EINVAL, err);
+  const long long nV = H.nV, n = 3 * nV, P = H.nnz;
+  if (what == 0) {
+    *rows = (long)n;
+    *cols = (long)n;
+    if (!out) return RAV_OK;
+    std::fill(out, out + n * n, 0.0);
+    for (long long i = 0; i < nV; ++i)
+      for (size_t k = 0; k < H.nbr[i].size(); ++k) {
+        const long long j = H.nbr[i][k];
+        const long long sl = sell_slot(H.soff, (int)i, (int)k);
+        out[i * n + j] += H.val[AD_A * P + sl];
+        out[(nV + i) * n + nV + j] += H.val[AD_A * P + sl];
+        out[i * n + 2 * nV + j] += H.val[AD_BTX * P + sl];
+        out[(nV + i) * n + 2 * nV + j] += H.val[AD_BTY * P + sl];
+        out[(2 * nV + i) * n + j] += H.val[AD_BX * P + sl];
+        out[(2 * nV + i) * n + nV + j] += H.val[AD_BY * P + sl];
+        out[(2 * nV + i) * n + 2 * nV + j] += H.val[AD_C * P + sl];
+      }
+    return RAV_OK;
+  }
+  if (what == 2) {
+    *rows = (long)n;
+    *cols = 1;
+    if (out) std::copy(H.blid.begin(), H.blid.end(), out);
+    return RAV_OK;
+  }
+  if (what == 3) {
+    if (!build_patches(topo[level], H, err)) return rav_set_error(nullptr, RAV_EUNSUPPORTED, err);
+    *rows = (long)nV;
+    *cols = 1;
+    if (!out) return RAV_OK;
+    for (size_t c = 0; c + 1 < H.cstart.size(); ++c)
+      for (int q = H.cstart[c]; q < H.cstart[c + 1]; ++q) out[H.order[q]] = (double)c;
+    return RAV_OK;
+  }
+  // what == 1: prolongation from grid level-1, all three fields, masked rows and columns zero
+  const long long nVc = topo[level - 1].nV(), nc = 3 * nVc;
+  if (!build_transfer(topo[level], topo[level - 1], H, (int)nVc, err)) return rav_set_error(nullptr, RAV_EINVAL, err);
+  *rows = (long)n;
+  *cols = (long)nc;
+  if (!out) return RAV_OK;
+  HostLevel Hc;
+  if (!assemble(topo[level - 1], d->beta, d->eta_out, false, Hc, err)) return rav_set_error(nullptr, RAV_EINVAL, err);
+  std::fill(out, out + n * nc, 0.0);
+  for (long long i = 0; i < nV; ++i)
+    for (int k = H.pptr[i]; k < H.pptr[i + 1]; ++k) {
+      const long long j = H.pidx[k];
+      const double w = H.pwt[k];
+      if (!H.vmask[i] && !Hc.vmask[j]) {
+        out[i * nc + j] += w;
+        out[(nV + i) * nc + nVc + j] += w;
+      }
+      out[(2 * nV + i) * nc + 2 * nVc + j] += w;
+    }
+  return RAV_OK;
+}

@@ -521,6 +521,38 @@ void rav_drop_graph(rav_ctx* ctx) {
   ctx->prof_exec_level = -1;
 }
 
+// Issues `issue(ctx)` on the context stream: captured into a graph on first
+// use and replayed afterwards (RAV_GRAPH=0 in the environment, or a failed
+// capture, issues the launches directly).
+void rav_graph_cycle(rav_ctx* ctx, void (*issue)(rav_ctx*)) {
+  static const bool graphs = [] {
+    const char* e = std::getenv("RAV_GRAPH");
+    return !(e && std::string(e) == "0");
+  }();
+  if (graphs && !ctx->graph_failed) {
+    if (!ctx->cycle_exec) {
+      hipGraph_t g = nullptr;
+      bool ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        issue(ctx);
+        ok = hipStreamEndCapture(ctx->stream, &g) == hipSuccess && g != nullptr;
+      }
+      if (ok) ok = hipGraphInstantiate(&ctx->cycle_exec, g, nullptr, nullptr, 0) == hipSuccess;
+      if (g) (void)hipGraphDestroy(g);
+      if (!ok) {
+        (void)hipGetLastError();
+        ctx->cycle_exec = nullptr;
+        ctx->graph_failed = true;
+      }
+    }
+    if (ctx->cycle_exec && hipGraphLaunch(ctx->cycle_exec, ctx->stream) == hipSuccess) return;
+    (void)hipGetLastError();
+    rav_drop_graph(ctx);
+    ctx->graph_failed = true;
+  }
+  issue(ctx);
+}
+
 // One solve cycle: V-cycle from a current finest residual, then the new
 // finest residual and its squared norm in d_norm.  Replayed from a graph when
 // possible; with profiling markers active (their events count launches on the
@@ -618,6 +650,8 @@ static rav_status need_factors(rav_ctx* ctx) {
 rav_status rav_create_ex(const rav_problem_desc* d, void* hip_stream, rav_ctx** out, bool invert_coarse) {
   if (!d || !out) return set_err(nullptr, RAV_EINVAL, "null descriptor or output pointer");
   *out = nullptr;
+  if (d->discretization == RAV_Q1Q1_ADAPTIVE)
+    return set_err(nullptr, RAV_EINVAL, "adaptive grids are created with rav_create_adaptive");
   if (d->discretization == RAV_Q1Q1_STAB) {
     if (!invert_coarse)
       return set_err(nullptr, RAV_EUNSUPPORTED, "batches are provided for the Taylor-Hood discretization");
@@ -826,6 +860,7 @@ extern "C" {
 
 rav_status rav_factor_patches(rav_ctx* ctx) {
   if (ctx && ctx->q1) return rav_q1_factor(ctx);
+  if (ctx && ctx->ad) return rav_ad_factor(ctx);
   if (!ctx) return RAV_EINVAL;
   rav_drop_graph(ctx);
   const rav_problem_desc& D = ctx->desc;
@@ -878,6 +913,7 @@ rav_status rav_factor_patches(rav_ctx* ctx) {
 
 rav_status rav_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free) {
   if (ctx && ctx->q1) return rav_q1_dofs(ctx, level, n_total, n_free);
+  if (ctx && ctx->ad) return rav_ad_dofs(ctx, level, n_total, n_free);
   if (check_level(ctx, level, false) != RAV_OK) return RAV_EINVAL;
   const Geo& g = ctx->lv[level].hd.g;
   if (n_total) *n_total = (long)g.n;
@@ -898,6 +934,10 @@ rav_status rav_n_levels(const rav_ctx* ctx, int* n) {
     *n = rav_q1_n_levels(ctx);
     return RAV_OK;
   }
+  if (ctx && ctx->ad && n) {
+    *n = rav_ad_n_levels(ctx);
+    return RAV_OK;
+  }
   if (!ctx || !n) return RAV_EINVAL;
   *n = (int)ctx->lv.size();
   return RAV_OK;
@@ -905,6 +945,7 @@ rav_status rav_n_levels(const rav_ctx* ctx, int* n) {
 
 rav_status rav_n_patches(const rav_ctx* ctx, int level, long* n) {
   if (ctx && ctx->q1) return rav_q1_n_patches(ctx, level, n);
+  if (ctx && ctx->ad) return rav_ad_n_patches(ctx, level, n);
   if (check_level(ctx, level, false) != RAV_OK || !n) return RAV_EINVAL;
   *n = (long)ctx->lv[level].npatch;
   return RAV_OK;
@@ -912,6 +953,7 @@ rav_status rav_n_patches(const rav_ctx* ctx, int level, long* n) {
 
 rav_status rav_assemble_rhs(rav_ctx* ctx, const double* params, int n_params, double* b_dev) {
   if (ctx && ctx->q1 && params && b_dev) return rav_q1_assemble_rhs(ctx, params, n_params, b_dev);
+  if (ctx && ctx->ad) return set_err(ctx, RAV_EUNSUPPORTED, "adaptive grids carry the driven cavity (rav_assemble_rhs_lid)");
   if (!ctx || !params || !b_dev) return RAV_EINVAL;
   const int need = ctx->desc.dim == 2 ? 25 : 65;
   if (n_params != need) return set_err(ctx, RAV_EINVAL, "mms parameter array must have " + std::to_string(need) + " entries");
@@ -937,6 +979,7 @@ rav_status rav_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev) {
   if (D.dim != 2 || !((D.bc_dirichlet_mask >> 3) & 1u))
     return set_err(ctx, RAV_EINVAL, "the driven cavity needs a 2D grid with a Dirichlet top side (bit 3)");
   if (ctx->q1) return rav_q1_assemble_rhs_lid(ctx, lid_u, b_dev);
+  if (ctx->ad) return rav_ad_assemble_rhs_lid(ctx, lid_u, b_dev);
   LevelHost& L = ctx->lv.back();
   launch_fill(b_dev, 0.0, L.hd.g.n, ctx->stream);
   launch_lift_lid(L.dd, L.hd.g, lid_u, b_dev, ctx->stream);
@@ -947,6 +990,7 @@ rav_status rav_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev) {
 
 rav_status rav_residual(rav_ctx* ctx, int level, const double* x, const double* b, double* r, double* norm) {
   if (ctx && ctx->q1 && x && b && r) return rav_q1_residual(ctx, level, x, b, r, norm);
+  if (ctx && ctx->ad && x && b && r) return rav_ad_residual(ctx, level, x, b, r, norm);
   if (check_level(ctx, level, false) != RAV_OK || !x || !b || !r) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   const long long n = L.hd.g.n;
@@ -961,6 +1005,7 @@ rav_status rav_residual(rav_ctx* ctx, int level, const double* x, const double* 
 
 rav_status rav_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const double* b) {
   if (ctx && ctx->q1 && x && b && sweeps >= 0) return rav_q1_smooth(ctx, level, sweeps, x, b);
+  if (ctx && ctx->ad && x && b && sweeps >= 0) return rav_ad_smooth(ctx, level, sweeps, x, b);
   if (check_level(ctx, level, true) != RAV_OK || !x || !b || sweeps < 0) return RAV_EINVAL;
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
@@ -975,6 +1020,7 @@ rav_status rav_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const doub
 
 rav_status rav_restrict(rav_ctx* ctx, int level, const double* rf, double* bc) {
   if (ctx && ctx->q1 && rf && bc) return rav_q1_restrict(ctx, level, rf, bc);
+  if (ctx && ctx->ad && rf && bc) return rav_ad_restrict(ctx, level, rf, bc);
   if (check_level(ctx, level, true) != RAV_OK || !rf || !bc) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   launch_copy(L.hd.r, rf, L.hd.g.n, ctx->stream);
@@ -986,6 +1032,7 @@ rav_status rav_restrict(rav_ctx* ctx, int level, const double* rf, double* bc) {
 
 rav_status rav_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf) {
   if (ctx && ctx->q1 && xc && xf) return rav_q1_prolong_add(ctx, level, xc, xf);
+  if (ctx && ctx->ad && xc && xf) return rav_ad_prolong_add(ctx, level, xc, xf);
   if (check_level(ctx, level, true) != RAV_OK || !xc || !xf) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   launch_copy(ctx->lv[level - 1].hd.x, xc, L.hd.gc.n, ctx->stream);
@@ -998,6 +1045,7 @@ rav_status rav_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf
 
 rav_status rav_coarse_solve(rav_ctx* ctx, const double* b0, double* x0) {
   if (ctx && ctx->q1 && b0 && x0) return rav_q1_coarse_solve(ctx, b0, x0);
+  if (ctx && ctx->ad && b0 && x0) return rav_ad_coarse_solve(ctx, b0, x0);
   if (!ctx || !b0 || !x0) return RAV_EINVAL;
   launch_coarse_gemv(ctx->Minv, ctx->nb, ctx->lv[0].hd.g.n, b0, x0, ctx->stream);
   CK(hipGetLastError());
@@ -1006,6 +1054,7 @@ rav_status rav_coarse_solve(rav_ctx* ctx, const double* b0, double* x0) {
 
 rav_status rav_vcycle(rav_ctx* ctx, double* x, const double* b) {
   if (ctx && ctx->q1 && x && b) return rav_q1_vcycle(ctx, x, b);
+  if (ctx && ctx->ad && x && b) return rav_ad_vcycle(ctx, x, b);
   if (!ctx || !x || !b) return RAV_EINVAL;
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   const int lf = (int)ctx->lv.size() - 1;
@@ -1023,6 +1072,7 @@ rav_status rav_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int 
                      double* rel_res) {
   if (!ctx || !x || !b || !(rtol > 0.0) || maxit < 0) return RAV_EINVAL;
   if (ctx->q1) return rav_q1_solve(ctx, x, b, rtol, maxit, iters, rel_res);
+  if (ctx->ad) return rav_ad_solve(ctx, x, b, rtol, maxit, iters, rel_res);
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   const int lf = (int)ctx->lv.size() - 1;
   LevelHost& L = ctx->lv[lf];
@@ -1097,7 +1147,7 @@ rav_status rav_set_params(rav_ctx* ctx, double omega, int nu_pre, int nu_post) {
   ctx->desc.omega = omega;
   ctx->desc.nu_pre = nu_pre;
   ctx->desc.nu_post = nu_post;
-  if (ctx->q1) return RAV_OK;
+  if (ctx->q1 || ctx->ad) return RAV_OK;
   for (LevelHost& L : ctx->lv) {
     L.hd.omega = omega;
     rav_status st = rav_upload_desc(ctx, L);
@@ -1114,7 +1164,7 @@ rav_status rav_set_fallback(rav_ctx* ctx, double rho_max, int* fell_back) {
 }
 
 rav_status rav_set_patch_omega(rav_ctx* ctx, int level, const float* omega_dev) {
-  if (ctx && ctx->q1) return set_err(ctx, RAV_EUNSUPPORTED, "per-patch weights are provided for Taylor-Hood");
+  if (ctx && (ctx->q1 || ctx->ad)) return set_err(ctx, RAV_EUNSUPPORTED, "per-patch weights are provided for Taylor-Hood");
   if (check_level(ctx, level, true) != RAV_OK) return RAV_EINVAL;
   ctx->lv[level].hd.omega_patch = omega_dev;
   return rav_upload_desc(ctx, ctx->lv[level]);
@@ -1150,6 +1200,8 @@ static rav_status desc_geo(const rav_problem_desc* d, int level, Geo* g) {
 
 rav_status rav_map_patch(const rav_problem_desc* d, int level, long patch, int* dofs, int* n, int* owned) {
   if (d && d->discretization == RAV_Q1Q1_STAB) return rav_q1_map_patch(d, level, patch, dofs, n, owned);
+  if (d && d->discretization == RAV_Q1Q1_ADAPTIVE)
+    return set_err(nullptr, RAV_EUNSUPPORTED, "adaptive patch maps need the grids: use rav_get_patch_map");
   Geo g;
   if (desc_geo(d, level, &g) != RAV_OK) return RAV_EINVAL;
   return map_patch_geo(g, d->patch, n_patches(g, d->patch), patch, dofs, n, owned);
@@ -1157,6 +1209,8 @@ rav_status rav_map_patch(const rav_problem_desc* d, int level, long patch, int* 
 
 rav_status rav_map_owner(const rav_problem_desc* d, int level, int* owner) {
   if (d && d->discretization == RAV_Q1Q1_STAB) return rav_q1_map_owner(d, level, owner);
+  if (d && d->discretization == RAV_Q1Q1_ADAPTIVE)
+    return set_err(nullptr, RAV_EUNSUPPORTED, "adaptive owner maps need the grids: use rav_get_owner");
   Geo g;
   if (desc_geo(d, level, &g) != RAV_OK || !owner) return RAV_EINVAL;
   for (long long i = 0; i < g.n; ++i) {
@@ -1172,6 +1226,7 @@ rav_status rav_map_owner(const rav_problem_desc* d, int level, int* owner) {
 
 rav_status rav_get_patch_map(const rav_ctx* ctx, int level, long patch, int* dofs, int* n, int* owned) {
   if (ctx && ctx->q1) return rav_q1_get_patch_map(ctx, level, patch, dofs, n, owned);
+  if (ctx && ctx->ad) return rav_ad_get_patch_map(ctx, level, patch, dofs, n, owned);
   if (check_level(ctx, level, false) != RAV_OK) return RAV_EINVAL;
   const LevelHost& L = ctx->lv[level];
   return map_patch_geo(L.hd.g, ctx->desc.patch, L.npatch, patch, dofs, n, owned);
@@ -1179,6 +1234,7 @@ rav_status rav_get_patch_map(const rav_ctx* ctx, int level, long patch, int* dof
 
 rav_status rav_get_owner(rav_ctx* ctx, int level, int* owner_dev) {
   if (ctx && ctx->q1 && owner_dev) return rav_q1_get_owner(ctx, level, owner_dev);
+  if (ctx && ctx->ad && owner_dev) return rav_ad_get_owner(ctx, level, owner_dev);
   if (check_level(ctx, level, false) != RAV_OK || !owner_dev) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   launch_owner(L.dd, ctx->desc.patch, L.hd.g.n, owner_dev, ctx->stream);
@@ -1189,6 +1245,7 @@ rav_status rav_get_owner(rav_ctx* ctx, int level, int* owner_dev) {
 
 rav_status rav_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* out, int* rows, int* cols) {
   if (ctx && ctx->q1 && out && rows && cols) return rav_q1_get_patch_inverse(ctx, level, patch, out, rows, cols);
+  if (ctx && ctx->ad && out && rows && cols) return rav_ad_get_patch_inverse(ctx, level, patch, out, rows, cols);
   if (check_level(ctx, level, true) != RAV_OK || !out || !rows || !cols) return RAV_EINVAL;
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
@@ -1269,7 +1326,7 @@ rav_status rav_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* ou
 }
 
 rav_status rav_export_matrix(rav_ctx* ctx, int level, double* out) {
-  if (ctx && ctx->q1) return set_err(ctx, RAV_EUNSUPPORTED, "dense export is provided for Taylor-Hood");
+  if (ctx && (ctx->q1 || ctx->ad)) return set_err(ctx, RAV_EUNSUPPORTED, "dense export is provided for Taylor-Hood");
   if (check_level(ctx, level, false) != RAV_OK || !out) return RAV_EINVAL;
   LevelHost& L = ctx->lv[level];
   const long long n = L.hd.g.n;
@@ -1287,6 +1344,7 @@ rav_status rav_export_matrix(rav_ctx* ctx, int level, double* out) {
 rav_status rav_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const double* b, float* ms_res,
                           float* ms_apply) {
   if (ctx && ctx->q1 && x && b && reps > 0) return rav_q1_time_sweep(ctx, level, reps, x, b, ms_res, ms_apply);
+  if (ctx && ctx->ad && x && b && reps > 0) return rav_ad_time_sweep(ctx, level, reps, x, b, ms_res, ms_apply);
   if (check_level(ctx, level, true) != RAV_OK || !x || !b || reps <= 0) return RAV_EINVAL;
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   if (ctx->desc.smoother == RAV_SMOOTHER_MV) return set_err(ctx, RAV_EUNSUPPORTED, "MV has no separate residual kernel");
@@ -1321,7 +1379,7 @@ rav_status rav_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const do
 }
 
 rav_status rav_profile_begin(rav_ctx* ctx, int level, int max_launches) {
-  if (ctx && ctx->q1) return set_err(ctx, RAV_EUNSUPPORTED, "profiling markers are provided for Taylor-Hood");
+  if (ctx && (ctx->q1 || ctx->ad)) return set_err(ctx, RAV_EUNSUPPORTED, "profiling markers are provided for Taylor-Hood");
   if (check_level(ctx, level, true) != RAV_OK || max_launches <= 0) return RAV_EINVAL;
   for (auto& e : ctx->prof_res) (void)hipEventDestroy(e);
   for (auto& e : ctx->prof_app) (void)hipEventDestroy(e);
@@ -1369,12 +1427,29 @@ rav_status rav_stream_copy(void* stream, double* dst, const double* src, long n)
   return hipGetLastError() == hipSuccess ? RAV_OK : RAV_EDEVICE;
 }
 
+rav_status rav_create_adaptive(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
+                               long lattice, void* hip_stream, rav_ctx** out) {
+  if (out) *out = nullptr;
+  return rav_ad_create(desc, leaves_host, n_leaves_host, lattice, hip_stream, out);
+}
+
+rav_status rav_adaptive_host_export(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
+                                    long lattice, int level, int what, double* out_host, long* rows, long* cols) {
+  return rav_ad_host_export(desc, leaves_host, n_leaves_host, lattice, level, what, out_host, rows, cols);
+}
+
+rav_status rav_adaptive_level_info(const rav_ctx* ctx, int level, long* info_host) {
+  if (!ctx || !ctx->ad) return RAV_EINVAL;
+  return rav_ad_level_info(ctx, level, info_host);
+}
+
 rav_status rav_destroy(rav_ctx* ctx) {
   if (!ctx) return RAV_OK;
   (void)hipStreamSynchronize(ctx->stream);
   rav_drop_graph(ctx);
   if (ctx->learn_free) ctx->learn_free(ctx);
   rav_q1_free(ctx);
+  rav_ad_free(ctx);
   for (LevelHost& L : ctx->lv) {
     GridDev& h = L.hd;
     (void)hipFree(h.x); (void)hipFree(h.b); (void)hipFree(h.r); (void)hipFree(h.vals);

@@ -72,10 +72,12 @@ void append_residual_tiles(std::vector<BlockTask>& out, int grid, const Geo& g);
 }  // namespace rav
 
 struct rav_q1_state;   // stabilized Q1-Q1 hierarchy (rav_q1.hip)
+struct rav_ad_state;   // stabilized Q1-Q1 on adaptive quadtree grids (rav_adapt.hip)
 
 struct rav_ctx {
   rav_problem_desc desc{};
   rav_q1_state* q1 = nullptr;   // set for RAV_Q1Q1_STAB: the entry points route to rav_q1_*
+  rav_ad_state* ad = nullptr;   // set by rav_create_adaptive: the entry points route to rav_ad_*
   std::vector<rav_inclusion> incl;
   hipStream_t stream = nullptr;
   std::vector<rav::LevelHost> lv;
@@ -133,6 +135,7 @@ void rav_residual_level(rav_ctx* ctx, int l, bool with_norm);
 void rav_apply_level(rav_ctx* ctx, int l);
 rav_status rav_read_norm(rav_ctx* ctx, double* out);
 void rav_drop_graph(rav_ctx* ctx);   // forget the captured solve cycle
+void rav_graph_cycle(rav_ctx* ctx, void (*issue)(rav_ctx*));   // issue, captured and replayed
 rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<rav::BlockTask>& logical, rav::BlockTask** out, int* n);
 
 // Stabilized Q1-Q1 (rav_q1.hip), reached through the public entry points.
@@ -159,3 +162,29 @@ rav_status rav_q1_get_patch_map(const rav_ctx* ctx, int level, long patch, int* 
 rav_status rav_q1_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* out, int* rows, int* cols);
 rav_status rav_q1_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const double* b, float* ms_res,
                              float* ms_apply);
+
+// Stabilized Q1-Q1 on adaptive quadtree grids (rav_adapt.hip).
+rav_status rav_ad_create(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice,
+                         void* hip_stream, rav_ctx** out);
+void rav_ad_free(rav_ctx* ctx);
+rav_status rav_ad_factor(rav_ctx* ctx);
+rav_status rav_ad_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free);
+int rav_ad_n_levels(const rav_ctx* ctx);
+rav_status rav_ad_n_patches(const rav_ctx* ctx, int level, long* n);
+rav_status rav_ad_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev);
+rav_status rav_ad_residual(rav_ctx* ctx, int level, const double* x, const double* b, double* r, double* norm);
+rav_status rav_ad_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const double* b);
+rav_status rav_ad_restrict(rav_ctx* ctx, int level, const double* rf, double* bc);
+rav_status rav_ad_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf);
+rav_status rav_ad_coarse_solve(rav_ctx* ctx, const double* b0, double* x0);
+rav_status rav_ad_vcycle(rav_ctx* ctx, double* x, const double* b);
+rav_status rav_ad_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int maxit, int* iters,
+                        double* rel_res);
+rav_status rav_ad_get_owner(rav_ctx* ctx, int level, int* owner_dev);
+rav_status rav_ad_get_patch_map(const rav_ctx* ctx, int level, long patch, int* dofs, int* n, int* owned);
+rav_status rav_ad_get_patch_inverse(rav_ctx* ctx, int level, long patch, double* out, int* rows, int* cols);
+rav_status rav_ad_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const double* b, float* ms_res,
+                             float* ms_apply);
+rav_status rav_ad_level_info(const rav_ctx* ctx, int level, long* info);
+rav_status rav_ad_host_export(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice,
+                              int level, int what, double* out, long* rows, long* cols);

@@ -167,7 +167,7 @@ rav_status gmres_check(rav_ctx* ctx, double* x_dev, const double* b_dev, double 
                        int max_restart) {
   if (!ctx || !x_dev || !b_dev || !(rtol > 0.0) || maxit < 0 || restart < 1 || restart > max_restart)
     return RAV_EINVAL;
-  if (ctx->q1) { ctx->err = "FGMRES is provided for the Taylor-Hood discretization"; return RAV_EUNSUPPORTED; }
+  if (ctx->q1 || ctx->ad) { ctx->err = "FGMRES is provided for the Taylor-Hood discretization"; return RAV_EUNSUPPORTED; }
   if (!ctx->factored) { ctx->err = "rav_factor_patches has not been called"; return RAV_EINVAL; }
   return RAV_OK;
 }

@@ -81,7 +81,7 @@ struct rav_mlp {
 static rav_status check_learn_ctx(rav_ctx* ctx) {
   if (!ctx) return RAV_EINVAL;
   const rav_problem_desc& D = ctx->desc;
-  if (ctx->q1 || D.dim != 2 || D.patch != RAV_PATCH_VERTEX || D.smoother != RAV_SMOOTHER_RAV) {
+  if (ctx->q1 || ctx->ad || D.dim != 2 || D.patch != RAV_PATCH_VERTEX || D.smoother != RAV_SMOOTHER_RAV) {
     ctx->err = "learned damping is provided for 2D vertex-patch RAV";
     return RAV_EUNSUPPORTED;
   }

@@ -231,40 +231,15 @@ void vcycle(rav_ctx* ctx, int l, bool r_valid) {
   smooth(ctx, l, ctx->desc.nu_post, false);
 }
 
-// One solve cycle from a current finest residual: V-cycle, then the new finest
-// residual and its norm.  Captured from the stream into a graph on first use
-// and replayed (RAV_GRAPH=0 issues the launches directly).
-void solve_cycle(rav_ctx* ctx) {
+// One solve cycle from a current finest residual: V-cycle, then the new
+// finest residual and its norm (replayed from a graph, rav_graph_cycle).
+void issue_cycle(rav_ctx* ctx) {
   const int lf = (int)st(ctx)->lv.size() - 1;
-  static const bool graphs = [] {
-    const char* e = std::getenv("RAV_GRAPH");
-    return !(e && std::string(e) == "0");
-  }();
-  if (graphs && !ctx->graph_failed) {
-    if (!ctx->cycle_exec) {
-      hipGraph_t g = nullptr;
-      bool ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-      if (ok) {
-        vcycle(ctx, lf, true);
-        residual(ctx, lf, true);
-        ok = hipStreamEndCapture(ctx->stream, &g) == hipSuccess && g != nullptr;
-      }
-      if (ok) ok = hipGraphInstantiate(&ctx->cycle_exec, g, nullptr, nullptr, 0) == hipSuccess;
-      if (g) (void)hipGraphDestroy(g);
-      if (!ok) {
-        (void)hipGetLastError();
-        ctx->cycle_exec = nullptr;
-        ctx->graph_failed = true;
-      }
-    }
-    if (ctx->cycle_exec && hipGraphLaunch(ctx->cycle_exec, ctx->stream) == hipSuccess) return;
-    (void)hipGetLastError();
-    rav_drop_graph(ctx);
-    ctx->graph_failed = true;
-  }
   vcycle(ctx, lf, true);
   residual(ctx, lf, true);
 }
+
+void solve_cycle(rav_ctx* ctx) { rav_graph_cycle(ctx, issue_cycle); }
 
 rav_status need_factors(rav_ctx* ctx) {
   if (!st(ctx)->have_factors) return rav_set_error(ctx, RAV_EINVAL, "rav_factor_patches has not been called");
