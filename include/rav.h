@@ -331,9 +331,10 @@ rav_status rav_stream_copy(void* hip_stream, double* dst_dev, const double* src_
  * rav_destroy; the others return RAV_EUNSUPPORTED. */
 rav_status rav_create_adaptive(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
                                long lattice, void* hip_stream, rav_ctx** out);
-/* Sizes of grid `level` into info_host[4]: regular vertices, stored operator
- * entries (vertex pairs, padded to 64-vertex slices), stored patch entries,
- * MV colours (0 on the coarsest grid). */
+/* Sizes of grid `level` into info_host[6]: regular vertices, stored operator
+ * entries (vertex pairs, padded to 64-vertex slices), stored patch entries
+ * (padded likewise), MV colours (0 on the coarsest grid), operator entries
+ * and patch entries without the padding. */
 rav_status rav_adaptive_level_info(const rav_ctx* ctx, int level, long* info_host);
 
 /* Host-only (touches no device, works without a GPU): the set-up that

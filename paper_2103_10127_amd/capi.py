@@ -369,8 +369,9 @@ class AdaptiveHierarchy(Hierarchy):
         self.dim, self.n_levels = 2, len(grids)
 
     def level_info(self, level):
-        """(vertices, stored operator entries, stored patch entries, MV colours)."""
-        out = (_L * 4)()
+        """(vertices, stored operator entries, stored patch entries, MV colours,
+        operator entries and patch entries without padding)."""
+        out = (_L * 6)()
         self._chk(self.lib.rav_adaptive_level_info(self.h, level, out))
         return tuple(int(v) for v in out)
 

@@ -11,7 +11,9 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
@@ -44,6 +46,7 @@ struct rav_ad_state {
     double *x = nullptr, *b = nullptr, *r = nullptr, *partials = nullptr;
     int nres = 0;
     long long pnnz = 0, kfull_n = 0;
+    long long nnz_true = 0, pnnz_true = 0;   // entries without the slice padding
     // host copies for the patch getters
     std::vector<int> h_poff, h_pv, h_pown;
   };
@@ -72,6 +75,19 @@ struct Wt {
   int v;
   double w;
 };
+
+// f(0) .. f(n-1) on the host's cores (set-up only).
+template <class F>
+void parallel_for(int n, F f) {
+  const int nt = std::max(1, std::min(n, (int)std::thread::hardware_concurrency()));
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&] {
+      for (int i = next++; i < n; i = next++) f(i);
+    });
+  for (auto& t : th) t.join();
+}
 
 // ---- host set-up ---------------------------------------------------------------
 // Grid topology: regular vertices, hanging nodes and the regular-vertex weights
@@ -187,17 +203,52 @@ struct Topo {
   }
 };
 
+// Rows of small integer lists, filled in two passes (count, then fill) by a
+// generator that emits (row, value) pairs; rows optionally sorted and made
+// unique.
+struct Csr {
+  std::vector<long long> ptr;
+  std::vector<int> idx;
+  int len(int i) const { return (int)(ptr[i + 1] - ptr[i]); }
+  const int* begin(int i) const { return idx.data() + ptr[i]; }
+  const int* end(int i) const { return idx.data() + ptr[i + 1]; }
+};
+
+template <class Gen>
+Csr build_csr(int nrows, Gen gen, bool sort_unique) {
+  Csr c;
+  c.ptr.assign(nrows + 1, 0);
+  gen([&](int r, int) { ++c.ptr[r + 1]; });
+  for (int i = 0; i < nrows; ++i) c.ptr[i + 1] += c.ptr[i];
+  c.idx.resize(c.ptr.back());
+  std::vector<long long> pos(c.ptr.begin(), c.ptr.end() - 1);
+  gen([&](int r, int v) { c.idx[pos[r]++] = v; });
+  if (!sort_unique) return c;
+  long long w = 0, a = c.ptr[0];
+  for (int i = 0; i < nrows; ++i) {
+    const long long b = c.ptr[i + 1];
+    std::sort(c.idx.begin() + a, c.idx.begin() + b);
+    const long long e = std::unique(c.idx.begin() + a, c.idx.begin() + b) - c.idx.begin();
+    c.ptr[i] = w;
+    for (long long k = a; k < e; ++k) c.idx[w++] = c.idx[k];
+    a = b;
+  }
+  c.ptr[nrows] = w;
+  c.idx.resize(w);
+  return c;
+}
+
 // Host image of one level, uploaded as a whole.
 struct HostLevel {
   int nV = 0;
   std::vector<unsigned char> vmask;
-  std::vector<std::vector<int>> nbr;   // structural columns of every vertex row
+  Csr nbr;                             // structural columns of every vertex row
   std::vector<int> soff, col;
   std::vector<double> val;             // 6 planes
   long long nnz = 0;
   std::vector<double> blid;            // lid lifting (finest grid)
   // patches
-  std::vector<std::vector<int>> pall;  // all vertices of patch i (MV colouring)
+  Csr pall;                            // all vertices of patch i (MV colouring)
   std::vector<int> poff, pv, pown;
   std::vector<long long> koff;
   long long pnnz = 0;
@@ -236,19 +287,16 @@ bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, st
     H.vmask[v] = (x == 0 || y == 0 || x == M || y == M) ? 1 : 0;
     is_lid[v] = (y == M && x > 0 && x < M) ? 1 : 0;
   }
-  H.nbr.assign(nV, {});
   std::vector<int> ve;
-  for (long long e = 0; e < g.nl; ++e) {
-    g.leaf_verts(e, ve);
-    for (int i : ve) H.nbr[i].insert(H.nbr[i].end(), ve.begin(), ve.end());
-  }
+  H.nbr = build_csr(nV, [&](auto&& emit) {
+    for (long long e = 0; e < g.nl; ++e) {
+      g.leaf_verts(e, ve);
+      for (int i : ve)
+        for (int j : ve) emit(i, j);
+    }
+  }, true);
   std::vector<int> len(nV);
-  for (int v = 0; v < nV; ++v) {
-    auto& r = H.nbr[v];
-    std::sort(r.begin(), r.end());
-    r.erase(std::unique(r.begin(), r.end()), r.end());
-    len[v] = (int)r.size();
-  }
+  for (int v = 0; v < nV; ++v) len[v] = H.nbr.len(v);
   H.soff = sell_offsets(nV, len);
   if ((long long)H.soff.back() >= (long long)INT_MAX / 2) { err = "grid too large"; return false; }
   H.nnz = H.soff.back();
@@ -256,7 +304,7 @@ bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, st
   H.val.assign(6 * H.nnz, 0.0);
   for (int v = 0; v < nV; ++v) {
     const int w = (H.soff[v / AD_SLICE + 1] - H.soff[v / AD_SLICE]) / AD_SLICE;
-    for (int k = 0; k < w; ++k) H.col[sell_slot(H.soff, v, k)] = k < len[v] ? H.nbr[v][k] : v;
+    for (int k = 0; k < w; ++k) H.col[sell_slot(H.soff, v, k)] = k < len[v] ? H.nbr.begin(v)[k] : v;
   }
   double Ar[4][4], Br[2][4][4], Cr[4][4];
   for (int a = 0; a < 4; ++a)
@@ -273,12 +321,13 @@ bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, st
       for (int ca = g.cw_ptr[4 * e + a]; ca < g.cw_ptr[4 * e + a + 1]; ++ca) {
         const int i = g.cw[ca].v;
         const double wi = g.cw[ca].w;
-        const auto& row = H.nbr[i];
+        const int* row = H.nbr.begin(i);
+        const int* rend = H.nbr.end(i);
         for (int b = 0; b < 4; ++b)
           for (int cb = g.cw_ptr[4 * e + b]; cb < g.cw_ptr[4 * e + b + 1]; ++cb) {
             const int j = g.cw[cb].v;
             const double ww = wi * g.cw[cb].w;
-            const int k = (int)(std::lower_bound(row.begin(), row.end(), j) - row.begin());
+            const int k = (int)(std::lower_bound(row, rend, j) - row);
             const long long s = sell_slot(H.soff, i, k);
             H.val[AD_A * P + s] += ww * eta * Ar[a][b];
             H.val[AD_BTX * P + s] += ww * sB * Br[0][a][b];
@@ -293,7 +342,7 @@ bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, st
     H.blid.assign(3LL * nV, 0.0);
     for (int i = 0; i < nV; ++i)
       for (int k = 0; k < len[i]; ++k) {
-        const int j = H.nbr[i][k];
+        const int j = H.nbr.begin(i)[k];
         if (!is_lid[j]) continue;
         const long long s = sell_slot(H.soff, i, k);
         if (!H.vmask[i]) H.blid[i] -= H.val[AD_A * P + s];
@@ -302,7 +351,7 @@ bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, st
   }
   for (int i = 0; i < nV; ++i)
     for (int k = 0; k < len[i]; ++k) {
-      const int j = H.nbr[i][k];
+      const int j = H.nbr.begin(i)[k];
       const long long s = sell_slot(H.soff, i, k);
       if (H.vmask[i]) { H.val[AD_A * P + s] = 0.0; H.val[AD_BTX * P + s] = 0.0; H.val[AD_BTY * P + s] = 0.0; }
       if (H.vmask[j]) { H.val[AD_A * P + s] = 0.0; H.val[AD_BX * P + s] = 0.0; H.val[AD_BY * P + s] = 0.0; }
@@ -317,26 +366,25 @@ bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, st
 // patch whose vertex set meets the row pattern of its own vertices.
 bool build_patches(const Topo& g, HostLevel& H, std::string& err) {
   const int nV = H.nV;
-  std::vector<std::vector<int>> touch(nV);
-  for (long long e = 0; e < g.nl; ++e) {
-    const long long x0 = g.leaf[3 * e], y0 = g.leaf[3 * e + 1], s = g.leaf[3 * e + 2];
-    for (int a = 0; a < 4; ++a) {
-      const int r = g.find_reg(g.key(x0 + (a & 1) * s, y0 + (a >> 1) * s));
-      if (r >= 0) touch[r].push_back((int)e);
+  // vertices of patch i: the vertices the corners of the leaves around i depend on
+  H.pall = build_csr(nV, [&](auto&& emit) {
+    for (long long e = 0; e < g.nl; ++e) {
+      const long long x0 = g.leaf[3 * e], y0 = g.leaf[3 * e + 1], s = g.leaf[3 * e + 2];
+      for (int a = 0; a < 4; ++a) {
+        const int r = g.find_reg(g.key(x0 + (a & 1) * s, y0 + (a >> 1) * s));
+        if (r < 0) continue;
+        for (int c = g.cw_ptr[4 * e]; c < g.cw_ptr[4 * e + 4]; ++c) emit(r, g.cw[c].v);
+      }
     }
-  }
-  H.pall.assign(nV, {});
-  std::vector<std::vector<int>> pfree(nV);
+  }, true);
+  Csr pfree = build_csr(nV, [&](auto&& emit) {
+    for (int i = 0; i < nV; ++i)
+      for (const int* v = H.pall.begin(i); v != H.pall.end(i); ++v)
+        if (!H.vmask[*v]) emit(i, *v);
+  }, false);
   std::vector<int> len(nV);
   for (int i = 0; i < nV; ++i) {
-    auto& V = H.pall[i];
-    for (int e : touch[i])
-      for (int c = g.cw_ptr[4 * e]; c < g.cw_ptr[4 * e + 4]; ++c) V.push_back(g.cw[c].v);
-    std::sort(V.begin(), V.end());
-    V.erase(std::unique(V.begin(), V.end()), V.end());
-    for (int v : V)
-      if (!H.vmask[v]) pfree[i].push_back(v);
-    len[i] = (int)pfree[i].size();
+    len[i] = pfree.len(i);
     if (len[i] > AD_NFMAX) { err = "a patch has more than 16 free velocity vertices"; return false; }
   }
   H.poff = sell_offsets(nV, len);
@@ -349,35 +397,38 @@ bool build_patches(const Topo& g, HostLevel& H, std::string& err) {
     const long long w = (H.poff[s + 1] - H.poff[s]) / AD_SLICE;
     H.koff[s + 1] = H.koff[s] + AD_SLICE * w * w;
   }
-  std::vector<std::vector<int>> tslots(nV);
   for (int i = 0; i < nV; ++i)
     for (int k = 0; k < len[i]; ++k) {
-      const int v = pfree[i][k];
-      const long long slot = sell_slot(H.poff, i, k);
-      H.pv[slot] = v;
+      const int v = pfree.begin(i)[k];
+      H.pv[sell_slot(H.poff, i, k)] = v;
       if (v == i) H.pown[i] = k;
-      tslots[v].push_back((int)slot);
     }
+  // AV gather lists: the slots that hold vertex v, in patch order
+  Csr tslots = build_csr(nV, [&](auto&& emit) {
+    for (int i = 0; i < nV; ++i)
+      for (int k = 0; k < len[i]; ++k) emit(pfree.begin(i)[k], (int)sell_slot(H.poff, i, k));
+  }, false);
   std::vector<int> tl(nV);
-  for (int v = 0; v < nV; ++v) tl[v] = (int)tslots[v].size();
+  for (int v = 0; v < nV; ++v) tl[v] = tslots.len(v);
   H.tsoff = sell_offsets(nV, tl);
   H.tpos.assign(H.tsoff.back(), -1);
   for (int v = 0; v < nV; ++v)
-    for (int k = 0; k < tl[v]; ++k) H.tpos[sell_slot(H.tsoff, v, k)] = tslots[v][k];
+    for (int k = 0; k < tl[v]; ++k) H.tpos[sell_slot(H.tsoff, v, k)] = tslots.begin(v)[k];
   // MV colouring
-  std::vector<std::vector<int>> holders(nV);   // patches whose vertex set holds v
-  for (int i = 0; i < nV; ++i)
-    for (int v : H.pall[i]) holders[v].push_back(i);
+  Csr holders = build_csr(nV, [&](auto&& emit) {   // patches whose vertex set holds v
+    for (int i = 0; i < nV; ++i)
+      for (const int* v = H.pall.begin(i); v != H.pall.end(i); ++v) emit(*v, i);
+  }, false);
   std::vector<int> colour(nV, -1), stamp(nV, -1);
   int ncol = 0;
   for (int i = 0; i < nV; ++i) {
     uint64_t banned = 0;
-    for (int v : H.pall[i])
-      for (int u : H.nbr[v]) {
-        if (stamp[u] == i) continue;
-        stamp[u] = i;
-        for (int q : holders[u])
-          if (q < i) banned |= 1ull << colour[q];
+    for (const int* v = H.pall.begin(i); v != H.pall.end(i); ++v)
+      for (const int* u = H.nbr.begin(*v); u != H.nbr.end(*v); ++u) {
+        if (stamp[*u] == i) continue;
+        stamp[*u] = i;
+        for (const int* q = holders.begin(*u); q != holders.end(*u); ++q)
+          if (*q < i) banned |= 1ull << colour[*q];
       }
     int c = 0;
     while (c < 64 && ((banned >> c) & 1ull)) ++c;
@@ -589,9 +640,9 @@ rav_status build_coarse(rav_ctx* ctx, const HostLevel& H) {
   S->nb = nb;
   std::vector<double> M((size_t)(nb * nb), 0.0);
   for (int i = 0; i < H.nV; ++i) {
-    const int w = (int)H.nbr[i].size();
+    const int w = H.nbr.len(i);
     for (int k = 0; k < w; ++k) {
-      const int j = H.nbr[i][k];
+      const int j = H.nbr.begin(i)[k];
       const long long s = sell_slot(H.soff, i, k);
       M[(size_t)(i * nb + j)] += H.val[AD_A * P + s];
       M[(size_t)((nV + i) * nb + nV + j)] += H.val[AD_A * P + s];
@@ -641,6 +692,8 @@ rav_status upload_level(rav_ctx* ctx, Level& L, const HostLevel& H, bool smoothe
   long long masked = 0;
   for (unsigned char m : H.vmask) masked += m;
   L.nfree = 3LL * H.nV - 2 * masked;
+  L.nnz_true = (long long)H.nbr.idx.size();
+  for (int v : H.pv) L.pnnz_true += v >= 0;
   ACK(upload(&L.vmask, H.vmask));
   ACK(upload(&L.soff, H.soff));
   ACK(upload(&L.col, H.col));
@@ -727,14 +780,19 @@ bool build_topos(const rav_problem_desc* d, const int* leaves, const long* n_lea
     first[l + 1] = first[l] + n_leaves[l];
   }
   topo.assign(nl, Topo());
-  for (int l = 0; l < nl; ++l) {
+  std::vector<std::string> errs(nl);
+  parallel_for(nl, [&](int t) {
+    const int l = nl - 1 - t;   // largest grids first
     const int* lv = leaves + 3 * first[l];
     std::string e2;
-    if (!check_leaves(lv, n_leaves[l], lattice, e2) || !topo[l].build(lv, n_leaves[l], lattice)) {
-      err = "grid " + std::to_string(l) + ": " + (e2.empty() ? topo[l].err : e2);
+    if (!check_leaves(lv, n_leaves[l], lattice, e2) || !topo[l].build(lv, n_leaves[l], lattice))
+      errs[l] = "grid " + std::to_string(l) + ": " + (e2.empty() ? topo[l].err : e2);
+  });
+  for (int l = 0; l < nl; ++l)
+    if (!errs[l].empty()) {
+      err = errs[l];
       return false;
     }
-  }
   if (3LL * topo[0].nV() + 1 > MAX_COARSE) {
     err = "coarsest grid too large for the dense direct solve";
     return false;
@@ -771,24 +829,30 @@ rav_status rav_ad_create(const rav_problem_desc* d, const int* leaves, const lon
   rav_ad_state* S = ctx->ad;
   S->mode = d->smoother == RAV_SMOOTHER_RAV ? AD_RAV : AD_FULL;
   S->lv.resize(nl);
+  std::vector<HostLevel> hosts(nl);
+  std::vector<std::string> errs(nl);
+  parallel_for(nl, [&](int t) {
+    const int l = nl - 1 - t;
+    HostLevel& H = hosts[l];
+    std::string e2;
+    if (!assemble(topo[l], d->beta, d->eta_out, l == nl - 1, H, e2) ||
+        (l > 0 && (!build_patches(topo[l], H, e2) || !build_transfer(topo[l], topo[l - 1], H, topo[l - 1].nV(), e2))))
+      errs[l] = "grid " + std::to_string(l) + ": " + e2;
+  });
+  for (int l = 0; l < nl; ++l)
+    if (!errs[l].empty()) {
+      ctx->err = errs[l];
+      return fail(errs[l].find("more than") != std::string::npos ? RAV_EUNSUPPORTED : RAV_EINVAL);
+    }
   for (int l = 0; l < nl; ++l) {
-    HostLevel H;
-    if (!assemble(topo[l], d->beta, d->eta_out, l == nl - 1, H, err)) {
-      ctx->err = err;
-      return fail(RAV_EINVAL);
-    }
-    if (l > 0) {
-      if (!build_patches(topo[l], H, err) || !build_transfer(topo[l], topo[l - 1], H, topo[l - 1].nV(), err)) {
-        ctx->err = "grid " + std::to_string(l) + ": " + err;
-        return fail(err.find("more than") != std::string::npos ? RAV_EUNSUPPORTED : RAV_EINVAL);
-      }
-    }
+    HostLevel& H = hosts[l];
     if ((s = upload_level(ctx, S->lv[l], H, l > 0, l > 0)) != RAV_OK) return fail(s);
     if (l == nl - 1) {
       hipError_t e = upload(&S->blid, H.blid);
       if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
     }
     if (l == 0 && (s = build_coarse(ctx, H)) != RAV_OK) return fail(s);
+    H = HostLevel();
   }
   *out = ctx;
   return RAV_OK;
@@ -1118,7 +1182,8 @@ rav_status rav_ad_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const
   return RAV_OK;
 }
 
-// Grid statistics for the host: vertices, operator entries (padded), MV colours.
+// Grid statistics for the host: vertices, operator and patch entries (padded), MV colours, and the
+// operator and patch entries without padding.
 rav_status rav_ad_level_info(const rav_ctx* ctx, int level, long* info) {
   if (check_lv(ctx, level, false) != RAV_OK || !info) return RAV_EINVAL;
   const Level& L = st(ctx)->lv[level];
@@ -1126,6 +1191,8 @@ rav_status rav_ad_level_info(const rav_ctx* ctx, int level, long* info) {
   info[1] = (long)L.dev.nnz;
   info[2] = (long)L.pnnz;
   info[3] = L.cstart.empty() ? 0 : (long)L.cstart.size() - 1;
+  info[4] = (long)L.nnz_true;
+  info[5] = (long)L.pnnz_true;
   return RAV_OK;
 }
 
@@ -1149,8 +1216,8 @@ rav_status rav_ad_host_export(const rav_problem_desc* d, const int* leaves, cons
     if (!out) return RAV_OK;
     std::fill(out, out + n * n, 0.0);
     for (long long i = 0; i < nV; ++i)
-      for (size_t k = 0; k < H.nbr[i].size(); ++k) {
-        const long long j = H.nbr[i][k];
+      for (int k = 0; k < H.nbr.len((int)i); ++k) {
+        const long long j = H.nbr.begin((int)i)[k];
         const long long sl = sell_slot(H.soff, (int)i, (int)k);
         out[i * n + j] += H.val[AD_A * P + sl];
         out[(nV + i) * n + nV + j] += H.val[AD_A * P + sl];
