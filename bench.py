@@ -86,6 +86,8 @@ def parse():
                          "cycles and time to 1e-8 on 32^2 (damping sweep) and 512^2; cavity: driven cavity, "
                          "smoothing-steps and mesh studies; q1q1: the stabilized Q1-Q1 driven cavity on 1024^2; "
                          "adaptive: the cavity on the adaptive grids of Table 1, RAV/MV/AV on every grid (Fig. 5)")
+    ap.add_argument("--quick", action="store_true",
+                    help="adaptive: only the Omega^10 RAV solve and its kernel times (for profiling)")
     ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--train-lr", type=float, default=1e-3)
     return ap.parse_args()
@@ -324,21 +326,7 @@ def main():
     }
 
     if args.copy_calibration:
-        from paper_2103_10127_amd import stream_copy
-        n = (1 << 30) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            stream_copy(dst, src)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(10):
-            stream_copy(dst, src)
-        ev1.record()
-        torch.cuda.synchronize()
-        out["copy_GBs"] = 2 * n * 8 * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
-        del src, dst
+        out["copy_GBs"] = _copy_calibration()
 
     if not args.no_mixed:
         H.close()
@@ -366,6 +354,26 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(out))
+
+
+def _copy_calibration() -> float:
+    """Launches the plain copy kernel on 1 GiB (13 times): the reference whose
+    HBM counter readings scale the PMC traffic summaries.  Returns its GB/s."""
+    import torch
+    from paper_2103_10127_amd import stream_copy
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        stream_copy(dst, src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        stream_copy(dst, src)
+    ev1.record()
+    torch.cuda.synchronize()
+    return 2 * n * 8 * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
 
 
 def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
@@ -756,8 +764,11 @@ def bench_adaptive(args):
 
     main = run(n_grids, "rav", 0.66, reps=3, sweep_times=True)
     print(f"adaptive Omega^10 RAV: {main['cycles']} cycles, {main['ms']:.1f} ms", file=sys.stderr, flush=True)
+    extra = {}
+    if args.copy_calibration:
+        extra["copy_GBs"] = _copy_calibration()
     study = []
-    for k in range(2, n_grids + 1):
+    for k in (range(2, n_grids + 1) if not args.quick else ()):
         for sm_, om in (("rav", 0.66), ("mv", 0.66), ("av", 0.1)):
             study.append(main if (k == n_grids and sm_ == "rav") else run(k, sm_, om, sweep_times=k == n_grids))
             r = study[-1]
@@ -771,6 +782,8 @@ def bench_adaptive(args):
     app_bytes = 28 * pnnz + 12 * nV + 24 * nV + 48 * nV
     ach_res = res_bytes / (main["ms_residual"] * 1e-3) / 1e9
     ach_app = app_bytes / (main["ms_apply"] * 1e-3) / 1e9
+    from paper_2103_10127_amd.profiling import ADAPTIVE_SOURCES, read_traffic
+    traffic = read_traffic(os.path.join(ROOT, "profiles", "rav_apply_adaptive_omega10_traffic.md"), ADAPTIVE_SOURCES)
     _line("RAV smoothed DoFs/s (whole V(3,3) solve to a 1e-8 residual reduction, adaptive grids)",
           main["smoothed_dofs"] / (1e-3 * main["ms"]), "DoF/s", 3, 1, main["ms"], "f64",
           {"workload": "2D driven cavity, stabilized Q1-Q1 (beta 0.05) on the adaptive quadtree hierarchy "
@@ -778,12 +791,12 @@ def bench_adaptive(args):
                        "omega 0.66"},
           data="synthetic (the Table 1 grids from the boundary-band refinement rule, lid velocity 1)",
           roofline={"bound": "hbm", "kernel": "k_ad_rav (Omega^10)", "achieved": ach_app, "peak": 8000.0,
-                    "unit": "GB/s", "frac": ach_app / 8000.0, "traffic": None, "algorithmic_bytes": app_bytes},
+                    "unit": "GB/s", "frac": ach_app / 8000.0, "traffic": traffic, "algorithmic_bytes": app_bytes},
           roofline_residual={"bound": "hbm", "kernel": "k_ad_residual (Omega^10)", "achieved": ach_res,
                              "peak": 8000.0, "unit": "GB/s", "frac": ach_res / 8000.0, "algorithmic_bytes": res_bytes},
           omega10={"vertices": nV, "operator_entries": nnz, "operator_entries_padded": nnz_pad,
                    "patch_entries": pnnz, "patch_entries_padded": pnnz_pad, "mv_colours": ncol},
-          rav_omega10=main, fig5_study=study)
+          rav_omega10=main, fig5_study=study, **extra)
 
 
 def bench_1024(args):

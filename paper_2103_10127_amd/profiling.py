@@ -8,8 +8,9 @@
 both including the 1 GiB copy of `bench.py --copy-calibration`) into HBM bytes
 per launch of the largest-grid launch group of the matched kernel: each counter
 is scaled by (bytes the copy moves) / (what the counter reads for the copy).
-The summary records a hash of the kernel's sources; `bench.py` reports the
-traffic only while the sources still hash to it.
+The summary records a hash of the kernel's sources (`--sources apply`: the
+uniform-grid apply, `--sources adaptive`: the adaptive-grid kernels);
+`bench.py` reports the traffic only while the sources still hash to it.
 
 A kernel is launched on every level of the hierarchy with a different grid
 size, so launches are grouped by (kernel name, grid size): the group with the
@@ -37,6 +38,7 @@ def _col(header, *cands):
 
 
 def _short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
     name = name.split("(")[0] if "(" in name and "<" not in name.split("(")[0] else name
     return name[:110]
 
@@ -91,20 +93,21 @@ def counter_summary(path: str, match: str | None = None):
 COPY_GRID = 16777216          # launch grid of the 1 GiB calibration copy
 COPY_KIB = (1 << 30) / 1024   # bytes the copy reads (and writes), in KiB
 TRAFFIC_SOURCES = ("csrc/k_apply.hip", "csrc/rav_internal.h", "csrc/rav_index.h")
+ADAPTIVE_SOURCES = ("csrc/k_adapt.hip", "csrc/rav_adapt.h")
 
 
-def sources_hash() -> str:
+def sources_hash(sources=TRAFFIC_SOURCES) -> str:
     import hashlib
     import os
     h = hashlib.sha256()
     here = os.path.dirname(os.path.abspath(__file__))
-    for rel in TRAFFIC_SOURCES:
+    for rel in sources:
         with open(os.path.join(here, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def traffic_summary(fetch_csv: str, write_csv: str, match: str) -> dict:
+def traffic_summary(fetch_csv: str, write_csv: str, match: str, sources=TRAFFIC_SOURCES) -> dict:
     out = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = counter_summary(path)
@@ -118,22 +121,22 @@ def traffic_summary(fetch_csv: str, write_csv: str, match: str) -> dict:
                             kib=k[counter], copy_kib=copy[0][counter], factor=factor,
                             bytes=k[counter] * factor * 1024)
     out["traffic_bytes"] = out["FETCH_SIZE"]["bytes"] + out["WRITE_SIZE"]["bytes"]
-    out["sources_sha256"] = sources_hash()
+    out["sources_sha256"] = sources_hash(sources)
     return out
 
 
-def read_traffic(path: str):
+def read_traffic(path: str, sources=TRAFFIC_SOURCES):
     """Traffic per launch from a committed summary, or None when it is missing
     or the kernel sources changed since the counters were taken."""
     import os
     if not os.path.exists(path):
         return None
     fields = {}
-    for line in open(path):
+    for line in open(path):   # the first kernel of a summary is the one reported
         if ":" in line and line.startswith("    "):
             k, v = line.strip().split(":", 1)
-            fields[k.strip()] = v.strip()
-    if fields.get("sources_sha256") != sources_hash():
+            fields.setdefault(k.strip(), v.strip())
+    if fields.get("sources_sha256") != sources_hash(sources):
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
@@ -148,6 +151,8 @@ def main():
     ap.add_argument("path2", nargs="?")
     ap.add_argument("--match", default=None)
     ap.add_argument("--top", type=int, default=25)
+    ap.add_argument("--sources", default="apply", choices=["apply", "adaptive"],
+                    help="kernel sources whose hash the traffic summary records")
     a = ap.parse_args()
     if a.mode == "trace":
         res = trace_summary(a.path, a.match)
@@ -159,7 +164,8 @@ def main():
         for r in counter_summary(a.path, a.match)[: a.top]:
             print(r)
     else:
-        t = traffic_summary(a.path, a.path2, a.match)
+        t = traffic_summary(a.path, a.path2, a.match,
+                            ADAPTIVE_SOURCES if a.sources == "adaptive" else TRAFFIC_SOURCES)
         f, w = t["FETCH_SIZE"], t["WRITE_SIZE"]
         print(f"kernel: {f['kernel']} (grid {f['grid']}, {f['dispatches']} dispatches averaged)")
         for c, r in (("FETCH_SIZE", f), ("WRITE_SIZE", w)):
