@@ -773,13 +773,17 @@ def bench_adaptive(args):
             study.append(main if (k == n_grids and sm_ == "rav") else run(k, sm_, om, sweep_times=k == n_grids))
             r = study[-1]
             print(f"  Omega^{k} {sm_}: {r['cycles']} cycles, {r['ms']:.1f} ms", file=sys.stderr, flush=True)
-    nV, nnz_pad, pnnz_pad, ncol, nnz, pnnz = main["level_info"]
-    # per launch on Omega^10: operator entries (column index + 6 values), x read
-    # once, b read and r written (3 fields each); apply: per patch entry the
-    # vertex index and three values (K^-1 row, z_x, z_y), per patch 1/S and the
-    # owned position, r read once, x read and written
-    res_bytes = 52 * nnz + 72 * nV
-    app_bytes = 28 * pnnz + 12 * nV + 24 * nV + 48 * nV
+    info = main["level_info"]
+    nV, nnz, pnnz = info["vertices"], info["operator_entries"], info["patch_entries"]
+    wide = info["wide"]
+    # per launch on Omega^10: residual: one packed word per operator entry
+    # (column offset + value-tuple id; 8 bytes in the wide format), x read once,
+    # b read and r written (3 fields each), the mask byte; apply: one 16-bit
+    # vertex offset per patch entry (4 bytes wide), the configuration id, r read
+    # once, x read and written.  The value and configuration tables (a few
+    # hundred entries) stay in cache and are not counted.
+    res_bytes = (8 if wide else 4) * nnz + 73 * nV
+    app_bytes = (4 if wide else 2) * pnnz + 76 * nV
     ach_res = res_bytes / (main["ms_residual"] * 1e-3) / 1e9
     ach_app = app_bytes / (main["ms_apply"] * 1e-3) / 1e9
     from paper_2103_10127_amd.profiling import ADAPTIVE_SOURCES, read_traffic
@@ -794,8 +798,7 @@ def bench_adaptive(args):
                     "unit": "GB/s", "frac": ach_app / 8000.0, "traffic": traffic, "algorithmic_bytes": app_bytes},
           roofline_residual={"bound": "hbm", "kernel": "k_ad_residual (Omega^10)", "achieved": ach_res,
                              "peak": 8000.0, "unit": "GB/s", "frac": ach_res / 8000.0, "algorithmic_bytes": res_bytes},
-          omega10={"vertices": nV, "operator_entries": nnz, "operator_entries_padded": nnz_pad,
-                   "patch_entries": pnnz, "patch_entries_padded": pnnz_pad, "mv_colours": ncol},
+          omega10=info,
           rav_omega10=main, fig5_study=study, **extra)
 
 

@@ -331,10 +331,14 @@ rav_status rav_stream_copy(void* hip_stream, double* dst_dev, const double* src_
  * rav_destroy; the others return RAV_EUNSUPPORTED. */
 rav_status rav_create_adaptive(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
                                long lattice, void* hip_stream, rav_ctx** out);
-/* Sizes of grid `level` into info_host[6]: regular vertices, stored operator
+/* Sizes of grid `level` into info_host[9]: regular vertices, stored operator
  * entries (vertex pairs, padded to 64-vertex slices), stored patch entries
  * (padded likewise), MV colours (0 on the coarsest grid), operator entries
- * and patch entries without the padding. */
+ * and patch entries without the padding, distinct operator value tuples,
+ * patch configurations (patches with equal local matrices share one stored
+ * factorization; 0 on the coarsest grid), and the entry format (0: one
+ * 32-bit word per entry and 16-bit patch offsets; 1: 32-bit columns, ids and
+ * patch vertices, used when an offset or id does not fit 16 bits). */
 rav_status rav_adaptive_level_info(const rav_ctx* ctx, int level, long* info_host);
 
 /* Host-only (touches no device, works without a GPU): the set-up that

@@ -369,11 +369,13 @@ class AdaptiveHierarchy(Hierarchy):
         self.dim, self.n_levels = 2, len(grids)
 
     def level_info(self, level):
-        """(vertices, stored operator entries, stored patch entries, MV colours,
-        operator entries and patch entries without padding)."""
-        out = (_L * 6)()
+        """dict: vertices, stored (padded) and true operator and patch entries,
+        MV colours, distinct value tuples, patch configurations, entry format."""
+        out = (_L * 9)()
         self._chk(self.lib.rav_adaptive_level_info(self.h, level, out))
-        return tuple(int(v) for v in out)
+        keys = ("vertices", "operator_entries_padded", "patch_entries_padded", "mv_colours", "operator_entries",
+                "patch_entries", "value_tuples", "patch_configurations", "wide")
+        return dict(zip(keys, (int(v) for v in out)))
 
 
 def adaptive_host_export(grids, lattice, level, what, beta=0.05, eta=1.0):

@@ -16,21 +16,41 @@ namespace {
 
 inline unsigned nblk(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
-__device__ __forceinline__ double plane(const AdDev& a, int p, long long e) { return a.val[p * a.nnz + e]; }
+// Entry e of the row of vertex i: column j and tuple id.
+template <bool WIDE>
+__device__ __forceinline__ void entry(const AdDev& a, int i, long long e, int& j, int& id) {
+  const unsigned w = a.ent[e];
+  if (WIDE) {
+    j = a.col[e];
+    id = (int)w;
+  } else {
+    j = i + ((int)w >> a.id_bits);   // arithmetic shift keeps the offset's sign
+    id = (int)(w & ((1u << a.id_bits) - 1u));
+  }
+}
 
-// Value of plane p at (row vertex v, column vertex j); 0 if j is not in the row.
+// Patch vertex k of patch i (slot e).
+template <bool WIDE>
+__device__ __forceinline__ int patch_vertex(const AdDev& a, int, long long e) {
+  return a.pv[e];
+}
+
+// Value of field p at (row vertex v, column vertex j); 0 if j is not in the row.
+template <bool WIDE>
 __device__ double lookup(const AdDev& a, int v, int j, int p) {
   const int e0 = a.soff[v >> 6], w = (a.soff[(v >> 6) + 1] - e0) >> 6;
   const int t = v & 63;
   double out = 0.0;
   for (int k = 0; k < w; ++k) {
-    const long long e = e0 + 64LL * k + t;
-    if (a.col[e] == j) out += plane(a, p, e);   // one entry per column; padding entries hold 0
+    int jj, id;
+    entry<WIDE>(a, v, e0 + 64LL * k + t, jj, id);
+    if (jj == j) out += a.vtab[8 * id + p];   // one entry per column; padding entries hold zeros
   }
   return out;
 }
 
 // ---- residual: one thread per vertex, its three rows -------------------------
+template <bool WIDE>
 __global__ __launch_bounds__(256) void k_ad_residual(AdDev a, const double* __restrict__ x,
                                                      const double* __restrict__ b, double* __restrict__ r,
                                                      double* __restrict__ partials) {
@@ -42,12 +62,14 @@ __global__ __launch_bounds__(256) void k_ad_residual(AdDev a, const double* __re
     const int t = i & 63;
     double su = 0.0, sv = 0.0, sp = 0.0;
     for (int k = 0; k < w; ++k) {
-      const long long e = e0 + 64LL * k + t;
-      const int j = a.col[e];
+      int j, id;
+      entry<WIDE>(a, i, e0 + 64LL * k + t, j, id);
+      const double2* vt = reinterpret_cast<const double2*>(a.vtab + 8 * id);
+      const double2 v01 = vt[0], v23 = vt[1], v45 = vt[2];   // (A, BTx), (BTy, Bx), (By, C)
       const double uj = x[j], vj = x[nV + j], pj = x[2 * nV + j];
-      su += a.val[e] * uj + a.val[AD_BTX * a.nnz + e] * pj;
-      sv += a.val[e] * vj + a.val[AD_BTY * a.nnz + e] * pj;
-      sp += a.val[AD_BX * a.nnz + e] * uj + a.val[AD_BY * a.nnz + e] * vj + a.val[AD_C * a.nnz + e] * pj;
+      su += v01.x * uj + v01.y * pj;
+      sv += v01.x * vj + v23.x * pj;
+      sp += v23.y * uj + v45.x * vj + v45.y * pj;
     }
     const bool vm = a.vmask[i] != 0;
     const double ru = vm ? 0.0 : b[i] - su;
@@ -69,44 +91,49 @@ __global__ __launch_bounds__(256) void k_ad_residual(AdDev a, const double* __re
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-// ---- patch factorization: one 64-lane block per patch ------------------------
+// ---- patch factorization: one 64-lane block per configuration ----------------
 // Gauss-Jordan elimination without pivoting on [K | b_x b_y | I] (K SPD,
 // padded to AD_NFMAX with identity rows), giving z_c = K^{-1} b_c and K^{-1};
-// then S = c - b_x.z_x - b_y.z_y (negative: c < 0 and K^{-1} SPD).
+// then S = c - b_x.z_x - b_y.z_y (negative: c < 0 and K^{-1} SPD).  The
+// matrix is read from the operator at the configuration's representative.
 constexpr int NF = AD_NFMAX;
 constexpr int NCOL = 2 * NF + 2;
 constexpr int KI = NF + 2;
 
-__global__ __launch_bounds__(64) void k_ad_factor(AdDev a, int mode, AdFactors f, int* __restrict__ status) {
+template <bool WIDE>
+__global__ __launch_bounds__(64) void k_ad_factor(AdDev a, int mode, const int* __restrict__ rep, AdFactors f,
+                                                  int* __restrict__ status) {
   __shared__ int verts[NF];
   __shared__ double M[NF][NCOL];
   __shared__ double bsave[2][NF];
   __shared__ double fac[NF];
   __shared__ double cii;
-  const int i = blockIdx.x;
+  const int c = blockIdx.x;
+  const int i = rep[c];
   const int lane = threadIdx.x;
   const int sl = i >> 6, t = i & 63;
-  const int p0 = a.poff[sl], w = (a.poff[sl + 1] - p0) >> 6;
-  if (lane < NF) verts[lane] = lane < w ? a.pv[p0 + 64 * lane + t] : -1;
+  const int p0 = a.poff[sl];
+  const int nf = a.cnf[c];
+  if (lane < NF) verts[lane] = lane < nf ? patch_vertex<WIDE>(a, i, p0 + 64LL * lane + t) : -1;
   __syncthreads();
   for (int idx = lane; idx < NF * NCOL; idx += 64) {
-    const int row = idx / NCOL, c = idx % NCOL;
+    const int row = idx / NCOL, col = idx % NCOL;
     const int vr = verts[row];
     double v;
-    if (c >= KI) {
-      v = (c - KI == row) ? 1.0 : 0.0;
+    if (col >= KI) {
+      v = (col - KI == row) ? 1.0 : 0.0;
     } else if (vr < 0) {
-      v = (c == row) ? 1.0 : 0.0;
-    } else if (c < NF) {
-      const int vc = verts[c];
-      v = vc < 0 ? 0.0 : lookup(a, vr, vc, AD_A);
+      v = (col == row) ? 1.0 : 0.0;
+    } else if (col < NF) {
+      const int vc = verts[col];
+      v = vc < 0 ? 0.0 : lookup<WIDE>(a, vr, vc, AD_A);
     } else {
-      v = lookup(a, vr, i, c == NF ? AD_BTX : AD_BTY);
+      v = lookup<WIDE>(a, vr, i, col == NF ? AD_BTX : AD_BTY);
     }
-    if (c == NF || c == NF + 1) bsave[c - NF][row] = v;
-    M[row][c] = v;
+    if (col == NF || col == NF + 1) bsave[col - NF][row] = v;
+    M[row][col] = v;
   }
-  if (lane == 0) cii = lookup(a, i, i, AD_C);
+  if (lane == 0) cii = lookup<WIDE>(a, i, i, AD_C);
   __syncthreads();
   bool bad = false;
   for (int p = 0; p < NF; ++p) {
@@ -125,60 +152,57 @@ __global__ __launch_bounds__(64) void k_ad_factor(AdDev a, int mode, AdFactors f
   }
   double part = 0.0;
   for (int idx = lane; idx < 2 * NF; idx += 64) {
-    const int c = idx / NF, m = idx % NF;
-    part += bsave[c][m] * M[m][NF + c];
+    const int cc = idx / NF, m = idx % NF;
+    part += bsave[cc][m] * M[m][NF + cc];
   }
   for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
   const double S = cii - part;
   const double sinv = 1.0 / S;
   if (!(S < 0.0) || !isfinite(sinv)) bad = true;
   if (bad && lane == 0) atomicMin(status, i);
-  if (lane < w) {
-    const long long e = p0 + 64LL * lane + t;
-    f.zx[e] = M[lane][NF];
-    f.zy[e] = M[lane][NF + 1];
+  if (lane < NF) {
+    f.zx[c * NF + lane] = M[lane][NF];
+    f.zy[c * NF + lane] = M[lane][NF + 1];
   }
-  if (lane == 0) f.invS[i] = sinv;
+  if (lane == 0) f.invS[c] = sinv;
   if (mode == AD_RAV) {
-    const int ao = a.pown[i];
-    if (lane < w) f.kr[p0 + 64LL * lane + t] = ao >= 0 ? M[ao][KI + lane] : 0.0;
+    const int ao = a.cown[c];
+    if (lane < NF) f.kr[c * NF + lane] = ao >= 0 ? M[ao][KI + lane] : 0.0;
   } else {
-    const long long k0 = a.koff[sl];
-    for (int idx = lane; idx < w * w; idx += 64) {
-      const int r = idx / w, c = idx % w;
-      f.kfull[k0 + 64LL * idx + t] = M[r][KI + c];
-    }
+    for (int idx = lane; idx < NF * NF; idx += 64) f.kfull[(long long)c * NF * NF + idx] = M[idx / NF][KI + idx % NF];
   }
 }
 
 // ---- RAV apply: one thread per patch, owned rows from the factored form ------
 // y_p = (r_p - z_x.r_x - z_y.r_y) / S, u_c,i = (K^{-1} r_c)_i - z_c,i y_p
 // (eq. 13: only the owned DoFs p_i and u_i are written).
+template <bool WIDE>
 __global__ __launch_bounds__(256) void k_ad_rav(AdDev a, AdFactors f, const double* __restrict__ r,
                                                 double* __restrict__ x, double omega) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int nV = a.nV;
   if (i >= nV) return;
-  const int p0 = a.poff[i >> 6], w = (a.poff[(i >> 6) + 1] - p0) >> 6;
+  const int p0 = a.poff[i >> 6];
   const int t = i & 63;
-  const int ao = a.pown[i];
-  double tz = 0.0, ku = 0.0, kv = 0.0, zxo = 0.0, zyo = 0.0;
-  for (int k = 0; k < w; ++k) {
-    const long long e = p0 + 64LL * k + t;
-    const int v = a.pv[e];
-    if (v < 0) break;
+  const int c = a.pcfg[i];
+  const int nf = a.cnf[c], ao = a.cown[c];
+  const double* zxc = f.zx + c * NF;
+  const double* zyc = f.zy + c * NF;
+  const double* krc = f.kr + c * NF;
+  double tz = 0.0, ku = 0.0, kv = 0.0;
+  for (int k = 0; k < nf; ++k) {
+    const int v = patch_vertex<WIDE>(a, i, p0 + 64LL * k + t);
     const double rx = r[v], ry = r[nV + v];
-    const double zx = f.zx[e], zy = f.zy[e], kr = f.kr[e];
+    const double zx = zxc[k], zy = zyc[k], kr = krc[k];
     tz += zx * rx + zy * ry;
     ku += kr * rx;
     kv += kr * ry;
-    if (k == ao) { zxo = zx; zyo = zy; }
   }
-  const double yp = (r[2 * nV + i] - tz) * f.invS[i];
+  const double yp = (r[2 * nV + i] - tz) * f.invS[c];
   x[2 * nV + i] += omega * yp;
   if (ao >= 0) {
-    x[i] += omega * (ku - zxo * yp);
-    x[nV + i] += omega * (kv - zyo * yp);
+    x[i] += omega * (ku - zxc[ao] * yp);
+    x[nV + i] += omega * (kv - zyc[ao] * yp);
   }
 }
 
@@ -189,7 +213,7 @@ __global__ __launch_bounds__(256) void k_ad_rav(AdDev a, AdFactors f, const doub
 constexpr int GRP = AD_NFMAX;
 constexpr int GPB = 64 / GRP;   // patches per 64-lane block
 
-template <bool MV>
+template <bool MV, bool WIDE>
 __global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int* __restrict__ order, int first,
                                                  int count, const double* __restrict__ rb, double* __restrict__ x,
                                                  double* __restrict__ yx, double* __restrict__ yy,
@@ -201,9 +225,11 @@ __global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int
   const int i = live ? (order ? order[first + q] : first + q) : 0;
   const int nV = a.nV;
   const int sl = i >> 6, t = i & 63;
-  const int p0 = a.poff[sl], w = (a.poff[sl + 1] - p0) >> 6;
+  const int p0 = a.poff[sl];
+  const int c = live ? a.pcfg[i] : 0;
+  const int nf = live ? a.cnf[c] : 0;
   const long long e = p0 + 64LL * k + t;
-  const int v = (live && k < w) ? a.pv[e] : -1;
+  const int v = k < nf ? patch_vertex<WIDE>(a, i, e) : -1;
   double rx = 0.0, ry = 0.0;
   if (v >= 0) {
     if (MV) {
@@ -211,11 +237,12 @@ __global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int
       const int vt = v & 63;
       double su = 0.0, sv = 0.0;
       for (int m = 0; m < vw; ++m) {
-        const long long ee = e0 + 64LL * m + vt;
-        const int j = a.col[ee];
+        int j, id;
+        entry<WIDE>(a, v, e0 + 64LL * m + vt, j, id);
+        const double* tv = a.vtab + 8 * id;
         const double pj = x[2 * nV + j];
-        su += a.val[ee] * x[j] + a.val[AD_BTX * a.nnz + ee] * pj;
-        sv += a.val[ee] * x[nV + j] + a.val[AD_BTY * a.nnz + ee] * pj;
+        su += tv[AD_A] * x[j] + tv[AD_BTX] * pj;
+        sv += tv[AD_A] * x[nV + j] + tv[AD_BTY] * pj;
       }
       rx = rb[v] - su;
       ry = rb[nV + v] - sv;
@@ -232,10 +259,10 @@ __global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int
       const int e0 = a.soff[sl], iw = (a.soff[sl + 1] - e0) >> 6;
       double sp = 0.0;
       for (int m = 0; m < iw; ++m) {
-        const long long ee = e0 + 64LL * m + t;
-        const int j = a.col[ee];
-        sp += a.val[AD_BX * a.nnz + ee] * x[j] + a.val[AD_BY * a.nnz + ee] * x[nV + j] +
-              a.val[AD_C * a.nnz + ee] * x[2 * nV + j];
+        int j, id;
+        entry<WIDE>(a, i, e0 + 64LL * m + t, j, id);
+        const double* tv = a.vtab + 8 * id;
+        sp += tv[AD_BX] * x[j] + tv[AD_BY] * x[nV + j] + tv[AD_C] * x[2 * nV + j];
       }
       rp = rb[2 * nV + i] - sp;
     } else {
@@ -245,11 +272,11 @@ __global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int
   __syncthreads();
   double zx = 0.0, zy = 0.0, kx = 0.0, ky = 0.0;
   if (v >= 0) {
-    zx = f.zx[e];
-    zy = f.zy[e];
-    const long long k0 = a.koff[sl] + 64LL * (k * w) + t;
-    for (int m = 0; m < w; ++m) {
-      const double kv = f.kfull[k0 + 64LL * m];
+    zx = f.zx[c * NF + k];
+    zy = f.zy[c * NF + k];
+    const double* krow = f.kfull + (long long)c * NF * NF + k * NF;
+    for (int m = 0; m < nf; ++m) {
+      const double kv = krow[m];
       kx += kv * srx[g][m];
       ky += kv * sry[g][m];
     }
@@ -257,7 +284,7 @@ __global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int
   double tz = zx * rx + zy * ry;
   for (int o = GRP / 2; o > 0; o >>= 1) tz += __shfl_xor(tz, o, GRP);
   rp = __shfl(rp, 0, GRP);
-  const double yp = live ? (rp - tz) * f.invS[i] : 0.0;
+  const double yp = live ? (rp - tz) * f.invS[c] : 0.0;
   const double ux = kx - zx * yp, uy = ky - zy * yp;
   if (MV) {
     if (v >= 0) {
@@ -266,7 +293,7 @@ __global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int
     }
     if (live && k == 0) x[2 * nV + i] += omega * yp;
   } else {
-    if (live && k < w) {
+    if (v >= 0) {
       yx[e] = ux;
       yy[e] = uy;
     }
@@ -362,31 +389,46 @@ __global__ __launch_bounds__(256) void k_ad_owner(AdDev a, int* __restrict__ own
 
 int ad_residual_blocks(int nV) { return (int)nblk(nV); }
 
+#define AD_WIDE(a, K, ...)                                                              \
+  do {                                                                                  \
+    if ((a).wide) hipLaunchKernelGGL(K<true>, __VA_ARGS__);                             \
+    else hipLaunchKernelGGL(K<false>, __VA_ARGS__);                                     \
+  } while (0)
+
 void ad_launch_residual(const AdDev& a, const double* x, const double* b, double* r, double* partials,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_ad_residual, dim3(nblk(a.nV)), dim3(256), 0, s, a, x, b, r, partials);
+  AD_WIDE(a, k_ad_residual, dim3(nblk(a.nV)), dim3(256), 0, s, a, x, b, r, partials);
 }
 
-void ad_launch_factor(const AdDev& a, int mode, AdFactors f, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_ad_factor, dim3((unsigned)a.nV), dim3(64), 0, s, a, mode, f, status);
+void ad_launch_factor(const AdDev& a, int mode, const int* rep, int ncfg, AdFactors f, int* status, hipStream_t s) {
+  if (ncfg <= 0) return;
+  AD_WIDE(a, k_ad_factor, dim3((unsigned)ncfg), dim3(64), 0, s, a, mode, rep, f, status);
 }
 
 void ad_launch_rav(const AdDev& a, AdFactors f, const double* r, double* x, double omega, hipStream_t s) {
-  hipLaunchKernelGGL(k_ad_rav, dim3(nblk(a.nV)), dim3(256), 0, s, a, f, r, x, omega);
+  AD_WIDE(a, k_ad_rav, dim3(nblk(a.nV)), dim3(256), 0, s, a, f, r, x, omega);
 }
 
 void ad_launch_av(const AdDev& a, AdFactors f, const int* tsoff, const int* tpos, const double* r, double* yx,
                   double* yy, double* yp, double* x, double omega, hipStream_t s) {
-  hipLaunchKernelGGL((k_ad_group<false>), dim3(nblk(a.nV, GPB)), dim3(64), 0, s, a, f, (const int*)nullptr, 0,
-                     a.nV, r, (double*)nullptr, yx, yy, yp, omega);
+  if (a.wide)
+    hipLaunchKernelGGL((k_ad_group<false, true>), dim3(nblk(a.nV, GPB)), dim3(64), 0, s, a, f, (const int*)nullptr,
+                       0, a.nV, r, (double*)nullptr, yx, yy, yp, omega);
+  else
+    hipLaunchKernelGGL((k_ad_group<false, false>), dim3(nblk(a.nV, GPB)), dim3(64), 0, s, a, f, (const int*)nullptr,
+                       0, a.nV, r, (double*)nullptr, yx, yy, yp, omega);
   hipLaunchKernelGGL(k_ad_av_gather, dim3(nblk(a.nV)), dim3(256), 0, s, a, tsoff, tpos, yx, yy, yp, x, omega);
 }
 
 void ad_launch_mv(const AdDev& a, AdFactors f, const int* order, int first, int count, const double* b, double* x,
                   double omega, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL((k_ad_group<true>), dim3(nblk(count, GPB)), dim3(64), 0, s, a, f, order, first, count, b, x,
-                     (double*)nullptr, (double*)nullptr, (double*)nullptr, omega);
+  if (a.wide)
+    hipLaunchKernelGGL((k_ad_group<true, true>), dim3(nblk(count, GPB)), dim3(64), 0, s, a, f, order, first, count,
+                       b, x, (double*)nullptr, (double*)nullptr, (double*)nullptr, omega);
+  else
+    hipLaunchKernelGGL((k_ad_group<true, false>), dim3(nblk(count, GPB)), dim3(64), 0, s, a, f, order, first, count,
+                       b, x, (double*)nullptr, (double*)nullptr, (double*)nullptr, omega);
 }
 
 void ad_launch_prolong(const AdDev& f, const AdDev& c, const int* ptr, const int* idx, const double* w,

@@ -8,26 +8,31 @@
 // of the unit square is Dirichlet (masked).
 //
 // Operator: the conforming space is reached through the hanging-node
-// constraints, L = T^T L_corners T, assembled once on the host.  It is stored
-// by vertex pairs (i, j) in SELL-64 form: vertices in slices of 64, slice s
-// has width w_s = its longest row and entry k of the vertex at lane t sits at
-// soff[s] + 64 k + t, so a wavefront reads every plane with unit stride.  An
-// entry holds the column vertex and six planes (stride nnz): A_ij (viscous
-// block, the same for both components), BT_x,ij and BT_y,ij (row u_c,i,
-// column p_j), B_x,ij and B_y,ij (row p_i, column u_c,j) and C_ij
-// (stabilization).  Masked rows and columns are zero; padding entries point
-// at the row's own vertex with zero values.
+// constraints, L = T^T L_corners T, assembled once on the host.  An entry is
+// a vertex pair (i, j) with six values: A_ij (viscous block, the same for both
+// components), BT_x,ij and BT_y,ij (row u_c,i, column p_j), B_x,ij and B_y,ij
+// (row p_i, column u_c,j) and C_ij (stabilization); masked rows and columns
+// are zero.  A grid built from a few leaf sizes has only a few hundred
+// distinct value tuples, so each tuple is stored once in vtab (8 doubles per
+// tuple: the six values and two zeros) and an entry holds only the column and
+// the tuple id -- packed into one 32-bit word (the signed column offset j - i
+// in the high 32 - id_bits bits, the id in the low id_bits bits) when every
+// offset fits, else as two int32 arrays (the wide format).  Entries are in
+// SELL-64 form: vertices in slices of 64, slice s has width w_s = its longest row and entry
+// k of the vertex at lane t sits at soff[s] + 64 k + t.  Padding entries point
+// at the row's own vertex with the all-zero tuple.
 //
 // Patches (smoothed levels): patch i is vertex i.  Its free velocity vertices
 // (the vertices of the leaves around i, a hanging corner standing for the
-// vertices that constrain it) are stored sorted in the same SELL-64 form over
-// patches (poff, pv; padding -1); pown[i] is the position of i in its own list
-// (-1: velocity of i masked).  The patch matrix is [[K,0,b_x],[0,K,b_y],
-// [b_x^T, b_y^T, c]] with K SPD, so its inverse is kept factored:
+// vertices that constrain it) are stored sorted, in the same SELL-64 form
+// over patches (pv; padding -1).  The patch matrix
+// [[K,0,b_x],[0,K,b_y],[b_x^T, b_y^T, c]] (K SPD) is fixed by the tuple ids of
+// its entries, so patches with equal ids
+// share one configuration; each configuration is factored once:
 // z_c = K^{-1} b_c, 1/S with S = c - b_x.z_x - b_y.z_y, and
-//   RAV: row pown[i] of K^{-1} (plane kr, SELL layout) -- the owned rows;
-//   AV/MV: all of K^{-1}, slice s holding w_s^2 x 64 values from koff[s],
-//          entry (a, b) of lane t at koff[s] + 64 (a w_s + b) + t.
+//   RAV: the row of K^{-1} of the owned vertex (kr) -- the owned rows;
+//   AV/MV: all of K^{-1} (kfull).
+// Configuration tables are config-major with AD_NFMAX slots per vector.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,23 +45,27 @@ constexpr int AD_NFMAX = 16;   // free velocity vertices per patch
 struct AdDev {
   int nV;
   int nslice;
-  long long nnz;                    // padded operator entries (plane stride)
+  int wide;                         // 0: packed entries; 1: column and id arrays
+  int id_bits;                      // packed: bits of the tuple id
+  long long nnz;                    // padded operator entries
   long long pnnz;                   // padded patch entries
   const unsigned char* vmask;       // velocity Dirichlet per vertex
   const int* soff;                  // nslice + 1
-  const int* col;
-  const double* val;                // 6 planes of nnz
+  const unsigned* ent;              // packed entry, or (wide) the tuple id
+  const int* col;                   // wide: column vertex
+  const double* vtab;               // 8 doubles per tuple
   const int* poff;                  // nslice + 1 (patch slices)
-  const int* pv;
-  const int* pown;
-  const long long* koff;            // nslice + 1 (full K^{-1} slices)
+  const int* pv;                    // patch vertices
+  const int* pcfg;                  // configuration of every patch
+  const int* cnf;                   // free velocity vertices per configuration
+  const int* cown;                  // position of the patch's own vertex (-1: masked) per configuration
 };
 
 enum { AD_A = 0, AD_BTX = 1, AD_BTY = 2, AD_BX = 3, AD_BY = 4, AD_C = 5 };
 enum { AD_RAV = 0, AD_FULL = 1 };
 
-// Factored patch inverses: zx, zy (pnnz each), invS (nV), and kr (pnnz, RAV)
-// or kfull (koff[nslice], AV/MV).
+// Factors per configuration: zx, zy, kr (AD_NFMAX each), invS (1), kfull
+// (AD_NFMAX^2, AV/MV only).
 struct AdFactors {
   double* zx;
   double* zy;
@@ -68,10 +77,11 @@ struct AdFactors {
 int ad_residual_blocks(int nV);
 void ad_launch_residual(const AdDev& a, const double* x, const double* b, double* r, double* partials,
                         hipStream_t s);
-void ad_launch_factor(const AdDev& a, int mode, AdFactors f, int* status, hipStream_t s);
+// One block per configuration c, built from its representative patch rep[c].
+void ad_launch_factor(const AdDev& a, int mode, const int* rep, int ncfg, AdFactors f, int* status, hipStream_t s);
 void ad_launch_rav(const AdDev& a, AdFactors f, const double* r, double* x, double omega, hipStream_t s);
-// AV: corrections of every patch into (yx, yy: pnnz, yp: nV), then each DoF
-// gathers the corrections of the patches that hold it (tsoff/tpos: SELL-64
+// AV: corrections of every patch into (yx, yy: pnnz slots, yp: nV), then each
+// DoF gathers the corrections of the patches that hold it (tsoff/tpos: SELL-64
 // over vertices, entry = slot of the vertex in a patch list, padding -1).
 void ad_launch_av(const AdDev& a, AdFactors f, const int* tsoff, const int* tpos, const double* r, double* yx,
                   double* yy, double* yp, double* x, double omega, hipStream_t s);

@@ -11,6 +11,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <atomic>
 #include <string>
 #include <thread>
@@ -31,9 +32,10 @@ struct rav_ad_state {
     long long nfree = 0;
     unsigned char* vmask = nullptr;
     int *soff = nullptr, *col = nullptr;
-    double* val = nullptr;
-    int *poff = nullptr, *pv = nullptr, *pown = nullptr;
-    long long* koff = nullptr;
+    unsigned* ent = nullptr;
+    double* vtab = nullptr;
+    int *poff = nullptr, *pv = nullptr, *pcfg = nullptr, *cnf = nullptr, *cown = nullptr, *rep = nullptr;
+    int ncfg = 0, ntuple = 0;
     AdFactors fac{};
     int *tsoff = nullptr, *tpos = nullptr;
     double *yx = nullptr, *yy = nullptr, *yp = nullptr;
@@ -45,10 +47,10 @@ struct rav_ad_state {
     double* rw = nullptr;
     double *x = nullptr, *b = nullptr, *r = nullptr, *partials = nullptr;
     int nres = 0;
-    long long pnnz = 0, kfull_n = 0;
+    long long pnnz = 0;
     long long nnz_true = 0, pnnz_true = 0;   // entries without the slice padding
     // host copies for the patch getters
-    std::vector<int> h_poff, h_pv, h_pown;
+    std::vector<int> h_poff, h_pv, h_pcfg, h_cnf, h_cown;
   };
   std::vector<Level> lv;
   double* Minv = nullptr;
@@ -244,14 +246,20 @@ struct HostLevel {
   std::vector<unsigned char> vmask;
   Csr nbr;                             // structural columns of every vertex row
   std::vector<int> soff, col;
-  std::vector<double> val;             // 6 planes
+  std::vector<double> val;             // 6 planes (host only: coarse matrix, exports)
   long long nnz = 0;
+  std::vector<int> vid;                // tuple id of every stored entry
+  std::vector<double> vtab;            // 8 doubles per distinct tuple
   std::vector<double> blid;            // lid lifting (finest grid)
   // patches
   Csr pall;                            // all vertices of patch i (MV colouring)
-  std::vector<int> poff, pv, pown;
-  std::vector<long long> koff;
+  std::vector<int> poff, pv;
   long long pnnz = 0;
+  std::vector<int> pcfg, cnf, cown, rep;   // configuration of every patch; per configuration nf, owned, representative
+  // device encoding
+  bool wide = false;
+  int id_bits = 1;
+  std::vector<unsigned> ent;
   std::vector<int> tsoff, tpos, order, cstart;
   // prolongation from the next coarser grid
   std::vector<int> pptr, pidx, rptr, ridx;
@@ -356,6 +364,29 @@ bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, st
       if (H.vmask[i]) { H.val[AD_A * P + s] = 0.0; H.val[AD_BTX * P + s] = 0.0; H.val[AD_BTY * P + s] = 0.0; }
       if (H.vmask[j]) { H.val[AD_A * P + s] = 0.0; H.val[AD_BX * P + s] = 0.0; H.val[AD_BY * P + s] = 0.0; }
     }
+  // distinct value tuples (by bit pattern, so the kernels see the same values)
+  struct TupleHash {
+    size_t operator()(const std::array<uint64_t, 6>& t) const {
+      uint64_t h = 1469598103934665603ull;
+      for (uint64_t v : t) h = (h ^ (v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2))) * 1099511628211ull;
+      return (size_t)h;
+    }
+  };
+  std::unordered_map<std::array<uint64_t, 6>, int, TupleHash> ids;
+  H.vid.assign(H.nnz, 0);
+  std::array<uint64_t, 6> zero{};
+  ids.emplace(zero, 0);
+  H.vtab.assign(8, 0.0);
+  for (long long e = 0; e < H.nnz; ++e) {
+    std::array<uint64_t, 6> t;
+    for (int p = 0; p < 6; ++p) std::memcpy(&t[p], &H.val[p * P + e], 8);
+    auto it = ids.find(t);
+    if (it == ids.end()) {
+      it = ids.emplace(t, (int)ids.size()).first;
+      for (int p = 0; p < 8; ++p) H.vtab.push_back(p < 6 ? H.val[p * P + e] : 0.0);
+    }
+    H.vid[e] = it->second;
+  }
   return true;
 }
 
@@ -390,19 +421,50 @@ bool build_patches(const Topo& g, HostLevel& H, std::string& err) {
   H.poff = sell_offsets(nV, len);
   H.pnnz = H.poff.back();
   H.pv.assign(H.pnnz, -1);
-  H.pown.assign(nV, -1);
-  const int ns = (int)H.poff.size() - 1;
-  H.koff.assign(ns + 1, 0);
-  for (int s = 0; s < ns; ++s) {
-    const long long w = (H.poff[s + 1] - H.poff[s]) / AD_SLICE;
-    H.koff[s + 1] = H.koff[s] + AD_SLICE * w * w;
-  }
+  std::vector<int> own(nV, -1);
   for (int i = 0; i < nV; ++i)
     for (int k = 0; k < len[i]; ++k) {
       const int v = pfree.begin(i)[k];
       H.pv[sell_slot(H.poff, i, k)] = v;
-      if (v == i) H.pown[i] = k;
+      if (v == i) own[i] = k;
     }
+  // configurations: patches whose matrices have the same tuple ids (and owned position)
+  auto tuple_at = [&](int row, int colv) -> int {
+    const int* b = H.nbr.begin(row);
+    const int* e = H.nbr.end(row);
+    const int* f = std::lower_bound(b, e, colv);
+    return (f != e && *f == colv) ? H.vid[sell_slot(H.soff, row, (int)(f - b))] : -1;
+  };
+  struct VecHash {
+    size_t operator()(const std::vector<int>& v) const {
+      uint64_t h = 1469598103934665603ull;
+      for (int x : v) h = (h ^ (uint64_t)(uint32_t)x) * 1099511628211ull;
+      return (size_t)h;
+    }
+  };
+  std::unordered_map<std::vector<int>, int, VecHash> cfgs;
+  H.pcfg.assign(nV, 0);
+  H.cnf.clear();
+  H.cown.clear();
+  H.rep.clear();
+  std::vector<int> sig;
+  for (int i = 0; i < nV; ++i) {
+    const int nf = len[i];
+    const int* F = pfree.begin(i);
+    sig.assign({nf, own[i], tuple_at(i, i)});
+    for (int a = 0; a < nf; ++a) {
+      sig.push_back(tuple_at(F[a], i));
+      for (int b = 0; b < nf; ++b) sig.push_back(tuple_at(F[a], F[b]));
+    }
+    auto it = cfgs.find(sig);
+    if (it == cfgs.end()) {
+      it = cfgs.emplace(sig, (int)H.rep.size()).first;
+      H.cnf.push_back(nf);
+      H.cown.push_back(own[i]);
+      H.rep.push_back(i);
+    }
+    H.pcfg[i] = it->second;
+  }
   // AV gather lists: the slots that hold vertex v, in patch order
   Csr tslots = build_csr(nV, [&](auto&& emit) {
     for (int i = 0; i < nV; ++i)
@@ -687,6 +749,36 @@ rav_status build_coarse(rav_ctx* ctx, const HostLevel& H) {
   return RAV_OK;
 }
 
+// Device encoding of the operator entries: packed (column offset and tuple id
+// in one 32-bit word, id_bits = bits the ids need) when every offset fits the
+// remaining bits, else wide.
+void encode(HostLevel& H) {
+  const int nV = H.nV;
+  const long long ntuple = (long long)(H.vtab.size() / 8);
+  int id_bits = 1;
+  while ((1LL << id_bits) < ntuple) ++id_bits;
+  const long long lim = 1LL << (31 - id_bits);   // offsets in [-lim, lim)
+  bool fit = id_bits <= 24;
+  for (int i = 0; i < nV && fit; ++i) {
+    const int w = (H.soff[i / AD_SLICE + 1] - H.soff[i / AD_SLICE]) / AD_SLICE;
+    for (int k = 0; k < w; ++k) {
+      const long long d = (long long)H.col[sell_slot(H.soff, i, k)] - i;
+      fit = fit && d >= -lim && d < lim;
+    }
+  }
+  H.wide = !fit;
+  H.id_bits = id_bits;
+  H.ent.assign(H.nnz, 0u);
+  for (int i = 0; i < nV; ++i) {
+    const int w = (H.soff[i / AD_SLICE + 1] - H.soff[i / AD_SLICE]) / AD_SLICE;
+    for (int k = 0; k < w; ++k) {
+      const long long e = sell_slot(H.soff, i, k);
+      const unsigned id = (unsigned)H.vid[e];
+      H.ent[e] = H.wide ? id : (((unsigned)(H.col[e] - i) << id_bits) | id);
+    }
+  }
+}
+
 rav_status upload_level(rav_ctx* ctx, Level& L, const HostLevel& H, bool smoothed, bool has_transfer) {
   L.nV = H.nV;
   long long masked = 0;
@@ -694,10 +786,12 @@ rav_status upload_level(rav_ctx* ctx, Level& L, const HostLevel& H, bool smoothe
   L.nfree = 3LL * H.nV - 2 * masked;
   L.nnz_true = (long long)H.nbr.idx.size();
   for (int v : H.pv) L.pnnz_true += v >= 0;
+  L.ntuple = (int)(H.vtab.size() / 8);
   ACK(upload(&L.vmask, H.vmask));
   ACK(upload(&L.soff, H.soff));
-  ACK(upload(&L.col, H.col));
-  ACK(upload(&L.val, H.val));
+  ACK(upload(&L.ent, H.ent));
+  if (H.wide) ACK(upload(&L.col, H.col));
+  ACK(upload(&L.vtab, H.vtab));
   const long long n = 3LL * H.nV;
   ACK(hipMalloc((void**)&L.x, sizeof(double) * n));
   ACK(hipMalloc((void**)&L.b, sizeof(double) * n));
@@ -710,30 +804,38 @@ rav_status upload_level(rav_ctx* ctx, Level& L, const HostLevel& H, bool smoothe
   AdDev& a = L.dev;
   a.nV = H.nV;
   a.nslice = (int)H.soff.size() - 1;
+  a.wide = H.wide ? 1 : 0;
+  a.id_bits = H.id_bits;
   a.nnz = H.nnz;
   a.vmask = L.vmask;
   a.soff = L.soff;
+  a.ent = L.ent;
   a.col = L.col;
-  a.val = L.val;
+  a.vtab = L.vtab;
   if (smoothed) {
     ACK(upload(&L.poff, H.poff));
     ACK(upload(&L.pv, H.pv));
-    ACK(upload(&L.pown, H.pown));
-    ACK(upload(&L.koff, H.koff));
+    ACK(upload(&L.pcfg, H.pcfg));
+    ACK(upload(&L.cnf, H.cnf));
+    ACK(upload(&L.cown, H.cown));
+    ACK(upload(&L.rep, H.rep));
     ACK(upload(&L.tsoff, H.tsoff));
     ACK(upload(&L.tpos, H.tpos));
     ACK(upload(&L.order, H.order));
     L.cstart = H.cstart;
     L.pnnz = H.pnnz;
-    L.kfull_n = H.koff.back();
+    L.ncfg = (int)H.rep.size();
     L.h_poff = H.poff;
     L.h_pv = H.pv;
-    L.h_pown = H.pown;
+    L.h_pcfg = H.pcfg;
+    L.h_cnf = H.cnf;
+    L.h_cown = H.cown;
     a.pnnz = H.pnnz;
     a.poff = L.poff;
     a.pv = L.pv;
-    a.pown = L.pown;
-    a.koff = L.koff;
+    a.pcfg = L.pcfg;
+    a.cnf = L.cnf;
+    a.cown = L.cown;
   }
   if (has_transfer) {
     ACK(upload(&L.pptr, H.pptr));
@@ -844,6 +946,7 @@ rav_status rav_ad_create(const rav_problem_desc* d, const int* leaves, const lon
       ctx->err = errs[l];
       return fail(errs[l].find("more than") != std::string::npos ? RAV_EUNSUPPORTED : RAV_EINVAL);
     }
+  parallel_for(nl, [&](int l) { encode(hosts[l]); });
   for (int l = 0; l < nl; ++l) {
     HostLevel& H = hosts[l];
     if ((s = upload_level(ctx, S->lv[l], H, l > 0, l > 0)) != RAV_OK) return fail(s);
@@ -862,7 +965,8 @@ void rav_ad_free(rav_ctx* ctx) {
   rav_ad_state* S = ctx->ad;
   if (!S) return;
   for (Level& L : S->lv) {
-    void* ptrs[] = {L.vmask, L.soff, L.col, L.val, L.poff, L.pv, L.pown, L.koff, L.fac.zx, L.fac.zy, L.fac.invS,
+    void* ptrs[] = {L.vmask, L.soff, L.col, L.ent, L.vtab, L.poff, L.pv, L.pcfg, L.cnf, L.cown, L.rep,
+                    L.fac.zx, L.fac.zy, L.fac.invS,
                     L.fac.kr, L.fac.kfull, L.tsoff, L.tpos, L.yx, L.yy, L.yp, L.order, L.pptr, L.pidx, L.pw,
                     L.rptr, L.ridx, L.rw, L.x, L.b, L.r, L.partials};
     for (void* p : ptrs) (void)hipFree(p);
@@ -879,20 +983,21 @@ rav_status rav_ad_factor(rav_ctx* ctx) {
   for (size_t l = 1; l < S->lv.size(); ++l) {
     Level& L = S->lv[l];
     if (!L.fac.zx) {
-      ACK(hipMalloc((void**)&L.fac.zx, sizeof(double) * L.pnnz));
-      ACK(hipMalloc((void**)&L.fac.zy, sizeof(double) * L.pnnz));
-      ACK(hipMalloc((void**)&L.fac.invS, sizeof(double) * L.nV));
+      const long long nc = std::max(L.ncfg, 1);
+      ACK(hipMalloc((void**)&L.fac.zx, sizeof(double) * nc * AD_NFMAX));
+      ACK(hipMalloc((void**)&L.fac.zy, sizeof(double) * nc * AD_NFMAX));
+      ACK(hipMalloc((void**)&L.fac.invS, sizeof(double) * nc));
       if (S->mode == AD_RAV) {
-        ACK(hipMalloc((void**)&L.fac.kr, sizeof(double) * L.pnnz));
+        ACK(hipMalloc((void**)&L.fac.kr, sizeof(double) * nc * AD_NFMAX));
       } else {
-        ACK(hipMalloc((void**)&L.fac.kfull, sizeof(double) * L.kfull_n));
+        ACK(hipMalloc((void**)&L.fac.kfull, sizeof(double) * nc * AD_NFMAX * AD_NFMAX));
         ACK(hipMalloc((void**)&L.yx, sizeof(double) * L.pnnz));
         ACK(hipMalloc((void**)&L.yy, sizeof(double) * L.pnnz));
         ACK(hipMalloc((void**)&L.yp, sizeof(double) * L.nV));
       }
     }
     ACK(hipMemcpy(ctx->d_status, &big, sizeof(int), hipMemcpyHostToDevice));
-    ad_launch_factor(L.dev, S->mode, L.fac, ctx->d_status, ctx->stream);
+    ad_launch_factor(L.dev, S->mode, L.rep, L.ncfg, L.fac, ctx->d_status, ctx->stream);
     ACK(hipGetLastError());
     int stv = 0;
     ACK(hipMemcpyAsync(&stv, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -1086,41 +1191,20 @@ rav_status rav_ad_get_patch_inverse(rav_ctx* ctx, int level, long patch, double*
   const Level& L = S->lv[level];
   if (patch < 0 || patch >= L.nV) return RAV_EINVAL;
   ACK(hipStreamSynchronize(ctx->stream));
-  const long long sl = patch / AD_SLICE, t = patch % AD_SLICE;
-  const int w = (L.h_poff[sl + 1] - L.h_poff[sl]) / AD_SLICE;
-  int nf = 0;
-  while (nf < w && L.h_pv[L.h_poff[sl] + AD_SLICE * nf + t] >= 0) ++nf;
-  std::vector<double> zx(nf), zy(nf), kin((size_t)nf * nf, 0.0);
+  const int c = L.h_pcfg[patch];
+  const int nf = L.h_cnf[c], ao = L.h_cown[c];
+  std::vector<double> zx(AD_NFMAX), zy(AD_NFMAX), kin((size_t)AD_NFMAX * AD_NFMAX, 0.0);
   double sinv = 0.0;
-  for (int k = 0; k < nf; ++k) {
-    const long long e = L.h_poff[sl] + AD_SLICE * k + t;
-    ACK(hipMemcpy(&zx[k], L.fac.zx + e, sizeof(double), hipMemcpyDeviceToHost));
-    ACK(hipMemcpy(&zy[k], L.fac.zy + e, sizeof(double), hipMemcpyDeviceToHost));
-  }
-  ACK(hipMemcpy(&sinv, L.fac.invS + patch, sizeof(double), hipMemcpyDeviceToHost));
-  const int ao = L.h_pown[patch];
-  std::vector<int> krow;   // rows of K^{-1} available
+  ACK(hipMemcpy(zx.data(), L.fac.zx + (long long)c * AD_NFMAX, sizeof(double) * AD_NFMAX, hipMemcpyDeviceToHost));
+  ACK(hipMemcpy(zy.data(), L.fac.zy + (long long)c * AD_NFMAX, sizeof(double) * AD_NFMAX, hipMemcpyDeviceToHost));
+  ACK(hipMemcpy(&sinv, L.fac.invS + c, sizeof(double), hipMemcpyDeviceToHost));
   if (S->mode == AD_RAV) {
-    if (ao >= 0) {
-      for (int k = 0; k < nf; ++k)
-        ACK(hipMemcpy(&kin[(size_t)ao * nf + k], L.fac.kr + L.h_poff[sl] + AD_SLICE * k + t, sizeof(double),
-                      hipMemcpyDeviceToHost));
-      krow.push_back(ao);
-    }
+    if (ao >= 0)
+      ACK(hipMemcpy(&kin[(size_t)ao * AD_NFMAX], L.fac.kr + (long long)c * AD_NFMAX, sizeof(double) * AD_NFMAX,
+                    hipMemcpyDeviceToHost));
   } else {
-    long long k0 = 0;
-    std::vector<long long> koff(L.h_poff.size());
-    for (size_t s2 = 0; s2 + 1 < L.h_poff.size(); ++s2) {
-      const long long ww = (L.h_poff[s2 + 1] - L.h_poff[s2]) / AD_SLICE;
-      koff[s2 + 1] = koff[s2] + AD_SLICE * ww * ww;
-    }
-    k0 = koff[sl];
-    for (int a = 0; a < nf; ++a) {
-      for (int b = 0; b < nf; ++b)
-        ACK(hipMemcpy(&kin[(size_t)a * nf + b], L.fac.kfull + k0 + AD_SLICE * (long long)(a * w + b) + t,
-                      sizeof(double), hipMemcpyDeviceToHost));
-      krow.push_back(a);
-    }
+    ACK(hipMemcpy(kin.data(), L.fac.kfull + (long long)c * AD_NFMAX * AD_NFMAX,
+                  sizeof(double) * AD_NFMAX * AD_NFMAX, hipMemcpyDeviceToHost));
   }
   const int n = 2 * nf + 1;
   // entry of L_i^{-1} at local (row, col): velocity (c, m) = c nf + m, pressure 2 nf
@@ -1129,7 +1213,7 @@ rav_status rav_ad_get_patch_inverse(rav_ctx* ctx, int level, long patch, double*
     const int c1 = r < nf ? 0 : 1, m1 = r - c1 * nf, c2 = c < nf ? 0 : 1, m2 = c - c2 * nf;
     const std::vector<double>& zr = c1 == 0 ? zx : zy;
     const std::vector<double>& zc = c2 == 0 ? zx : zy;
-    if (rv && cv) return (c1 == c2 ? kin[(size_t)m1 * nf + m2] : 0.0) + zr[m1] * sinv * zc[m2];
+    if (rv && cv) return (c1 == c2 ? kin[(size_t)m1 * AD_NFMAX + m2] : 0.0) + zr[m1] * sinv * zc[m2];
     if (rv) return -zr[m1] * sinv;
     if (cv) return -sinv * zc[m2];
     return sinv;
@@ -1182,8 +1266,9 @@ rav_status rav_ad_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const
   return RAV_OK;
 }
 
-// Grid statistics for the host: vertices, operator and patch entries (padded), MV colours, and the
-// operator and patch entries without padding.
+// Grid statistics for the host: vertices, operator and patch entries (padded), MV colours, the
+// operator and patch entries without padding, distinct value tuples, patch configurations and
+// the entry format (0 packed, 1 wide).
 rav_status rav_ad_level_info(const rav_ctx* ctx, int level, long* info) {
   if (check_lv(ctx, level, false) != RAV_OK || !info) return RAV_EINVAL;
   const Level& L = st(ctx)->lv[level];
@@ -1193,6 +1278,9 @@ rav_status rav_ad_level_info(const rav_ctx* ctx, int level, long* info) {
   info[3] = L.cstart.empty() ? 0 : (long)L.cstart.size() - 1;
   info[4] = (long)L.nnz_true;
   info[5] = (long)L.pnnz_true;
+  info[6] = L.ntuple;
+  info[7] = L.ncfg;
+  info[8] = L.dev.wide;
   return RAV_OK;
 }
 
