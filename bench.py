@@ -778,12 +778,12 @@ def bench_adaptive(args):
     wide = info["wide"]
     # per launch on Omega^10: residual: one packed word per operator entry
     # (column offset + value-tuple id; 8 bytes in the wide format), x read once,
-    # b read and r written (3 fields each), the mask byte; apply: one 16-bit
-    # vertex offset per patch entry (4 bytes wide), the configuration id, r read
-    # once, x read and written.  The value and configuration tables (a few
-    # hundred entries) stay in cache and are not counted.
+    # b read and r written (3 fields each), the mask byte; apply: the vertex of
+    # every patch entry (int32), the configuration id, r read once, x read and
+    # written.  The value and configuration tables (a few hundred entries) stay
+    # in cache and are not counted.
     res_bytes = (8 if wide else 4) * nnz + 73 * nV
-    app_bytes = (4 if wide else 2) * pnnz + 76 * nV
+    app_bytes = 4 * pnnz + 76 * nV
     ach_res = res_bytes / (main["ms_residual"] * 1e-3) / 1e9
     ach_app = app_bytes / (main["ms_apply"] * 1e-3) / 1e9
     from paper_2103_10127_amd.profiling import ADAPTIVE_SOURCES, read_traffic

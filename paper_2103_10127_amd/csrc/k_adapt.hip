@@ -49,48 +49,6 @@ __device__ double lookup(const AdDev& a, int v, int j, int p) {
   return out;
 }
 
-// ---- residual: one thread per vertex, its three rows -------------------------
-template <bool WIDE>
-__global__ __launch_bounds__(256) void k_ad_residual(AdDev a, const double* __restrict__ x,
-                                                     const double* __restrict__ b, double* __restrict__ r,
-                                                     double* __restrict__ partials) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int nV = a.nV;
-  double sq = 0.0;
-  if (i < nV) {
-    const int e0 = a.soff[i >> 6], w = (a.soff[(i >> 6) + 1] - e0) >> 6;
-    const int t = i & 63;
-    double su = 0.0, sv = 0.0, sp = 0.0;
-    for (int k = 0; k < w; ++k) {
-      int j, id;
-      entry<WIDE>(a, i, e0 + 64LL * k + t, j, id);
-      const double2* vt = reinterpret_cast<const double2*>(a.vtab + 8 * id);
-      const double2 v01 = vt[0], v23 = vt[1], v45 = vt[2];   // (A, BTx), (BTy, Bx), (By, C)
-      const double uj = x[j], vj = x[nV + j], pj = x[2 * nV + j];
-      su += v01.x * uj + v01.y * pj;
-      sv += v01.x * vj + v23.x * pj;
-      sp += v23.y * uj + v45.x * vj + v45.y * pj;
-    }
-    const bool vm = a.vmask[i] != 0;
-    const double ru = vm ? 0.0 : b[i] - su;
-    const double rv = vm ? 0.0 : b[nV + i] - sv;
-    const double rp = b[2 * nV + i] - sp;
-    r[i] = ru;
-    r[nV + i] = rv;
-    r[2 * nV + i] = rp;
-    sq = ru * ru + rv * rv + rp * rp;
-  }
-  if (!partials) return;
-  __shared__ double red[256];
-  red[threadIdx.x] = sq;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
-}
-
 // ---- patch factorization: one 64-lane block per configuration ----------------
 // Gauss-Jordan elimination without pivoting on [K | b_x b_y | I] (K SPD,
 // padded to AD_NFMAX with identity rows), giving z_c = K^{-1} b_c and K^{-1};
@@ -173,15 +131,43 @@ __global__ __launch_bounds__(64) void k_ad_factor(AdDev a, int mode, const int* 
   }
 }
 
-// ---- RAV apply: one thread per patch, owned rows from the factored form ------
-// y_p = (r_p - z_x.r_x - z_y.r_y) / S, u_c,i = (K^{-1} r_c)_i - z_c,i y_p
-// (eq. 13: only the owned DoFs p_i and u_i are written).
+// ---- per-vertex and per-patch bodies -------------------------------------------
+
+// r = b - L x on the three rows of vertex i (masked velocity rows 0); returns
+// the sum of their squares.
 template <bool WIDE>
-__global__ __launch_bounds__(256) void k_ad_rav(AdDev a, AdFactors f, const double* __restrict__ r,
-                                                double* __restrict__ x, double omega) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ double residual_vertex(const AdDev& a, int i, const double* __restrict__ x,
+                                                  const double* __restrict__ b, double* __restrict__ r) {
   const int nV = a.nV;
-  if (i >= nV) return;
+  const int e0 = a.soff[i >> 6], w = (a.soff[(i >> 6) + 1] - e0) >> 6;
+  const int t = i & 63;
+  double su = 0.0, sv = 0.0, sp = 0.0;
+  for (int k = 0; k < w; ++k) {
+    int j, id;
+    entry<WIDE>(a, i, e0 + 64LL * k + t, j, id);
+    const double2* vt = reinterpret_cast<const double2*>(a.vtab + 8 * id);
+    const double2 v01 = vt[0], v23 = vt[1], v45 = vt[2];   // (A, BTx), (BTy, Bx), (By, C)
+    const double uj = x[j], vj = x[nV + j], pj = x[2 * nV + j];
+    su += v01.x * uj + v01.y * pj;
+    sv += v01.x * vj + v23.x * pj;
+    sp += v23.y * uj + v45.x * vj + v45.y * pj;
+  }
+  const bool vm = a.vmask[i] != 0;
+  const double ru = vm ? 0.0 : b[i] - su;
+  const double rv = vm ? 0.0 : b[nV + i] - sv;
+  const double rp = b[2 * nV + i] - sp;
+  r[i] = ru;
+  r[nV + i] = rv;
+  r[2 * nV + i] = rp;
+  return ru * ru + rv * rv + rp * rp;
+}
+
+// RAV on patch i from the factored form: y_p = (r_p - z_x.r_x - z_y.r_y) / S,
+// u_c,i = (K^{-1} r_c)_i - z_c,i y_p (eq. 13: only the owned p_i and u_i are written).
+template <bool WIDE>
+__device__ __forceinline__ void rav_patch(const AdDev& a, const AdFactors& f, int i, const double* __restrict__ r,
+                                          double* __restrict__ x, double omega) {
+  const int nV = a.nV;
   const int p0 = a.poff[i >> 6];
   const int t = i & 63;
   const int c = a.pcfg[i];
@@ -206,32 +192,38 @@ __global__ __launch_bounds__(256) void k_ad_rav(AdDev a, AdFactors f, const doub
   }
 }
 
-// ---- AV / MV: a group of AD_NFMAX lanes per patch ----------------------------
-// Lane k holds patch vertex k: r_x, r_y of that vertex (AV: read from r; MV:
-// recomputed from b and the current x, eq. 15), y_c,k = (K^{-1} r_c)_k - z_c,k y_p.
-// AV writes the corrections per patch slot; MV adds them to x at once.
+// AV / MV on a group of AD_NFMAX lanes per patch.  Lane k holds patch vertex
+// k: r_x, r_y of that vertex (AV: read from r; MV: recomputed from b and the
+// current x, eq. 15), y_c,k = (K^{-1} r_c)_k - z_c,k y_p.  AV writes the
+// corrections per patch slot; MV adds them to x at once.  Stage 1 loads the
+// patch residual into the group's row of shared memory (srx, sry); stage 2,
+// after a barrier, solves and writes.
 constexpr int GRP = AD_NFMAX;
-constexpr int GPB = 64 / GRP;   // patches per 64-lane block
+
+struct GroupState {
+  int i, v, c, nf;
+  long long e;
+  double rx, ry, rp;
+  bool live;
+};
 
 template <bool MV, bool WIDE>
-__global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int* __restrict__ order, int first,
-                                                 int count, const double* __restrict__ rb, double* __restrict__ x,
-                                                 double* __restrict__ yx, double* __restrict__ yy,
-                                                 double* __restrict__ yp_out, double omega) {
-  __shared__ double srx[GPB][GRP], sry[GPB][GRP];
-  const int g = threadIdx.x / GRP, k = threadIdx.x % GRP;
-  const int q = blockIdx.x * GPB + g;
-  const bool live = q < count;
-  const int i = live ? (order ? order[first + q] : first + q) : 0;
+__device__ __forceinline__ GroupState group_load(const AdDev& a, bool live, int i, int k,
+                                                 const double* __restrict__ rb, const double* __restrict__ x,
+                                                 double* srx, double* sry) {
+  GroupState g;
+  g.live = live;
+  g.i = live ? i : 0;
   const int nV = a.nV;
-  const int sl = i >> 6, t = i & 63;
-  const int p0 = a.poff[sl];
-  const int c = live ? a.pcfg[i] : 0;
-  const int nf = live ? a.cnf[c] : 0;
-  const long long e = p0 + 64LL * k + t;
-  const int v = k < nf ? patch_vertex<WIDE>(a, i, e) : -1;
-  double rx = 0.0, ry = 0.0;
-  if (v >= 0) {
+  const int sl = g.i >> 6, t = g.i & 63;
+  g.c = live ? a.pcfg[g.i] : 0;
+  g.nf = live ? a.cnf[g.c] : 0;
+  g.e = a.poff[sl] + 64LL * k + t;
+  g.v = k < g.nf ? patch_vertex<WIDE>(a, g.i, g.e) : -1;
+  g.rx = 0.0;
+  g.ry = 0.0;
+  if (g.v >= 0) {
+    const int v = g.v;
     if (MV) {
       const int e0 = a.soff[v >> 6], vw = (a.soff[(v >> 6) + 1] - e0) >> 6;
       const int vt = v & 63;
@@ -244,71 +236,77 @@ __global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int
         su += tv[AD_A] * x[j] + tv[AD_BTX] * pj;
         sv += tv[AD_A] * x[nV + j] + tv[AD_BTY] * pj;
       }
-      rx = rb[v] - su;
-      ry = rb[nV + v] - sv;
+      g.rx = rb[v] - su;
+      g.ry = rb[nV + v] - sv;
     } else {
-      rx = rb[v];
-      ry = rb[nV + v];
+      g.rx = rb[v];
+      g.ry = rb[nV + v];
     }
   }
-  srx[g][k] = rx;
-  sry[g][k] = ry;
-  double rp = 0.0;
+  srx[k] = g.rx;
+  sry[k] = g.ry;
+  g.rp = 0.0;
   if (live && k == 0) {
     if (MV) {
       const int e0 = a.soff[sl], iw = (a.soff[sl + 1] - e0) >> 6;
       double sp = 0.0;
       for (int m = 0; m < iw; ++m) {
         int j, id;
-        entry<WIDE>(a, i, e0 + 64LL * m + t, j, id);
+        entry<WIDE>(a, g.i, e0 + 64LL * m + t, j, id);
         const double* tv = a.vtab + 8 * id;
         sp += tv[AD_BX] * x[j] + tv[AD_BY] * x[nV + j] + tv[AD_C] * x[2 * nV + j];
       }
-      rp = rb[2 * nV + i] - sp;
+      g.rp = rb[2 * nV + g.i] - sp;
     } else {
-      rp = rb[2 * nV + i];
+      g.rp = rb[2 * nV + g.i];
     }
   }
-  __syncthreads();
+  return g;
+}
+
+// All lanes of the wavefront call this (the group reduction uses shuffles).
+template <bool MV>
+__device__ __forceinline__ void group_solve(const AdFactors& f, const GroupState& g, int k, int nV,
+                                            const double* srx, const double* sry, double* __restrict__ x,
+                                            double* __restrict__ yx, double* __restrict__ yy,
+                                            double* __restrict__ yp_out, double omega) {
   double zx = 0.0, zy = 0.0, kx = 0.0, ky = 0.0;
-  if (v >= 0) {
-    zx = f.zx[c * NF + k];
-    zy = f.zy[c * NF + k];
-    const double* krow = f.kfull + (long long)c * NF * NF + k * NF;
-    for (int m = 0; m < nf; ++m) {
+  if (g.v >= 0) {
+    zx = f.zx[g.c * NF + k];
+    zy = f.zy[g.c * NF + k];
+    const double* krow = f.kfull + (long long)g.c * NF * NF + k * NF;
+    for (int m = 0; m < g.nf; ++m) {
       const double kv = krow[m];
-      kx += kv * srx[g][m];
-      ky += kv * sry[g][m];
+      kx += kv * srx[m];
+      ky += kv * sry[m];
     }
   }
-  double tz = zx * rx + zy * ry;
+  double tz = zx * g.rx + zy * g.ry;
   for (int o = GRP / 2; o > 0; o >>= 1) tz += __shfl_xor(tz, o, GRP);
-  rp = __shfl(rp, 0, GRP);
-  const double yp = live ? (rp - tz) * f.invS[c] : 0.0;
+  const double rp = __shfl(g.rp, 0, GRP);
+  const double yp = g.live ? (rp - tz) * f.invS[g.c] : 0.0;
   const double ux = kx - zx * yp, uy = ky - zy * yp;
   if (MV) {
-    if (v >= 0) {
-      x[v] += omega * ux;
-      x[nV + v] += omega * uy;
+    if (g.v >= 0) {
+      x[g.v] += omega * ux;
+      x[nV + g.v] += omega * uy;
     }
-    if (live && k == 0) x[2 * nV + i] += omega * yp;
+    if (g.live && k == 0) x[2 * nV + g.i] += omega * yp;
   } else {
-    if (v >= 0) {
-      yx[e] = ux;
-      yy[e] = uy;
+    if (g.v >= 0) {
+      yx[g.e] = ux;
+      yy[g.e] = uy;
     }
-    if (live && k == 0) yp_out[i] = yp;
+    if (g.live && k == 0) yp_out[g.i] = yp;
   }
 }
 
-// AV gather: every DoF adds the corrections of the patches that hold it.
-__global__ __launch_bounds__(256) void k_ad_av_gather(AdDev a, const int* __restrict__ tsoff,
-                                                      const int* __restrict__ tpos, const double* __restrict__ yx,
-                                                      const double* __restrict__ yy, const double* __restrict__ yp,
-                                                      double* __restrict__ x, double omega) {
-  const int v = blockIdx.x * 256 + threadIdx.x;
+// AV gather: vertex v adds the corrections of the patches that hold it.
+__device__ __forceinline__ void av_gather_vertex(const AdDev& a, const int* __restrict__ tsoff,
+                                                 const int* __restrict__ tpos, const double* __restrict__ yx,
+                                                 const double* __restrict__ yy, const double* __restrict__ yp,
+                                                 double* __restrict__ x, double omega, int v) {
   const int nV = a.nV;
-  if (v >= nV) return;
   const int e0 = tsoff[v >> 6], w = (tsoff[(v >> 6) + 1] - e0) >> 6;
   const int t = v & 63;
   double su = 0.0, sv = 0.0;
@@ -325,12 +323,10 @@ __global__ __launch_bounds__(256) void k_ad_av_gather(AdDev a, const int* __rest
   x[2 * nV + v] += omega * yp[v];
 }
 
-// ---- transfers ---------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ad_prolong(AdDev f, AdDev c, const int* __restrict__ ptr,
-                                                    const int* __restrict__ idx, const double* __restrict__ w,
-                                                    const double* __restrict__ xc, double* __restrict__ xf) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= f.nV) return;
+// xf += P xc on the three rows of fine vertex i.
+__device__ __forceinline__ void prolong_vertex(const AdDev& f, const AdDev& c, const int* __restrict__ ptr,
+                                               const int* __restrict__ idx, const double* __restrict__ w,
+                                               const double* __restrict__ xc, double* __restrict__ xf, int i) {
   double su = 0.0, sv = 0.0, sp = 0.0;
   for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
     const int j = idx[k];
@@ -347,13 +343,11 @@ __global__ __launch_bounds__(256) void k_ad_prolong(AdDev f, AdDev c, const int*
   xf[2 * f.nV + i] += sp;
 }
 
-// bc = P^T rf; xc = 0 and (rc != NULL) rc = bc, the residual of xc = 0.
-__global__ __launch_bounds__(256) void k_ad_restrict(AdDev f, AdDev c, const int* __restrict__ ptr,
-                                                     const int* __restrict__ idx, const double* __restrict__ w,
-                                                     const double* __restrict__ rf, double* __restrict__ bc,
-                                                     double* __restrict__ xc, double* __restrict__ rc) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= c.nV) return;
+// bc = P^T rf on coarse vertex j; xc = 0 and (rc != NULL) rc = bc, the residual of xc = 0.
+__device__ __forceinline__ void restrict_vertex(const AdDev& f, const AdDev& c, const int* __restrict__ ptr,
+                                                const int* __restrict__ idx, const double* __restrict__ w,
+                                                const double* __restrict__ rf, double* __restrict__ bc,
+                                                double* __restrict__ xc, double* __restrict__ rc, int j) {
   double su = 0.0, sv = 0.0, sp = 0.0;
   for (int k = ptr[j]; k < ptr[j + 1]; ++k) {
     const int i = idx[k];
@@ -368,6 +362,71 @@ __global__ __launch_bounds__(256) void k_ad_restrict(AdDev f, AdDev c, const int
   bc[j] = su; bc[n + j] = sv; bc[2 * n + j] = sp;
   xc[j] = 0.0; xc[n + j] = 0.0; xc[2 * n + j] = 0.0;
   if (rc) { rc[j] = su; rc[n + j] = sv; rc[2 * n + j] = sp; }
+}
+
+// ---- grid-wide kernels -----------------------------------------------------------
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_ad_residual(AdDev a, const double* __restrict__ x,
+                                                     const double* __restrict__ b, double* __restrict__ r,
+                                                     double* __restrict__ partials) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const double sq = i < a.nV ? residual_vertex<WIDE>(a, i, x, b, r) : 0.0;
+  if (!partials) return;
+  __shared__ double red[256];
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_ad_rav(AdDev a, AdFactors f, const double* __restrict__ r,
+                                                double* __restrict__ x, double omega) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < a.nV) rav_patch<WIDE>(a, f, i, r, x, omega);
+}
+
+constexpr int GPB = 64 / GRP;   // patches per 64-lane block
+
+template <bool MV, bool WIDE>
+__global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int* __restrict__ order, int first,
+                                                 int count, const double* __restrict__ rb, double* __restrict__ x,
+                                                 double* __restrict__ yx, double* __restrict__ yy,
+                                                 double* __restrict__ yp_out, double omega) {
+  __shared__ double srx[GPB][GRP], sry[GPB][GRP];
+  const int g = threadIdx.x / GRP, k = threadIdx.x % GRP;
+  const int q = blockIdx.x * GPB + g;
+  const bool live = q < count;
+  const int i = live ? (order ? order[first + q] : first + q) : 0;
+  const GroupState st = group_load<MV, WIDE>(a, live, i, k, rb, x, srx[g], sry[g]);
+  __syncthreads();
+  group_solve<MV>(f, st, k, a.nV, srx[g], sry[g], x, yx, yy, yp_out, omega);
+}
+
+__global__ __launch_bounds__(256) void k_ad_av_gather(AdDev a, const int* __restrict__ tsoff,
+                                                      const int* __restrict__ tpos, const double* __restrict__ yx,
+                                                      const double* __restrict__ yy, const double* __restrict__ yp,
+                                                      double* __restrict__ x, double omega) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v < a.nV) av_gather_vertex(a, tsoff, tpos, yx, yy, yp, x, omega, v);
+}
+
+__global__ __launch_bounds__(256) void k_ad_prolong(AdDev f, AdDev c, const int* __restrict__ ptr,
+                                                    const int* __restrict__ idx, const double* __restrict__ w,
+                                                    const double* __restrict__ xc, double* __restrict__ xf) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < f.nV) prolong_vertex(f, c, ptr, idx, w, xc, xf, i);
+}
+
+__global__ __launch_bounds__(256) void k_ad_restrict(AdDev f, AdDev c, const int* __restrict__ ptr,
+                                                     const int* __restrict__ idx, const double* __restrict__ w,
+                                                     const double* __restrict__ rf, double* __restrict__ bc,
+                                                     double* __restrict__ xc, double* __restrict__ rc) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < c.nV) restrict_vertex(f, c, ptr, idx, w, rf, bc, xc, rc, j);
 }
 
 __global__ __launch_bounds__(256) void k_ad_scale(const double* __restrict__ src, double alpha,

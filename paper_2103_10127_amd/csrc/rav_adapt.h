@@ -95,6 +95,7 @@ void ad_launch_prolong(const AdDev& f, const AdDev& c, const int* ptr, const int
                        const double* xc, double* xf, hipStream_t s);
 void ad_launch_restrict(const AdDev& f, const AdDev& c, const int* ptr, const int* idx, const double* w,
                         const double* rf, double* bc, double* xc, double* rc, hipStream_t s);
+
 void ad_launch_scale(const double* src, double alpha, double* dst, long long n, hipStream_t s);
 void ad_launch_owner(const AdDev& a, int* owner, hipStream_t s);
 
