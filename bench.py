@@ -348,6 +348,7 @@ def main():
                 Hm.close()
         out["variants"] = variants
         out["q1q1_cavity_1024"] = q1q1_summary()
+        out["adaptive_cavity_table1"] = adaptive_summary()
     else:
         H.close()
 
@@ -635,6 +636,40 @@ def q1q1_summary() -> dict:
     return {"dofs": n, "status": "converged" if st == 0 else str(st), "cycles": it,
             "time_to_1e-8_ms": 1e3 * best,
             "smoothed_dofs_per_s": it * sum(6 * level_n[l] for l in range(1, nl)) / best}
+
+
+def adaptive_summary() -> dict:
+    """The paper's own grids beside the headline: stabilized Q1-Q1 driven cavity
+    on the adaptive hierarchy of Table 1 (Omega^1..Omega^10, 3,063,075 DoFs),
+    RAV V(3,3), omega 0.66, beta 0.05, solve to 1e-8 (best of 3)."""
+    import torch
+    from paper_2103_10127_amd.capi import AdaptiveHierarchy
+    n_grids = 10
+    t0 = time.perf_counter()
+    H = AdaptiveHierarchy(ri.cavity_grids(n_grids), ri.lattice(n_grids), smoother="rav", omega=0.66, nu_pre=3,
+                          nu_post=3, beta=0.05)
+    H.factor()
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    n, _ = H.dofs(n_grids - 1)
+    level_n = [H.dofs(l)[0] for l in range(n_grids)]
+    b = torch.zeros(n, dtype=torch.float64, device="cuda")
+    H.assemble_rhs_lid(b, 1.0)
+    x = torch.zeros_like(b)
+    H.solve(x, b, 1e-8, 2)
+    best, st, it = None, None, 0
+    for _ in range(3):
+        x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, it, _ = H.solve(x, b, 1e-8, 200)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        best = dt if best is None else min(best, dt)
+    H.close()
+    return {"dofs": n, "status": "converged" if st == 0 else str(st), "cycles": it,
+            "time_to_1e-8_ms": 1e3 * best, "setup_s": round(setup, 2),
+            "smoothed_dofs_per_s": it * sum(6 * level_n[l] for l in range(1, n_grids)) / best}
 
 
 def bench_q1q1(args):
