@@ -62,3 +62,18 @@ def is_balanced(leaves):
             if np.isin((px * M + py)[ok], corners).any():
                 return False
     return True
+
+
+def uniform_refinement_counts(n_vertices: int, n_cells: int, holes: int, steps: int):
+    """(cells, vertices) of a conforming quadrilateral mesh of a planar domain
+    with `holes` holes after each of `steps` uniform refinements.  Euler's
+    formula V - E + F = 1 - holes gives the edge count; one refinement adds a
+    vertex per edge and per cell, splits every edge in two and every cell in
+    four (four new interior edges)."""
+    V, F = n_vertices, n_cells
+    E = V + F - (1 - holes)
+    out = []
+    for _ in range(steps):
+        V, E, F = V + E + F, 2 * E + 4 * F, 4 * F
+        out.append((F, V))
+    return out

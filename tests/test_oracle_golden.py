@@ -51,3 +51,30 @@ def test_table1_adaptive_hierarchy_counts():
         assert 3 * regular == n_dof, (k, 3 * regular, n_dof)
         if k <= 7:
             assert ad.is_balanced(leaves), k
+
+
+TABLE2 = os.path.join(os.path.dirname(__file__), "golden", "table2_grids.txt")
+
+
+def test_table2_first_grids_are_uniform_refinements():
+    """Table 2 (Sec. 4.2): the cylinder channel is a domain with one hole.  Its
+    coarse grid (758 cells, 2526 / 3 = 842 vertices) refined uniformly twice
+    gives exactly the printed counts of Omega^2 and Omega^3 (three unknowns
+    per vertex); from Omega^4 on the grids are refined adaptively (fewer cells
+    than a uniform step would give) and every printed DoF count is still three
+    per vertex.  The mesh itself and the refinement rule beyond Omega^3 are not
+    given, so the cylinder grids are not built."""
+    from oracle import adaptive as ad
+    rows = [tuple(int(v) for v in line.split()) for line in open(TABLE2)
+            if line.strip() and not line.startswith("#")]
+    (_, n_e1, n_dof1) = rows[0]
+    assert n_dof1 % 3 == 0
+    steps = ad.uniform_refinement_counts(n_dof1 // 3, n_e1, holes=1, steps=2)
+    for (k, n_e, n_dof), (cells, verts) in zip(rows[1:3], steps):
+        assert (cells, 3 * verts) == (n_e, n_dof), k
+    # a domain without the hole would not match
+    assert ad.uniform_refinement_counts(n_dof1 // 3, n_e1, holes=0, steps=1)[0][1] * 3 != rows[1][2]
+    for (k, n_e, n_dof), (_, n_e_prev, _) in zip(rows[3:], rows[2:]):
+        assert n_dof % 3 == 0 and n_e_prev < n_e < 4 * n_e_prev, k
+    # the uniform Table 1 coarse grid (unit square, no hole) follows the same rule
+    assert ad.uniform_refinement_counts(25, 16, holes=0, steps=1)[0] == (64, 81)
