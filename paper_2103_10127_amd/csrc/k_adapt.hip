@@ -142,6 +142,7 @@ __device__ __forceinline__ double residual_vertex(const AdDev& a, int i, const d
   const int e0 = a.soff[i >> 6], w = (a.soff[(i >> 6) + 1] - e0) >> 6;
   const int t = i & 63;
   double su = 0.0, sv = 0.0, sp = 0.0;
+#pragma unroll 2
   for (int k = 0; k < w; ++k) {
     int j, id;
     entry<WIDE>(a, i, e0 + 64LL * k + t, j, id);
@@ -176,6 +177,7 @@ __device__ __forceinline__ void rav_patch(const AdDev& a, const AdFactors& f, in
   const double* zyc = f.zy + c * NF;
   const double* krc = f.kr + c * NF;
   double tz = 0.0, ku = 0.0, kv = 0.0;
+#pragma unroll 2   // two patch vertices' loads in flight (measured 39.7 -> 30.4 us per Omega^10 launch)
   for (int k = 0; k < nf; ++k) {
     const int v = patch_vertex<WIDE>(a, i, p0 + 64LL * k + t);
     const double rx = r[v], ry = r[nV + v];
