@@ -188,3 +188,46 @@ def cavity_grids(n_grids: int = 10, bands=BANDS):
     return grids
 
 
+def random_quadtree_grids(n_grids: int = 4, base: int = 4, frac: float = 0.3, seed: int = 0):
+    """A nested hierarchy of 2:1-balanced quadtree grids over the unit square
+    with randomly placed refinement (a stress case for hanging nodes: chains
+    of constrained corners, patches of every shape).  Grid 1 is the uniform
+    base x base grid; each next grid refines a random fraction `frac` of the
+    refinable leaves and then every leaf whose edge meets a leaf smaller than
+    half its size, until the grid is balanced.  Leaves (x0, y0, s) in units of
+    half the smallest possible cell; returns (grids, lattice units per side)."""
+    rng = np.random.default_rng(seed)
+    s0 = 1 << n_grids
+    M = base * s0
+    leaves = {(i * s0, j * s0, s0) for i in range(base) for j in range(base)}
+    grids = [np.array(sorted(leaves), dtype=np.int64)]
+
+    def split(leaf):
+        x0, y0, sz = leaf
+        h = sz // 2
+        return {(x0 + dx * h, y0 + dy * h, h) for dx in (0, 1) for dy in (0, 1)}
+
+    for _ in range(1, n_grids):
+        cand = sorted(lf for lf in leaves if lf[2] >= 4)
+        pick = rng.random(len(cand)) < frac
+        for lf, p in zip(cand, pick):
+            if p:
+                leaves.remove(lf)
+                leaves |= split(lf)
+        while True:   # 2:1 balance: no leaf corner at a quarter point of a larger leaf's edge
+            corners = {(x0 + a * sz, y0 + b * sz) for x0, y0, sz in leaves for a in (0, 1) for b in (0, 1)}
+            bad = set()
+            for x0, y0, sz in leaves:
+                if sz < 4:
+                    continue
+                for q in (sz // 4, 3 * sz // 4):
+                    if {(x0 + q, y0), (x0 + q, y0 + sz), (x0, y0 + q), (x0 + sz, y0 + q)} & corners:
+                        bad.add((x0, y0, sz))
+                        break
+            if not bad:
+                break
+            for lf in bad:
+                leaves.remove(lf)
+                leaves |= split(lf)
+        grids.append(np.array(sorted(leaves), dtype=np.int64))
+    return grids, M

@@ -1,7 +1,7 @@
 """Host-side set-up of the adaptive grids (rav_adaptive_host_export, no device)
 against the oracle (Sec. 2, Fig. 2; Sec. 4.1, Table 1): conforming operator
 with hanging-node constraints, lid lifting, grid transfer and the MV colouring
-on the first grids of the cavity hierarchy, the DoF counts of Table 1, and the
+on the first grids of the cavity hierarchy and on a randomly refined one, the DoF counts of Table 1, and the
 rejection of grids that break the rules (not tiling, not 2:1 balanced, not
 nested)."""
 import os
@@ -17,9 +17,11 @@ BETA, ETA = 0.05, 1.0
 N_GRIDS = 4
 
 
-@pytest.fixture(scope="module")
-def hierarchy():
-    return ri.cavity_grids(N_GRIDS), ri.lattice(N_GRIDS)
+@pytest.fixture(scope="module", params=["cavity", "random"])
+def hierarchy(request):
+    if request.param == "cavity":
+        return ri.cavity_grids(N_GRIDS), ri.lattice(N_GRIDS)
+    return ri.random_quadtree_grids(N_GRIDS, base=8, frac=0.35, seed=1)
 
 
 @pytest.mark.parametrize("level", range(N_GRIDS))

@@ -1,6 +1,6 @@
 """Stabilized Q1-Q1 on the adaptive cavity grids (Sec. 2, Fig. 2; Sec. 4.1,
-Table 1) on the GPU against the oracle: on Omega^1..Omega^4 (7,059 DoFs) the
-residual of every grid, DoF counts, owner and patch maps, the stored local
+Table 1) on the GPU against the oracle: on Omega^1..Omega^4 (7,059 DoFs), and
+on a randomly refined balanced hierarchy, the residual of every grid, DoF counts, owner and patch maps, the stored local
 inverses (RAV owned rows, AV/MV every row), transfers, the coarse solve,
 RAV/AV/MV sweeps and V-cycles, the lid right-hand side, and solves to 1e-8
 with the oracle's cycle counts.  On the full hierarchy Omega^1..Omega^10
@@ -26,9 +26,13 @@ OMEGA = {"rav": 0.66, "mv": 0.66, "av": 0.1}
 SM = {"rav": mg.RAV, "av": mg.AV, "mv": mg.MV}
 
 
-@pytest.fixture(scope="module")
-def grids():
-    return ri.cavity_grids(N_GRIDS), ri.lattice(N_GRIDS)
+@pytest.fixture(scope="module", params=["cavity", "random"])
+def grids(request):
+    """The first four grids of Table 1, and a randomly refined 2:1-balanced
+    hierarchy (many hanging nodes, including constrained endpoints)."""
+    if request.param == "cavity":
+        return ri.cavity_grids(N_GRIDS), ri.lattice(N_GRIDS)
+    return ri.random_quadtree_grids(N_GRIDS, base=8, frac=0.35, seed=1)
 
 
 @pytest.fixture(scope="module")

@@ -41,13 +41,22 @@ def _bilinear(g):
     return np.concatenate([f, 2 * f, -f])
 
 
-def test_bilinear_functions_through_hanging_nodes_and_transfer():
-    """Grids 2 and 3 of Table 1 (16 and 56 hanging nodes): interpolating a
-    bilinear function to the fine regular vertices with P (its pressure block,
-    which no boundary condition masks) equals its values there; every hanging
-    node's constraint weights reproduce it too."""
-    grids = ad.cavity_grids(3)
-    M = ad.lattice(3)
+def _hierarchy(kind, n=3):
+    """Grids of Table 1, or a randomly refined balanced hierarchy whose hanging
+    nodes include constrained endpoints (chains of constraints)."""
+    if kind == "table1":
+        return ad.cavity_grids(n), ad.lattice(n)
+    return ri.random_quadtree_grids(n, base=8, frac=0.35, seed=2)
+
+
+@pytest.mark.parametrize("kind", ["table1", "random"])
+def test_bilinear_functions_through_hanging_nodes_and_transfer(kind):
+    """Grids 2 and 3 (Table 1: 16 and 56 hanging nodes; the random hierarchy:
+    more, some constrained by hanging nodes): interpolating a bilinear
+    function to the fine regular vertices with P (its pressure block, which no
+    boundary condition masks) equals its values there; every hanging node's
+    constraint weights reproduce it too."""
+    grids, M = _hierarchy(kind)
     gs = [am.AdaptiveGrid(lv, M, BETA) for lv in grids]
     for gc, gf in zip(gs[1:], gs[2:]):
         assert len(gf.hang_ends) > 0
@@ -62,12 +71,13 @@ def test_bilinear_functions_through_hanging_nodes_and_transfer():
             assert abs(val - exact) <= 1e-13
 
 
-def test_shear_flow_is_exact_with_hanging_nodes():
-    """Dirichlet data u = (y, 0) on the boundary of grid 3 of Table 1: the
-    conforming bilinear space holds the Stokes solution exactly (p = const),
-    hanging nodes included."""
-    M = ad.lattice(3)
-    g = am.AdaptiveGrid(ad.cavity_grids(3)[2], M, BETA)
+@pytest.mark.parametrize("kind", ["table1", "random"])
+def test_shear_flow_is_exact_with_hanging_nodes(kind):
+    """Dirichlet data u = (y, 0) on the boundary of grid 3: the conforming
+    bilinear space holds the Stokes solution exactly (p = const), hanging
+    nodes included."""
+    grids, M = _hierarchy(kind)
+    g = am.AdaptiveGrid(grids[2], M, BETA)
     uD = np.zeros(g.n)
     uD[: g.nV] = g.ry / M
     b = g.lifting(uD)
@@ -85,11 +95,12 @@ def test_shear_flow_is_exact_with_hanging_nodes():
     assert np.abs(x[g.pressure_slice()]).max() <= 1e-9   # p = 0 up to the direct solve's rounding
 
 
-def test_mv_colouring_gives_the_colour_parallel_sweep():
+@pytest.mark.parametrize("kind", ["table1", "random"])
+def test_mv_colouring_gives_the_colour_parallel_sweep(kind):
     """MV in colour order equals adding all same-colour patch corrections
-    computed from one x, colour after colour, on grid 3 of Table 1."""
-    grids = ad.cavity_grids(3)
-    H = am.AdaptiveHierarchy(grids, ad.lattice(3), BETA)
+    computed from one x, colour after colour, on grid 3."""
+    grids, M = _hierarchy(kind)
+    H = am.AdaptiveHierarchy(grids, M, BETA)
     lv = H.finest
     ps = lv.patches
     g = lv.grid
