@@ -40,6 +40,8 @@
 #ifndef RAV_H
 #define RAV_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -354,6 +356,19 @@ rav_status rav_adaptive_level_info(const rav_ctx* ctx, int level, long* info_hos
  * rav_create_adaptive. */
 rav_status rav_adaptive_host_export(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
                                     long lattice, int level, int what, double* out_host, long* rows, long* cols);
+
+/* Device memory of every buffer the library allocates (hierarchies, patch
+ * inverses, work vectors of rav_solve_gmres, batches, networks): by default
+ * hipMalloc/hipFree; with this call the caller's functions instead, e.g. a
+ * framework's caching allocator.  alloc(bytes, user) returns device memory
+ * on the current device aligned to at least 256 bytes, or NULL (the library
+ * call then returns RAV_ENOMEM); release(ptr, user) frees it.  Both NULL
+ * restores hipMalloc/hipFree.  RAV_EINVAL if only one function is given or
+ * while any context, batch or network exists (each buffer is released by the
+ * allocator that made it).  Not to be called while another thread uses the
+ * library.  rav_solve_gmres_noalloc allocates nothing either way. */
+rav_status rav_set_device_allocator(void* (*alloc)(size_t bytes, void* user), void (*release)(void* ptr, void* user),
+                                    void* user);
 
 rav_status rav_destroy(rav_ctx* ctx);
 

@@ -51,6 +51,8 @@ _I = ctypes.c_int
 _L = ctypes.c_long
 _D = ctypes.c_double
 _S = ctypes.c_int   # rav_status
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 SIGNATURES = {
     "rav_create": (_S, [ctypes.POINTER(RavProblemDesc), _P, ctypes.POINTER(_P)]),
@@ -108,6 +110,7 @@ SIGNATURES = {
     "rav_batch_destroy": (_S, [_P]),
     "rav_batch_last_error": (ctypes.c_char_p, [_P]),
     "rav_last_error": (ctypes.c_char_p, [_P]),
+    "rav_set_device_allocator": (_S, [_ALLOC_FN, _RELEASE_FN, _P]),
     "rav_create_adaptive": (_S, [ctypes.POINTER(RavProblemDesc), ctypes.POINTER(_I), ctypes.POINTER(_L), _L, _P,
                                  ctypes.POINTER(_P)]),
     "rav_adaptive_level_info": (_S, [_P, _I, ctypes.POINTER(_L)]),
@@ -123,6 +126,10 @@ def header_functions(path: str = HEADER) -> list[str]:
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    try:   # torch's HIP runtime first: the library then uses the runtime torch's streams belong to
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
     lib = ctypes.CDLL(path)
@@ -556,6 +563,31 @@ def map_owner(desc, level, n_total):
     if st < 0:
         raise RavError(st, "rav_map_owner")
     return out
+
+
+_allocator = None   # the ctypes callbacks of the installed allocator (kept alive here)
+
+
+def set_device_allocator(alloc=None, release=None):
+    """Device memory of the library's buffers from Python callables:
+    alloc(nbytes) -> device address (int), release(address).  No arguments
+    restore hipMalloc/hipFree.  Only while no context, batch or network
+    exists (``rav_set_device_allocator``)."""
+    global _allocator
+    fa = _ALLOC_FN() if alloc is None else _ALLOC_FN(lambda n, user: alloc(n) or None)   # None: NULL
+    fr = _RELEASE_FN() if release is None else _RELEASE_FN(lambda ptr, user: release(ptr))
+    st = lib().rav_set_device_allocator(fa, fr, None)
+    if st < 0:
+        raise RavError(st, lib().rav_last_error(None).decode())
+    _allocator = None if alloc is None else (fa, fr)
+
+
+def use_torch_allocator():
+    """Serve the library's device buffers from PyTorch's caching allocator
+    (current device and stream)."""
+    import torch
+    set_device_allocator(lambda n: torch.cuda.caching_allocator_alloc(n),
+                         lambda p: torch.cuda.caching_allocator_delete(p))
 
 
 def stream_copy(dst, src, n=None, stream=None):

@@ -603,7 +603,7 @@ template <class T>
 hipError_t upload(T** d, const std::vector<T>& h) {
   *d = nullptr;
   if (h.empty()) return hipSuccess;
-  hipError_t e = hipMalloc((void**)d, sizeof(T) * h.size());
+  hipError_t e = rav_dmalloc((void**)d, sizeof(T) * h.size());
   if (e == hipSuccess) e = hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
   return e;
 }
@@ -723,18 +723,18 @@ rav_status build_coarse(rav_ctx* ctx, const HostLevel& H) {
     M[(size_t)(n0 * nb + j)] = 1.0;
     M[(size_t)(j * nb + n0)] = 1.0;
   }
-  ACK(hipMalloc((void**)&S->Minv, sizeof(double) * nb * nb));
+  ACK(rav_dmalloc((void**)&S->Minv, sizeof(double) * nb * nb));
   ACK(hipMemcpy(S->Minv, M.data(), sizeof(double) * nb * nb, hipMemcpyHostToDevice));
   double** dM = nullptr;
   int *piv = nullptr, *perm = nullptr, *pst = nullptr;
   double *colk = nullptr, *Rs = nullptr;
   const int big = INT_MAX;
-  ACK(hipMalloc((void**)&dM, sizeof(double*)));
-  ACK(hipMalloc((void**)&piv, sizeof(int) * nb));
-  ACK(hipMalloc((void**)&perm, sizeof(int) * nb));
-  ACK(hipMalloc((void**)&pst, sizeof(int)));
-  ACK(hipMalloc((void**)&colk, sizeof(double) * nb));
-  ACK(hipMalloc((void**)&Rs, sizeof(double) * GJ_PANEL * nb));
+  ACK(rav_dmalloc((void**)&dM, sizeof(double*)));
+  ACK(rav_dmalloc((void**)&piv, sizeof(int) * nb));
+  ACK(rav_dmalloc((void**)&perm, sizeof(int) * nb));
+  ACK(rav_dmalloc((void**)&pst, sizeof(int)));
+  ACK(rav_dmalloc((void**)&colk, sizeof(double) * nb));
+  ACK(rav_dmalloc((void**)&Rs, sizeof(double) * GJ_PANEL * nb));
   ACK(hipMemcpy(dM, &S->Minv, sizeof(double*), hipMemcpyHostToDevice));
   ACK(hipMemcpy(pst, &big, sizeof(int), hipMemcpyHostToDevice));
   launch_bgj_invert(dM, nb, 1, piv, colk, Rs, perm, pst, ctx->stream);
@@ -742,8 +742,8 @@ rav_status build_coarse(rav_ctx* ctx, const HostLevel& H) {
   int status = 0;
   ACK(hipMemcpyAsync(&status, pst, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   ACK(hipStreamSynchronize(ctx->stream));
-  (void)hipFree(dM); (void)hipFree(piv); (void)hipFree(perm); (void)hipFree(pst); (void)hipFree(colk);
-  (void)hipFree(Rs);
+  (void)rav_dfree(dM); (void)rav_dfree(piv); (void)rav_dfree(perm); (void)rav_dfree(pst); (void)rav_dfree(colk);
+  (void)rav_dfree(Rs);
   if (status != INT_MAX)
     return rav_set_error(ctx, RAV_ESINGULAR, "zero pivot in the coarse matrix at column " + std::to_string(status));
   return RAV_OK;
@@ -793,14 +793,14 @@ rav_status upload_level(rav_ctx* ctx, Level& L, const HostLevel& H, bool smoothe
   if (H.wide) ACK(upload(&L.col, H.col));
   ACK(upload(&L.vtab, H.vtab));
   const long long n = 3LL * H.nV;
-  ACK(hipMalloc((void**)&L.x, sizeof(double) * n));
-  ACK(hipMalloc((void**)&L.b, sizeof(double) * n));
-  ACK(hipMalloc((void**)&L.r, sizeof(double) * n));
+  ACK(rav_dmalloc((void**)&L.x, sizeof(double) * n));
+  ACK(rav_dmalloc((void**)&L.b, sizeof(double) * n));
+  ACK(rav_dmalloc((void**)&L.r, sizeof(double) * n));
   ACK(hipMemset(L.x, 0, sizeof(double) * n));
   ACK(hipMemset(L.b, 0, sizeof(double) * n));
   ACK(hipMemset(L.r, 0, sizeof(double) * n));
   L.nres = ad_residual_blocks(H.nV);
-  ACK(hipMalloc((void**)&L.partials, sizeof(double) * L.nres));
+  ACK(rav_dmalloc((void**)&L.partials, sizeof(double) * L.nres));
   AdDev& a = L.dev;
   a.nV = H.nV;
   a.nslice = (int)H.soff.size() - 1;
@@ -969,10 +969,10 @@ void rav_ad_free(rav_ctx* ctx) {
                     L.fac.zx, L.fac.zy, L.fac.invS,
                     L.fac.kr, L.fac.kfull, L.tsoff, L.tpos, L.yx, L.yy, L.yp, L.order, L.pptr, L.pidx, L.pw,
                     L.rptr, L.ridx, L.rw, L.x, L.b, L.r, L.partials};
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) (void)rav_dfree(p);
   }
-  (void)hipFree(S->Minv);
-  (void)hipFree(S->blid);
+  (void)rav_dfree(S->Minv);
+  (void)rav_dfree(S->blid);
   delete S;
   ctx->ad = nullptr;
 }
@@ -984,16 +984,16 @@ rav_status rav_ad_factor(rav_ctx* ctx) {
     Level& L = S->lv[l];
     if (!L.fac.zx) {
       const long long nc = std::max(L.ncfg, 1);
-      ACK(hipMalloc((void**)&L.fac.zx, sizeof(double) * nc * AD_NFMAX));
-      ACK(hipMalloc((void**)&L.fac.zy, sizeof(double) * nc * AD_NFMAX));
-      ACK(hipMalloc((void**)&L.fac.invS, sizeof(double) * nc));
+      ACK(rav_dmalloc((void**)&L.fac.zx, sizeof(double) * nc * AD_NFMAX));
+      ACK(rav_dmalloc((void**)&L.fac.zy, sizeof(double) * nc * AD_NFMAX));
+      ACK(rav_dmalloc((void**)&L.fac.invS, sizeof(double) * nc));
       if (S->mode == AD_RAV) {
-        ACK(hipMalloc((void**)&L.fac.kr, sizeof(double) * nc * AD_NFMAX));
+        ACK(rav_dmalloc((void**)&L.fac.kr, sizeof(double) * nc * AD_NFMAX));
       } else {
-        ACK(hipMalloc((void**)&L.fac.kfull, sizeof(double) * nc * AD_NFMAX * AD_NFMAX));
-        ACK(hipMalloc((void**)&L.yx, sizeof(double) * L.pnnz));
-        ACK(hipMalloc((void**)&L.yy, sizeof(double) * L.pnnz));
-        ACK(hipMalloc((void**)&L.yp, sizeof(double) * L.nV));
+        ACK(rav_dmalloc((void**)&L.fac.kfull, sizeof(double) * nc * AD_NFMAX * AD_NFMAX));
+        ACK(rav_dmalloc((void**)&L.yx, sizeof(double) * L.pnnz));
+        ACK(rav_dmalloc((void**)&L.yy, sizeof(double) * L.pnnz));
+        ACK(rav_dmalloc((void**)&L.yp, sizeof(double) * L.nV));
       }
     }
     ACK(hipMemcpy(ctx->d_status, &big, sizeof(int), hipMemcpyHostToDevice));

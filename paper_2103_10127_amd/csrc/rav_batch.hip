@@ -61,6 +61,7 @@ __global__ __launch_bounds__(256) void k_norm_scatter(const double* __restrict__
 }  // namespace
 
 struct rav_batch {
+  LiveCount live_;
   std::vector<rav_ctx*> sub;
   hipStream_t stream = nullptr;
   int dim = 2, prec = P_FP64, nu_pre = 2, nu_post = 2, kind = 0;
@@ -113,14 +114,14 @@ static std::string g_batch_error;
 static rav_status upload(rav_batch* B, const std::vector<BlockTask>& logical, BlockTask** out, int* n) {
   std::vector<BlockTask> t = xcd_order(logical);
   *n = (int)t.size();
-  BCK(hipMalloc((void**)out, sizeof(BlockTask) * std::max<size_t>(t.size(), 1)));
+  BCK(rav_dmalloc((void**)out, sizeof(BlockTask) * std::max<size_t>(t.size(), 1)));
   BCK(hipMemcpy(*out, t.data(), sizeof(BlockTask) * t.size(), hipMemcpyHostToDevice));
   return RAV_OK;
 }
 
 template <typename T>
 static rav_status upload_vec(rav_batch* B, const std::vector<T>& v, T** out) {
-  BCK(hipMalloc((void**)out, sizeof(T) * std::max<size_t>(v.size(), 1)));
+  BCK(rav_dmalloc((void**)out, sizeof(T) * std::max<size_t>(v.size(), 1)));
   if (!v.empty()) BCK(hipMemcpy(*out, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
   return RAV_OK;
 }
@@ -188,7 +189,7 @@ static rav_status build_plans(rav_batch* B) {
     }
     if (!P.top.empty()) {
       if ((st = upload(B, tr, &P.top_res, &P.n_top_res)) != RAV_OK) return st;
-      BCK(hipMalloc((void**)&P.partials, sizeof(double) * tr.size()));
+      BCK(rav_dmalloc((void**)&P.partials, sizeof(double) * tr.size()));
       if ((st = upload_vec(B, first, &P.first)) != RAV_OK) return st;
       if ((st = upload_vec(B, count, &P.count)) != RAV_OK) return st;
       if ((st = upload_vec(B, pid, &P.pid)) != RAV_OK) return st;
@@ -355,12 +356,12 @@ rav_status rav_batch_create(const rav_problem_desc* descs, int n, void* hip_stre
       if (st != RAV_OK) return fail(st, "coarse matrix: " + grp[g]->err);
     }
   }
-  if (hipMalloc((void**)&B->d_active, sizeof(int) * n) != hipSuccess ||
-      hipMalloc((void**)&B->d_norm2, sizeof(double) * n) != hipSuccess ||
+  if (rav_dmalloc((void**)&B->d_active, sizeof(int) * n) != hipSuccess ||
+      rav_dmalloc((void**)&B->d_norm2, sizeof(double) * n) != hipSuccess ||
       hipHostMalloc((void**)&B->h_norm2, sizeof(double) * n, hipHostMallocDefault) != hipSuccess ||
       hipHostGetDevicePointer((void**)&B->h_norm2_dev, B->h_norm2, 0) != hipSuccess ||
-      hipMalloc((void**)&B->d_dst, sizeof(double*) * n) != hipSuccess ||
-      hipMalloc((void**)&B->d_src, sizeof(double*) * n) != hipSuccess)
+      rav_dmalloc((void**)&B->d_dst, sizeof(double*) * n) != hipSuccess ||
+      rav_dmalloc((void**)&B->d_src, sizeof(double*) * n) != hipSuccess)
     return fail(RAV_ENOMEM, "batch table allocation failed");
   std::vector<int> ones(n, 1);
   if (hipMemcpy(B->d_active, ones.data(), sizeof(int) * n, hipMemcpyHostToDevice) != hipSuccess)
@@ -412,14 +413,14 @@ static rav_status autotune_batch(rav_batch* B) {
         float ms = 0.f;
         if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
         if (ms < best) {
-          if (best_tasks) (void)hipFree(best_tasks);
+          if (best_tasks) (void)rav_dfree(best_tasks);
           best = ms; best_split = split; best_tasks = tasks; best_n = nt;
         } else {
-          (void)hipFree(tasks);
+          (void)rav_dfree(tasks);
         }
       }
       if (best_tasks) {
-        (void)hipFree(al.tasks);
+        (void)rav_dfree(al.tasks);
         al.tasks = best_tasks; al.ntasks = best_n; al.split = best_split;
       }
       B->apply_split_log.push_back(al.split);
@@ -557,7 +558,7 @@ static rav_status build_vector_tasks(rav_batch* B) {
   if (st != RAV_OK) return st;
   if ((st = upload_vec(B, first, &B->v_first)) != RAV_OK) return st;
   if ((st = upload_vec(B, count, &B->v_count)) != RAV_OK) return st;
-  BCK(hipMalloc((void**)&B->v_partial, sizeof(double) * std::max<size_t>(vt.size(), 1)));
+  BCK(rav_dmalloc((void**)&B->v_partial, sizeof(double) * std::max<size_t>(vt.size(), 1)));
   return RAV_OK;
 }
 
@@ -582,7 +583,7 @@ rav_status rav_batch_solve_gmres(rav_batch* B, double* const* x, const double* c
   int* jdev = nullptr;
   const long long ntab = (long long)P * (2LL * m + 6);
   auto cleanup = [&]() {
-    (void)hipFree(work); (void)hipFree(tabs); (void)hipFree(hdev); (void)hipFree(ydev); (void)hipFree(jdev);
+    (void)rav_dfree(work); (void)rav_dfree(tabs); (void)rav_dfree(hdev); (void)rav_dfree(ydev); (void)rav_dfree(jdev);
   };
   auto fail = [&](hipError_t e, const char* what) {
     B->err = std::string(what) + ": " + hipGetErrorString(e);
@@ -590,11 +591,11 @@ rav_status rav_batch_solve_gmres(rav_batch* B, double* const* x, const double* c
     return e == hipErrorOutOfMemory ? RAV_ENOMEM : RAV_EDEVICE;
   };
   hipError_t e;
-  if ((e = hipMalloc((void**)&work, sizeof(double) * std::max(total, 1LL))) != hipSuccess) return fail(e, "work");
-  if ((e = hipMalloc((void**)&tabs, sizeof(double*) * ntab)) != hipSuccess) return fail(e, "tables");
-  if ((e = hipMalloc((void**)&hdev, sizeof(double) * P * (m + 2) * (m + 1))) != hipSuccess) return fail(e, "h");
-  if ((e = hipMalloc((void**)&ydev, sizeof(double) * P * m)) != hipSuccess) return fail(e, "y");
-  if ((e = hipMalloc((void**)&jdev, sizeof(int) * P)) != hipSuccess) return fail(e, "jend");
+  if ((e = rav_dmalloc((void**)&work, sizeof(double) * std::max(total, 1LL))) != hipSuccess) return fail(e, "work");
+  if ((e = rav_dmalloc((void**)&tabs, sizeof(double*) * ntab)) != hipSuccess) return fail(e, "tables");
+  if ((e = rav_dmalloc((void**)&hdev, sizeof(double) * P * (m + 2) * (m + 1))) != hipSuccess) return fail(e, "h");
+  if ((e = rav_dmalloc((void**)&ydev, sizeof(double) * P * m)) != hipSuccess) return fail(e, "y");
+  if ((e = rav_dmalloc((void**)&jdev, sizeof(int) * P)) != hipSuccess) return fail(e, "jend");
   std::vector<double*> ht(ntab);
   double** const dV = tabs;                       // V_i of problem p at dV[i * P + p]
   double** const dZ = tabs + (long long)P * (m + 1);
@@ -775,16 +776,16 @@ rav_status rav_batch_destroy(rav_batch* B) {
   if (!B) return RAV_OK;
   (void)hipStreamSynchronize(B->stream);
   for (DepthPlan& P : B->depth) {
-    (void)hipFree(P.dG); (void)hipFree(P.res); (void)hipFree(P.rtask); (void)hipFree(P.ptask);
-    (void)hipFree(P.top_res); (void)hipFree(P.partials); (void)hipFree(P.first); (void)hipFree(P.count);
-    (void)hipFree(P.pid); (void)hipFree(P.coarse);
-    for (ApplyLaunch& a : P.apply) (void)hipFree(a.tasks);
+    (void)rav_dfree(P.dG); (void)rav_dfree(P.res); (void)rav_dfree(P.rtask); (void)rav_dfree(P.ptask);
+    (void)rav_dfree(P.top_res); (void)rav_dfree(P.partials); (void)rav_dfree(P.first); (void)rav_dfree(P.count);
+    (void)rav_dfree(P.pid); (void)rav_dfree(P.coarse);
+    for (ApplyLaunch& a : P.apply) (void)rav_dfree(a.tasks);
   }
   if (B->cycle_exec) (void)hipGraphExecDestroy(B->cycle_exec);
-  (void)hipFree(B->vtasks); (void)hipFree(B->v_first); (void)hipFree(B->v_count); (void)hipFree(B->v_partial);
+  (void)rav_dfree(B->vtasks); (void)rav_dfree(B->v_first); (void)rav_dfree(B->v_count); (void)rav_dfree(B->v_partial);
   for (rav_ctx* c : B->sub) rav_destroy(c);
-  (void)hipFree(B->d_active); (void)hipFree(B->d_norm2); (void)hipFree(B->d_dst); (void)hipFree((void*)B->d_src);
-  (void)hipFree(B->d_n); (void)hipFree(B->copy_tasks);
+  (void)rav_dfree(B->d_active); (void)rav_dfree(B->d_norm2); (void)rav_dfree(B->d_dst); (void)rav_dfree((void*)B->d_src);
+  (void)rav_dfree(B->d_n); (void)rav_dfree(B->copy_tasks);
   if (B->h_norm2) (void)hipHostFree(B->h_norm2);
   delete B;
   return RAV_OK;

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -154,9 +155,37 @@ rav_status rav_set_error(rav_ctx* ctx, rav_status st, const std::string& msg) {
 static rav_status set_err(rav_ctx* ctx, rav_status st, const std::string& msg) { return rav_set_error(ctx, st, msg); }
 
 // Status word, norm buffers (device and pinned host) and the inclusion table.
+// ---- device memory ------------------------------------------------------------
+std::atomic<long> rav_live_objects{0};
+
+namespace {
+struct DeviceAllocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*release)(void*, void*) = nullptr;
+  void* user = nullptr;
+};
+DeviceAllocator g_alloc;
+std::mutex g_alloc_mutex;
+}  // namespace
+
+hipError_t rav_dmalloc(void** p, size_t bytes) {
+  if (!g_alloc.alloc) return hipMalloc(p, bytes);
+  *p = nullptr;
+  if (bytes == 0) return hipSuccess;   // as hipMalloc
+  *p = g_alloc.alloc(bytes, g_alloc.user);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+hipError_t rav_dfree(void* p) {
+  if (!p) return hipSuccess;
+  if (!g_alloc.release) return hipFree(p);
+  g_alloc.release(p, g_alloc.user);
+  return hipSuccess;
+}
+
 rav_status rav_init_common(rav_ctx* ctx, const rav_problem_desc* d) {
-  CK(hipMalloc((void**)&ctx->d_status, sizeof(int)));
-  CK(hipMalloc((void**)&ctx->d_norm, sizeof(double)));
+  CK(rav_dmalloc((void**)&ctx->d_status, sizeof(int)));
+  CK(rav_dmalloc((void**)&ctx->d_norm, sizeof(double)));
   CK(hipHostMalloc((void**)&ctx->h_norm, sizeof(double), hipHostMallocDefault));
   CK(hipHostGetDevicePointer((void**)&ctx->h_norm_dev, ctx->h_norm, 0));
   std::vector<double> inc(4 * std::max(d->n_incl, 1), 0.0);
@@ -164,7 +193,7 @@ rav_status rav_init_common(rav_ctx* ctx, const rav_problem_desc* d) {
     const rav_inclusion& c = d->incl[i];
     inc[4 * i + 0] = c.cx; inc[4 * i + 1] = c.cy; inc[4 * i + 2] = c.cz; inc[4 * i + 3] = c.r;
   }
-  CK(hipMalloc((void**)&ctx->d_incl, sizeof(double) * inc.size()));
+  CK(rav_dmalloc((void**)&ctx->d_incl, sizeof(double) * inc.size()));
   CK(hipMemcpy(ctx->d_incl, inc.data(), sizeof(double) * inc.size(), hipMemcpyHostToDevice));
   return RAV_OK;
 }
@@ -172,7 +201,7 @@ rav_status rav_init_common(rav_ctx* ctx, const rav_problem_desc* d) {
 rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<BlockTask>& logical, BlockTask** out, int* n) {
   std::vector<BlockTask> t = xcd_order(logical);
   *n = (int)t.size();
-  CK(hipMalloc((void**)out, sizeof(BlockTask) * std::max<size_t>(t.size(), 1)));
+  CK(rav_dmalloc((void**)out, sizeof(BlockTask) * std::max<size_t>(t.size(), 1)));
   CK(hipMemcpy(*out, t.data(), sizeof(BlockTask) * t.size(), hipMemcpyHostToDevice));
   return RAV_OK;
 }
@@ -215,14 +244,14 @@ static rav_status build_level(rav_ctx* ctx, int l) {
     off += h.seg_rows[s] * seg_slots(D.dim, s);
   }
   L.nvals = off;
-  CK(hipMalloc((void**)&h.x, sizeof(double) * g.n));
-  CK(hipMalloc((void**)&h.b, sizeof(double) * g.n));
-  CK(hipMalloc((void**)&h.r, sizeof(double) * g.n));
-  CK(hipMalloc((void**)&h.vals, sizeof(double) * off));
+  CK(rav_dmalloc((void**)&h.x, sizeof(double) * g.n));
+  CK(rav_dmalloc((void**)&h.b, sizeof(double) * g.n));
+  CK(rav_dmalloc((void**)&h.r, sizeof(double) * g.n));
+  CK(rav_dmalloc((void**)&h.vals, sizeof(double) * off));
   CK(hipMemsetAsync(h.x, 0, sizeof(double) * g.n, ctx->stream));
   CK(hipMemsetAsync(h.b, 0, sizeof(double) * g.n, ctx->stream));
   CK(hipMemsetAsync(h.r, 0, sizeof(double) * g.n, ctx->stream));
-  CK(hipMalloc((void**)&L.dd, sizeof(GridDev)));
+  CK(rav_dmalloc((void**)&L.dd, sizeof(GridDev)));
   L.npatch = n_patches(g, D.patch);
   std::vector<BlockTask> tiles;
   append_residual_tiles(tiles, 0, g);
@@ -240,7 +269,7 @@ static rav_status build_level(rav_ctx* ctx, int l) {
     if (st != RAV_OK) return st;
   }
   const int n_part = std::max(L.n_res_tiles, residual_tiled_ok(D.dim, N) ? residual_tiles(D.dim, N) : 1);
-  CK(hipMalloc((void**)&L.partials, sizeof(double) * n_part));
+  CK(rav_dmalloc((void**)&L.partials, sizeof(double) * n_part));
   // patch buckets (smoothed levels only)
   if (l > 0) {
     const int nbk = n_buckets(D.dim, D.patch);
@@ -270,8 +299,8 @@ static rav_status build_level(rav_ctx* ctx, int l) {
   const long long ncell = (long long)N * N * (D.dim == 3 ? N : 1);
   double* etaq = nullptr;
   unsigned char* uni = nullptr;
-  CK(hipMalloc((void**)&etaq, sizeof(double) * ncell * (D.dim == 2 ? 9 : 27)));
-  CK(hipMalloc((void**)&uni, ncell));
+  CK(rav_dmalloc((void**)&etaq, sizeof(double) * ncell * (D.dim == 2 ? 9 : 27)));
+  CK(rav_dmalloc((void**)&uni, ncell));
   std::vector<BlockTask> at;
   for (int s = 0; s < nseg; ++s)
     for (long long r0 = 0; r0 < h.seg_rows[s]; r0 += BLOCK) {
@@ -298,10 +327,10 @@ static rav_status build_level(rav_ctx* ctx, int l) {
   L.ncut = (long long)cut_cells.size();
   const long long nv2 = D.dim == 2 ? 81 : 729;
   int *d_cut_idx = nullptr, *d_cut_cells = nullptr;
-  CK(hipMalloc((void**)&L.ceta, sizeof(double) * ncell));
-  CK(hipMalloc((void**)&L.cutA, sizeof(double) * std::max<long long>(L.ncut * nv2, 1)));
-  CK(hipMalloc((void**)&d_cut_idx, sizeof(int) * ncell));
-  CK(hipMalloc((void**)&d_cut_cells, sizeof(int) * std::max<long long>(L.ncut, 1)));
+  CK(rav_dmalloc((void**)&L.ceta, sizeof(double) * ncell));
+  CK(rav_dmalloc((void**)&L.cutA, sizeof(double) * std::max<long long>(L.ncut * nv2, 1)));
+  CK(rav_dmalloc((void**)&d_cut_idx, sizeof(int) * ncell));
+  CK(rav_dmalloc((void**)&d_cut_cells, sizeof(int) * std::max<long long>(L.ncut, 1)));
   CK(hipMemcpy(d_cut_idx, cut_idx.data(), sizeof(int) * ncell, hipMemcpyHostToDevice));
   if (L.ncut) CK(hipMemcpy(d_cut_cells, cut_cells.data(), sizeof(int) * L.ncut, hipMemcpyHostToDevice));
   launch_cell_coef(D.dim, ncell, L.dd, etaq, d_cut_idx, d_cut_cells, (int)L.ncut, R, ctx->d_incl, D.n_incl,
@@ -309,11 +338,11 @@ static rav_status build_level(rav_ctx* ctx, int l) {
   launch_assemble(D.dim, L.dd, atd, natd, etaq, uni, d_cut_idx, L.cutA, ctx->stream);
   CK(hipGetLastError());
   CK(hipStreamSynchronize(ctx->stream));
-  CK(hipFree(d_cut_idx));
-  CK(hipFree(d_cut_cells));
-  CK(hipFree(etaq));
-  CK(hipFree(uni));
-  CK(hipFree(atd));
+  CK(rav_dfree(d_cut_idx));
+  CK(rav_dfree(d_cut_cells));
+  CK(rav_dfree(etaq));
+  CK(rav_dfree(uni));
+  CK(rav_dfree(atd));
   h.ceta = L.ceta;
   h.cutA = L.cutA;
   return rav_upload_desc(ctx, L);
@@ -331,7 +360,7 @@ static rav_status build_coarse_matrix(rav_ctx* ctx) {
   if (nb > MAX_COARSE)
     return set_err(ctx, RAV_EINVAL, "the coarsest grid has " + std::to_string(nb) + " unknowns; its dense direct "
                    "solve is limited to " + std::to_string(MAX_COARSE) + " (use more levels)");
-  CK(hipMalloc((void**)&ctx->Minv, sizeof(double) * nb * nb));
+  CK(rav_dmalloc((void**)&ctx->Minv, sizeof(double) * nb * nb));
   launch_coarse_build(L.dd, g.dim, ctx->Minv, nb, ctx->bordered, 1, ctx->stream);
   CK(hipGetLastError());
   return RAV_OK;
@@ -369,10 +398,10 @@ rav_status rav_invert_coarse(rav_ctx* const* ctxs, int n, hipStream_t s, std::ve
   std::vector<double*> hM(n);
   for (int i = 0; i < n; ++i) hM[i] = ctxs[i]->Minv;
   std::vector<int> big(n, INT_MAX);
-  if (chk(hipMalloc((void**)&dM, sizeof(double*) * n)) && chk(hipMalloc((void**)&piv, sizeof(int) * n * nb)) &&
-      chk(hipMalloc((void**)&perm, sizeof(int) * n * nb)) && chk(hipMalloc((void**)&st, sizeof(int) * n)) &&
-      chk(hipMalloc((void**)&colk, sizeof(double) * n * nb)) &&
-      chk(hipMalloc((void**)&Rs, sizeof(double) * n * GJ_PANEL * nb)) &&
+  if (chk(rav_dmalloc((void**)&dM, sizeof(double*) * n)) && chk(rav_dmalloc((void**)&piv, sizeof(int) * n * nb)) &&
+      chk(rav_dmalloc((void**)&perm, sizeof(int) * n * nb)) && chk(rav_dmalloc((void**)&st, sizeof(int) * n)) &&
+      chk(rav_dmalloc((void**)&colk, sizeof(double) * n * nb)) &&
+      chk(rav_dmalloc((void**)&Rs, sizeof(double) * n * GJ_PANEL * nb)) &&
       chk(hipMemcpy(dM, hM.data(), sizeof(double*) * n, hipMemcpyHostToDevice)) &&
       chk(hipMemcpy(st, big.data(), sizeof(int) * n, hipMemcpyHostToDevice))) {
     launch_bgj_invert(dM, nb, n, piv, colk, Rs, perm, st, s);
@@ -381,8 +410,8 @@ rav_status rav_invert_coarse(rav_ctx* const* ctxs, int n, hipStream_t s, std::ve
       chk(hipMemcpy(status_out->data(), st, sizeof(int) * n, hipMemcpyDeviceToHost));
     }
   }
-  (void)hipFree(dM); (void)hipFree(piv); (void)hipFree(perm); (void)hipFree(st); (void)hipFree(colk);
-  (void)hipFree(Rs);
+  (void)rav_dfree(dM); (void)rav_dfree(piv); (void)rav_dfree(perm); (void)rav_dfree(st); (void)rav_dfree(colk);
+  (void)rav_dfree(Rs);
   return result;
 }
 
@@ -780,7 +809,7 @@ static rav_status merge_apply(rav_ctx* ctx) {
       const int cls = L.hd.bk[al.bucket].cls;
       if (ctx->desc.dim == 3 && al.split != APPLY_ROWS && (cls == 3 || cls >= 5)) L.multi_edges = true;
     }
-    (void)hipFree(L.multi_tasks);
+    (void)rav_dfree(L.multi_tasks);
     L.multi_tasks = nullptr;
     L.n_multi = 0;
     const rav_status st = rav_upload_tasks(ctx, mt, &L.multi_tasks, &L.n_multi);
@@ -833,20 +862,20 @@ static rav_status autotune_apply(rav_ctx* ctx) {
         if (log) std::fprintf(stderr, "rav autotune: level %zu bucket %d (%lld patches) split %d: %.1f us\n", l,
                               al.bucket, cnt, split, 1e3f * ms / 3.0f);
         if (!have || ms < best_ms) {
-          if (have && best.tasks != al.tasks) (void)hipFree(best.tasks);
+          if (have && best.tasks != al.tasks) (void)rav_dfree(best.tasks);
           best = cand;
           best_ms = ms;
           have = true;
         } else if (cand.tasks != al.tasks) {
-          (void)hipFree(cand.tasks);
+          (void)rav_dfree(cand.tasks);
         }
       }
       if (result != RAV_OK) {
-        if (have && best.tasks != al.tasks) (void)hipFree(best.tasks);
+        if (have && best.tasks != al.tasks) (void)rav_dfree(best.tasks);
         break;
       }
       if (best.tasks != al.tasks) {
-        (void)hipFree(al.tasks);
+        (void)rav_dfree(al.tasks);
         al = best;
       }
     }
@@ -872,8 +901,8 @@ rav_status rav_factor_patches(rav_ctx* ctx) {
     GridDev& h = L.hd;
     if (full) {
       if (!h.Winv) {
-        CK(hipMalloc((void**)&h.Winv, sizeof(double) * L.npatch * npad * npad));
-        if (D.smoother == RAV_SMOOTHER_AV) CK(hipMalloc((void**)&h.Y, sizeof(double) * L.npatch * npad));
+        CK(rav_dmalloc((void**)&h.Winv, sizeof(double) * L.npatch * npad * npad));
+        if (D.smoother == RAV_SMOOTHER_AV) CK(rav_dmalloc((void**)&h.Y, sizeof(double) * L.npatch * npad));
       }
     } else {
       const int V = ctx->prec == P_FP64 ? 2 : ctx->prec == P_FP32 ? 4 : 8;
@@ -883,7 +912,7 @@ rav_status rav_factor_patches(rav_ctx* ctx) {
         B.nchunk = ((B.factored ? (long long)fact_nvals(D.dim) : (long long)npad * B.nown) + V - 1) / V;
         if (!B.W) {
           const size_t bytes = esz * (size_t)V * (size_t)B.nchunk * (size_t)B.count_pad;
-          CK(hipMalloc(&B.W, bytes));
+          CK(rav_dmalloc(&B.W, bytes));
           CK(hipMemsetAsync(B.W, 0, bytes, ctx->stream));
         }
       }
@@ -962,14 +991,14 @@ rav_status rav_assemble_rhs(rav_ctx* ctx, const double* params, int n_params, do
   const long long ncell = (long long)g.N * g.N * (g.dim == 3 ? g.N : 1);
   const int nq = g.dim == 2 ? 9 : 27;
   double *dp = nullptr, *fq = nullptr;
-  CK(hipMalloc((void**)&dp, sizeof(double) * n_params));
-  CK(hipMalloc((void**)&fq, sizeof(double) * ncell * nq * g.dim));
+  CK(rav_dmalloc((void**)&dp, sizeof(double) * n_params));
+  CK(rav_dmalloc((void**)&fq, sizeof(double) * ncell * nq * g.dim));
   CK(hipMemcpy(dp, params, sizeof(double) * n_params, hipMemcpyHostToDevice));
   launch_rhs(g.dim, &L.hd, L.dd, dp, fq, b_dev, ctx->stream);
   CK(hipGetLastError());
   CK(hipStreamSynchronize(ctx->stream));
-  CK(hipFree(dp));
-  CK(hipFree(fq));
+  CK(rav_dfree(dp));
+  CK(rav_dfree(fq));
   return RAV_OK;
 }
 
@@ -1332,12 +1361,12 @@ rav_status rav_export_matrix(rav_ctx* ctx, int level, double* out) {
   const long long n = L.hd.g.n;
   if (n > 20000) return set_err(ctx, RAV_EINVAL, "level too large for a dense export");
   double* M = nullptr;
-  CK(hipMalloc((void**)&M, sizeof(double) * n * n));
+  CK(rav_dmalloc((void**)&M, sizeof(double) * n * n));
   launch_coarse_build(L.dd, ctx->desc.dim, M, n, 0, 0, ctx->stream);
   CK(hipGetLastError());
   CK(hipStreamSynchronize(ctx->stream));
   CK(hipMemcpy(out, M, sizeof(double) * n * n, hipMemcpyDeviceToHost));
-  CK(hipFree(M));
+  CK(rav_dfree(M));
   return RAV_OK;
 }
 
@@ -1443,6 +1472,19 @@ rav_status rav_adaptive_level_info(const rav_ctx* ctx, int level, long* info_hos
   return rav_ad_level_info(ctx, level, info_host);
 }
 
+rav_status rav_set_device_allocator(void* (*alloc)(size_t bytes, void* user), void (*release)(void* ptr, void* user),
+                                    void* user) {
+  std::lock_guard<std::mutex> lock(g_alloc_mutex);
+  if ((alloc == nullptr) != (release == nullptr))
+    return set_err(nullptr, RAV_EINVAL, "the allocator needs both functions, or neither");
+  if (rav_live_objects.load() != 0)
+    return set_err(nullptr, RAV_EINVAL, "the device allocator can only change while no context, batch or network exists");
+  g_alloc.alloc = alloc;
+  g_alloc.release = release;
+  g_alloc.user = user;
+  return RAV_OK;
+}
+
 rav_status rav_destroy(rav_ctx* ctx) {
   if (!ctx) return RAV_OK;
   (void)hipStreamSynchronize(ctx->stream);
@@ -1452,18 +1494,18 @@ rav_status rav_destroy(rav_ctx* ctx) {
   rav_ad_free(ctx);
   for (LevelHost& L : ctx->lv) {
     GridDev& h = L.hd;
-    (void)hipFree(h.x); (void)hipFree(h.b); (void)hipFree(h.r); (void)hipFree(h.vals);
-    (void)hipFree(h.Winv); (void)hipFree(h.Y);
-    for (int i = 0; i < h.nbk; ++i) (void)hipFree(h.bk[i].W);
-    (void)hipFree(L.dd); (void)hipFree(L.res_tasks); (void)hipFree(L.partials);
-    (void)hipFree(L.rtasks); (void)hipFree(L.ptasks);
-    (void)hipFree(L.ceta); (void)hipFree(L.cutA);
-    for (ApplyLaunch& a : L.apply) (void)hipFree(a.tasks);
-    (void)hipFree(L.multi_tasks);
+    (void)rav_dfree(h.x); (void)rav_dfree(h.b); (void)rav_dfree(h.r); (void)rav_dfree(h.vals);
+    (void)rav_dfree(h.Winv); (void)rav_dfree(h.Y);
+    for (int i = 0; i < h.nbk; ++i) (void)rav_dfree(h.bk[i].W);
+    (void)rav_dfree(L.dd); (void)rav_dfree(L.res_tasks); (void)rav_dfree(L.partials);
+    (void)rav_dfree(L.rtasks); (void)rav_dfree(L.ptasks);
+    (void)rav_dfree(L.ceta); (void)rav_dfree(L.cutA);
+    for (ApplyLaunch& a : L.apply) (void)rav_dfree(a.tasks);
+    (void)rav_dfree(L.multi_tasks);
   }
-  (void)hipFree(ctx->d_incl); (void)hipFree(ctx->Minv); (void)hipFree(ctx->d_status);
-  (void)hipFree(ctx->d_norm);
-  (void)hipFree(ctx->coarse_tasks);
+  (void)rav_dfree(ctx->d_incl); (void)rav_dfree(ctx->Minv); (void)rav_dfree(ctx->d_status);
+  (void)rav_dfree(ctx->d_norm);
+  (void)rav_dfree(ctx->coarse_tasks);
   if (ctx->h_norm) (void)hipHostFree(ctx->h_norm);
   for (auto& e : ctx->gprof_res) if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->gprof_app) if (e) (void)hipEventDestroy(e);

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -74,7 +75,22 @@ void append_residual_tiles(std::vector<BlockTask>& out, int grid, const Geo& g);
 struct rav_q1_state;   // stabilized Q1-Q1 hierarchy (rav_q1.hip)
 struct rav_ad_state;   // stabilized Q1-Q1 on adaptive quadtree grids (rav_adapt.hip)
 
+// Device memory of the library's buffers: hipMalloc/hipFree, or the caller's
+// allocator set by rav_set_device_allocator.  Every context, batch and network
+// counts itself in rav_live_objects, so the allocator cannot change while a
+// buffer it made is alive.
+hipError_t rav_dmalloc(void** p, size_t bytes);
+hipError_t rav_dfree(void* p);
+extern std::atomic<long> rav_live_objects;
+struct LiveCount {
+  LiveCount() { ++rav_live_objects; }
+  ~LiveCount() { --rav_live_objects; }
+  LiveCount(const LiveCount&) = delete;
+  LiveCount& operator=(const LiveCount&) = delete;
+};
+
 struct rav_ctx {
+  LiveCount live_;
   rav_problem_desc desc{};
   rav_q1_state* q1 = nullptr;   // set for RAV_Q1Q1_STAB: the entry points route to rav_q1_*
   rav_ad_state* ad = nullptr;   // set by rav_create_adaptive: the entry points route to rav_ad_*

@@ -210,18 +210,18 @@ extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double*
   std::vector<double*> V(m + 1, nullptr), Z(m, nullptr);
   double *xk = nullptr, *bk = nullptr, *partial = nullptr, *hdev = nullptr, *hhost = nullptr;
   auto cleanup = [&]() {
-    for (double* p : V) (void)hipFree(p);
-    for (double* p : Z) (void)hipFree(p);
-    (void)hipFree(xk); (void)hipFree(bk); (void)hipFree(partial); (void)hipFree(hdev);
+    for (double* p : V) (void)rav_dfree(p);
+    for (double* p : Z) (void)rav_dfree(p);
+    (void)rav_dfree(xk); (void)rav_dfree(bk); (void)rav_dfree(partial); (void)rav_dfree(hdev);
     if (hhost) (void)hipHostFree(hhost);
   };
   auto alloc = [&]() -> rav_status {
-    for (double*& p : V) KCK(hipMalloc((void**)&p, sizeof(double) * n));
-    for (double*& p : Z) KCK(hipMalloc((void**)&p, sizeof(double) * n));
-    KCK(hipMalloc((void**)&xk, sizeof(double) * n));
-    KCK(hipMalloc((void**)&bk, sizeof(double) * n));
-    KCK(hipMalloc((void**)&partial, sizeof(double) * 1024));
-    KCK(hipMalloc((void**)&hdev, sizeof(double) * (m + 2) * (m + 1)));
+    for (double*& p : V) KCK(rav_dmalloc((void**)&p, sizeof(double) * n));
+    for (double*& p : Z) KCK(rav_dmalloc((void**)&p, sizeof(double) * n));
+    KCK(rav_dmalloc((void**)&xk, sizeof(double) * n));
+    KCK(rav_dmalloc((void**)&bk, sizeof(double) * n));
+    KCK(rav_dmalloc((void**)&partial, sizeof(double) * 1024));
+    KCK(rav_dmalloc((void**)&hdev, sizeof(double) * (m + 2) * (m + 1)));
     KCK(hipHostMalloc((void**)&hhost, sizeof(double) * (m + 2), hipHostMallocDefault));
     return RAV_OK;
   };

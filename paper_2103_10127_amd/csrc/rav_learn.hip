@@ -42,13 +42,13 @@ struct LearnState {
 void learn_free(rav_ctx* ctx) {
   LearnState* S = static_cast<LearnState*>(ctx->learn);
   if (!S) return;
-  for (double* p : S->states) (void)hipFree(p);
-  (void)hipFree(S->z); (void)hipFree(S->rbuf); (void)hipFree(S->lam); (void)hipFree(S->zero);
-  (void)hipFree(S->Y); (void)hipFree(S->gom); (void)hipFree(S->F); (void)hipFree(S->omega);
-  for (GridDev* p : S->vx) (void)hipFree(p);
-  (void)hipFree(S->vz); (void)hipFree(S->vlam); (void)hipFree(S->partial);
-  for (float* p : S->level_omega) (void)hipFree(p);
-  for (float* p : S->level_feat) (void)hipFree(p);
+  for (double* p : S->states) (void)rav_dfree(p);
+  (void)rav_dfree(S->z); (void)rav_dfree(S->rbuf); (void)rav_dfree(S->lam); (void)rav_dfree(S->zero);
+  (void)rav_dfree(S->Y); (void)rav_dfree(S->gom); (void)rav_dfree(S->F); (void)rav_dfree(S->omega);
+  for (GridDev* p : S->vx) (void)rav_dfree(p);
+  (void)rav_dfree(S->vz); (void)rav_dfree(S->vlam); (void)rav_dfree(S->partial);
+  for (float* p : S->level_omega) (void)rav_dfree(p);
+  for (float* p : S->level_feat) (void)rav_dfree(p);
   delete S;
   ctx->learn = nullptr;
 }
@@ -64,6 +64,7 @@ LearnState* state(rav_ctx* ctx) {
 }  // namespace
 
 struct rav_mlp {
+  LiveCount live_;
   float* theta = nullptr;
   double *m = nullptr, *v = nullptr, *grad = nullptr;
   int t = 0;
@@ -94,7 +95,7 @@ static rav_status level_features(rav_ctx* ctx, int l, float** F) {
   if ((int)S->level_feat.size() < (int)ctx->lv.size()) S->level_feat.resize(ctx->lv.size(), nullptr);
   LevelHost& L = ctx->lv[l];
   if (!S->level_feat[l]) {
-    LCK(hipMalloc((void**)&S->level_feat[l], sizeof(float) * 16 * L.npatch));
+    LCK(rav_dmalloc((void**)&S->level_feat[l], sizeof(float) * 16 * L.npatch));
     launch_features(L.dd, L.npatch, ctx->d_incl, ctx->desc.n_incl, ctx->desc.eta_out, ctx->desc.eta_in,
                     S->level_feat[l], ctx->stream);
     LCK(hipGetLastError());
@@ -109,10 +110,10 @@ rav_status rav_mlp_create(const float* theta_host, rav_mlp** out) {
   rav_ctx* ctx = nullptr;
   if (!theta_host || !out) return RAV_EINVAL;
   rav_mlp* M = new rav_mlp();
-  if (hipMalloc((void**)&M->theta, sizeof(float) * NPARAM) != hipSuccess ||
-      hipMalloc((void**)&M->m, sizeof(double) * NPARAM) != hipSuccess ||
-      hipMalloc((void**)&M->v, sizeof(double) * NPARAM) != hipSuccess ||
-      hipMalloc((void**)&M->grad, sizeof(double) * NPARAM) != hipSuccess) {
+  if (rav_dmalloc((void**)&M->theta, sizeof(float) * NPARAM) != hipSuccess ||
+      rav_dmalloc((void**)&M->m, sizeof(double) * NPARAM) != hipSuccess ||
+      rav_dmalloc((void**)&M->v, sizeof(double) * NPARAM) != hipSuccess ||
+      rav_dmalloc((void**)&M->grad, sizeof(double) * NPARAM) != hipSuccess) {
     rav_mlp_destroy(M);
     return RAV_ENOMEM;
   }
@@ -135,7 +136,7 @@ rav_status rav_mlp_get(const rav_mlp* M, float* theta_host, double* grad_host) {
 
 rav_status rav_mlp_destroy(rav_mlp* M) {
   if (!M) return RAV_OK;
-  (void)hipFree(M->theta); (void)hipFree(M->m); (void)hipFree(M->v); (void)hipFree(M->grad);
+  (void)rav_dfree(M->theta); (void)rav_dfree(M->m); (void)rav_dfree(M->v); (void)rav_dfree(M->grad);
   delete M;
   return RAV_OK;
 }
@@ -161,7 +162,7 @@ rav_status rav_learn_set_omega(rav_ctx* ctx, const rav_mlp* M) {
     if (!M) {
       L.hd.omega_patch = nullptr;
     } else {
-      if (!S->level_omega[l]) LCK(hipMalloc((void**)&S->level_omega[l], sizeof(float) * L.npatch));
+      if (!S->level_omega[l]) LCK(rav_dmalloc((void**)&S->level_omega[l], sizeof(float) * L.npatch));
       if ((st = rav_learn_patch_omega(ctx, M, l, S->level_omega[l])) != RAV_OK) return st;
       L.hd.omega_patch = S->level_omega[l];
     }
@@ -174,27 +175,27 @@ static rav_status ensure_twogrid(rav_ctx* ctx, int nu) {
   LearnState* S = state(ctx);
   LevelHost& Lf = ctx->lv[1];
   if (S->nu == nu && !S->states.empty()) return RAV_OK;
-  for (double* p : S->states) (void)hipFree(p);
-  for (GridDev* p : S->vx) (void)hipFree(p);
+  for (double* p : S->states) (void)rav_dfree(p);
+  for (GridDev* p : S->vx) (void)rav_dfree(p);
   S->states.assign(2 * nu + 2, nullptr);
   S->vx.assign(2 * nu + 2, nullptr);
   S->nu = nu;
   S->n = Lf.hd.g.n;
   S->npatch = Lf.npatch;
   const long long n = S->n;
-  for (double*& p : S->states) LCK(hipMalloc((void**)&p, sizeof(double) * n));
+  for (double*& p : S->states) LCK(rav_dmalloc((void**)&p, sizeof(double) * n));
   if (!S->z) {
-    LCK(hipMalloc((void**)&S->z, sizeof(double) * n));
-    LCK(hipMalloc((void**)&S->rbuf, sizeof(double) * n));
-    LCK(hipMalloc((void**)&S->lam, sizeof(double) * n));
-    LCK(hipMalloc((void**)&S->zero, sizeof(double) * n));
+    LCK(rav_dmalloc((void**)&S->z, sizeof(double) * n));
+    LCK(rav_dmalloc((void**)&S->rbuf, sizeof(double) * n));
+    LCK(rav_dmalloc((void**)&S->lam, sizeof(double) * n));
+    LCK(rav_dmalloc((void**)&S->zero, sizeof(double) * n));
     LCK(hipMemset(S->zero, 0, sizeof(double) * n));
-    LCK(hipMalloc((void**)&S->Y, sizeof(double) * S->npatch * 51));
-    LCK(hipMalloc((void**)&S->gom, sizeof(double) * S->npatch));
-    LCK(hipMalloc((void**)&S->omega, sizeof(float) * S->npatch));
-    LCK(hipMalloc((void**)&S->partial, sizeof(double) * NPARAM * mlp_backward_blocks(S->npatch)));
-    LCK(hipMalloc((void**)&S->vz, sizeof(GridDev)));
-    LCK(hipMalloc((void**)&S->vlam, sizeof(GridDev)));
+    LCK(rav_dmalloc((void**)&S->Y, sizeof(double) * S->npatch * 51));
+    LCK(rav_dmalloc((void**)&S->gom, sizeof(double) * S->npatch));
+    LCK(rav_dmalloc((void**)&S->omega, sizeof(float) * S->npatch));
+    LCK(rav_dmalloc((void**)&S->partial, sizeof(double) * NPARAM * mlp_backward_blocks(S->npatch)));
+    LCK(rav_dmalloc((void**)&S->vz, sizeof(GridDev)));
+    LCK(rav_dmalloc((void**)&S->vlam, sizeof(GridDev)));
   }
   GridDev v = Lf.hd;
   v.b = S->zero;
@@ -202,7 +203,7 @@ static rav_status ensure_twogrid(rav_ctx* ctx, int nu) {
   v.omega_patch = S->omega;
   for (int s = 0; s < 2 * nu + 2; ++s) {
     v.x = S->states[s];
-    LCK(hipMalloc((void**)&S->vx[s], sizeof(GridDev)));
+    LCK(rav_dmalloc((void**)&S->vx[s], sizeof(GridDev)));
     LCK(hipMemcpy(S->vx[s], &v, sizeof(GridDev), hipMemcpyHostToDevice));
   }
   v.x = S->z;

@@ -109,9 +109,9 @@ rav_status build_cells(rav_ctx* ctx, Level& L, int R) {
   const long long ncell = ipowll(L.q.N, D.dim);
   double* eta0 = nullptr;
   unsigned char* uni = nullptr;
-  QCK(hipMalloc((void**)&eta0, sizeof(double) * ncell));
-  QCK(hipMalloc((void**)&uni, ncell));
-  QCK(hipMalloc((void**)&L.ceta, sizeof(double) * ncell));
+  QCK(rav_dmalloc((void**)&eta0, sizeof(double) * ncell));
+  QCK(rav_dmalloc((void**)&uni, ncell));
+  QCK(rav_dmalloc((void**)&L.ceta, sizeof(double) * ncell));
   q1_launch_cell_eta(D.dim, L.q, R, ctx->d_incl, D.n_incl, D.eta_out, D.eta_in, eta0, uni, ctx->stream);
   QCK(hipGetLastError());
   std::vector<double> he(ncell);
@@ -119,8 +119,8 @@ rav_status build_cells(rav_ctx* ctx, Level& L, int R) {
   QCK(hipMemcpyAsync(he.data(), eta0, sizeof(double) * ncell, hipMemcpyDeviceToHost, ctx->stream));
   QCK(hipMemcpyAsync(hu.data(), uni, ncell, hipMemcpyDeviceToHost, ctx->stream));
   QCK(hipStreamSynchronize(ctx->stream));
-  (void)hipFree(eta0);
-  (void)hipFree(uni);
+  (void)rav_dfree(eta0);
+  (void)rav_dfree(uni);
   const double ascale = std::pow(L.q.h, D.dim - 2);
   std::vector<int> cut;
   for (long long c = 0; c < ncell; ++c) {
@@ -137,14 +137,14 @@ rav_status build_cells(rav_ctx* ctx, Level& L, int R) {
   if (!cut.empty()) {
     const int nb = 1 << D.dim;
     int* dcells = nullptr;
-    QCK(hipMalloc((void**)&dcells, sizeof(int) * cut.size()));
+    QCK(rav_dmalloc((void**)&dcells, sizeof(int) * cut.size()));
     QCK(hipMemcpy(dcells, cut.data(), sizeof(int) * cut.size(), hipMemcpyHostToDevice));
-    QCK(hipMalloc((void**)&L.cutK, sizeof(double) * cut.size() * nb * nb));
+    QCK(rav_dmalloc((void**)&L.cutK, sizeof(double) * cut.size() * nb * nb));
     q1_launch_cut_matrices(D.dim, L.q, R, dcells, (int)cut.size(), ctx->d_incl, D.n_incl, D.eta_out, D.eta_in,
                            L.cutK, ctx->stream);
     QCK(hipGetLastError());
     QCK(hipStreamSynchronize(ctx->stream));
-    (void)hipFree(dcells);
+    (void)rav_dfree(dcells);
   }
   L.q.cutK = L.cutK;
   return RAV_OK;
@@ -156,19 +156,19 @@ rav_status build_coarse(rav_ctx* ctx) {
   S->bordered = all_dirichlet(ctx->desc) ? 1 : 0;
   S->nb = L0.q.n + S->bordered;
   const long long nb = S->nb;
-  QCK(hipMalloc((void**)&S->Minv, sizeof(double) * nb * nb));
+  QCK(rav_dmalloc((void**)&S->Minv, sizeof(double) * nb * nb));
   q1_launch_dense(ctx->desc.dim, L0.q, S->Minv, nb, S->bordered, ctx->stream);
   QCK(hipGetLastError());
   double** dM = nullptr;
   int *piv = nullptr, *perm = nullptr, *pst = nullptr;
   double *colk = nullptr, *Rs = nullptr;
   const int big = INT_MAX;
-  QCK(hipMalloc((void**)&dM, sizeof(double*)));
-  QCK(hipMalloc((void**)&piv, sizeof(int) * nb));
-  QCK(hipMalloc((void**)&perm, sizeof(int) * nb));
-  QCK(hipMalloc((void**)&pst, sizeof(int)));
-  QCK(hipMalloc((void**)&colk, sizeof(double) * nb));
-  QCK(hipMalloc((void**)&Rs, sizeof(double) * GJ_PANEL * nb));
+  QCK(rav_dmalloc((void**)&dM, sizeof(double*)));
+  QCK(rav_dmalloc((void**)&piv, sizeof(int) * nb));
+  QCK(rav_dmalloc((void**)&perm, sizeof(int) * nb));
+  QCK(rav_dmalloc((void**)&pst, sizeof(int)));
+  QCK(rav_dmalloc((void**)&colk, sizeof(double) * nb));
+  QCK(rav_dmalloc((void**)&Rs, sizeof(double) * GJ_PANEL * nb));
   QCK(hipMemcpy(dM, &S->Minv, sizeof(double*), hipMemcpyHostToDevice));
   QCK(hipMemcpy(pst, &big, sizeof(int), hipMemcpyHostToDevice));
   launch_bgj_invert(dM, nb, 1, piv, colk, Rs, perm, pst, ctx->stream);
@@ -176,8 +176,8 @@ rav_status build_coarse(rav_ctx* ctx) {
   int status = 0;
   QCK(hipMemcpyAsync(&status, pst, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   QCK(hipStreamSynchronize(ctx->stream));
-  (void)hipFree(dM); (void)hipFree(piv); (void)hipFree(perm); (void)hipFree(pst); (void)hipFree(colk);
-  (void)hipFree(Rs);
+  (void)rav_dfree(dM); (void)rav_dfree(piv); (void)rav_dfree(perm); (void)rav_dfree(pst); (void)rav_dfree(colk);
+  (void)rav_dfree(Rs);
   if (status != INT_MAX)
     return rav_set_error(ctx, RAV_ESINGULAR, "zero pivot in the coarse matrix at column " + std::to_string(status));
   return RAV_OK;
@@ -301,11 +301,11 @@ rav_status rav_q1_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** 
     Level& L = S->lv[l];
     L.q = make_q1(*d, l);
     const long long n = L.q.n;
-    hipError_t e = hipMalloc((void**)&L.x, sizeof(double) * n);
-    if (e == hipSuccess) e = hipMalloc((void**)&L.b, sizeof(double) * n);
-    if (e == hipSuccess) e = hipMalloc((void**)&L.r, sizeof(double) * n);
+    hipError_t e = rav_dmalloc((void**)&L.x, sizeof(double) * n);
+    if (e == hipSuccess) e = rav_dmalloc((void**)&L.b, sizeof(double) * n);
+    if (e == hipSuccess) e = rav_dmalloc((void**)&L.r, sizeof(double) * n);
     L.nres = q1_residual_blocks(L.q);
-    if (e == hipSuccess) e = hipMalloc((void**)&L.partials, sizeof(double) * L.nres);
+    if (e == hipSuccess) e = rav_dmalloc((void**)&L.partials, sizeof(double) * L.nres);
     if (e == hipSuccess) e = hipMemsetAsync(L.x, 0, sizeof(double) * n, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(L.b, 0, sizeof(double) * n, ctx->stream);
     if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
@@ -321,10 +321,10 @@ void rav_q1_free(rav_ctx* ctx) {
   rav_q1_state* S = ctx->q1;
   if (!S) return;
   for (Level& L : S->lv) {
-    (void)hipFree(L.x); (void)hipFree(L.b); (void)hipFree(L.r); (void)hipFree(L.ceta); (void)hipFree(L.cutK);
-    (void)hipFree(L.W); (void)hipFree(L.Y); (void)hipFree(L.partials);
+    (void)rav_dfree(L.x); (void)rav_dfree(L.b); (void)rav_dfree(L.r); (void)rav_dfree(L.ceta); (void)rav_dfree(L.cutK);
+    (void)rav_dfree(L.W); (void)rav_dfree(L.Y); (void)rav_dfree(L.partials);
   }
-  (void)hipFree(S->Minv);
+  (void)rav_dfree(S->Minv);
   delete S;
   ctx->q1 = nullptr;
 }
@@ -336,8 +336,8 @@ rav_status rav_q1_factor(rav_ctx* ctx) {
   const int big = INT_MAX;
   for (size_t l = 1; l < S->lv.size(); ++l) {
     Level& L = S->lv[l];
-    if (!L.W) QCK(hipMalloc((void**)&L.W, sizeof(double) * nvals * L.q.nV));
-    if (S->mode == Q1_FULL && !L.Y) QCK(hipMalloc((void**)&L.Y, sizeof(double) * q1_npad(dim) * L.q.nV));
+    if (!L.W) QCK(rav_dmalloc((void**)&L.W, sizeof(double) * nvals * L.q.nV));
+    if (S->mode == Q1_FULL && !L.Y) QCK(rav_dmalloc((void**)&L.Y, sizeof(double) * q1_npad(dim) * L.q.nV));
     QCK(hipMemcpy(ctx->d_status, &big, sizeof(int), hipMemcpyHostToDevice));
     q1_launch_factor(dim, L.q, S->mode, L.W, ctx->d_status, ctx->stream);
     QCK(hipGetLastError());
@@ -383,12 +383,12 @@ rav_status rav_q1_assemble_rhs(rav_ctx* ctx, const double* params, int n_params,
     return rav_set_error(ctx, RAV_EINVAL, "mms parameter array must have " + std::to_string(need) + " entries");
   Level& L = st(ctx)->lv.back();
   double* dp = nullptr;
-  QCK(hipMalloc((void**)&dp, sizeof(double) * n_params));
+  QCK(rav_dmalloc((void**)&dp, sizeof(double) * n_params));
   QCK(hipMemcpy(dp, params, sizeof(double) * n_params, hipMemcpyHostToDevice));
   q1_launch_rhs(ctx->desc.dim, L.q, dp, b_dev, ctx->stream);
   QCK(hipGetLastError());
   QCK(hipStreamSynchronize(ctx->stream));
-  QCK(hipFree(dp));
+  QCK(rav_dfree(dp));
   return RAV_OK;
 }
 
