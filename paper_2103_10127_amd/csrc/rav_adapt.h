@@ -41,12 +41,15 @@ namespace rav {
 
 constexpr int AD_SLICE = 64;
 constexpr int AD_NFMAX = 16;   // free velocity vertices per patch
+constexpr int AD_LDS_TUPLES = 1024;   // value tables up to this size are staged in LDS by the residual
 
 struct AdDev {
   int nV;
   int nslice;
   int wide;                         // 0: packed entries; 1: column and id arrays
   int id_bits;                      // packed: bits of the tuple id
+  int ntuple;                       // distinct value tuples (rows of vtab)
+  int table_lds;                    // residual stages vtab in LDS (ntuple <= AD_LDS_TUPLES)
   long long nnz;                    // padded operator entries
   long long pnnz;                   // padded patch entries
   const unsigned char* vmask;       // velocity Dirichlet per vertex
@@ -74,7 +77,8 @@ struct AdFactors {
   double* kfull;
 };
 
-int ad_residual_blocks(int nV);
+// Partial sums the residual writes when asked for its norm (one per block).
+int ad_residual_blocks(const AdDev& a);
 void ad_launch_residual(const AdDev& a, const double* x, const double* b, double* r, double* partials,
                         hipStream_t s);
 // One block per configuration c, built from its representative patch rep[c].

@@ -11,6 +11,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <atomic>
 #include <string>
@@ -799,19 +800,24 @@ rav_status upload_level(rav_ctx* ctx, Level& L, const HostLevel& H, bool smoothe
   ACK(hipMemset(L.x, 0, sizeof(double) * n));
   ACK(hipMemset(L.b, 0, sizeof(double) * n));
   ACK(hipMemset(L.r, 0, sizeof(double) * n));
-  L.nres = ad_residual_blocks(H.nV);
-  ACK(rav_dmalloc((void**)&L.partials, sizeof(double) * L.nres));
   AdDev& a = L.dev;
   a.nV = H.nV;
   a.nslice = (int)H.soff.size() - 1;
   a.wide = H.wide ? 1 : 0;
   a.id_bits = H.id_bits;
+  a.ntuple = L.ntuple;
+  {   // RAV_AD_TABLE_LDS=0 keeps the table in global memory (the path of larger tables)
+    const char* e = std::getenv("RAV_AD_TABLE_LDS");
+    a.table_lds = (L.ntuple <= AD_LDS_TUPLES && !(e && std::string(e) == "0")) ? 1 : 0;
+  }
   a.nnz = H.nnz;
   a.vmask = L.vmask;
   a.soff = L.soff;
   a.ent = L.ent;
   a.col = L.col;
   a.vtab = L.vtab;
+  L.nres = ad_residual_blocks(a);
+  ACK(rav_dmalloc((void**)&L.partials, sizeof(double) * L.nres));
   if (smoothed) {
     ACK(upload(&L.poff, H.poff));
     ACK(upload(&L.pv, H.pv));

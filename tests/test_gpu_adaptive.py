@@ -56,7 +56,10 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def test_residual_dofs_and_owner_every_grid(grids, oracle):
+@pytest.mark.parametrize("table", ["lds", "global"])
+def test_residual_dofs_and_owner_every_grid(grids, oracle, table, monkeypatch):
+    if table == "global":
+        monkeypatch.setenv("RAV_AD_TABLE_LDS", "0")
     H = _gpu(grids)
     for l, lv in enumerate(oracle.levels):
         g = lv.grid
@@ -159,10 +162,14 @@ def test_sweeps_and_vcycles(grids, oracle, smoother):
     H.close()
 
 
+@pytest.mark.parametrize("table", ["lds", "global"])
 @pytest.mark.parametrize("smoother", ["rav", "av", "mv"])
-def test_solve_matches_oracle(grids, oracle, smoother):
+def test_solve_matches_oracle(grids, oracle, smoother, table, monkeypatch):
     """V(3,3) to 1e-8 (Sec. 4): the oracle's cycle count within 1 and the
-    same solution within 1e-8."""
+    same solution within 1e-8, with the residual's value table in LDS and in
+    global memory."""
+    if table == "global":
+        monkeypatch.setenv("RAV_AD_TABLE_LDS", "0")
     g = oracle.finest.grid
     b = g.lid_rhs()
     xo, ko, _, sto = oracle.solve(b, 1e-8, 200, SM[smoother], OMEGA[smoother], 3)
