@@ -210,10 +210,10 @@ struct GroupState {
   bool live;
 };
 
-template <bool MV, bool WIDE>
+template <bool MV, bool WIDE, bool LDS>
 __device__ __forceinline__ GroupState group_load(const AdDev& a, bool live, int i, int k,
                                                  const double* __restrict__ rb, const double* __restrict__ x,
-                                                 double* srx, double* sry) {
+                                                 double* srx, double* sry, const double2* tab) {
   GroupState g;
   g.live = live;
   g.i = live ? i : 0;
@@ -234,10 +234,11 @@ __device__ __forceinline__ GroupState group_load(const AdDev& a, bool live, int 
       for (int m = 0; m < vw; ++m) {
         int j, id;
         entry<WIDE>(a, v, e0 + 64LL * m + vt, j, id);
-        const double* tv = a.vtab + 8 * id;
+        const double2* vt = LDS ? tab + 3 * id : reinterpret_cast<const double2*>(a.vtab + 8 * id);
+        const double2 v01 = vt[0], v23 = vt[1];   // (A, BTx), (BTy, Bx)
         const double pj = x[2 * nV + j];
-        su += tv[AD_A] * x[j] + tv[AD_BTX] * pj;
-        sv += tv[AD_A] * x[nV + j] + tv[AD_BTY] * pj;
+        su += v01.x * x[j] + v01.y * pj;
+        sv += v01.x * x[nV + j] + v23.x * pj;
       }
       g.rx = rb[v] - su;
       g.ry = rb[nV + v] - sv;
@@ -256,8 +257,9 @@ __device__ __forceinline__ GroupState group_load(const AdDev& a, bool live, int 
       for (int m = 0; m < iw; ++m) {
         int j, id;
         entry<WIDE>(a, g.i, e0 + 64LL * m + t, j, id);
-        const double* tv = a.vtab + 8 * id;
-        sp += tv[AD_BX] * x[j] + tv[AD_BY] * x[nV + j] + tv[AD_C] * x[2 * nV + j];
+        const double2* vt = LDS ? tab + 3 * id : reinterpret_cast<const double2*>(a.vtab + 8 * id);
+        const double2 v23 = vt[1], v45 = vt[2];   // (BTy, Bx), (By, C)
+        sp += v23.y * x[j] + v45.x * x[nV + j] + v45.y * x[2 * nV + j];
       }
       g.rp = rb[2 * nV + g.i] - sp;
     } else {
@@ -375,17 +377,22 @@ constexpr int LDS_TUPLES = AD_LDS_TUPLES;
 constexpr int RB_LDS = 1024;   // block of the LDS variant
 constexpr int RB = 256;        // block of the plain variant
 
+// Copies the six values of every tuple (the first three double2 of its row of
+// vtab) into tab; every thread of the block calls it.
+template <int BLOCK>
+__device__ __forceinline__ void stage_table(const AdDev& a, double2* tab) {
+  for (int q = threadIdx.x; q < a.ntuple * 3; q += BLOCK)
+    tab[q] = reinterpret_cast<const double2*>(a.vtab)[(q / 3) * 4 + q % 3];
+  __syncthreads();
+}
+
 template <bool WIDE, bool LDS, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_ad_residual(AdDev a, const double* __restrict__ x,
                                                        const double* __restrict__ b, double* __restrict__ r,
                                                        double* __restrict__ partials) {
   __shared__ double2 tab[LDS ? LDS_TUPLES * 3 : 1];
   __shared__ double red[BLOCK];
-  if (LDS) {
-    for (int q = threadIdx.x; q < a.ntuple * 3; q += BLOCK)
-      tab[q] = reinterpret_cast<const double2*>(a.vtab)[(q / 3) * 4 + q % 3];
-    __syncthreads();
-  }
+  if (LDS) stage_table<BLOCK>(a, tab);
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   const double sq = i < a.nV ? residual_vertex<WIDE, LDS>(a, i, x, b, r, tab) : 0.0;
   if (!partials) return;
@@ -405,19 +412,25 @@ __global__ __launch_bounds__(256) void k_ad_rav(AdDev a, AdFactors f, const doub
   if (i < a.nV) rav_patch<WIDE>(a, f, i, r, x, omega);
 }
 
-constexpr int GPB = 64 / GRP;   // patches per 64-lane block
+// BLOCK / GRP patches per block.  AV reads no operator values (64-lane
+// blocks); MV recomputes residual rows and, when the table fits, stages it in
+// LDS with 512-thread blocks (Omega^10 finest MV sweep: 1.52 -> 1.32 ms).
+constexpr int GB = 64;
+constexpr int GB_LDS = 512;
 
-template <bool MV, bool WIDE>
-__global__ __launch_bounds__(64) void k_ad_group(AdDev a, AdFactors f, const int* __restrict__ order, int first,
-                                                 int count, const double* __restrict__ rb, double* __restrict__ x,
-                                                 double* __restrict__ yx, double* __restrict__ yy,
-                                                 double* __restrict__ yp_out, double omega) {
-  __shared__ double srx[GPB][GRP], sry[GPB][GRP];
+template <bool MV, bool WIDE, bool LDS, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_ad_group(AdDev a, AdFactors f, const int* __restrict__ order, int first,
+                                                    int count, const double* __restrict__ rb, double* __restrict__ x,
+                                                    double* __restrict__ yx, double* __restrict__ yy,
+                                                    double* __restrict__ yp_out, double omega) {
+  __shared__ double2 tab[LDS ? LDS_TUPLES * 3 : 1];
+  __shared__ double srx[BLOCK / GRP][GRP], sry[BLOCK / GRP][GRP];
+  if (LDS) stage_table<BLOCK>(a, tab);
   const int g = threadIdx.x / GRP, k = threadIdx.x % GRP;
-  const int q = blockIdx.x * GPB + g;
+  const int q = blockIdx.x * (BLOCK / GRP) + g;
   const bool live = q < count;
   const int i = live ? (order ? order[first + q] : first + q) : 0;
-  const GroupState st = group_load<MV, WIDE>(a, live, i, k, rb, x, srx[g], sry[g]);
+  const GroupState st = group_load<MV, WIDE, LDS>(a, live, i, k, rb, x, srx[g], sry[g], tab);
   __syncthreads();
   group_solve<MV>(f, st, k, a.nV, srx[g], sry[g], x, yx, yy, yp_out, omega);
 }
@@ -496,24 +509,37 @@ void ad_launch_rav(const AdDev& a, AdFactors f, const double* r, double* x, doub
 
 void ad_launch_av(const AdDev& a, AdFactors f, const int* tsoff, const int* tpos, const double* r, double* yx,
                   double* yy, double* yp, double* x, double omega, hipStream_t s) {
+  const dim3 g(nblk(a.nV, GB / GRP)), blk(GB);
   if (a.wide)
-    hipLaunchKernelGGL((k_ad_group<false, true>), dim3(nblk(a.nV, GPB)), dim3(64), 0, s, a, f, (const int*)nullptr,
-                       0, a.nV, r, (double*)nullptr, yx, yy, yp, omega);
+    hipLaunchKernelGGL((k_ad_group<false, true, false, GB>), g, blk, 0, s, a, f, (const int*)nullptr, 0, a.nV, r,
+                       (double*)nullptr, yx, yy, yp, omega);
   else
-    hipLaunchKernelGGL((k_ad_group<false, false>), dim3(nblk(a.nV, GPB)), dim3(64), 0, s, a, f, (const int*)nullptr,
-                       0, a.nV, r, (double*)nullptr, yx, yy, yp, omega);
+    hipLaunchKernelGGL((k_ad_group<false, false, false, GB>), g, blk, 0, s, a, f, (const int*)nullptr, 0, a.nV, r,
+                       (double*)nullptr, yx, yy, yp, omega);
   hipLaunchKernelGGL(k_ad_av_gather, dim3(nblk(a.nV)), dim3(256), 0, s, a, tsoff, tpos, yx, yy, yp, x, omega);
 }
 
 void ad_launch_mv(const AdDev& a, AdFactors f, const int* order, int first, int count, const double* b, double* x,
                   double omega, hipStream_t s) {
   if (count <= 0) return;
+  double* const none = nullptr;
+  if (a.table_lds) {
+    const dim3 g(nblk(count, GB_LDS / GRP)), blk(GB_LDS);
+    if (a.wide)
+      hipLaunchKernelGGL((k_ad_group<true, true, true, GB_LDS>), g, blk, 0, s, a, f, order, first, count, b, x, none,
+                         none, none, omega);
+    else
+      hipLaunchKernelGGL((k_ad_group<true, false, true, GB_LDS>), g, blk, 0, s, a, f, order, first, count, b, x,
+                         none, none, none, omega);
+    return;
+  }
+  const dim3 g(nblk(count, GB / GRP)), blk(GB);
   if (a.wide)
-    hipLaunchKernelGGL((k_ad_group<true, true>), dim3(nblk(count, GPB)), dim3(64), 0, s, a, f, order, first, count,
-                       b, x, (double*)nullptr, (double*)nullptr, (double*)nullptr, omega);
+    hipLaunchKernelGGL((k_ad_group<true, true, false, GB>), g, blk, 0, s, a, f, order, first, count, b, x, none,
+                       none, none, omega);
   else
-    hipLaunchKernelGGL((k_ad_group<true, false>), dim3(nblk(count, GPB)), dim3(64), 0, s, a, f, order, first, count,
-                       b, x, (double*)nullptr, (double*)nullptr, (double*)nullptr, omega);
+    hipLaunchKernelGGL((k_ad_group<true, false, false, GB>), g, blk, 0, s, a, f, order, first, count, b, x, none,
+                       none, none, omega);
 }
 
 void ad_launch_prolong(const AdDev& f, const AdDev& c, const int* ptr, const int* idx, const double* w,

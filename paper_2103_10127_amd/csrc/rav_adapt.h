@@ -41,7 +41,7 @@ namespace rav {
 
 constexpr int AD_SLICE = 64;
 constexpr int AD_NFMAX = 16;   // free velocity vertices per patch
-constexpr int AD_LDS_TUPLES = 1024;   // value tables up to this size are staged in LDS by the residual
+constexpr int AD_LDS_TUPLES = 1024;   // value tables up to this size are staged in LDS (residual, MV)
 
 struct AdDev {
   int nV;
@@ -49,7 +49,7 @@ struct AdDev {
   int wide;                         // 0: packed entries; 1: column and id arrays
   int id_bits;                      // packed: bits of the tuple id
   int ntuple;                       // distinct value tuples (rows of vtab)
-  int table_lds;                    // residual stages vtab in LDS (ntuple <= AD_LDS_TUPLES)
+  int table_lds;                    // residual and MV stage vtab in LDS (ntuple <= AD_LDS_TUPLES)
   long long nnz;                    // padded operator entries
   long long pnnz;                   // padded patch entries
   const unsigned char* vmask;       // velocity Dirichlet per vertex
