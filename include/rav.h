@@ -296,17 +296,28 @@ rav_status rav_profile_end(rav_ctx* ctx, float* avg_residual_ms, float* avg_appl
 /* Plain device copy of n doubles on hip_stream (bandwidth calibration). */
 rav_status rav_stream_copy(void* hip_stream, double* dst_dev, const double* src_dev, long n);
 
-/* ---- adaptively refined grids (Sec. 2, Fig. 2; Sec. 4.1, Table 1) ----------
+/* ---- adaptively refined grids (Sec. 2, Fig. 2; Sec. 4.1-4.2, Tables 1-2) ---
  * Stabilized Q1-Q1 (eq. 8, beta and the viscosity eta_out of the descriptor)
- * on a hierarchy of quadtree grids over the unit square, each grid refining
- * the previous one, with hanging nodes: a leaf corner at the midpoint of a
+ * on a hierarchy of quadtree grids over a region of the rectangle
+ * [0, lattice_x] x [0, lattice_y] (lattice units; lengths in units of the
+ * height, a leaf of s units has size s / lattice_y), each grid refining the
+ * previous one, with hanging nodes: a leaf corner at the midpoint of a
  * larger neighbour's edge carries no unknown and takes the mean of that edge's
  * endpoints, so the discrete space is the conforming Q1 space (Fig. 2).  The
  * operator of every grid is assembled anew on that grid (Sec. 4) as
  * L = T^T L_leaves T with T the constraint map.  Unknowns: [u_x; u_y; p] over
  * the regular vertices (leaf corners that are not hanging), numbered
- * lexicographically (y slowest); velocity is Dirichlet on the whole boundary
- * (the driven cavity, rav_assemble_rhs_lid; bc_dirichlet_mask must be 0xF).
+ * lexicographically (y slowest).  The region is the union of the coarsest
+ * grid's leaves: cells of the rectangle that no leaf covers are holes
+ * (obstacles).  Velocity is Dirichlet on the boundary of holes and on the
+ * sides of the rectangle whose bit is set in bc_dirichlet_mask (bit 0: x = 0,
+ * bit 1: x = lattice_x, bit 2: y = 0, bit 3: y = lattice_y; a vertex on both a
+ * Dirichlet and an open side is Dirichlet); on the other sides the velocity
+ * is free (the natural outflow condition of the weak form, Sec. 4.2).  Data
+ * enter through the lifting (rav_assemble_rhs_lid for the driven cavity,
+ * rav_assemble_rhs_dirichlet for any values).  With all four sides Dirichlet
+ * the pressure is fixed up to a constant and the coarse solve imposes zero
+ * mean; otherwise the coarse matrix is inverted as it is.
  * Vanka patch i (one per regular vertex): p_i and the free velocity at the
  * vertices of the leaves around vertex i, a hanging corner standing for the
  * vertices that constrain it (at most 16 free vertices, else
@@ -316,23 +327,33 @@ rav_status rav_stream_copy(void* hip_stream, double* dst_dev, const double* src_
  * of its own vertices), which is the sequential sweep in that order.
  *
  * leaves_host: the leaves of all grids, coarsest first, as int32 triples
- * (x0, y0, s) in lattice units (the unit square is lattice x lattice units;
- * s an even power of two, x0 and y0 multiples of s); n_leaves_host[l] leaves
- * for grid l, l < desc->n_levels.  Copied; the host arrays may be freed on
- * return.  Every grid must tile the square, be 2:1 balanced and refine the
- * previous one; the coarsest must have at most 16383 DoFs (dense direct
- * solve).  desc: discretization RAV_Q1Q1_ADAPTIVE, dim 2, n_cells ignored,
+ * (x0, y0, s) in lattice units (s a power of two >= 2, x0 and y0 multiples
+ * of s, the cell inside the rectangle); n_leaves_host[l] leaves for grid l,
+ * l < desc->n_levels.  Copied; the host arrays may be freed on return.  The
+ * leaves of a grid must not overlap, every grid must cover the coarsest
+ * grid's region, be 2:1 balanced and refine the previous one; the coarsest
+ * must have at most 16383 DoFs (dense direct solve).  lattice_x, lattice_y in
+ * [2, 2^24].  desc: discretization RAV_Q1Q1_ADAPTIVE, dim 2, n_cells ignored,
  * no inclusions, vertex patches, FP64, coarse_galerkin 0; inv_format is
  * ignored (the owned rows are kept factored: row i of K_i^{-1}, K_i^{-1} b_c
  * and the inverse Schur complement).  RAV_EINVAL with a message (before any
  * device work) for grids that break these rules.  The context then serves
  * rav_factor_patches, rav_dofs, rav_n_levels, rav_n_patches,
- * rav_assemble_rhs_lid, rav_residual, rav_smooth, rav_restrict,
+ * rav_assemble_rhs_lid, rav_assemble_rhs_dirichlet, rav_residual, rav_smooth, rav_restrict,
  * rav_prolong_add, rav_coarse_solve, rav_vcycle, rav_solve, rav_set_params,
  * rav_get_patch_map, rav_get_owner, rav_get_patch_inverse, rav_time_sweep and
  * rav_destroy; the others return RAV_EUNSUPPORTED. */
 rav_status rav_create_adaptive(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
-                               long lattice, void* hip_stream, rav_ctx** out);
+                               long lattice_x, long lattice_y, void* hip_stream, rav_ctx** out);
+/* Right-hand side of Dirichlet data on the finest grid of an adaptive
+ * context (Sec. 4.2: the parabolic inflow, eq. 14): b_dev = -L_all[:, masked]
+ * u_D with L_all the operator before any velocity is masked, masked rows
+ * zero, so the solution x holds the free unknowns and u = x + u_D.  ud_host:
+ * 2 n host doubles, u_x then u_y of every regular vertex in the library's
+ * order (rav_adaptive_host_export what = 4 gives the vertices); only the
+ * values at Dirichlet vertices are read.  b_dev: 3 n device doubles.
+ * Synchronises.  RAV_EUNSUPPORTED for contexts of uniform grids. */
+rav_status rav_assemble_rhs_dirichlet(rav_ctx* ctx, const double* ud_host, double* b_dev);
 /* Sizes of grid `level` into info_host[9]: regular vertices, stored operator
  * entries (vertex pairs, padded to 64-vertex slices), stored patch entries
  * (padded likewise), MV colours (0 on the coarsest grid), operator entries
@@ -350,12 +371,17 @@ rav_status rav_adaptive_level_info(const rav_ctx* ctx, int level, long* info_hos
  * what = 1: the prolongation from grid level-1 (*rows = n_total(level),
  *           *cols = n_total(level-1); masked velocity rows/columns zero);
  * what = 2: the lid lifting for lid velocity 1 on this grid (*rows = n_total,
- *           *cols = 1; rav_assemble_rhs_lid scales the finest one);
- * what = 3: the MV colour of every patch (*rows = n_patches, *cols = 1).
+ *           *cols = 1; rav_assemble_rhs_lid scales the finest one; needs a
+ *           Dirichlet top side);
+ * what = 3: the MV colour of every patch (*rows = n_patches, *cols = 1);
+ * what = 4: the regular vertices in the library's order (*rows = vertices,
+ *           *cols = 3: x and y in lattice units, 1 if the velocity there is
+ *           Dirichlet else 0).
  * out_host NULL only reports the shape.  Same validation and errors as
  * rav_create_adaptive. */
 rav_status rav_adaptive_host_export(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
-                                    long lattice, int level, int what, double* out_host, long* rows, long* cols);
+                                    long lattice_x, long lattice_y, int level, int what, double* out_host, long* rows,
+                                    long* cols);
 
 /* Device memory of every buffer the library allocates (hierarchies, patch
  * inverses, work vectors of rav_solve_gmres, batches, networks): by default

@@ -2,8 +2,11 @@
 nodes, and its multigrid hierarchy (Sec. 2, eqs. 5-8 and Fig. 2; Sec. 3,
 eq. 13; Sec. 4.1).  Test infrastructure: plain, slow, fp64 (scipy.sparse).
 
-Grid: leaf cells (x0, y0, s) in integer lattice units, M units per side of the
-unit square (rav_inputs.cavity_grids).  Vertices are leaf corners; a corner that is the
+Grid: leaf cells (x0, y0, s) in integer lattice units inside the rectangle
+[0, M] x [0, My] (My = M: the unit square of the driven cavity,
+rav_inputs.cavity_grids; the channel of the cylinder benchmark,
+rav_inputs.channel_grids), lengths in units of the height My.  The domain is
+the union of the leaves: cells of the rectangle that no leaf covers are holes.  Vertices are leaf corners; a corner that is the
 midpoint of an edge of a larger neighbouring leaf is a hanging node: its value
 is the mean of that edge's two endpoints (recursively, if an endpoint hangs
 itself), so the discrete space is the conforming Q1 space on the grid.  The
@@ -14,9 +17,13 @@ Operator: the element matrices of oracle.q1q1 (2-point Gauss; A with viscosity
 eta, B = -(div v, q), stabilization C = -beta diam_e^2 (grad q, grad p)_e with
 each leaf's own diameter) assembled over the leaves with their corners, then
 restricted to the conforming space: L = T^T L_corners T with T the constraint
-map from regular unknowns to all corner values.  Velocity on the boundary is
-Dirichlet (the driven cavity: no-slip walls, lid data through the lifting
-b = -L_all[free, masked] u_D).
+map from regular unknowns to all corner values.  Velocity is Dirichlet on the
+boundary of holes and on the sides of the rectangle set in dmask (bit 0:
+x = 0, 1: x = M, 2: y = 0, 3: y = My), free on the other sides (the natural
+outflow condition, Sec. 4.2); data enter through the lifting
+b = -L_all[free, masked] u_D (the driven cavity's lid, Sec. 4.1; the
+channel's parabolic inflow, eq. 14).  With every side Dirichlet the pressure
+is fixed only up to a constant (the coarse solve then imposes zero mean).
 
 Vanka patches (Sec. 3): the patch of regular vertex i holds p_i and every free
 velocity unknown of the leaves around vertex i (the structural nonzeros of row
@@ -42,14 +49,16 @@ from .q1q1 import RefQ1
 
 
 class AdaptiveGrid:
-    def __init__(self, leaves, M: int, beta: float, eta: float = 1.0):
+    def __init__(self, leaves, M: int, beta: float, eta: float = 1.0, My: int | None = None, dmask: int = 0xF):
         self.leaves = np.asarray(leaves, dtype=np.int64)
         self.M = M
+        self.My = My = M if My is None else My
+        self.dmask = dmask
         self.dim = 2
         x0, y0, s = self.leaves[:, 0], self.leaves[:, 1], self.leaves[:, 2]
         h = s // 2
         corners = np.stack([np.stack([x0 + a * s, y0 + b * s], 1) for b in (0, 1) for a in (0, 1)], 1)   # (n,4,2), local a = ax + 2 ay
-        key = lambda p: p[..., 0] * (M + 1) + p[..., 1]
+        key = lambda p: p[..., 0] * (My + 1) + p[..., 1]
         ckey = key(corners)
         mids = np.stack([[x0 + h, y0], [x0 + h, y0 + s], [x0, y0 + h], [x0 + s, y0 + h]], 0).transpose(2, 0, 1)   # (n,4,2)
         ends = [((x0, y0), (x0 + s, y0)), ((x0, y0 + s), (x0 + s, y0 + s)), ((x0, y0), (x0, y0 + s)),
@@ -63,9 +72,9 @@ class AdaptiveGrid:
             hit = np.isin(mkey[:, e], hang)
             for li in np.nonzero(hit)[0]:
                 (ax, ay), (bx, by) = ends[e]
-                self.hang_ends[int(mkey[li, e])] = (int(ax[li] * (M + 1) + ay[li]), int(bx[li] * (M + 1) + by[li]))
+                self.hang_ends[int(mkey[li, e])] = (int(ax[li] * (My + 1) + ay[li]), int(bx[li] * (My + 1) + by[li]))
         reg = np.setdiff1d(allc, hang, assume_unique=True)
-        rx, ry = reg // (M + 1), reg % (M + 1)
+        rx, ry = reg // (My + 1), reg % (My + 1)
         order = np.lexsort((rx, ry))            # y slowest, x fastest
         self.reg_keys = reg[order]
         self.rx, self.ry = rx[order], ry[order]
@@ -74,14 +83,44 @@ class AdaptiveGrid:
         self.reg_index = {int(k): i for i, k in enumerate(self.reg_keys)}
         self.corner_keys = ckey
         self.beta, self.eta = beta, eta
-        self.h_leaf = s / M
-        # Dirichlet: velocity at boundary vertices
-        on_b = (self.rx == 0) | (self.ry == 0) | (self.rx == M) | (self.ry == M)
+        self.h_leaf = s / My
+        on_b = self._dirichlet(ckey)
         self.dirichlet_node = on_b
         self.free = np.ones(self.n, dtype=bool)
         self.free[: self.nV] = ~on_b
         self.free[self.nV: 2 * self.nV] = ~on_b
-        self.all_dirichlet = True
+        self.all_dirichlet = dmask == 0xF
+
+    def _dirichlet(self, ckey):
+        """Dirichlet flag per regular vertex.  The leaves that have vertex v as
+        a corner fill some of the four quadrants around v; v is on the boundary
+        when a quadrant is empty, and Dirichlet when an empty quadrant lies in
+        the rectangle (a hole) or beyond a side whose dmask bit is set."""
+        filled = np.zeros((self.nV, 2, 2), dtype=bool)   # [v, quadrant on +x side, quadrant on +y side]
+        for li in range(len(self.leaves)):
+            for a in range(4):
+                v = self.reg_index.get(int(ckey[li, a]))
+                if v is not None:
+                    filled[v, 1 - (a & 1), 1 - (a >> 1)] = True
+        out = np.zeros(self.nV, dtype=bool)
+        for v in range(self.nV):
+            x, y = int(self.rx[v]), int(self.ry[v])
+            for qx in (0, 1):
+                for qy in (0, 1):
+                    if filled[v, qx, qy]:
+                        continue
+                    beyond = []
+                    if qx == 0 and x == 0:
+                        beyond.append(0)
+                    if qx == 1 and x == self.M:
+                        beyond.append(1)
+                    if qy == 0 and y == 0:
+                        beyond.append(2)
+                    if qy == 1 and y == self.My:
+                        beyond.append(3)
+                    if not beyond or any((self.dmask >> side) & 1 for side in beyond):
+                        out[v] = True
+        return out
 
     def pressure_slice(self):
         return slice(2 * self.nV, self.n)
@@ -145,9 +184,20 @@ class AdaptiveGrid:
         return L
 
     def lid_velocity(self, U=1.0):
+        """Lid data: u_x = U on the top side strictly between the corners."""
+        assert (self.dmask >> 3) & 1, "the lid needs a Dirichlet top side"
         u = np.zeros(self.n)
-        top = (self.ry == self.M) & (self.rx > 0) & (self.rx < self.M)
+        top = (self.ry == self.My) & (self.rx > 0) & (self.rx < self.M)
         u[: self.nV][top] = U
+        return u
+
+    def inflow_velocity(self, ubar):
+        """Inflow data of the channel (eq. 14): u_x = 4 ubar y (H - y) / H^2,
+        u_y = 0 on the side x = 0, H the height (1 in these units)."""
+        u = np.zeros(self.n)
+        y = self.ry / self.My
+        inflow = (self.rx == 0) & self.dirichlet_node
+        u[: self.nV][inflow] = 4.0 * ubar * y[inflow] * (1.0 - y[inflow])
         return u
 
     def lifting(self, uD):
@@ -201,7 +251,6 @@ class AdaptiveGrid:
 def prolongation(fine: AdaptiveGrid, coarse: AdaptiveGrid):
     """Coarse FE function at the fine regular vertices (all three fields)."""
     rows, cols, vals = [], [], []
-    M = coarse.M
     for i in range(fine.nV):
         px, py = int(fine.rx[i]), int(fine.ry[i])
         li = coarse.locate(px, py)
@@ -303,9 +352,9 @@ class AdaptiveHierarchy(mg.Hierarchy):
     """V-cycle over the grids of an adaptive hierarchy (grid 0 coarsest); the
     smoothing, V-cycle and solve of the uniform-grid oracle."""
 
-    def __init__(self, leaves_list, M, beta, eta=1.0):
+    def __init__(self, leaves_list, M, beta, eta=1.0, My=None, dmask=0xF):
         self.dim = 2
-        grids = [AdaptiveGrid(lv, M, beta, eta) for lv in leaves_list]
+        grids = [AdaptiveGrid(lv, M, beta, eta, My, dmask) for lv in leaves_list]
         self.levels = [AdaptiveLevel(g, smooth=l > 0) for l, g in enumerate(grids)]
         for l in range(1, len(grids)):
             self.levels[l].P = prolongation(grids[l], grids[l - 1])

@@ -111,11 +111,12 @@ SIGNATURES = {
     "rav_batch_last_error": (ctypes.c_char_p, [_P]),
     "rav_last_error": (ctypes.c_char_p, [_P]),
     "rav_set_device_allocator": (_S, [_ALLOC_FN, _RELEASE_FN, _P]),
-    "rav_create_adaptive": (_S, [ctypes.POINTER(RavProblemDesc), ctypes.POINTER(_I), ctypes.POINTER(_L), _L, _P,
-                                 ctypes.POINTER(_P)]),
+    "rav_create_adaptive": (_S, [ctypes.POINTER(RavProblemDesc), ctypes.POINTER(_I), ctypes.POINTER(_L), _L, _L,
+                                 _P, ctypes.POINTER(_P)]),
+    "rav_assemble_rhs_dirichlet": (_S, [_P, _P, _P]),
     "rav_adaptive_level_info": (_S, [_P, _I, ctypes.POINTER(_L)]),
-    "rav_adaptive_host_export": (_S, [ctypes.POINTER(RavProblemDesc), ctypes.POINTER(_I), ctypes.POINTER(_L), _L, _I,
-                                      _I, ctypes.POINTER(_D), ctypes.POINTER(_L), ctypes.POINTER(_L)]),
+    "rav_adaptive_host_export": (_S, [ctypes.POINTER(RavProblemDesc), ctypes.POINTER(_I), ctypes.POINTER(_L), _L, _L,
+                                      _I, _I, ctypes.POINTER(_D), ctypes.POINTER(_L), ctypes.POINTER(_L)]),
 }
 
 
@@ -343,8 +344,8 @@ class Hierarchy:
         return a.value, c.value
 
 
-def _adaptive_desc(n_grids, smoother, omega, nu_pre, nu_post, beta, eta):
-    return make_desc(dim=2, n_cells=0, n_levels=n_grids, dmask=0b1111, smoother=smoother, omega=omega,
+def _adaptive_desc(n_grids, smoother, omega, nu_pre, nu_post, beta, eta, dmask=0b1111):
+    return make_desc(dim=2, n_cells=0, n_levels=n_grids, dmask=dmask, smoother=smoother, omega=omega,
                      nu_pre=nu_pre, nu_post=nu_post, eta_out=eta, eta_in=eta, discretization="q1q1-adaptive",
                      beta=beta)
 
@@ -358,18 +359,21 @@ def _leaf_arrays(grids):
 class AdaptiveHierarchy(Hierarchy):
     """Stabilized Q1-Q1 on a hierarchy of adaptively refined quadtree grids
     (``rav_create_adaptive``): ``grids`` lists the leaf arrays (n, 3) of
-    (x0, y0, s), coarsest first, in units of ``lattice`` per side."""
+    (x0, y0, s), coarsest first, in lattice units of the rectangle
+    ``lattice`` x ``lattice_y`` (default: the square); ``dmask`` the sides
+    with Dirichlet velocity (bit 0: x = 0, 1: x = max, 2: y = 0, 3: y = max)."""
 
     def __init__(self, grids, lattice, smoother="rav", omega=0.66, nu_pre=2, nu_post=2, beta=0.05, eta=1.0,
-                 stream=None):
+                 stream=None, lattice_y=None, dmask=0b1111):
         self.lib = lib()
-        self.desc = _adaptive_desc(len(grids), smoother, omega, nu_pre, nu_post, beta, eta)
+        self.desc = _adaptive_desc(len(grids), smoother, omega, nu_pre, nu_post, beta, eta, dmask)
         leaves, counts = _leaf_arrays(grids)
         self.stream = _stream() if stream is None else stream
         h = _P()
+        ly = lattice if lattice_y is None else lattice_y
         st = self.lib.rav_create_adaptive(ctypes.byref(self.desc), leaves.ctypes.data_as(ctypes.POINTER(_I)),
-                                          counts.ctypes.data_as(ctypes.POINTER(_L)), int(lattice), self.stream,
-                                          ctypes.byref(h))
+                                          counts.ctypes.data_as(ctypes.POINTER(_L)), int(lattice), int(ly),
+                                          self.stream, ctypes.byref(h))
         if st < 0:
             raise RavError(st, self.lib.rav_last_error(None).decode())
         self.h = h
@@ -384,16 +388,23 @@ class AdaptiveHierarchy(Hierarchy):
                 "patch_entries", "value_tuples", "patch_configurations", "wide")
         return dict(zip(keys, (int(v) for v in out)))
 
+    def assemble_rhs_dirichlet(self, ud, b):
+        """b = -L_all[:, masked] u_D on the finest grid; ud: host float64
+        array (2, n_vertices) or flat, u_x then u_y per regular vertex."""
+        u = np.ascontiguousarray(np.asarray(ud, dtype=np.float64).reshape(-1))
+        return self._chk(self.lib.rav_assemble_rhs_dirichlet(self.h, u.ctypes.data_as(_P), _ptr(b)))
 
-def adaptive_host_export(grids, lattice, level, what, beta=0.05, eta=1.0):
+
+def adaptive_host_export(grids, lattice, level, what, beta=0.05, eta=1.0, lattice_y=None, dmask=0b1111):
     """Host-only set-up of one adaptive grid (``rav_adaptive_host_export``):
-    what = "operator" | "prolong" | "lid" | "colours"."""
-    kinds = {"operator": 0, "prolong": 1, "lid": 2, "colours": 3}
-    desc = _adaptive_desc(len(grids), "mv" if what == "colours" else "rav", 0.66, 2, 2, beta, eta)
+    what = "operator" | "prolong" | "lid" | "colours" | "vertices"."""
+    kinds = {"operator": 0, "prolong": 1, "lid": 2, "colours": 3, "vertices": 4}
+    desc = _adaptive_desc(len(grids), "mv" if what == "colours" else "rav", 0.66, 2, 2, beta, eta, dmask)
     leaves, counts = _leaf_arrays(grids)
     rows, cols = _L(), _L()
+    ly = lattice if lattice_y is None else lattice_y
     args = (ctypes.byref(desc), leaves.ctypes.data_as(ctypes.POINTER(_I)), counts.ctypes.data_as(ctypes.POINTER(_L)),
-            int(lattice), level, kinds[what])
+            int(lattice), int(ly), level, kinds[what])
     st = lib().rav_adaptive_host_export(*args, None, ctypes.byref(rows), ctypes.byref(cols))
     if st < 0:
         raise RavError(st, lib().rav_last_error(None).decode())

@@ -56,7 +56,12 @@ struct rav_ad_state {
   std::vector<Level> lv;
   double* Minv = nullptr;
   long long nb = 0;
-  double* blid = nullptr;   // finest grid: lid lifting for a lid velocity of 1
+  double* blid = nullptr;   // finest grid: lid lifting for a lid velocity of 1 (null without a Dirichlet top)
+  // finest grid, host: velocity Dirichlet flag per vertex and the couplings of
+  // L_all to masked columns (row, column, A, B_x, B_y) for general lifting
+  std::vector<unsigned char> fine_mask;
+  std::vector<int> dc_row, dc_col;
+  std::vector<double> dc_val;
   int mode = AD_RAV;
   bool have_factors = false;
 };
@@ -97,7 +102,7 @@ void parallel_for(int n, F f) {
 // of every leaf corner (a hanging node is the mean of the two endpoints of the
 // coarse edge whose midpoint it is, applied recursively).
 struct Topo {
-  long long M = 0;
+  long long Mx = 0, My = 0;    // the domain lies in [0, Mx] x [0, My] (lattice units)
   const int* leaf = nullptr;   // (x0, y0, s) per leaf
   long long nl = 0;
   std::vector<long long> reg, hang, ha, hb;
@@ -107,7 +112,9 @@ struct Topo {
   std::vector<char> hstate;
   std::string err;
 
-  long long key(long long x, long long y) const { return y * (M + 1) + x; }
+  long long key(long long x, long long y) const { return y * (Mx + 1) + x; }
+  long long kx(long long k) const { return k % (Mx + 1); }
+  long long ky(long long k) const { return k / (Mx + 1); }
   int nV() const { return (int)reg.size(); }
   int find_reg(long long k) const {
     auto it = std::lower_bound(reg.begin(), reg.end(), k);
@@ -142,10 +149,11 @@ struct Topo {
     return true;
   }
 
-  bool build(const int* leaves, long long n, long long Mlat) {
+  bool build(const int* leaves, long long n, long long Mlx, long long Mly) {
     leaf = leaves;
     nl = n;
-    M = Mlat;
+    Mx = Mlx;
+    My = Mly;
     std::vector<long long> corners(4 * nl), mids(4 * nl);
     for (long long e = 0; e < nl; ++e) {
       const long long x0 = leaf[3 * e], y0 = leaf[3 * e + 1], s = leaf[3 * e + 2], h = s / 2;
@@ -251,7 +259,11 @@ struct HostLevel {
   long long nnz = 0;
   std::vector<int> vid;                // tuple id of every stored entry
   std::vector<double> vtab;            // 8 doubles per distinct tuple
-  std::vector<double> blid;            // lid lifting (finest grid)
+  std::vector<double> blid;            // lid lifting (finest grid; empty without a Dirichlet top side)
+  // finest grid: the entries (row vertex, masked column vertex) of L_all with
+  // A, B_x, B_y, for the lifting of any Dirichlet data
+  std::vector<int> dc_row, dc_col;
+  std::vector<double> dc_val;
   // patches
   Csr pall;                            // all vertices of patch i (MV colouring)
   std::vector<int> poff, pv;
@@ -282,19 +294,54 @@ long long sell_slot(const std::vector<int>& off, int v, int k) {
   return off[v / AD_SLICE] + (long long)AD_SLICE * k + (v % AD_SLICE);
 }
 
-// Conforming operator L = T^T L_corners T of one grid (rows and columns of
-// masked velocity zero) and, with `lid`, the lifting b = -L_all[:, masked] u_D
-// of the lid velocity u_x = 1 on the top side strictly between the corners.
-bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, std::string& err) {
+// Velocity Dirichlet vertices: a regular vertex is on the boundary when one of
+// the four quadrants around it holds no leaf.  It is Dirichlet when such a
+// quadrant lies inside the rectangle (a hole: obstacles are no-slip) or across
+// a side of the rectangle whose bit is set in dmask (bit 0: x = 0, 1: x = Mx,
+// 2: y = 0, 3: y = My); across open sides only, it keeps its velocity unknowns
+// (natural outflow condition).
+std::vector<unsigned char> dirichlet_vertices(const Topo& g, unsigned dmask) {
   const int nV = g.nV();
-  const long long M = g.M;
+  std::vector<unsigned char> cover(nV, 0), mask(nV, 0);
+  for (long long e = 0; e < g.nl; ++e) {
+    const long long x0 = g.leaf[3 * e], y0 = g.leaf[3 * e + 1], s = g.leaf[3 * e + 2];
+    for (int a = 0; a < 4; ++a) {
+      const int v = g.find_reg(g.key(x0 + (a & 1) * s, y0 + (a >> 1) * s));
+      if (v >= 0) cover[v] |= (unsigned char)(1u << ((1 - (a & 1)) | (2 - (a & 2))));   // quadrant: +x bit 0, +y bit 1
+    }
+  }
+  for (int v = 0; v < nV; ++v) {
+    const long long x = g.kx(g.reg[v]), y = g.ky(g.reg[v]);
+    for (int q = 0; q < 4 && !mask[v]; ++q) {
+      if (cover[v] >> q & 1) continue;
+      const bool px = q & 1, py = q & 2;
+      unsigned sides = 0;
+      if (!px && x == 0) sides |= 1u;
+      if (px && x == g.Mx) sides |= 2u;
+      if (!py && y == 0) sides |= 4u;
+      if (py && y == g.My) sides |= 8u;
+      mask[v] = (sides == 0 || (sides & dmask)) ? 1 : 0;
+    }
+  }
+  return mask;
+}
+
+// Conforming operator L = T^T L_corners T of one grid (rows and columns of
+// masked velocity zero); on the finest grid also the couplings of L_all to the
+// masked velocity columns (any Dirichlet data's lifting b = -L_all[:, masked]
+// u_D) and, with a Dirichlet top side, that lifting for the lid velocity
+// u_x = 1 on the top side strictly between the corners.  Lengths are in units
+// of the domain height: a leaf of s lattice units has size s / My.
+bool assemble(const Topo& g, double beta, double eta, unsigned dmask, bool finest, HostLevel& H,
+              std::string& err) {
+  const int nV = g.nV();
   H.nV = nV;
-  H.vmask.assign(nV, 0);
+  H.vmask = dirichlet_vertices(g, dmask);
+  const bool lid = finest && (dmask & 8u);
   std::vector<unsigned char> is_lid(nV, 0);
   for (int v = 0; v < nV; ++v) {
-    const long long x = g.reg[v] % (M + 1), y = g.reg[v] / (M + 1);
-    H.vmask[v] = (x == 0 || y == 0 || x == M || y == M) ? 1 : 0;
-    is_lid[v] = (y == M && x > 0 && x < M) ? 1 : 0;
+    const long long x = g.kx(g.reg[v]), y = g.ky(g.reg[v]);
+    is_lid[v] = (y == g.My && x > 0 && x < g.Mx) ? 1 : 0;
   }
   std::vector<int> ve;
   H.nbr = build_csr(nV, [&](auto&& emit) {
@@ -324,7 +371,7 @@ bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, st
     }
   const long long P = H.nnz;
   for (long long e = 0; e < g.nl; ++e) {
-    const double h = (double)g.leaf[3 * e + 2] / (double)M;
+    const double h = (double)g.leaf[3 * e + 2] / (double)g.My;
     const double sB = -h, sC = -beta * 2.0 * h * h;
     for (int a = 0; a < 4; ++a)
       for (int ca = g.cw_ptr[4 * e + a]; ca < g.cw_ptr[4 * e + a + 1]; ++ca) {
@@ -358,6 +405,16 @@ bool assemble(const Topo& g, double beta, double eta, bool lid, HostLevel& H, st
         H.blid[2LL * nV + i] -= H.val[AD_BX * P + s];
       }
   }
+  if (finest)
+    for (int i = 0; i < nV; ++i)
+      for (int k = 0; k < len[i]; ++k) {
+        const int j = H.nbr.begin(i)[k];
+        if (!H.vmask[j]) continue;
+        const long long s = sell_slot(H.soff, i, k);
+        H.dc_row.push_back(i);
+        H.dc_col.push_back(j);
+        H.dc_val.insert(H.dc_val.end(), {H.val[AD_A * P + s], H.val[AD_BX * P + s], H.val[AD_BY * P + s]});
+      }
   for (int i = 0; i < nV; ++i)
     for (int k = 0; k < len[i]; ++k) {
       const int j = H.nbr.begin(i)[k];
@@ -512,11 +569,11 @@ bool build_patches(const Topo& g, HostLevel& H, std::string& err) {
 // (bilinear on a coarse leaf that contains the vertex, hanging coarse corners
 // through their constraints), and its transpose.
 bool build_transfer(const Topo& fine, const Topo& coarse, HostLevel& H, int nVc, std::string& err) {
-  const long long M = fine.M;
+  const long long Mx = fine.Mx, My = fine.My, M = std::max(Mx, My);
   std::unordered_map<long long, int> cells;
   cells.reserve((size_t)coarse.nl * 2);
   int smin = INT_MAX;
-  auto ckey = [&](long long x0, long long y0, long long s) { return ((y0 * (M + 1)) + x0) * 64 + __builtin_ctzll(s); };
+  auto ckey = [&](long long x0, long long y0, long long s) { return ((y0 * (Mx + 1)) + x0) * 64 + __builtin_ctzll(s); };
   for (long long e = 0; e < coarse.nl; ++e) {
     cells[ckey(coarse.leaf[3 * e], coarse.leaf[3 * e + 1], coarse.leaf[3 * e + 2])] = (int)e;
     smin = std::min(smin, coarse.leaf[3 * e + 2]);
@@ -535,15 +592,20 @@ bool build_transfer(const Topo& fine, const Topo& coarse, HostLevel& H, int nVc,
   H.pwt.clear();
   std::vector<Wt> row;
   for (int i = 0; i < nV; ++i) {
-    const long long px = fine.reg[i] % (M + 1), py = fine.reg[i] / (M + 1);
+    const long long px = fine.kx(fine.reg[i]), py = fine.ky(fine.reg[i]);
     int li = -1;
     long long x0 = 0, y0 = 0, sc = smin;
-    for (; sc <= M; sc *= 2) {
-      x0 = std::min(px / sc * sc, M - sc);
-      y0 = std::min(py / sc * sc, M - sc);
-      auto it = cells.find(ckey(x0, y0, sc));
-      if (it != cells.end()) { li = it->second; break; }
-    }
+    // the coarse leaf that holds the vertex: of the cells of size sc that touch
+    // it (one to four), the first that is a leaf
+    for (; sc <= M && li < 0; sc *= 2)
+      for (int c = 0; c < 4 && li < 0; ++c) {
+        const long long cx = px / sc * sc - ((c & 1) && px % sc == 0 ? sc : 0);
+        const long long cy = py / sc * sc - ((c & 2) && py % sc == 0 ? sc : 0);
+        if (cx < 0 || cy < 0 || cx + sc > Mx || cy + sc > My) continue;
+        auto it = cells.find(ckey(cx, cy, sc));
+        if (it != cells.end()) { li = it->second; x0 = cx; y0 = cy; }
+      }
+    sc = li >= 0 ? coarse.leaf[3 * li + 2] : sc;
     if (li < 0) { err = "a fine vertex lies in no coarse leaf"; return false; }
     const double tx = (double)(px - x0) / (double)sc, ty = (double)(py - y0) / (double)sc;
     row.clear();
@@ -577,15 +639,19 @@ bool build_transfer(const Topo& fine, const Topo& coarse, HostLevel& H, int nVc,
   return true;
 }
 
-bool check_leaves(const int* lv, long long n, long long M, std::string& err) {
+// Leaves of one grid: aligned power-of-two cells (s >= 2) inside the
+// rectangle, pairwise disjoint; `area` receives their total area (every grid
+// must cover the coarsest grid's region, which nesting then makes the same).
+bool check_leaves(const int* lv, long long n, long long Mx, long long My, long long& area, std::string& err) {
   std::unordered_set<long long> seen;
   seen.reserve((size_t)n * 2);
-  long long area = 0;
-  auto k3 = [&](long long x0, long long y0, long long s) { return ((y0 * (M + 1)) + x0) * 64 + __builtin_ctzll(s); };
+  area = 0;
+  const long long M = std::max(Mx, My);
+  auto k3 = [&](long long x0, long long y0, long long s) { return ((y0 * (Mx + 1)) + x0) * 64 + __builtin_ctzll(s); };
   for (long long e = 0; e < n; ++e) {
     const long long x0 = lv[3 * e], y0 = lv[3 * e + 1], s = lv[3 * e + 2];
-    if (s < 2 || (s & (s - 1)) || x0 < 0 || y0 < 0 || x0 % s || y0 % s || x0 + s > M || y0 + s > M) {
-      err = "leaf " + std::to_string(e) + " is not an aligned cell of even power-of-two size inside the square";
+    if (s < 2 || (s & (s - 1)) || x0 < 0 || y0 < 0 || x0 % s || y0 % s || x0 + s > Mx || y0 + s > My) {
+      err = "leaf " + std::to_string(e) + " is not an aligned cell of even power-of-two size inside the rectangle";
       return false;
     }
     if (!seen.insert(k3(x0, y0, s)).second) { err = "duplicate leaf " + std::to_string(e); return false; }
@@ -596,7 +662,6 @@ bool check_leaves(const int* lv, long long n, long long M, std::string& err) {
     for (long long sc = 2 * s; sc <= M; sc *= 2)
       if (seen.count(k3(x0 / sc * sc, y0 / sc * sc, sc))) { err = "overlapping leaves"; return false; }
   }
-  if (area != M * M) { err = "leaves do not tile the unit square"; return false; }
   return true;
 }
 
@@ -695,11 +760,14 @@ rav_status need_factors(rav_ctx* ctx) {
   return RAV_OK;
 }
 
-// Dense coarse matrix (masked rows and columns replaced by the identity) with
-// the zero-mean pressure border, inverted once on the device.
+// Dense coarse matrix (masked rows and columns replaced by the identity),
+// inverted once on the device.  With Dirichlet velocity on the whole boundary
+// the pressure is fixed only up to a constant: the matrix is then bordered by
+// the zero-mean pressure constraint.
 rav_status build_coarse(rav_ctx* ctx, const HostLevel& H) {
   rav_ad_state* S = st(ctx);
-  const long long n0 = 3LL * H.nV, nb = n0 + 1, nV = H.nV, P = H.nnz;
+  const bool border = ctx->desc.bc_dirichlet_mask == 0xFu;
+  const long long n0 = 3LL * H.nV, nb = n0 + (border ? 1 : 0), nV = H.nV, P = H.nnz;
   S->nb = nb;
   std::vector<double> M((size_t)(nb * nb), 0.0);
   for (int i = 0; i < H.nV; ++i) {
@@ -720,7 +788,7 @@ rav_status build_coarse(rav_ctx* ctx, const HostLevel& H) {
       M[(size_t)((nV + i) * nb + nV + i)] = 1.0;
     }
   }
-  for (long long j = 2 * nV; j < n0; ++j) {
+  for (long long j = 2 * nV; j < n0 && border; ++j) {
     M[(size_t)(n0 * nb + j)] = 1.0;
     M[(size_t)(j * nb + n0)] = 1.0;
   }
@@ -854,15 +922,15 @@ rav_status upload_level(rav_ctx* ctx, Level& L, const HostLevel& H, bool smoothe
   return RAV_OK;
 }
 
-rav_status check_desc(const rav_problem_desc* d, long lattice) {
+rav_status check_desc(const rav_problem_desc* d, long lattice_x, long lattice_y) {
   if (d->discretization != RAV_Q1Q1_ADAPTIVE)
     return rav_set_error(nullptr, RAV_EINVAL, "rav_create_adaptive needs discretization RAV_Q1Q1_ADAPTIVE");
   if (d->dim != 2) return rav_set_error(nullptr, RAV_EUNSUPPORTED, "adaptive grids are provided in 2D");
   if (d->n_levels < 2 || d->n_levels > 24) return rav_set_error(nullptr, RAV_EINVAL, "n_levels must be in [2, 24]");
-  if (lattice < 2 || lattice > (1L << 24) || (lattice & (lattice - 1)))
-    return rav_set_error(nullptr, RAV_EINVAL, "lattice must be a power of two in [2, 2^24]");
-  if (d->bc_dirichlet_mask != 0xFu)
-    return rav_set_error(nullptr, RAV_EUNSUPPORTED, "adaptive grids are provided with Dirichlet velocity on all sides");
+  if (lattice_x < 2 || lattice_x > (1L << 24) || lattice_y < 2 || lattice_y > (1L << 24))
+    return rav_set_error(nullptr, RAV_EINVAL, "lattice sizes must be in [2, 2^24]");
+  if (d->bc_dirichlet_mask > 0xFu)
+    return rav_set_error(nullptr, RAV_EINVAL, "bc_dirichlet_mask has bits beyond the four sides");
   if (!(d->beta > 0.0)) return rav_set_error(nullptr, RAV_EINVAL, "the stabilization constant beta must be > 0");
   if (!(d->eta_out > 0.0)) return rav_set_error(nullptr, RAV_EINVAL, "viscosity must be > 0");
   if (d->n_incl != 0) return rav_set_error(nullptr, RAV_EUNSUPPORTED, "adaptive grids use a constant viscosity");
@@ -879,8 +947,8 @@ rav_status check_desc(const rav_problem_desc* d, long lattice) {
 }
 
 // Validates every grid and builds its topology.
-bool build_topos(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice,
-                 std::vector<Topo>& topo, std::string& err) {
+bool build_topos(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice_x,
+                 long lattice_y, std::vector<Topo>& topo, std::string& err) {
   const int nl = d->n_levels;
   std::vector<long long> first(nl + 1, 0);
   for (int l = 0; l < nl; ++l) {
@@ -889,16 +957,23 @@ bool build_topos(const rav_problem_desc* d, const int* leaves, const long* n_lea
   }
   topo.assign(nl, Topo());
   std::vector<std::string> errs(nl);
+  std::vector<long long> area(nl, 0);
   parallel_for(nl, [&](int t) {
     const int l = nl - 1 - t;   // largest grids first
     const int* lv = leaves + 3 * first[l];
     std::string e2;
-    if (!check_leaves(lv, n_leaves[l], lattice, e2) || !topo[l].build(lv, n_leaves[l], lattice))
+    if (!check_leaves(lv, n_leaves[l], lattice_x, lattice_y, area[l], e2) ||
+        !topo[l].build(lv, n_leaves[l], lattice_x, lattice_y))
       errs[l] = "grid " + std::to_string(l) + ": " + (e2.empty() ? topo[l].err : e2);
   });
   for (int l = 0; l < nl; ++l)
     if (!errs[l].empty()) {
       err = errs[l];
+      return false;
+    }
+  for (int l = 1; l < nl; ++l)
+    if (area[l] != area[0]) {
+      err = "grid " + std::to_string(l) + ": leaves do not cover the region of the coarsest grid";
       return false;
     }
   if (3LL * topo[0].nV() + 1 > MAX_COARSE) {
@@ -911,15 +986,16 @@ bool build_topos(const rav_problem_desc* d, const int* leaves, const long* n_lea
 }  // namespace
 
 // ============================================================================
-rav_status rav_ad_create(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice,
-                         void* hip_stream, rav_ctx** out) {
+rav_status rav_ad_create(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice_x,
+                         long lattice_y, void* hip_stream, rav_ctx** out) {
   if (!d || !leaves || !n_leaves || !out) return rav_set_error(nullptr, RAV_EINVAL, "null argument");
-  rav_status s0 = check_desc(d, lattice);
+  rav_status s0 = check_desc(d, lattice_x, lattice_y);
   if (s0 != RAV_OK) return s0;
   const int nl = d->n_levels;
   std::vector<Topo> topo;
   std::string err;
-  if (!build_topos(d, leaves, n_leaves, lattice, topo, err)) return rav_set_error(nullptr, RAV_EINVAL, err);
+  if (!build_topos(d, leaves, n_leaves, lattice_x, lattice_y, topo, err))
+    return rav_set_error(nullptr, RAV_EINVAL, err);
 
   rav_ctx* ctx = new rav_ctx();
   ctx->desc = *d;
@@ -943,7 +1019,7 @@ rav_status rav_ad_create(const rav_problem_desc* d, const int* leaves, const lon
     const int l = nl - 1 - t;
     HostLevel& H = hosts[l];
     std::string e2;
-    if (!assemble(topo[l], d->beta, d->eta_out, l == nl - 1, H, e2) ||
+    if (!assemble(topo[l], d->beta, d->eta_out, d->bc_dirichlet_mask, l == nl - 1, H, e2) ||
         (l > 0 && (!build_patches(topo[l], H, e2) || !build_transfer(topo[l], topo[l - 1], H, topo[l - 1].nV(), e2))))
       errs[l] = "grid " + std::to_string(l) + ": " + e2;
   });
@@ -959,6 +1035,10 @@ rav_status rav_ad_create(const rav_problem_desc* d, const int* leaves, const lon
     if (l == nl - 1) {
       hipError_t e = upload(&S->blid, H.blid);
       if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return fail(RAV_EDEVICE); }
+      S->fine_mask = H.vmask;
+      S->dc_row = std::move(H.dc_row);
+      S->dc_col = std::move(H.dc_col);
+      S->dc_val = std::move(H.dc_val);
     }
     if (l == 0 && (s = build_coarse(ctx, H)) != RAV_OK) return fail(s);
     H = HostLevel();
@@ -1036,8 +1116,30 @@ rav_status rav_ad_n_patches(const rav_ctx* ctx, int level, long* n) {
 
 rav_status rav_ad_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev) {
   const Level& L = st(ctx)->lv.back();
+  if (!st(ctx)->blid) return rav_set_error(ctx, RAV_EINVAL, "the lid needs Dirichlet velocity on the top side");
   ad_launch_scale(st(ctx)->blid, lid_u, b_dev, 3LL * L.nV, ctx->stream);
   ACK(hipGetLastError());
+  ACK(hipStreamSynchronize(ctx->stream));
+  return RAV_OK;
+}
+
+// b = -L_all[:, masked] u_D on the finest grid, masked rows zero (host sums
+// over the stored couplings, then one copy).
+rav_status rav_ad_assemble_rhs_dirichlet(rav_ctx* ctx, const double* ud, double* b_dev) {
+  const rav_ad_state* S = st(ctx);
+  const long long nV = S->lv.back().nV;
+  std::vector<double> b(3 * nV, 0.0);
+  for (size_t q = 0; q < S->dc_row.size(); ++q) {
+    const int i = S->dc_row[q], j = S->dc_col[q];
+    const double a = S->dc_val[3 * q], bx = S->dc_val[3 * q + 1], by = S->dc_val[3 * q + 2];
+    const double ux = ud[j], uy = ud[nV + j];
+    if (!S->fine_mask[i]) {
+      b[i] -= a * ux;
+      b[nV + i] -= a * uy;
+    }
+    b[2 * nV + i] -= bx * ux + by * uy;
+  }
+  ACK(hipMemcpyAsync(b_dev, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice, ctx->stream));
   ACK(hipStreamSynchronize(ctx->stream));
   return RAV_OK;
 }
@@ -1291,19 +1393,34 @@ rav_status rav_ad_level_info(const rav_ctx* ctx, int level, long* info) {
 }
 
 // Host-only set-up of one grid, for checks without a device.
-rav_status rav_ad_host_export(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice,
-                              int level, int what, double* out, long* rows, long* cols) {
+rav_status rav_ad_host_export(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice_x,
+                              long lattice_y, int level, int what, double* out, long* rows, long* cols) {
   if (!d || !leaves || !n_leaves || !rows || !cols) return rav_set_error(nullptr, RAV_EINVAL, "null argument");
-  rav_status s0 = check_desc(d, lattice);
+  rav_status s0 = check_desc(d, lattice_x, lattice_y);
   if (s0 != RAV_OK) return s0;
-  if (level < 0 || level >= d->n_levels || what < 0 || what > 3 || (level == 0 && (what == 1 || what == 3)))
+  if (level < 0 || level >= d->n_levels || what < 0 || what > 4 || (level == 0 && (what == 1 || what == 3)))
     return rav_set_error(nullptr, RAV_EINVAL, "bad level or export kind");
+  if (what == 2 && !(d->bc_dirichlet_mask & 8u))
+    return rav_set_error(nullptr, RAV_EINVAL, "the lid needs Dirichlet velocity on the top side");
   std::vector<Topo> topo;
   std::string err;
-  if (!build_topos(d, leaves, n_leaves, lattice, topo, err)) return rav_set_error(nullptr, RAV_EINVAL, err);
+  if (!build_topos(d, leaves, n_leaves, lattice_x, lattice_y, topo, err))
+    return rav_set_error(nullptr, RAV_EINVAL, err);
   HostLevel H;
-  if (!assemble(topo[level], d->beta, d->eta_out, what == 2, H, err)) return rav_set_error(nullptr, RAV_EINVAL, err);
+  if (!assemble(topo[level], d->beta, d->eta_out, d->bc_dirichlet_mask, what == 2, H, err))
+    return rav_set_error(nullptr, RAV_EINVAL, err);
   const long long nV = H.nV, n = 3 * nV, P = H.nnz;
+  if (what == 4) {
+    *rows = (long)nV;
+    *cols = 3;
+    if (!out) return RAV_OK;
+    for (long long v = 0; v < nV; ++v) {
+      out[3 * v] = (double)topo[level].kx(topo[level].reg[v]);
+      out[3 * v + 1] = (double)topo[level].ky(topo[level].reg[v]);
+      out[3 * v + 2] = (double)H.vmask[v];
+    }
+    return RAV_OK;
+  }
   if (what == 0) {
     *rows = (long)n;
     *cols = (long)n;
@@ -1345,7 +1462,8 @@ rav_status rav_ad_host_export(const rav_problem_desc* d, const int* leaves, cons
   *cols = (long)nc;
   if (!out) return RAV_OK;
   HostLevel Hc;
-  if (!assemble(topo[level - 1], d->beta, d->eta_out, false, Hc, err)) return rav_set_error(nullptr, RAV_EINVAL, err);
+  if (!assemble(topo[level - 1], d->beta, d->eta_out, d->bc_dirichlet_mask, false, Hc, err))
+    return rav_set_error(nullptr, RAV_EINVAL, err);
   std::fill(out, out + n * nc, 0.0);
   for (long long i = 0; i < nV; ++i)
     for (int k = H.pptr[i]; k < H.pptr[i + 1]; ++k) {

@@ -1457,14 +1457,21 @@ rav_status rav_stream_copy(void* stream, double* dst, const double* src, long n)
 }
 
 rav_status rav_create_adaptive(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
-                               long lattice, void* hip_stream, rav_ctx** out) {
+                               long lattice_x, long lattice_y, void* hip_stream, rav_ctx** out) {
   if (out) *out = nullptr;
-  return rav_ad_create(desc, leaves_host, n_leaves_host, lattice, hip_stream, out);
+  return rav_ad_create(desc, leaves_host, n_leaves_host, lattice_x, lattice_y, hip_stream, out);
 }
 
 rav_status rav_adaptive_host_export(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
-                                    long lattice, int level, int what, double* out_host, long* rows, long* cols) {
-  return rav_ad_host_export(desc, leaves_host, n_leaves_host, lattice, level, what, out_host, rows, cols);
+                                    long lattice_x, long lattice_y, int level, int what, double* out_host, long* rows,
+                                    long* cols) {
+  return rav_ad_host_export(desc, leaves_host, n_leaves_host, lattice_x, lattice_y, level, what, out_host, rows, cols);
+}
+
+rav_status rav_assemble_rhs_dirichlet(rav_ctx* ctx, const double* ud_host, double* b_dev) {
+  if (!ctx || !ud_host || !b_dev) return RAV_EINVAL;
+  if (!ctx->ad) return set_err(ctx, RAV_EUNSUPPORTED, "rav_assemble_rhs_dirichlet serves adaptive-grid contexts");
+  return rav_ad_assemble_rhs_dirichlet(ctx, ud_host, b_dev);
 }
 
 rav_status rav_adaptive_level_info(const rav_ctx* ctx, int level, long* info_host) {

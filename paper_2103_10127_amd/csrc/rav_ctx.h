@@ -180,14 +180,15 @@ rav_status rav_q1_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const
                              float* ms_apply);
 
 // Stabilized Q1-Q1 on adaptive quadtree grids (rav_adapt.hip).
-rav_status rav_ad_create(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice,
-                         void* hip_stream, rav_ctx** out);
+rav_status rav_ad_create(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice_x,
+                         long lattice_y, void* hip_stream, rav_ctx** out);
 void rav_ad_free(rav_ctx* ctx);
 rav_status rav_ad_factor(rav_ctx* ctx);
 rav_status rav_ad_dofs(const rav_ctx* ctx, int level, long* n_total, long* n_free);
 int rav_ad_n_levels(const rav_ctx* ctx);
 rav_status rav_ad_n_patches(const rav_ctx* ctx, int level, long* n);
 rav_status rav_ad_assemble_rhs_lid(rav_ctx* ctx, double lid_u, double* b_dev);
+rav_status rav_ad_assemble_rhs_dirichlet(rav_ctx* ctx, const double* ud_host, double* b_dev);
 rav_status rav_ad_residual(rav_ctx* ctx, int level, const double* x, const double* b, double* r, double* norm);
 rav_status rav_ad_smooth(rav_ctx* ctx, int level, int sweeps, double* x, const double* b);
 rav_status rav_ad_restrict(rav_ctx* ctx, int level, const double* rf, double* bc);
@@ -202,5 +203,5 @@ rav_status rav_ad_get_patch_inverse(rav_ctx* ctx, int level, long patch, double*
 rav_status rav_ad_time_sweep(rav_ctx* ctx, int level, int reps, double* x, const double* b, float* ms_res,
                              float* ms_apply);
 rav_status rav_ad_level_info(const rav_ctx* ctx, int level, long* info);
-rav_status rav_ad_host_export(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice,
-                              int level, int what, double* out, long* rows, long* cols);
+rav_status rav_ad_host_export(const rav_problem_desc* d, const int* leaves, const long* n_leaves, long lattice_x,
+                              long lattice_y, int level, int what, double* out, long* rows, long* cols);

@@ -1,8 +1,10 @@
 """Host-side set-up of the adaptive grids (rav_adaptive_host_export, no device)
 against the oracle (Sec. 2, Fig. 2; Sec. 4.1, Table 1): conforming operator
 with hanging-node constraints, lid lifting, grid transfer and the MV colouring
-on the first grids of the cavity hierarchy and on a randomly refined one, the DoF counts of Table 1, and the
-rejection of grids that break the rules (not tiling, not 2:1 balanced, not
+on the first grids of the cavity hierarchy, on a randomly refined one and on a
+channel with an obstacle and an open outflow side (Sec. 4.2: the vertices and
+their Dirichlet flags too), the DoF counts of Table 1, and the rejection of
+grids that break the rules (not covering the region, not 2:1 balanced, not
 nested)."""
 import os
 
@@ -17,33 +19,49 @@ BETA, ETA = 0.05, 1.0
 N_GRIDS = 4
 
 
-@pytest.fixture(scope="module", params=["cavity", "random"])
+@pytest.fixture(scope="module", params=["cavity", "random", "channel"])
 def hierarchy(request):
+    """(grids, lattice_x, lattice_y, Dirichlet mask)."""
     if request.param == "cavity":
-        return ri.cavity_grids(N_GRIDS), ri.lattice(N_GRIDS)
-    return ri.random_quadtree_grids(N_GRIDS, base=8, frac=0.35, seed=1)
+        M = ri.lattice(N_GRIDS)
+        return ri.cavity_grids(N_GRIDS), M, M, ri.ALL_DIRICHLET_2D
+    if request.param == "random":
+        G, M = ri.random_quadtree_grids(N_GRIDS, base=8, frac=0.35, seed=1)
+        return G, M, M, ri.ALL_DIRICHLET_2D
+    G, Mx, My = ri.channel_grids(N_GRIDS, bands=(ri.UNIFORM, 1, 1), cells=(16, 3))
+    return G, Mx, My, ri.OUTFLOW_2D
+
+
+def _export(hierarchy, level, what):
+    G, Mx, My, dm = hierarchy
+    return capi.adaptive_host_export(G, Mx, level, what, BETA, ETA, lattice_y=My, dmask=dm)
+
+
+def _grid(hierarchy, level):
+    G, Mx, My, dm = hierarchy
+    return am.AdaptiveGrid(G[level], Mx, BETA, ETA, My=My, dmask=dm)
 
 
 @pytest.mark.parametrize("level", range(N_GRIDS))
-def test_operator_and_lid_match_oracle(hierarchy, level):
-    G, M = hierarchy
-    g = am.AdaptiveGrid(G[level], M, BETA, ETA)
+def test_operator_vertices_and_lid_match_oracle(hierarchy, level):
+    g = _grid(hierarchy, level)
     L = g.assemble().toarray()
-    Lh = capi.adaptive_host_export(G, M, level, "operator", BETA, ETA)
+    Lh = _export(hierarchy, level, "operator")
     assert Lh.shape == L.shape
     np.testing.assert_allclose(Lh, L, rtol=0, atol=1e-13 * np.abs(L).max())
-    np.testing.assert_allclose(capi.adaptive_host_export(G, M, level, "lid", BETA, ETA), g.lid_rhs(),
-                               rtol=0, atol=1e-14)
+    np.testing.assert_allclose(_export(hierarchy, level, "lid"), g.lid_rhs(), rtol=0, atol=1e-14)
+    V = _export(hierarchy, level, "vertices")
+    np.testing.assert_array_equal(V[:, 0], g.rx)
+    np.testing.assert_array_equal(V[:, 1], g.ry)
+    np.testing.assert_array_equal(V[:, 2].astype(bool), g.dirichlet_node)
 
 
 @pytest.mark.parametrize("level", range(1, N_GRIDS))
 def test_transfer_and_colouring_match_oracle(hierarchy, level):
-    G, M = hierarchy
-    g = am.AdaptiveGrid(G[level], M, BETA, ETA)
-    gc = am.AdaptiveGrid(G[level - 1], M, BETA, ETA)
+    g, gc = _grid(hierarchy, level), _grid(hierarchy, level - 1)
     P = am.prolongation(g, gc).toarray()
-    np.testing.assert_allclose(capi.adaptive_host_export(G, M, level, "prolong", BETA, ETA), P, rtol=0, atol=1e-15)
-    col = capi.adaptive_host_export(G, M, level, "colours", BETA, ETA)
+    np.testing.assert_allclose(_export(hierarchy, level, "prolong"), P, rtol=0, atol=1e-15)
+    col = _export(hierarchy, level, "colours")
     np.testing.assert_array_equal(col.astype(np.int64), am.mv_colouring(g))
 
 
@@ -75,7 +93,7 @@ def test_invalid_grids_are_rejected():
     coarse = np.array([(x, y, 8) for y in (0, 8) for x in (0, 8)], dtype=np.int32)
     fine = np.array([(x, y, 4) for y in range(0, 16, 4) for x in range(0, 16, 4)], dtype=np.int32)
     capi.adaptive_host_export([coarse, fine], M, 1, "prolong", BETA, ETA)   # valid
-    assert "tile" in _expect_einval([coarse, fine[:-1]], M)
+    assert "cover" in _expect_einval([coarse, fine[:-1]], M)
     # one 8-cell next to 2-cells: not 2:1 balanced
     unbal = [(0, 0, 8), (8, 8, 8), (0, 8, 8)] + [(8 + x, y, 2) for y in range(0, 8, 2) for x in range(0, 8, 2)]
     assert "balanced" in _expect_einval([coarse, np.array(unbal, dtype=np.int32)], M)
@@ -83,5 +101,6 @@ def test_invalid_grids_are_rejected():
     assert "nested" in _expect_einval([fine, coarse], M)
     odd = np.concatenate([fine[:-1], [(12, 12, 3)]]).astype(np.int32)   # size 3: not a power of two
     assert "aligned" in _expect_einval([coarse, odd], M)
-    with pytest.raises(capi.RavError):
-        capi.adaptive_host_export([coarse, fine], 12, 1, "prolong", BETA, ETA)   # lattice not a power of two
+    with pytest.raises(capi.RavError) as e:
+        capi.adaptive_host_export([coarse, fine], 12, 1, "prolong", BETA, ETA)   # leaves beyond a 12-unit lattice
+    assert "inside the rectangle" in str(e.value)

@@ -1,9 +1,11 @@
 """Stabilized Q1-Q1 on the adaptive cavity grids (Sec. 2, Fig. 2; Sec. 4.1,
-Table 1) on the GPU against the oracle: on Omega^1..Omega^4 (7,059 DoFs), and
-on a randomly refined balanced hierarchy, the residual of every grid, DoF counts, owner and patch maps, the stored local
+Table 1) on the GPU against the oracle: on Omega^1..Omega^4 (7,059 DoFs), on
+a randomly refined balanced hierarchy, and on a channel with an obstacle, an
+inflow and an open outflow side (Sec. 4.2; no pressure constraint), the
+residual of every grid, DoF counts, owner and patch maps, the stored local
 inverses (RAV owned rows, AV/MV every row), transfers, the coarse solve,
-RAV/AV/MV sweeps and V-cycles, the lid right-hand side, and solves to 1e-8
-with the oracle's cycle counts.  On the full hierarchy Omega^1..Omega^10
+RAV/AV/MV sweeps and V-cycles, the lid and Dirichlet-data right-hand sides,
+and solves to 1e-8 with the oracle's cycle counts.  On the full hierarchy Omega^1..Omega^10
 (3,063,075 DoFs, the paper's finest cavity grid) in the configuration the
 benchmark times: the RAV V(3,3) solve reaches 1e-8, and the lid right-hand
 side and the final residual agree on sampled rows with the oracle's rows,
@@ -26,26 +28,40 @@ OMEGA = {"rav": 0.66, "mv": 0.66, "av": 0.1}
 SM = {"rav": mg.RAV, "av": mg.AV, "mv": mg.MV}
 
 
-@pytest.fixture(scope="module", params=["cavity", "random"])
+@pytest.fixture(scope="module", params=["cavity", "random", "channel"])
 def grids(request):
-    """The first four grids of Table 1, and a randomly refined 2:1-balanced
-    hierarchy (many hanging nodes, including constrained endpoints)."""
+    """(grids, lattice_x, lattice_y, Dirichlet mask): the first four grids of
+    Table 1, a randomly refined 2:1-balanced hierarchy (many hanging nodes,
+    including constrained endpoints), and a small channel (16 x 3 coarse cells,
+    a one-cell obstacle, refined towards the walls and the obstacle)."""
     if request.param == "cavity":
-        return ri.cavity_grids(N_GRIDS), ri.lattice(N_GRIDS)
-    return ri.random_quadtree_grids(N_GRIDS, base=8, frac=0.35, seed=1)
+        M = ri.lattice(N_GRIDS)
+        return ri.cavity_grids(N_GRIDS), M, M, ri.ALL_DIRICHLET_2D
+    if request.param == "random":
+        G, M = ri.random_quadtree_grids(N_GRIDS, base=8, frac=0.35, seed=1)
+        return G, M, M, ri.ALL_DIRICHLET_2D
+    G, Mx, My = ri.channel_grids(N_GRIDS, bands=(ri.UNIFORM, 1, 1), cells=(16, 3))
+    return G, Mx, My, ri.OUTFLOW_2D
 
 
 @pytest.fixture(scope="module")
 def oracle(grids):
-    G, M = grids
-    return am.AdaptiveHierarchy(G, M, BETA, ETA)
+    G, Mx, My, dm = grids
+    return am.AdaptiveHierarchy(G, Mx, BETA, ETA, My=My, dmask=dm)
 
 
 def _gpu(grids, smoother="rav", nu=2):
-    G, M = grids
-    print(f"[gpu] adaptive {len(G)} grids {smoother} nu={nu}", flush=True)
-    H = AdaptiveHierarchy(G, M, smoother=smoother, omega=OMEGA[smoother], nu_pre=nu, nu_post=nu, beta=BETA, eta=ETA)
+    G, Mx, My, dm = grids
+    print(f"[gpu] adaptive {len(G)} grids {Mx}x{My} mask {dm} {smoother} nu={nu}", flush=True)
+    H = AdaptiveHierarchy(G, Mx, smoother=smoother, omega=OMEGA[smoother], nu_pre=nu, nu_post=nu, beta=BETA, eta=ETA,
+                          lattice_y=My, dmask=dm)
     return H
+
+
+def _rhs(g):
+    """The benchmark's data: the driven cavity's lid, or the channel's
+    parabolic inflow (eq. 14, mean velocity 0.3)."""
+    return g.lid_rhs() if g.all_dirichlet else g.lifting(g.inflow_velocity(0.3))
 
 
 def _rel(a, b):
@@ -136,6 +152,22 @@ def test_lid_rhs(grids, oracle):
     H.close()
 
 
+def test_dirichlet_rhs(grids, oracle):
+    """rav_assemble_rhs_dirichlet against the oracle's lifting, for random
+    data on the Dirichlet vertices (the library reads only those)."""
+    H = _gpu(grids)
+    g = oracle.finest.grid
+    rng = np.random.default_rng(5)
+    ud = rng.standard_normal((2, g.nV))
+    u = np.zeros(g.n)
+    u[: 2 * g.nV] = ud.reshape(-1)
+    bo = g.lifting(np.where(g.free, 0.0, u))
+    b = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    H.assemble_rhs_dirichlet(ud, b)
+    assert np.abs(b.cpu().numpy() - bo).max() <= 1e-14 * np.abs(bo).max()
+    H.close()
+
+
 @pytest.mark.parametrize("smoother", ["rav", "av", "mv"])
 def test_sweeps_and_vcycles(grids, oracle, smoother):
     H = _gpu(grids, smoother)
@@ -150,7 +182,7 @@ def test_sweeps_and_vcycles(grids, oracle, smoother):
         xo = oracle.smooth(l, x, b, SM[smoother], om, 2)
         assert _rel(xd.cpu().numpy() - x, xo - x) <= 1e-12, (smoother, l)
     g = oracle.finest.grid
-    bb = g.lid_rhs()
+    bb = _rhs(g)
     bd = _dev(bb)
     xd = torch.zeros_like(bd)
     xo = np.zeros(g.n)
@@ -171,7 +203,7 @@ def test_solve_matches_oracle(grids, oracle, smoother, table, monkeypatch):
     if table == "global":
         monkeypatch.setenv("RAV_AD_TABLE_LDS", "0")
     g = oracle.finest.grid
-    b = g.lid_rhs()
+    b = _rhs(g)
     xo, ko, _, sto = oracle.solve(b, 1e-8, 200, SM[smoother], OMEGA[smoother], 3)
     H = _gpu(grids, smoother, nu=3)
     H.factor()

@@ -3,7 +3,11 @@ uniformly refined grid it is the uniform Q1-Q1 oracle (operator and patches),
 bilinear functions pass through hanging nodes and the transfer exactly, the
 shear flow u = (y, 0) is the discrete solution on a grid with hanging nodes,
 the MV colouring makes the colour-parallel sweep equal the sequential one,
-and the V-cycle over the first four Table 1 grids converges."""
+and the V-cycle over the first four Table 1 grids converges.  On the channel
+with an obstacle and an open outflow side (Sec. 4.2): the vertex and
+Dirichlet counts of the coarse grid by hand and Euler's formula, and the linear
+flow u = (y, 0), p = 0 is the discrete solution and a fixed point of the
+V-cycle (natural outflow condition, no pressure constraint)."""
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -127,3 +131,65 @@ def test_vcycle_over_table1_grids_converges():
     for smoother, om, cap in (("rav", 0.66, 10), ("mv", 0.66, 10), ("av", 0.1, 30)):
         _, k, _, st = H.solve(b, 1e-8, 100, smoother, om, 3)
         assert st == "converged" and k <= cap, (smoother, k)
+
+# ---- channel with an obstacle and an open outflow side (Sec. 4.2) -------------
+SMALL_CHANNEL = dict(bands=(ri.UNIFORM, 1, 1), cells=(16, 3))
+
+
+def test_channel_coarse_grid_counts():
+    """The coarse channel: 64 x 12 cells minus the six whose centres lie in the
+    cylinder (cells (4,5), (5,4), (5,5), (5,6), (6,5), (6,6)), so 762 cells;
+    65 x 13 lattice vertices minus the one inside the hole (6,6): 844.
+    Dirichlet velocity: the rectangle's 2 x 65 + 2 x 11 boundary vertices
+    minus the 11 inside the open side x = 64, plus the 12 vertices around the
+    hole: 153.  Two uniform refinements of a mesh with one hole give the next
+    vertex counts by Euler's formula.  The small test channel (16 x 3 cells, a
+    one-cell hole): 68 vertices, 2 x 17 wall, 2 inflow and 4 hole vertices
+    Dirichlet."""
+    G, Mx, My = ri.channel_grids(3)
+    g = am.AdaptiveGrid(G[0], Mx, BETA, My=My, dmask=ri.OUTFLOW_2D)
+    assert (len(G[0]), g.nV, int(g.dirichlet_node.sum())) == (762, 844, 153)
+    assert not g.all_dirichlet
+    steps = ad.uniform_refinement_counts(844, 762, holes=1, steps=2)
+    assert [(len(lv), ad.vertex_counts(lv)[2]) for lv in G[1:3]] == steps
+    Gs, Mxs, Mys = ri.channel_grids(2, **SMALL_CHANNEL)
+    gs = am.AdaptiveGrid(Gs[0], Mxs, BETA, My=Mys, dmask=ri.OUTFLOW_2D)
+    assert (gs.nV, int(gs.dirichlet_node.sum())) == (68, 2 * 17 + 2 + 4)
+
+
+@pytest.mark.parametrize("level", [0, 3])
+def test_linear_flow_is_exact_in_the_channel(level):
+    """With u_D = (y, 0) on every Dirichlet vertex (walls, inflow side and the
+    obstacle) and the outflow side open, u = (y, 0), p = 0 solves the
+    continuous problem (the natural condition grad(u) n - p n = 0 holds on
+    x = const) and lies in the discrete space, so it is the discrete solution,
+    on the coarse grid and on a grid with hanging nodes."""
+    G, Mx, My = ri.channel_grids(4, **SMALL_CHANNEL)
+    g = am.AdaptiveGrid(G[level], Mx, BETA, My=My, dmask=ri.OUTFLOW_2D)
+    if level:
+        assert ad.vertex_counts(G[level])[1] > 0
+    outflow = (g.rx == Mx) & (g.ry > 0) & (g.ry < My)
+    assert outflow.any() and g.free[: g.nV][outflow].all()
+    u = np.zeros(g.n)
+    u[: g.nV] = g.ry / My
+    b = g.lifting(np.where(g.free, 0.0, u))
+    fr = g.free
+    x = np.zeros(g.n)
+    x[fr] = spl.spsolve(g.assemble().tocsc()[fr][:, fr], b[fr])
+    ex = np.where(fr, u, 0.0)
+    assert np.abs(x[: 2 * g.nV] - ex[: 2 * g.nV]).max() <= 1e-12
+    assert np.abs(x[2 * g.nV:]).max() <= 1e-9
+
+
+def test_linear_flow_is_a_fixed_point_of_the_channel_vcycle():
+    G, Mx, My = ri.channel_grids(4, **SMALL_CHANNEL)
+    H = am.AdaptiveHierarchy(G, Mx, BETA, My=My, dmask=ri.OUTFLOW_2D)
+    assert not H.bordered
+    g = H.finest.grid
+    u = np.zeros(g.n)
+    u[: g.nV] = g.ry / My
+    b = g.lifting(np.where(g.free, 0.0, u))
+    ex = np.where(g.free, u, 0.0)
+    for smoother in (mg.RAV, mg.MV):
+        x = H.vcycle(ex.copy(), b, smoother, 0.66, 2)
+        assert np.abs(x - ex).max() <= 1e-11, smoother

@@ -63,7 +63,8 @@ def test_table2_first_grids_are_uniform_refinements():
     per vertex); from Omega^4 on the grids are refined adaptively (fewer cells
     than a uniform step would give) and every printed DoF count is still three
     per vertex.  The mesh itself and the refinement rule beyond Omega^3 are not
-    given, so the cylinder grids are not built."""
+    given, so the benchmark runs on a stand-in channel (rav_inputs.channel_grids,
+    pinned in test_oracle_adaptive.py)."""
     from oracle import adaptive as ad
     rows = [tuple(int(v) for v in line.split()) for line in open(TABLE2)
             if line.strip() and not line.startswith("#")]
