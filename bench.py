@@ -78,16 +78,18 @@ def parse():
                     help="also launch the plain copy kernel on 1 GiB (for HBM counter scaling)")
     ap.add_argument("--workload", default="2d-512",
                     choices=["2d-512", "3d-64", "3d-64-vertex", "2d-1024", "batch256", "learned", "smoothers", "q1q1",
-                             "cavity", "adaptive"],
+                             "cavity", "adaptive", "channel"],
                     help="2d-512: the headline solve (default); 3d-64: finest-level element-patch sweep; "
                          "3d-64-vertex: 64^3 solve with vertex patches; 2d-1024: inclusions at contrast 1e4; "
                          "batch256: 256 problems; learned: per-patch damping trained on small problems, "
                          "evaluated on held-out 128^2/256^2 problems at contrast 1e2 against fixed omega; smoothers: RAV/AV/MV cost per cycle, "
                          "cycles and time to 1e-8 on 32^2 (damping sweep) and 512^2; cavity: driven cavity, "
                          "smoothing-steps and mesh studies; q1q1: the stabilized Q1-Q1 driven cavity on 1024^2; "
-                         "adaptive: the cavity on the adaptive grids of Table 1, RAV/MV/AV on every grid (Fig. 5)")
+                         "adaptive: the cavity on the adaptive grids of Table 1, RAV/MV/AV on every grid (Fig. 5); "
+                         "channel: flow past a cylinder on a stand-in of Table 2's grids, smoothing-steps and mesh "
+                         "studies (Figs. 7-9)")
     ap.add_argument("--quick", action="store_true",
-                    help="adaptive: only the Omega^10 RAV solve and its kernel times (for profiling)")
+                    help="adaptive, channel: only the finest-grid RAV solve (and, adaptive, its kernel times)")
     ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--train-lr", type=float, default=1e-3)
     return ap.parse_args()
@@ -231,7 +233,7 @@ def main():
     if args.workload != "2d-512":
         {"3d-64": bench_3d, "3d-64-vertex": bench_3d_vertex, "2d-1024": bench_1024, "batch256": bench_batch,
          "learned": bench_learned, "smoothers": bench_smoothers, "cavity": bench_cavity,
-         "q1q1": bench_q1q1, "adaptive": bench_adaptive}[args.workload](args)
+         "q1q1": bench_q1q1, "adaptive": bench_adaptive, "channel": bench_channel}[args.workload](args)
         return
     import torch
     from paper_2103_10127_amd import Hierarchy
@@ -835,6 +837,107 @@ def bench_adaptive(args):
                              "peak": 8000.0, "unit": "GB/s", "frac": ach_res / 8000.0, "algorithmic_bytes": res_bytes},
           omega10=info,
           rav_omega10=main, fig5_study=study, **extra)
+
+
+def bench_channel(args):
+    """The paper's second benchmark (Sec. 4.2, Table 2, Figs. 7-9) on a
+    stand-in of its grids: Stokes flow through a channel past a cylindrical
+    obstacle, parabolic inflow (eq. 14, mean 0.3 m/s), no slip on the walls
+    and the obstacle, open outflow; stabilized Q1-Q1 (beta 0.05) on the
+    adaptive hierarchy Omega^1 .. Omega^7 of rav_inputs.channel_grids (counts
+    within 2 % of Table 2's, 1,680,678 DoFs on Omega^7).  Mesh study: V(3,3)
+    solves to a 1e-8 residual reduction with RAV and MV (omega 0.66) and AV
+    (omega 0.1) for every fine grid Omega^k, k = 2..7 (Figs. 8-9); smoothing
+    steps study on Omega^7: V(n,n), n = 1..6, for the three smoothers (Fig. 7).
+    value = smoothed DoFs/s of the RAV V(3,3) solve on Omega^7."""
+    import torch
+    from paper_2103_10127_amd import capi
+    from paper_2103_10127_amd.capi import AdaptiveHierarchy
+
+    n_grids = 7
+    grids, Mx, My = ri.channel_grids(n_grids)
+    dmask = ri.OUTFLOW_2D
+    ubar = 0.3
+
+    inflow_cache = {}
+
+    def inflow(k):
+        if k not in inflow_cache:
+            V = capi.adaptive_host_export(grids[:k], Mx, k - 1, "vertices", lattice_y=My, dmask=dmask)
+            y = V[:, 1] / My
+            ud = np.zeros((2, len(V)))
+            ud[0] = np.where(V[:, 0] == 0, 4.0 * ubar * y * (1.0 - y), 0.0)
+            inflow_cache[k] = ud
+        return inflow_cache[k]
+
+    def make(k, smoother, omega, nu):
+        t0 = time.perf_counter()
+        H = AdaptiveHierarchy(grids[:k], Mx, smoother=smoother, omega=omega, nu_pre=nu, nu_post=nu, beta=0.05,
+                              lattice_y=My, dmask=dmask)
+        H.factor()
+        torch.cuda.synchronize()
+        n, _ = H.dofs(k - 1)
+        b = torch.zeros(n, dtype=torch.float64, device="cuda")
+        H.assemble_rhs_dirichlet(inflow(k), b)
+        return H, b, time.perf_counter() - t0
+
+    def solve(H, b, k, smoother, omega, nu, reps=1, maxit=300):
+        level_n = [H.dofs(l)[0] for l in range(k)]
+        x = torch.zeros_like(b)
+        H.solve(x, b, 1e-8, 2)
+        best = None
+        for _ in range(reps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, it, rel = H.solve(x, b, 1e-8, maxit)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            best = dt if best is None else min(best, dt)
+        return {"grid": k, "dofs": level_n[-1], "smoother": smoother, "omega": omega, "nu": nu,
+                "status": {0: "converged", 1: "maxit", -4: "diverged"}.get(st, str(st)), "cycles": it,
+                "rho_avg": rel ** (1.0 / it) if it > 0 and rel > 0 else None, "ms": 1e3 * best,
+                "ms_per_cycle": 1e3 * best / max(it, 1),
+                "smoothed_dofs": it * sum(2 * nu * level_n[l] for l in range(1, k))}
+
+    H, b, setup = make(n_grids, "rav", 0.66, 3)
+    main = solve(H, b, n_grids, "rav", 0.66, 3, reps=3)
+    main["setup_s"] = round(setup, 2)
+    main["level_info"] = H.level_info(n_grids - 1)
+    print(f"channel Omega^7 RAV: {main['cycles']} cycles, {main['ms']:.1f} ms", file=sys.stderr, flush=True)
+    steps = []
+    if not args.quick:
+        for sm_, om in (("rav", 0.66), ("mv", 0.66), ("av", 0.1)):
+            Hs = H if sm_ == "rav" else make(n_grids, sm_, om, 3)[0]
+            for nu in range(1, 7):
+                Hs.set_params(om, nu, nu)
+                steps.append(solve(Hs, b, n_grids, sm_, om, nu, maxit=200))
+                r = steps[-1]
+                print(f"  nu={nu} {sm_}: {r['status']} {r['cycles']} cycles, {r['ms']:.1f} ms", file=sys.stderr,
+                      flush=True)
+            if Hs is not H:
+                Hs.close()
+    H.close()
+    study = []
+    for k in (range(2, n_grids + 1) if not args.quick else ()):
+        for sm_, om in (("rav", 0.66), ("mv", 0.66), ("av", 0.1)):
+            if k == n_grids and sm_ == "rav":
+                study.append(main)
+                continue
+            Hk, bk, st_ = make(k, sm_, om, 3)
+            study.append(solve(Hk, bk, k, sm_, om, 3))
+            study[-1]["setup_s"] = round(st_, 2)
+            Hk.close()
+            r = study[-1]
+            print(f"  Omega^{k} {sm_}: {r['cycles']} cycles, {r['ms']:.1f} ms", file=sys.stderr, flush=True)
+    _line("RAV smoothed DoFs/s (whole V(3,3) solve to a 1e-8 residual reduction, channel with an obstacle)",
+          main["smoothed_dofs"] / (1e-3 * main["ms"]), "DoF/s", 3, 1, main["ms"], "f64",
+          {"workload": "2D channel past a cylindrical obstacle (parabolic inflow, mean 0.3 m/s; open outflow), "
+                       "stabilized Q1-Q1 (beta 0.05) on a 7-grid adaptive quadtree hierarchy standing in for "
+                       "Table 2's (1,680,678 DoFs on Omega^7, hanging nodes), RAV V(3,3), omega 0.66"},
+          data="synthetic (64 x 12 coarse cells minus the six inside the cylinder, refined towards the walls "
+               "and the obstacle)",
+          rav_omega7=main, fig7_smoothing_steps=steps, fig89_mesh_study=study)
 
 
 def bench_1024(args):
