@@ -215,14 +215,14 @@ def test_solve_matches_oracle(grids, oracle, smoother, table, monkeypatch):
     H.close()
 
 
-# ---- full hierarchy, sampled rows ----------------------------------------------
-def _regular_vertices(leaves, M):
-    """Keys y (M + 1) + x of the regular vertices of a grid, sorted, which is
+# ---- full hierarchies, sampled rows -------------------------------------------
+def _regular_vertices(leaves, Mx):
+    """Keys y (Mx + 1) + x of the regular vertices of a grid, sorted, which is
     the library's vertex order (y slowest): leaf corners that are not edge
     midpoints of another leaf."""
     x0, y0, s = (leaves[:, k].astype(np.int64) for k in range(3))
     h = s // 2
-    key = lambda x, y: y * (M + 1) + x
+    key = lambda x, y: y * (Mx + 1) + x
     corners = np.unique(np.concatenate([key(x0 + a * s, y0 + b * s) for a in (0, 1) for b in (0, 1)]))
     mids = np.unique(np.concatenate([key(x0 + h, y0), key(x0 + h, y0 + s), key(x0, y0 + h), key(x0 + s, y0 + h)]))
     return np.setdiff1d(corners, mids, assume_unique=True)   # sorted: y slowest, x fastest
@@ -241,16 +241,45 @@ def _window(leaves, px, py, rings=3):
     return leaves[m]
 
 
-def test_full_hierarchy_solve_sampled():
-    n = 10
-    G, M = ri.cavity_grids(n), ri.lattice(n)
-    print("[gpu] adaptive full hierarchy (Omega^10, 3,063,075 DoFs) RAV V(3,3)", flush=True)
-    H = AdaptiveHierarchy(G, M, smoother="rav", omega=0.66, nu_pre=3, nu_post=3, beta=BETA, eta=ETA)
+def _nearest(xs_, ys, px, py):
+    return int(np.argmin(np.abs(xs_ - px) + np.abs(ys - py)))
+
+
+@pytest.mark.parametrize("case", ["cavity-omega10", "channel-omega7"])
+def test_full_hierarchy_solve_sampled(case):
+    """The configurations the benchmarks time: the cavity on Omega^1..Omega^10
+    (3,063,075 DoFs) with its lid, and the channel on Omega^1..Omega^7
+    (1,680,678 DoFs) with its parabolic inflow; RAV V(3,3) to 1e-8, then the
+    right-hand side and the final residual on sampled vertices (random, and at
+    the places where the data or the boundary change) against rows the oracle
+    assembles from the leaves around each vertex."""
+    if case.startswith("cavity"):
+        n = 10
+        G, Mx = ri.cavity_grids(n), ri.lattice(n)
+        My, dm, n_expect = Mx, ri.ALL_DIRICHLET_2D, 3_063_075
+    else:
+        n = 7
+        G, Mx, My = ri.channel_grids(n)
+        dm, n_expect = ri.OUTFLOW_2D, 1_680_678
+    print(f"[gpu] adaptive full hierarchy {case} ({n_expect} DoFs) RAV V(3,3)", flush=True)
+    H = AdaptiveHierarchy(G, Mx, smoother="rav", omega=0.66, nu_pre=3, nu_post=3, beta=BETA, eta=ETA,
+                          lattice_y=My, dmask=dm)
     H.factor()
     n_total, _ = H.dofs(n - 1)
-    assert n_total == 3_063_075
+    assert n_total == n_expect
+    leaves = np.asarray(G[-1], dtype=np.int64)
+    reg = _regular_vertices(leaves, Mx)
+    nV = len(reg)
+    assert 3 * nV == n_total
+    ys, xs_ = reg // (Mx + 1), reg % (Mx + 1)
     b = torch.zeros(n_total, dtype=torch.float64, device="cuda")
-    H.assemble_rhs_lid(b, 1.0)
+    if case.startswith("cavity"):
+        H.assemble_rhs_lid(b, 1.0)
+    else:
+        yy = ys / My
+        ud = np.zeros((2, nV))
+        ud[0] = np.where(xs_ == 0, 4.0 * 0.3 * yy * (1.0 - yy), 0.0)
+        H.assemble_rhs_dirichlet(ud, b)
     x = torch.zeros_like(b)
     st, it, rel = H.solve(x, b, 1e-8, 100)
     print(f"[gpu]   {it} cycles, rel {rel:.2e}", flush=True)
@@ -259,33 +288,37 @@ def test_full_hierarchy_solve_sampled():
     rn = H.residual(n - 1, x, b, r, norm=True)
     b0, xs, rg = b.cpu().numpy(), x.cpu().numpy(), r.cpu().numpy()
     assert rn <= 1.01e-8 * np.linalg.norm(b0)
-    leaves = np.asarray(G[-1], dtype=np.int64)
-    reg = _regular_vertices(leaves, M)
-    nV = len(reg)
-    assert 3 * nV == n_total
     rng = np.random.default_rng(97)
-    ys, xs_ = reg // (M + 1), reg % (M + 1)
-    special = [np.argmin(np.abs(ys - M) + np.abs(xs_ - 1)),        # next to the lid's left end
-               np.argmin(np.abs(ys - M // 2) + np.abs(xs_ - M // 2)),   # centre
-               np.argmin(np.abs(ys - 1024) + np.abs(xs_ - M // 2))]     # a refinement transition
+    if case.startswith("cavity"):
+        special = [_nearest(xs_, ys, 1, My),              # next to the lid's left end
+                   _nearest(xs_, ys, Mx // 2, My // 2),   # centre
+                   _nearest(xs_, ys, Mx // 2, 1024)]      # a refinement transition
+    else:
+        s0 = Mx // 64                                     # coarse cell
+        special = [_nearest(xs_, ys, 0, My // 2),         # inflow side
+                   _nearest(xs_, ys, 1, My // 2),         # next to it
+                   _nearest(xs_, ys, Mx, My // 2),        # outflow side (free velocity)
+                   _nearest(xs_, ys, 4 * s0, 5 * s0),     # obstacle corner
+                   _nearest(xs_, ys, 7 * s0, 6 * s0),     # obstacle corner
+                   _nearest(xs_, ys, 5 * s0 + 1, 7 * s0)]  # obstacle top
     sample = np.unique(np.concatenate([rng.choice(nV, 40, replace=False), special]))
     for v in sample:
-        px, py = int(reg[v] % (M + 1)), int(reg[v] // (M + 1))
-        g = am.AdaptiveGrid(_window(leaves, px, py), M, BETA, ETA)
-        i = g.reg_index[px * (M + 1) + py]
+        px, py = int(xs_[v]), int(ys[v])
+        g = am.AdaptiveGrid(_window(leaves, px, py), Mx, BETA, ETA, My=My, dmask=dm)
+        i = g.reg_index[px * (My + 1) + py]
         Lw = g.assemble().tocsr()
         Law = g.assemble(keep_masked=True).tocsr()
         # window vertex -> library vertex
-        wkey = g.ry * (M + 1) + g.rx
+        wkey = g.ry * (Mx + 1) + g.rx
         gidx = np.minimum(np.searchsorted(reg, wkey), nV - 1)
         known = np.tile(reg[gidx] == wkey, 3)   # corners hanging in the full grid may look regular at the rim
         gcol = np.concatenate([gidx, nV + gidx, 2 * nV + gidx])
-        uD = g.lid_velocity(1.0)
+        uD = g.lid_velocity(1.0) if case.startswith("cavity") else g.inflow_velocity(0.3)
         for f in range(3):
             row, grow = f * g.nV + i, f * nV + v
             cols, vals = Lw.indices[Lw.indptr[row]:Lw.indptr[row + 1]], Lw.data[Lw.indptr[row]:Lw.indptr[row + 1]]
             assert known[cols].all(), (v, f)
-            # lid right-hand side of this row: -L_all[row, masked] u_D
+            # right-hand side of this row: -L_all[row, masked] u_D
             ca, va = Law.indices[Law.indptr[row]:Law.indptr[row + 1]], Law.data[Law.indptr[row]:Law.indptr[row + 1]]
             bo = 0.0 if not g.free[row] else -np.sum(va * np.where(g.free[ca], 0.0, uD[ca]))
             assert abs(b0[grow] - bo) <= 1e-14 * max(1.0, abs(bo)), (v, f)
