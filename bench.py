@@ -903,7 +903,12 @@ def bench_channel(args):
     H, b, setup = make(n_grids, "rav", 0.66, 3)
     main = solve(H, b, n_grids, "rav", 0.66, 3, reps=3)
     main["setup_s"] = round(setup, 2)
-    main["level_info"] = H.level_info(n_grids - 1)
+    main["level_info"] = info = H.level_info(n_grids - 1)
+    xs = torch.zeros_like(b)
+    main["ms_residual"], main["ms_apply"] = H.time_sweep(n_grids - 1, 20, xs, b)
+    # bytes per launch on Omega^7, counted as for the cavity grids
+    app_bytes = 4 * info["patch_entries"] + 76 * info["vertices"]
+    ach_app = app_bytes / (main["ms_apply"] * 1e-3) / 1e9
     print(f"channel Omega^7 RAV: {main['cycles']} cycles, {main['ms']:.1f} ms", file=sys.stderr, flush=True)
     steps = []
     if not args.quick:
@@ -937,6 +942,8 @@ def bench_channel(args):
                        "Table 2's (1,680,678 DoFs on Omega^7, hanging nodes), RAV V(3,3), omega 0.66"},
           data="synthetic (64 x 12 coarse cells minus the six inside the cylinder, refined towards the walls "
                "and the obstacle)",
+          roofline={"bound": "hbm", "kernel": "k_ad_rav (Omega^7)", "achieved": ach_app, "peak": 8000.0,
+                    "unit": "GB/s", "frac": ach_app / 8000.0, "traffic": None, "algorithmic_bytes": app_bytes},
           rav_omega7=main, fig7_smoothing_steps=steps, fig89_mesh_study=study)
 
 
