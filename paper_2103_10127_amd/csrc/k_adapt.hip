@@ -370,9 +370,11 @@ __device__ __forceinline__ void restrict_vertex(const AdDev& f, const AdDev& c, 
 }
 
 // ---- grid-wide kernels -----------------------------------------------------------
-// The value table is read three times per operator entry; when it fits, each
-// 1024-thread block stages it in LDS first (48 KB for 1024 tuples), which
-// takes those reads off the vector-memory path (Omega^10: 40.8 -> 31.1 us).
+// The value table is read three times per operator entry; when it fits and
+// the grid is large, each 1024-thread block stages it in LDS first (48 KB for
+// 1024 tuples), which takes those reads off the vector-memory path (Omega^10:
+// 40.8 -> 31.1 us).  Below AD_RES_LDS_MIN_VERTICES the 256-thread kernel with
+// the table in global memory gives more blocks to a launch-bound grid.
 constexpr int LDS_TUPLES = AD_LDS_TUPLES;
 constexpr int RB_LDS = 1024;   // block of the LDS variant
 constexpr int RB = 256;        // block of the plain variant
@@ -476,7 +478,7 @@ __global__ __launch_bounds__(256) void k_ad_owner(AdDev a, int* __restrict__ own
 }  // namespace
 
 int ad_residual_blocks(const AdDev& a) {
-  return (int)(a.table_lds ? nblk(a.nV, RB_LDS) : nblk(a.nV, RB));
+  return (int)(a.res_lds ? nblk(a.nV, RB_LDS) : nblk(a.nV, RB));
 }
 
 #define AD_WIDE(a, K, ...)                                                              \
@@ -487,7 +489,7 @@ int ad_residual_blocks(const AdDev& a) {
 
 void ad_launch_residual(const AdDev& a, const double* x, const double* b, double* r, double* partials,
                         hipStream_t s) {
-  const bool lds = a.table_lds != 0;
+  const bool lds = a.res_lds != 0;
   const dim3 g(lds ? nblk(a.nV, RB_LDS) : nblk(a.nV, RB)), blk(lds ? RB_LDS : RB);
   if (a.wide) {
     if (lds) hipLaunchKernelGGL((k_ad_residual<true, true, RB_LDS>), g, blk, 0, s, a, x, b, r, partials);

@@ -42,6 +42,9 @@ namespace rav {
 constexpr int AD_SLICE = 64;
 constexpr int AD_NFMAX = 16;   // free velocity vertices per patch
 constexpr int AD_LDS_TUPLES = 1024;   // value tables up to this size are staged in LDS (residual, MV)
+// The residual stages the table only on grids of at least this many vertices:
+// on smaller ones the 256-thread kernel's extra blocks are worth more.
+constexpr int AD_RES_LDS_MIN_VERTICES = 150000;
 
 struct AdDev {
   int nV;
@@ -49,7 +52,8 @@ struct AdDev {
   int wide;                         // 0: packed entries; 1: column and id arrays
   int id_bits;                      // packed: bits of the tuple id
   int ntuple;                       // distinct value tuples (rows of vtab)
-  int table_lds;                    // residual and MV stage vtab in LDS (ntuple <= AD_LDS_TUPLES)
+  int table_lds;                    // MV stages vtab in LDS (ntuple <= AD_LDS_TUPLES)
+  int res_lds;                      // the residual stages vtab in LDS (table_lds and a large grid)
   long long nnz;                    // padded operator entries
   long long pnnz;                   // padded patch entries
   const unsigned char* vmask;       // velocity Dirichlet per vertex

@@ -874,9 +874,12 @@ rav_status upload_level(rav_ctx* ctx, Level& L, const HostLevel& H, bool smoothe
   a.wide = H.wide ? 1 : 0;
   a.id_bits = H.id_bits;
   a.ntuple = L.ntuple;
-  {   // RAV_AD_TABLE_LDS=0 keeps the table in global memory (the path of larger tables)
+  {   // RAV_AD_TABLE_LDS=0 keeps the table in global memory (the path of larger tables),
+      // =1 stages it for the residual on every grid size
     const char* e = std::getenv("RAV_AD_TABLE_LDS");
-    a.table_lds = (L.ntuple <= AD_LDS_TUPLES && !(e && std::string(e) == "0")) ? 1 : 0;
+    const bool off = e && std::string(e) == "0", all = e && std::string(e) == "1";
+    a.table_lds = (L.ntuple <= AD_LDS_TUPLES && !off) ? 1 : 0;
+    a.res_lds = (a.table_lds && (all || L.nV >= AD_RES_LDS_MIN_VERTICES)) ? 1 : 0;
   }
   a.nnz = H.nnz;
   a.vmask = L.vmask;

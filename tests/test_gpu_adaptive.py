@@ -72,10 +72,10 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("table", ["lds", "global"])
+@pytest.mark.parametrize("table", ["lds", "global", "size-rule"])
 def test_residual_dofs_and_owner_every_grid(grids, oracle, table, monkeypatch):
-    if table == "global":
-        monkeypatch.setenv("RAV_AD_TABLE_LDS", "0")
+    if table != "size-rule":   # lds: the residual's table in LDS on every grid; global: nowhere
+        monkeypatch.setenv("RAV_AD_TABLE_LDS", "1" if table == "lds" else "0")
     H = _gpu(grids)
     for l, lv in enumerate(oracle.levels):
         g = lv.grid
@@ -194,14 +194,15 @@ def test_sweeps_and_vcycles(grids, oracle, smoother):
     H.close()
 
 
-@pytest.mark.parametrize("table", ["lds", "global"])
+@pytest.mark.parametrize("table", ["lds", "global", "size-rule"])
 @pytest.mark.parametrize("smoother", ["rav", "av", "mv"])
 def test_solve_matches_oracle(grids, oracle, smoother, table, monkeypatch):
     """V(3,3) to 1e-8 (Sec. 4): the oracle's cycle count within 1 and the
-    same solution within 1e-8, with the residual's value table in LDS and in
-    global memory."""
-    if table == "global":
-        monkeypatch.setenv("RAV_AD_TABLE_LDS", "0")
+    same solution within 1e-8, with the residual's value table in LDS, in
+    global memory, and by the default size rule (global on these small grids,
+    while MV keeps its table in LDS)."""
+    if table != "size-rule":   # lds: the residual's table in LDS on every grid; global: nowhere
+        monkeypatch.setenv("RAV_AD_TABLE_LDS", "1" if table == "lds" else "0")
     g = oracle.finest.grid
     b = _rhs(g)
     xo, ko, _, sto = oracle.solve(b, 1e-8, 200, SM[smoother], OMEGA[smoother], 3)
