@@ -104,3 +104,27 @@ def test_invalid_grids_are_rejected():
     with pytest.raises(capi.RavError) as e:
         capi.adaptive_host_export([coarse, fine], 12, 1, "prolong", BETA, ETA)   # leaves beyond a 12-unit lattice
     assert "inside the rectangle" in str(e.value)
+
+
+def test_open_sides_and_holes():
+    """Dirichlet flags by side and around holes, from the library's set-up:
+    with every side open and no hole nothing is Dirichlet; opening the top
+    frees its inner vertices and leaves no lid (the lid export is refused);
+    a hole's rim is Dirichlet whatever the mask."""
+    M = 16
+    full = np.array([(x, y, 4) for y in range(0, 16, 4) for x in range(0, 16, 4)], dtype=np.int32)
+    coarse = np.array([(x, y, 8) for y in (0, 8) for x in (0, 8)], dtype=np.int32)
+    V = capi.adaptive_host_export([coarse, full], M, 1, "vertices", BETA, ETA, dmask=0)
+    assert V.shape == (25, 3) and not V[:, 2].any()
+    V = capi.adaptive_host_export([coarse, full], M, 1, "vertices", BETA, ETA, dmask=0b0111)
+    top_inner = (V[:, 1] == M) & (V[:, 0] > 0) & (V[:, 0] < M)
+    assert not V[top_inner, 2].any() and V[~top_inner & ((V[:, 0] == 0) | (V[:, 1] == 0)), 2].all()
+    with pytest.raises(capi.RavError) as e:
+        capi.adaptive_host_export([coarse, full], M, 1, "lid", BETA, ETA, dmask=0b0111)
+    assert "top side" in str(e.value)
+    # a hole: the coarse cell (8, 8, 8) left out of both grids
+    c2 = coarse[:3]
+    f2 = full[~((full[:, 0] >= 8) & (full[:, 1] >= 8))]
+    V = capi.adaptive_host_export([c2, f2], M, 1, "vertices", BETA, ETA, dmask=0)
+    rim = ((V[:, 0] >= 8) & (V[:, 1] >= 8))
+    assert rim.sum() == 5 and V[rim, 2].all() and not V[~rim, 2].any()
