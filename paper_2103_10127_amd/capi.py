@@ -392,6 +392,9 @@ class AdaptiveHierarchy(Hierarchy):
         """b = -L_all[:, masked] u_D on the finest grid; ud: host float64
         array (2, n_vertices) or flat, u_x then u_y per regular vertex."""
         u = np.ascontiguousarray(np.asarray(ud, dtype=np.float64).reshape(-1))
+        n_total, _ = self.dofs(self.n_levels - 1)
+        if u.size != 2 * (n_total // 3):
+            raise ValueError(f"ud holds {u.size} values; the finest grid needs 2 x {n_total // 3}")
         return self._chk(self.lib.rav_assemble_rhs_dirichlet(self.h, u.ctypes.data_as(_P), _ptr(b)))
 
 

@@ -165,6 +165,8 @@ def test_dirichlet_rhs(grids, oracle):
     b = torch.zeros(g.n, dtype=torch.float64, device="cuda")
     H.assemble_rhs_dirichlet(ud, b)
     assert np.abs(b.cpu().numpy() - bo).max() <= 1e-14 * np.abs(bo).max()
+    with pytest.raises(ValueError):
+        H.assemble_rhs_dirichlet(ud[:, :-1], b)
     H.close()
 
 
