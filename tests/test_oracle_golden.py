@@ -79,3 +79,26 @@ def test_table2_first_grids_are_uniform_refinements():
         assert n_dof % 3 == 0 and n_e_prev < n_e < 4 * n_e_prev, k
     # the uniform Table 1 coarse grid (unit square, no hole) follows the same rule
     assert ad.uniform_refinement_counts(25, 16, holes=0, steps=1)[0] == (64, 81)
+
+
+def test_channel_stand_in_follows_table2():
+    """The stand-in channel hierarchy (rav_inputs.channel_grids: 64 x 12 square
+    coarse cells minus the six inside the cylinder, refined towards the walls
+    and the obstacle) has the element and DoF counts of Table 2 within 2 % on
+    every grid, is 2:1 balanced and nested, and its DoF counts are three per
+    regular vertex (counted by the oracle, hanging nodes excluded)."""
+    import rav_inputs as ri
+    from oracle import adaptive as ad
+    rows = [tuple(int(v) for v in line.split()) for line in open(TABLE2)
+            if line.strip() and not line.startswith("#")]
+    grids, Mx, My = ri.channel_grids(len(rows))
+    assert (Mx, My) == (64 << len(rows), 12 << len(rows))
+    table = {k: (n_e, n_dof) for k, n_e, n_dof in rows}
+    for k, leaves in enumerate(grids, start=1):
+        n_e, n_dof = table[k]
+        regular = ad.vertex_counts(leaves)[2]
+        assert abs(len(leaves) - n_e) <= 0.02 * n_e and abs(3 * regular - n_dof) <= 0.02 * n_dof, k
+        assert ad.is_balanced(leaves), k
+    for fine, coarse in zip(grids[1:], grids[:-1]):
+        assert (fine[:, 2] ** 2).sum() == (coarse[:, 2] ** 2).sum()   # same region
+        assert fine[:, 2].min() == coarse[:, 2].min() // 2             # one more level each step
