@@ -89,8 +89,8 @@ typedef enum { RAV_ROWS = 0, RAV_FACTORED = 1 } rav_inv_format;
  * vertex v at f (N+1)^d + lin(v); it is provided with vertex patches and FP64
  * inverses for RAV (either storage format), AV and MV (full local inverses; MV
  * in the colour order sum_d (k_d mod 4) 4^d, each patch recomputing its residual
- * rows, eq. 15); batches, FGMRES, the learned weights, profiling markers and
- * rav_export_matrix return RAV_EUNSUPPORTED for it. */
+ * rows, eq. 15), and FGMRES; batches, the learned weights, profiling markers
+ * and rav_export_matrix return RAV_EUNSUPPORTED for it. */
 typedef enum { RAV_TAYLOR_HOOD = 0, RAV_Q1Q1_STAB = 1, RAV_Q1Q1_ADAPTIVE = 2 } rav_discretization;
 
 /* Circular (2D: cx, cy, r) or spherical (3D: cx, cy, cz, r) inclusion. */
@@ -210,7 +210,9 @@ rav_status rav_solve(rav_ctx* ctx, double* x_dev, const double* b_dev, double rt
  * maxit bounds the number of preconditioner applications (V-cycles); stops
  * when the true residual ||b - L x||_2 <= rtol ||b - L x_0||_2.  Allocates
  * 2*restart+3 work vectors of the finest level for the duration of the call.
- * Same return convention as rav_solve; *iters counts V-cycles. */
+ * Serves every context: Taylor-Hood, stabilized Q1-Q1 and adaptive grids
+ * (the V-cycle of the context's own smoother).  Same return convention as
+ * rav_solve; *iters counts V-cycles. */
 rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit, int restart,
                            int* iters, double* rel_res);
 
@@ -340,9 +342,10 @@ rav_status rav_stream_copy(void* hip_stream, double* dst_dev, const double* src_
  * device work) for grids that break these rules.  The context then serves
  * rav_factor_patches, rav_dofs, rav_n_levels, rav_n_patches,
  * rav_assemble_rhs_lid, rav_assemble_rhs_dirichlet, rav_residual, rav_smooth, rav_restrict,
- * rav_prolong_add, rav_coarse_solve, rav_vcycle, rav_solve, rav_set_params,
- * rav_get_patch_map, rav_get_owner, rav_get_patch_inverse, rav_time_sweep and
- * rav_destroy; the others return RAV_EUNSUPPORTED. */
+ * rav_prolong_add, rav_coarse_solve, rav_vcycle, rav_solve, rav_solve_gmres,
+ * rav_solve_gmres_noalloc, rav_set_params, rav_get_patch_map, rav_get_owner,
+ * rav_get_patch_inverse, rav_time_sweep and rav_destroy; the others return
+ * RAV_EUNSUPPORTED. */
 rav_status rav_create_adaptive(const rav_problem_desc* desc, const int* leaves_host, const long* n_leaves_host,
                                long lattice_x, long lattice_y, void* hip_stream, rav_ctx** out);
 /* Right-hand side of Dirichlet data on the finest grid of an adaptive

@@ -154,6 +154,15 @@ void rav_drop_graph(rav_ctx* ctx);   // forget the captured solve cycle
 void rav_graph_cycle(rav_ctx* ctx, void (*issue)(rav_ctx*));   // issue, captured and replayed
 rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<rav::BlockTask>& logical, rav::BlockTask** out, int* n);
 
+// The finest level of a hierarchy as FGMRES sees it: n unknowns, the level's
+// own iterate, right-hand side and residual vectors (device), and whether the
+// patches are factored.
+struct RavFinest {
+  long long n;
+  double *x, *b, *r;
+  bool factored;
+};
+
 // Stabilized Q1-Q1 (rav_q1.hip), reached through the public entry points.
 rav_status rav_q1_create(const rav_problem_desc* d, void* hip_stream, rav_ctx** out);
 void rav_q1_free(rav_ctx* ctx);
@@ -169,6 +178,9 @@ rav_status rav_q1_restrict(rav_ctx* ctx, int level, const double* rf, double* bc
 rav_status rav_q1_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf);
 rav_status rav_q1_coarse_solve(rav_ctx* ctx, const double* b0, double* x0);
 rav_status rav_q1_vcycle(rav_ctx* ctx, double* x, const double* b);
+RavFinest rav_q1_finest(rav_ctx* ctx);
+void rav_q1_residual_finest(rav_ctx* ctx, bool with_norm);
+void rav_q1_vcycle_finest(rav_ctx* ctx);
 rav_status rav_q1_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int maxit, int* iters,
                         double* rel_res);
 rav_status rav_q1_map_patch(const rav_problem_desc* d, int level, long patch, int* dofs, int* n, int* owned);
@@ -195,6 +207,9 @@ rav_status rav_ad_restrict(rav_ctx* ctx, int level, const double* rf, double* bc
 rav_status rav_ad_prolong_add(rav_ctx* ctx, int level, const double* xc, double* xf);
 rav_status rav_ad_coarse_solve(rav_ctx* ctx, const double* b0, double* x0);
 rav_status rav_ad_vcycle(rav_ctx* ctx, double* x, const double* b);
+RavFinest rav_ad_finest(rav_ctx* ctx);
+void rav_ad_residual_finest(rav_ctx* ctx, bool with_norm);
+void rav_ad_vcycle_finest(rav_ctx* ctx);
 rav_status rav_ad_solve(rav_ctx* ctx, double* x, const double* b, double rtol, int maxit, int* iters,
                         double* rel_res);
 rav_status rav_ad_get_owner(rav_ctx* ctx, int level, int* owner_dev);

@@ -36,6 +36,25 @@ void rav_vcycle_finest(rav_ctx* ctx);
 
 namespace {
 
+// The finest level of any discretization: its vectors, its residual (norm in
+// the context's norm slot when asked) and one V-cycle in place on them.
+struct Finest {
+  RavFinest v;
+  void (*residual)(rav_ctx*, bool);
+  void (*vcycle)(rav_ctx*);
+};
+
+void th_residual_finest(rav_ctx* ctx, bool with_norm) {
+  rav_residual_level(ctx, (int)ctx->lv.size() - 1, with_norm);
+}
+
+Finest finest_of(rav_ctx* ctx) {
+  if (ctx->q1) return Finest{rav_q1_finest(ctx), rav_q1_residual_finest, rav_q1_vcycle_finest};
+  if (ctx->ad) return Finest{rav_ad_finest(ctx), rav_ad_residual_finest, rav_ad_vcycle_finest};
+  LevelHost& L = ctx->lv.back();
+  return Finest{RavFinest{L.hd.g.n, L.hd.x, L.hd.b, L.hd.r, ctx->factored != 0}, th_residual_finest, rav_vcycle_finest};
+}
+
 // Device and host buffers of one FGMRES(m) solve.  Device: the Krylov basis
 // V_0..V_m and the preconditioned directions Z_0..Z_{m-1} (n doubles each),
 // the iterate xk and right-hand side bk, 1024 dot-product partial sums and
@@ -53,9 +72,9 @@ struct GmresWork {
 
 rav_status gmres_run(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit, int m,
                      const GmresWork& w, int* iters, double* rel_res) {
-  const int lf = (int)ctx->lv.size() - 1;
-  LevelHost& L = ctx->lv[lf];
-  const long long n = L.hd.g.n;
+  const Finest F = finest_of(ctx);
+  const long long n = F.v.n;
+  double *Lx = F.v.x, *Lb = F.v.b, *Lr = F.v.r;
   hipStream_t s = ctx->stream;
   double** V = w.V;
   double** Z = w.Z;
@@ -63,11 +82,11 @@ rav_status gmres_run(rav_ctx* ctx, double* x_dev, const double* b_dev, double rt
   double *H = w.H, *cs = w.cs, *sn = w.sn, *g = w.g, *y = w.y;
   launch_copy(xk, x_dev, n, s);
   launch_copy(bk, b_dev, n, s);
-  // residual of the current iterate into L.r (norm in ctx->d_norm)
+  // residual of the current iterate into the level's r (norm in ctx->d_norm)
   auto true_residual = [&](double* nrm) -> rav_status {
-    launch_copy(L.hd.x, xk, n, s);
-    launch_copy(L.hd.b, bk, n, s);
-    rav_residual_level(ctx, lf, true);
+    launch_copy(Lx, xk, n, s);
+    launch_copy(Lb, bk, n, s);
+    F.residual(ctx, true);
     return rav_read_norm(ctx, nrm);
   };
   double beta0 = 0.0;
@@ -90,21 +109,21 @@ rav_status gmres_run(rav_ctx* ctx, double* x_dev, const double* b_dev, double rt
       beta = beta0;
     }
     // V_0 = r / beta
-    launch_axpby(1.0 / beta, L.hd.r, 0.0, V[0], n, s);
+    launch_axpby(1.0 / beta, Lr, 0.0, V[0], n, s);
     for (int i = 0; i <= m; ++i) g[i] = 0.0;
     g[0] = beta;
     int jend = 0;
     for (int j = 0; j < m && total < maxit; ++j) {
       // Z_j = M V_j (one V-cycle from zero)
-      launch_copy(L.hd.b, V[j], n, s);
-      launch_fill(L.hd.x, 0.0, n, s);
-      rav_vcycle_finest(ctx);
-      launch_copy(Z[j], L.hd.x, n, s);
+      launch_copy(Lb, V[j], n, s);
+      launch_fill(Lx, 0.0, n, s);
+      F.vcycle(ctx);
+      launch_copy(Z[j], Lx, n, s);
       // w = L Z_j  (residual with b = 0 gives -L Z_j)
-      launch_fill(L.hd.b, 0.0, n, s);
-      rav_residual_level(ctx, lf, false);
+      launch_fill(Lb, 0.0, n, s);
+      F.residual(ctx, false);
       double* wv = V[j + 1];
-      launch_axpby(-1.0, L.hd.r, 0.0, wv, n, s);
+      launch_axpby(-1.0, Lr, 0.0, wv, n, s);
       // modified Gram-Schmidt, coefficients h[i][j] in device memory
       for (int i = 0; i <= j; ++i) {
         double* hij = hdev + (size_t)j * (m + 2) + i;
@@ -167,8 +186,7 @@ rav_status gmres_check(rav_ctx* ctx, double* x_dev, const double* b_dev, double 
                        int max_restart) {
   if (!ctx || !x_dev || !b_dev || !(rtol > 0.0) || maxit < 0 || restart < 1 || restart > max_restart)
     return RAV_EINVAL;
-  if (ctx->q1 || ctx->ad) { ctx->err = "FGMRES is provided for the Taylor-Hood discretization"; return RAV_EUNSUPPORTED; }
-  if (!ctx->factored) { ctx->err = "rav_factor_patches has not been called"; return RAV_EINVAL; }
+  if (!finest_of(ctx).v.factored) { ctx->err = "rav_factor_patches has not been called"; return RAV_EINVAL; }
   return RAV_OK;
 }
 
@@ -205,7 +223,7 @@ extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double*
                                       int restart, int* iters, double* rel_res) {
   rav_status result = gmres_check(ctx, x_dev, b_dev, rtol, maxit, restart, 200);
   if (result != RAV_OK) return result;
-  const long long n = ctx->lv.back().hd.g.n;
+  const long long n = finest_of(ctx).v.n;
   const int m = restart;
   std::vector<double*> V(m + 1, nullptr), Z(m, nullptr);
   double *xk = nullptr, *bk = nullptr, *partial = nullptr, *hdev = nullptr, *hhost = nullptr;
@@ -238,7 +256,7 @@ extern "C" rav_status rav_solve_gmres_noalloc(rav_ctx* ctx, double* x_dev, const
                                               int maxit, int restart, int* iters, double* rel_res) {
   rav_status result = gmres_check(ctx, x_dev, b_dev, rtol, maxit, restart, RAV_NOALLOC_MAX_RESTART);
   if (result != RAV_OK) return result;
-  const long long n = ctx->lv.back().hd.g.n;
+  const long long n = finest_of(ctx).v.n;
   const long long stride = (n + 31) / 32 * 32;   // 256-byte aligned vectors
   const int m = restart;
   const long long need = SCRATCH_HEAD + (2LL * m + 3) * stride;

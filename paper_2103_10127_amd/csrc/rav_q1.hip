@@ -454,6 +454,16 @@ rav_status rav_q1_coarse_solve(rav_ctx* ctx, const double* b0, double* x0) {
   return RAV_OK;
 }
 
+// FGMRES hooks (rav_krylov.hip): the finest level's vectors, its residual
+// (norm into the context's norm slot) and one V-cycle in place on them.
+RavFinest rav_q1_finest(rav_ctx* ctx) {
+  const int lf = (int)st(ctx)->lv.size() - 1;
+  Level& L = st(ctx)->lv[lf];
+  return RavFinest{L.q.n, L.x, L.b, L.r, st(ctx)->have_factors};
+}
+void rav_q1_residual_finest(rav_ctx* ctx, bool with_norm) { residual(ctx, (int)st(ctx)->lv.size() - 1, with_norm); }
+void rav_q1_vcycle_finest(rav_ctx* ctx) { vcycle(ctx, (int)st(ctx)->lv.size() - 1, false); }
+
 rav_status rav_q1_vcycle(rav_ctx* ctx, double* x, const double* b) {
   if (need_factors(ctx) != RAV_OK) return RAV_EINVAL;
   const int lf = (int)st(ctx)->lv.size() - 1;
