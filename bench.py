@@ -798,7 +798,7 @@ def bench_adaptive(args):
     n_grids = 10
     grids, M = ri.cavity_grids(n_grids), ri.lattice(n_grids)
 
-    def run(k, smoother, omega, reps=1, sweep_times=False):
+    def run(k, smoother, omega, reps=1, sweep_times=False, gmres=False):
         t0 = time.perf_counter()
         H = AdaptiveHierarchy(grids[:k], M, smoother=smoother, omega=omega, nu_pre=3, nu_post=3, beta=0.05)
         H.factor()
@@ -824,13 +824,15 @@ def bench_adaptive(args):
                "rho_avg": rel ** (1.0 / it) if it > 0 and rel > 0 else None, "ms": 1e3 * best,
                "ms_per_cycle": 1e3 * best / max(it, 1), "setup_s": round(setup, 2),
                "smoothed_dofs": it * sum(6 * level_n[l] for l in range(1, k))}
+        if gmres:
+            out["fgmres"] = _gmres_timed(H, b)
         if sweep_times:
             out["level_info"] = H.level_info(k - 1)
             out["ms_residual"], out["ms_apply"] = H.time_sweep(k - 1, 20, x, b)
         H.close()
         return out
 
-    main = run(n_grids, "rav", 0.66, reps=3, sweep_times=True)
+    main = run(n_grids, "rav", 0.66, reps=3, sweep_times=True, gmres=not args.quick)
     print(f"adaptive Omega^10 RAV: {main['cycles']} cycles, {main['ms']:.1f} ms", file=sys.stderr, flush=True)
     extra = {}
     if args.copy_calibration:
@@ -868,6 +870,25 @@ def bench_adaptive(args):
                              "peak": 8000.0, "unit": "GB/s", "frac": ach_res / 8000.0, "algorithmic_bytes": res_bytes},
           omega10=info,
           rav_omega10=main, fig5_study=study, **extra)
+
+
+def _gmres_timed(H, b, reps=3, restart=30):
+    """Best of `reps` FGMRES(restart) solves to 1e-8 preconditioned by the
+    context's V-cycle: V-cycles used and time."""
+    import torch
+    x = torch.zeros_like(b)
+    H.solve_gmres(x, b, 1e-8, 2, restart)
+    best, st, it = None, None, 0
+    for _ in range(reps):
+        x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, it, rel = H.solve_gmres(x, b, 1e-8, 300, restart)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        best = dt if best is None else min(best, dt)
+    return {"status": {0: "converged", 1: "maxit", -4: "diverged"}.get(st, str(st)), "vcycles": it,
+            "ms": 1e3 * best, "restart": restart}
 
 
 def bench_channel(args):
@@ -935,6 +956,8 @@ def bench_channel(args):
     main = solve(H, b, n_grids, "rav", 0.66, 3, reps=3)
     main["setup_s"] = round(setup, 2)
     main["level_info"] = info = H.level_info(n_grids - 1)
+    if not args.quick:
+        main["fgmres"] = _gmres_timed(H, b)
     xs = torch.zeros_like(b)
     main["ms_residual"], main["ms_apply"] = H.time_sweep(n_grids - 1, 20, xs, b)
     # bytes per launch on Omega^7, counted as for the cavity grids

@@ -209,7 +209,9 @@ rav_status rav_solve(rav_ctx* ctx, double* x_dev, const double* b_dev, double rt
  * right-preconditioned by one V(nu_pre, nu_post) cycle from a zero guess.
  * maxit bounds the number of preconditioner applications (V-cycles); stops
  * when the true residual ||b - L x||_2 <= rtol ||b - L x_0||_2.  Allocates
- * 2*restart+3 work vectors of the finest level for the duration of the call.
+ * 2*restart+3 work vectors of the finest level on its first call (and on a
+ * call with another restart) and keeps them in the context until rav_destroy,
+ * so later calls allocate nothing.
  * Serves every context: Taylor-Hood, stabilized Q1-Q1 and adaptive grids
  * (the V-cycle of the context's own smoother).  Same return convention as
  * rav_solve; *iters counts V-cycles. */

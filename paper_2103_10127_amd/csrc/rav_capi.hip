@@ -546,35 +546,38 @@ void rav_vcycle_finest(rav_ctx* ctx) { vcycle_level(ctx, (int)ctx->lv.size() - 1
 void rav_drop_graph(rav_ctx* ctx) {
   if (ctx->cycle_exec) (void)hipGraphExecDestroy(ctx->cycle_exec);
   if (ctx->prof_exec) (void)hipGraphExecDestroy(ctx->prof_exec);
-  ctx->cycle_exec = ctx->prof_exec = nullptr;
+  if (ctx->pc_exec) (void)hipGraphExecDestroy(ctx->pc_exec);
+  ctx->cycle_exec = ctx->prof_exec = ctx->pc_exec = nullptr;
   ctx->prof_exec_level = -1;
 }
 
 // Issues `issue(ctx)` on the context stream: captured into a graph on first
 // use and replayed afterwards (RAV_GRAPH=0 in the environment, or a failed
 // capture, issues the launches directly).
-void rav_graph_cycle(rav_ctx* ctx, void (*issue)(rav_ctx*)) {
+void rav_graph_cycle(rav_ctx* ctx, void (*issue)(rav_ctx*)) { rav_graph_issue(ctx, issue, &ctx->cycle_exec); }
+
+void rav_graph_issue(rav_ctx* ctx, void (*issue)(rav_ctx*), hipGraphExec_t* slot) {
   static const bool graphs = [] {
     const char* e = std::getenv("RAV_GRAPH");
     return !(e && std::string(e) == "0");
   }();
   if (graphs && !ctx->graph_failed) {
-    if (!ctx->cycle_exec) {
+    if (!*slot) {
       hipGraph_t g = nullptr;
       bool ok = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
         issue(ctx);
         ok = hipStreamEndCapture(ctx->stream, &g) == hipSuccess && g != nullptr;
       }
-      if (ok) ok = hipGraphInstantiate(&ctx->cycle_exec, g, nullptr, nullptr, 0) == hipSuccess;
+      if (ok) ok = hipGraphInstantiate(slot, g, nullptr, nullptr, 0) == hipSuccess;
       if (g) (void)hipGraphDestroy(g);
       if (!ok) {
         (void)hipGetLastError();
-        ctx->cycle_exec = nullptr;
+        *slot = nullptr;
         ctx->graph_failed = true;
       }
     }
-    if (ctx->cycle_exec && hipGraphLaunch(ctx->cycle_exec, ctx->stream) == hipSuccess) return;
+    if (*slot && hipGraphLaunch(*slot, ctx->stream) == hipSuccess) return;
     (void)hipGetLastError();
     rav_drop_graph(ctx);
     ctx->graph_failed = true;
@@ -1497,6 +1500,7 @@ rav_status rav_destroy(rav_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   rav_drop_graph(ctx);
   if (ctx->learn_free) ctx->learn_free(ctx);
+  if (ctx->gm_free) ctx->gm_free(ctx);
   rav_q1_free(ctx);
   rav_ad_free(ctx);
   for (LevelHost& L : ctx->lv) {

@@ -120,6 +120,10 @@ struct rav_ctx {
   // learned damping: state owned by rav_learn.hip, released through learn_free
   void* learn = nullptr;
   void (*learn_free)(rav_ctx*) = nullptr;
+  // FGMRES work vectors kept between rav_solve_gmres calls (rav_krylov.hip),
+  // released through gm_free
+  void* gm_cache = nullptr;
+  void (*gm_free)(rav_ctx*) = nullptr;
   // fall back to the scalar omega when a cycle reduces the residual by less than this factor (0 = off)
   double fallback_rho = 0.0;
   int fell_back = 0;
@@ -127,6 +131,7 @@ struct rav_ctx {
   // stream on the first solve cycle and replayed for the others (RAV_GRAPH=0
   // disables); dropped whenever parameters, factors or tasks change
   hipGraphExec_t cycle_exec = nullptr;
+  hipGraphExec_t pc_exec = nullptr;      // FGMRES: the preconditioner's V-cycle on the finest vectors
   bool graph_failed = false;
   // the same cycle captured with the profiling markers of prof_level: its
   // event pairs are re-recorded by every replay and read after each cycle
@@ -152,6 +157,7 @@ void rav_apply_level(rav_ctx* ctx, int l);
 rav_status rav_read_norm(rav_ctx* ctx, double* out);
 void rav_drop_graph(rav_ctx* ctx);   // forget the captured solve cycle
 void rav_graph_cycle(rav_ctx* ctx, void (*issue)(rav_ctx*));   // issue, captured and replayed
+void rav_graph_issue(rav_ctx* ctx, void (*issue)(rav_ctx*), hipGraphExec_t* slot);   // the same, own graph
 rav_status rav_upload_tasks(rav_ctx* ctx, const std::vector<rav::BlockTask>& logical, rav::BlockTask** out, int* n);
 
 // The finest level of a hierarchy as FGMRES sees it: n unknowns, the level's

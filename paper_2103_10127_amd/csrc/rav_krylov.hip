@@ -117,7 +117,8 @@ rav_status gmres_run(rav_ctx* ctx, double* x_dev, const double* b_dev, double rt
       // Z_j = M V_j (one V-cycle from zero)
       launch_copy(Lb, V[j], n, s);
       launch_fill(Lx, 0.0, n, s);
-      F.vcycle(ctx);
+      if (ctx->prof_level < 0) rav_graph_issue(ctx, F.vcycle, &ctx->pc_exec);   // captured once, replayed
+      else F.vcycle(ctx);
       launch_copy(Z[j], Lx, n, s);
       // w = L Z_j  (residual with b = 0 gives -L Z_j)
       launch_fill(Lb, 0.0, n, s);
@@ -219,37 +220,69 @@ rav_status scratch_address(rav_ctx* ctx, double** out) {
 
 }  // namespace
 
+namespace {
+
+// Work vectors of rav_solve_gmres, kept by the context between calls: the
+// first call (and one with another restart) allocates them, rav_destroy
+// releases them, so a solve loop allocates nothing after its first solve.
+struct GmCache {
+  int m = 0;
+  long long n = 0;
+  std::vector<double*> V, Z;
+  double *xk = nullptr, *bk = nullptr, *partial = nullptr, *hdev = nullptr, *hhost = nullptr;
+};
+
+void gm_release(rav_ctx* ctx) {
+  GmCache* c = static_cast<GmCache*>(ctx->gm_cache);
+  if (!c) return;
+  for (double* p : c->V) (void)rav_dfree(p);
+  for (double* p : c->Z) (void)rav_dfree(p);
+  (void)rav_dfree(c->xk); (void)rav_dfree(c->bk); (void)rav_dfree(c->partial); (void)rav_dfree(c->hdev);
+  if (c->hhost) (void)hipHostFree(c->hhost);
+  delete c;
+  ctx->gm_cache = nullptr;
+}
+
+rav_status gm_workspace(rav_ctx* ctx, int m, long long n, GmCache** out) {
+  GmCache* c = static_cast<GmCache*>(ctx->gm_cache);
+  if (c && c->m == m && c->n == n) { *out = c; return RAV_OK; }
+  gm_release(ctx);
+  c = new GmCache();
+  ctx->gm_cache = c;
+  ctx->gm_free = gm_release;
+  c->m = m;
+  c->n = n;
+  c->V.assign(m + 1, nullptr);
+  c->Z.assign(m, nullptr);
+  auto alloc = [&]() -> rav_status {
+    for (double*& p : c->V) KCK(rav_dmalloc((void**)&p, sizeof(double) * n));
+    for (double*& p : c->Z) KCK(rav_dmalloc((void**)&p, sizeof(double) * n));
+    KCK(rav_dmalloc((void**)&c->xk, sizeof(double) * n));
+    KCK(rav_dmalloc((void**)&c->bk, sizeof(double) * n));
+    KCK(rav_dmalloc((void**)&c->partial, sizeof(double) * 1024));
+    KCK(rav_dmalloc((void**)&c->hdev, sizeof(double) * (m + 2) * (m + 1)));
+    KCK(hipHostMalloc((void**)&c->hhost, sizeof(double) * (m + 2), hipHostMallocDefault));
+    return RAV_OK;
+  };
+  const rav_status st = alloc();
+  if (st != RAV_OK) { gm_release(ctx); return st; }
+  *out = c;
+  return RAV_OK;
+}
+
+}  // namespace
+
 extern "C" rav_status rav_solve_gmres(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol, int maxit,
                                       int restart, int* iters, double* rel_res) {
   rav_status result = gmres_check(ctx, x_dev, b_dev, rtol, maxit, restart, 200);
   if (result != RAV_OK) return result;
-  const long long n = finest_of(ctx).v.n;
   const int m = restart;
-  std::vector<double*> V(m + 1, nullptr), Z(m, nullptr);
-  double *xk = nullptr, *bk = nullptr, *partial = nullptr, *hdev = nullptr, *hhost = nullptr;
-  auto cleanup = [&]() {
-    for (double* p : V) (void)rav_dfree(p);
-    for (double* p : Z) (void)rav_dfree(p);
-    (void)rav_dfree(xk); (void)rav_dfree(bk); (void)rav_dfree(partial); (void)rav_dfree(hdev);
-    if (hhost) (void)hipHostFree(hhost);
-  };
-  auto alloc = [&]() -> rav_status {
-    for (double*& p : V) KCK(rav_dmalloc((void**)&p, sizeof(double) * n));
-    for (double*& p : Z) KCK(rav_dmalloc((void**)&p, sizeof(double) * n));
-    KCK(rav_dmalloc((void**)&xk, sizeof(double) * n));
-    KCK(rav_dmalloc((void**)&bk, sizeof(double) * n));
-    KCK(rav_dmalloc((void**)&partial, sizeof(double) * 1024));
-    KCK(rav_dmalloc((void**)&hdev, sizeof(double) * (m + 2) * (m + 1)));
-    KCK(hipHostMalloc((void**)&hhost, sizeof(double) * (m + 2), hipHostMallocDefault));
-    return RAV_OK;
-  };
-  if ((result = alloc()) != RAV_OK) { cleanup(); return result; }
+  GmCache* c = nullptr;
+  if ((result = gm_workspace(ctx, m, finest_of(ctx).v.n, &c)) != RAV_OK) return result;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  const GmresWork w{V.data(), Z.data(), xk, bk, partial, hdev, hhost, H.data(), cs.data(), sn.data(), g.data(),
-                    y.data()};
-  result = gmres_run(ctx, x_dev, b_dev, rtol, maxit, m, w, iters, rel_res);
-  cleanup();
-  return result;
+  const GmresWork w{c->V.data(), c->Z.data(), c->xk, c->bk, c->partial, c->hdev, c->hhost, H.data(), cs.data(),
+                    sn.data(), g.data(), y.data()};
+  return gmres_run(ctx, x_dev, b_dev, rtol, maxit, m, w, iters, rel_res);
 }
 
 extern "C" rav_status rav_solve_gmres_noalloc(rav_ctx* ctx, double* x_dev, const double* b_dev, double rtol,
