@@ -331,6 +331,8 @@ def main():
         out["copy_GBs"] = _copy_calibration()
 
     if not args.no_mixed:
+        # the same problem by FGMRES(30) with one of these V-cycles as preconditioner
+        out["fgmres"] = _gmres_timed(H, b)
         H.close()
         variants = {}
         esz = {"fp64": 8, "fp32": 4, "bf16": 2}
