@@ -985,7 +985,9 @@ rav_status rav_n_patches(const rav_ctx* ctx, int level, long* n) {
 
 rav_status rav_assemble_rhs(rav_ctx* ctx, const double* params, int n_params, double* b_dev) {
   if (ctx && ctx->q1 && params && b_dev) return rav_q1_assemble_rhs(ctx, params, n_params, b_dev);
-  if (ctx && ctx->ad) return set_err(ctx, RAV_EUNSUPPORTED, "adaptive grids carry the driven cavity (rav_assemble_rhs_lid)");
+  if (ctx && ctx->ad)
+    return set_err(ctx, RAV_EUNSUPPORTED,
+                   "adaptive grids take their data through the lifting (rav_assemble_rhs_lid, rav_assemble_rhs_dirichlet)");
   if (!ctx || !params || !b_dev) return RAV_EINVAL;
   const int need = ctx->desc.dim == 2 ? 25 : 65;
   if (n_params != need) return set_err(ctx, RAV_EINVAL, "mms parameter array must have " + std::to_string(need) + " entries");
