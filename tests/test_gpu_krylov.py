@@ -95,3 +95,34 @@ def test_gmres_adaptive(case):
     xo, ko, _ = _oracle_fgmres(H, b, mg.RAV, 0.66, 2)
     _check_gmres(AdaptiveHierarchy(G_, Mx, smoother="rav", omega=0.66, nu_pre=2, nu_post=2, beta=0.05,
                                    lattice_y=My, dmask=dm), g, b, xo, ko)
+
+
+def test_gmres_workspace_kept_and_replaced():
+    """The context keeps FGMRES's work vectors between calls and replaces them
+    when the restart length changes: restart 10, then 30, then 10 again on one
+    context give the first call's iterate bit for bit, and the 30 result agrees
+    with a fresh context's (to rounding: the set-up autotuner may pick other
+    lane counts, so other summation orders, in another context)."""
+    print("[gpu] gmres workspace reuse", flush=True)
+    N, nl = 32, 3
+    xs = {}
+    G = Hierarchy(dim=2, n_cells=N, n_levels=nl)
+    G.factor()
+    g_n = G.dofs(nl - 1)[0]
+    H = mg.Hierarchy(2, N, nl, ri.ALL_DIRICHLET_2D, 0, 1.0, 1.0, ri.inclusions(3000))
+    b = torch.from_numpy(A.assemble_rhs(H.finest.grid, ri.mms_params(2, 3001))).cuda()
+    assert b.numel() == g_n
+    for tag, m in (("a", 10), ("b", 30), ("c", 10)):
+        x = torch.zeros(g_n, dtype=torch.float64, device="cuda")
+        st, it, rel = G.solve_gmres(x, b, 1e-8, 300, m)
+        assert st == 0, (tag, st)
+        xs[tag] = (x, it)
+    assert torch.equal(xs["a"][0], xs["c"][0]) and xs["a"][1] == xs["c"][1]
+    G.close()
+    F = Hierarchy(dim=2, n_cells=N, n_levels=nl)
+    F.factor()
+    x = torch.zeros(g_n, dtype=torch.float64, device="cuda")
+    st, it, rel = F.solve_gmres(x, b, 1e-8, 300, 30)
+    assert st == 0 and it == xs["b"][1]
+    assert float((x - xs["b"][0]).norm() / xs["b"][0].norm()) <= 1e-10
+    F.close()
